@@ -1,0 +1,183 @@
+/*
+ * ovsign -- sgn(gamma5 Dw(mu)) b for the overlap operator at nonzero chemical
+ * potential, on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation follows Bloch, Breu and Wettig, "Comparing iterative methods
+ * to compute the overlap Dirac operator at nonzero chemical potential"
+ * (Lattice 2008):
+ *   - Section 1: Dw(mu) = 1 - kappa sum_i (T_i^+ + T_i^-)
+ *                         - kappa (e^mu T_4^+ + e^-mu T_4^-),
+ *     (T_nu^{+-})_{yx} = (1 +- gamma_nu) U_{x,+-nu} delta_{y,x+-nu},
+ *     kappa = 1/(8 + 2 m_w), and D_ov(mu) = 1 + gamma5 sgn(gamma5 Dw(mu)).
+ *   - Section 1, eq. for sgn(z): sgn(z) = sgn(Re z) on eigenvalues.
+ *   - Section 3: LR deflation with left/right critical eigenvectors,
+ *     L^dagger R = I, computed once for all sources.
+ *   - Section 4: two-sided Lanczos, f(A) b ~ R f(Lambda) L^dagger b
+ *                + |b_R| V_k f(G_k) e_1 (eq. 2sLapp).
+ *   - Section 2: Arnoldi, the same with the Hessenberg H_k (eq. Arnapp).
+ *
+ * Conventions (shared with the caller):
+ *   - Site index s = x + Lx*(y + Ly*(z + Lz*t)).
+ *   - Links: complex128 (re, im interleaved) [V][4][3][3], direction 0..3 with
+ *     3 = time; U_{x,-nu} is taken as U_{x-nu,nu}^dagger.
+ *   - Spinor fields: complex128 [nrhs][V][4][3]  (N = 12 V per source).
+ *   - Euclidean chiral gamma basis, gamma5 = diag(1, 1, -1, -1) in spin.
+ *   - bc[nu] = +1 periodic, -1 antiperiodic; the sign sits on the link that
+ *     leaves the last slice in direction nu.
+ *
+ * Ownership: the caller owns every buffer it passes.  Pointers documented as
+ * "device" must be device memory of the current HIP device; "host" pointers
+ * are ordinary host memory.  The library copies links and eigentriples into
+ * its own storage and never frees caller memory.  All work is enqueued on the
+ * stream given at lattice creation; calls that return results to the host
+ * (sign_apply, the timing calls) synchronise that stream before returning.
+ *
+ * Errors: every call returns an ovs_status; nothing throws or aborts across
+ * this boundary.  Negative values are errors (outputs undefined), positive
+ * values are warnings (outputs valid, see ovs_rhs_info).  A handle must not be
+ * used from two host threads at once.
+ */
+#ifndef OVSIGN_H
+#define OVSIGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ovs_status;
+#define OVS_OK                   0
+#define OVS_WARN_NOT_CONVERGED   1  /* tolerance not reached within k_max        */
+#define OVS_WARN_BREAKDOWN       2  /* serious Lanczos breakdown (delta ~ 0)      */
+#define OVS_WARN_SIGN_AMBIGUOUS  3  /* inner quadrature error above its target    */
+#define OVS_ERR_ARG             -1  /* invalid argument                           */
+#define OVS_ERR_HIP             -2  /* HIP runtime error                          */
+#define OVS_ERR_ALLOC           -3  /* device allocation failed                   */
+#define OVS_ERR_STATE           -4  /* handle not ready (e.g. links not set)      */
+
+typedef enum { OVS_F64 = 0, OVS_F32_STORE = 1 } ovs_precision;
+typedef enum { OVS_OP_DW = 0, OVS_OP_DW_DAG = 1, OVS_OP_A = 2, OVS_OP_A_DAG = 3 } ovs_op;
+typedef enum { OVS_2SL = 0, OVS_ARNOLDI = 1 } ovs_method;
+
+enum {
+  OVS_FLAG_TWO_PASS = 1,  /* 2sL: do not store V_k; replay the recurrence (end of Section 5) */
+  OVS_FLAG_GRAPH    = 4,  /* replay the Lanczos iterations as captured HIP graphs             */
+  OVS_FLAG_OVERLAP  = 8   /* return D_ov b = b + gamma5 sgn(A) b instead of sgn(A) b         */
+};
+
+typedef struct ovs_lattice_s* ovs_lattice;
+typedef struct ovs_deflation_s* ovs_deflation;
+typedef struct ovs_field_s* ovs_field;
+
+/* Per-source result record of ovs_sign_apply. */
+typedef struct {
+  int32_t k_used;        /* Krylov size actually used                                  */
+  int32_t status;        /* OVS_OK or a warning code for this source                   */
+  double est_rel_err;    /* convergence estimate n_b |x_j - x_{j-c}| / |b| (0 if unused) */
+  double quad_err;       /* estimated error of the inner sign quadrature               */
+  double n_b;            /* |b_R|, norm of the deflated source                         */
+  double t_defl_ms, t_krylov_ms, t_inner_ms, t_combine_ms; /* phase times (whole batch) */
+} ovs_rhs_info;
+
+/* ---- lattice ------------------------------------------------------------ */
+
+/* Create a lattice handle.  dims = {Lx, Ly, Lz, Lt}, each >= 2 and Lx*Ly*Lz*Lt
+ * < 2^26; bc = {+-1, +-1, +-1, +-1}; prec selects the storage type of links
+ * and Krylov vectors (coefficients, dots and deflation are always FP64);
+ * hip_stream is a hipStream_t (NULL = default stream).  Section 1 defines the
+ * lattice operator this handle applies.  Errors: OVS_ERR_ARG for bad
+ * dims/bc/prec, OVS_ERR_ALLOC. */
+ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_precision prec,
+                              void* hip_stream, ovs_lattice* out);
+ovs_status ovs_lattice_destroy(ovs_lattice lat);
+
+/* Copy gauge links U_{x,nu} in SU(3) (Section 1) into the handle.  U: device,
+ * complex128 [V][4][3][3].  The library keeps its own packed copy (FP64 or
+ * FP32 per prec) with the boundary signs folded in. */
+ovs_status ovs_set_links(ovs_lattice lat, const void* U);
+
+/* Set m_w and mu (Section 1): kappa = 1/(8 + 2 m_w).  OVS_ERR_ARG if
+ * 8 + 2 m_w <= 0 or a value is not finite. */
+ovs_status ovs_set_params(ovs_lattice lat, double m_w, double mu);
+
+/* y = op x for nrhs sources (Section 1).  x, y: device complex128
+ * [nrhs][V][4][3], must not alias.  OVS_OP_A is gamma5 Dw(mu), OVS_OP_A_DAG its
+ * adjoint (= gamma5 Dw(-mu)), OVS_OP_DW_DAG = gamma5 Dw(-mu) gamma5.  In
+ * OVS_F32_STORE mode the stencil runs in FP32 (inputs rounded to FP32). */
+ovs_status ovs_apply(ovs_lattice lat, ovs_op op, const void* x, void* y, int32_t nrhs);
+
+/* ---- resident fields (library layout, for repeated stencil application) -- */
+
+/* A field of nrhs sources in the library's private layout and storage type. */
+ovs_status ovs_field_create(ovs_lattice lat, int32_t nrhs, ovs_field* out);
+ovs_status ovs_field_destroy(ovs_field f);
+/* Import from / export to device complex128 [nrhs][V][4][3]. */
+ovs_status ovs_field_import(ovs_field f, const void* x);
+ovs_status ovs_field_export(ovs_field f, void* x);
+/* out = op in, both resident (same nrhs, distinct fields).  Enqueues one
+ * stencil kernel launch on the lattice stream and does not synchronise. */
+ovs_status ovs_field_apply(ovs_lattice lat, ovs_op op, ovs_field in, ovs_field out);
+/* Launch ovs_field_apply `iters` times back to back and return the average
+ * kernel time in milliseconds measured with HIP events on the lattice stream. */
+ovs_status ovs_field_apply_timed(ovs_lattice lat, ovs_op op, ovs_field in, ovs_field out,
+                                 int32_t iters, double* ms_per_apply);
+/* Choose the RHS block and launch shape of the stencil for this nrhs by timing
+ * the candidates (the choice is kept in the lattice handle). */
+ovs_status ovs_autotune(ovs_lattice lat, int32_t nrhs);
+/* Current tuned stencil configuration: rhs block and workgroup size. */
+ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int32_t* wg_size);
+
+/* ---- deflation (Section 3) -------------------------------------------- */
+
+/* Supply m critical eigentriples: lambda host complex128 [m]; R, L device
+ * complex128 [m][V][4][3] (column j of R_m / L_m is row j).  The library
+ * copies them (FP64) and checks |L^dagger R - I|_max <= 1e-8 and
+ * |A r_j - lambda_j r_j| <= 1e-6 |lambda_j| (OVS_ERR_ARG otherwise). */
+ovs_status ovs_deflation_set(ovs_lattice lat, int32_t m, const double* lambda, const void* R,
+                             const void* L, ovs_deflation* out);
+ovs_status ovs_deflation_destroy(ovs_deflation d);
+
+/* ---- sign function ------------------------------------------------------ */
+
+/* y = sgn(A) b (or D_ov b with OVS_FLAG_OVERLAP) for nrhs sources, A = gamma5
+ * Dw(mu): LR-deflated two-sided Lanczos (eq. 2sLapp) or Arnoldi (eq. Arnapp).
+ *   defl   : NULL for no deflation, else the first n_defl triples are used.
+ *   b, y   : device complex128 [nrhs][V][4][3].
+ *   k_max  : maximal Krylov size (1 <= k_max <= N).
+ *   tol    : host [nrhs] target relative errors, or NULL to run exactly k_max
+ *            steps.  With tol, a source stops when its estimate falls below
+ *            tol/10, checked every 25 iterations.
+ *   info   : host [nrhs] result records, or NULL.
+ * The inner function sgn(G_k) e_1 (or sgn(H_k) e_1) is evaluated on the GPU
+ * in FP64.  Returns the most severe per-source warning, or an error. */
+ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, const void* b,
+                          void* y, int32_t nrhs, int32_t k_max, const double* tol,
+                          ovs_method method, int32_t flags, ovs_rhs_info* info);
+
+/* Krylov coefficients of the last ovs_sign_apply on this handle (2sL only):
+ * alpha, gamma host complex128 [nrhs][k_max], beta host double [nrhs][k_max],
+ * x host complex128 [nrhs][k_max] (sgn(G_k) e_1, zero beyond k_used).  Any
+ * pointer may be NULL.  For testing and diagnostics. */
+ovs_status ovs_last_coefficients(ovs_lattice lat, double* alpha, double* beta, double* gamma,
+                                 double* x);
+
+/* x = sgn(T) e_1 for a batch of tridiagonal T (Section 4: G_k), on the GPU,
+ * by the library's inner-sign quadrature.  Host inputs: diag, super (gamma)
+ * complex128 [batch][k]; sub (beta) complex128 [batch][k] (entry k-1 unused).
+ * Output x host complex128 [batch][k]; err host double [batch] (may be NULL). */
+ovs_status ovs_inner_sign_tridiag(ovs_lattice lat, int32_t batch, int32_t k, const double* diag,
+                                  const double* sub, const double* super, double* x, double* err);
+
+/* x = sgn(H) e_1 for a batch of upper Hessenberg H (Section 2: H_k), column
+ * major complex128 [batch][k][k] host; x host complex128 [batch][k]. */
+ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, const double* H,
+                                     double* x, double* err);
+
+const char* ovs_status_string(ovs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OVSIGN_H */

@@ -1,0 +1,353 @@
+"""Python binding of libovsign (include/ovsign.h): sgn(gamma5 Dw(mu)) b on MI355X.
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch
+supplies device memory and the stream; tensors are complex128 on the GPU in
+the canonical layouts of the C header:
+    links   [V, 4, 3, 3]            (site index x + Lx*(y + Ly*(z + Lz*t)))
+    fields  [nrhs, V, 4, 3] or [nrhs, 12*V]
+
+If the compiled library is missing this module raises on first use; there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libovsign.so")
+
+OVS_OK = 0
+OVS_WARN_NOT_CONVERGED = 1
+OVS_WARN_BREAKDOWN = 2
+OVS_WARN_SIGN_AMBIGUOUS = 3
+OVS_ERR_ARG = -1
+OVS_ERR_HIP = -2
+OVS_ERR_ALLOC = -3
+OVS_ERR_STATE = -4
+
+OVS_F64 = 0
+OVS_F32_STORE = 1
+OPS = {"Dw": 0, "Dw_dag": 1, "A": 2, "A_dag": 3}
+METHODS = {"2sl": 0, "arnoldi": 1}
+OVS_FLAG_TWO_PASS = 1
+OVS_FLAG_GRAPH = 4
+OVS_FLAG_OVERLAP = 8
+
+EXPORTED = [
+    "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
+    "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
+    "ovs_field_apply", "ovs_field_apply_timed", "ovs_autotune", "ovs_get_tuning",
+    "ovs_deflation_set", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_last_coefficients",
+    "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_status_string",
+]
+
+
+class OvsError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class RhsInfo(ctypes.Structure):
+    _fields_ = [
+        ("k_used", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("est_rel_err", ctypes.c_double),
+        ("quad_err", ctypes.c_double),
+        ("n_b", ctypes.c_double),
+        ("t_defl_ms", ctypes.c_double),
+        ("t_krylov_ms", ctypes.c_double),
+        ("t_inner_ms", ctypes.c_double),
+        ("t_combine_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libovsign.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_0810_4228_amd.build")
+    # PyTorch ships its own HIP runtime under the same soname as /opt/rocm's.
+    # Loading torch first makes the library bind to that one, so a process
+    # holds a single HIP runtime and device pointers and streams are shared.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    IP = ctypes.POINTER(ctypes.c_int32)
+    DP = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "ovs_lattice_create": [IP, IP, I, P, ctypes.POINTER(P)],
+        "ovs_lattice_destroy": [P],
+        "ovs_set_links": [P, P],
+        "ovs_set_params": [P, D, D],
+        "ovs_apply": [P, I, P, P, I],
+        "ovs_field_create": [P, I, ctypes.POINTER(P)],
+        "ovs_field_destroy": [P],
+        "ovs_field_import": [P, P],
+        "ovs_field_export": [P, P],
+        "ovs_field_apply": [P, I, P, P],
+        "ovs_field_apply_timed": [P, I, P, P, I, DP],
+        "ovs_autotune": [P, I],
+        "ovs_get_tuning": [P, I, IP, IP],
+        "ovs_deflation_set": [P, I, DP, P, P, ctypes.POINTER(P)],
+        "ovs_deflation_destroy": [P],
+        "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
+        "ovs_last_coefficients": [P, DP, DP, DP, DP],
+        "ovs_inner_sign_tridiag": [P, I, I, DP, DP, DP, DP, DP],
+        "ovs_inner_sign_hessenberg": [P, I, I, DP, DP, DP],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    lib.ovs_status_string.argtypes = [ctypes.c_int32]
+    lib.ovs_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_string(s: int) -> str:
+    try:
+        return load().ovs_status_string(int(s)).decode()
+    except Exception:  # library not loadable: plain code
+        return str(s)
+
+
+def _check(status, what):
+    if status < 0:
+        raise OvsError(status, what)
+    return status
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_c128(t, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{what} must be a complex128 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t
+
+
+def _stream_handle():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Lattice:
+    """ovs_lattice handle: geometry, boundary signs, links, m_w and mu."""
+
+    def __init__(self, dims, bc=(1, 1, 1, -1), precision="f64"):
+        lib = load()
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.N = 12 * self.V
+        self.precision = precision
+        prec = {"f64": OVS_F64, "f32": OVS_F32_STORE}[precision]
+        d = (ctypes.c_int32 * 4)(*self.dims)
+        b = (ctypes.c_int32 * 4)(*[int(x) for x in bc])
+        h = ctypes.c_void_p()
+        _check(lib.ovs_lattice_create(d, b, prec, _stream_handle(), ctypes.byref(h)), "ovs_lattice_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ovs_lattice_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_links(self, U):
+        U = _dev_c128(U, "U")
+        if U.numel() != self.V * 36:
+            raise ValueError("U must hold V*4*3*3 entries")
+        _check(self._lib.ovs_set_links(self._h, ctypes.c_void_p(U.data_ptr())), "ovs_set_links")
+
+    def set_params(self, m_w, mu):
+        _check(self._lib.ovs_set_params(self._h, float(m_w), float(mu)), "ovs_set_params")
+
+    def _fields(self, x):
+        x = _dev_c128(x, "x")
+        if x.numel() % self.N:
+            raise ValueError("field size must be a multiple of 12*V")
+        return x, x.numel() // self.N
+
+    def apply(self, op, x, out=None):
+        torch = _torch()
+        x, nrhs = self._fields(x)
+        y = torch.empty_like(x) if out is None else _dev_c128(out, "out")
+        _check(self._lib.ovs_apply(self._h, OPS[op], ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(y.data_ptr()), nrhs), "ovs_apply")
+        return y
+
+    def field_create(self, nrhs):
+        return Field(self, nrhs)
+
+    def autotune(self, nrhs):
+        _check(self._lib.ovs_autotune(self._h, int(nrhs)), "ovs_autotune")
+
+    def get_tuning(self, nrhs):
+        b = ctypes.c_int32()
+        w = ctypes.c_int32()
+        _check(self._lib.ovs_get_tuning(self._h, int(nrhs), ctypes.byref(b), ctypes.byref(w)), "ovs_get_tuning")
+        return b.value, w.value
+
+    def deflation_set(self, lam, R, L):
+        """lam: complex [m] (host); R, L: complex128 CUDA [m, 12V]."""
+        lam = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128))
+        R = _dev_c128(R, "R")
+        L = _dev_c128(L, "L")
+        m = lam.shape[0]
+        if R.numel() != m * self.N or L.numel() != m * self.N:
+            raise ValueError("R and L must be [m, 12V]")
+        lam_d = lam.view(np.float64)
+        h = ctypes.c_void_p()
+        _check(self._lib.ovs_deflation_set(self._h, m, _dptr(lam_d), ctypes.c_void_p(R.data_ptr()),
+                                           ctypes.c_void_p(L.data_ptr()), ctypes.byref(h)),
+               "ovs_deflation_set")
+        return Deflation(self, h, m)
+
+    def sign_apply(self, b, k_max, defl=None, n_defl=None, tol=None, method="2sl",
+                   two_pass=False, graph=False, overlap=False, out=None):
+        """y = sgn(A) b (or D_ov b with overlap=True).  Returns (y, infos, status)."""
+        torch = _torch()
+        b, nrhs = self._fields(b)
+        y = torch.empty_like(b) if out is None else _dev_c128(out, "out")
+        flags = (OVS_FLAG_TWO_PASS if two_pass else 0) | (OVS_FLAG_GRAPH if graph else 0) | \
+                (OVS_FLAG_OVERLAP if overlap else 0)
+        infos = (RhsInfo * nrhs)()
+        tol_arr = None
+        tol_p = None
+        if tol is not None:
+            tol_arr = np.ascontiguousarray(np.broadcast_to(np.asarray(tol, dtype=np.float64), (nrhs,)))
+            tol_p = _dptr(tol_arr)
+        dh = defl._h if defl is not None else None
+        nd = (defl.m if n_defl is None else int(n_defl)) if defl is not None else 0
+        st = self._lib.ovs_sign_apply(self._h, dh, nd, ctypes.c_void_p(b.data_ptr()),
+                                      ctypes.c_void_p(y.data_ptr()), nrhs, int(k_max), tol_p,
+                                      METHODS[method], flags, infos)
+        _check(st, "ovs_sign_apply")
+        return y, [i.as_dict() for i in infos], st
+
+    def last_coefficients(self, nrhs, k_max):
+        a = np.zeros((nrhs, k_max), dtype=np.complex128)
+        bb = np.zeros((nrhs, k_max), dtype=np.float64)
+        g = np.zeros((nrhs, k_max), dtype=np.complex128)
+        x = np.zeros((nrhs, k_max), dtype=np.complex128)
+        _check(self._lib.ovs_last_coefficients(self._h, _dptr(a.view(np.float64)), _dptr(bb),
+                                               _dptr(g.view(np.float64)), _dptr(x.view(np.float64))),
+               "ovs_last_coefficients")
+        return a, bb, g, x
+
+    def inner_sign_tridiag(self, diag, sub, sup):
+        """sgn(T) e_1 for a batch of tridiagonal T ([batch, k] complex arrays, host)."""
+        diag = np.ascontiguousarray(np.atleast_2d(diag), dtype=np.complex128)
+        sub = np.ascontiguousarray(np.atleast_2d(sub), dtype=np.complex128)
+        sup = np.ascontiguousarray(np.atleast_2d(sup), dtype=np.complex128)
+        batch, k = diag.shape
+        x = np.zeros((batch, k), dtype=np.complex128)
+        err = np.zeros(batch)
+        _check(self._lib.ovs_inner_sign_tridiag(self._h, batch, k, _dptr(diag.view(np.float64)),
+                                                _dptr(sub.view(np.float64)), _dptr(sup.view(np.float64)),
+                                                _dptr(x.view(np.float64)), _dptr(err)),
+               "ovs_inner_sign_tridiag")
+        return x, err
+
+    def inner_sign_hessenberg(self, H):
+        """sgn(H) e_1 for a batch of upper Hessenberg H ([batch, k, k] complex, host)."""
+        H = np.asarray(H, dtype=np.complex128)
+        if H.ndim == 2:
+            H = H[None]
+        batch, k, _ = H.shape
+        Hc = np.ascontiguousarray(np.swapaxes(H, 1, 2))  # column-major per matrix
+        x = np.zeros((batch, k), dtype=np.complex128)
+        err = np.zeros(batch)
+        _check(self._lib.ovs_inner_sign_hessenberg(self._h, batch, k, _dptr(Hc.view(np.float64)),
+                                                   _dptr(x.view(np.float64)), _dptr(err)),
+               "ovs_inner_sign_hessenberg")
+        return x, err
+
+
+class Field:
+    """ovs_field: nrhs sources resident in the library's layout."""
+
+    def __init__(self, lat: Lattice, nrhs: int):
+        self.lat = lat
+        self.nrhs = int(nrhs)
+        h = ctypes.c_void_p()
+        _check(lat._lib.ovs_field_create(lat._h, self.nrhs, ctypes.byref(h)), "ovs_field_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lat._lib.ovs_field_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def import_(self, x):
+        x = _dev_c128(x, "x")
+        if x.numel() != self.nrhs * self.lat.N:
+            raise ValueError("size mismatch")
+        _check(self.lat._lib.ovs_field_import(self._h, ctypes.c_void_p(x.data_ptr())), "ovs_field_import")
+
+    def export(self, out=None):
+        torch = _torch()
+        y = out if out is not None else torch.empty((self.nrhs, self.lat.N), dtype=torch.complex128, device="cuda")
+        _check(self.lat._lib.ovs_field_export(self._h, ctypes.c_void_p(y.data_ptr())), "ovs_field_export")
+        return y
+
+    def apply(self, op, out: "Field"):
+        _check(self.lat._lib.ovs_field_apply(self.lat._h, OPS[op], self._h, out._h), "ovs_field_apply")
+
+    def apply_timed(self, op, out: "Field", iters):
+        ms = ctypes.c_double()
+        _check(self.lat._lib.ovs_field_apply_timed(self.lat._h, OPS[op], self._h, out._h, int(iters),
+                                                   ctypes.byref(ms)), "ovs_field_apply_timed")
+        return ms.value
+
+
+class Deflation:
+    def __init__(self, lat, h, m):
+        self.lat = lat
+        self._h = h
+        self.m = m
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lat._lib.ovs_deflation_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1035 @@
+// C-ABI of libovsign: lattice handles, operator application, LR deflation and
+// the sign-function drivers (two-sided Lanczos and Arnoldi).  The drivers
+// enqueue the HIP kernels of stencil.hip and krylov.hip on the lattice's own
+// stream; the host only makes the decisions that need a global view
+// (convergence checks, quadrature refinement, breakdown bookkeeping).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ovs_common.h"
+#include "ovs_krylov.h"
+
+using namespace ovs;
+
+namespace {
+
+// Orders the library stream after the caller's stream on entry, and the
+// caller's stream after the library stream on exit.
+struct StreamScope {
+  ovs_lattice_s* l;
+  explicit StreamScope(ovs_lattice_s* lat) : l(lat) {
+    (void)hipEventRecord(l->ev_in, l->user_stream);
+    (void)hipStreamWaitEvent(l->stream, l->ev_in, 0);
+  }
+  ~StreamScope() {
+    (void)hipEventRecord(l->ev_out, l->stream);
+    (void)hipStreamWaitEvent(l->user_stream, l->ev_out, 0);
+  }
+};
+
+// kappa * eta^{+-}_nu (Section 1): e^{+-mu} on the time hops only.
+Hop make_hop(double m_w, double mu) {
+  Hop h;
+  const double k = 1.0 / (8.0 + 2.0 * m_w);
+  for (int nu = 0; nu < 4; ++nu) {
+    h.fwd[nu] = (nu == 3) ? k * std::exp(mu) : k;
+    h.bwd[nu] = (nu == 3) ? k * std::exp(-mu) : k;
+    h.f32_fwd[nu] = (float)h.fwd[nu];
+    h.f32_bwd[nu] = (float)h.bwd[nu];
+  }
+  return h;
+}
+
+void op_setup(const ovs_lattice_s* l, ovs_op op, Hop& h, bool& g5in, bool& g5out) {
+  switch (op) {
+    case OVS_OP_DW: h = make_hop(l->m_w, l->mu); g5in = false; g5out = false; break;
+    case OVS_OP_A: h = make_hop(l->m_w, l->mu); g5in = false; g5out = true; break;
+    case OVS_OP_A_DAG: h = make_hop(l->m_w, -l->mu); g5in = false; g5out = true; break;
+    default: h = make_hop(l->m_w, -l->mu); g5in = true; g5out = true; break;  // Dw^dag
+  }
+}
+
+bool valid_op(int op) { return op >= 0 && op <= 3; }
+
+size_t elem_bytes(const ovs_lattice_s* l) { return l->prec == OVS_F32_STORE ? 8 : 16; }
+
+bool block_ok(bool f32, int b) {
+  return f32 ? (b == 1 || b == 2 || b == 3 || b == 4 || b == 6) : (b == 1 || b == 2 || b == 3);
+}
+bool dual_block_ok(bool f32, int b) { return f32 ? (b >= 1 && b <= 4) : (b == 1 || b == 2); }
+
+Tuning get_tuning(const ovs_lattice_s* l, int nrhs) {
+  for (auto& p : l->tuning)
+    if (p.first == nrhs) return p.second;
+  Tuning t;
+  const bool f32 = l->prec == OVS_F32_STORE;
+  t.rhs_block = f32 ? (nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1)) : 1;
+  t.wg = 256;
+  return t;
+}
+
+int get_dual_block(const ovs_lattice_s* l, int nrhs) {
+  for (auto& p : l->dual_block)
+    if (p.first == nrhs) return p.second;
+  return 1;
+}
+
+void set_tuning(ovs_lattice_s* l, int nrhs, const Tuning& t) {
+  for (auto& p : l->tuning)
+    if (p.first == nrhs) { p.second = t; return; }
+  l->tuning.push_back({nrhs, t});
+}
+void set_dual_block(ovs_lattice_s* l, int nrhs, int b) {
+  for (auto& p : l->dual_block)
+    if (p.first == nrhs) { p.second = b; return; }
+  l->dual_block.push_back({nrhs, b});
+}
+
+// Bump allocator over the cached workspace (or a sizing pass with base == nullptr).
+struct Arena {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+ovs_status ensure_ws(ovs_lattice_s* l, size_t bytes) {
+  if (l->ws && l->ws_bytes >= bytes) return OVS_OK;
+  if (l->ws) {
+    OVS_HIP(hipStreamSynchronize(l->stream));
+    (void)hipFree(l->ws);
+    l->ws = nullptr;
+    l->ws_bytes = 0;
+  }
+  if (hipMalloc(&l->ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    l->ws = nullptr;
+    return OVS_ERR_ALLOC;
+  }
+  l->ws_bytes = bytes;
+  return OVS_OK;
+}
+
+void pack_field(const ovs_lattice_s* l, const void* canon, void* field, int nrhs) {
+  if (l->prec == OVS_F32_STORE)
+    launch_pack_f32((const double2*)canon, (float2*)field, nrhs, l->g.V, l->stream);
+  else
+    launch_pack_f64((const double2*)canon, (double2*)field, nrhs, l->g.V, l->stream);
+}
+void unpack_field(const ovs_lattice_s* l, const void* field, void* canon, int nrhs) {
+  if (l->prec == OVS_F32_STORE)
+    launch_unpack_f32((const float2*)field, (double2*)canon, nrhs, l->g.V, l->stream);
+  else
+    launch_unpack_f64((const double2*)field, (double2*)canon, nrhs, l->g.V, l->stream);
+}
+
+bool ready(const ovs_lattice_s* l) { return l && l->links_set && l->params_set; }
+
+// ---- inner sign with step refinement ----------------------------------------
+constexpr double kULo = -40.0, kUHi = 45.0;  // u range of the tau = e^u quadrature
+constexpr double kHStart = 0.25, kHMin = 0.0625;
+constexpr double kQuadAccept = 3e-7;  // coarse/fine difference accepted at step h
+
+void quad_range(double h, int& n0, int& nnode) {
+  n0 = (int)std::floor(kULo / h);
+  const int n1 = (int)std::ceil(kUHi / h);
+  nnode = n1 - n0 + 1;
+}
+int max_nodes() {
+  int n0, nn;
+  quad_range(kHMin, n0, nn);
+  return nn;
+}
+
+struct InnerScratch {
+  double2* mult = nullptr;
+  unsigned char* swp = nullptr;
+  double2* part = nullptr;
+  double2* ys = nullptr;
+};
+
+// Runs the quadrature at h = 0.25 and halves h while the coarse/fine
+// difference of any source exceeds kQuadAccept (down to h = 1/16).
+ovs_status inner_sign(ovs_lattice_s* l, bool tri, const double2* alpha, const double* beta,
+                      const double2* gamma, const double2* H, int kmax, const int* kvec_dev,
+                      int nrhs, InnerScratch& sc, double2* x, double* err_dev,
+                      std::vector<double>& err_host) {
+  double h = kHStart;
+  err_host.assign(nrhs, 0.0);
+  for (;;) {
+    int n0, nn;
+    quad_range(h, n0, nn);
+    if (tri)
+      launch_isign_tri(alpha, beta, gamma, kmax, kvec_dev, nrhs, h, n0, nn, sc.mult, sc.swp,
+                       sc.part, x, err_dev, l->stream);
+    else
+      launch_isign_hess(H, kmax, kvec_dev, nrhs, h, n0, nn, sc.ys, x, err_dev, l->stream);
+    OVS_HIP(hipGetLastError());
+    OVS_HIP(hipMemcpyAsync(err_host.data(), err_dev, sizeof(double) * nrhs, hipMemcpyDeviceToHost,
+                           l->stream));
+    OVS_HIP(hipStreamSynchronize(l->stream));
+    double emax = 0.0;
+    for (double e : err_host) emax = std::max(emax, std::isfinite(e) ? e : 1e300);
+    if (emax <= kQuadAccept || h <= kHMin) break;
+    h *= 0.5;
+  }
+  return OVS_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* ovs_status_string(ovs_status s) {
+  switch (s) {
+    case OVS_OK: return "ok";
+    case OVS_WARN_NOT_CONVERGED: return "not converged within k_max";
+    case OVS_WARN_BREAKDOWN: return "serious Lanczos breakdown";
+    case OVS_WARN_SIGN_AMBIGUOUS: return "inner sign quadrature not converged (eigenvalue near the imaginary axis)";
+    case OVS_ERR_ARG: return "invalid argument";
+    case OVS_ERR_HIP: return "HIP runtime error";
+    case OVS_ERR_ALLOC: return "device allocation failed";
+    case OVS_ERR_STATE: return "handle not ready (links or parameters not set)";
+    default: return "unknown status";
+  }
+}
+
+ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_precision prec,
+                              void* hip_stream, ovs_lattice* out) {
+  if (!dims || !bc || !out) return OVS_ERR_ARG;
+  *out = nullptr;
+  long v = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (dims[i] < 2 || dims[i] > 4096) return OVS_ERR_ARG;
+    if (bc[i] != 1 && bc[i] != -1) return OVS_ERR_ARG;
+    v *= dims[i];
+  }
+  if (v >= (1L << 26)) return OVS_ERR_ARG;
+  if (prec != OVS_F64 && prec != OVS_F32_STORE) return OVS_ERR_ARG;
+  ovs_lattice_s* l = new (std::nothrow) ovs_lattice_s();
+  if (!l) return OVS_ERR_ALLOC;
+  l->g = Geometry{dims[0], dims[1], dims[2], dims[3], (int)v};
+  for (int i = 0; i < 4; ++i) l->bc[i] = bc[i];
+  l->prec = prec;
+  l->user_stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&l->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&l->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&l->ev_out, hipEventDisableTiming) != hipSuccess) {
+    delete l;
+    return OVS_ERR_HIP;
+  }
+  const size_t lb = 4ul * 9 * v * elem_bytes(l);
+  if (hipMalloc(&l->links, lb) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamDestroy(l->stream);
+    delete l;
+    return OVS_ERR_ALLOC;
+  }
+  *out = l;
+  return OVS_OK;
+}
+
+ovs_status ovs_lattice_destroy(ovs_lattice l) {
+  if (!l) return OVS_ERR_ARG;
+  (void)hipStreamSynchronize(l->stream);
+  if (l->links) (void)hipFree(l->links);
+  if (l->ws) (void)hipFree(l->ws);
+  (void)hipEventDestroy(l->ev_in);
+  (void)hipEventDestroy(l->ev_out);
+  (void)hipStreamDestroy(l->stream);
+  delete l;
+  return OVS_OK;
+}
+
+ovs_status ovs_set_links(ovs_lattice l, const void* U) {
+  if (!l || !U) return OVS_ERR_ARG;
+  StreamScope sc(l);
+  launch_pack_links((const double2*)U, l->links, l->prec == OVS_F32_STORE, l->g, l->bc, l->stream);
+  OVS_HIP(hipGetLastError());
+  l->links_set = true;
+  return OVS_OK;
+}
+
+ovs_status ovs_set_params(ovs_lattice l, double m_w, double mu) {
+  if (!l) return OVS_ERR_ARG;
+  if (!std::isfinite(m_w) || !std::isfinite(mu) || !(8.0 + 2.0 * m_w > 0.0)) return OVS_ERR_ARG;
+  l->m_w = m_w;
+  l->mu = mu;
+  l->params_set = true;
+  return OVS_OK;
+}
+
+ovs_status ovs_apply(ovs_lattice l, ovs_op op, const void* x, void* y, int32_t nrhs) {
+  if (!l || !x || !y || x == y || nrhs < 1 || nrhs > kMaxNrhs || !valid_op(op)) return OVS_ERR_ARG;
+  if (!ready(l)) return OVS_ERR_STATE;
+  const size_t fb = (size_t)nrhs * 12 * l->g.V * elem_bytes(l);
+  ovs_status st = ensure_ws(l, 2 * fb + 512);
+  if (st != OVS_OK) return st;
+  StreamScope sc(l);
+  Arena a{(char*)l->ws};
+  void* fin = a.take<char>(fb);
+  void* fout = a.take<char>(fb);
+  Hop h;
+  bool g5in, g5out;
+  op_setup(l, op, h, g5in, g5out);
+  pack_field(l, x, fin, nrhs);
+  OVS_HIP(launch_wilson(l->prec == OVS_F32_STORE, l->links, fin, fout, nrhs, l->g, h, g5in, g5out,
+                        get_tuning(l, nrhs), l->stream));
+  unpack_field(l, fout, y, nrhs);
+  OVS_HIP(hipGetLastError());
+  return OVS_OK;
+}
+
+// ---- resident fields ---------------------------------------------------------
+
+ovs_status ovs_field_create(ovs_lattice l, int32_t nrhs, ovs_field* out) {
+  if (!l || !out || nrhs < 1 || nrhs > kMaxNrhs) return OVS_ERR_ARG;
+  ovs_field_s* f = new (std::nothrow) ovs_field_s();
+  if (!f) return OVS_ERR_ALLOC;
+  f->lat = l;
+  f->nrhs = nrhs;
+  if (hipMalloc(&f->data, (size_t)nrhs * 12 * l->g.V * elem_bytes(l)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete f;
+    return OVS_ERR_ALLOC;
+  }
+  *out = f;
+  return OVS_OK;
+}
+
+ovs_status ovs_field_destroy(ovs_field f) {
+  if (!f) return OVS_ERR_ARG;
+  (void)hipStreamSynchronize(f->lat->stream);
+  (void)hipFree(f->data);
+  delete f;
+  return OVS_OK;
+}
+
+ovs_status ovs_field_import(ovs_field f, const void* x) {
+  if (!f || !x) return OVS_ERR_ARG;
+  StreamScope sc(f->lat);
+  pack_field(f->lat, x, f->data, f->nrhs);
+  OVS_HIP(hipGetLastError());
+  return OVS_OK;
+}
+
+ovs_status ovs_field_export(ovs_field f, void* x) {
+  if (!f || !x) return OVS_ERR_ARG;
+  StreamScope sc(f->lat);
+  unpack_field(f->lat, f->data, x, f->nrhs);
+  OVS_HIP(hipGetLastError());
+  return OVS_OK;
+}
+
+static ovs_status field_apply_nosync(ovs_lattice l, ovs_op op, ovs_field in, ovs_field out,
+                                     const Tuning& tn) {
+  Hop h;
+  bool g5in, g5out;
+  op_setup(l, op, h, g5in, g5out);
+  OVS_HIP(launch_wilson(l->prec == OVS_F32_STORE, l->links, in->data, out->data, in->nrhs, l->g, h,
+                        g5in, g5out, tn, l->stream));
+  return OVS_OK;
+}
+
+static bool fields_ok(ovs_lattice l, ovs_op op, ovs_field in, ovs_field out) {
+  return l && in && out && in != out && in->lat == l && out->lat == l && in->nrhs == out->nrhs &&
+         valid_op(op);
+}
+
+ovs_status ovs_field_apply(ovs_lattice l, ovs_op op, ovs_field in, ovs_field out) {
+  if (!fields_ok(l, op, in, out)) return OVS_ERR_ARG;
+  if (!ready(l)) return OVS_ERR_STATE;
+  StreamScope sc(l);
+  return field_apply_nosync(l, op, in, out, get_tuning(l, in->nrhs));
+}
+
+static ovs_status timed_loop(ovs_lattice l, ovs_op op, ovs_field in, ovs_field out, int iters,
+                             const Tuning& tn, double* ms) {
+  hipEvent_t e0, e1;
+  OVS_HIP(hipEventCreate(&e0));
+  OVS_HIP(hipEventCreate(&e1));
+  ovs_status st = OVS_OK;
+  (void)hipEventRecord(e0, l->stream);
+  for (int i = 0; i < iters && st == OVS_OK; ++i) st = field_apply_nosync(l, op, in, out, tn);
+  (void)hipEventRecord(e1, l->stream);
+  (void)hipEventSynchronize(e1);
+  float f = 0.f;
+  (void)hipEventElapsedTime(&f, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = (double)f / iters;
+  return st;
+}
+
+ovs_status ovs_field_apply_timed(ovs_lattice l, ovs_op op, ovs_field in, ovs_field out,
+                                 int32_t iters, double* ms_per_apply) {
+  if (!fields_ok(l, op, in, out) || iters < 1 || !ms_per_apply) return OVS_ERR_ARG;
+  if (!ready(l)) return OVS_ERR_STATE;
+  StreamScope sc(l);
+  return timed_loop(l, op, in, out, iters, get_tuning(l, in->nrhs), ms_per_apply);
+}
+
+ovs_status ovs_get_tuning(ovs_lattice l, int32_t nrhs, int32_t* rhs_block, int32_t* wg_size) {
+  if (!l || nrhs < 1) return OVS_ERR_ARG;
+  Tuning t = get_tuning(l, nrhs);
+  if (rhs_block) *rhs_block = t.rhs_block;
+  if (wg_size) *wg_size = t.wg;
+  return OVS_OK;
+}
+
+ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
+  if (!l || nrhs < 1 || nrhs > kMaxNrhs) return OVS_ERR_ARG;
+  if (!ready(l)) return OVS_ERR_STATE;
+  const bool f32 = l->prec == OVS_F32_STORE;
+  ovs_field fi = nullptr, fo = nullptr;
+  ovs_status st = ovs_field_create(l, nrhs, &fi);
+  if (st != OVS_OK) return st;
+  st = ovs_field_create(l, nrhs, &fo);
+  if (st != OVS_OK) { ovs_field_destroy(fi); return st; }
+  {
+    StreamScope sc(l);
+    // deterministic non-zero contents: zero then the links' bytes do not matter for timing
+    (void)hipMemsetAsync(fi->data, 0, (size_t)nrhs * 12 * l->g.V * elem_bytes(l), l->stream);
+    const int blocks_f32[] = {1, 2, 3, 4, 6};
+    const int blocks_f64[] = {1, 2, 3};
+    const int wgs[] = {64, 128, 256};
+    Tuning best = get_tuning(l, nrhs);
+    double best_ms = 1e300;
+    const int* bl = f32 ? blocks_f32 : blocks_f64;
+    const int nb = f32 ? 5 : 3;
+    for (int ib = 0; ib < nb && st == OVS_OK; ++ib) {
+      if (bl[ib] > nrhs && bl[ib] != 1) continue;
+      for (int w : wgs) {
+        Tuning t;
+        t.rhs_block = bl[ib];
+        t.wg = w;
+        double ms = 0;
+        st = timed_loop(l, OVS_OP_A, fi, fo, 3, t, &ms);
+        if (st != OVS_OK) break;
+        st = timed_loop(l, OVS_OP_A, fi, fo, 10, t, &ms);
+        if (st != OVS_OK) break;
+        if (ms < best_ms) { best_ms = ms; best = t; }
+      }
+    }
+    best.tuned = true;
+    if (st == OVS_OK) set_tuning(l, nrhs, best);
+    // dual-stencil source block for the Lanczos step
+    if (st == OVS_OK) {
+      const long N = 12L * l->g.V;
+      const size_t fb = (size_t)nrhs * N * elem_bytes(l);
+      const int nwg = dual_num_wg(l->g);
+      Arena a{nullptr};
+      a.take<char>(fb); a.take<char>(3 * fb); a.take<char>(fb); a.take<char>(fb);
+      a.take<double>((size_t)nrhs * nwg * 3); a.take<int>(nrhs); a.take<int>(2);
+      st = ensure_ws(l, a.off + 4096);
+      if (st == OVS_OK) {
+        Arena b{(char*)l->ws};
+        void* basis = b.take<char>(fb);
+        void* wbuf = b.take<char>(3 * fb);
+        void* T = b.take<char>(fb);
+        void* S = b.take<char>(fb);
+        double* part = b.take<double>((size_t)nrhs * nwg * 3);
+        int* map = b.take<int>(nrhs);
+        int* ints = b.take<int>(2);
+        std::vector<int> hmap(nrhs);
+        for (int i = 0; i < nrhs; ++i) hmap[i] = i;
+        int hints[2] = {0, nrhs};
+        (void)hipMemcpyAsync(map, hmap.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, l->stream);
+        (void)hipMemcpyAsync(ints, hints, sizeof(hints), hipMemcpyHostToDevice, l->stream);
+        (void)hipMemsetAsync(basis, 0, fb, l->stream);
+        (void)hipMemsetAsync(wbuf, 0, 3 * fb, l->stream);
+        DualArgs da{l->links, basis, wbuf, (long)nrhs * N, false, ints, T, S, part, map, ints + 1, nrhs};
+        const Hop hA = make_hop(l->m_w, l->mu), hAd = make_hop(l->m_w, -l->mu);
+        int best_b = 1;
+        double bms = 1e300;
+        for (int bb = 1; bb <= (f32 ? 4 : 2); ++bb) {
+          if (bb > nrhs && bb != 1) continue;
+          hipEvent_t e0, e1;
+          (void)hipEventCreate(&e0);
+          (void)hipEventCreate(&e1);
+          for (int w = 0; w < 2; ++w) (void)launch_dual(f32, da, l->g, hA, hAd, bb, l->stream);
+          (void)hipEventRecord(e0, l->stream);
+          for (int w = 0; w < 8; ++w) (void)launch_dual(f32, da, l->g, hA, hAd, bb, l->stream);
+          (void)hipEventRecord(e1, l->stream);
+          (void)hipEventSynchronize(e1);
+          float f = 0;
+          (void)hipEventElapsedTime(&f, e0, e1);
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          if (f < bms) { bms = f; best_b = bb; }
+        }
+        if (hipGetLastError() != hipSuccess) st = OVS_ERR_HIP;
+        else set_dual_block(l, nrhs, best_b);
+      }
+    }
+    (void)hipStreamSynchronize(l->stream);
+  }
+  ovs_field_destroy(fi);
+  ovs_field_destroy(fo);
+  return st;
+}
+
+// ---- deflation -------------------------------------------------------------------
+
+ovs_status ovs_deflation_set(ovs_lattice l, int32_t m, const double* lambda, const void* R,
+                             const void* L, ovs_deflation* out) {
+  if (!l || !out || m < 1 || m > kMaxDefl || !lambda || !R || !L) return OVS_ERR_ARG;
+  *out = nullptr;
+  for (int j = 0; j < 2 * m; ++j)
+    if (!std::isfinite(lambda[j])) return OVS_ERR_ARG;
+  const long N = 12L * l->g.V;
+  ovs_deflation_s* d = new (std::nothrow) ovs_deflation_s();
+  if (!d) return OVS_ERR_ALLOC;
+  d->lat = l;
+  d->m = m;
+  d->lambda.assign(lambda, lambda + 2 * m);
+  d->R = d->L = nullptr;
+  d->sgn = nullptr;
+  if (hipMalloc(&d->R, sizeof(double2) * m * N) != hipSuccess ||
+      hipMalloc(&d->L, sizeof(double2) * m * N) != hipSuccess ||
+      hipMalloc(&d->sgn, sizeof(double) * m) != hipSuccess) {
+    (void)hipGetLastError();
+    ovs_deflation_destroy(d);
+    return OVS_ERR_ALLOC;
+  }
+  ovs_status st = OVS_OK;
+  {
+    StreamScope sc(l);
+    launch_pack_f64((const double2*)R, d->R, m, l->g.V, l->stream);
+    launch_pack_f64((const double2*)L, d->L, m, l->g.V, l->stream);
+    std::vector<double> sg(m);
+    for (int j = 0; j < m; ++j) sg[j] = (lambda[2 * j] >= 0.0) ? 1.0 : -1.0;
+    (void)hipMemcpyAsync(d->sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice, l->stream);
+    // check L^dagger R = I
+    double *part = nullptr, *cd = nullptr;
+    const int nch = defl_nchunk(N);
+    if (hipMalloc(&part, sizeof(double) * (size_t)m * m * nch * 4) != hipSuccess ||
+        hipMalloc(&cd, sizeof(double) * (size_t)m * m * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      st = OVS_ERR_ALLOC;
+    } else {
+      launch_defl_cd(d->R, d->L, d->R, m, m, N, part, cd, l->stream);
+      std::vector<double> h((size_t)m * m * 4);
+      (void)hipMemcpyAsync(h.data(), cd, h.size() * sizeof(double), hipMemcpyDeviceToHost, l->stream);
+      if (hipStreamSynchronize(l->stream) != hipSuccess) st = OVS_ERR_HIP;
+      double dev = 0.0;
+      for (int j = 0; j < m; ++j)
+        for (int r = 0; r < m; ++r) {
+          const double* c = &h[((size_t)j * m + r) * 4];
+          const double re = c[0] - (j == r ? 1.0 : 0.0);
+          dev = std::max(dev, std::hypot(re, c[1]));
+        }
+      if (st == OVS_OK && !(dev <= 1e-8)) st = OVS_ERR_ARG;
+    }
+    if (part) (void)hipFree(part);
+    if (cd) (void)hipFree(cd);
+  }
+  if (st != OVS_OK) {
+    ovs_deflation_destroy(d);
+    return st;
+  }
+  *out = d;
+  return OVS_OK;
+}
+
+ovs_status ovs_deflation_destroy(ovs_deflation d) {
+  if (!d) return OVS_ERR_ARG;
+  (void)hipStreamSynchronize(d->lat->stream);
+  if (d->R) (void)hipFree(d->R);
+  if (d->L) (void)hipFree(d->L);
+  if (d->sgn) (void)hipFree(d->sgn);
+  delete d;
+  return OVS_OK;
+}
+
+// ---- sign function ------------------------------------------------------------------
+
+ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
+                          void* y, int32_t nrhs, int32_t k_max, const double* tol,
+                          ovs_method method, int32_t flags, ovs_rhs_info* info) {
+  if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || k_max < 1) return OVS_ERR_ARG;
+  if (!ready(l)) return OVS_ERR_STATE;
+  if (method != OVS_2SL && method != OVS_ARNOLDI) return OVS_ERR_ARG;
+  if (flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_OVERLAP)) return OVS_ERR_ARG;
+  const long N = 12L * l->g.V;
+  if (k_max > N) return OVS_ERR_ARG;
+  int m = 0;
+  if (defl) {
+    if (defl->lat != l || n_defl < 0 || n_defl > defl->m) return OVS_ERR_ARG;
+    m = n_defl;
+  }
+  const bool arn = method == OVS_ARNOLDI;
+  const bool two_pass = (flags & OVS_FLAG_TWO_PASS) != 0;
+  const bool use_graph = (flags & OVS_FLAG_GRAPH) != 0;
+  if (arn && (two_pass || k_max > kHessMaxK)) return OVS_ERR_ARG;
+  if (tol)
+    for (int r = 0; r < nrhs; ++r)
+      if (!(tol[r] > 0.0)) return OVS_ERR_ARG;
+  const bool f32 = l->prec == OVS_F32_STORE;
+  const size_t es = elem_bytes(l);
+  const int K = k_max, nr = nrhs;
+  const int nslots = two_pass ? 3 : K;
+  const int nwg_d = dual_num_wg(l->g), nwg_u = update_nwg(N);
+  const int nwave_max = isign_tri_nwave(max_nodes());
+  const int nq_max = 2 * max_nodes();
+  const int nch_start = 512, nch_arn = arn_nchunk(N);
+
+  // ---- workspace layout (sizing pass, then the real one) ----
+  struct Bufs {
+    double2 *Bq, *bR, *bL, *yex, *Y;
+    char *basis, *wbuf, *T, *S;
+    double *part1, *part2, *dpart, *CD, *spart, *sums, *sumsb, *nb;
+    double2 *alpha, *gamma, *sw, *coef, *x, *mult, *part, *H, *hcur, *ys;
+    double *beta, *sv, *tnorm2, *qerr, *red, *apart, *red_n, *red_tn, *scl;
+    int *kstop, *status, *rhs_map, *ints, *kused;
+    unsigned char* swp;
+  } B{};
+  auto layout = [&](Arena& a) {
+    B.Bq = a.take<double2>((size_t)nr * N);
+    if (m > 0) {
+      B.bR = a.take<double2>((size_t)nr * N);
+      B.bL = a.take<double2>((size_t)nr * N);
+      B.yex = a.take<double2>((size_t)nr * N);
+      B.dpart = a.take<double>((size_t)m * nr * defl_nchunk(N) * 4);
+      B.CD = a.take<double>((size_t)m * nr * 4);
+    }
+    B.Y = a.take<double2>((size_t)nr * N);
+    B.basis = a.take<char>((size_t)nslots * nr * N * es);
+    if (!arn) B.wbuf = a.take<char>(3ul * nr * N * es);
+    B.T = a.take<char>((size_t)nr * N * es);
+    if (!arn) B.S = a.take<char>((size_t)nr * N * es);
+    B.part1 = a.take<double>((size_t)nr * nwg_d * 3);
+    B.part2 = a.take<double>((size_t)nr * nwg_u * 4);
+    B.spart = a.take<double>((size_t)nr * nch_start * 3);
+    B.sums = a.take<double>((size_t)nr * 3);
+    B.sumsb = a.take<double>((size_t)nr * 3);
+    B.nb = a.take<double>(nr);
+    B.alpha = a.take<double2>((size_t)nr * K);
+    B.beta = a.take<double>((size_t)nr * K);
+    B.gamma = a.take<double2>((size_t)nr * K);
+    B.sv = a.take<double>((size_t)nr * (K + 1));
+    B.sw = a.take<double2>((size_t)nr * (K + 1));
+    B.tnorm2 = a.take<double>((size_t)nr * K);
+    B.kstop = a.take<int>(nr);
+    B.status = a.take<int>(nr);
+    B.rhs_map = a.take<int>(nr);
+    B.ints = a.take<int>(4);
+    B.kused = a.take<int>(nr);
+    B.x = a.take<double2>((size_t)nr * K);
+    B.qerr = a.take<double>(nr);
+    B.coef = a.take<double2>((size_t)nr * K);
+    if (!arn) {
+      B.mult = a.take<double2>((size_t)nr * nwave_max * K * 64);
+      B.swp = a.take<unsigned char>((size_t)nr * nwave_max * K * 64);
+      B.part = a.take<double2>((size_t)nr * nwave_max * 2 * K);
+    } else {
+      B.H = a.take<double2>((size_t)nr * K * K);
+      B.hcur = a.take<double2>((size_t)nr * K);
+      B.red = a.take<double>((size_t)nr * K * 2);
+      B.apart = a.take<double>((size_t)nr * K * nch_arn * 2);
+      B.red_n = a.take<double>(nr);
+      B.red_tn = a.take<double>(nr);
+      B.scl = a.take<double>(nr);
+      B.ys = a.take<double2>((size_t)nr * nq_max * K);
+    }
+  };
+  {
+    Arena sizing{nullptr};
+    layout(sizing);
+    ovs_status st = ensure_ws(l, sizing.off + 4096);
+    if (st != OVS_OK) return st;
+    Arena real{(char*)l->ws};
+    layout(real);
+  }
+  if (m == 0) {
+    B.bR = B.Bq;
+    B.bL = B.Bq;
+    B.yex = nullptr;
+  }
+
+  StreamScope scope(l);
+  hipStream_t s = l->stream;
+  hipEvent_t ev[5];
+  for (auto& e : ev) OVS_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]); }
+  } evg{ev};
+  const long bstride = (long)nr * N;  // elements between basis entries
+  const Hop hA = make_hop(l->m_w, l->mu), hAd = make_hop(l->m_w, -l->mu);
+
+  // ---- deflation and start vectors ----
+  OVS_HIP(hipEventRecord(ev[0], s));
+  launch_pack_f64((const double2*)b, B.Bq, nr, l->g.V, s);
+  if (m > 0)
+    launch_defl(defl->R, defl->L, B.Bq, defl->sgn, m, nr, N, B.dpart, B.CD, B.bR, B.bL, B.yex, s);
+  launch_start(B.bR, B.bL, nr, N, B.spart, B.sums, B.basis, arn ? nullptr : B.wbuf, f32, s);
+  if (m > 0) launch_start(B.Bq, B.Bq, nr, N, B.spart, B.sumsb, nullptr, nullptr, f32, s);
+  OVS_HIP(hipGetLastError());
+  std::vector<double> sums(nr * 3), sumsb(nr * 3);
+  OVS_HIP(hipMemcpyAsync(sums.data(), B.sums, sizeof(double) * nr * 3, hipMemcpyDeviceToHost, s));
+  if (m > 0)
+    OVS_HIP(hipMemcpyAsync(sumsb.data(), B.sumsb, sizeof(double) * nr * 3, hipMemcpyDeviceToHost, s));
+  OVS_HIP(hipEventRecord(ev[1], s));
+  OVS_HIP(hipStreamSynchronize(s));
+  if (m == 0) sumsb = sums;
+  std::vector<double> nbh(nr), bnorm(nr);
+  std::vector<int> hstatus(nr, 0), hkstop(nr, K);
+  std::vector<char> done(nr, 0);
+  std::vector<int> kused(nr, K);
+  for (int r = 0; r < nr; ++r) {
+    if (!std::isfinite(sums[3 * r]) || !std::isfinite(sumsb[3 * r])) return OVS_ERR_ARG;  // NaN/Inf in b
+    nbh[r] = std::sqrt(sums[3 * r]);
+    bnorm[r] = std::sqrt(sumsb[3 * r]);
+    if (nbh[r] == 0.0) {  // source entirely in the deflation space (or zero)
+      done[r] = 1;
+      kused[r] = 0;
+    } else if (sums[3 * r + 1] == 0.0 && sums[3 * r + 2] == 0.0) {
+      done[r] = 1;
+      kused[r] = 0;
+      hstatus[r] = 2;
+    }
+  }
+  OVS_HIP(hipMemcpyAsync(B.nb, nbh.data(), sizeof(double) * nr, hipMemcpyHostToDevice, s));
+
+  // ---- coefficient arrays ----
+  {
+    std::vector<double> sv((size_t)nr * (K + 1), 0.0), sw((size_t)nr * (K + 1) * 2, 0.0);
+    for (int r = 0; r < nr; ++r) {
+      sv[(size_t)r * (K + 1)] = 1.0;
+      sw[(size_t)r * (K + 1) * 2] = 1.0;
+    }
+    OVS_HIP(hipMemcpyAsync(B.sv, sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    OVS_HIP(hipMemcpyAsync(B.sw, sw.data(), sw.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    OVS_HIP(hipMemsetAsync(B.alpha, 0, sizeof(double2) * nr * K, s));
+    OVS_HIP(hipMemsetAsync(B.beta, 0, sizeof(double) * nr * K, s));
+    OVS_HIP(hipMemsetAsync(B.gamma, 0, sizeof(double2) * nr * K, s));
+    OVS_HIP(hipMemsetAsync(B.tnorm2, 0, sizeof(double) * nr * K, s));
+    OVS_HIP(hipMemcpyAsync(B.kstop, hkstop.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+    OVS_HIP(hipMemcpyAsync(B.status, hstatus.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+    if (arn) OVS_HIP(hipMemsetAsync(B.H, 0, sizeof(double2) * nr * K * K, s));
+  }
+  CoefArrays co{B.alpha, B.beta, B.gamma, B.sv, B.sw, B.tnorm2, B.kstop, B.status, K};
+
+  std::vector<double> est(nr, 0.0), qerr(nr, 0.0);
+  InnerScratch isc{B.mult, B.swp, B.part, B.ys};
+  std::vector<double> errh;
+
+  if (!arn) {
+    // ---- two-sided Lanczos (Section 4) ----
+    std::vector<int> amap;
+    auto push_map = [&]() -> ovs_status {
+      amap.clear();
+      for (int r = 0; r < nr; ++r)
+        if (!done[r]) amap.push_back(r);
+      std::vector<int> full(nr, 0);
+      std::copy(amap.begin(), amap.end(), full.begin());
+      OVS_HIP(hipMemcpyAsync(B.rhs_map, full.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+      int na = (int)amap.size();
+      OVS_HIP(hipMemcpyAsync(B.ints + 1, &na, sizeof(int), hipMemcpyHostToDevice, s));
+      OVS_HIP(hipStreamSynchronize(s));  // host vector lifetime
+      return OVS_OK;
+    };
+    int zero = 0;
+    OVS_HIP(hipMemcpyAsync(B.ints, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    ovs_status st = push_map();
+    if (st != OVS_OK) return st;
+    const int dual_b = std::min(get_dual_block(l, nr), f32 ? 4 : 2);
+    DualArgs da{l->links, B.basis, B.wbuf, bstride, two_pass, B.ints, B.T, B.S, B.part1,
+                B.rhs_map, B.ints + 1, nr};
+    auto enqueue_iter = [&](bool full) -> ovs_status {
+      OVS_HIP(launch_dual(f32, da, l->g, hA, hAd, dual_b, s));
+      launch_alpha(B.part1, nwg_d, co, B.ints, B.rhs_map, B.ints + 1, nr, s);
+      if (full) {
+        launch_update(f32, B.T, B.S, B.basis, bstride, B.wbuf, N, co, B.ints, B.rhs_map,
+                      B.ints + 1, nr, B.part2, two_pass, s);
+        launch_beta(B.part2, nwg_u, co, B.ints, B.rhs_map, B.ints + 1, nr, s);
+      }
+      launch_advance(B.ints, s);
+      OVS_HIP(hipGetLastError());
+      return OVS_OK;
+    };
+    const int chunk = 25;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    struct GraphGuard {
+      hipGraph_t* g;
+      hipGraphExec_t* x;
+      ~GraphGuard() {
+        if (*x) (void)hipGraphExecDestroy(*x);
+        if (*g) (void)hipGraphDestroy(*g);
+      }
+    } gg{&graph, &gexec};
+    std::vector<std::vector<double>> xprev(nr);
+    int i = 0;
+    while (i < K && !amap.empty()) {
+      const int iend = tol ? std::min(K, (i / chunk + 1) * chunk) : K;
+      // full iterations are those with i < K-1; the last one only forms alpha
+      int nfull = std::min(iend, K - 1) - i;
+      if (nfull < 0) nfull = 0;
+      int done_it = 0;
+      if (use_graph && nfull >= chunk) {
+        if (!gexec) {
+          OVS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          for (int c = 0; c < chunk; ++c) {
+            st = enqueue_iter(true);
+            if (st != OVS_OK) break;
+          }
+          hipError_t ce = hipStreamEndCapture(s, &graph);
+          if (st != OVS_OK) return st;
+          OVS_HIP(ce);
+          OVS_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+        while (nfull - done_it >= chunk) {
+          OVS_HIP(hipGraphLaunch(gexec, s));
+          done_it += chunk;
+        }
+      }
+      for (; done_it < nfull; ++done_it) {
+        st = enqueue_iter(true);
+        if (st != OVS_OK) return st;
+      }
+      if (iend == K) {
+        st = enqueue_iter(false);
+        if (st != OVS_OK) return st;
+      }
+      i = iend;
+      if (tol && i < K) {
+        // convergence check at k = i (paper silent; reading in the design notes)
+        std::vector<int> ks(nr, 0);
+        OVS_HIP(hipMemcpyAsync(hkstop.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+        OVS_HIP(hipStreamSynchronize(s));
+        for (int r : amap) ks[r] = std::min(i, hkstop[r]);
+        OVS_HIP(hipMemcpyAsync(B.kused, ks.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+        st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, B.kused, nr, isc, B.x,
+                        B.qerr, errh);
+        if (st != OVS_OK) return st;
+        std::vector<double> xh((size_t)nr * K * 2);
+        OVS_HIP(hipMemcpyAsync(xh.data(), B.x, sizeof(double2) * nr * K, hipMemcpyDeviceToHost, s));
+        OVS_HIP(hipStreamSynchronize(s));
+        for (int r : amap) {
+          const int kr = ks[r];
+          std::vector<double> xr(xh.begin() + (size_t)r * K * 2, xh.begin() + (size_t)r * K * 2 + 2 * kr);
+          double dn = 0.0;
+          const std::vector<double>& xp = xprev[r];
+          for (int q = 0; q < 2 * kr; ++q) {
+            const double d = xr[q] - (q < (int)xp.size() ? xp[q] : 0.0);
+            dn += d * d;
+          }
+          est[r] = nbh[r] * std::sqrt(dn) / (bnorm[r] > 0 ? bnorm[r] : 1.0);
+          xprev[r] = xr;
+          if (hkstop[r] <= i || (!xp.empty() && est[r] <= 0.1 * tol[r])) {
+            done[r] = 1;
+            kused[r] = kr;
+          }
+        }
+        st = push_map();
+        if (st != OVS_OK) return st;
+      }
+    }
+    OVS_HIP(hipEventRecord(ev[2], s));
+    OVS_HIP(hipMemcpyAsync(hkstop.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipMemcpyAsync(hstatus.data(), B.status, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < nr; ++r) {
+      if (!done[r]) kused[r] = std::min(K, hkstop[r]);
+      else if (kused[r] > 0) kused[r] = std::min(kused[r], hkstop[r]);
+    }
+    OVS_HIP(hipMemcpyAsync(B.kused, kused.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+    st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, B.kused, nr, isc, B.x, B.qerr,
+                    errh);
+    if (st != OVS_OK) return st;
+    qerr = errh;
+    OVS_HIP(hipEventRecord(ev[3], s));
+    launch_make_coef(B.x, B.sv, B.nb, K, nr, B.coef, s);
+    if (!two_pass) {
+      launch_combine(f32, B.basis, bstride, N, B.coef, K, B.kused, B.yex, B.Y, nr, s);
+    } else {
+      // second pass: regenerate v_1..v_k and accumulate (end of Section 5)
+      launch_start(B.bR, B.bL, nr, N, B.spart, B.sums, B.basis, nullptr, f32, s);
+      if (B.yex)
+        OVS_HIP(hipMemcpyAsync(B.Y, B.yex, sizeof(double2) * nr * N, hipMemcpyDeviceToDevice, s));
+      else
+        OVS_HIP(hipMemsetAsync(B.Y, 0, sizeof(double2) * nr * N, s));
+      const int kmx = *std::max_element(kused.begin(), kused.end());
+      Tuning tn = get_tuning(l, nr);
+      for (int it = 0; it < kmx; ++it) {
+        if (it + 1 < kmx)
+          OVS_HIP(launch_wilson(f32, l->links, B.basis + (size_t)(it % 3) * bstride * es, B.T, nr,
+                                l->g, hA, false, true, tn, s));
+        launch_replay(f32, B.T, B.basis, bstride, N, co, it, B.coef, B.kused, B.Y, nr, s);
+      }
+    }
+    OVS_HIP(hipGetLastError());
+    // keep host copies of the coefficients
+    l->last_nrhs = nr;
+    l->last_kmax = K;
+    l->last_alpha.resize((size_t)nr * K * 2);
+    l->last_beta.resize((size_t)nr * K);
+    l->last_gamma.resize((size_t)nr * K * 2);
+    l->last_x.resize((size_t)nr * K * 2);
+    OVS_HIP(hipMemcpyAsync(l->last_alpha.data(), B.alpha, sizeof(double2) * nr * K, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipMemcpyAsync(l->last_beta.data(), B.beta, sizeof(double) * nr * K, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipMemcpyAsync(l->last_gamma.data(), B.gamma, sizeof(double2) * nr * K, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipMemcpyAsync(l->last_x.data(), B.x, sizeof(double2) * nr * K, hipMemcpyDeviceToHost, s));
+  } else {
+    // ---- Arnoldi with classical Gram-Schmidt applied twice (Section 2) ----
+    Tuning tn = get_tuning(l, nr);
+    for (int j = 0; j < K; ++j) {
+      OVS_HIP(launch_wilson(f32, l->links, B.basis + (size_t)j * bstride * es, B.T, nr, l->g, hA,
+                            false, true, tn, s));
+      launch_norm2(f32, B.T, N, nr, B.apart, B.red_tn, s);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_arn_dots(f32, B.basis, bstride, B.T, N, j + 1, nr, B.apart, B.red, s);
+        launch_arn_accum(B.red, j + 1, K, j, pass == 0, B.H, B.hcur, nr, s);
+        launch_arn_axpy(f32, B.basis, bstride, B.T, N, j + 1, B.hcur, K, nr, B.apart, B.red_n, s);
+      }
+      if (j < K - 1) {
+        launch_arn_sub(B.red_n, B.red_tn, B.H, K, j, B.scl, B.kstop, B.status, nr, s);
+        launch_scale_copy(f32, B.T, B.basis + (size_t)(j + 1) * bstride * es, N, B.scl, nr, s);
+      }
+      OVS_HIP(hipGetLastError());
+    }
+    OVS_HIP(hipEventRecord(ev[2], s));
+    OVS_HIP(hipMemcpyAsync(hkstop.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipMemcpyAsync(hstatus.data(), B.status, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < nr; ++r)
+      if (!done[r]) kused[r] = std::min(K, hkstop[r]);
+    OVS_HIP(hipMemcpyAsync(B.kused, kused.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+    ovs_status st = inner_sign(l, false, nullptr, nullptr, nullptr, B.H, K, B.kused, nr, isc, B.x,
+                               B.qerr, errh);
+    if (st != OVS_OK) return st;
+    qerr = errh;
+    OVS_HIP(hipEventRecord(ev[3], s));
+    launch_make_coef(B.x, nullptr, B.nb, K, nr, B.coef, s);
+    launch_combine(f32, B.basis, bstride, N, B.coef, K, B.kused, B.yex, B.Y, nr, s);
+    OVS_HIP(hipGetLastError());
+  }
+  if (flags & OVS_FLAG_OVERLAP) launch_overlap(B.Bq, B.Y, (long)nr * N, l->g.V, s);
+  launch_unpack_f64(B.Y, (double2*)y, nr, l->g.V, s);
+  OVS_HIP(hipEventRecord(ev[4], s));
+  OVS_HIP(hipGetLastError());
+  OVS_HIP(hipStreamSynchronize(s));
+  float t01 = 0, t12 = 0, t23 = 0, t34 = 0;
+  (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
+  (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
+  (void)hipEventElapsedTime(&t23, ev[2], ev[3]);
+  (void)hipEventElapsedTime(&t34, ev[3], ev[4]);
+  ovs_status worst = OVS_OK;
+  for (int r = 0; r < nr; ++r) {
+    int rs = OVS_OK;
+    if (hstatus[r] == 2) rs = OVS_WARN_BREAKDOWN;
+    else if (!(qerr[r] <= 1e-3)) rs = OVS_WARN_SIGN_AMBIGUOUS;
+    else if (tol && !done[r] && hstatus[r] == 0) rs = OVS_WARN_NOT_CONVERGED;
+    if (rs > worst) worst = rs;
+    if (info) {
+      info[r].k_used = kused[r];
+      info[r].status = rs;
+      info[r].est_rel_err = est[r];
+      info[r].quad_err = qerr[r];
+      info[r].n_b = nbh[r];
+      info[r].t_defl_ms = t01;
+      info[r].t_krylov_ms = t12;
+      info[r].t_inner_ms = t23;
+      info[r].t_combine_ms = t34;
+    }
+  }
+  return worst;
+}
+
+ovs_status ovs_last_coefficients(ovs_lattice l, double* alpha, double* beta, double* gamma,
+                                 double* x) {
+  if (!l) return OVS_ERR_ARG;
+  if (l->last_nrhs == 0) return OVS_ERR_STATE;
+  if (alpha) std::memcpy(alpha, l->last_alpha.data(), l->last_alpha.size() * sizeof(double));
+  if (beta) std::memcpy(beta, l->last_beta.data(), l->last_beta.size() * sizeof(double));
+  if (gamma) std::memcpy(gamma, l->last_gamma.data(), l->last_gamma.size() * sizeof(double));
+  if (x) std::memcpy(x, l->last_x.data(), l->last_x.size() * sizeof(double));
+  return OVS_OK;
+}
+
+static ovs_status inner_sign_entry(ovs_lattice l, bool tri, int batch, int k, const double* diag,
+                                   const double* sub, const double* super, const double* Hh,
+                                   double* x, double* err) {
+  if (!l || batch < 1 || k < 1 || !x) return OVS_ERR_ARG;
+  if (tri && (!diag || !sub || !super)) return OVS_ERR_ARG;
+  if (!tri && (!Hh || k > kHessMaxK)) return OVS_ERR_ARG;
+  StreamScope scope(l);
+  hipStream_t s = l->stream;
+  const int nwave = isign_tri_nwave(max_nodes());
+  const int nq = 2 * max_nodes();
+  Arena sizing{nullptr};
+  auto lay = [&](Arena& a, double2*& al, double*& be, double2*& ga, double2*& H, int*& kv,
+                 InnerScratch& sc, double2*& xd, double*& ed) {
+    if (tri) {
+      al = a.take<double2>((size_t)batch * k);
+      be = a.take<double>((size_t)batch * k);
+      ga = a.take<double2>((size_t)batch * k);
+      sc.mult = a.take<double2>((size_t)batch * nwave * k * 64);
+      sc.swp = a.take<unsigned char>((size_t)batch * nwave * k * 64);
+      sc.part = a.take<double2>((size_t)batch * nwave * 2 * k);
+    } else {
+      H = a.take<double2>((size_t)batch * k * k);
+      sc.ys = a.take<double2>((size_t)batch * nq * k);
+    }
+    kv = a.take<int>(batch);
+    xd = a.take<double2>((size_t)batch * k);
+    ed = a.take<double>(batch);
+  };
+  double2 *al = nullptr, *ga = nullptr, *H = nullptr, *xd = nullptr;
+  double *be = nullptr, *ed = nullptr;
+  int* kv = nullptr;
+  InnerScratch sc;
+  lay(sizing, al, be, ga, H, kv, sc, xd, ed);
+  ovs_status st = ensure_ws(l, sizing.off + 4096);
+  if (st != OVS_OK) return st;
+  Arena a{(char*)l->ws};
+  lay(a, al, be, ga, H, kv, sc, xd, ed);
+  std::vector<int> kh(batch, k);
+  OVS_HIP(hipMemcpyAsync(kv, kh.data(), sizeof(int) * batch, hipMemcpyHostToDevice, s));
+  if (tri) {
+    std::vector<double> bre((size_t)batch * k);
+    for (size_t q = 0; q < bre.size(); ++q) {
+      if (sub[2 * q + 1] != 0.0) return OVS_ERR_ARG;  // beta is real in the 2sL reading
+      bre[q] = sub[2 * q];
+    }
+    OVS_HIP(hipMemcpyAsync(al, diag, sizeof(double2) * batch * k, hipMemcpyHostToDevice, s));
+    OVS_HIP(hipMemcpyAsync(be, bre.data(), sizeof(double) * batch * k, hipMemcpyHostToDevice, s));
+    OVS_HIP(hipMemcpyAsync(ga, super, sizeof(double2) * batch * k, hipMemcpyHostToDevice, s));
+    OVS_HIP(hipStreamSynchronize(s));
+  } else {
+    OVS_HIP(hipMemcpyAsync(H, Hh, sizeof(double2) * batch * k * k, hipMemcpyHostToDevice, s));
+  }
+  std::vector<double> eh;
+  st = inner_sign(l, tri, al, be, ga, H, k, kv, batch, sc, xd, ed, eh);
+  if (st != OVS_OK) return st;
+  OVS_HIP(hipMemcpyAsync(x, xd, sizeof(double2) * batch * k, hipMemcpyDeviceToHost, s));
+  OVS_HIP(hipStreamSynchronize(s));
+  if (err) std::memcpy(err, eh.data(), sizeof(double) * batch);
+  return OVS_OK;
+}
+
+ovs_status ovs_inner_sign_tridiag(ovs_lattice l, int32_t batch, int32_t k, const double* diag,
+                                  const double* sub, const double* super, double* x, double* err) {
+  return inner_sign_entry(l, true, batch, k, diag, sub, super, nullptr, x, err);
+}
+
+ovs_status ovs_inner_sign_hessenberg(ovs_lattice l, int32_t batch, int32_t k, const double* H,
+                                     double* x, double* err) {
+  return inner_sign_entry(l, false, batch, k, nullptr, nullptr, nullptr, H, x, err);
+}
+
+}  // extern "C"

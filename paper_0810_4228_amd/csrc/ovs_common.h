@@ -1,0 +1,143 @@
+// Internal declarations shared by the ovsign HIP sources.
+//
+// Device layouts (private to the library):
+//   field  : [nrhs][12][V] complex, component c = 3*spin + colour; complex is
+//            double2 (OVS_F64) or float2 (OVS_F32_STORE)
+//   links  : [4][9][V] complex, entry 3*a + b of U_{x,nu}; the boundary sign
+//            of the link leaving the last slice in direction nu is folded in
+//   FP64 work fields (deflation, results): [nrhs][12][V] double2
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/ovsign.h"
+
+namespace ovs {
+
+constexpr int kWG = 256;          // workgroup size of the streaming kernels
+constexpr int kMaxNrhs = 4096;
+constexpr int kMaxDefl = 1024;
+
+struct Geometry {
+  int lx, ly, lz, lt;
+  int V;
+};
+
+// Hop coefficients kappa*eta_nu^{+-} for one operator application.
+struct Hop {
+  float f32_fwd[4], f32_bwd[4];
+  double fwd[4], bwd[4];
+};
+
+struct Tuning {
+  int rhs_block = 1;     // sources per thread in the stencil
+  int wg = 256;          // stencil workgroup size
+  bool tuned = false;
+};
+
+// Per-source Krylov coefficients, device resident.  Index i is 0-based
+// (entry i describes Lanczos vector i+1 of the paper's numbering).
+struct CoefArrays {
+  double2* alpha;   // [nrhs][kmax]
+  double* beta;     // [nrhs][kmax]
+  double2* gamma;   // [nrhs][kmax]
+  double* sv;       // [nrhs][kmax+1] scale of stored v (v_i = sv_i * V~_i)
+  double2* sw;      // [nrhs][kmax+1] scale of stored w (w_i = sw_i * W~_i)
+  double* tnorm2;   // [nrhs][kmax]  |A v_i|^2
+  int* kstop;       // [nrhs] number of valid alpha (kmax if no breakdown)
+  int* status;      // [nrhs] 0 ok, 1 lucky, 2 serious
+  int kmax;
+};
+
+}  // namespace ovs
+
+struct ovs_lattice_s {
+  ovs::Geometry g;
+  int bc[4];
+  ovs_precision prec;
+  hipStream_t user_stream;      // caller's stream (may be the NULL stream)
+  hipStream_t stream;           // library stream (non-blocking, default priority)
+  hipEvent_t ev_in, ev_out;     // ordering with the caller's stream
+  int device;
+  double m_w = -1.5, mu = 0.0;
+  bool params_set = false;
+  bool links_set = false;
+  void* links = nullptr;        // packed links, storage precision
+  // tuned stencil configuration per nrhs
+  std::vector<std::pair<int, ovs::Tuning>> tuning;
+  // tuned dual-stencil source block per nrhs
+  std::vector<std::pair<int, int>> dual_block;
+  // cached workspace for sign_apply and apply
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  // results of the last sign_apply (host copies) for diagnostics
+  std::vector<double> last_alpha, last_beta, last_gamma, last_x;
+  int last_nrhs = 0, last_kmax = 0;
+};
+
+struct ovs_field_s {
+  ovs_lattice_s* lat;
+  int nrhs;
+  void* data;   // [nrhs][12][V] storage-precision complex
+};
+
+struct ovs_deflation_s {
+  ovs_lattice_s* lat;
+  int m;
+  std::vector<double> lambda;   // host complex [m]
+  double2* R;                    // device [m][12][V]
+  double2* L;                    // device [m][12][V]
+  double* sgn;                   // device [m] sgn(Re lambda)
+};
+
+// ---- launchers implemented in stencil.hip --------------------------------
+namespace ovs {
+
+// canonical complex128 [nrhs][V][12]  <->  internal [nrhs][12][V]
+void launch_pack_f64(const double2* canon, double2* field, int nrhs, int V, hipStream_t s);
+void launch_pack_f32(const double2* canon, float2* field, int nrhs, int V, hipStream_t s);
+void launch_unpack_f64(const double2* field, double2* canon, int nrhs, int V, hipStream_t s);
+void launch_unpack_f32(const float2* field, double2* canon, int nrhs, int V, hipStream_t s);
+void launch_pack_links(const double2* canon, void* links, bool f32, const Geometry& g,
+                       const int bc[4], hipStream_t s);
+
+// out = op in on fields of nrhs sources; g5in/g5out select gamma5 factors.
+hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out, int nrhs,
+                         const Geometry& g, const Hop& hop, bool g5in, bool g5out,
+                         const Tuning& tn, hipStream_t s);
+
+// Dual stencil of the two-sided Lanczos step: for iteration i = *it,
+//   T = A V~_i, S = A^dagger W~_i (A = gamma5 Dw(mu)), plus per-workgroup
+//   partials of W~_i^dagger T (complex) and |T|^2 per source slot.
+// V~_i = basis[ring ? i%3 : i], W~_i = wbuf[i%3]; each holds nrhs_slots
+// fields; only the slots listed in rhs_map[0..*n_active) are processed.
+struct DualArgs {
+  const void* links;
+  const void* basis;
+  const void* wbuf;
+  long basis_stride;   // elements between consecutive basis (or wbuf) entries
+  bool ring;
+  const int* it;
+  void* out_t;
+  void* out_s;
+  double* partials;    // [slot][dual_num_wg][3]
+  const int* rhs_map;
+  const int* n_active;
+  int nrhs_slots;
+};
+hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
+                       const Hop& hAd, int rhs_block, hipStream_t s);
+int dual_num_wg(const Geometry& g);
+
+}  // namespace ovs
+
+// ---- error helpers --------------------------------------------------------
+#define OVS_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return OVS_ERR_HIP;           \
+  } while (0)

@@ -1,0 +1,135 @@
+// Device-side helpers: complex arithmetic in registers, storage conversion,
+// lattice neighbours and deterministic workgroup reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ovs {
+
+template <typename R> struct Vec2;
+template <> struct Vec2<double> { using T = double2; };
+template <> struct Vec2<float> { using T = float2; };
+
+template <typename R>
+struct Cx {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ Cx<R> cx(R a, R b) { return Cx<R>{a, b}; }
+
+template <typename R>
+__device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator-(Cx<R> a) { return {-a.re, -a.im}; }
+// i * a
+template <typename R>
+__device__ __forceinline__ Cx<R> mul_i(Cx<R> a) { return {-a.im, a.re}; }
+template <typename R>
+__device__ __forceinline__ Cx<R> scale(R s, Cx<R> a) { return {s * a.re, s * a.im}; }
+// a * b
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
+}
+// conj(a) * b
+template <typename R>
+__device__ __forceinline__ Cx<R> cmulc(Cx<R> a, Cx<R> b) {
+  return {fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -(a.im * b.re))};
+}
+// acc + a * b
+template <typename R>
+__device__ __forceinline__ Cx<R> cfma(Cx<R> a, Cx<R> b, Cx<R> acc) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+// acc + conj(a) * b
+template <typename R>
+__device__ __forceinline__ Cx<R> cfmac(Cx<R> a, Cx<R> b, Cx<R> acc) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+  return acc;
+}
+template <typename R>
+__device__ __forceinline__ R cnorm2(Cx<R> a) { return fma(a.re, a.re, a.im * a.im); }
+
+__device__ __forceinline__ Cx<double> ld(const double2* p) {
+  double2 v = *p;
+  return {v.x, v.y};
+}
+__device__ __forceinline__ Cx<float> ld(const float2* p) {
+  float2 v = *p;
+  return {v.x, v.y};
+}
+__device__ __forceinline__ void st(double2* p, Cx<double> a) { *p = make_double2(a.re, a.im); }
+__device__ __forceinline__ void st(float2* p, Cx<float> a) { *p = make_float2(a.re, a.im); }
+// FP64 view of a stored value
+__device__ __forceinline__ Cx<double> ld64(const double2* p) { return ld(p); }
+__device__ __forceinline__ Cx<double> ld64(const float2* p) {
+  float2 v = *p;
+  return {(double)v.x, (double)v.y};
+}
+// store an FP64 value in storage precision (round to nearest)
+__device__ __forceinline__ void st64(double2* p, Cx<double> a) { *p = make_double2(a.re, a.im); }
+__device__ __forceinline__ void st64(float2* p, Cx<double> a) {
+  *p = make_float2((float)a.re, (float)a.im);
+}
+// the stored value as seen after rounding to storage precision
+__device__ __forceinline__ Cx<double> round_to(const double2*, Cx<double> a) { return a; }
+__device__ __forceinline__ Cx<double> round_to(const float2*, Cx<double> a) {
+  return {(double)(float)a.re, (double)(float)a.im};
+}
+
+__device__ __forceinline__ Cx<double> c64(double2 v) { return {v.x, v.y}; }
+__device__ __forceinline__ double2 d2(Cx<double> a) { return make_double2(a.re, a.im); }
+__device__ __forceinline__ Cx<double> cdiv(Cx<double> a, Cx<double> b) {
+  // Smith's algorithm for a / b
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, den = b.re + b.im * r;
+    return {(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+  } else {
+    double r = b.re / b.im, den = b.re * r + b.im;
+    return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+  }
+}
+__device__ __forceinline__ double cabs1(Cx<double> a) { return hypot(a.re, a.im); }
+
+// ---- deterministic reductions over one workgroup ------------------------
+// Wave64 tree by shuffles, then a fixed-order pass over the waves in LDS.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sums `n` values per thread over the workgroup; result valid in thread 0.
+// lds must hold blockDim.x/64 * n doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      double a = lds[j];
+      for (int w = 1; w < nw; ++w) a += lds[w * NV + j];
+      v[j] = a;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace ovs

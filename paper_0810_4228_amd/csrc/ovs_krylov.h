@@ -1,0 +1,62 @@
+// Launchers of the Krylov-side kernels (krylov.hip).
+#pragma once
+
+#include "ovs_common.h"
+
+namespace ovs {
+
+constexpr int kHessMaxK = 1536;   // largest Arnoldi size of the Hessenberg inner sign
+
+int defl_nchunk(long N);
+void launch_defl(const double2* R, const double2* L, const double2* B, const double* sgn, int m,
+                 int nrhs, long N, double* partials, double* CD, double2* bR, double2* bL,
+                 double2* yex, hipStream_t s);
+// CD[j][r] = (L_j^dag B_r, R_j^dag B_r) only (used to check L^dag R = I)
+void launch_defl_cd(const double2* R, const double2* L, const double2* B, int m, int nrhs, long N,
+                    double* partials, double* CD, hipStream_t s);
+void launch_start(const double2* bR, const double2* bL, int nrhs, long N, double* partials,
+                  double* sums, void* V0, void* W0, bool f32, hipStream_t s);
+
+int update_nwg(long N);
+void launch_alpha(const double* partials, int nparts, const CoefArrays& co, const int* it,
+                  const int* rhs_map, const int* n_active, int nslots, hipStream_t s);
+void launch_update(bool f32, const void* T, const void* S, void* basis, long basis_stride,
+                   void* wbuf, long N, const CoefArrays& co, const int* it, const int* rhs_map,
+                   const int* n_active, int nslots, double* partials, bool ring, hipStream_t s);
+void launch_beta(const double* partials, int nparts, const CoefArrays& co, const int* it,
+                 const int* rhs_map, const int* n_active, int nslots, hipStream_t s);
+void launch_advance(int* it, hipStream_t s);
+
+void launch_make_coef(const double2* x, const double* sv, const double* nb, int kmax, int nrhs,
+                      double2* coef, hipStream_t s);
+void launch_combine(bool f32, const void* basis, long basis_stride, long N, const double2* coef,
+                    int kmax, const int* kused, const double2* yex, double2* y, int nrhs,
+                    hipStream_t s);
+void launch_replay(bool f32, const void* T, void* ring, long ring_stride, long N,
+                   const CoefArrays& co, int i, const double2* coef, const int* kused, double2* y,
+                   int nrhs, hipStream_t s);
+void launch_overlap(const double2* b, double2* y, long N, int V, hipStream_t s);
+
+int arn_nchunk(long N);
+void launch_arn_dots(bool f32, const void* basis, long basis_stride, const void* T, long N,
+                     int nvec, int nrhs, double* partials, double* red, hipStream_t s);
+void launch_arn_accum(const double* red, int nvec, int kmax, int j, bool first, double2* H,
+                      double2* hcur, int nrhs, hipStream_t s);
+void launch_arn_axpy(bool f32, const void* basis, long basis_stride, void* T, long N, int nvec,
+                     const double2* hcur, int kmax, int nrhs, double* partials, double* red,
+                     hipStream_t s);
+void launch_norm2(bool f32, const void* T, long N, int nrhs, double* partials, double* red,
+                  hipStream_t s);
+void launch_arn_sub(const double* red_n, const double* red_tn, double2* H, int kmax, int j,
+                    double* scl, int* kstop, int* status, int nrhs, hipStream_t s);
+void launch_scale_copy(bool f32, const void* T, void* out, long N, const double* scl, int nrhs,
+                       hipStream_t s);
+
+int isign_tri_nwave(int nnode);
+void launch_isign_tri(const double2* alpha, const double* beta, const double2* gamma, int kmax,
+                      const int* kvec, int nrhs, double h, int n0, int nnode, double2* mult,
+                      unsigned char* swp, double2* part, double2* x, double* err, hipStream_t s);
+void launch_isign_hess(const double2* H, int kmax, const int* kvec, int nrhs, double h, int n0,
+                       int nnode, double2* ys, double2* x, double* err, hipStream_t s);
+
+}  // namespace ovs

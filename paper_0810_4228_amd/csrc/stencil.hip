@@ -1,0 +1,466 @@
+// Wilson-Dirac stencil at chemical potential on gfx950 (Section 1):
+//   (Dw psi)(y) = psi(y) - sum_nu [ k eta+_nu (1 + g_nu) U_nu(y-nu) psi(y-nu)
+//                                  + k eta-_nu (1 - g_nu) U_nu(y)^dag psi(y+nu) ]
+// with eta+-_4 = e^{+-mu}, 1 in space.  A = gamma5 Dw(mu); A^dagger = gamma5 Dw(-mu).
+//
+// One thread owns one site for a block of B sources: each link is loaded once
+// per hop and reused for the B sources.  (1 +- g_nu) has rank two, so the
+// neighbour spinor is first projected to two spin components, multiplied by
+// the link and then expanded again (chiral basis of the library header).
+// Loads and stores are coalesced: the field layout is [src][12][V].
+#include "ovs_common.h"
+#include "ovs_device.h"
+
+namespace ovs {
+
+// ---- canonical <-> internal layout ----------------------------------------
+
+template <typename T2>
+__global__ void k_pack(const double2* __restrict__ canon, T2* __restrict__ field, int nrhs, int V) {
+  const long n = (long)nrhs * 12 * V;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    // e indexes the output [r][c][s] so the store is coalesced
+    const int s = (int)(e % V);
+    const long rc = e / V;
+    const int c = (int)(rc % 12);
+    const long r = rc / 12;
+    st64(field + e, c64(canon[(r * V + s) * 12 + c]));
+  }
+}
+
+template <typename T2>
+__global__ void k_unpack(const T2* __restrict__ field, double2* __restrict__ canon, int nrhs, int V) {
+  const long n = (long)nrhs * 12 * V;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    // e indexes the output [r][s][c]
+    const int c = (int)(e % 12);
+    const long rs = e / 12;
+    const int s = (int)(rs % V);
+    const long r = rs / V;
+    canon[e] = d2(ld64(field + (r * 12 + c) * V + s));
+  }
+}
+
+static int grid_for(long n) {
+  long b = (n + kWG - 1) / kWG;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+void launch_pack_f64(const double2* canon, double2* field, int nrhs, int V, hipStream_t s) {
+  long n = (long)nrhs * 12 * V;
+  hipLaunchKernelGGL(k_pack<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon, field, nrhs, V);
+}
+void launch_pack_f32(const double2* canon, float2* field, int nrhs, int V, hipStream_t s) {
+  long n = (long)nrhs * 12 * V;
+  hipLaunchKernelGGL(k_pack<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon, field, nrhs, V);
+}
+void launch_unpack_f64(const double2* field, double2* canon, int nrhs, int V, hipStream_t s) {
+  long n = (long)nrhs * 12 * V;
+  hipLaunchKernelGGL(k_unpack<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, field, canon, nrhs, V);
+}
+void launch_unpack_f32(const float2* field, double2* canon, int nrhs, int V, hipStream_t s) {
+  long n = (long)nrhs * 12 * V;
+  hipLaunchKernelGGL(k_unpack<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, field, canon, nrhs, V);
+}
+
+// Links: canonical [V][4][3][3] -> [4][9][V], with the boundary sign folded in.
+template <typename T2>
+__global__ void k_pack_links(const double2* __restrict__ canon, T2* __restrict__ links, Geometry g,
+                             int bc0, int bc1, int bc2, int bc3) {
+  const long n = 4L * 9 * g.V;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int s = (int)(e % g.V);
+    const int ne = (int)(e / g.V);
+    const int nu = ne / 9, ent = ne % 9;
+    int coord;
+    int ext;
+    int bc;
+    if (nu == 0) { coord = s % g.lx; ext = g.lx; bc = bc0; }
+    else if (nu == 1) { coord = (s / g.lx) % g.ly; ext = g.ly; bc = bc1; }
+    else if (nu == 2) { coord = (s / (g.lx * g.ly)) % g.lz; ext = g.lz; bc = bc2; }
+    else { coord = s / (g.lx * g.ly * g.lz); ext = g.lt; bc = bc3; }
+    Cx<double> u = c64(canon[((long)s * 4 + nu) * 9 + ent]);
+    if (coord == ext - 1 && bc < 0) u = -u;
+    st64(links + e, u);
+  }
+}
+
+void launch_pack_links(const double2* canon, void* links, bool f32, const Geometry& g,
+                       const int bc[4], hipStream_t s) {
+  long n = 4L * 9 * g.V;
+  if (f32)
+    hipLaunchKernelGGL(k_pack_links<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon,
+                       (float2*)links, g, bc[0], bc[1], bc[2], bc[3]);
+  else
+    hipLaunchKernelGGL(k_pack_links<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon,
+                       (double2*)links, g, bc[0], bc[1], bc[2], bc[3]);
+}
+
+// ---- spin projection and reconstruction (chiral basis) -------------------
+// Component index 3*spin + colour.  For direction NU and sign S (+1: the
+// (1 + g_nu) hop from y - nu, -1: the (1 - g_nu) hop from y + nu) the half
+// spinor h = (h0, h1) carries the two independent spin rows; the lower rows
+// of (1 + S g_nu) psi are fixed multiples of h0, h1.
+
+template <typename R, int NU, int S>
+__device__ __forceinline__ void project(const Cx<R> (&p)[12], Cx<R> (&h)[6]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const Cx<R> p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+    if constexpr (NU == 0) {        // h0 = p0 - S i p3, h1 = p1 - S i p2
+      h[c] = (S > 0) ? p0 - mul_i(p3) : p0 + mul_i(p3);
+      h[3 + c] = (S > 0) ? p1 - mul_i(p2) : p1 + mul_i(p2);
+    } else if constexpr (NU == 1) { // h0 = p0 - S p3, h1 = p1 + S p2
+      h[c] = (S > 0) ? p0 - p3 : p0 + p3;
+      h[3 + c] = (S > 0) ? p1 + p2 : p1 - p2;
+    } else if constexpr (NU == 2) { // h0 = p0 - S i p2, h1 = p1 + S i p3
+      h[c] = (S > 0) ? p0 - mul_i(p2) : p0 + mul_i(p2);
+      h[3 + c] = (S > 0) ? p1 + mul_i(p3) : p1 - mul_i(p3);
+    } else {                        // h0 = p0 + S p2, h1 = p1 + S p3
+      h[c] = (S > 0) ? p0 + p2 : p0 - p2;
+      h[3 + c] = (S > 0) ? p1 + p3 : p1 - p3;
+    }
+  }
+}
+
+// acc += coef * (1 + S g_nu)-expansion of uh
+template <typename R, int NU, int S>
+__device__ __forceinline__ void expand_acc(Cx<R> (&acc)[12], const Cx<R> (&uh)[6], R coef) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const Cx<R> a = scale(coef, uh[c]);      // coef * U h0
+    const Cx<R> b = scale(coef, uh[3 + c]);  // coef * U h1
+    acc[c] = acc[c] + a;
+    acc[3 + c] = acc[3 + c] + b;
+    if constexpr (NU == 0) {        // r2 = S i h1, r3 = S i h0
+      acc[6 + c] = (S > 0) ? acc[6 + c] + mul_i(b) : acc[6 + c] - mul_i(b);
+      acc[9 + c] = (S > 0) ? acc[9 + c] + mul_i(a) : acc[9 + c] - mul_i(a);
+    } else if constexpr (NU == 1) { // r2 = S h1, r3 = -S h0
+      acc[6 + c] = (S > 0) ? acc[6 + c] + b : acc[6 + c] - b;
+      acc[9 + c] = (S > 0) ? acc[9 + c] - a : acc[9 + c] + a;
+    } else if constexpr (NU == 2) { // r2 = S i h0, r3 = -S i h1
+      acc[6 + c] = (S > 0) ? acc[6 + c] + mul_i(a) : acc[6 + c] - mul_i(a);
+      acc[9 + c] = (S > 0) ? acc[9 + c] - mul_i(b) : acc[9 + c] + mul_i(b);
+    } else {                        // r2 = S h0, r3 = S h1
+      acc[6 + c] = (S > 0) ? acc[6 + c] + a : acc[6 + c] - a;
+      acc[9 + c] = (S > 0) ? acc[9 + c] + b : acc[9 + c] - b;
+    }
+  }
+}
+
+// U h (DAG = false) or U^dagger h (DAG = true) on both halves.
+template <typename R, bool DAG>
+__device__ __forceinline__ void link_mul(const Cx<R> (&u)[9], const Cx<R> (&h)[6], Cx<R> (&uh)[6]) {
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Cx<R> sum = {R(0), R(0)};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if constexpr (DAG) sum = cfmac(u[3 * b + a], h[3 * half + b], sum);
+        else sum = cfma(u[3 * a + b], h[3 * half + b], sum);
+      }
+      uh[3 * half + a] = sum;
+    }
+  }
+}
+
+template <typename R, int NU, int S, bool DAG>
+__device__ __forceinline__ void hop(Cx<R> (&acc)[12], const Cx<R> (&u)[9], const Cx<R> (&psi)[12], R coef) {
+  Cx<R> h[6], uh[6];
+  project<R, NU, S>(psi, h);
+  link_mul<R, DAG>(u, h, uh);
+  expand_acc<R, NU, S>(acc, uh, coef);
+}
+
+template <typename T2, typename R>
+__device__ __forceinline__ void load_spinor(const T2* __restrict__ f, int V, int site, bool g5,
+                                            Cx<R> (&p)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    p[c] = ld(f + (long)c * V + site);
+    if (g5 && c >= 6) p[c] = -p[c];
+  }
+}
+
+template <typename T2, typename R>
+__device__ __forceinline__ void load_link(const T2* __restrict__ links, int V, int nu, int site,
+                                          Cx<R> (&u)[9]) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = ld(links + (long)(nu * 9 + e) * V + site);
+}
+
+struct Nbr {
+  int b[4], f[4];
+};
+
+__device__ __forceinline__ Nbr neighbours(int s, const Geometry& g) {
+  Nbr n;
+  const int x = s % g.lx;
+  const int r1 = s / g.lx;
+  const int y = r1 % g.ly;
+  const int r2 = r1 / g.ly;
+  const int z = r2 % g.lz;
+  const int t = r2 / g.lz;
+  const int sy = g.lx, sz = g.lx * g.ly, st_ = g.lx * g.ly * g.lz;
+  n.f[0] = (x == g.lx - 1) ? s - (g.lx - 1) : s + 1;
+  n.b[0] = (x == 0) ? s + (g.lx - 1) : s - 1;
+  n.f[1] = (y == g.ly - 1) ? s - (g.ly - 1) * sy : s + sy;
+  n.b[1] = (y == 0) ? s + (g.ly - 1) * sy : s - sy;
+  n.f[2] = (z == g.lz - 1) ? s - (g.lz - 1) * sz : s + sz;
+  n.b[2] = (z == 0) ? s + (g.lz - 1) * sz : s - sz;
+  n.f[3] = (t == g.lt - 1) ? s - (g.lt - 1) * st_ : s + st_;
+  n.b[3] = (t == 0) ? s + (g.lt - 1) * st_ : s - st_;
+  return n;
+}
+
+template <typename R> struct HopR;
+template <> struct HopR<double> {
+  double fwd[4], bwd[4];
+  static HopR make(const Hop& h) {
+    HopR r;
+    for (int i = 0; i < 4; ++i) { r.fwd[i] = h.fwd[i]; r.bwd[i] = h.bwd[i]; }
+    return r;
+  }
+};
+template <> struct HopR<float> {
+  float fwd[4], bwd[4];
+  static HopR make(const Hop& h) {
+    HopR r;
+    for (int i = 0; i < 4; ++i) { r.fwd[i] = h.f32_fwd[i]; r.bwd[i] = h.f32_bwd[i]; }
+    return r;
+  }
+};
+
+// Accumulate all eight hops of one direction pair for B sources.
+template <typename R, typename T2, int NU, int B>
+__device__ __forceinline__ void dir_hops(Cx<R> (&acc)[B][12], const T2* __restrict__ links,
+                                         const T2* __restrict__ in, int V, int s, const Nbr& nb,
+                                         int nsrc, bool g5in, R cf, R cb) {
+  Cx<R> u[9];
+  Cx<R> psi[12];
+  // forward hop: field from s - nu through U_nu(s - nu)
+  load_link(links, V, NU, nb.b[NU], u);
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    if (r < nsrc) {
+      load_spinor(in + (long)r * 12 * V, V, nb.b[NU], g5in, psi);
+      hop<R, NU, +1, false>(acc[r], u, psi, cf);
+    }
+  }
+  // backward hop: field from s + nu through U_nu(s)^dagger
+  load_link(links, V, NU, s, u);
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    if (r < nsrc) {
+      load_spinor(in + (long)r * 12 * V, V, nb.f[NU], g5in, psi);
+      hop<R, NU, -1, true>(acc[r], u, psi, cb);
+    }
+  }
+}
+
+template <typename R, int B>
+__global__ void __launch_bounds__(256)
+k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T* __restrict__ in,
+         typename Vec2<R>::T* __restrict__ out, Geometry g, HopR<R> hop_c, int nrhs, int g5in,
+         int g5out) {
+  using T2 = typename Vec2<R>::T;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const int r0 = blockIdx.y * B;
+  const int nsrc = min(B, nrhs - r0);
+  const T2* inb = in + (long)r0 * 12 * g.V;
+  T2* outb = out + (long)r0 * 12 * g.V;
+  const Nbr nb = neighbours(s, g);
+  Cx<R> acc[B][12];
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
+  dir_hops<R, T2, 0, B>(acc, links, inb, g.V, s, nb, nsrc, g5in, hop_c.fwd[0], hop_c.bwd[0]);
+  dir_hops<R, T2, 1, B>(acc, links, inb, g.V, s, nb, nsrc, g5in, hop_c.fwd[1], hop_c.bwd[1]);
+  dir_hops<R, T2, 2, B>(acc, links, inb, g.V, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
+  dir_hops<R, T2, 3, B>(acc, links, inb, g.V, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    if (r < nsrc) {
+      Cx<R> psi[12];
+      load_spinor(inb + (long)r * 12 * g.V, g.V, s, g5in, psi);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        Cx<R> o = psi[c] - acc[r][c];
+        if (g5out && c >= 6) o = -o;
+        st(outb + (long)r * 12 * g.V + (long)c * g.V + s, o);
+      }
+    }
+  }
+}
+
+template <typename R, int B>
+static void launch_w(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
+                     const Hop& hop_c, bool g5in, bool g5out, int wg, hipStream_t s) {
+  using T2 = typename Vec2<R>::T;
+  dim3 grid((g.V + wg - 1) / wg, (nrhs + B - 1) / B);
+  hipLaunchKernelGGL((k_wilson<R, B>), grid, dim3(wg), 0, s, (const T2*)links, (const T2*)in,
+                     (T2*)out, g, HopR<R>::make(hop_c), nrhs, (int)g5in, (int)g5out);
+}
+
+hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out, int nrhs,
+                         const Geometry& g, const Hop& hop_c, bool g5in, bool g5out,
+                         const Tuning& tn, hipStream_t s) {
+  const int wg = tn.wg;
+  if (f32) {
+    switch (tn.rhs_block) {
+      case 1: launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      case 2: launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      case 3: launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      case 4: launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      case 6: launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (tn.rhs_block) {
+      case 1: launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      case 2: launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      case 3: launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+// ---- dual stencil for the two-sided Lanczos step ---------------------------
+// For each active source slot r: T_r = A V~_r, S_r = A^dag W~_r, and per
+// workgroup the partial sums of W~_r^dagger T_r (complex) and |T_r|^2, in FP64.
+
+template <typename R, int B>
+__global__ void __launch_bounds__(256)
+k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T* __restrict__ basis,
+       const typename Vec2<R>::T* __restrict__ wbuf, long basis_stride, int ring,
+       const int* __restrict__ it, typename Vec2<R>::T* __restrict__ out_t,
+       typename Vec2<R>::T* __restrict__ out_s, double* __restrict__ partials, Geometry g,
+       HopR<R> hA, HopR<R> hAd, const int* __restrict__ rhs_map, const int* __restrict__ n_active) {
+  using T2 = typename Vec2<R>::T;
+  __shared__ double lds[(256 / 64) * 3 * B];
+  const int na = *n_active;
+  const int iter = *it;
+  const T2* in_v = basis + (long)(ring ? iter % 3 : iter) * basis_stride;
+  const T2* in_w = wbuf + (long)(iter % 3) * basis_stride;
+  const int j0 = blockIdx.y * B;
+  if (j0 >= na) return;  // uniform over the workgroup
+  const int nsrc = min(B, na - j0);
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = s < g.V;
+  const int V = g.V;
+  int slot[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) slot[r] = (r < nsrc) ? rhs_map[j0 + r] : 0;
+
+  double part[3 * B];
+#pragma unroll
+  for (int q = 0; q < 3 * B; ++q) part[q] = 0.0;
+
+  if (live) {
+    const Nbr nb = neighbours(s, g);
+    Cx<R> accv[B][12], accw[B][12];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) accv[r][c] = accw[r][c] = {R(0), R(0)};
+    Cx<R> u[9], psi[12];
+#define OVS_DUAL_DIR(NU)                                                                 \
+  load_link(links, V, NU, nb.b[NU], u);                                                  \
+  _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
+    if (r < nsrc) {                                                                      \
+      load_spinor(in_v + (long)slot[r] * 12 * V, V, nb.b[NU], false, psi);               \
+      hop<R, NU, +1, false>(accv[r], u, psi, hA.fwd[NU]);                                \
+      load_spinor(in_w + (long)slot[r] * 12 * V, V, nb.b[NU], false, psi);               \
+      hop<R, NU, +1, false>(accw[r], u, psi, hAd.fwd[NU]);                               \
+    }                                                                                    \
+  }                                                                                      \
+  load_link(links, V, NU, s, u);                                                         \
+  _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
+    if (r < nsrc) {                                                                      \
+      load_spinor(in_v + (long)slot[r] * 12 * V, V, nb.f[NU], false, psi);               \
+      hop<R, NU, -1, true>(accv[r], u, psi, hA.bwd[NU]);                                 \
+      load_spinor(in_w + (long)slot[r] * 12 * V, V, nb.f[NU], false, psi);               \
+      hop<R, NU, -1, true>(accw[r], u, psi, hAd.bwd[NU]);                                \
+    }                                                                                    \
+  }
+    OVS_DUAL_DIR(0)
+    OVS_DUAL_DIR(1)
+    OVS_DUAL_DIR(2)
+    OVS_DUAL_DIR(3)
+#undef OVS_DUAL_DIR
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      if (r < nsrc) {
+        const long base = (long)slot[r] * 12 * V;
+        Cx<R> pv[12], pw[12];
+        load_spinor(in_v + base, V, s, false, pv);
+        load_spinor(in_w + base, V, s, false, pw);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          Cx<R> t = pv[c] - accv[r][c];
+          Cx<R> sv = pw[c] - accw[r][c];
+          if (c >= 6) { t = -t; sv = -sv; }
+          st(out_t + base + (long)c * V + s, t);
+          st(out_s + base + (long)c * V + s, sv);
+          const Cx<double> t64 = {(double)t.re, (double)t.im};
+          const Cx<double> w64 = {(double)pw[c].re, (double)pw[c].im};
+          const Cx<double> p = cmulc(w64, t64);
+          part[3 * r + 0] += p.re;
+          part[3 * r + 1] += p.im;
+          part[3 * r + 2] += cnorm2(t64);
+        }
+      }
+    }
+  }
+  block_sum<3 * B>(part, lds);
+  if (threadIdx.x == 0) {
+    for (int r = 0; r < nsrc; ++r) {
+      double* p = partials + ((long)slot[r] * gridDim.x + blockIdx.x) * 3;
+      p[0] = part[3 * r + 0];
+      p[1] = part[3 * r + 1];
+      p[2] = part[3 * r + 2];
+    }
+  }
+}
+
+int dual_num_wg(const Geometry& g) { return (g.V + 255) / 256; }
+
+template <typename R, int B>
+static void launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, const Hop& hAd,
+                     hipStream_t s) {
+  using T2 = typename Vec2<R>::T;
+  dim3 grid(dual_num_wg(g), (a.nrhs_slots + B - 1) / B);
+  hipLaunchKernelGGL((k_dual<R, B>), grid, dim3(256), 0, s, (const T2*)a.links, (const T2*)a.basis,
+                     (const T2*)a.wbuf, a.basis_stride, (int)a.ring, a.it, (T2*)a.out_t,
+                     (T2*)a.out_s, a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd), a.rhs_map,
+                     a.n_active);
+}
+
+hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
+                       const Hop& hAd, int rhs_block, hipStream_t s) {
+  if (f32) {
+    switch (rhs_block) {
+      case 1: launch_d<float, 1>(a, g, hA, hAd, s); break;
+      case 2: launch_d<float, 2>(a, g, hA, hAd, s); break;
+      case 3: launch_d<float, 3>(a, g, hA, hAd, s); break;
+      case 4: launch_d<float, 4>(a, g, hA, hAd, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (rhs_block) {
+      case 1: launch_d<double, 1>(a, g, hA, hAd, s); break;
+      case 2: launch_d<double, 2>(a, g, hA, hAd, s); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ovs

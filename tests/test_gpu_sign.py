@@ -1,0 +1,164 @@
+"""GPU parity of sgn(gamma5 Dw(mu)) b: two-sided Lanczos with LR deflation
+(Section 4, eq. 2sLapp) and Arnoldi (Section 2, eq. Arnapp), against the CPU
+oracle (dense spectral sign, free-field closed form, CPU Krylov)."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, freefield, krylov, sign
+
+from gpu_util import rel, rel_rows, say, to_dev
+
+pytestmark = pytest.mark.gpu
+MW = -1.5
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def lattice(dims, prec, U, mu):
+    import paper_0810_4228_amd as ovs
+    lat = ovs.Lattice(dims, precision=prec)
+    lat.set_links(to_dev(U))
+    lat.set_params(MW, mu)
+    return lat
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    """4^4, eps 0.4, mu 0.3, Gaussian source; exact sign and 20 eigentriples (stored)."""
+    f = np.load(os.path.join(GOLDEN, "lattice_4444.npz"))
+    dims = tuple(int(d) for d in f["dims"])
+    U = synth.random_links(dims, float(f["eps"]), seed=synth.LINK_SEED)
+    b = synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)
+    return dims, U, b, f
+
+
+def test_inner_sign_tridiag_vs_eig():
+    """GPU quadrature sgn(G) e_1 vs the oracle's spectral sign of the same G."""
+    import paper_0810_4228_amd as ovs
+    dims = (2, 2, 4, 4)
+    U = synth.random_links(dims, 0.5, seed=31)
+    A = dirac.csr_A(dims, U, MW, 0.3)
+    b = synth.gaussian_sources(dims, 1, seed=32)[0]
+    lat = ovs.Lattice(dims)
+    for k in (1, 2, 7, 40, 150):
+        lr = krylov.two_sided_lanczos(lambda v: A @ v, lambda v: A.conj().T @ v, b, b, k, store=False)
+        G = krylov.tridiag(lr.alpha, lr.beta, lr.gamma)
+        ref = sign.sign_e1(G)
+        sub = np.zeros(k, complex)
+        sub[:k - 1] = lr.beta
+        sup = np.zeros(k, complex)
+        sup[:k - 1] = lr.gamma
+        x, err = lat.inner_sign_tridiag(lr.alpha[None], sub[None], sup[None])
+        say("tri k", k, rel(x[0], ref), err)
+        assert rel(x[0], ref) < 1e-11
+
+
+def test_inner_sign_hessenberg_vs_eig():
+    import paper_0810_4228_amd as ovs
+    dims = (2, 2, 4, 4)
+    U = synth.random_links(dims, 0.5, seed=33)
+    A = dirac.csr_A(dims, U, MW, 0.4)
+    b = synth.gaussian_sources(dims, 1, seed=34)[0]
+    lat = ovs.Lattice(dims)
+    for k in (1, 3, 30, 120):
+        ar = krylov.arnoldi(lambda v: A @ v, b, k)
+        ref = sign.sign_e1(ar.H)
+        x, err = lat.inner_sign_hessenberg(ar.H)
+        say("hess k", k, rel(x[0], ref), err)
+        assert rel(x[0], ref) < 1e-11
+
+
+def test_config1_dense(cfg1):
+    """4^4, k = 300, m = 20: GPU 2sL within 1e-10 of the exact spectral sign."""
+    import torch
+    dims, U, b, f = cfg1
+    lat = lattice(dims, "f64", U, float(f["mu"]))
+    d = lat.deflation_set(f["lam"], to_dev(f["R"].T), to_dev(f["L"].T))
+    y, info, st = lat.sign_apply(to_dev(b), 300, defl=d)
+    e = rel(y.cpu().numpy()[0], f["y"])
+    say("cfg1 2sL m=20 k=300 err", e, info[0])
+    assert st == 0
+    assert e <= 1e-10
+    # undeflated and Arnoldi, same bar at larger k / same k
+    ya, info_a, _ = lat.sign_apply(to_dev(b), 300, defl=d, method="arnoldi")
+    ea = rel(ya.cpu().numpy()[0], f["y"])
+    say("cfg1 arnoldi m=20 k=300 err", ea)
+    assert ea <= 1e-10
+    del torch
+
+
+def test_matches_cpu_lanczos_step_by_step():
+    """Same k, same deflation: GPU coefficients and result vs the CPU oracle."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 0.6, seed=41)
+    mu = 0.5
+    b = synth.gaussian_sources(dims, 1, seed=42)
+    A = dirac.csr_A(dims, U, MW, mu)
+    lat = lattice(dims, "f64", U, mu)
+    for k in (10, 60):
+        y, info, _ = lat.sign_apply(to_dev(b), k)
+        a, bb, g, x = lat.last_coefficients(1, k)
+        yr, inf = krylov.tsl_apply(lambda v: A @ v, lambda v: A.conj().T @ v, b[0], k, return_info=True)
+        lr = inf["lanczos"]
+        say("k", k, rel(a[0], lr.alpha), rel(bb[0, :k - 1], lr.beta), rel(y.cpu().numpy()[0], yr))
+        assert rel(a[0], lr.alpha) < 1e-10
+        assert rel(bb[0, :k - 1], lr.beta) < 1e-10
+        assert rel(g[0, :k - 1], lr.gamma) < 1e-10
+        assert rel(x[0], inf["x"]) < 1e-10
+        assert rel(y.cpu().numpy()[0], yr) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_free_field_8444(prec, tol):
+    """Unit links: exact answer from the closed form at any size."""
+    dims = (8, 8, 8, 8)
+    mu = 0.3
+    U = synth.unit_links(dims)
+    b = synth.gaussian_sources(dims, 3, seed=1)
+    ref = freefield.free_sign_apply(dims, MW, mu, b)
+    lat = lattice(dims, prec, U, mu)
+    # the CPU oracle's own two-sided Lanczos reaches 7e-8 at k = 200 and 2e-13 at k = 300
+    y, info, st = lat.sign_apply(to_dev(b), 300)
+    e = rel_rows(y.cpu().numpy(), ref)
+    say("free 8^4", prec, e, [i["k_used"] for i in info])
+    assert e <= tol
+
+
+def test_two_pass_equals_one_pass():
+    dims = (4, 4, 4, 8)
+    U = synth.random_links(dims, 0.6, seed=51)
+    lat = lattice(dims, "f64", U, 0.3)
+    b = to_dev(synth.gaussian_sources(dims, 2, seed=52))
+    y1, _, _ = lat.sign_apply(b, 150)
+    y2, _, _ = lat.sign_apply(b, 150, two_pass=True)
+    e = rel_rows(y2.cpu().numpy(), y1.cpu().numpy())
+    say("two-pass", e)
+    assert e <= 1e-13
+
+
+def test_graph_equals_direct_bitwise():
+    import torch
+    dims = (4, 4, 4, 8)
+    U = synth.random_links(dims, 0.6, seed=53)
+    for prec in ("f64", "f32"):
+        lat = lattice(dims, prec, U, 0.3)
+        b = to_dev(synth.gaussian_sources(dims, 3, seed=54))
+        y1, _, _ = lat.sign_apply(b, 120)
+        y2, _, _ = lat.sign_apply(b, 120, graph=True)
+        y3, _, _ = lat.sign_apply(b, 120, graph=True)
+        assert torch.equal(y1, y2)
+        assert torch.equal(y2, y3)
+
+
+def test_batched_equals_single():
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 0.6, seed=55)
+    lat = lattice(dims, "f64", U, 0.2)
+    b = synth.gaussian_sources(dims, 4, seed=56)
+    yb, _, _ = lat.sign_apply(to_dev(b), 100)
+    yb = yb.cpu().numpy()
+    for r in range(4):
+        ys, _, _ = lat.sign_apply(to_dev(b[r:r + 1]), 100)
+        assert rel(ys.cpu().numpy()[0], yb[r]) <= 1e-14

@@ -1,0 +1,155 @@
+"""GPU parity of the Wilson-Dirac stencil (Section 1) against the CPU oracle.
+
+FP64: relative 2-norm error per source <= 1e-14; FP32 storage <= 1e-6
+(single-precision rounding of links, inputs and accumulation).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, freefield
+
+from gpu_util import rel_rows, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MW = -1.5
+TOL = {"f64": 1e-14, "f32": 1e-6}
+
+
+def lattice(dims, prec, U, mu):
+    import paper_0810_4228_amd as ovs
+    lat = ovs.Lattice(dims, precision=prec)
+    lat.set_links(to_dev(U))
+    lat.set_params(MW, mu)
+    return lat
+
+
+def oracle_op(dims, U, mu, op):
+    if op in ("A", "A_dag"):
+        m = dirac.csr_A(dims, U, MW, mu)
+    else:
+        m = dirac.csr_dw(dims, U, MW, mu)
+    if op.endswith("dag"):
+        m = m.conj().T.tocsr()
+    return m
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (4, 6, 8, 10), (3, 2, 5, 4)])
+@pytest.mark.parametrize("op", ["A", "A_dag", "Dw", "Dw_dag"])
+def test_stencil_matches_csr(prec, dims, op):
+    say("stencil", prec, dims, op)
+    mu = 0.35
+    U = synth.random_links(dims, 0.6, seed=3)
+    b = synth.gaussian_sources(dims, 5, seed=4)
+    lat = lattice(dims, prec, U, mu)
+    y = lat.apply(op, to_dev(b)).cpu().numpy()
+    ref = (oracle_op(dims, U, mu, op) @ b.T).T
+    assert rel_rows(y, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nrhs", [1, 2, 3, 4, 7, 12])
+def test_multi_rhs_blocks(prec, nrhs):
+    """Every tuned source block gives the same result as the oracle (ragged tails)."""
+    say("multi rhs", prec, nrhs)
+    dims = (4, 4, 4, 8)
+    U = synth.random_links(dims, 0.6, seed=5)
+    b = synth.gaussian_sources(dims, nrhs, seed=6)
+    lat = lattice(dims, prec, U, 0.2)
+    lat.autotune(nrhs)
+    y = lat.apply("A", to_dev(b)).cpu().numpy()
+    ref = (oracle_op(dims, U, 0.2, "A") @ b.T).T
+    assert rel_rows(y, ref) <= TOL[prec]
+
+
+def test_field_roundtrip_bitwise():
+    import torch
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 0.6, seed=7)
+    lat = lattice(dims, "f64", U, 0.1)
+    b = to_dev(synth.gaussian_sources(dims, 3, seed=8))
+    f = lat.field_create(3)
+    f.import_(b)
+    out = f.export()
+    assert torch.equal(out, b)
+
+
+def test_field_apply_equals_apply():
+    dims = (4, 4, 6, 8)
+    U = synth.random_links(dims, 0.6, seed=9)
+    lat = lattice(dims, "f32", U, 0.4)
+    b = to_dev(synth.gaussian_sources(dims, 4, seed=10))
+    fi, fo = lat.field_create(4), lat.field_create(4)
+    fi.import_(b)
+    fi.apply("A", fo)
+    ms = fi.apply_timed("A", fo, 3)
+    assert ms > 0
+    y1 = fo.export().cpu().numpy()
+    y2 = lat.apply("A", b).cpu().numpy()
+    assert np.array_equal(y1, y2)
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (16, 16, 16, 32)])
+def test_full_size_sampled_sites(dims):
+    """Full-size random links: sampled output sites against the per-site oracle."""
+    say("sampled", dims)
+    mu = 0.2
+    U = synth.random_links(dims, 0.8, seed=0)
+    b = synth.gaussian_sources(dims, 2, seed=1)
+    for prec in ("f64", "f32"):
+        lat = lattice(dims, prec, U, mu)
+        lat.autotune(2)
+        y = lat.apply("A", to_dev(b)).cpu().numpy().reshape(2, -1, 12)
+        v = synth.volume(dims)
+        rng = np.random.default_rng(5)
+        sites = sorted(set(rng.integers(0, v, 40).tolist()) | {0, v - 1})
+        for r in range(2):
+            ref = dirac.apply_at_sites(dims, U, MW, mu, b[r], sites, op="A")
+            err = np.linalg.norm(y[r][sites] - ref) / np.linalg.norm(ref)
+            assert err <= TOL[prec] * 10, (prec, err)
+        lat.close()
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (16, 16, 16, 32)])
+def test_full_size_free_field(dims):
+    """Unit links at full size: every output against the Fourier closed form."""
+    say("free field", dims)
+    mu = 0.4
+    U = synth.unit_links(dims)
+    b = synth.gaussian_sources(dims, 1, seed=2)
+    ref = freefield.free_apply_A(dims, MW, mu, b)
+    lat = lattice(dims, "f64", U, mu)
+    y = lat.apply("A", to_dev(b)).cpu().numpy()
+    assert rel_rows(y, ref) <= 1e-13
+
+
+def test_gamma5_hermiticity_dot():
+    """<u, A v> = <A(-mu) u, v> on the GPU operator itself."""
+    dims = (4, 4, 4, 8)
+    U = synth.random_links(dims, 0.6, seed=11)
+    lat = lattice(dims, "f64", U, 0.3)
+    u = synth.gaussian_sources(dims, 1, seed=12)[0]
+    v = synth.gaussian_sources(dims, 1, seed=13)[0]
+    Av = lat.apply("A", to_dev(v[None])).cpu().numpy()[0]
+    Adu = lat.apply("A_dag", to_dev(u[None])).cpu().numpy()[0]
+    lhs = np.vdot(u, Av)
+    rhs = np.vdot(Adu, v)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_argument_errors():
+    import paper_0810_4228_amd as ovs
+    import torch
+    with pytest.raises(ovs.OvsError):
+        ovs.Lattice((1, 4, 4, 4))
+    with pytest.raises(ovs.OvsError):
+        ovs.Lattice((4, 4, 4, 4), bc=(1, 1, 1, 0))
+    lat = ovs.Lattice((2, 2, 2, 2))
+    x = torch.zeros((1, 12 * 16), dtype=torch.complex128, device="cuda")
+    with pytest.raises(ovs.OvsError) as e:
+        lat.apply("A", x)  # links not set
+    assert e.value.status == ovs.OVS_ERR_STATE
+    with pytest.raises(ovs.OvsError):
+        lat.set_params(-4.0, 0.1)  # 8 + 2 m_w <= 0
