@@ -128,6 +128,10 @@ ovs_status ovs_field_apply_timed(ovs_lattice lat, ovs_op op, ovs_field in, ovs_f
 ovs_status ovs_autotune(ovs_lattice lat, int32_t nrhs);
 /* Current tuned stencil configuration: rhs block and workgroup size. */
 ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int32_t* wg_size);
+/* Full tuned configuration for nrhs sources, host int32 [8]:
+ * {stencil rhs block, stencil workgroup size, stencil LDS cap KiB, stencil block order,
+ *  Lanczos dual-stencil rhs block, its workgroup size, its LDS cap KiB, its block order}. */
+ovs_status ovs_get_tuning_ex(ovs_lattice lat, int32_t nrhs, int32_t out[8]);
 
 /* ---- deflation (Section 3) -------------------------------------------- */
 

@@ -39,7 +39,7 @@ OVS_FLAG_OVERLAP = 8
 EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
     "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
-    "ovs_field_apply", "ovs_field_apply_timed", "ovs_autotune", "ovs_get_tuning",
+    "ovs_field_apply", "ovs_field_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex",
     "ovs_deflation_set", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_status_string",
 ]
@@ -100,6 +100,7 @@ def load():
         "ovs_field_apply_timed": [P, I, P, P, I, DP],
         "ovs_autotune": [P, I],
         "ovs_get_tuning": [P, I, IP, IP],
+        "ovs_get_tuning_ex": [P, I, IP],
         "ovs_deflation_set": [P, I, DP, P, P, ctypes.POINTER(P)],
         "ovs_deflation_destroy": [P],
         "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
@@ -215,6 +216,12 @@ class Lattice:
         w = ctypes.c_int32()
         _check(self._lib.ovs_get_tuning(self._h, int(nrhs), ctypes.byref(b), ctypes.byref(w)), "ovs_get_tuning")
         return b.value, w.value
+
+    def get_tuning_ex(self, nrhs):
+        out = (ctypes.c_int32 * 8)()
+        _check(self._lib.ovs_get_tuning_ex(self._h, int(nrhs), out), "ovs_get_tuning_ex")
+        keys = ("rhs_block", "wg", "lds_kb", "order")
+        return {"stencil": dict(zip(keys, out[0:4])), "dual": dict(zip(keys, out[4:8]))}
 
     def deflation_set(self, lam, R, L):
         """lam: complex [m] (host); R, L: complex128 CUDA [m, 12V]."""

@@ -58,10 +58,6 @@ bool valid_op(int op) { return op >= 0 && op <= 3; }
 
 size_t elem_bytes(const ovs_lattice_s* l) { return l->prec == OVS_F32_STORE ? 8 : 16; }
 
-bool block_ok(bool f32, int b) {
-  return f32 ? (b == 1 || b == 2 || b == 3 || b == 4 || b == 6) : (b == 1 || b == 2 || b == 3);
-}
-bool dual_block_ok(bool f32, int b) { return f32 ? (b >= 1 && b <= 4) : (b == 1 || b == 2); }
 
 Tuning get_tuning(const ovs_lattice_s* l, int nrhs) {
   for (auto& p : l->tuning)
@@ -73,10 +69,10 @@ Tuning get_tuning(const ovs_lattice_s* l, int nrhs) {
   return t;
 }
 
-int get_dual_block(const ovs_lattice_s* l, int nrhs) {
-  for (auto& p : l->dual_block)
+Tuning get_dual_tuning(const ovs_lattice_s* l, int nrhs) {
+  for (auto& p : l->dual_tuning)
     if (p.first == nrhs) return p.second;
-  return 1;
+  return Tuning{};
 }
 
 void set_tuning(ovs_lattice_s* l, int nrhs, const Tuning& t) {
@@ -84,10 +80,19 @@ void set_tuning(ovs_lattice_s* l, int nrhs, const Tuning& t) {
     if (p.first == nrhs) { p.second = t; return; }
   l->tuning.push_back({nrhs, t});
 }
-void set_dual_block(ovs_lattice_s* l, int nrhs, int b) {
-  for (auto& p : l->dual_block)
-    if (p.first == nrhs) { p.second = b; return; }
-  l->dual_block.push_back({nrhs, b});
+void set_dual_tuning(ovs_lattice_s* l, int nrhs, const Tuning& t) {
+  for (auto& p : l->dual_tuning)
+    if (p.first == nrhs) { p.second = t; return; }
+  l->dual_tuning.push_back({nrhs, t});
+}
+
+// Occupancy caps tried by the autotuner: dynamic LDS per workgroup in KiB
+// (0 = none; 40, 53, 80, 160 allow 4, 3, 2, 1 workgroups per CU of 160 KiB).
+std::vector<int> lds_candidates(const ovs_lattice_s* l) {
+  std::vector<int> c;
+  for (int kb : {0, 40, 53, 80, 159})
+    if (kb <= l->lds_max_kb - 1) c.push_back(kb);
+  return c;
 }
 
 // Bump allocator over the cached workspace (or a sizing pass with base == nullptr).
@@ -139,6 +144,26 @@ bool ready(const ovs_lattice_s* l) { return l && l->links_set && l->params_set; 
 constexpr double kULo = -40.0, kUHi = 45.0;  // u range of the tau = e^u quadrature
 constexpr double kHStart = 0.25, kHMin = 0.0625;
 constexpr double kQuadAccept = 3e-7;  // coarse/fine difference accepted at step h
+constexpr int kProbe = 512;           // sampled entries per source for the convergence estimate
+constexpr int kCheckEvery = 25;       // iterations between convergence checks
+
+// Distinct sampled positions in [0, N), sorted (fixed sequence, same for all calls).
+std::vector<int> probe_positions(long N, int P) {
+  std::vector<int> idx;
+  idx.reserve(P);
+  std::vector<char> used(N, 0);
+  unsigned long long st = 0x9E3779B97F4A7C15ull;
+  while ((int)idx.size() < P) {
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    const long p = (long)((st >> 17) % (unsigned long long)N);
+    if (!used[p]) {
+      used[p] = 1;
+      idx.push_back((int)p);
+    }
+  }
+  std::sort(idx.begin(), idx.end());
+  return idx;
+}
 
 void quad_range(double h, int& n0, int& nnode) {
   n0 = (int)std::floor(kULo / h);
@@ -229,6 +254,15 @@ ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_pr
       hipEventCreateWithFlags(&l->ev_out, hipEventDisableTiming) != hipSuccess) {
     delete l;
     return OVS_ERR_HIP;
+  }
+  {
+    int optin = 0, dflt = 0;
+    (void)hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, l->device);
+    (void)hipDeviceGetAttribute(&dflt, hipDeviceAttributeMaxSharedMemoryPerBlock, l->device);
+    const int kb = std::max(optin, dflt) / 1024;
+    l->lds_max_kb = kb > 0 ? kb : 64;
+    set_lds_limit(l->lds_max_kb);
+    (void)hipGetLastError();
   }
   const size_t lb = 4ul * 9 * v * elem_bytes(l);
   if (hipMalloc(&l->links, lb) != hipSuccess) {
@@ -389,6 +423,14 @@ ovs_status ovs_get_tuning(ovs_lattice l, int32_t nrhs, int32_t* rhs_block, int32
   return OVS_OK;
 }
 
+ovs_status ovs_get_tuning_ex(ovs_lattice l, int32_t nrhs, int32_t out[8]) {
+  if (!l || nrhs < 1 || !out) return OVS_ERR_ARG;
+  const Tuning t = get_tuning(l, nrhs), d = get_dual_tuning(l, nrhs);
+  out[0] = t.rhs_block; out[1] = t.wg; out[2] = t.lds_kb; out[3] = t.order;
+  out[4] = d.rhs_block; out[5] = 256; out[6] = d.lds_kb; out[7] = d.order;
+  return OVS_OK;
+}
+
 ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
   if (!l || nrhs < 1 || nrhs > kMaxNrhs) return OVS_ERR_ARG;
   if (!ready(l)) return OVS_ERR_STATE;
@@ -409,19 +451,24 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
     double best_ms = 1e300;
     const int* bl = f32 ? blocks_f32 : blocks_f64;
     const int nb = f32 ? 5 : 3;
-    for (int ib = 0; ib < nb && st == OVS_OK; ++ib) {
+    for (int ib = 0; ib < nb; ++ib) {
       if (bl[ib] > nrhs && bl[ib] != 1) continue;
-      for (int w : wgs) {
-        Tuning t;
-        t.rhs_block = bl[ib];
-        t.wg = w;
-        double ms = 0;
-        st = timed_loop(l, OVS_OP_A, fi, fo, 3, t, &ms);
-        if (st != OVS_OK) break;
-        st = timed_loop(l, OVS_OP_A, fi, fo, 10, t, &ms);
-        if (st != OVS_OK) break;
-        if (ms < best_ms) { best_ms = ms; best = t; }
-      }
+      for (int w : wgs)
+        for (int kb : lds_candidates(l))
+          for (int order = 0; order < 2; ++order) {
+            Tuning t;
+            t.rhs_block = bl[ib];
+            t.wg = w;
+            t.lds_kb = kb;
+            t.order = order;
+            double ms = 0;
+            if (timed_loop(l, OVS_OP_A, fi, fo, 2, t, &ms) != OVS_OK ||
+                timed_loop(l, OVS_OP_A, fi, fo, 8, t, &ms) != OVS_OK) {
+              (void)hipGetLastError();  // configuration rejected at launch: skip it
+              continue;
+            }
+            if (ms < best_ms) { best_ms = ms; best = t; }
+          }
     }
     best.tuned = true;
     if (st == OVS_OK) set_tuning(l, nrhs, best);
@@ -450,28 +497,44 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
         (void)hipMemcpyAsync(ints, hints, sizeof(hints), hipMemcpyHostToDevice, l->stream);
         (void)hipMemsetAsync(basis, 0, fb, l->stream);
         (void)hipMemsetAsync(wbuf, 0, 3 * fb, l->stream);
-        DualArgs da{l->links, basis, wbuf, (long)nrhs * N, false, ints, T, S, part, map, ints + 1, nrhs};
         const Hop hA = make_hop(l->m_w, l->mu), hAd = make_hop(l->m_w, -l->mu);
-        int best_b = 1;
+        Tuning dbest;
         double bms = 1e300;
         for (int bb = 1; bb <= (f32 ? 4 : 2); ++bb) {
           if (bb > nrhs && bb != 1) continue;
-          hipEvent_t e0, e1;
-          (void)hipEventCreate(&e0);
-          (void)hipEventCreate(&e1);
-          for (int w = 0; w < 2; ++w) (void)launch_dual(f32, da, l->g, hA, hAd, bb, l->stream);
-          (void)hipEventRecord(e0, l->stream);
-          for (int w = 0; w < 8; ++w) (void)launch_dual(f32, da, l->g, hA, hAd, bb, l->stream);
-          (void)hipEventRecord(e1, l->stream);
-          (void)hipEventSynchronize(e1);
-          float f = 0;
-          (void)hipEventElapsedTime(&f, e0, e1);
-          (void)hipEventDestroy(e0);
-          (void)hipEventDestroy(e1);
-          if (f < bms) { bms = f; best_b = bb; }
+          for (int kb : lds_candidates(l))
+            for (int order = 0; order < 2; ++order) {
+              DualArgs da{l->links, basis, wbuf, (long)nrhs * N, false, ints, T, S, part, map,
+                          ints + 1, nrhs, kb, order};
+              hipEvent_t e0, e1;
+              (void)hipEventCreate(&e0);
+              (void)hipEventCreate(&e1);
+              bool ok = true;
+              for (int w = 0; w < 2 && ok; ++w)
+                ok = launch_dual(f32, da, l->g, hA, hAd, bb, l->stream) == hipSuccess;
+              (void)hipEventRecord(e0, l->stream);
+              for (int w = 0; w < 6 && ok; ++w)
+                ok = launch_dual(f32, da, l->g, hA, hAd, bb, l->stream) == hipSuccess;
+              (void)hipEventRecord(e1, l->stream);
+              (void)hipEventSynchronize(e1);
+              float f = 0;
+              (void)hipEventElapsedTime(&f, e0, e1);
+              (void)hipEventDestroy(e0);
+              (void)hipEventDestroy(e1);
+              if (!ok) {
+                (void)hipGetLastError();
+                continue;
+              }
+              if (f < bms) {
+                bms = f;
+                dbest.rhs_block = bb;
+                dbest.lds_kb = kb;
+                dbest.order = order;
+              }
+            }
         }
-        if (hipGetLastError() != hipSuccess) st = OVS_ERR_HIP;
-        else set_dual_block(l, nrhs, best_b);
+        dbest.tuned = true;
+        set_dual_tuning(l, nrhs, dbest);
       }
     }
     (void)hipStreamSynchronize(l->stream);
@@ -593,9 +656,12 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
     double *part1, *part2, *dpart, *CD, *spart, *sums, *sumsb, *nb;
     double2 *alpha, *gamma, *sw, *coef, *x, *mult, *part, *H, *hcur, *ys;
     double *beta, *sv, *tnorm2, *qerr, *red, *apart, *red_n, *red_tn, *scl;
-    int *kstop, *status, *rhs_map, *ints, *kused;
+    int *kstop, *status, *rhs_map, *ints, *kused, *pidx;
     unsigned char* swp;
+    double2 *probes, *yp;
   } B{};
+  const bool probing = tol != nullptr && !arn;
+  const int P = (int)std::min<long>(kProbe, N);
   auto layout = [&](Arena& a) {
     B.Bq = a.take<double2>((size_t)nr * N);
     if (m > 0) {
@@ -630,6 +696,11 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
     B.x = a.take<double2>((size_t)nr * K);
     B.qerr = a.take<double>(nr);
     B.coef = a.take<double2>((size_t)nr * K);
+    if (probing) {
+      B.pidx = a.take<int>(P);
+      B.probes = a.take<double2>((size_t)nr * K * P);
+      B.yp = a.take<double2>((size_t)nr * P);
+    }
     if (!arn) {
       B.mult = a.take<double2>((size_t)nr * nwave_max * K * 64);
       B.swp = a.take<unsigned char>((size_t)nr * nwave_max * K * 64);
@@ -693,7 +764,8 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
     if (!std::isfinite(sums[3 * r]) || !std::isfinite(sumsb[3 * r])) return OVS_ERR_ARG;  // NaN/Inf in b
     nbh[r] = std::sqrt(sums[3 * r]);
     bnorm[r] = std::sqrt(sumsb[3 * r]);
-    if (nbh[r] == 0.0) {  // source entirely in the deflation space (or zero)
+    if (nbh[r] <= 1e-12 * bnorm[r]) {  // source in the deflation space (or zero): y = y_ex
+      nbh[r] = 0.0;
       done[r] = 1;
       kused[r] = 0;
     } else if (sums[3 * r + 1] == 0.0 && sums[3 * r + 2] == 0.0) {
@@ -746,9 +818,18 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
     OVS_HIP(hipMemcpyAsync(B.ints, &zero, sizeof(int), hipMemcpyHostToDevice, s));
     ovs_status st = push_map();
     if (st != OVS_OK) return st;
-    const int dual_b = std::min(get_dual_block(l, nr), f32 ? 4 : 2);
+    std::vector<int> pidx_h;
+    if (probing) {
+      pidx_h = probe_positions(N, P);
+      OVS_HIP(hipMemcpyAsync(B.pidx, pidx_h.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+      launch_probe_gather(f32, B.basis, bstride, N, two_pass, B.ints, true, B.pidx, P, K,
+                          B.rhs_map, B.ints + 1, nr, B.probes, s);
+      OVS_HIP(hipStreamSynchronize(s));  // pidx_h lifetime
+    }
+    const Tuning dt = get_dual_tuning(l, nr);
+    const int dual_b = std::min(dt.rhs_block, f32 ? 4 : 2);
     DualArgs da{l->links, B.basis, B.wbuf, bstride, two_pass, B.ints, B.T, B.S, B.part1,
-                B.rhs_map, B.ints + 1, nr};
+                B.rhs_map, B.ints + 1, nr, dt.lds_kb, dt.order};
     auto enqueue_iter = [&](bool full) -> ovs_status {
       OVS_HIP(launch_dual(f32, da, l->g, hA, hAd, dual_b, s));
       launch_alpha(B.part1, nwg_d, co, B.ints, B.rhs_map, B.ints + 1, nr, s);
@@ -756,12 +837,15 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
         launch_update(f32, B.T, B.S, B.basis, bstride, B.wbuf, N, co, B.ints, B.rhs_map,
                       B.ints + 1, nr, B.part2, two_pass, s);
         launch_beta(B.part2, nwg_u, co, B.ints, B.rhs_map, B.ints + 1, nr, s);
+        if (probing)
+          launch_probe_gather(f32, B.basis, bstride, N, two_pass, B.ints, false, B.pidx, P, K,
+                              B.rhs_map, B.ints + 1, nr, B.probes, s);
       }
       launch_advance(B.ints, s);
       OVS_HIP(hipGetLastError());
       return OVS_OK;
     };
-    const int chunk = 25;
+    const int chunk = kCheckEvery;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     struct GraphGuard {
@@ -816,23 +900,26 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
         st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, B.kused, nr, isc, B.x,
                         B.qerr, errh);
         if (st != OVS_OK) return st;
-        std::vector<double> xh((size_t)nr * K * 2);
-        OVS_HIP(hipMemcpyAsync(xh.data(), B.x, sizeof(double2) * nr * K, hipMemcpyDeviceToHost, s));
+        // relative change of y on the sampled entries since the previous check
+        launch_make_coef(B.x, B.sv, B.nb, K, nr, B.coef, s);
+        launch_probe_y(B.probes, B.coef, B.kused, K, B.yex, N, B.pidx, P, B.yp, nr, s);
+        std::vector<double> yph((size_t)nr * P * 2);
+        OVS_HIP(hipMemcpyAsync(yph.data(), B.yp, sizeof(double2) * nr * P, hipMemcpyDeviceToHost, s));
         OVS_HIP(hipStreamSynchronize(s));
         for (int r : amap) {
-          const int kr = ks[r];
-          std::vector<double> xr(xh.begin() + (size_t)r * K * 2, xh.begin() + (size_t)r * K * 2 + 2 * kr);
-          double dn = 0.0;
-          const std::vector<double>& xp = xprev[r];
-          for (int q = 0; q < 2 * kr; ++q) {
-            const double d = xr[q] - (q < (int)xp.size() ? xp[q] : 0.0);
-            dn += d * d;
+          const double* yr = &yph[(size_t)r * P * 2];
+          std::vector<double>& yprev = xprev[r];
+          double dn = 0.0, yn = 0.0;
+          for (int q = 0; q < 2 * P; ++q) {
+            yn += yr[q] * yr[q];
+            if (!yprev.empty()) dn += (yr[q] - yprev[q]) * (yr[q] - yprev[q]);
           }
-          est[r] = nbh[r] * std::sqrt(dn) / (bnorm[r] > 0 ? bnorm[r] : 1.0);
-          xprev[r] = xr;
-          if (hkstop[r] <= i || (!xp.empty() && est[r] <= 0.1 * tol[r])) {
+          const bool had_prev = !yprev.empty();
+          est[r] = (had_prev && yn > 0) ? std::sqrt(dn / yn) : 1.0;
+          yprev.assign(yr, yr + 2 * P);
+          if (hkstop[r] <= i || (had_prev && est[r] <= 0.1 * tol[r])) {
             done[r] = 1;
-            kused[r] = kr;
+            kused[r] = ks[r];
           }
         }
         st = push_map();

@@ -282,6 +282,44 @@ __global__ void __launch_bounds__(256) k_beta(const double* __restrict__ partial
   }
 }
 
+// Probe sketch for the convergence estimate: the entries idx[0..P) of the
+// stored Lanczos vector V~_j (j = *it + 1, or j = 0 before the first step) of
+// every active source are copied to probes[slot][j][P] in FP64.
+template <typename T2>
+__global__ void __launch_bounds__(256) k_probe_gather(const T2* __restrict__ basis, long basis_stride,
+                                                      long N, int ring, const int* __restrict__ it,
+                                                      int first, const int* __restrict__ idx, int P,
+                                                      int kmax, const int* __restrict__ rhs_map,
+                                                      const int* __restrict__ n_active,
+                                                      double2* __restrict__ probes) {
+  const int jj = blockIdx.y;
+  if (jj >= *n_active) return;
+  const int slot = rhs_map[jj];
+  const int j = first ? 0 : *it + 1;
+  if (j >= kmax) return;
+  const long sl = ring ? (j % 3) : j;
+  const T2* v = basis + sl * basis_stride + (long)slot * N;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
+    probes[((long)slot * kmax + j) * P + p] = d2(ld64(v + idx[p]));
+}
+
+// yp[r][p] = yex[r][idx[p]] + sum_{i < k_r} coef[r][i] probes[r][i][p]
+__global__ void __launch_bounds__(256) k_probe_y(const double2* __restrict__ probes,
+                                                 const double2* __restrict__ coef,
+                                                 const int* __restrict__ kvec, int kmax,
+                                                 const double2* __restrict__ yex, long N,
+                                                 const int* __restrict__ idx, int P,
+                                                 double2* __restrict__ yp) {
+  const int r = blockIdx.y;
+  const int k = kvec[r];
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+    Cx<double> acc = yex ? c64(yex[(long)r * N + idx[p]]) : Cx<double>{0, 0};
+    for (int i = 0; i < k; ++i)
+      acc = cfma(c64(coef[(long)r * kmax + i]), c64(probes[((long)r * kmax + i) * P + p]), acc);
+    yp[(long)r * P + p] = d2(acc);
+  }
+}
+
 __global__ void k_advance(int* it) { *it += 1; }
 
 // ===========================================================================
@@ -769,6 +807,28 @@ void launch_beta(const double* partials, int nparts, const CoefArrays& co, const
                  const int* rhs_map, const int* n_active, int nslots, hipStream_t s) {
   hipLaunchKernelGGL(k_beta, dim3(nslots), dim3(256), 0, s, partials, nparts, co, it, rhs_map,
                      n_active);
+}
+
+void launch_probe_gather(bool f32, const void* basis, long basis_stride, long N, bool ring,
+                         const int* it, bool first, const int* idx, int P, int kmax,
+                         const int* rhs_map, const int* n_active, int nslots, double2* probes,
+                         hipStream_t s) {
+  dim3 grid(cdiv_i(P, 256), nslots);
+  if (f32)
+    hipLaunchKernelGGL(k_probe_gather<float2>, grid, dim3(256), 0, s, (const float2*)basis,
+                       basis_stride, N, (int)ring, it, (int)first, idx, P, kmax, rhs_map, n_active,
+                       probes);
+  else
+    hipLaunchKernelGGL(k_probe_gather<double2>, grid, dim3(256), 0, s, (const double2*)basis,
+                       basis_stride, N, (int)ring, it, (int)first, idx, P, kmax, rhs_map, n_active,
+                       probes);
+}
+
+void launch_probe_y(const double2* probes, const double2* coef, const int* kvec, int kmax,
+                    const double2* yex, long N, const int* idx, int P, double2* yp, int nrhs,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_probe_y, dim3(cdiv_i(P, 256), nrhs), dim3(256), 0, s, probes, coef, kvec,
+                     kmax, yex, N, idx, P, yp);
 }
 
 void launch_advance(int* it, hipStream_t s) {

@@ -36,6 +36,8 @@ struct Hop {
 struct Tuning {
   int rhs_block = 1;     // sources per thread in the stencil
   int wg = 256;          // stencil workgroup size
+  int lds_kb = 0;        // dynamic LDS per workgroup (KiB): caps workgroups per CU
+  int order = 0;         // 0: source blocks of a tile adjacent, 1: source block slowest
   bool tuned = false;
 };
 
@@ -69,8 +71,9 @@ struct ovs_lattice_s {
   void* links = nullptr;        // packed links, storage precision
   // tuned stencil configuration per nrhs
   std::vector<std::pair<int, ovs::Tuning>> tuning;
-  // tuned dual-stencil source block per nrhs
-  std::vector<std::pair<int, int>> dual_block;
+  // tuned dual-stencil configuration per nrhs (wg unused: always 256)
+  std::vector<std::pair<int, ovs::Tuning>> dual_tuning;
+  int lds_max_kb = 64;          // largest dynamic LDS request the device accepts
   // cached workspace for sign_apply and apply
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -109,6 +112,8 @@ void launch_pack_links(const double2* canon, void* links, bool f32, const Geomet
 hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out, int nrhs,
                          const Geometry& g, const Hop& hop, bool g5in, bool g5out,
                          const Tuning& tn, hipStream_t s);
+// Lets kernels request dynamic LDS above the default per-workgroup limit.
+void set_lds_limit(int kb);
 
 // Dual stencil of the two-sided Lanczos step: for iteration i = *it,
 //   T = A V~_i, S = A^dagger W~_i (A = gamma5 Dw(mu)), plus per-workgroup
@@ -128,6 +133,8 @@ struct DualArgs {
   const int* rhs_map;
   const int* n_active;
   int nrhs_slots;
+  int lds_kb;          // occupancy cap, as in Tuning
+  int order;
 };
 hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
                        const Hop& hAd, int rhs_block, hipStream_t s);

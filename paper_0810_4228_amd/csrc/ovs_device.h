@@ -101,6 +101,48 @@ __device__ __forceinline__ Cx<double> cdiv(Cx<double> a, Cx<double> b) {
 }
 __device__ __forceinline__ double cabs1(Cx<double> a) { return hypot(a.re, a.im); }
 
+// ---- XCD-aware workgroup -> (site tile, source block) map -----------------
+// Workgroups are handed to the 8 XCDs round robin (bid % 8).  The map gives
+// each XCD a contiguous range of tiles so that neighbour sites read by a tile
+// were loaded into the same XCD's L2 by nearby tiles.  On "planar" lattices
+// (the tile size divides Lx*Ly) the XCD ranges are chunks of time slices and
+// the tiles inside a chunk are ordered plane-tile, then t, then z, so the
+// x/y/z/t neighbours of a tile are at most (tiles per plane)*(t per chunk)
+// tiles away.  The source blocks of one tile are adjacent, so its links are
+// reused from L2 across blocks.
+struct TileMap {
+  int ntiles;      // site tiles of `wg` sites
+  int nrb;         // source blocks
+  int per_xcd;     // workgroups per XCD (grid = 8 * per_xcd)
+  int planar;      // tile size divides Lx*Ly
+  int ppt;         // tiles per xy plane (planar)
+  int tchunk;      // time slices per XCD chunk (planar)
+  int wg;          // sites per tile
+  int plane;       // Lx*Ly
+  int lz;
+  int rb_slow;     // source block is the slowest index
+};
+
+__device__ __forceinline__ bool map_tile(int bid, const TileMap& m, int& site0, int& rb, int& tile) {
+  const int q = (bid & 7) * m.per_xcd + (bid >> 3);
+  if (q >= m.ntiles * m.nrb) return false;
+  rb = m.rb_slow ? q / m.ntiles : q % m.nrb;
+  const int tq = m.rb_slow ? q % m.ntiles : q / m.nrb;
+  tile = tq;
+  if (m.planar) {
+    const int p = tq % m.ppt;
+    int r = tq / m.ppt;
+    const int tin = r % m.tchunk;
+    r /= m.tchunk;
+    const int z = r % m.lz;
+    const int tc = r / m.lz;
+    site0 = p * m.wg + m.plane * (z + m.lz * (tc * m.tchunk + tin));
+  } else {
+    site0 = tq * m.wg;
+  }
+  return true;
+}
+
 // ---- deterministic reductions over one workgroup ------------------------
 // Wave64 tree by shuffles, then a fixed-order pass over the waves in LDS.
 __device__ __forceinline__ double wave_sum(double v) {

@@ -26,6 +26,13 @@ void launch_update(bool f32, const void* T, const void* S, void* basis, long bas
 void launch_beta(const double* partials, int nparts, const CoefArrays& co, const int* it,
                  const int* rhs_map, const int* n_active, int nslots, hipStream_t s);
 void launch_advance(int* it, hipStream_t s);
+void launch_probe_gather(bool f32, const void* basis, long basis_stride, long N, bool ring,
+                         const int* it, bool first, const int* idx, int P, int kmax,
+                         const int* rhs_map, const int* n_active, int nslots, double2* probes,
+                         hipStream_t s);
+void launch_probe_y(const double2* probes, const double2* coef, const int* kvec, int kmax,
+                    const double2* yex, long N, const int* idx, int P, double2* yp, int nrhs,
+                    hipStream_t s);
 
 void launch_make_coef(const double2* x, const double* sv, const double* nb, int kmax, int nrhs,
                       double2* coef, hipStream_t s);

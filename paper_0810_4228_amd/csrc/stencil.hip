@@ -266,11 +266,13 @@ template <typename R, int B>
 __global__ void __launch_bounds__(256)
 k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T* __restrict__ in,
          typename Vec2<R>::T* __restrict__ out, Geometry g, HopR<R> hop_c, int nrhs, int g5in,
-         int g5out) {
+         int g5out, TileMap tm) {
   using T2 = typename Vec2<R>::T;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  int site0, rb, tile;
+  if (!map_tile(blockIdx.x, tm, site0, rb, tile)) return;
+  const int s = site0 + threadIdx.x;
   if (s >= g.V) return;
-  const int r0 = blockIdx.y * B;
+  const int r0 = rb * B;
   const int nsrc = min(B, nrhs - r0);
   const T2* inb = in + (long)r0 * 12 * g.V;
   T2* outb = out + (long)r0 * 12 * g.V;
@@ -299,13 +301,42 @@ k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::
   }
 }
 
+// Dynamic LDS requests above the default per-workgroup limit need a
+// per-kernel opt-in; the limit is set once per process from the device query.
+static int g_lds_limit_kb = 64;
+void set_lds_limit(int kb) { g_lds_limit_kb = kb; }
+static void apply_lds_limit(const void* fn) {
+  if (g_lds_limit_kb > 64)
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g_lds_limit_kb * 1024);
+}
+
+TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order) {
+  TileMap m;
+  m.rb_slow = order;
+  m.wg = wg;
+  m.nrb = nrb;
+  m.plane = g.lx * g.ly;
+  m.lz = g.lz;
+  m.planar = (m.plane % wg == 0) ? 1 : 0;
+  m.ntiles = (g.V + wg - 1) / wg;
+  m.ppt = m.planar ? m.plane / wg : 1;
+  m.tchunk = (m.planar && g.lt % 8 == 0) ? g.lt / 8 : g.lt;
+  const long nb = (long)m.ntiles * nrb;
+  m.per_xcd = (int)((nb + 7) / 8);
+  return m;
+}
+
 template <typename R, int B>
 static void launch_w(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
-                     const Hop& hop_c, bool g5in, bool g5out, int wg, hipStream_t s) {
+                     const Hop& hop_c, bool g5in, bool g5out, int wg, int lds_kb, int order,
+                     hipStream_t s) {
   using T2 = typename Vec2<R>::T;
-  dim3 grid((g.V + wg - 1) / wg, (nrhs + B - 1) / B);
-  hipLaunchKernelGGL((k_wilson<R, B>), grid, dim3(wg), 0, s, (const T2*)links, (const T2*)in,
-                     (T2*)out, g, HopR<R>::make(hop_c), nrhs, (int)g5in, (int)g5out);
+  const TileMap tm = make_tile_map(g, wg, (nrhs + B - 1) / B, order);
+  static bool lds_set = false;
+  if (!lds_set) { apply_lds_limit((const void*)k_wilson<R, B>); lds_set = true; }
+  hipLaunchKernelGGL((k_wilson<R, B>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s, (const T2*)links,
+                     (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs, (int)g5in, (int)g5out,
+                     tm);
 }
 
 hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out, int nrhs,
@@ -314,18 +345,18 @@ hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out,
   const int wg = tn.wg;
   if (f32) {
     switch (tn.rhs_block) {
-      case 1: launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
-      case 2: launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
-      case 3: launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
-      case 4: launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
-      case 6: launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      case 1: launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
+      case 2: launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
+      case 3: launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
+      case 4: launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
+      case 6: launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (tn.rhs_block) {
-      case 1: launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
-      case 2: launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
-      case 3: launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, s); break;
+      case 1: launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
+      case 2: launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
+      case 3: launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -342,17 +373,20 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
        const typename Vec2<R>::T* __restrict__ wbuf, long basis_stride, int ring,
        const int* __restrict__ it, typename Vec2<R>::T* __restrict__ out_t,
        typename Vec2<R>::T* __restrict__ out_s, double* __restrict__ partials, Geometry g,
-       HopR<R> hA, HopR<R> hAd, const int* __restrict__ rhs_map, const int* __restrict__ n_active) {
+       HopR<R> hA, HopR<R> hAd, const int* __restrict__ rhs_map, const int* __restrict__ n_active,
+       TileMap tm) {
   using T2 = typename Vec2<R>::T;
   __shared__ double lds[(256 / 64) * 3 * B];
+  int site0, rb, tile;
+  if (!map_tile(blockIdx.x, tm, site0, rb, tile)) return;  // uniform over the workgroup
   const int na = *n_active;
   const int iter = *it;
   const T2* in_v = basis + (long)(ring ? iter % 3 : iter) * basis_stride;
   const T2* in_w = wbuf + (long)(iter % 3) * basis_stride;
-  const int j0 = blockIdx.y * B;
+  const int j0 = rb * B;
   if (j0 >= na) return;  // uniform over the workgroup
   const int nsrc = min(B, na - j0);
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = site0 + threadIdx.x;
   const bool live = s < g.V;
   const int V = g.V;
   int slot[B];
@@ -422,7 +456,7 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
   block_sum<3 * B>(part, lds);
   if (threadIdx.x == 0) {
     for (int r = 0; r < nsrc; ++r) {
-      double* p = partials + ((long)slot[r] * gridDim.x + blockIdx.x) * 3;
+      double* p = partials + ((long)slot[r] * tm.ntiles + tile) * 3;
       p[0] = part[3 * r + 0];
       p[1] = part[3 * r + 1];
       p[2] = part[3 * r + 2];
@@ -436,11 +470,14 @@ template <typename R, int B>
 static void launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, const Hop& hAd,
                      hipStream_t s) {
   using T2 = typename Vec2<R>::T;
-  dim3 grid(dual_num_wg(g), (a.nrhs_slots + B - 1) / B);
-  hipLaunchKernelGGL((k_dual<R, B>), grid, dim3(256), 0, s, (const T2*)a.links, (const T2*)a.basis,
-                     (const T2*)a.wbuf, a.basis_stride, (int)a.ring, a.it, (T2*)a.out_t,
-                     (T2*)a.out_s, a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd), a.rhs_map,
-                     a.n_active);
+  const TileMap tm = make_tile_map(g, 256, (a.nrhs_slots + B - 1) / B, a.order);
+  static bool lds_set = false;
+  if (!lds_set) { apply_lds_limit((const void*)k_dual<R, B>); lds_set = true; }
+  hipLaunchKernelGGL((k_dual<R, B>), dim3(8 * tm.per_xcd), dim3(256), a.lds_kb * 1024, s,
+                     (const T2*)a.links,
+                     (const T2*)a.basis, (const T2*)a.wbuf, a.basis_stride, (int)a.ring, a.it,
+                     (T2*)a.out_t, (T2*)a.out_s, a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd),
+                     a.rhs_map, a.n_active, tm);
 }
 
 hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
