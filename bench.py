@@ -6,7 +6,7 @@ One step is one ovs_sign_apply over a batch of sources resident in HBM:
 packing, LR deflation projection (when eigentriples are given), the
 two-sided Lanczos loop with per-source convergence checks, the inner sign
 sgn(G_k) e_1 and the combination.  The workload (synthetic, seeded):
-16^3 x 32 lattice, links P_SU3(1 + 0.8 G), m_w = -1.5, mu = 0.4, 12 Gaussian
+16^3 x 32 lattice, links P_SU3(1 + 0.6 G), m_w = -1.5, mu = 0.4, 12 Gaussian
 sources, FP32 storage with FP64 coefficients, target relative error 1e-5.
 
 Prints one JSON line.  value = solves/s of the timed steps.  The roofline
@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Dw(μ) stencil GB/s vs HBM peak; sign(A)b solves/s at stated rel. error"
 HBM_PEAK_GBS = 8000.0
 DIMS = (16, 16, 16, 32)
-EPS, MU, MW = 0.8, 0.4, -1.5
+EPS, MU, MW = 0.6, 0.4, -1.5
 NRHS = 12
 TOL = 1e-5
 KMAX = 1000
@@ -176,7 +176,7 @@ def main():
         "config": {
             "workload": "sgn(gamma5 Dw(mu)) b by two-sided Lanczos, 16^3x32, 12 Gaussian sources",
             "lattice": "16x16x16x32",
-            "links": "P_SU3(1+0.8G) seed 0",
+            "links": "P_SU3(1+0.6G) seed 0",
             "m_w": MW, "mu": MU, "nrhs": NRHS, "tol": TOL, "k_max": KMAX, "n_defl": 0,
             "storage": "f32 vectors and links, f64 coefficients/dots",
             "graph": True,

@@ -129,7 +129,8 @@ ovs_status ovs_autotune(ovs_lattice lat, int32_t nrhs);
 /* Current tuned stencil configuration: rhs block and workgroup size. */
 ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int32_t* wg_size);
 /* Full tuned configuration for nrhs sources, host int32 [8]:
- * {stencil rhs block, stencil workgroup size, stencil LDS cap KiB, stencil block order,
+ * {stencil shape = 100*rhs block + 10*lanes per site + streaming stores,
+ *  stencil workgroup size, stencil LDS cap KiB, stencil block order,
  *  Lanczos dual-stencil rhs block, its workgroup size, its LDS cap KiB, its block order}. */
 ovs_status ovs_get_tuning_ex(ovs_lattice lat, int32_t nrhs, int32_t out[8]);
 
@@ -141,6 +142,18 @@ ovs_status ovs_get_tuning_ex(ovs_lattice lat, int32_t nrhs, int32_t out[8]);
  * |A r_j - lambda_j r_j| <= 1e-6 |lambda_j| (OVS_ERR_ARG otherwise). */
 ovs_status ovs_deflation_set(ovs_lattice lat, int32_t m, const double* lambda, const void* R,
                              const void* L, ovs_deflation* out);
+/* Compute the m critical eigentriples on the GPU (Section 5 obtains them with
+ * ARPACK; here Chebyshev-filtered subspace iteration on A^2 and on A^dagger^2
+ * with Rayleigh-Ritz steps on A, A^dagger; FP64 throughout, also on FP32
+ * lattices).  tol: target relative residual |A r - lambda r| / |lambda|;
+ * max_iter: filter passes per side.  Returns OVS_WARN_NOT_CONVERGED (handle
+ * still created) if tol or |L^dagger R - I| <= 1e-6 was not reached. */
+ovs_status ovs_deflation_compute(ovs_lattice lat, int32_t m, double tol, int32_t max_iter,
+                                 ovs_deflation* out);
+/* Copy out eigenvalues (host complex128 [m]), R and L (device complex128
+ * [m][V][4][3]) and info (host double [3]: max relative residual,
+ * max |L^dagger R - I|, filter passes).  Any pointer may be NULL. */
+ovs_status ovs_deflation_get(ovs_deflation d, double* lambda, void* R, void* L, double* info);
 ovs_status ovs_deflation_destroy(ovs_deflation d);
 
 /* ---- sign function ------------------------------------------------------ */
@@ -179,7 +192,17 @@ ovs_status ovs_inner_sign_tridiag(ovs_lattice lat, int32_t batch, int32_t k, con
 ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, const double* H,
                                      double* x, double* err);
 
+/* Eigen-decomposition of a small general complex matrix on the host (the
+ * Rayleigh-Ritz step of ovs_deflation_compute): A host complex128 n x n,
+ * column major; lambda host complex128 [n]; V host complex128 n x n, unit-norm
+ * right eigenvectors as columns.  No GPU is used.  OVS_ERR_ARG if the QR
+ * iteration does not converge. */
+ovs_status ovs_small_eig(int32_t n, const double* A, double* lambda, double* V);
+
 const char* ovs_status_string(ovs_status s);
+/* Description of the last failing runtime call on this host thread (for
+ * OVS_ERR_HIP); empty if none. */
+const char* ovs_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -40,14 +40,20 @@ EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
     "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
     "ovs_field_apply", "ovs_field_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex",
-    "ovs_deflation_set", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_last_coefficients",
-    "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_status_string",
+    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_last_coefficients",
+    "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
 ]
 
 
 class OvsError(RuntimeError):
     def __init__(self, status, what):
-        super().__init__(f"{what}: {status_string(status)} ({status})")
+        detail = ""
+        if status == OVS_ERR_HIP:
+            try:
+                detail = " [" + load().ovs_last_error().decode() + "]"
+            except Exception:
+                pass
+        super().__init__(f"{what}: {status_string(status)} ({status}){detail}")
         self.status = status
 
 
@@ -103,10 +109,13 @@ def load():
         "ovs_get_tuning_ex": [P, I, IP],
         "ovs_deflation_set": [P, I, DP, P, P, ctypes.POINTER(P)],
         "ovs_deflation_destroy": [P],
+        "ovs_deflation_compute": [P, I, D, I, ctypes.POINTER(P)],
+        "ovs_deflation_get": [P, DP, P, P, DP],
         "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
         "ovs_last_coefficients": [P, DP, DP, DP, DP],
         "ovs_inner_sign_tridiag": [P, I, I, DP, DP, DP, DP, DP],
         "ovs_inner_sign_hessenberg": [P, I, I, DP, DP, DP],
+        "ovs_small_eig": [I, DP, DP, DP],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -114,6 +123,8 @@ def load():
         f.restype = ctypes.c_int32
     lib.ovs_status_string.argtypes = [ctypes.c_int32]
     lib.ovs_status_string.restype = ctypes.c_char_p
+    lib.ovs_last_error.argtypes = []
+    lib.ovs_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -221,7 +232,10 @@ class Lattice:
         out = (ctypes.c_int32 * 8)()
         _check(self._lib.ovs_get_tuning_ex(self._h, int(nrhs), out), "ovs_get_tuning_ex")
         keys = ("rhs_block", "wg", "lds_kb", "order")
-        return {"stencil": dict(zip(keys, out[0:4])), "dual": dict(zip(keys, out[4:8]))}
+        st = dict(zip(keys, out[0:4]))
+        shape = st["rhs_block"]
+        st.update(rhs_block=shape // 100, lanes_per_site=(shape // 10) % 10, streaming_store=shape % 10)
+        return {"stencil": st, "dual": dict(zip(keys, out[4:8]))}
 
     def deflation_set(self, lam, R, L):
         """lam: complex [m] (host); R, L: complex128 CUDA [m, 12V]."""
@@ -237,6 +251,13 @@ class Lattice:
                                            ctypes.c_void_p(L.data_ptr()), ctypes.byref(h)),
                "ovs_deflation_set")
         return Deflation(self, h, m)
+
+    def deflation_compute(self, m, tol=1e-10, max_iter=30):
+        """Critical eigentriples computed on the GPU.  Returns (Deflation, status)."""
+        h = ctypes.c_void_p()
+        st = _check(self._lib.ovs_deflation_compute(self._h, int(m), float(tol), int(max_iter),
+                                                    ctypes.byref(h)), "ovs_deflation_compute")
+        return Deflation(self, h, int(m)), st
 
     def sign_apply(self, b, k_max, defl=None, n_defl=None, tol=None, method="2sl",
                    two_pass=False, graph=False, overlap=False, out=None):
@@ -299,6 +320,18 @@ class Lattice:
         return x, err
 
 
+def small_eig(A):
+    """Eigenvalues and unit right eigenvectors of a small complex matrix (host code of the library)."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    Ac = np.ascontiguousarray(A.T)  # column major
+    lam = np.zeros(n, dtype=np.complex128)
+    V = np.zeros((n, n), dtype=np.complex128)
+    _check(load().ovs_small_eig(n, _dptr(Ac.view(np.float64)), _dptr(lam.view(np.float64)),
+                                _dptr(V.view(np.float64))), "ovs_small_eig")
+    return lam, V.T.copy()  # V was filled column major
+
+
 class Field:
     """ovs_field: nrhs sources resident in the library's layout."""
 
@@ -347,6 +380,19 @@ class Deflation:
         self.lat = lat
         self._h = h
         self.m = m
+
+    def get(self):
+        """(lambda [m] host, R [m, 12V] CUDA, L [m, 12V] CUDA, info [3] host)."""
+        torch = _torch()
+        lam = np.zeros(self.m, dtype=np.complex128)
+        info = np.zeros(3)
+        R = torch.empty((self.m, self.lat.N), dtype=torch.complex128, device="cuda")
+        L = torch.empty_like(R)
+        _check(self.lat._lib.ovs_deflation_get(self._h, _dptr(lam.view(np.float64)),
+                                               ctypes.c_void_p(R.data_ptr()),
+                                               ctypes.c_void_p(L.data_ptr()), _dptr(info)),
+               "ovs_deflation_get")
+        return lam, R, L, info
 
     def close(self):
         if getattr(self, "_h", None):

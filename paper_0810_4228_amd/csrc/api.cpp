@@ -7,14 +7,24 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
 
 #include "ovs_common.h"
+#include "dense.h"
+#include "ovs_eig.h"
 #include "ovs_krylov.h"
 
 using namespace ovs;
+
+namespace ovs {
+static thread_local char g_last_error[512] = "";
+void record_error(const char* what, int line, hipError_t e) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s (line %d): %s", what, line, hipGetErrorString(e));
+}
+}  // namespace ovs
 
 namespace {
 
@@ -23,6 +33,7 @@ namespace {
 struct StreamScope {
   ovs_lattice_s* l;
   explicit StreamScope(ovs_lattice_s* lat) : l(lat) {
+    (void)hipGetLastError();  // drop a stale error left by an earlier library call (e.g. rocBLAS)
     (void)hipEventRecord(l->ev_in, l->user_stream);
     (void)hipStreamWaitEvent(l->stream, l->ev_in, 0);
   }
@@ -127,15 +138,15 @@ ovs_status ensure_ws(ovs_lattice_s* l, size_t bytes) {
 
 void pack_field(const ovs_lattice_s* l, const void* canon, void* field, int nrhs) {
   if (l->prec == OVS_F32_STORE)
-    launch_pack_f32((const double2*)canon, (float2*)field, nrhs, l->g.V, l->stream);
+    launch_pack_f32((const double2*)canon, (float2*)field, nrhs, l->g, l->stream);
   else
-    launch_pack_f64((const double2*)canon, (double2*)field, nrhs, l->g.V, l->stream);
+    launch_pack_f64((const double2*)canon, (double2*)field, nrhs, l->g, l->stream);
 }
 void unpack_field(const ovs_lattice_s* l, const void* field, void* canon, int nrhs) {
   if (l->prec == OVS_F32_STORE)
-    launch_unpack_f32((const float2*)field, (double2*)canon, nrhs, l->g.V, l->stream);
+    launch_unpack_f32((const float2*)field, (double2*)canon, nrhs, l->g, l->stream);
   else
-    launch_unpack_f64((const double2*)field, (double2*)canon, nrhs, l->g.V, l->stream);
+    launch_unpack_f64((const double2*)field, (double2*)canon, nrhs, l->g, l->stream);
 }
 
 bool ready(const ovs_lattice_s* l) { return l && l->links_set && l->params_set; }
@@ -147,8 +158,10 @@ constexpr double kQuadAccept = 3e-7;  // coarse/fine difference accepted at step
 constexpr int kProbe = 512;           // sampled entries per source for the convergence estimate
 constexpr int kCheckEvery = 25;       // iterations between convergence checks
 
-// Distinct sampled positions in [0, N), sorted (fixed sequence, same for all calls).
-std::vector<int> probe_positions(long N, int P) {
+// Distinct sampled field positions c*Vs + s (s < V), sorted; a fixed
+// sequence, the same for all calls.
+std::vector<int> probe_positions(const Geometry& g, int P) {
+  const long N = 12L * g.V;
   std::vector<int> idx;
   idx.reserve(P);
   std::vector<char> used(N, 0);
@@ -158,12 +171,13 @@ std::vector<int> probe_positions(long N, int P) {
     const long p = (long)((st >> 17) % (unsigned long long)N);
     if (!used[p]) {
       used[p] = 1;
-      idx.push_back((int)p);
+      idx.push_back((int)((p / g.V) * g.Vs + (p % g.V)));
     }
   }
   std::sort(idx.begin(), idx.end());
   return idx;
 }
+
 
 void quad_range(double h, int& n0, int& nnode) {
   n0 = (int)std::floor(kULo / h);
@@ -216,6 +230,8 @@ ovs_status inner_sign(ovs_lattice_s* l, bool tri, const double2* alpha, const do
 // ============================================================================
 extern "C" {
 
+const char* ovs_last_error(void) { return g_last_error; }
+
 const char* ovs_status_string(ovs_status s) {
   switch (s) {
     case OVS_OK: return "ok";
@@ -244,7 +260,7 @@ ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_pr
   if (prec != OVS_F64 && prec != OVS_F32_STORE) return OVS_ERR_ARG;
   ovs_lattice_s* l = new (std::nothrow) ovs_lattice_s();
   if (!l) return OVS_ERR_ALLOC;
-  l->g = Geometry{dims[0], dims[1], dims[2], dims[3], (int)v};
+  l->g = Geometry{dims[0], dims[1], dims[2], dims[3], (int)v, (int)(((v + 63) / 64) * 64 + 64)};
   for (int i = 0; i < 4; ++i) l->bc[i] = bc[i];
   l->prec = prec;
   l->user_stream = (hipStream_t)hip_stream;
@@ -264,7 +280,7 @@ ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_pr
     set_lds_limit(l->lds_max_kb);
     (void)hipGetLastError();
   }
-  const size_t lb = 4ul * 9 * v * elem_bytes(l);
+  const size_t lb = 4ul * 9 * l->g.Vs * elem_bytes(l);
   if (hipMalloc(&l->links, lb) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipStreamDestroy(l->stream);
@@ -279,6 +295,7 @@ ovs_status ovs_lattice_destroy(ovs_lattice l) {
   if (!l) return OVS_ERR_ARG;
   (void)hipStreamSynchronize(l->stream);
   if (l->links) (void)hipFree(l->links);
+  if (l->links64) (void)hipFree(l->links64);
   if (l->ws) (void)hipFree(l->ws);
   (void)hipEventDestroy(l->ev_in);
   (void)hipEventDestroy(l->ev_out);
@@ -291,6 +308,14 @@ ovs_status ovs_set_links(ovs_lattice l, const void* U) {
   if (!l || !U) return OVS_ERR_ARG;
   StreamScope sc(l);
   launch_pack_links((const double2*)U, l->links, l->prec == OVS_F32_STORE, l->g, l->bc, l->stream);
+  if (l->prec == OVS_F32_STORE) {
+    if (!l->links64 && hipMalloc(&l->links64, 4ul * 9 * l->g.Vs * sizeof(double2)) != hipSuccess) {
+      (void)hipGetLastError();
+      l->links64 = nullptr;
+      return OVS_ERR_ALLOC;
+    }
+    launch_pack_links((const double2*)U, l->links64, false, l->g, l->bc, l->stream);
+  }
   OVS_HIP(hipGetLastError());
   l->links_set = true;
   return OVS_OK;
@@ -308,7 +333,7 @@ ovs_status ovs_set_params(ovs_lattice l, double m_w, double mu) {
 ovs_status ovs_apply(ovs_lattice l, ovs_op op, const void* x, void* y, int32_t nrhs) {
   if (!l || !x || !y || x == y || nrhs < 1 || nrhs > kMaxNrhs || !valid_op(op)) return OVS_ERR_ARG;
   if (!ready(l)) return OVS_ERR_STATE;
-  const size_t fb = (size_t)nrhs * 12 * l->g.V * elem_bytes(l);
+  const size_t fb = (size_t)nrhs * 12 * l->g.Vs * elem_bytes(l);
   ovs_status st = ensure_ws(l, 2 * fb + 512);
   if (st != OVS_OK) return st;
   StreamScope sc(l);
@@ -334,7 +359,7 @@ ovs_status ovs_field_create(ovs_lattice l, int32_t nrhs, ovs_field* out) {
   if (!f) return OVS_ERR_ALLOC;
   f->lat = l;
   f->nrhs = nrhs;
-  if (hipMalloc(&f->data, (size_t)nrhs * 12 * l->g.V * elem_bytes(l)) != hipSuccess) {
+  if (hipMalloc(&f->data, (size_t)nrhs * 12 * l->g.Vs * elem_bytes(l)) != hipSuccess) {
     (void)hipGetLastError();
     delete f;
     return OVS_ERR_ALLOC;
@@ -426,7 +451,7 @@ ovs_status ovs_get_tuning(ovs_lattice l, int32_t nrhs, int32_t* rhs_block, int32
 ovs_status ovs_get_tuning_ex(ovs_lattice l, int32_t nrhs, int32_t out[8]) {
   if (!l || nrhs < 1 || !out) return OVS_ERR_ARG;
   const Tuning t = get_tuning(l, nrhs), d = get_dual_tuning(l, nrhs);
-  out[0] = t.rhs_block; out[1] = t.wg; out[2] = t.lds_kb; out[3] = t.order;
+  out[0] = t.rhs_block * 100 + t.g * 10 + t.nt; out[1] = t.wg; out[2] = t.lds_kb; out[3] = t.order;
   out[4] = d.rhs_block; out[5] = 256; out[6] = d.lds_kb; out[7] = d.order;
   return OVS_OK;
 }
@@ -443,7 +468,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
   {
     StreamScope sc(l);
     // deterministic non-zero contents: zero then the links' bytes do not matter for timing
-    (void)hipMemsetAsync(fi->data, 0, (size_t)nrhs * 12 * l->g.V * elem_bytes(l), l->stream);
+    (void)hipMemsetAsync(fi->data, 0, (size_t)nrhs * 12 * l->g.Vs * elem_bytes(l), l->stream);
     const int blocks_f32[] = {1, 2, 3, 4, 6};
     const int blocks_f64[] = {1, 2, 3};
     const int wgs[] = {64, 128, 256};
@@ -451,13 +476,22 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
     double best_ms = 1e300;
     const int* bl = f32 ? blocks_f32 : blocks_f64;
     const int nb = f32 ? 5 : 3;
-    for (int ib = 0; ib < nb; ++ib) {
-      if (bl[ib] > nrhs && bl[ib] != 1) continue;
+    // candidates: source blocking in registers (g = 1, block b) or lanes per
+    // site (g > 1, block 1)
+    std::vector<std::pair<int, int>> shapes;
+    for (int ib = 0; ib < nb; ++ib)
+      if (bl[ib] <= nrhs || bl[ib] == 1) shapes.push_back({bl[ib], 1});
+    for (int gg : {2, 4, 8})
+      if (gg <= nrhs) shapes.push_back({1, gg});
+    for (auto sh : shapes) {
       for (int w : wgs)
         for (int kb : lds_candidates(l))
-          for (int order = 0; order < 2; ++order) {
+          for (int order = 0; order < 2; ++order)
+            for (int nt = 0; nt < 2; ++nt) {
             Tuning t;
-            t.rhs_block = bl[ib];
+            t.rhs_block = sh.first;
+            t.g = sh.second;
+            t.nt = nt;
             t.wg = w;
             t.lds_kb = kb;
             t.order = order;
@@ -474,7 +508,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
     if (st == OVS_OK) set_tuning(l, nrhs, best);
     // dual-stencil source block for the Lanczos step
     if (st == OVS_OK) {
-      const long N = 12L * l->g.V;
+      const long N = 12L * l->g.Vs;
       const size_t fb = (size_t)nrhs * N * elem_bytes(l);
       const int nwg = dual_num_wg(l->g);
       Arena a{nullptr};
@@ -552,7 +586,7 @@ ovs_status ovs_deflation_set(ovs_lattice l, int32_t m, const double* lambda, con
   *out = nullptr;
   for (int j = 0; j < 2 * m; ++j)
     if (!std::isfinite(lambda[j])) return OVS_ERR_ARG;
-  const long N = 12L * l->g.V;
+  const long N = 12L * l->g.Vs;  // padded field length
   ovs_deflation_s* d = new (std::nothrow) ovs_deflation_s();
   if (!d) return OVS_ERR_ALLOC;
   d->lat = l;
@@ -570,8 +604,8 @@ ovs_status ovs_deflation_set(ovs_lattice l, int32_t m, const double* lambda, con
   ovs_status st = OVS_OK;
   {
     StreamScope sc(l);
-    launch_pack_f64((const double2*)R, d->R, m, l->g.V, l->stream);
-    launch_pack_f64((const double2*)L, d->L, m, l->g.V, l->stream);
+    launch_pack_f64((const double2*)R, d->R, m, l->g, l->stream);
+    launch_pack_f64((const double2*)L, d->L, m, l->g, l->stream);
     std::vector<double> sg(m);
     for (int j = 0; j < m; ++j) sg[j] = (lambda[2 * j] >= 0.0) ? 1.0 : -1.0;
     (void)hipMemcpyAsync(d->sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice, l->stream);
@@ -607,6 +641,60 @@ ovs_status ovs_deflation_set(ovs_lattice l, int32_t m, const double* lambda, con
   return OVS_OK;
 }
 
+ovs_status ovs_deflation_compute(ovs_lattice l, int32_t m, double tol, int32_t max_iter,
+                                 ovs_deflation* out) {
+  if (!l || !out || m < 1 || m > kMaxDefl || !(tol > 0.0) || max_iter < 1) return OVS_ERR_ARG;
+  if (!ready(l)) return OVS_ERR_STATE;
+  *out = nullptr;
+  const long N = 12L * l->g.Vs;
+  ovs_deflation_s* d = new (std::nothrow) ovs_deflation_s();
+  if (!d) return OVS_ERR_ALLOC;
+  d->lat = l;
+  d->m = m;
+  d->R = d->L = nullptr;
+  d->sgn = nullptr;
+  if (hipMalloc(&d->R, sizeof(double2) * m * N) != hipSuccess ||
+      hipMalloc(&d->L, sizeof(double2) * m * N) != hipSuccess ||
+      hipMalloc(&d->sgn, sizeof(double) * m) != hipSuccess) {
+    (void)hipGetLastError();
+    ovs_deflation_destroy(d);
+    return OVS_ERR_ALLOC;
+  }
+  d->lambda.assign(2 * m, 0.0);
+  ovs_status st;
+  {
+    StreamScope sc(l);
+    st = compute_eigentriples(l, m, tol, max_iter, d->R, d->L, d->lambda.data(), d->info);
+    if (st == OVS_OK) {
+      std::vector<double> sg(m);
+      for (int j = 0; j < m; ++j) sg[j] = (d->lambda[2 * j] >= 0.0) ? 1.0 : -1.0;
+      if (hipMemcpyAsync(d->sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice, l->stream) != hipSuccess ||
+          hipStreamSynchronize(l->stream) != hipSuccess)
+        st = OVS_ERR_HIP;
+    }
+  }
+  if (st != OVS_OK) {
+    ovs_deflation_destroy(d);
+    return st;
+  }
+  *out = d;
+  // residual above the requested tolerance or poor biorthogonality: usable, flagged
+  return (d->info[0] <= tol && d->info[1] <= 1e-6) ? OVS_OK : OVS_WARN_NOT_CONVERGED;
+}
+
+ovs_status ovs_deflation_get(ovs_deflation d, double* lambda, void* R, void* L, double* info) {
+  if (!d) return OVS_ERR_ARG;
+  ovs_lattice_s* l = d->lat;
+  if (lambda) std::memcpy(lambda, d->lambda.data(), sizeof(double) * 2 * d->m);
+  if (info) std::memcpy(info, d->info, sizeof(d->info));
+  StreamScope sc(l);
+  if (R) launch_unpack_f64(d->R, (double2*)R, d->m, l->g, l->stream);
+  if (L) launch_unpack_f64(d->L, (double2*)L, d->m, l->g, l->stream);
+  OVS_HIP(hipGetLastError());
+  OVS_HIP(hipStreamSynchronize(l->stream));
+  return OVS_OK;
+}
+
 ovs_status ovs_deflation_destroy(ovs_deflation d) {
   if (!d) return OVS_ERR_ARG;
   (void)hipStreamSynchronize(d->lat->stream);
@@ -626,8 +714,8 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
   if (!ready(l)) return OVS_ERR_STATE;
   if (method != OVS_2SL && method != OVS_ARNOLDI) return OVS_ERR_ARG;
   if (flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_OVERLAP)) return OVS_ERR_ARG;
-  const long N = 12L * l->g.V;
-  if (k_max > N) return OVS_ERR_ARG;
+  if (k_max > 12L * l->g.V) return OVS_ERR_ARG;
+  const long N = 12L * l->g.Vs;  // padded field length of one source
   int m = 0;
   if (defl) {
     if (defl->lat != l || n_defl < 0 || n_defl > defl->m) return OVS_ERR_ARG;
@@ -661,7 +749,7 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
     double2 *probes, *yp;
   } B{};
   const bool probing = tol != nullptr && !arn;
-  const int P = (int)std::min<long>(kProbe, N);
+  const int P = (int)std::min<long>(kProbe, 12L * l->g.V);
   auto layout = [&](Arena& a) {
     B.Bq = a.take<double2>((size_t)nr * N);
     if (m > 0) {
@@ -732,6 +820,9 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
 
   StreamScope scope(l);
   hipStream_t s = l->stream;
+  // stencil outputs write only s < V: their pad entries must start at zero
+  launch_zero_pad(B.T, f32, 12L * nr, l->g, s);
+  if (B.S) launch_zero_pad(B.S, f32, 12L * nr, l->g, s);
   hipEvent_t ev[5];
   for (auto& e : ev) OVS_HIP(hipEventCreate(&e));
   struct EvGuard {
@@ -743,7 +834,7 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
 
   // ---- deflation and start vectors ----
   OVS_HIP(hipEventRecord(ev[0], s));
-  launch_pack_f64((const double2*)b, B.Bq, nr, l->g.V, s);
+  launch_pack_f64((const double2*)b, B.Bq, nr, l->g, s);
   if (m > 0)
     launch_defl(defl->R, defl->L, B.Bq, defl->sgn, m, nr, N, B.dpart, B.CD, B.bR, B.bL, B.yex, s);
   launch_start(B.bR, B.bL, nr, N, B.spart, B.sums, B.basis, arn ? nullptr : B.wbuf, f32, s);
@@ -820,7 +911,7 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
     if (st != OVS_OK) return st;
     std::vector<int> pidx_h;
     if (probing) {
-      pidx_h = probe_positions(N, P);
+      pidx_h = probe_positions(l->g, P);
       OVS_HIP(hipMemcpyAsync(B.pidx, pidx_h.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
       launch_probe_gather(f32, B.basis, bstride, N, two_pass, B.ints, true, B.pidx, P, K,
                           B.rhs_map, B.ints + 1, nr, B.probes, s);
@@ -1005,8 +1096,8 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
     launch_combine(f32, B.basis, bstride, N, B.coef, K, B.kused, B.yex, B.Y, nr, s);
     OVS_HIP(hipGetLastError());
   }
-  if (flags & OVS_FLAG_OVERLAP) launch_overlap(B.Bq, B.Y, (long)nr * N, l->g.V, s);
-  launch_unpack_f64(B.Y, (double2*)y, nr, l->g.V, s);
+  if (flags & OVS_FLAG_OVERLAP) launch_overlap(B.Bq, B.Y, (long)nr * N, l->g.Vs, s);
+  launch_unpack_f64(B.Y, (double2*)y, nr, l->g, s);
   OVS_HIP(hipEventRecord(ev[4], s));
   OVS_HIP(hipGetLastError());
   OVS_HIP(hipStreamSynchronize(s));
@@ -1107,6 +1198,14 @@ static ovs_status inner_sign_entry(ovs_lattice l, bool tri, int batch, int k, co
   OVS_HIP(hipStreamSynchronize(s));
   if (err) std::memcpy(err, eh.data(), sizeof(double) * batch);
   return OVS_OK;
+}
+
+ovs_status ovs_small_eig(int32_t n, const double* A, double* lambda, double* V) {
+  if (n < 1 || n > 4096 || !A || !lambda || !V) return OVS_ERR_ARG;
+  const int r = dense::eig(n, reinterpret_cast<const std::complex<double>*>(A),
+                           reinterpret_cast<std::complex<double>*>(lambda),
+                           reinterpret_cast<std::complex<double>*>(V));
+  return r == 0 ? OVS_OK : OVS_ERR_ARG;
 }
 
 ovs_status ovs_inner_sign_tridiag(ovs_lattice l, int32_t batch, int32_t k, const double* diag,

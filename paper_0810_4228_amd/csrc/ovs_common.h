@@ -1,11 +1,13 @@
 // Internal declarations shared by the ovsign HIP sources.
 //
 // Device layouts (private to the library):
-//   field  : [nrhs][12][V] complex, component c = 3*spin + colour; complex is
-//            double2 (OVS_F64) or float2 (OVS_F32_STORE)
-//   links  : [4][9][V] complex, entry 3*a + b of U_{x,nu}; the boundary sign
+//   field  : [nrhs][12][Vs] complex, component c = 3*spin + colour; complex is
+//            double2 (OVS_F64) or float2 (OVS_F32_STORE).  Vs = V rounded up
+//            to a wave plus one wave, so component planes are not a power of
+//            two apart (L2 set aliasing); pad entries s >= V are kept zero.
+//   links  : [4][9][Vs] complex, entry 3*a + b of U_{x,nu}; the boundary sign
 //            of the link leaving the last slice in direction nu is folded in
-//   FP64 work fields (deflation, results): [nrhs][12][V] double2
+//   FP64 work fields (deflation, results): [nrhs][12][Vs] double2
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,6 +27,7 @@ constexpr int kMaxDefl = 1024;
 struct Geometry {
   int lx, ly, lz, lt;
   int V;
+  int Vs;   // padded stride of one component plane (V rounded up, plus one wave)
 };
 
 // Hop coefficients kappa*eta_nu^{+-} for one operator application.
@@ -38,6 +41,8 @@ struct Tuning {
   int wg = 256;          // stencil workgroup size
   int lds_kb = 0;        // dynamic LDS per workgroup (KiB): caps workgroups per CU
   int order = 0;         // 0: source blocks of a tile adjacent, 1: source block slowest
+  int g = 1;             // lanes sharing one site (each lane one source); 1 = source blocking
+  int nt = 0;            // streaming (non-temporal) stores of the output
   bool tuned = false;
 };
 
@@ -69,6 +74,7 @@ struct ovs_lattice_s {
   bool params_set = false;
   bool links_set = false;
   void* links = nullptr;        // packed links, storage precision
+  void* links64 = nullptr;      // FP64 copy for the eigensolver (FP32 lattices only)
   // tuned stencil configuration per nrhs
   std::vector<std::pair<int, ovs::Tuning>> tuning;
   // tuned dual-stencil configuration per nrhs (wg unused: always 256)
@@ -92,19 +98,22 @@ struct ovs_deflation_s {
   ovs_lattice_s* lat;
   int m;
   std::vector<double> lambda;   // host complex [m]
-  double2* R;                    // device [m][12][V]
-  double2* L;                    // device [m][12][V]
+  double2* R;                    // device [m][12][Vs]
+  double2* L;                    // device [m][12][Vs]
   double* sgn;                   // device [m] sgn(Re lambda)
+  double info[3] = {0, 0, 0};    // computed: max residual, max |L^dag R - I|, passes
 };
 
 // ---- launchers implemented in stencil.hip --------------------------------
 namespace ovs {
 
 // canonical complex128 [nrhs][V][12]  <->  internal [nrhs][12][V]
-void launch_pack_f64(const double2* canon, double2* field, int nrhs, int V, hipStream_t s);
-void launch_pack_f32(const double2* canon, float2* field, int nrhs, int V, hipStream_t s);
-void launch_unpack_f64(const double2* field, double2* canon, int nrhs, int V, hipStream_t s);
-void launch_unpack_f32(const float2* field, double2* canon, int nrhs, int V, hipStream_t s);
+void launch_pack_f64(const double2* canon, double2* field, int nrhs, const Geometry& g, hipStream_t s);
+void launch_pack_f32(const double2* canon, float2* field, int nrhs, const Geometry& g, hipStream_t s);
+void launch_unpack_f64(const double2* field, double2* canon, int nrhs, const Geometry& g, hipStream_t s);
+void launch_unpack_f32(const float2* field, double2* canon, int nrhs, const Geometry& g, hipStream_t s);
+// zero the pad entries [V, Vs) of nplanes component planes
+void launch_zero_pad(void* base, bool f32, long nplanes, const Geometry& g, hipStream_t s);
 void launch_pack_links(const double2* canon, void* links, bool f32, const Geometry& g,
                        const int bc[4], hipStream_t s);
 
@@ -143,8 +152,15 @@ int dual_num_wg(const Geometry& g);
 }  // namespace ovs
 
 // ---- error helpers --------------------------------------------------------
-#define OVS_HIP(call)                                   \
-  do {                                                  \
-    hipError_t e_ = (call);                             \
-    if (e_ != hipSuccess) return OVS_ERR_HIP;           \
+namespace ovs {
+// Records the failing runtime call for ovs_last_error (per host thread).
+void record_error(const char* what, int line, hipError_t e);
+}
+#define OVS_HIP(call)                                           \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) {                                     \
+      ovs::record_error(#call, __LINE__, e_);                   \
+      return OVS_ERR_HIP;                                       \
+    }                                                           \
   } while (0)

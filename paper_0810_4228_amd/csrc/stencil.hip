@@ -16,20 +16,22 @@ namespace ovs {
 // ---- canonical <-> internal layout ----------------------------------------
 
 template <typename T2>
-__global__ void k_pack(const double2* __restrict__ canon, T2* __restrict__ field, int nrhs, int V) {
-  const long n = (long)nrhs * 12 * V;
+__global__ void k_pack(const double2* __restrict__ canon, T2* __restrict__ field, int nrhs, int V,
+                       int Vs) {
+  const long n = (long)nrhs * 12 * Vs;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    // e indexes the output [r][c][s] so the store is coalesced
-    const int s = (int)(e % V);
-    const long rc = e / V;
+    // e indexes the padded output [r][c][Vs] so the store is coalesced; pad entries are zero
+    const int s = (int)(e % Vs);
+    const long rc = e / Vs;
     const int c = (int)(rc % 12);
     const long r = rc / 12;
-    st64(field + e, c64(canon[(r * V + s) * 12 + c]));
+    st64(field + e, s < V ? c64(canon[(r * V + s) * 12 + c]) : Cx<double>{0.0, 0.0});
   }
 }
 
 template <typename T2>
-__global__ void k_unpack(const T2* __restrict__ field, double2* __restrict__ canon, int nrhs, int V) {
+__global__ void k_unpack(const T2* __restrict__ field, double2* __restrict__ canon, int nrhs, int V,
+                         int Vs) {
   const long n = (long)nrhs * 12 * V;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
     // e indexes the output [r][s][c]
@@ -37,7 +39,7 @@ __global__ void k_unpack(const T2* __restrict__ field, double2* __restrict__ can
     const long rs = e / 12;
     const int s = (int)(rs % V);
     const long r = rs / V;
-    canon[e] = d2(ld64(field + (r * 12 + c) * V + s));
+    canon[e] = d2(ld64(field + (r * 12 + c) * Vs + s));
   }
 }
 
@@ -48,32 +50,53 @@ static int grid_for(long n) {
   return (int)b;
 }
 
-void launch_pack_f64(const double2* canon, double2* field, int nrhs, int V, hipStream_t s) {
-  long n = (long)nrhs * 12 * V;
-  hipLaunchKernelGGL(k_pack<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon, field, nrhs, V);
+void launch_pack_f64(const double2* canon, double2* field, int nrhs, const Geometry& g, hipStream_t s) {
+  long n = (long)nrhs * 12 * g.Vs;
+  hipLaunchKernelGGL(k_pack<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon, field, nrhs, g.V, g.Vs);
 }
-void launch_pack_f32(const double2* canon, float2* field, int nrhs, int V, hipStream_t s) {
-  long n = (long)nrhs * 12 * V;
-  hipLaunchKernelGGL(k_pack<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon, field, nrhs, V);
+void launch_pack_f32(const double2* canon, float2* field, int nrhs, const Geometry& g, hipStream_t s) {
+  long n = (long)nrhs * 12 * g.Vs;
+  hipLaunchKernelGGL(k_pack<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon, field, nrhs, g.V, g.Vs);
 }
-void launch_unpack_f64(const double2* field, double2* canon, int nrhs, int V, hipStream_t s) {
-  long n = (long)nrhs * 12 * V;
-  hipLaunchKernelGGL(k_unpack<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, field, canon, nrhs, V);
+void launch_unpack_f64(const double2* field, double2* canon, int nrhs, const Geometry& g, hipStream_t s) {
+  long n = (long)nrhs * 12 * g.V;
+  hipLaunchKernelGGL(k_unpack<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, field, canon, nrhs, g.V, g.Vs);
 }
-void launch_unpack_f32(const float2* field, double2* canon, int nrhs, int V, hipStream_t s) {
-  long n = (long)nrhs * 12 * V;
-  hipLaunchKernelGGL(k_unpack<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, field, canon, nrhs, V);
+void launch_unpack_f32(const float2* field, double2* canon, int nrhs, const Geometry& g, hipStream_t s) {
+  long n = (long)nrhs * 12 * g.V;
+  hipLaunchKernelGGL(k_unpack<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, field, canon, nrhs, g.V, g.Vs);
+}
+
+template <typename T2>
+__global__ void k_zero_pad(T2* __restrict__ base, long nplanes, int V, int Vs) {
+  const int w = Vs - V;
+  const long n = nplanes * w;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    st64(base + (e / w) * Vs + V + (e % w), Cx<double>{0.0, 0.0});
+}
+
+void launch_zero_pad(void* base, bool f32, long nplanes, const Geometry& g, hipStream_t s) {
+  const long n = nplanes * (g.Vs - g.V);
+  if (n <= 0) return;
+  if (f32)
+    hipLaunchKernelGGL(k_zero_pad<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, (float2*)base, nplanes, g.V, g.Vs);
+  else
+    hipLaunchKernelGGL(k_zero_pad<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, (double2*)base, nplanes, g.V, g.Vs);
 }
 
 // Links: canonical [V][4][3][3] -> [4][9][V], with the boundary sign folded in.
 template <typename T2>
 __global__ void k_pack_links(const double2* __restrict__ canon, T2* __restrict__ links, Geometry g,
                              int bc0, int bc1, int bc2, int bc3) {
-  const long n = 4L * 9 * g.V;
+  const long n = 4L * 9 * g.Vs;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const int s = (int)(e % g.V);
-    const int ne = (int)(e / g.V);
+    const int s = (int)(e % g.Vs);
+    const int ne = (int)(e / g.Vs);
     const int nu = ne / 9, ent = ne % 9;
+    if (s >= g.V) {
+      st64(links + e, Cx<double>{0.0, 0.0});
+      continue;
+    }
     int coord;
     int ext;
     int bc;
@@ -89,7 +112,7 @@ __global__ void k_pack_links(const double2* __restrict__ canon, T2* __restrict__
 
 void launch_pack_links(const double2* canon, void* links, bool f32, const Geometry& g,
                        const int bc[4], hipStream_t s) {
-  long n = 4L * 9 * g.V;
+  long n = 4L * 9 * g.Vs;
   if (f32)
     hipLaunchKernelGGL(k_pack_links<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon,
                        (float2*)links, g, bc[0], bc[1], bc[2], bc[3]);
@@ -193,6 +216,18 @@ __device__ __forceinline__ void load_link(const T2* __restrict__ links, int V, i
   for (int e = 0; e < 9; ++e) u[e] = ld(links + (long)(nu * 9 + e) * V + site);
 }
 
+// Store that marks the line as streaming (not kept for reuse in L2).
+__device__ __forceinline__ void st_nt(float2* p, Cx<float> a) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  v2 v = {a.re, a.im};
+  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
+__device__ __forceinline__ void st_nt(double2* p, Cx<double> a) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  v2 v = {a.re, a.im};
+  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
+
 struct Nbr {
   int b[4], f[4];
 };
@@ -266,7 +301,7 @@ template <typename R, int B>
 __global__ void __launch_bounds__(256)
 k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T* __restrict__ in,
          typename Vec2<R>::T* __restrict__ out, Geometry g, HopR<R> hop_c, int nrhs, int g5in,
-         int g5out, TileMap tm) {
+         int g5out, int nt, TileMap tm) {
   using T2 = typename Vec2<R>::T;
   int site0, rb, tile;
   if (!map_tile(blockIdx.x, tm, site0, rb, tile)) return;
@@ -274,30 +309,68 @@ k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::
   if (s >= g.V) return;
   const int r0 = rb * B;
   const int nsrc = min(B, nrhs - r0);
-  const T2* inb = in + (long)r0 * 12 * g.V;
-  T2* outb = out + (long)r0 * 12 * g.V;
+  const int Vs = g.Vs;
+  const T2* inb = in + (long)r0 * 12 * Vs;
+  T2* outb = out + (long)r0 * 12 * Vs;
   const Nbr nb = neighbours(s, g);
   Cx<R> acc[B][12];
 #pragma unroll
   for (int r = 0; r < B; ++r)
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
-  dir_hops<R, T2, 0, B>(acc, links, inb, g.V, s, nb, nsrc, g5in, hop_c.fwd[0], hop_c.bwd[0]);
-  dir_hops<R, T2, 1, B>(acc, links, inb, g.V, s, nb, nsrc, g5in, hop_c.fwd[1], hop_c.bwd[1]);
-  dir_hops<R, T2, 2, B>(acc, links, inb, g.V, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
-  dir_hops<R, T2, 3, B>(acc, links, inb, g.V, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+  dir_hops<R, T2, 0, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[0], hop_c.bwd[0]);
+  dir_hops<R, T2, 1, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[1], hop_c.bwd[1]);
+  dir_hops<R, T2, 2, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
+  dir_hops<R, T2, 3, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     if (r < nsrc) {
       Cx<R> psi[12];
-      load_spinor(inb + (long)r * 12 * g.V, g.V, s, g5in, psi);
+      load_spinor(inb + (long)r * 12 * Vs, Vs, s, g5in, psi);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         Cx<R> o = psi[c] - acc[r][c];
         if (g5out && c >= 6) o = -o;
-        st(outb + (long)r * 12 * g.V + (long)c * g.V + s, o);
+        if (nt) st_nt(outb + (long)r * 12 * Vs + (long)c * Vs + s, o);
+        else st(outb + (long)r * 12 * Vs + (long)c * Vs + s, o);
       }
     }
+  }
+}
+
+// Variant with G lanes per site: lane j of a site group takes source rb*G + j,
+// so one wave load of a link serves G sources without holding G
+// accumulators per thread.  Workgroup tiles hold blockDim/G sites.
+template <typename R, int G>
+__global__ void __launch_bounds__(256)
+k_wilson_g(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T* __restrict__ in,
+           typename Vec2<R>::T* __restrict__ out, Geometry g, HopR<R> hop_c, int nrhs, int g5in,
+           int g5out, int nt, TileMap tm) {
+  using T2 = typename Vec2<R>::T;
+  int site0, rb, tile;
+  if (!map_tile(blockIdx.x, tm, site0, rb, tile)) return;
+  const int s = site0 + (int)threadIdx.x / G;
+  const int r = rb * G + (int)threadIdx.x % G;
+  if (s >= g.V || r >= nrhs) return;
+  const int Vs = g.Vs;
+  const T2* inr = in + (long)r * 12 * Vs;
+  T2* outr = out + (long)r * 12 * Vs;
+  const Nbr nb = neighbours(s, g);
+  Cx<R> acc[1][12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[0][c] = {R(0), R(0)};
+  dir_hops<R, T2, 0, 1>(acc, links, inr, Vs, s, nb, 1, g5in, hop_c.fwd[0], hop_c.bwd[0]);
+  dir_hops<R, T2, 1, 1>(acc, links, inr, Vs, s, nb, 1, g5in, hop_c.fwd[1], hop_c.bwd[1]);
+  dir_hops<R, T2, 2, 1>(acc, links, inr, Vs, s, nb, 1, g5in, hop_c.fwd[2], hop_c.bwd[2]);
+  dir_hops<R, T2, 3, 1>(acc, links, inr, Vs, s, nb, 1, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+  Cx<R> psi[12];
+  load_spinor(inr, Vs, s, g5in, psi);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    Cx<R> o = psi[c] - acc[0][c];
+    if (g5out && c >= 6) o = -o;
+    if (nt) st_nt(outr + (long)c * Vs + s, o);
+    else st(outr + (long)c * Vs + s, o);
   }
 }
 
@@ -306,8 +379,13 @@ k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::
 static int g_lds_limit_kb = 64;
 void set_lds_limit(int kb) { g_lds_limit_kb = kb; }
 static void apply_lds_limit(const void* fn) {
-  if (g_lds_limit_kb > 64)
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, g_lds_limit_kb * 1024);
+  if (g_lds_limit_kb > 64) {
+    // a rejected request only means larger LDS caps fail at launch (and are
+    // skipped by the autotuner); it must not leave a sticky error behind
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (g_lds_limit_kb - 1) * 1024) != hipSuccess)
+      (void)hipGetLastError();
+  }
 }
 
 TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order) {
@@ -329,34 +407,67 @@ TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order) {
 template <typename R, int B>
 static void launch_w(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
                      const Hop& hop_c, bool g5in, bool g5out, int wg, int lds_kb, int order,
-                     hipStream_t s) {
+                     int nt, hipStream_t s) {
   using T2 = typename Vec2<R>::T;
   const TileMap tm = make_tile_map(g, wg, (nrhs + B - 1) / B, order);
   static bool lds_set = false;
   if (!lds_set) { apply_lds_limit((const void*)k_wilson<R, B>); lds_set = true; }
   hipLaunchKernelGGL((k_wilson<R, B>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s, (const T2*)links,
                      (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs, (int)g5in, (int)g5out,
-                     tm);
+                     nt, tm);
+}
+
+template <typename R, int G>
+static void launch_wg(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
+                      const Hop& hop_c, bool g5in, bool g5out, int wg, int lds_kb, int order, int nt,
+                      hipStream_t s) {
+  using T2 = typename Vec2<R>::T;
+  const TileMap tm = make_tile_map(g, wg / G, (nrhs + G - 1) / G, order);
+  static bool lds_set = false;
+  if (!lds_set) { apply_lds_limit((const void*)k_wilson_g<R, G>); lds_set = true; }
+  hipLaunchKernelGGL((k_wilson_g<R, G>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s,
+                     (const T2*)links, (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs,
+                     (int)g5in, (int)g5out, nt, tm);
 }
 
 hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out, int nrhs,
                          const Geometry& g, const Hop& hop_c, bool g5in, bool g5out,
                          const Tuning& tn, hipStream_t s) {
   const int wg = tn.wg;
+  if (tn.g > 1) {
+#define OVS_WG(RT, GG) launch_wg<RT, GG>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s)
+    if (f32) {
+      switch (tn.g) {
+        case 2: OVS_WG(float, 2); break;
+        case 4: OVS_WG(float, 4); break;
+        case 8: OVS_WG(float, 8); break;
+        default: return hipErrorInvalidValue;
+      }
+    } else {
+      switch (tn.g) {
+        case 2: OVS_WG(double, 2); break;
+        case 4: OVS_WG(double, 4); break;
+        case 8: OVS_WG(double, 8); break;
+        default: return hipErrorInvalidValue;
+      }
+    }
+#undef OVS_WG
+    return hipGetLastError();
+  }
   if (f32) {
     switch (tn.rhs_block) {
-      case 1: launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
-      case 2: launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
-      case 3: launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
-      case 4: launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
-      case 6: launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
+      case 1: launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 2: launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 3: launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 4: launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 6: launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (tn.rhs_block) {
-      case 1: launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
-      case 2: launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
-      case 3: launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, s); break;
+      case 1: launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 2: launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 3: launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -388,7 +499,7 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
   const int nsrc = min(B, na - j0);
   const int s = site0 + threadIdx.x;
   const bool live = s < g.V;
-  const int V = g.V;
+  const int V = g.Vs;  // stride of the padded component planes
   int slot[B];
 #pragma unroll
   for (int r = 0; r < B; ++r) slot[r] = (r < nsrc) ? rhs_map[j0 + r] : 0;

@@ -41,3 +41,21 @@ def test_binding_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(ovs, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         ovs.load()
+
+
+def test_small_eig_host():
+    """The library's host eigensolver (Rayleigh-Ritz step) against numpy (no GPU)."""
+    import numpy as np
+
+    import paper_0810_4228_amd as ovs
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 9, 48):
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        lam, V = ovs.small_eig(A)
+        assert np.abs(A @ V - V * lam).max() <= 1e-12 * np.abs(A).max()
+        assert np.allclose(np.linalg.norm(V, axis=0), 1.0)
+        assert np.abs(np.sort_complex(lam) - np.sort_complex(np.linalg.eigvals(A))).max() < 1e-11
+    # defective-ish upper triangular with clustered diagonal
+    T = np.triu(rng.standard_normal((20, 20)), 1) + np.diag(np.repeat([0.5, -0.5], 10) + 1e-3 * np.arange(20))
+    lam, V = ovs.small_eig(T.astype(complex))
+    assert np.abs(np.sort(lam.real) - np.sort(np.diag(T))).max() < 1e-9
