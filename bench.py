@@ -36,6 +36,27 @@ TOL = 1e-5
 KMAX = 1000
 
 
+# HBM bytes per launch of the tuned FP32 stencil on this workload, from the
+# FETCH_SIZE / WRITE_SIZE counters scaled by a device copy of known size
+# (profiles/k_wilson_16x16x16x32_f32x12_hbm_counters.txt).  Reported only while
+# the kernel source is the one that was measured.
+STENCIL_TRAFFIC = {"source_sha256_prefix": "8475e3a639d1d3fa",
+                   "bytes_per_launch": 2.0 * 202726.59 * 1024 + 1.0 * 147456.0 * 1024}
+
+
+def stencil_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_0810_4228_amd", "csrc", "stencil.hip")
+    try:
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if digest.startswith(STENCIL_TRAFFIC["source_sha256_prefix"]):
+        return STENCIL_TRAFFIC["bytes_per_launch"]
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -100,12 +121,30 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="time the stencil kernel only (for counter collection)")
+    ap.add_argument("--tuning", default=None,
+                    help="JSON file with a saved kernel configuration: loaded if present, "
+                         "written after autotuning otherwise")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device 5 times: the known-size reference "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        n = 256 * 1024 * 1024 // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": 4 * n, "dispatches": 5}))
+        return
 
     import paper_0810_4228_amd as ovs
     import synth
@@ -120,8 +159,20 @@ def main():
     lat.set_params(MW, MU)
     bt = torch.from_numpy(b).to(dev)
     del U
-    log("bench: autotune")
-    lat.autotune(NRHS)
+    key = f"{DIMS}-{NRHS}-f32"
+    saved = None
+    if args.tuning and os.path.exists(args.tuning):
+        with open(args.tuning) as fh:
+            saved = json.load(fh).get(key)
+    if saved:
+        log("bench: tuning from", args.tuning)
+        lat.set_tuning_raw(NRHS, saved)
+    else:
+        log("bench: autotune")
+        lat.autotune(NRHS)
+        if args.tuning:
+            with open(args.tuning, "w") as fh:
+                json.dump({key: lat.get_tuning_raw(NRHS)}, fh)
     rb, wg = lat.get_tuning(NRHS)
     tuning = lat.get_tuning_ex(NRHS)
     log("bench: tuning", tuning)
@@ -137,6 +188,10 @@ def main():
     log(f"bench: stencil {ms_st * 1e3:.1f} us/apply, {st_gbs:.0f} GB/s (block {rb}, wg {wg})")
     fi.close()
     fo.close()
+
+    if args.stencil_only:
+        print(json.dumps({"stencil_us": ms_st * 1e3, "stencil_gbps": st_gbs, "tuning": tuning}))
+        return
 
     # ---- sign solves ----
     tol = [TOL] * NRHS
@@ -189,7 +244,7 @@ def main():
                     "frac_peak": st_gbs / HBM_PEAK_GBS, "rhs_block": rb, "wg": wg,
                     "bytes_per_apply": st_bytes},
         "roofline": {"bound": "hbm", "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": st_gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": st_gbs / HBM_PEAK_GBS, "traffic": stencil_traffic()},
     }
     if not args.no_check:
         log("bench: free-field accuracy check")

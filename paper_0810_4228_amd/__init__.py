@@ -39,7 +39,7 @@ OVS_FLAG_OVERLAP = 8
 EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
     "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
-    "ovs_field_apply", "ovs_field_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex",
+    "ovs_field_apply", "ovs_field_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
     "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
 ]
@@ -107,6 +107,7 @@ def load():
         "ovs_autotune": [P, I],
         "ovs_get_tuning": [P, I, IP, IP],
         "ovs_get_tuning_ex": [P, I, IP],
+        "ovs_set_tuning_ex": [P, I, IP],
         "ovs_deflation_set": [P, I, DP, P, P, ctypes.POINTER(P)],
         "ovs_deflation_destroy": [P],
         "ovs_deflation_compute": [P, I, D, I, ctypes.POINTER(P)],
@@ -228,6 +229,15 @@ class Lattice:
         _check(self._lib.ovs_get_tuning(self._h, int(nrhs), ctypes.byref(b), ctypes.byref(w)), "ovs_get_tuning")
         return b.value, w.value
 
+    def get_tuning_raw(self, nrhs):
+        out = (ctypes.c_int32 * 8)()
+        _check(self._lib.ovs_get_tuning_ex(self._h, int(nrhs), out), "ovs_get_tuning_ex")
+        return list(out)
+
+    def set_tuning_raw(self, nrhs, cfg):
+        arr = (ctypes.c_int32 * 8)(*[int(v) for v in cfg])
+        _check(self._lib.ovs_set_tuning_ex(self._h, int(nrhs), arr), "ovs_set_tuning_ex")
+
     def get_tuning_ex(self, nrhs):
         out = (ctypes.c_int32 * 8)()
         _check(self._lib.ovs_get_tuning_ex(self._h, int(nrhs), out), "ovs_get_tuning_ex")
@@ -235,7 +245,10 @@ class Lattice:
         st = dict(zip(keys, out[0:4]))
         shape = st["rhs_block"]
         st.update(rhs_block=shape // 100, lanes_per_site=(shape // 10) % 10, streaming_store=shape % 10)
-        return {"stencil": st, "dual": dict(zip(keys, out[4:8]))}
+        du = dict(zip(keys, out[4:8]))
+        shape = du["rhs_block"]
+        du.update(rhs_block=shape // 100, streaming_store=shape % 10)
+        return {"stencil": st, "dual": du}
 
     def deflation_set(self, lam, R, L):
         """lam: complex [m] (host); R, L: complex128 CUDA [m, 12V]."""

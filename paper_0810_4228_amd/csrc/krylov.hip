@@ -224,8 +224,8 @@ __global__ void __launch_bounds__(256) k_update(const T2* __restrict__ T, const 
       vt = cfma(c3, ld64(Vm + e), vt);
       wt = cfma(d3, ld64(Wm + e), wt);
     }
-    st64(Vn + e, vt);
-    st64(Wn + e, wt);
+    st64_nt(Vn + e, vt);
+    st64_nt(Wn + e, wt);
     const Cx<double> vr = round_to(Vn, vt), wr = round_to(Wn, wt);
     const Cx<double> dl = cmulc(wr, vr);
     v[0] += dl.re;

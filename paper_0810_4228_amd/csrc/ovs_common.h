@@ -144,6 +144,7 @@ struct DualArgs {
   int nrhs_slots;
   int lds_kb;          // occupancy cap, as in Tuning
   int order;
+  int nt;              // streaming stores of T and S
 };
 hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
                        const Hop& hAd, int rhs_block, hipStream_t s);

@@ -81,6 +81,17 @@ __device__ __forceinline__ void st64(double2* p, Cx<double> a) { *p = make_doubl
 __device__ __forceinline__ void st64(float2* p, Cx<double> a) {
   *p = make_float2((float)a.re, (float)a.im);
 }
+// streaming (non-temporal) stores of an FP64 value in storage precision
+__device__ __forceinline__ void st64_nt(double2* p, Cx<double> a) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  v2 v = {a.re, a.im};
+  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
+__device__ __forceinline__ void st64_nt(float2* p, Cx<double> a) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  v2 v = {(float)a.re, (float)a.im};
+  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
 // the stored value as seen after rounding to storage precision
 __device__ __forceinline__ Cx<double> round_to(const double2*, Cx<double> a) { return a; }
 __device__ __forceinline__ Cx<double> round_to(const float2*, Cx<double> a) {

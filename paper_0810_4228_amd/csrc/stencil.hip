@@ -485,7 +485,7 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
        const int* __restrict__ it, typename Vec2<R>::T* __restrict__ out_t,
        typename Vec2<R>::T* __restrict__ out_s, double* __restrict__ partials, Geometry g,
        HopR<R> hA, HopR<R> hAd, const int* __restrict__ rhs_map, const int* __restrict__ n_active,
-       TileMap tm) {
+       int nt, TileMap tm) {
   using T2 = typename Vec2<R>::T;
   __shared__ double lds[(256 / 64) * 3 * B];
   int site0, rb, tile;
@@ -552,8 +552,13 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
           Cx<R> t = pv[c] - accv[r][c];
           Cx<R> sv = pw[c] - accw[r][c];
           if (c >= 6) { t = -t; sv = -sv; }
-          st(out_t + base + (long)c * V + s, t);
-          st(out_s + base + (long)c * V + s, sv);
+          if (nt) {
+            st_nt(out_t + base + (long)c * V + s, t);
+            st_nt(out_s + base + (long)c * V + s, sv);
+          } else {
+            st(out_t + base + (long)c * V + s, t);
+            st(out_s + base + (long)c * V + s, sv);
+          }
           const Cx<double> t64 = {(double)t.re, (double)t.im};
           const Cx<double> w64 = {(double)pw[c].re, (double)pw[c].im};
           const Cx<double> p = cmulc(w64, t64);
@@ -588,7 +593,7 @@ static void launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, const 
                      (const T2*)a.links,
                      (const T2*)a.basis, (const T2*)a.wbuf, a.basis_stride, (int)a.ring, a.it,
                      (T2*)a.out_t, (T2*)a.out_s, a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd),
-                     a.rhs_map, a.n_active, tm);
+                     a.rhs_map, a.n_active, a.nt, tm);
 }
 
 hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
