@@ -178,6 +178,33 @@ ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, c
                           void* y, int32_t nrhs, int32_t k_max, const double* tol,
                           ovs_method method, int32_t flags, ovs_rhs_info* info);
 
+/* Gradient of L = sum_r Re <chi_r, y_r>, where y_r = |b_r| V_k sgn(G_k) e_1 is
+ * the two-sided Lanczos approximation of sgn(gamma5 Dw(mu)) b_r (Section 4,
+ * eq. 2sLapp) at exactly k iterations without deflation, with respect to the
+ * sources, mu and the links: the exact derivative of that algorithm (reverse
+ * sweep of its recurrences; the inner sign and its Jacobian by the tau = e^u
+ * trapezoid rule).  Complex gradients follow dL = Re <zbar, dz> with
+ * zbar = dL/dRe z + i dL/dIm z; link matrices are differentiated entry by
+ * entry (no projection on su(3)).
+ *   b, chi   : device complex128 [nrhs][V][4][3] (canonical layout).
+ *   k        : Krylov size, 1 <= k <= 65535; every source must complete k
+ *              iterations.
+ *   y        : device complex128 [nrhs][V][4][3], or NULL: the forward result.
+ *   grad_b   : device complex128 [nrhs][V][4][3].
+ *   grad_mu  : host double [1], summed over sources.
+ *   grad_U   : device complex128 [V][4][3][3] (link layout), summed over sources.
+ *   quad_err : host double [nrhs], or NULL: relative change of the quadrature
+ *              (x and the Jacobian band) between its last two step sizes.
+ * Needs an OVS_F64 lattice (OVS_ERR_ARG otherwise) and about (2k + 16) nrhs
+ * FP64 fields of workspace, kept in the handle's cache (OVS_ERR_ALLOC if it
+ * does not fit).  Returns OVS_WARN_BREAKDOWN, writing no output, when a
+ * source breaks down before k iterations; OVS_WARN_SIGN_AMBIGUOUS, with all
+ * outputs written, when the quadrature changed by more than 1e-6 between its
+ * two finest steps. */
+ovs_status ovs_sign_apply_vjp(ovs_lattice lat, const void* b, const void* chi, int32_t nrhs,
+                              int32_t k, void* y, void* grad_b, double* grad_mu, void* grad_U,
+                              double* quad_err);
+
 /* Krylov coefficients of the last ovs_sign_apply on this handle (2sL only):
  * alpha, gamma host complex128 [nrhs][k_max], beta host double [nrhs][k_max],
  * x host complex128 [nrhs][k_max] (sgn(G_k) e_1, zero beyond k_used).  Any

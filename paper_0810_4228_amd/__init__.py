@@ -40,7 +40,7 @@ EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
     "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
     "ovs_field_apply", "ovs_field_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
-    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_last_coefficients",
+    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
 ]
 
@@ -113,6 +113,7 @@ def load():
         "ovs_deflation_compute": [P, I, D, I, ctypes.POINTER(P)],
         "ovs_deflation_get": [P, DP, P, P, DP],
         "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
+        "ovs_sign_apply_vjp": [P, P, P, I, I, P, P, DP, P, DP],
         "ovs_last_coefficients": [P, DP, DP, DP, DP],
         "ovs_inner_sign_tridiag": [P, I, I, DP, DP, DP, DP, DP],
         "ovs_inner_sign_hessenberg": [P, I, I, DP, DP, DP],
@@ -294,6 +295,30 @@ class Lattice:
         _check(st, "ovs_sign_apply")
         return y, [i.as_dict() for i in infos], st
 
+    def sign_apply_vjp(self, b, chi, k, want_y=True):
+        """Gradient of L = sum_r Re <chi_r, y_r> for the k-step two-sided Lanczos
+        y_r ~ sgn(A) b_r without deflation (FP64 lattices).  Returns
+        (y or None, grad_b, grad_mu, grad_U [V,4,3,3], quad_err [nrhs], status)."""
+        torch = _torch()
+        b, nrhs = self._fields(b)
+        chi, n2 = self._fields(chi)
+        if n2 != nrhs:
+            raise ValueError("chi must hold as many fields as b")
+        y = torch.empty_like(b) if want_y else None
+        gb = torch.empty_like(b)
+        gU = torch.empty((self.V, 4, 3, 3), dtype=torch.complex128, device=b.device)
+        gmu = ctypes.c_double(0.0)
+        qerr = np.zeros(nrhs, dtype=np.float64)
+        st = self._lib.ovs_sign_apply_vjp(
+            self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(chi.data_ptr()), nrhs, int(k),
+            ctypes.c_void_p(y.data_ptr()) if y is not None else None,
+            ctypes.c_void_p(gb.data_ptr()), ctypes.byref(gmu), ctypes.c_void_p(gU.data_ptr()),
+            _dptr(qerr))
+        _check(st, "ovs_sign_apply_vjp")
+        if st == OVS_WARN_BREAKDOWN:
+            raise OvsError(st, "ovs_sign_apply_vjp")
+        return y, gb, gmu.value, gU, qerr, st
+
     def last_coefficients(self, nrhs, k_max):
         a = np.zeros((nrhs, k_max), dtype=np.complex128)
         bb = np.zeros((nrhs, k_max), dtype=np.float64)
@@ -417,3 +442,50 @@ class Deflation:
             self.close()
         except Exception:
             pass
+
+
+_sign_fn = None
+
+
+def _sign_function():
+    global _sign_fn
+    if _sign_fn is not None:
+        return _sign_fn
+    torch = _torch()
+
+    class SignFunction(torch.autograd.Function):
+        """y = k-step two-sided Lanczos sgn(gamma5 Dw(mu; U)) b, differentiable in
+        (b, mu, U); the backward pass is ovs_sign_apply_vjp."""
+
+        @staticmethod
+        def forward(ctx, b, mu, U, lat, m_w, k):
+            lat.set_links(U)
+            lat.set_params(m_w, float(mu))
+            y, _, st = lat.sign_apply(b, k)
+            if st == OVS_WARN_BREAKDOWN:
+                raise OvsError(st, "ovs_sign_apply")
+            ctx.save_for_backward(b, mu, U)
+            ctx.lat, ctx.m_w, ctx.k = lat, m_w, k
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            b, mu, U = ctx.saved_tensors
+            lat = ctx.lat
+            lat.set_links(U)
+            lat.set_params(ctx.m_w, float(mu))
+            _, gb, gmu, gU, _, _ = lat.sign_apply_vjp(b, gy.contiguous(), ctx.k, want_y=False)
+            gmu_t = torch.tensor(gmu, dtype=mu.dtype, device=mu.device)
+            return gb.view_as(b), gmu_t, gU.view_as(U), None, None, None
+
+    _sign_fn = SignFunction
+    return _sign_fn
+
+
+def sign_autograd(lat, b, mu, U, m_w, k):
+    """Differentiable y = sgn(A) b by k-step two-sided Lanczos without deflation.
+
+    lat: an FP64 Lattice of the right size; its links and parameters are set
+    from U (complex128 [V,4,3,3], CUDA) and mu (real 0-dim tensor) on every
+    call.  b: complex128 CUDA [nrhs, 12V] or [12V]."""
+    return _sign_function().apply(b, mu, U, lat, float(m_w), int(k))

@@ -15,6 +15,7 @@
 #include "ovs_common.h"
 #include "dense.h"
 #include "ovs_eig.h"
+#include "ovs_host.h"
 #include "ovs_krylov.h"
 
 using namespace ovs;
@@ -26,22 +27,7 @@ void record_error(const char* what, int line, hipError_t e) {
 }
 }  // namespace ovs
 
-namespace {
-
-// Orders the library stream after the caller's stream on entry, and the
-// caller's stream after the library stream on exit.
-struct StreamScope {
-  ovs_lattice_s* l;
-  explicit StreamScope(ovs_lattice_s* lat) : l(lat) {
-    (void)hipGetLastError();  // drop a stale error left by an earlier library call (e.g. rocBLAS)
-    (void)hipEventRecord(l->ev_in, l->user_stream);
-    (void)hipStreamWaitEvent(l->stream, l->ev_in, 0);
-  }
-  ~StreamScope() {
-    (void)hipEventRecord(l->ev_out, l->stream);
-    (void)hipStreamWaitEvent(l->user_stream, l->ev_out, 0);
-  }
-};
+namespace ovs {
 
 // kappa * eta^{+-}_nu (Section 1): e^{+-mu} on the time hops only.
 Hop make_hop(double m_w, double mu) {
@@ -105,19 +91,6 @@ std::vector<int> lds_candidates(const ovs_lattice_s* l) {
     if (kb <= l->lds_max_kb - 1) c.push_back(kb);
   return c;
 }
-
-// Bump allocator over the cached workspace (or a sizing pass with base == nullptr).
-struct Arena {
-  char* base;
-  size_t off = 0;
-  template <class T>
-  T* take(size_t n) {
-    off = (off + 255) & ~size_t(255);
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += n * sizeof(T);
-    return p;
-  }
-};
 
 ovs_status ensure_ws(ovs_lattice_s* l, size_t bytes) {
   if (l->ws && l->ws_bytes >= bytes) return OVS_OK;
@@ -225,7 +198,7 @@ ovs_status inner_sign(ovs_lattice_s* l, bool tri, const double2* alpha, const do
   return OVS_OK;
 }
 
-}  // namespace
+}  // namespace ovs
 
 // ============================================================================
 extern "C" {

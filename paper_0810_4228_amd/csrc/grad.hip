@@ -1,0 +1,653 @@
+// Kernels of the gradient of L = Re <chi, y_k> with respect to b, mu and the
+// links, for the two-sided Lanczos approximation of Section 4 without
+// deflation, y_k = |b| V_k sgn(G_k) e_1 (eq. 2sLapp with m = 0).
+//
+// The driver (gradient.cpp) runs the Lanczos recurrences forward storing the
+// FP64 bases V, W, then walks them backwards.  Every vector step of the
+// reverse sweep is a short linear combination of stored fields with fused
+// dot products (k_lin); the scalar steps run one thread per source; the
+// stencil adjoints are ordinary A and A^dagger applications; the link and mu
+// derivatives are accumulated by k_gforce.  Reductions are fixed-order.
+#include <cmath>
+
+#include "ovs_common.h"
+#include "ovs_device.h"
+#include "ovs_grad.h"
+#include "ovs_spin.h"
+
+namespace ovs {
+
+// ---- linear combinations with fused dots -------------------------------------
+
+int lin_nchunk(long stride) {
+  long c = (stride + kWG - 1) / kWG;
+  if (c > 256) c = 256;
+  if (c < 1) c = 1;
+  return (int)c;
+}
+
+__global__ void __launch_bounds__(kWG) k_lin(LinArgs a, long stride, int nrhs) {
+  __shared__ double lds[(kWG / 64) * 2 * kLinDots];
+  const int r = blockIdx.y;
+  const long off = (long)r * stride;
+  Cx<double> c[kLinTerms];
+#pragma unroll
+  for (int j = 0; j < kLinTerms; ++j)
+    c[j] = (j < a.nterm) ? c64(a.coef[(long)j * nrhs + r]) : Cx<double>{0.0, 0.0};
+  double part[2 * kLinDots];
+#pragma unroll
+  for (int q = 0; q < 2 * kLinDots; ++q) part[q] = 0.0;
+  for (long e = (long)blockIdx.x * kWG + threadIdx.x; e < stride; e += (long)gridDim.x * kWG) {
+    Cx<double> v = {0.0, 0.0};
+    if (a.accumulate) v = c64(a.out[off + e]);
+#pragma unroll
+    for (int j = 0; j < kLinTerms; ++j)
+      if (j < a.nterm) v = cfma(c[j], c64(a.x[j][off + e]), v);
+    if (a.out) a.out[off + e] = d2(v);
+#pragma unroll
+    for (int q = 0; q < kLinDots; ++q) {
+      if (q < a.ndot) {
+        const Cx<double> y = a.y[q] ? c64(a.y[q][off + e]) : v;
+        const Cx<double> p = cmulc(y, v);
+        part[2 * q] += p.re;
+        part[2 * q + 1] += p.im;
+      }
+    }
+  }
+  if (a.ndot == 0) return;  // uniform over the workgroup
+  block_sum<2 * kLinDots>(part, lds);
+  if (threadIdx.x == 0) {
+    double* dst = a.partials + ((long)r * gridDim.x + blockIdx.x) * 2 * kLinDots;
+#pragma unroll
+    for (int q = 0; q < 2 * kLinDots; ++q) dst[q] = part[q];
+  }
+}
+
+void launch_lin(const LinArgs& a, long stride, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_lin, dim3(lin_nchunk(stride), nrhs), dim3(kWG), 0, s, a, stride, nrhs);
+}
+
+// Fixed-order sum of the partials of dot q for source r.
+__device__ Cx<double> dot_sum(const double* part, int r, int q, int nchunk) {
+  Cx<double> acc = {0.0, 0.0};
+  const double* p = part + (long)r * nchunk * 2 * kLinDots;
+  for (int c = 0; c < nchunk; ++c) {
+    acc.re += p[c * 2 * kLinDots + 2 * q];
+    acc.im += p[c * 2 * kLinDots + 2 * q + 1];
+  }
+  return acc;
+}
+
+__device__ __forceinline__ Cx<double> cconj(Cx<double> a) { return {a.re, -a.im}; }
+__device__ __forceinline__ void set_coef(const GradScalars& s, int t, int j, int r, Cx<double> v) {
+  s.coef[((long)t * kLinTerms + j) * s.nrhs + r] = d2(v);
+}
+
+// ---- forward scalar steps ------------------------------------------------------
+
+__global__ void k_gf_norm(GradScalars s, const double* part, int nchunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const double nb = sqrt(dot_sum(part, r, 0, nchunk).re);
+  s.nb[r] = nb;
+  s.status[r] = 0;
+  set_coef(s, kTabNorm, 0, r, {nb > 0.0 ? 1.0 / nb : 0.0, 0.0});
+}
+
+// alpha_i = w_i^dagger t_i (dot 0), |t_i|^2 (dot 1); coefficient rows of the update.
+__global__ void k_gf_alpha(GradScalars s, int i, const double* part, int nchunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const long rk = (long)r * s.kmax;
+  const Cx<double> al = dot_sum(part, r, 0, nchunk);
+  s.alpha[rk + i] = d2(al);
+  s.tnorm2[rk + i] = dot_sum(part, r, 1, nchunk).re;
+  const Cx<double> gprev = (i > 0) ? c64(s.gamma[rk + i - 1]) : Cx<double>{0.0, 0.0};
+  const double bprev = (i > 0) ? s.beta[rk + i - 1] : 0.0;
+  set_coef(s, kTabV, 0, r, {1.0, 0.0});
+  set_coef(s, kTabV, 1, r, -al);
+  set_coef(s, kTabV, 2, r, -gprev);
+  set_coef(s, kTabW, 0, r, {1.0, 0.0});
+  set_coef(s, kTabW, 1, r, -cconj(al));
+  set_coef(s, kTabW, 2, r, {-bprev, 0.0});
+}
+
+// beta_i = |v~|, delta_i = w~^dagger v~, gamma_i = delta_i / beta_i, with the
+// breakdown tests of the forward recurrences (lucky: |v~| <= 1e-14 |t|;
+// serious: |delta| <= 1e-13 |v~| |w~|).
+__global__ void k_gf_beta(GradScalars s, int i, const double* part_v, const double* part_w,
+                          int nchunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const long rk = (long)r * s.kmax;
+  const double vn = sqrt(dot_sum(part_v, r, 0, nchunk).re);
+  const Cx<double> delta = cconj(dot_sum(part_w, r, 0, nchunk));  // dot 0 = v~^dagger w~
+  const double wn = sqrt(dot_sum(part_w, r, 1, nchunk).re);
+  if (s.status[r] == 0) {
+    if (vn <= 1e-14 * sqrt(s.tnorm2[rk + i])) s.status[r] = 1;
+    else if (cabs1(delta) <= 1e-13 * vn * wn) s.status[r] = 2;
+  }
+  const Cx<double> g = vn > 0.0 ? scale(1.0 / vn, delta) : Cx<double>{0.0, 0.0};
+  s.beta[rk + i] = vn;
+  s.gamma[rk + i] = d2(g);
+  set_coef(s, kTabSV, 0, r, {vn > 0.0 ? 1.0 / vn : 0.0, 0.0});
+  const bool gz = g.re == 0.0 && g.im == 0.0;
+  set_coef(s, kTabSW, 0, r, gz ? Cx<double>{0.0, 0.0} : cdiv({1.0, 0.0}, cconj(g)));
+}
+
+void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gf_norm, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, part, nchunk);
+}
+void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gf_alpha, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part, nchunk);
+}
+void launch_gf_beta(const GradScalars& s, int i, const double* part_v, const double* part_w,
+                    int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gf_beta, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part_v, part_w,
+                     nchunk);
+}
+
+// ---- reverse scalar steps ------------------------------------------------------
+// Adjoint rules used below (zbar = dL/dRe z + i dL/dIm z, dL = Re <zbar, dz>):
+//   z = c u         : ubar += conj(c) zbar,   cbar += u^dagger zbar
+//   z = u^dagger v  : vbar += zbar u,         ubar += conj(zbar) v
+//   z = u / conj(c) : ubar += zbar / c,       cbar += -(zbar^dagger z) / conj(c)
+//   r = |u| (real)  : ubar += rbar u / r
+
+// Last step (i = k-1): only t = A v_{k-1} and alpha_{k-1} = w_{k-1}^dagger t exist.
+__global__ void k_gr_first(GradScalars s) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const int i = s.kmax - 1;
+  const long rk = (long)r * s.kmax;
+  const Cx<double> ab = c64(s.abar[rk + i]);
+  set_coef(s, kTabSV, 0, r, ab);                                           // tbar = abar w_i
+  set_coef(s, kTabSW, 0, r, scale(s.nb[r], cconj(c64(s.x[rk + i]))));     // vbar = nb conj(x_i) chi
+  set_coef(s, kTabWB, 0, r, cconj(ab));                                    // wbar = conj(abar) t_i
+}
+
+// Step i < k-1, first half.  Inputs: dots of the completed vbar_{i+1}, wbar_{i+1}
+// with v_{i+1}, w_{i+1}.  Through v_{i+1} = v~/beta_i, w_{i+1} = w~/conj(gamma_i),
+// gamma_i = delta_i/beta_i, beta_i = |v~|, delta_i = w~^dagger v~:
+//   gbar_i += -(wbar_{i+1}^dagger w_{i+1}) / conj(gamma_i)
+//   bbar_i += -Re(vbar_{i+1}^dagger v_{i+1}) / beta_i - Re(conj(gbar_i) gamma_i) / beta_i
+//   dbar    = gbar_i / beta_i
+//   vbar~_i = vbar_{i+1}/beta_i + bbar_i v_{i+1} + dbar conj(gamma_i) w_{i+1}
+//   wbar~_i = wbar_{i+1}/gamma_i + conj(dbar) beta_i v_{i+1}
+__global__ void k_gr_s1(GradScalars s, int i, const double* part_v, const double* part_w,
+                        int nchunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const long rk = (long)r * s.kmax;
+  const Cx<double> d2v = cconj(dot_sum(part_v, r, 0, nchunk));  // vbar^dagger v
+  const Cx<double> d1w = cconj(dot_sum(part_w, r, 0, nchunk));  // wbar^dagger w
+  const double be = s.beta[rk + i];
+  const Cx<double> ga = c64(s.gamma[rk + i]);
+  Cx<double> gb = c64(s.gbar[rk + i]);
+  double bb = s.bbar[rk + i];
+  gb = gb - cdiv(d1w, cconj(ga));
+  bb -= d2v.re / be;
+  const Cx<double> db = scale(1.0 / be, gb);
+  bb -= (gb.re * ga.re + gb.im * ga.im) / be;  // Re(conj(gbar) gamma)
+  s.gbar[rk + i] = d2(gb);
+  s.bbar[rk + i] = bb;
+  set_coef(s, kTabV, 0, r, {1.0 / be, 0.0});
+  set_coef(s, kTabV, 1, r, {bb, 0.0});
+  set_coef(s, kTabV, 2, r, cmul(db, cconj(ga)));
+  set_coef(s, kTabW, 0, r, cdiv({1.0, 0.0}, ga));
+  set_coef(s, kTabW, 1, r, scale(be, cconj(db)));
+}
+
+// Step i < k-1, second half.  Inputs: v_i^dagger vbar~ (d5), v_{i-1}^dagger vbar~
+// (d6), w_i^dagger wbar~ (conj d4), w_{i-1}^dagger wbar~ (d3).  Through
+// v~ = t_i - alpha_i v_i - gamma_{i-1} v_{i-1}, w~ = s_i - conj(alpha_i) w_i -
+// beta_{i-1} w_{i-1} and alpha_i = w_i^dagger t_i:
+//   abar_i += -d4 - d5;  bbar_{i-1} += -Re d3;  gbar_{i-1} += -d6
+//   tbar_i = vbar~_i + abar_i w_i                (then vbar_i += A^dagger tbar_i)
+//   sbar_i = wbar~_i                              (then wbar_i += A sbar_i)
+//   vbar_i = nb conj(x_i) chi - conj(gamma_i) vbar~_{i+1} - conj(alpha_i) vbar~_i
+//   wbar_i = -beta_i wbar~_{i+1} - alpha_i wbar~_i + conj(abar_i) t_i,
+//            t_i = beta_i v_{i+1} + alpha_i v_i + gamma_{i-1} v_{i-1}
+__global__ void k_gr_s2(GradScalars s, int i, const double* part_v, const double* part_w,
+                        int nchunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const long rk = (long)r * s.kmax;
+  const Cx<double> d5 = dot_sum(part_v, r, 0, nchunk);
+  const Cx<double> d4 = cconj(dot_sum(part_w, r, 0, nchunk));
+  Cx<double> ab = c64(s.abar[rk + i]) - d4 - d5;
+  s.abar[rk + i] = d2(ab);
+  if (i > 0) {
+    const Cx<double> d6 = dot_sum(part_v, r, 1, nchunk);
+    const Cx<double> d3 = dot_sum(part_w, r, 1, nchunk);
+    s.bbar[rk + i - 1] -= d3.re;
+    s.gbar[rk + i - 1] = d2(c64(s.gbar[rk + i - 1]) - d6);
+  }
+  const Cx<double> al = c64(s.alpha[rk + i]);
+  const Cx<double> ga = c64(s.gamma[rk + i]);
+  const double be = s.beta[rk + i];
+  const Cx<double> gprev = (i > 0) ? c64(s.gamma[rk + i - 1]) : Cx<double>{0.0, 0.0};
+  set_coef(s, kTabSV, 0, r, {1.0, 0.0});
+  set_coef(s, kTabSV, 1, r, ab);
+  set_coef(s, kTabSW, 0, r, scale(s.nb[r], cconj(c64(s.x[rk + i]))));
+  set_coef(s, kTabSW, 1, r, -cconj(ga));
+  set_coef(s, kTabSW, 2, r, -cconj(al));
+  const Cx<double> cab = cconj(ab);
+  set_coef(s, kTabWB, 0, r, {-be, 0.0});
+  set_coef(s, kTabWB, 1, r, -al);
+  set_coef(s, kTabWB, 2, r, scale(be, cab));
+  set_coef(s, kTabWB, 3, r, cmul(cab, al));
+  set_coef(s, kTabWB, 4, r, cmul(cab, gprev));
+}
+
+// v_1 = w_1 = b/|b|: grad_b = ubar/|b| + nbar v_1 with ubar = vbar_1 + wbar_1 and
+// nbar = Re(chi^dagger y)/|b| - Re(ubar^dagger v_1)/|b|, chi^dagger y = sum_i x_i conj(xbar_i).
+__global__ void k_gr_final(GradScalars s, const double* part, int nchunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const long rk = (long)r * s.kmax;
+  const double nb = s.nb[r];
+  double cy = 0.0;
+  for (int i = 0; i < s.kmax; ++i) {
+    const Cx<double> p = cmulc(c64(s.xbar[rk + i]), c64(s.x[rk + i]));
+    cy += p.re;
+  }
+  const double uv = dot_sum(part, r, 0, nchunk).re;  // Re(v_1^dagger ubar)
+  const double nbar = (cy - uv) / nb;
+  set_coef(s, kTabFin, 0, r, {1.0 / nb, 0.0});
+  set_coef(s, kTabFin, 1, r, {nbar, 0.0});
+}
+
+void launch_gr_first(const GradScalars& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_gr_first, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s);
+}
+void launch_gr_s1(const GradScalars& s, int i, const double* part_v, const double* part_w,
+                  int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gr_s1, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part_v, part_w,
+                     nchunk);
+}
+void launch_gr_s2(const GradScalars& s, int i, const double* part_v, const double* part_w,
+                  int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gr_s2, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part_v, part_w,
+                     nchunk);
+}
+void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gr_final, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, part, nchunk);
+}
+
+// ---- basis dots and combination -------------------------------------------------
+
+constexpr int kBasisChunks = 32;
+
+__global__ void __launch_bounds__(kWG) k_basis_dots(const double2* basis, const double2* chi,
+                                                    long stride, int nrhs, double* partials) {
+  __shared__ double lds[(kWG / 64) * 2];
+  const int i = blockIdx.y, r = blockIdx.z;
+  const double2* v = basis + ((long)i * nrhs + r) * stride;
+  const double2* c = chi + (long)r * stride;
+  double part[2] = {0.0, 0.0};
+  for (long e = (long)blockIdx.x * kWG + threadIdx.x; e < stride; e += (long)gridDim.x * kWG) {
+    const Cx<double> p = cmulc(c64(v[e]), c64(c[e]));
+    part[0] += p.re;
+    part[1] += p.im;
+  }
+  block_sum<2>(part, lds);
+  if (threadIdx.x == 0) {
+    double* dst = partials + (((long)r * gridDim.y + i) * gridDim.x + blockIdx.x) * 2;
+    dst[0] = part[0];
+    dst[1] = part[1];
+  }
+}
+
+__global__ void k_basis_dots_final(GradScalars s, const double* partials) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)s.nrhs * s.kmax) return;
+  const double* p = partials + t * kBasisChunks * 2;
+  Cx<double> acc = {0.0, 0.0};
+#pragma unroll 1
+  for (int c = 0; c < kBasisChunks; ++c) {
+    acc.re += p[2 * c];
+    acc.im += p[2 * c + 1];
+  }
+  const int r = (int)(t / s.kmax);
+  s.xbar[t] = d2(scale(s.nb[r], acc));
+}
+
+void launch_basis_dots(const double2* basis, const double2* chi, long stride, int kmax, int nrhs,
+                       double* partials, const GradScalars& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_basis_dots, dim3(kBasisChunks, kmax, nrhs), dim3(kWG), 0, st, basis, chi,
+                     stride, nrhs, partials);
+  const long n = (long)nrhs * kmax;
+  hipLaunchKernelGGL(k_basis_dots_final, dim3((int)((n + 255) / 256)), dim3(256), 0, st, s,
+                     partials);
+}
+
+__global__ void k_gcombine(const double2* basis, long stride, int kmax, int nrhs, GradScalars s,
+                           double2* y) {
+  const int r = blockIdx.y;
+  const long rk = (long)r * kmax;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < stride;
+       e += (long)gridDim.x * blockDim.x) {
+    Cx<double> acc = {0.0, 0.0};
+    for (int i = 0; i < kmax; ++i)
+      acc = cfma(c64(s.x[rk + i]), c64(basis[((long)i * nrhs + r) * stride + e]), acc);
+    y[(long)r * stride + e] = d2(scale(s.nb[r], acc));
+  }
+}
+
+void launch_gcombine(const double2* basis, long stride, int kmax, int nrhs, const GradScalars& s,
+                     double2* y, hipStream_t st) {
+  long b = (stride + kWG - 1) / kWG;
+  if (b > 2048) b = 2048;
+  hipLaunchKernelGGL(k_gcombine, dim3((int)b, nrhs), dim3(kWG), 0, st, basis, stride, kmax, nrhs,
+                     s, y);
+}
+
+// ---- inner sign and its vector-Jacobian product -----------------------------------
+// One thread per (node, sign): LU with row interchanges of the tridiagonal
+// M = G + i sigma (sigma = +-tau), then q = M^{-1} e_1 and p = M^{-H} xbar.
+// Per-thread arrays live in scratch as [entry][thread] (coalesced).
+
+struct VjpScratch {
+  double2 *dl, *d, *du, *du2, *q, *p;
+  unsigned char* piv;
+};
+
+static VjpScratch carve(void* base, int k, int nthr) {
+  VjpScratch v;
+  double2* b = (double2*)base;
+  const long n = (long)k * nthr;
+  v.dl = b;
+  v.d = b + n;
+  v.du = b + 2 * n;
+  v.du2 = b + 3 * n;
+  v.q = b + 4 * n;
+  v.p = b + 5 * n;
+  v.piv = (unsigned char*)(b + 6 * n);
+  return v;
+}
+
+size_t isign_vjp_scratch_bytes(int k, int nnode) {
+  const long n = (long)k * 2 * nnode;
+  return (size_t)n * (6 * sizeof(double2) + 1) + 256;
+}
+
+__global__ void k_isign_vjp(const double2* alpha, const double* beta, const double2* gamma,
+                            const double2* xbar, int k, double h, int n0, int nnode,
+                            VjpScratch sc) {
+  const int nthr = 2 * nnode;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nthr) return;
+  const double tau = exp((double)(n0 + (t >> 1)) * h);
+  const double sigma = (t & 1) ? -tau : tau;
+#define AT(arr, i) arr[(long)(i) * nthr + t]
+  for (int i = 0; i < k; ++i) {
+    const Cx<double> a = c64(alpha[i]);
+    AT(sc.d, i) = make_double2(a.re, a.im + sigma);
+    if (i < k - 1) {
+      AT(sc.dl, i) = make_double2(beta[i], 0.0);
+      AT(sc.du, i) = gamma[i];
+    }
+  }
+  // factor
+  for (int i = 0; i < k - 1; ++i) {
+    const Cx<double> di = c64(AT(sc.d, i)), li = c64(AT(sc.dl, i));
+    if (cabs1(di) >= cabs1(li)) {
+      const Cx<double> f = cdiv(li, di);
+      AT(sc.dl, i) = d2(f);
+      AT(sc.d, i + 1) = d2(c64(AT(sc.d, i + 1)) - cmul(f, c64(AT(sc.du, i))));
+      if (i < k - 2) AT(sc.du2, i) = make_double2(0.0, 0.0);
+      AT(sc.piv, i) = 0;
+    } else {
+      const Cx<double> f = cdiv(di, li);
+      const Cx<double> dn = c64(AT(sc.d, i + 1));
+      const Cx<double> ui = c64(AT(sc.du, i));
+      AT(sc.d, i) = d2(li);
+      AT(sc.dl, i) = d2(f);
+      AT(sc.du, i) = d2(dn);
+      AT(sc.d, i + 1) = d2(ui - cmul(f, dn));
+      if (i < k - 2) {
+        const Cx<double> un = c64(AT(sc.du, i + 1));
+        AT(sc.du2, i) = d2(un);
+        AT(sc.du, i + 1) = d2(-cmul(f, un));
+      }
+      AT(sc.piv, i) = 1;
+    }
+  }
+  // q = M^{-1} e_1: L then U
+  for (int i = 0; i < k; ++i) AT(sc.q, i) = make_double2(i == 0 ? 1.0 : 0.0, 0.0);
+  for (int i = 0; i < k - 1; ++i) {
+    const Cx<double> f = c64(AT(sc.dl, i));
+    if (AT(sc.piv, i)) {
+      const Cx<double> bi = c64(AT(sc.q, i)), bn = c64(AT(sc.q, i + 1));
+      AT(sc.q, i) = d2(bn);
+      AT(sc.q, i + 1) = d2(bi - cmul(f, bn));
+    } else {
+      AT(sc.q, i + 1) = d2(c64(AT(sc.q, i + 1)) - cmul(f, c64(AT(sc.q, i))));
+    }
+  }
+  for (int i = k - 1; i >= 0; --i) {
+    Cx<double> b = c64(AT(sc.q, i));
+    if (i + 1 < k) b = b - cmul(c64(AT(sc.du, i)), c64(AT(sc.q, i + 1)));
+    if (i + 2 < k) b = b - cmul(c64(AT(sc.du2, i)), c64(AT(sc.q, i + 2)));
+    AT(sc.q, i) = d2(cdiv(b, c64(AT(sc.d, i))));
+  }
+  // p = M^{-H} xbar: U^H then L^H
+  for (int i = 0; i < k; ++i) {
+    Cx<double> b = c64(xbar[i]);
+    if (i >= 1) b = b - cmulc(c64(AT(sc.du, i - 1)), c64(AT(sc.p, i - 1)));
+    if (i >= 2) b = b - cmulc(c64(AT(sc.du2, i - 2)), c64(AT(sc.p, i - 2)));
+    AT(sc.p, i) = d2(cdiv(b, cconj(c64(AT(sc.d, i)))));
+  }
+  for (int i = k - 2; i >= 0; --i) {
+    const Cx<double> f = c64(AT(sc.dl, i));
+    const Cx<double> bi = c64(AT(sc.p, i)), bn = c64(AT(sc.p, i + 1));
+    const Cx<double> v = bi - cmulc(f, bn);
+    if (AT(sc.piv, i)) {
+      AT(sc.p, i) = d2(bn);
+      AT(sc.p, i + 1) = d2(v);
+    } else {
+      AT(sc.p, i) = d2(v);
+    }
+  }
+#undef AT
+}
+
+// Sums over nodes (fixed order) with the trapezoid weights h tau / pi.
+__global__ void k_isign_vjp_reduce(int k, double h, int n0, int nnode, VjpScratch sc,
+                                   IsignVjpOut out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const int nthr = 2 * nnode;
+  Cx<double> x = {0.0, 0.0}, gd = {0.0, 0.0}, gs = {0.0, 0.0}, gu = {0.0, 0.0};
+  for (int t = 0; t < nthr; ++t) {
+    const double w = h * exp((double)(n0 + (t >> 1)) * h) / M_PI;
+    const Cx<double> qi = c64(sc.q[(long)i * nthr + t]);
+    const Cx<double> pi_ = c64(sc.p[(long)i * nthr + t]);
+    x = x + scale(w, qi);
+    gd = gd - scale(w, cmulc(qi, pi_));
+    if (i + 1 < k) {
+      const Cx<double> qn = c64(sc.q[(long)(i + 1) * nthr + t]);
+      const Cx<double> pn = c64(sc.p[(long)(i + 1) * nthr + t]);
+      gs = gs - scale(w, cmulc(qi, pn));   // Gbar_{i+1,i} = -p_{i+1} conj(q_i)
+      gu = gu - scale(w, cmulc(qn, pi_));  // Gbar_{i,i+1} = -p_i conj(q_{i+1})
+    }
+  }
+  out.x[i] = d2(x);
+  out.gd[i] = d2(gd);
+  if (i + 1 < k) {
+    out.gsub_re[i] = gs.re;
+    out.gsup[i] = d2(gu);
+  }
+}
+
+void launch_isign_vjp(const double2* alpha, const double* beta, const double2* gamma,
+                      const double2* xbar, int k, double h, int n0, int nnode, void* scratch,
+                      const IsignVjpOut& out, hipStream_t st) {
+  const int nthr = 2 * nnode;
+  const VjpScratch sc = carve(scratch, k, nthr);
+  hipLaunchKernelGGL(k_isign_vjp, dim3((nthr + 63) / 64), dim3(64), 0, st, alpha, beta, gamma,
+                     xbar, k, h, n0, nnode, sc);
+  hipLaunchKernelGGL(k_isign_vjp_reduce, dim3((k + 63) / 64), dim3(64), 0, st, k, h, n0, nnode, sc,
+                     out);
+}
+
+// ---- link force -----------------------------------------------------------------
+// For Re <pbar, A p>, A = gamma5 Dw with hop coefficient k eta on packed links
+// U~ (boundary signs folded in), the gradient with respect to U~_nu(x) is
+//   forward hop into x+nu : -k eta+ sum_s [(1+g_nu) g5 pbar(x+nu)]_s [p(x)]_s^dagger
+//   backward hop into x   : -k eta- sum_s [(1-g_nu) p(x+nu)]_s [g5 pbar(x)]_s^dagger
+// (colour outer products summed over spin).  With (1 +- g_nu) = E P, P the
+// two-row projection of the stencil and E = P^dagger, each sum reduces to two
+// outer products of projected half spinors.
+
+struct HopPair {
+  double fA[4], bA[4], fAd[4], bAd[4];
+};
+
+__device__ __forceinline__ void load_sp(const double2* f, long Vs, int s, bool g5,
+                                        Cx<double> (&p)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    p[c] = c64(f[(long)c * Vs + s]);
+    if (g5 && c >= 6) p[c] = -p[c];
+  }
+}
+
+// F[a][b] += c * sum_k h_k[a] conj(g_k[b])
+__device__ __forceinline__ void outer_acc(Cx<double> (&F)[9], const Cx<double> (&h)[6],
+                                          const Cx<double> (&g)[6], double c) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const Cx<double> v = cmulc(g[b], h[a]) + cmulc(g[3 + b], h[3 + a]);
+      F[3 * a + b] = F[3 * a + b] + scale(c, v);
+    }
+}
+
+// forward and backward hop terms of one (adjoint, input) pair
+template <int NU>
+__device__ __forceinline__ void force_pair(Cx<double> (&Ff)[9], Cx<double> (&Fb)[9],
+                                           const double2* bar, const double2* in, long Vs, int s,
+                                           int sf, double cf, double cb) {
+  Cx<double> a[12], b[12], h[6], g[6];
+  load_sp(bar, Vs, sf, true, a);
+  project<double, NU, +1>(a, h);
+  load_sp(in, Vs, s, false, b);
+  project<double, NU, +1>(b, g);
+  outer_acc(Ff, h, g, -cf);
+  load_sp(in, Vs, sf, false, a);
+  project<double, NU, -1>(a, h);
+  load_sp(bar, Vs, s, true, b);
+  project<double, NU, -1>(b, g);
+  outer_acc(Fb, h, g, -cb);
+}
+
+template <int NU>
+__device__ __forceinline__ void force_dir(double2* F, const double2* pbar, const double2* p,
+                                          const double2* qbar, const double2* q, long stride,
+                                          int nrhs, const Geometry& g, int s, int sf,
+                                          const HopPair& hp) {
+  const long Vs = g.Vs;
+  Cx<double> fp[9], fm[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) fp[e] = fm[e] = {0.0, 0.0};
+  for (int r = 0; r < nrhs; ++r) {
+    const long o = (long)r * stride;
+    // A(mu): forward carries e^{+mu}, backward e^{-mu}
+    if constexpr (NU == 3) force_pair<NU>(fp, fm, pbar + o, p + o, Vs, s, sf, hp.fA[NU], hp.bA[NU]);
+    else force_pair<NU>(fp, fp, pbar + o, p + o, Vs, s, sf, hp.fA[NU], hp.bA[NU]);
+    if (qbar) {
+      // A(mu)^dagger = A(-mu): forward carries e^{-mu}, backward e^{+mu}
+      if constexpr (NU == 3)
+        force_pair<NU>(fm, fp, qbar + o, q + o, Vs, s, sf, hp.fAd[NU], hp.bAd[NU]);
+      else force_pair<NU>(fp, fp, qbar + o, q + o, Vs, s, sf, hp.fAd[NU], hp.bAd[NU]);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double2* dst = F + ((long)NU * 9 + e) * Vs + s;
+    *dst = d2(c64(*dst) + fp[e]);
+  }
+  if constexpr (NU == 3) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      double2* dst = F + ((long)4 * 9 + e) * Vs + s;
+      *dst = d2(c64(*dst) + fm[e]);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kWG) k_gforce(double2* F, const double2* pbar, const double2* p,
+                                                const double2* qbar, const double2* q, long stride,
+                                                int nrhs, Geometry g, HopPair hp) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const Nbr nb = neighbours(s, g);
+  force_dir<0>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[0], hp);
+  force_dir<1>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[1], hp);
+  force_dir<2>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[2], hp);
+  force_dir<3>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[3], hp);
+}
+
+void launch_gforce(double2* F, const double2* pbar, const double2* p, const double2* qbar,
+                   const double2* q, long stride, int nrhs, const Geometry& g, const Hop& hA,
+                   const Hop& hAd, hipStream_t st) {
+  HopPair hp;
+  for (int nu = 0; nu < 4; ++nu) {
+    hp.fA[nu] = hA.fwd[nu];
+    hp.bA[nu] = hA.bwd[nu];
+    hp.fAd[nu] = hAd.fwd[nu];
+    hp.bAd[nu] = hAd.bwd[nu];
+  }
+  hipLaunchKernelGGL(k_gforce, dim3((g.V + kWG - 1) / kWG), dim3(kWG), 0, st, F, pbar, p, qbar, q,
+                     stride, nrhs, g, hp);
+}
+
+__global__ void __launch_bounds__(kWG) k_gforce_out(const double2* F, const double2* links,
+                                                    Geometry g, int bc0, int bc1, int bc2, int bc3,
+                                                    double2* grad_U, double* partials) {
+  __shared__ double lds[(kWG / 64)];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double part[1] = {0.0};
+  if (s < g.V) {
+    const int x = s % g.lx, y = (s / g.lx) % g.ly, z = (s / (g.lx * g.ly)) % g.lz,
+              t = s / (g.lx * g.ly * g.lz);
+    const int coord[4] = {x, y, z, t};
+    const int ext[4] = {g.lx, g.ly, g.lz, g.lt};
+    const int bc[4] = {bc0, bc1, bc2, bc3};
+    for (int nu = 0; nu < 4; ++nu) {
+      const double sg = (coord[nu] == ext[nu] - 1 && bc[nu] < 0) ? -1.0 : 1.0;
+      for (int e = 0; e < 9; ++e) {
+        Cx<double> v = c64(F[((long)nu * 9 + e) * g.Vs + s]);
+        if (nu == 3) {
+          const Cx<double> vm = c64(F[((long)4 * 9 + e) * g.Vs + s]);
+          const Cx<double> u = c64(links[((long)3 * 9 + e) * g.Vs + s]);
+          part[0] += cmulc(v, u).re - cmulc(vm, u).re;
+          v = v + vm;
+        }
+        grad_U[((long)s * 4 + nu) * 9 + e] = d2(scale(sg, v));
+      }
+    }
+  }
+  block_sum<1>(part, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = part[0];
+}
+
+__global__ void k_sum_partials(const double* partials, int n, double* out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double a = 0.0;
+  for (int i = 0; i < n; ++i) a += partials[i];
+  *out = a;
+}
+
+void launch_gforce_out(const double2* F, const double2* links, const Geometry& g, const int bc[4],
+                       double2* grad_U, double* partials, double* grad_mu, hipStream_t st) {
+  const int nb = (g.V + kWG - 1) / kWG;
+  hipLaunchKernelGGL(k_gforce_out, dim3(nb), dim3(kWG), 0, st, F, links, g, bc[0], bc[1], bc[2],
+                     bc[3], grad_U, partials);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1), 0, st, partials, nb, grad_mu);
+}
+
+}  // namespace ovs

@@ -1,0 +1,113 @@
+// Kernels of the sign-function gradient (grad.hip) and their launchers.
+//
+// The gradient is the reverse sweep of the two-sided Lanczos approximation
+// y_k = |b| V_k sgn(G_k) e_1 (Section 4, no deflation).  All fields here are
+// FP64, [nrhs][12][Vs] with pads zero; per-source scalars are [nrhs] or
+// [nrhs][kmax] arrays of double / double2 in device memory.
+#pragma once
+
+#include "ovs_common.h"
+
+namespace ovs {
+
+constexpr int kLinTerms = 5;
+constexpr int kLinDots = 2;
+
+// out_r = sum_j coef[j*nrhs + r] * x_j,r (+ out_r when accumulate), and
+// partial sums of dot_q,r = sum conj(y_q,r) * out_r (y_q = nullptr: the
+// combination itself).  out may be null (dots only).  Source r's field is at
+// offset r*stride of every pointer.
+struct LinArgs {
+  const double2* x[kLinTerms] = {};
+  int nterm = 0;
+  const double2* coef = nullptr;   // [kLinTerms][nrhs]
+  double2* out = nullptr;
+  int accumulate = 0;
+  const double2* y[kLinDots] = {};
+  int ndot = 0;
+  double* partials = nullptr;      // [nrhs][lin_nchunk][kLinDots][2]
+};
+int lin_nchunk(long stride);
+void launch_lin(const LinArgs& a, long stride, int nrhs, hipStream_t s);
+
+// Per-source scalar steps (one thread per source); see grad.hip.
+struct GradScalars {
+  double2* alpha;    // [nrhs][kmax]
+  double* beta;      // [nrhs][kmax]
+  double2* gamma;    // [nrhs][kmax]
+  double* tnorm2;    // [nrhs][kmax]
+  double2* x;        // [nrhs][kmax]  sgn(G_k) e_1
+  double2* xbar;     // [nrhs][kmax]
+  double2* abar;     // [nrhs][kmax]
+  double* bbar;      // [nrhs][kmax]
+  double2* gbar;     // [nrhs][kmax]
+  double* nb;        // [nrhs]
+  int* status;       // [nrhs] 0 ok, 1 lucky breakdown, 2 serious breakdown
+  double2* coef;     // [kCoefTables][kLinTerms][nrhs]
+  int kmax;
+  int nrhs;
+};
+constexpr int kCoefTables = 8;
+// Coefficient tables (indices into GradScalars::coef).
+enum {
+  kTabNorm = 0,  // forward: [1/|b|]
+  kTabV = 1,     // forward: v~ = t - alpha v_i - gamma_{i-1} v_{i-1};  reverse: vbar~_i
+  kTabW = 2,     // forward: w~ = s - conj(alpha) w_i - beta_{i-1} w_{i-1}; reverse: wbar~_i
+  kTabSV = 3,    // forward: [1/beta_i];  reverse: tbar_i
+  kTabSW = 4,    // forward: [1/conj(gamma_i)];  reverse: vbar_i
+  kTabWB = 5,    // reverse: wbar_i
+  kTabOne = 6,   // [1, 1, 1, 1, 1]
+  kTabFin = 7    // reverse: grad_b = ubar/|b| + nbar v_1
+};
+inline double2* coef_table(const GradScalars& s, int t) {
+  return s.coef + (long)t * kLinTerms * s.nrhs;
+}
+
+// forward
+void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
+void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st);
+void launch_gf_beta(const GradScalars& s, int i, const double* part_v, const double* part_w,
+                    int nchunk, hipStream_t st);
+// reverse
+void launch_gr_first(const GradScalars& s, hipStream_t st);
+void launch_gr_s1(const GradScalars& s, int i, const double* part_v, const double* part_w,
+                  int nchunk, hipStream_t st);
+void launch_gr_s2(const GradScalars& s, int i, const double* part_v, const double* part_w,
+                  int nchunk, hipStream_t st);
+void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
+
+// xbar_i = nb * v_i^dagger chi for i < kmax (basis [kmax][nrhs][12][Vs]).
+void launch_basis_dots(const double2* basis, const double2* chi, long stride, int kmax, int nrhs,
+                       double* partials, const GradScalars& s, hipStream_t st);
+// y_r = nb_r * sum_i x_i v_i
+void launch_gcombine(const double2* basis, long stride, int kmax, int nrhs, const GradScalars& s,
+                     double2* y, hipStream_t st);
+
+// Inner sign and its vector-Jacobian product for one source by the tau = e^u
+// trapezoid rule at step h: x = (1/pi) int sum_+- (G +- i tau)^{-1} e_1 dtau and
+// Gbar (band of G) = -(1/pi) int sum_+- p conj(q)^T dtau with
+// q = (G +- i tau)^{-1} e_1, p = (G +- i tau)^{-H} xbar.
+struct IsignVjpOut {
+  double2* x;        // [k]
+  double2* gd;       // [k]   Gbar_{i,i}
+  double* gsub_re;   // [k-1] Re Gbar_{i+1,i} (beta_i is real)
+  double2* gsup;     // [k-1] Gbar_{i,i+1}
+};
+size_t isign_vjp_scratch_bytes(int k, int nnode);
+void launch_isign_vjp(const double2* alpha, const double* beta, const double2* gamma,
+                      const double2* xbar, int k, double h, int n0, int nnode, void* scratch,
+                      const IsignVjpOut& out, hipStream_t st);
+
+// Link force: F ([5][9][Vs] FP64, packed-link gradient; slot 3 the e^{+mu}
+// part and slot 4 the e^{-mu} part of direction 4) += gradient of
+//   Re <pbar, A(mu) p> + Re <qbar, A(mu)^dagger q>   summed over sources.
+// q/qbar may be null.
+void launch_gforce(double2* F, const double2* pbar, const double2* p, const double2* qbar,
+                   const double2* q, long stride, int nrhs, const Geometry& g, const Hop& hA,
+                   const Hop& hAd, hipStream_t st);
+// grad_U (canonical [V][4][3][3]) = boundary sign * (F_nu + [nu=3] F_4), and
+// grad_mu = Re sum tr(F_3^dagger U_4) - Re sum tr(F_4^dagger U_4) (packed links).
+void launch_gforce_out(const double2* F, const double2* links, const Geometry& g, const int bc[4],
+                       double2* grad_U, double* partials, double* grad_mu, hipStream_t st);
+
+}  // namespace ovs

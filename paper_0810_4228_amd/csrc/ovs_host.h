@@ -1,0 +1,55 @@
+// Host-side helpers shared by the C-ABI sources (api.cpp, gradient.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "ovs_common.h"
+
+namespace ovs {
+
+// Orders the library stream after the caller's stream on entry, and the
+// caller's stream after the library stream on exit.
+struct StreamScope {
+  ovs_lattice_s* l;
+  explicit StreamScope(ovs_lattice_s* lat) : l(lat) {
+    (void)hipGetLastError();  // drop a stale error left by an earlier library call (e.g. rocBLAS)
+    (void)hipEventRecord(l->ev_in, l->user_stream);
+    (void)hipStreamWaitEvent(l->stream, l->ev_in, 0);
+  }
+  ~StreamScope() {
+    (void)hipEventRecord(l->ev_out, l->stream);
+    (void)hipStreamWaitEvent(l->user_stream, l->ev_out, 0);
+  }
+};
+
+// Bump allocator over the cached workspace (or a sizing pass with base == nullptr).
+struct Arena {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// kappa * eta^{+-}_nu (Section 1): e^{+-mu} on the time hops only.
+Hop make_hop(double m_w, double mu);
+// Hop coefficients and gamma5 placement of an operator.
+void op_setup(const ovs_lattice_s* l, ovs_op op, Hop& h, bool& g5in, bool& g5out);
+size_t elem_bytes(const ovs_lattice_s* l);
+// Stencil configuration for nrhs sources (tuned, or the default).
+Tuning get_tuning(const ovs_lattice_s* l, int nrhs);
+// Grows the lattice's cached workspace to at least bytes.
+ovs_status ensure_ws(ovs_lattice_s* l, size_t bytes);
+// canonical complex128 <-> internal storage-precision fields
+void pack_field(const ovs_lattice_s* l, const void* canon, void* field, int nrhs);
+void unpack_field(const ovs_lattice_s* l, const void* field, void* canon, int nrhs);
+// links and parameters set
+bool ready(const ovs_lattice_s* l);
+
+}  // namespace ovs

@@ -28,6 +28,7 @@ __all__ = [
     "gaussian_sources",
     "point_sources",
     "random_gauge",
+    "complex_normal",
     "LINK_SEED",
     "SOURCE_SEED",
     "COTANGENT_SEED",
@@ -97,3 +98,10 @@ def random_gauge(dims, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     g = rng.standard_normal((v, 3, 3, 2))
     return np.ascontiguousarray(su3_project(g[..., 0] + 1j * g[..., 1]))
+
+
+def complex_normal(shape, seed: int) -> np.ndarray:
+    """(x + i y)/sqrt(2) with x, then y, drawn as whole arrays of standard
+    normals from default_rng(seed): random test directions."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)

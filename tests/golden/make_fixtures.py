@@ -2,14 +2,28 @@
 
 Calls only the CPU oracle (oracle/) and the seeded input generators (synth/);
 nothing here touches the HIP library.  Re-run with
-    python tests/golden/make_fixtures.py
-after any change to the oracle's arithmetic.
+    python tests/golden/make_fixtures.py [lattice_4444] [gradient_8888]
+(both when no name is given) after any change to the oracle's arithmetic.
 
 lattice_4444.npz -- the 4^4 workload: links P_SU3(1 + 0.4 G) (seed 0),
     m_w = -1.5, mu = 0.3, one Gaussian source (seed 1).  Holds the exact
     sgn(A) b by the spectral definition (Section 1, eq. (1.3)-(1.4)), the 20
     critical eigentriples (Section 3: smallest |lambda|, L^dagger R = I) and
     the full spectrum's smallest |lambda| and |Re lambda|.
+
+gradient_8888_k150.npz, gradient_8888_k400.npz -- the gradient workload: 8^4,
+    links P_SU3(1 + 0.6 G) (seed 0), m_w = -1.5, mu = 0.3, one Gaussian
+    source b (seed 1) and cotangent chi (seed 2), two-sided Lanczos without
+    deflation (Section 4) at k = 150 and k = 400.  Each holds the oracle's
+    reverse-sweep gradient of L = Re <chi, y_k> (256 sampled entries of y and
+    grad_b, 64 sampled links of grad_U, grad_mu, full norms, directional
+    derivatives), central finite differences of the oracle's forward y_k in
+    three directions (mu, a random link direction E, a random source
+    direction db; synth.complex_normal seeds 3 and 4), and the rounding noise
+    of the forward: L(mu +- 1e-13) - L(mu).  At k = 400 that noise is ~1e-5
+    (biorthogonality is lost), so its differences are central ones at
+    h = 1e-3; at k = 150 it is ~1e-12 and the differences are Richardson
+    extrapolations (4 D(h/2) - D(h))/3 of central ones at h = 1e-5.
 """
 import os
 import sys
@@ -20,7 +34,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import synth  # noqa: E402
-from oracle import dirac, sign  # noqa: E402
+from oracle import dirac, grad, krylov, sign  # noqa: E402
 
 
 def lattice_4444():
@@ -43,6 +57,65 @@ def lattice_4444():
     )
 
 
+def gradient_8888_at(k, h, richardson):
+    dims = (8, 8, 8, 8)
+    m_w, mu, eps = -1.5, 0.3, 0.6
+    U = synth.random_links(dims, eps, seed=synth.LINK_SEED)
+    b = synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)[0]
+    chi = synth.gaussian_sources(dims, 1, seed=synth.COTANGENT_SEED)[0]
+    y, gb, gmu, gU, _ = grad.tsl_vjp(dims, U, m_w, mu, b, chi, k)
+    E = synth.complex_normal(U.shape, 3)
+    db = synth.complex_normal(b.shape, 4)
+
+    def loss(UU, mm, bb):
+        A = dirac.csr_A(dims, UU, m_w, mm)
+        Ad = dirac.csr_A(dims, UU, m_w, -mm)
+        yy = krylov.tsl_apply(lambda z: A @ z, lambda z: Ad @ z, bb, k)
+        return float(np.real(np.vdot(chi, yy)))
+
+    L0 = loss(U, mu, b)
+    noise = max(abs(loss(U, mu + 1e-13, b) - L0), abs(loss(U, mu - 1e-13, b) - L0))
+    def central(f, hh):
+        return (f(hh) - f(-hh)) / (2 * hh)
+
+    def diff(f):
+        if not richardson:
+            return central(f, h)
+        # (4 D(h/2) - D(h)) / 3 cancels the h^2 term of the central difference
+        return (4.0 * central(f, h / 2) - central(f, h)) / 3.0
+
+    fd_mu = diff(lambda t: loss(U, mu + t, b))
+    fd_U = diff(lambda t: loss(U + t * E, mu, b))
+    fd_b = diff(lambda t: loss(U, mu, b + t * db))
+    rng = np.random.default_rng(5)
+    V = int(np.prod(dims))
+    idx_b = np.sort(rng.choice(12 * V, 256, replace=False))
+    idx_U = np.sort(rng.choice(4 * V, 64, replace=False))
+    np.savez_compressed(
+        os.path.join(HERE, f"gradient_8888_k{k}.npz"),
+        dims=np.array(dims), m_w=m_w, mu=mu, eps=eps, k=k, h=h, richardson=richardson,
+        loss=float(np.real(np.vdot(chi, y))), noise=noise,
+        idx_b=idx_b, idx_U=idx_U,
+        y_samp=y[idx_b], grad_b_samp=gb[idx_b], grad_U_samp=gU.reshape(4 * V, 9)[idx_U],
+        grad_mu=gmu, norm_y=np.linalg.norm(y), norm_grad_b=np.linalg.norm(gb),
+        norm_grad_U=np.linalg.norm(gU),
+        vjp_dir_U=float(np.real(np.vdot(gU, E))), vjp_dir_b=float(np.real(np.vdot(gb, db))),
+        fd_mu=fd_mu, fd_U=fd_U, fd_b=fd_b,
+    )
+
+
+def gradient_8888():
+    gradient_8888_at(150, 1e-5, True)
+    gradient_8888_at(400, 1e-3, False)
+
+
 if __name__ == "__main__":
-    lattice_4444()
-    print("written")
+    names = sys.argv[1:] or ["lattice_4444", "gradient_8888"]
+    for name in names:
+        if name == "gradient_8888_k150":
+            gradient_8888_at(150, 1e-5, True)
+        elif name == "gradient_8888_k400":
+            gradient_8888_at(400, 1e-3, False)
+        else:
+            globals()[name]()
+        print("written", name)

@@ -173,3 +173,17 @@ def test_tsl_vjp_converges_to_dk():
     assert np.linalg.norm(gb - gb_ex) <= 1e-6 * np.linalg.norm(gb_ex)
     assert abs(gmu - gmu_ex) <= 1e-6 * abs(gmu_ex)
     assert np.linalg.norm(gU - gU_ex) <= 1e-6 * np.linalg.norm(gU_ex)
+
+
+@pytest.mark.parametrize("k", [150, 400])
+def test_fixture_8888_gradient_matches_fd(k):
+    """Full-size pin (8^4): the stored oracle gradient against the stored
+    central finite differences of the oracle's forward y_k, both written by
+    tests/golden/make_fixtures.py, in three directions.  The tolerance adds
+    the forward's measured rounding noise over the step (stored beside it)."""
+    import os
+    f = np.load(os.path.join(os.path.dirname(__file__), "golden", f"gradient_8888_k{k}.npz"))
+    slack = 4.0 * float(f["noise"]) / float(f["h"])
+    for an, fd in (("grad_mu", "fd_mu"), ("vjp_dir_U", "fd_U"), ("vjp_dir_b", "fd_b")):
+        a, d = float(f[an]), float(f[fd])
+        assert abs(a - d) <= 1e-6 * max(1.0, abs(d)) + slack, (an, a, d, slack)
