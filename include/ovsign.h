@@ -131,8 +131,9 @@ ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int
 /* Full tuned configuration for nrhs sources, host int32 [8]:
  * {stencil shape = 100*rhs block + 10*lanes per site + streaming stores,
  *  stencil workgroup size, stencil LDS cap KiB, stencil block order,
- *  Lanczos dual-stencil shape = 100*rhs block + 10 + streaming stores, its workgroup size,
- *  its LDS cap KiB, its block order}. */
+ *  Lanczos dual-stencil shape = 100*rhs block + 10*lanes per site + streaming stores
+ *  (lanes per site 1: one thread computes A v and A^dag w; 2: a lane pair splits
+ *  the two operators), its workgroup size, its LDS cap KiB, its block order}. */
 ovs_status ovs_get_tuning_ex(ovs_lattice lat, int32_t nrhs, int32_t out[8]);
 /* Install a configuration in the encoding of ovs_get_tuning_ex (e.g. one saved
  * from an earlier ovs_autotune).  OVS_ERR_ARG for values the kernels do not

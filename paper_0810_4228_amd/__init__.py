@@ -248,7 +248,7 @@ class Lattice:
         st.update(rhs_block=shape // 100, lanes_per_site=(shape // 10) % 10, streaming_store=shape % 10)
         du = dict(zip(keys, out[4:8]))
         shape = du["rhs_block"]
-        du.update(rhs_block=shape // 100, streaming_store=shape % 10)
+        du.update(rhs_block=shape // 100, lanes_per_site=(shape // 10) % 10, streaming_store=shape % 10)
         return {"stencil": st, "dual": du}
 
     def deflation_set(self, lam, R, L):

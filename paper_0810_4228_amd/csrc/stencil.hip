@@ -277,6 +277,16 @@ k_wilson_g(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>
 // per-kernel opt-in; the limit is set once per process from the device query.
 static int g_lds_limit_kb = 64;
 void set_lds_limit(int kb) { g_lds_limit_kb = kb; }
+// A launch whose static plus dynamic LDS exceeds the per-workgroup limit is an
+// invalid dispatch (the queue aborts): launchers check before launching.
+static bool lds_fits(const void* fn, int dyn_kb) {
+  hipFuncAttributes at;
+  if (hipFuncGetAttributes(&at, fn) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (long)at.sharedSizeBytes + (long)dyn_kb * 1024 <= (long)g_lds_limit_kb * 1024;
+}
 static void apply_lds_limit(const void* fn) {
   if (g_lds_limit_kb > 64) {
     // a rejected request only means larger LDS caps fail at launch (and are
@@ -304,37 +314,42 @@ TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order) {
 }
 
 template <typename R, int B>
-static void launch_w(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
+static hipError_t launch_w(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
                      const Hop& hop_c, bool g5in, bool g5out, int wg, int lds_kb, int order,
                      int nt, hipStream_t s) {
   using T2 = typename Vec2<R>::T;
   const TileMap tm = make_tile_map(g, wg, (nrhs + B - 1) / B, order);
   static bool lds_set = false;
   if (!lds_set) { apply_lds_limit((const void*)k_wilson<R, B>); lds_set = true; }
+  if (!lds_fits((const void*)k_wilson<R, B>, lds_kb)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_wilson<R, B>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s, (const T2*)links,
                      (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs, (int)g5in, (int)g5out,
                      nt, tm);
+  return hipSuccess;
 }
 
 template <typename R, int G>
-static void launch_wg(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
+static hipError_t launch_wg(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
                       const Hop& hop_c, bool g5in, bool g5out, int wg, int lds_kb, int order, int nt,
                       hipStream_t s) {
   using T2 = typename Vec2<R>::T;
   const TileMap tm = make_tile_map(g, wg / G, (nrhs + G - 1) / G, order);
   static bool lds_set = false;
   if (!lds_set) { apply_lds_limit((const void*)k_wilson_g<R, G>); lds_set = true; }
+  if (!lds_fits((const void*)k_wilson_g<R, G>, lds_kb)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_wilson_g<R, G>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s,
                      (const T2*)links, (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs,
                      (int)g5in, (int)g5out, nt, tm);
+  return hipSuccess;
 }
 
 hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out, int nrhs,
                          const Geometry& g, const Hop& hop_c, bool g5in, bool g5out,
                          const Tuning& tn, hipStream_t s) {
   const int wg = tn.wg;
+  hipError_t e = hipSuccess;
   if (tn.g > 1) {
-#define OVS_WG(RT, GG) launch_wg<RT, GG>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s)
+#define OVS_WG(RT, GG) e = launch_wg<RT, GG>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s)
     if (f32) {
       switch (tn.g) {
         case 2: OVS_WG(float, 2); break;
@@ -351,25 +366,27 @@ hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out,
       }
     }
 #undef OVS_WG
+    if (e != hipSuccess) return e;
     return hipGetLastError();
   }
   if (f32) {
     switch (tn.rhs_block) {
-      case 1: launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 2: launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 3: launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 4: launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 6: launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 1: e = launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 2: e = launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 3: e = launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 4: e = launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 6: e = launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (tn.rhs_block) {
-      case 1: launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 2: launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 3: launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 1: e = launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 2: e = launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 3: e = launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
       default: return hipErrorInvalidValue;
     }
   }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -395,7 +412,9 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
   const T2* in_w = wbuf + (long)(iter % 3) * basis_stride;
   const int j0 = rb * B;
   if (j0 >= na) return;  // uniform over the workgroup
-  const int nsrc = min(B, na - j0);
+  // opaque to the optimiser, as in k_dual_pair: keeps the per-source guards
+  int nsrc = min(B, na - j0);
+  __asm__ volatile("" : "+s"(nsrc));
   const int s = site0 + threadIdx.x;
   const bool live = s < g.V;
   const int V = g.Vs;  // stride of the padded component planes
@@ -470,11 +489,137 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
   }
   block_sum<3 * B>(part, lds);
   if (threadIdx.x == 0) {
-    for (int r = 0; r < nsrc; ++r) {
-      double* p = partials + ((long)slot[r] * tm.ntiles + tile) * 3;
-      p[0] = part[3 * r + 0];
-      p[1] = part[3 * r + 1];
-      p[2] = part[3 * r + 2];
+    // compile-time bound: part[] stays in registers (a runtime bound makes it
+    // an indexed array that the compiler may place in LDS or scratch)
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      if (r < nsrc) {
+        double* p = partials + ((long)slot[r] * tm.ntiles + tile) * 3;
+        p[0] = part[3 * r + 0];
+        p[1] = part[3 * r + 1];
+        p[2] = part[3 * r + 2];
+      }
+    }
+  }
+}
+
+// Operator-pair variant: lanes 2j and 2j+1 of a 512-thread workgroup take
+// the same site, lane 2j computing T = A V~ and lane 2j+1 S = A^dag W~ for the
+// source block.  Both operators are the same stencil with e^{+mu} and e^{-mu}
+// swapped on the time hops, so the pair loads the same link addresses (one
+// fetch serves both lanes) and each lane holds one set of accumulators: half
+// the registers of k_dual, twice the waves in flight.  Tiles are the same 256
+// sites, so the partial-sum layout is unchanged; the even lane also reads
+// W~ at its own site for W~^dagger T.
+template <typename R, int B>
+__global__ void __launch_bounds__(512)
+k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
+            const typename Vec2<R>::T* __restrict__ basis,
+            const typename Vec2<R>::T* __restrict__ wbuf, long basis_stride, int ring,
+            const int* __restrict__ it, typename Vec2<R>::T* __restrict__ out_t,
+            typename Vec2<R>::T* __restrict__ out_s, double* __restrict__ partials, Geometry g,
+            HopR<R> hA, HopR<R> hAd, const int* __restrict__ rhs_map,
+            const int* __restrict__ n_active, int nt, TileMap tm) {
+  using T2 = typename Vec2<R>::T;
+  __shared__ double lds[(512 / 64) * 3 * B];
+  int site0, rb, tile;
+  if (!map_tile(blockIdx.x, tm, site0, rb, tile)) return;  // uniform over the workgroup
+  const int na = *n_active;
+  const int iter = *it;
+  const T2* in_v = basis + (long)(ring ? iter % 3 : iter) * basis_stride;
+  const T2* in_w = wbuf + (long)(iter % 3) * basis_stride;
+  const int j0 = rb * B;
+  if (j0 >= na) return;  // uniform over the workgroup
+  // The empty asm hides that nsrc >= 1 from the optimiser: the per-source
+  // guards below stay scalar branches that bound each hop's load batch (with
+  // the guards folded away the scheduler hoists every load of the site and spills).
+  int nsrc = min(B, na - j0);
+  __asm__ volatile("" : "+s"(nsrc));
+  const int op = threadIdx.x & 1;
+  const int s = site0 + (threadIdx.x >> 1);
+  const bool live = s < g.V;
+  const int V = g.Vs;
+  const T2* in = op ? in_w : in_v;
+  T2* out = op ? out_s : out_t;
+  R cf[4], cb[4];
+#pragma unroll
+  for (int nu = 0; nu < 4; ++nu) {
+    cf[nu] = op ? hAd.fwd[nu] : hA.fwd[nu];
+    cb[nu] = op ? hAd.bwd[nu] : hA.bwd[nu];
+  }
+  int slot[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) slot[r] = (r < nsrc) ? rhs_map[j0 + r] : 0;
+
+  double part[3 * B];
+#pragma unroll
+  for (int q = 0; q < 3 * B; ++q) part[q] = 0.0;
+
+  if (live) {
+    const Nbr nb = neighbours(s, g);
+    Cx<R> acc[B][12];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
+    Cx<R> u[9], psi[12];
+#define OVS_PAIR_DIR(NU)                                                                 \
+  load_link(links, V, NU, nb.b[NU], u);                                                  \
+  _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
+    if (r < nsrc) {                                                                      \
+      load_spinor(in + (long)slot[r] * 12 * V, V, nb.b[NU], false, psi);                 \
+      hop<R, NU, +1, false>(acc[r], u, psi, cf[NU]);                                     \
+    }                                                                                    \
+  }                                                                                      \
+  load_link(links, V, NU, s, u);                                                         \
+  _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
+    if (r < nsrc) {                                                                      \
+      load_spinor(in + (long)slot[r] * 12 * V, V, nb.f[NU], false, psi);                 \
+      hop<R, NU, -1, true>(acc[r], u, psi, cb[NU]);                                      \
+    }                                                                                    \
+  }
+    OVS_PAIR_DIR(0)
+    OVS_PAIR_DIR(1)
+    OVS_PAIR_DIR(2)
+    OVS_PAIR_DIR(3)
+#undef OVS_PAIR_DIR
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      if (r < nsrc) {
+        const long base = (long)slot[r] * 12 * V;
+        Cx<R> p[12], pw[12];
+        load_spinor(in + base, V, s, false, p);
+        if (!op) load_spinor(in_w + base, V, s, false, pw);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          Cx<R> o = p[c] - acc[r][c];
+          if (c >= 6) o = -o;
+          if (nt) st_nt(out + base + (long)c * V + s, o);
+          else st(out + base + (long)c * V + s, o);
+          if (!op) {
+            const Cx<double> t64 = {(double)o.re, (double)o.im};
+            const Cx<double> w64 = {(double)pw[c].re, (double)pw[c].im};
+            const Cx<double> q = cmulc(w64, t64);
+            part[3 * r + 0] += q.re;
+            part[3 * r + 1] += q.im;
+            part[3 * r + 2] += cnorm2(t64);
+          }
+        }
+      }
+    }
+  }
+  block_sum<3 * B>(part, lds);
+  if (threadIdx.x == 0) {
+    // compile-time bound: part[] stays in registers (a runtime bound makes it
+    // an indexed array that the compiler may place in LDS or scratch)
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      if (r < nsrc) {
+        double* p = partials + ((long)slot[r] * tm.ntiles + tile) * 3;
+        p[0] = part[3 * r + 0];
+        p[1] = part[3 * r + 1];
+        p[2] = part[3 * r + 2];
+      }
     }
   }
 }
@@ -482,36 +627,50 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
 int dual_num_wg(const Geometry& g) { return (g.V + 255) / 256; }
 
 template <typename R, int B>
-static void launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, const Hop& hAd,
+static hipError_t launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, const Hop& hAd,
                      hipStream_t s) {
   using T2 = typename Vec2<R>::T;
   const TileMap tm = make_tile_map(g, 256, (a.nrhs_slots + B - 1) / B, a.order);
   static bool lds_set = false;
-  if (!lds_set) { apply_lds_limit((const void*)k_dual<R, B>); lds_set = true; }
-  hipLaunchKernelGGL((k_dual<R, B>), dim3(8 * tm.per_xcd), dim3(256), a.lds_kb * 1024, s,
-                     (const T2*)a.links,
-                     (const T2*)a.basis, (const T2*)a.wbuf, a.basis_stride, (int)a.ring, a.it,
-                     (T2*)a.out_t, (T2*)a.out_s, a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd),
-                     a.rhs_map, a.n_active, a.nt, tm);
+  if (!lds_set) {
+    apply_lds_limit((const void*)k_dual<R, B>);
+    apply_lds_limit((const void*)k_dual_pair<R, B>);
+    lds_set = true;
+  }
+  const void* fn = a.pair ? (const void*)k_dual_pair<R, B> : (const void*)k_dual<R, B>;
+  if (!lds_fits(fn, a.lds_kb)) return hipErrorInvalidValue;
+  if (a.pair)
+    hipLaunchKernelGGL((k_dual_pair<R, B>), dim3(8 * tm.per_xcd), dim3(512), a.lds_kb * 1024, s,
+                       (const T2*)a.links, (const T2*)a.basis, (const T2*)a.wbuf, a.basis_stride,
+                       (int)a.ring, a.it, (T2*)a.out_t, (T2*)a.out_s, a.partials, g,
+                       HopR<R>::make(hA), HopR<R>::make(hAd), a.rhs_map, a.n_active, a.nt, tm);
+  else
+    hipLaunchKernelGGL((k_dual<R, B>), dim3(8 * tm.per_xcd), dim3(256), a.lds_kb * 1024, s,
+                       (const T2*)a.links, (const T2*)a.basis, (const T2*)a.wbuf, a.basis_stride,
+                       (int)a.ring, a.it, (T2*)a.out_t, (T2*)a.out_s, a.partials, g,
+                       HopR<R>::make(hA), HopR<R>::make(hAd), a.rhs_map, a.n_active, a.nt, tm);
+  return hipSuccess;
 }
 
 hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
                        const Hop& hAd, int rhs_block, hipStream_t s) {
+  hipError_t e = hipSuccess;
   if (f32) {
     switch (rhs_block) {
-      case 1: launch_d<float, 1>(a, g, hA, hAd, s); break;
-      case 2: launch_d<float, 2>(a, g, hA, hAd, s); break;
-      case 3: launch_d<float, 3>(a, g, hA, hAd, s); break;
-      case 4: launch_d<float, 4>(a, g, hA, hAd, s); break;
+      case 1: e = launch_d<float, 1>(a, g, hA, hAd, s); break;
+      case 2: e = launch_d<float, 2>(a, g, hA, hAd, s); break;
+      case 3: e = launch_d<float, 3>(a, g, hA, hAd, s); break;
+      case 4: e = launch_d<float, 4>(a, g, hA, hAd, s); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (rhs_block) {
-      case 1: launch_d<double, 1>(a, g, hA, hAd, s); break;
-      case 2: launch_d<double, 2>(a, g, hA, hAd, s); break;
+      case 1: e = launch_d<double, 1>(a, g, hA, hAd, s); break;
+      case 2: e = launch_d<double, 2>(a, g, hA, hAd, s); break;
       default: return hipErrorInvalidValue;
     }
   }
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -111,6 +111,38 @@ def test_matches_cpu_lanczos_step_by_step():
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_dual_variants_match_cpu(prec, tol):
+    """Every dual-stencil configuration the autotuner can pick (one thread for
+    both operators or a lane pair, source blocks 1..4, block order, streaming
+    stores) gives the CPU oracle's two-sided Lanczos result: a ragged lattice
+    (V = 576, not a multiple of the 256-site tile) and 5 sources (ragged
+    source blocks)."""
+    dims = (4, 4, 6, 6)
+    U = synth.random_links(dims, 0.5, seed=81)
+    mu = 0.35
+    b = synth.gaussian_sources(dims, 5, seed=82)
+    A = dirac.csr_A(dims, U, MW, mu)
+    k = 40
+    ref = np.stack([krylov.tsl_apply(lambda v: A @ v, lambda v: A.conj().T @ v, bb, k) for bb in b])
+    lat = lattice(dims, prec, U, mu)
+    base = lat.get_tuning_raw(5)
+    blocks = (1, 2, 3, 4) if prec == "f32" else (1, 2)
+    for lanes in (1, 2):
+        for blk in blocks:
+            for order, nt in ((0, 0), (1, 1)):
+                cfg = list(base)
+                cfg[4] = 100 * blk + 10 * lanes + nt
+                cfg[5] = 256 * lanes
+                cfg[6] = 0
+                cfg[7] = order
+                lat.set_tuning_raw(5, cfg)
+                y, info, st = lat.sign_apply(to_dev(b), k)
+                e = rel_rows(y.cpu().numpy(), ref)
+                say("dual", prec, "lanes", lanes, "block", blk, "order", order, "nt", nt, f"{e:.2e}")
+                assert e <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_free_field_8444(prec, tol):
     """Unit links: exact answer from the closed form at any size."""
     dims = (8, 8, 8, 8)
