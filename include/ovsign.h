@@ -171,7 +171,9 @@ ovs_status ovs_deflation_destroy(ovs_deflation d);
  *   k_max  : maximal Krylov size (1 <= k_max <= N).
  *   tol    : host [nrhs] target relative errors, or NULL to run exactly k_max
  *            steps.  With tol, a source stops when its estimate falls below
- *            tol/10, checked every 25 iterations.
+ *            tol/10, checked every 25 iterations.  On an OVS_F32_STORE lattice
+ *            the sources with tol < 1e-6 (below what FP32 storage attains) run
+ *            as an FP64 group on the FP64 copy of the links; the rest in FP32.
  *   info   : host [nrhs] result records, or NULL.
  * The inner function sgn(G_k) e_1 (or sgn(H_k) e_1) is evaluated on the GPU
  * in FP64.  Returns the most severe per-source warning, or an error. */

@@ -264,9 +264,21 @@ ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_pr
   return OVS_OK;
 }
 
+static void destroy_shadow(ovs_lattice_s* l) {
+  ovs_lattice_s* sh = l->shadow64;
+  if (!sh) return;
+  if (sh->ws) (void)hipFree(sh->ws);
+  (void)hipEventDestroy(sh->ev_in);
+  (void)hipEventDestroy(sh->ev_out);
+  delete sh;  // links (the parent's links64) and stream belong to the parent
+  l->shadow64 = nullptr;
+}
+
 ovs_status ovs_lattice_destroy(ovs_lattice l) {
-  if (!l) return OVS_ERR_ARG;
+  if (!l || l->parent) return OVS_ERR_ARG;
   (void)hipStreamSynchronize(l->stream);
+  destroy_shadow(l);
+  if (l->split_buf) (void)hipFree(l->split_buf);
   if (l->links) (void)hipFree(l->links);
   if (l->links64) (void)hipFree(l->links64);
   if (l->ws) (void)hipFree(l->ws);
@@ -716,9 +728,10 @@ ovs_status ovs_deflation_destroy(ovs_deflation d) {
 
 // ---- sign function ------------------------------------------------------------------
 
-ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
-                          void* y, int32_t nrhs, int32_t k_max, const double* tol,
-                          ovs_method method, int32_t flags, ovs_rhs_info* info) {
+static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
+                                  const void* b, void* y, int32_t nrhs, int32_t k_max,
+                                  const double* tol, ovs_method method, int32_t flags,
+                                  ovs_rhs_info* info) {
   if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || k_max < 1) return OVS_ERR_ARG;
   if (!ready(l)) return OVS_ERR_STATE;
   if (method != OVS_2SL && method != OVS_ARNOLDI) return OVS_ERR_ARG;
@@ -727,7 +740,8 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
   const long N = 12L * l->g.Vs;  // padded field length of one source
   int m = 0;
   if (defl) {
-    if (defl->lat != l || n_defl < 0 || n_defl > defl->m) return OVS_ERR_ARG;
+    if ((defl->lat != l && defl->lat != l->parent) || n_defl < 0 || n_defl > defl->m)
+      return OVS_ERR_ARG;
     m = n_defl;
   }
   const bool arn = method == OVS_ARNOLDI;
@@ -1135,6 +1149,112 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
     }
   }
   return worst;
+}
+
+// FP32 storage limits the attainable relative error to a few 1e-8 (measured
+// with the oracle at 4^4).  Sources asking for less than kF32Floor run in
+// FP64 on the shadow handle: the same driver on the FP64 copy of the links,
+// on the same stream.  Each group is gathered into contiguous buffers.
+constexpr double kF32Floor = 1e-6;
+
+static ovs_status shadow_ready(ovs_lattice_s* l) {
+  if (!l->links64) return OVS_ERR_STATE;
+  if (!l->shadow64) {
+    ovs_lattice_s* sh = new (std::nothrow) ovs_lattice_s();
+    if (!sh) return OVS_ERR_ALLOC;
+    sh->g = l->g;
+    for (int i = 0; i < 4; ++i) sh->bc[i] = l->bc[i];
+    sh->prec = OVS_F64;
+    sh->user_stream = l->stream;
+    sh->stream = l->stream;
+    sh->device = l->device;
+    sh->lds_max_kb = l->lds_max_kb;
+    sh->parent = l;
+    if (hipEventCreateWithFlags(&sh->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sh->ev_out, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      delete sh;
+      return OVS_ERR_HIP;
+    }
+    l->shadow64 = sh;
+  }
+  ovs_lattice_s* sh = l->shadow64;
+  sh->links = l->links64;
+  sh->m_w = l->m_w;
+  sh->mu = l->mu;
+  sh->links_set = l->links_set;
+  sh->params_set = l->params_set;
+  return OVS_OK;
+}
+
+ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
+                          void* y, int32_t nrhs, int32_t k_max, const double* tol,
+                          ovs_method method, int32_t flags, ovs_rhs_info* info) {
+  if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || l->parent) return OVS_ERR_ARG;
+  if (!tol || l->prec != OVS_F32_STORE)
+    return sign_apply_impl(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
+  std::vector<int> lo, hi;
+  for (int r = 0; r < nrhs; ++r) {
+    if (!(tol[r] > 0.0)) return OVS_ERR_ARG;
+    (tol[r] < kF32Floor ? lo : hi).push_back(r);
+  }
+  if (lo.empty())
+    return sign_apply_impl(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
+  if (!ready(l)) return OVS_ERR_STATE;
+  ovs_status st = shadow_ready(l);
+  if (st != OVS_OK) return st;
+  if (hi.empty())
+    return sign_apply_impl(l->shadow64, defl, n_defl, b, y, nrhs, k_max, tol, method, flags,
+                           info);
+  // gather both groups: [b_lo | y_lo | b_hi | y_hi], canonical complex128 fields
+  const size_t fb = 12ul * l->g.V * sizeof(double2);
+  const size_t need = 2 * (size_t)nrhs * fb;
+  if (l->split_bytes < need) {
+    OVS_HIP(hipStreamSynchronize(l->stream));
+    if (l->split_buf) (void)hipFree(l->split_buf);
+    l->split_buf = nullptr;
+    l->split_bytes = 0;
+    if (hipMalloc(&l->split_buf, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return OVS_ERR_ALLOC;
+    }
+    l->split_bytes = need;
+  }
+  StreamScope sc(l);
+  char* base = (char*)l->split_buf;
+  const int nlo = (int)lo.size(), nhi = (int)hi.size();
+  char* b_lo = base;
+  char* y_lo = b_lo + nlo * fb;
+  char* b_hi = y_lo + nlo * fb;
+  char* y_hi = b_hi + nhi * fb;
+  for (int j = 0; j < nlo; ++j)
+    OVS_HIP(hipMemcpyAsync(b_lo + j * fb, (const char*)b + lo[j] * fb, fb,
+                           hipMemcpyDeviceToDevice, l->stream));
+  for (int j = 0; j < nhi; ++j)
+    OVS_HIP(hipMemcpyAsync(b_hi + j * fb, (const char*)b + hi[j] * fb, fb,
+                           hipMemcpyDeviceToDevice, l->stream));
+  std::vector<double> tlo(nlo), thi(nhi);
+  for (int j = 0; j < nlo; ++j) tlo[j] = tol[lo[j]];
+  for (int j = 0; j < nhi; ++j) thi[j] = tol[hi[j]];
+  std::vector<ovs_rhs_info> ilo(nlo), ihi(nhi);
+  const ovs_status s_lo = sign_apply_impl(l->shadow64, defl, n_defl, b_lo, y_lo, nlo, k_max,
+                                          tlo.data(), method, flags, ilo.data());
+  if (s_lo < 0) return s_lo;
+  const ovs_status s_hi = sign_apply_impl(l, defl, n_defl, b_hi, y_hi, nhi, k_max, thi.data(),
+                                          method, flags, ihi.data());
+  if (s_hi < 0) return s_hi;
+  for (int j = 0; j < nlo; ++j)
+    OVS_HIP(hipMemcpyAsync((char*)y + lo[j] * fb, y_lo + j * fb, fb, hipMemcpyDeviceToDevice,
+                           l->stream));
+  for (int j = 0; j < nhi; ++j)
+    OVS_HIP(hipMemcpyAsync((char*)y + hi[j] * fb, y_hi + j * fb, fb, hipMemcpyDeviceToDevice,
+                           l->stream));
+  OVS_HIP(hipStreamSynchronize(l->stream));
+  if (info) {
+    for (int j = 0; j < nlo; ++j) info[lo[j]] = ilo[j];
+    for (int j = 0; j < nhi; ++j) info[hi[j]] = ihi[j];
+  }
+  return std::max(s_lo, s_hi);
 }
 
 ovs_status ovs_last_coefficients(ovs_lattice l, double* alpha, double* beta, double* gamma,

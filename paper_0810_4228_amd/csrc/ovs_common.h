@@ -86,6 +86,12 @@ struct ovs_lattice_s {
   // results of the last sign_apply (host copies) for diagnostics
   std::vector<double> last_alpha, last_beta, last_gamma, last_x;
   int last_nrhs = 0, last_kmax = 0;
+  // FP64 handle for sources whose tolerance is below the FP32 storage floor
+  // (FP32 lattices only): shares links64, the stream and the parameters.
+  ovs_lattice_s* shadow64 = nullptr;
+  ovs_lattice_s* parent = nullptr;   // set on a shadow: the handle it serves
+  void* split_buf = nullptr;         // gathered sources / results of the split
+  size_t split_bytes = 0;
 };
 
 struct ovs_field_s {

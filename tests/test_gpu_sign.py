@@ -110,13 +110,40 @@ def test_matches_cpu_lanczos_step_by_step():
         assert rel(y.cpu().numpy()[0], yr) < 1e-10
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5)])
-def test_dual_variants_match_cpu(prec, tol):
+def test_mixed_tolerance_fp64_group(cfg1):
+    """FP32-storage lattice, tolerances 1e-5 and 1e-9 alternating, m = 20: the
+    1e-9 sources run as an FP64 group and reach the exact sign (stored 4^4
+    spectral result; sources are multiples c b of the stored source, so
+    sgn(A) c b = c y) far below the FP32 floor.  They equal an FP64 lattice's
+    result on the same sub-batch bit for bit."""
+    dims, U, b1, f = cfg1
+    mu = float(f["mu"])
+    c = np.array([1.0, 0.5j, -2.0, 1.0 + 1.0j])
+    b = c[:, None] * b1[0][None, :]
+    ref = c[:, None] * f["y"][None, :]
+    tol = [1e-5, 1e-9, 1e-5, 1e-9]
+    lat = lattice(dims, "f32", U, mu)
+    d = lat.deflation_set(f["lam"], to_dev(f["R"].T), to_dev(f["L"].T))
+    y, info, st = lat.sign_apply(to_dev(b), 1000, defl=d, tol=tol)
+    y = y.cpu().numpy()
+    errs = [rel(y[r], ref[r]) for r in range(4)]
+    say("mixed tolerances: errors", errs, "k", [i["k_used"] for i in info])
+    assert errs[1] <= 1e-8 and errs[3] <= 1e-8
+    assert errs[0] <= 1e-4 and errs[2] <= 1e-4
+    lat64 = lattice(dims, "f64", U, mu)
+    d64 = lat64.deflation_set(f["lam"], to_dev(f["R"].T), to_dev(f["L"].T))
+    y64, _, _ = lat64.sign_apply(to_dev(b[[1, 3]]), 1000, defl=d64, tol=[1e-9, 1e-9])
+    assert np.array_equal(y[[1, 3]], y64.cpu().numpy())
+
+
+@pytest.mark.parametrize("prec,tol,agree", [("f64", 1e-10, 1e-12), ("f32", 3e-5, 1e-6)])
+def test_dual_variants_match_cpu(prec, tol, agree):
     """Every dual-stencil configuration the autotuner can pick (one thread for
     both operators or a lane pair, source blocks 1..4, block order, streaming
     stores) gives the CPU oracle's two-sided Lanczos result: a ragged lattice
     (V = 576, not a multiple of the 256-site tile) and 5 sources (ragged
-    source blocks)."""
+    source blocks).  FP32 storage at this unconverged k sits ~8e-6 from the
+    FP64 oracle; the variants agree with each other to rounding."""
     dims = (4, 4, 6, 6)
     U = synth.random_links(dims, 0.5, seed=81)
     mu = 0.35
@@ -127,6 +154,7 @@ def test_dual_variants_match_cpu(prec, tol):
     lat = lattice(dims, prec, U, mu)
     base = lat.get_tuning_raw(5)
     blocks = (1, 2, 3, 4) if prec == "f32" else (1, 2)
+    first = None
     for lanes in (1, 2):
         for blk in blocks:
             for order, nt in ((0, 0), (1, 1)):
@@ -137,9 +165,12 @@ def test_dual_variants_match_cpu(prec, tol):
                 cfg[7] = order
                 lat.set_tuning_raw(5, cfg)
                 y, info, st = lat.sign_apply(to_dev(b), k)
-                e = rel_rows(y.cpu().numpy(), ref)
+                yh = y.cpu().numpy()
+                e = rel_rows(yh, ref)
+                first = yh if first is None else first
                 say("dual", prec, "lanes", lanes, "block", blk, "order", order, "nt", nt, f"{e:.2e}")
                 assert e <= tol
+                assert rel_rows(yh, first) <= agree
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5)])
