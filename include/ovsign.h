@@ -66,6 +66,9 @@ enum {
   OVS_FLAG_GRAPH    = 4,  /* replay the Lanczos iterations as captured HIP graphs             */
   OVS_FLAG_OVERLAP  = 8   /* return D_ov b = b + gamma5 sgn(A) b instead of sgn(A) b         */
 };
+enum {
+  OVS_VJP_STORE_BASIS = 1 /* ovs_sign_apply_vjp: keep both bases instead of recomputing them */
+};
 
 typedef struct ovs_lattice_s* ovs_lattice;
 typedef struct ovs_deflation_s* ovs_deflation;
@@ -131,9 +134,10 @@ ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int
 /* Full tuned configuration for nrhs sources, host int32 [8]:
  * {stencil shape = 100*rhs block + 10*lanes per site + streaming stores,
  *  stencil workgroup size, stencil LDS cap KiB, stencil block order,
- *  Lanczos dual-stencil shape = 100*rhs block + 10*lanes per site + streaming stores
- *  (lanes per site 1: one thread computes A v and A^dag w; 2: a lane pair splits
- *  the two operators), its workgroup size, its LDS cap KiB, its block order}. */
+ *  Lanczos dual-stencil shape = 100*rhs block + 10*variant + streaming stores
+ *  (variant 1: one thread computes A v and A^dag w; 2: a lane pair splits the two
+ *  operators; 3: as 2 with the tile's spinors staged in LDS, rhs block <= 2 in
+ *  FP32, 1 in FP64), its workgroup size, its LDS cap KiB, its block order}. */
 ovs_status ovs_get_tuning_ex(ovs_lattice lat, int32_t nrhs, int32_t out[8]);
 /* Install a configuration in the encoding of ovs_get_tuning_ex (e.g. one saved
  * from an earlier ovs_autotune).  OVS_ERR_ARG for values the kernels do not
@@ -192,21 +196,26 @@ ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, c
  *   b, chi   : device complex128 [nrhs][V][4][3] (canonical layout).
  *   k        : Krylov size, 1 <= k <= 65535; every source must complete k
  *              iterations.
+ *   flags    : 0: the Lanczos vectors are recomputed in the reverse sweep from
+ *              checkpoints every ceil(sqrt k) steps (bitwise the forward ones);
+ *              OVS_VJP_STORE_BASIS: both bases are kept instead (no replay,
+ *              2k fields per source).
  *   y        : device complex128 [nrhs][V][4][3], or NULL: the forward result.
  *   grad_b   : device complex128 [nrhs][V][4][3].
  *   grad_mu  : host double [1], summed over sources.
  *   grad_U   : device complex128 [V][4][3][3] (link layout), summed over sources.
  *   quad_err : host double [nrhs], or NULL: relative change of the quadrature
  *              (x and the Jacobian band) between its last two step sizes.
- * Needs an OVS_F64 lattice (OVS_ERR_ARG otherwise) and about (2k + 16) nrhs
- * FP64 fields of workspace, kept in the handle's cache (OVS_ERR_ALLOC if it
- * does not fit).  Returns OVS_WARN_BREAKDOWN, writing no output, when a
+ * Needs an OVS_F64 lattice (OVS_ERR_ARG otherwise) and FP64 workspace of about
+ * (4k/c + 2c + 22) nrhs fields with c = ceil(sqrt k), or (2k + 18) nrhs with
+ * OVS_VJP_STORE_BASIS, kept in the handle's cache (OVS_ERR_ALLOC if it does
+ * not fit).  Returns OVS_WARN_BREAKDOWN, writing no output, when a
  * source breaks down before k iterations; OVS_WARN_SIGN_AMBIGUOUS, with all
  * outputs written, when the quadrature changed by more than 1e-6 between its
  * two finest steps. */
 ovs_status ovs_sign_apply_vjp(ovs_lattice lat, const void* b, const void* chi, int32_t nrhs,
-                              int32_t k, void* y, void* grad_b, double* grad_mu, void* grad_U,
-                              double* quad_err);
+                              int32_t k, int32_t flags, void* y, void* grad_b, double* grad_mu,
+                              void* grad_U, double* quad_err);
 
 /* Krylov coefficients of the last ovs_sign_apply on this handle (2sL only):
  * alpha, gamma host complex128 [nrhs][k_max], beta host double [nrhs][k_max],

@@ -35,6 +35,7 @@ METHODS = {"2sl": 0, "arnoldi": 1}
 OVS_FLAG_TWO_PASS = 1
 OVS_FLAG_GRAPH = 4
 OVS_FLAG_OVERLAP = 8
+OVS_VJP_STORE_BASIS = 1
 
 EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
@@ -113,7 +114,7 @@ def load():
         "ovs_deflation_compute": [P, I, D, I, ctypes.POINTER(P)],
         "ovs_deflation_get": [P, DP, P, P, DP],
         "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
-        "ovs_sign_apply_vjp": [P, P, P, I, I, P, P, DP, P, DP],
+        "ovs_sign_apply_vjp": [P, P, P, I, I, I, P, P, DP, P, DP],
         "ovs_last_coefficients": [P, DP, DP, DP, DP],
         "ovs_inner_sign_tridiag": [P, I, I, DP, DP, DP, DP, DP],
         "ovs_inner_sign_hessenberg": [P, I, I, DP, DP, DP],
@@ -248,7 +249,9 @@ class Lattice:
         st.update(rhs_block=shape // 100, lanes_per_site=(shape // 10) % 10, streaming_store=shape % 10)
         du = dict(zip(keys, out[4:8]))
         shape = du["rhs_block"]
-        du.update(rhs_block=shape // 100, lanes_per_site=(shape // 10) % 10, streaming_store=shape % 10)
+        variants = {1: "one thread per site", 2: "lane pair", 3: "lane pair, LDS-staged tile"}
+        du.update(rhs_block=shape // 100, variant=variants.get((shape // 10) % 10, "?"),
+                  streaming_store=shape % 10)
         return {"stencil": st, "dual": du}
 
     def deflation_set(self, lam, R, L):
@@ -295,10 +298,11 @@ class Lattice:
         _check(st, "ovs_sign_apply")
         return y, [i.as_dict() for i in infos], st
 
-    def sign_apply_vjp(self, b, chi, k, want_y=True):
+    def sign_apply_vjp(self, b, chi, k, want_y=True, store_basis=False):
         """Gradient of L = sum_r Re <chi_r, y_r> for the k-step two-sided Lanczos
-        y_r ~ sgn(A) b_r without deflation (FP64 lattices).  Returns
-        (y or None, grad_b, grad_mu, grad_U [V,4,3,3], quad_err [nrhs], status)."""
+        y_r ~ sgn(A) b_r without deflation (FP64 lattices).  The reverse sweep
+        recomputes the Lanczos vectors from checkpoints unless store_basis.
+        Returns (y or None, grad_b, grad_mu, grad_U [V,4,3,3], quad_err [nrhs], status)."""
         torch = _torch()
         b, nrhs = self._fields(b)
         chi, n2 = self._fields(chi)
@@ -311,6 +315,7 @@ class Lattice:
         qerr = np.zeros(nrhs, dtype=np.float64)
         st = self._lib.ovs_sign_apply_vjp(
             self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(chi.data_ptr()), nrhs, int(k),
+            OVS_VJP_STORE_BASIS if store_basis else 0,
             ctypes.c_void_p(y.data_ptr()) if y is not None else None,
             ctypes.c_void_p(gb.data_ptr()), ctypes.byref(gmu), ctypes.c_void_p(gU.data_ptr()),
             _dptr(qerr))

@@ -437,7 +437,7 @@ ovs_status ovs_get_tuning_ex(ovs_lattice l, int32_t nrhs, int32_t out[8]) {
   if (!l || nrhs < 1 || !out) return OVS_ERR_ARG;
   const Tuning t = get_tuning(l, nrhs), d = get_dual_tuning(l, nrhs);
   out[0] = t.rhs_block * 100 + t.g * 10 + t.nt; out[1] = t.wg; out[2] = t.lds_kb; out[3] = t.order;
-  out[4] = d.rhs_block * 100 + d.g * 10 + d.nt; out[5] = 256 * d.g; out[6] = d.lds_kb;
+  out[4] = d.rhs_block * 100 + d.g * 10 + d.nt; out[5] = d.g == 1 ? 256 : 512; out[6] = d.lds_kb;
   out[7] = d.order;
   return OVS_OK;
 }
@@ -462,7 +462,8 @@ ovs_status ovs_set_tuning_ex(ovs_lattice l, int32_t nrhs, const int32_t cfg[8]) 
                           : (t.rhs_block >= 1 && t.rhs_block <= 3);
   const bool g_ok = t.g == 1 || ((t.g == 2 || t.g == 4 || t.g == 8) && t.rhs_block == 1);
   const bool wg_ok = t.wg == 64 || t.wg == 128 || t.wg == 256;
-  const bool d_ok = d.rhs_block >= 1 && d.rhs_block <= (f32 ? 4 : 2) && (d.g == 1 || d.g == 2);
+  const bool d_ok = d.rhs_block >= 1 && d.rhs_block <= (f32 ? 4 : 2) && d.g >= 1 && d.g <= 3 &&
+                    (d.g != 3 || d.rhs_block <= (f32 ? 2 : 1));
   if (!blk_ok || !g_ok || !wg_ok || !d_ok || t.nt < 0 || t.nt > 1 || d.nt < 0 || d.nt > 1 ||
       t.lds_kb < 0 || t.lds_kb >= l->lds_max_kb || d.lds_kb < 0 || d.lds_kb >= l->lds_max_kb ||
       t.order < 0 || t.order > 1 || d.order < 0 || d.order > 1)
@@ -551,7 +552,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
         const Hop hA = make_hop(l->m_w, l->mu), hAd = make_hop(l->m_w, -l->mu);
         Tuning dbest;
         double bms = 1e300;
-        for (int pair = 0; pair < 2; ++pair)
+        for (int pair = 0; pair < 3; ++pair)
         for (int bb = 1; bb <= (f32 ? 4 : 2); ++bb) {
           if (bb > nrhs && bb != 1) continue;
           for (int kb : lds_candidates(l))
@@ -584,7 +585,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
                 dbest.lds_kb = kb;
                 dbest.order = order;
                 dbest.nt = nt;
-                dbest.g = pair ? 2 : 1;
+                dbest.g = pair + 1;
               }
             }
         }
@@ -943,7 +944,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     const Tuning dt = get_dual_tuning(l, nr);
     const int dual_b = std::min(dt.rhs_block, f32 ? 4 : 2);
     DualArgs da{l->links, B.basis, B.wbuf, bstride, two_pass, B.ints, B.T, B.S, B.part1,
-                B.rhs_map, B.ints + 1, nr, dt.lds_kb, dt.order, dt.nt, dt.g == 2 ? 1 : 0};
+                B.rhs_map, B.ints + 1, nr, dt.lds_kb, dt.order, dt.nt, dt.g - 1};
     auto enqueue_iter = [&](bool full) -> ovs_status {
       OVS_HIP(launch_dual(f32, da, l->g, hA, hAd, dual_b, s));
       launch_alpha(B.part1, nwg_d, co, B.ints, B.rhs_map, B.ints + 1, nr, s);

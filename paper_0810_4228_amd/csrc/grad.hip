@@ -164,6 +164,7 @@ __global__ void k_gr_first(GradScalars s) {
   set_coef(s, kTabSV, 0, r, ab);                                           // tbar = abar w_i
   set_coef(s, kTabSW, 0, r, scale(s.nb[r], cconj(c64(s.x[rk + i]))));     // vbar = nb conj(x_i) chi
   set_coef(s, kTabWB, 0, r, cconj(ab));                                    // wbar = conj(abar) t_i
+  set_coef(s, kTabY, 0, r, scale(s.nb[r], c64(s.x[rk + i])));              // y += nb x_i v_i
 }
 
 // Step i < k-1, first half.  Inputs: dots of the completed vbar_{i+1}, wbar_{i+1}
@@ -238,6 +239,7 @@ __global__ void k_gr_s2(GradScalars s, int i, const double* part_v, const double
   set_coef(s, kTabWB, 2, r, scale(be, cab));
   set_coef(s, kTabWB, 3, r, cmul(cab, al));
   set_coef(s, kTabWB, 4, r, cmul(cab, gprev));
+  set_coef(s, kTabY, 0, r, scale(s.nb[r], c64(s.x[rk + i])));
 }
 
 // v_1 = w_1 = b/|b|: grad_b = ubar/|b| + nbar v_1 with ubar = vbar_1 + wbar_1 and
@@ -275,72 +277,41 @@ void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipSt
   hipLaunchKernelGGL(k_gr_final, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, part, nchunk);
 }
 
-// ---- basis dots and combination -------------------------------------------------
+// ---- source projections and replay coefficients -----------------------------
 
-constexpr int kBasisChunks = 32;
-
-__global__ void __launch_bounds__(kWG) k_basis_dots(const double2* basis, const double2* chi,
-                                                    long stride, int nrhs, double* partials) {
-  __shared__ double lds[(kWG / 64) * 2];
-  const int i = blockIdx.y, r = blockIdx.z;
-  const double2* v = basis + ((long)i * nrhs + r) * stride;
-  const double2* c = chi + (long)r * stride;
-  double part[2] = {0.0, 0.0};
-  for (long e = (long)blockIdx.x * kWG + threadIdx.x; e < stride; e += (long)gridDim.x * kWG) {
-    const Cx<double> p = cmulc(c64(v[e]), c64(c[e]));
-    part[0] += p.re;
-    part[1] += p.im;
-  }
-  block_sum<2>(part, lds);
-  if (threadIdx.x == 0) {
-    double* dst = partials + (((long)r * gridDim.y + i) * gridDim.x + blockIdx.x) * 2;
-    dst[0] = part[0];
-    dst[1] = part[1];
-  }
+__global__ void k_gf_xbar(GradScalars s, int i, const double* part, int nchunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const Cx<double> d = dot_sum(part, r, 0, nchunk);  // chi^dagger v_i
+  s.xbar[(long)r * s.kmax + i] = d2(scale(s.nb[r], cconj(d)));
 }
 
-__global__ void k_basis_dots_final(GradScalars s, const double* partials) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)s.nrhs * s.kmax) return;
-  const double* p = partials + t * kBasisChunks * 2;
-  Cx<double> acc = {0.0, 0.0};
-#pragma unroll 1
-  for (int c = 0; c < kBasisChunks; ++c) {
-    acc.re += p[2 * c];
-    acc.im += p[2 * c + 1];
-  }
-  const int r = (int)(t / s.kmax);
-  s.xbar[t] = d2(scale(s.nb[r], acc));
+void launch_gf_xbar(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gf_xbar, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part, nchunk);
 }
 
-void launch_basis_dots(const double2* basis, const double2* chi, long stride, int kmax, int nrhs,
-                       double* partials, const GradScalars& s, hipStream_t st) {
-  hipLaunchKernelGGL(k_basis_dots, dim3(kBasisChunks, kmax, nrhs), dim3(kWG), 0, st, basis, chi,
-                     stride, nrhs, partials);
-  const long n = (long)nrhs * kmax;
-  hipLaunchKernelGGL(k_basis_dots_final, dim3((int)((n + 255) / 256)), dim3(256), 0, st, s,
-                     partials);
+__global__ void k_gp_coef(GradScalars s, int i) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  const long rk = (long)r * s.kmax;
+  const Cx<double> al = c64(s.alpha[rk + i]);
+  const Cx<double> gprev = (i > 0) ? c64(s.gamma[rk + i - 1]) : Cx<double>{0.0, 0.0};
+  const double bprev = (i > 0) ? s.beta[rk + i - 1] : 0.0;
+  set_coef(s, kTabV, 0, r, {1.0, 0.0});
+  set_coef(s, kTabV, 1, r, -al);
+  set_coef(s, kTabV, 2, r, -gprev);
+  set_coef(s, kTabW, 0, r, {1.0, 0.0});
+  set_coef(s, kTabW, 1, r, -cconj(al));
+  set_coef(s, kTabW, 2, r, {-bprev, 0.0});
+  const double vn = s.beta[rk + i];
+  const Cx<double> g = c64(s.gamma[rk + i]);
+  set_coef(s, kTabSV, 0, r, {vn > 0.0 ? 1.0 / vn : 0.0, 0.0});
+  const bool gz = g.re == 0.0 && g.im == 0.0;
+  set_coef(s, kTabSW, 0, r, gz ? Cx<double>{0.0, 0.0} : cdiv({1.0, 0.0}, cconj(g)));
 }
 
-__global__ void k_gcombine(const double2* basis, long stride, int kmax, int nrhs, GradScalars s,
-                           double2* y) {
-  const int r = blockIdx.y;
-  const long rk = (long)r * kmax;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < stride;
-       e += (long)gridDim.x * blockDim.x) {
-    Cx<double> acc = {0.0, 0.0};
-    for (int i = 0; i < kmax; ++i)
-      acc = cfma(c64(s.x[rk + i]), c64(basis[((long)i * nrhs + r) * stride + e]), acc);
-    y[(long)r * stride + e] = d2(scale(s.nb[r], acc));
-  }
-}
-
-void launch_gcombine(const double2* basis, long stride, int kmax, int nrhs, const GradScalars& s,
-                     double2* y, hipStream_t st) {
-  long b = (stride + kWG - 1) / kWG;
-  if (b > 2048) b = 2048;
-  hipLaunchKernelGGL(k_gcombine, dim3((int)b, nrhs), dim3(kWG), 0, st, basis, stride, kmax, nrhs,
-                     s, y);
+void launch_gp_coef(const GradScalars& s, int i, hipStream_t st) {
+  hipLaunchKernelGGL(k_gp_coef, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i);
 }
 
 // ---- inner sign and its vector-Jacobian product -----------------------------------

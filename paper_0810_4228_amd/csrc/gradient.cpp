@@ -3,13 +3,19 @@
 // no deflation) with respect to the sources b, the chemical potential mu and
 // the links U.
 //
-// Forward: the recurrences (4.1)-(4.4) with FP64 bases V, W kept in HBM
-// (2 k nrhs fields; 288 GB holds k = 1000 at 16^3 x 32 for several sources,
-// so nothing is recomputed).  Inner sign: sgn(G_k) e_1 and its vector-Jacobian
-// product from the same tau = e^u trapezoid rule, step h halved until two
-// levels agree.  Reverse sweep: per iteration two linear-combination passes
-// with fused dots, two scalar steps, the stencil adjoints A^dagger tbar and
-// A sbar, and the link-force accumulation (grad.hip).
+// Forward: the recurrences (4.1)-(4.4) in FP64.  By default only checkpoints
+// are kept: the pairs (v_{jc-1}, v_{jc}), (w_{jc-1}, w_{jc}) every c = ceil(sqrt k)
+// steps; the reverse sweep replays each segment forward from its checkpoint
+// with the stored coefficients (the same kernels and coefficient arithmetic as
+// the forward pass, so the replayed vectors are bitwise those of the forward)
+// and then walks it backwards.  Memory: about 4k/c + 2c + 18 fields per
+// source instead of 2k + 18; cost: one more forward pass.  With
+// OVS_VJP_STORE_BASIS both bases are kept instead.
+// Inner sign: sgn(G_k) e_1 and its vector-Jacobian product from the same
+// tau = e^u trapezoid rule, step h halved until two levels agree.  Reverse
+// sweep: per iteration linear-combination passes with fused dots, two scalar
+// steps, the stencil adjoints A^dagger tbar and A sbar, and the link-force
+// accumulation (grad.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,78 +51,93 @@ double max_rel_change(const std::vector<double2>& a, const std::vector<double2>&
 }  // namespace
 
 extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const void* chi,
-                                         int32_t nrhs, int32_t k, void* y, void* grad_b,
-                                         double* grad_mu, void* grad_U, double* quad_err) {
+                                         int32_t nrhs, int32_t k, int32_t flags, void* y,
+                                         void* grad_b, double* grad_mu, void* grad_U,
+                                         double* quad_err) {
   if (!l || !b || !chi || !grad_b || !grad_mu || !grad_U) return OVS_ERR_ARG;
   if (nrhs < 1 || nrhs > kMaxNrhs || k < 1 || k > 65535) return OVS_ERR_ARG;
-  if (l->prec != OVS_F64) return OVS_ERR_ARG;
+  if (flags & ~OVS_VJP_STORE_BASIS) return OVS_ERR_ARG;
+  if (l->prec != OVS_F64 || l->parent) return OVS_ERR_ARG;
   if (!ready(l)) return OVS_ERR_STATE;
+  const bool store = (flags & OVS_VJP_STORE_BASIS) != 0;
   const Geometry& g = l->g;
   const long F = 12L * g.Vs;        // elements of one source field
   const long NF = (long)nrhs * F;   // elements of one batch of fields
   const int nch = lin_nchunk(F);
+  const int cseg = store ? k : std::max(1, (int)std::ceil(std::sqrt((double)k)));
+  const int nseg = (k + cseg - 1) / cseg;
   int n0max, nnmax;
   vjp_range(kVjpHMin, n0max, nnmax);
+  constexpr int kFields = 18;
 
   // ---- workspace ----
-  auto carve = [&](Arena& a, double2*& V, double2*& W, double2** fld, GradScalars& s,
-                   double2*& Fg, double*& parts, double*& bparts, double*& fparts, double*& gmu,
-                   void*& vjp, IsignVjpOut (&vo)[2]) {
-    V = a.take<double2>((size_t)k * NF);
-    W = a.take<double2>((size_t)k * NF);
-    for (int j = 0; j < 16; ++j) fld[j] = a.take<double2>(NF);
-    Fg = a.take<double2>(5L * 9 * g.Vs);
+  struct Ptrs {
+    double2 *V, *W, *ckV, *ckW, *fld[kFields], *Fg;
+    double *parts, *fparts, *gmu;
+    void* vjp;
+    IsignVjpOut vo[2];
+  } P_{};
+  GradScalars S{};
+  auto carve = [&](Arena& a) {
+    if (store) {
+      P_.V = a.take<double2>((size_t)k * NF);
+      P_.W = a.take<double2>((size_t)k * NF);
+    } else {
+      P_.V = a.take<double2>((size_t)(cseg + 2) * NF);   // segment buffer (forward ring)
+      P_.W = a.take<double2>((size_t)(cseg + 2) * NF);
+      P_.ckV = a.take<double2>((size_t)2 * nseg * NF);
+      P_.ckW = a.take<double2>((size_t)2 * nseg * NF);
+    }
+    for (int j = 0; j < kFields; ++j) P_.fld[j] = a.take<double2>(NF);
+    P_.Fg = a.take<double2>(5L * 9 * g.Vs);
     const size_t nk = (size_t)nrhs * k;
-    s.alpha = a.take<double2>(nk);
-    s.beta = a.take<double>(nk);
-    s.gamma = a.take<double2>(nk);
-    s.tnorm2 = a.take<double>(nk);
-    s.x = a.take<double2>(nk);
-    s.xbar = a.take<double2>(nk);
-    s.abar = a.take<double2>(nk);
-    s.bbar = a.take<double>(nk);
-    s.gbar = a.take<double2>(nk);
-    s.nb = a.take<double>(nrhs);
-    s.status = a.take<int>(nrhs);
-    s.coef = a.take<double2>((size_t)kCoefTables * kLinTerms * nrhs);
-    s.kmax = k;
-    s.nrhs = nrhs;
-    parts = a.take<double>((size_t)4 * nrhs * nch * 2 * kLinDots);
-    bparts = a.take<double>((size_t)nrhs * k * 32 * 2);
-    fparts = a.take<double>((size_t)(g.V + kWG - 1) / kWG + 1);
-    gmu = a.take<double>(1);
-    vjp = a.take<char>(isign_vjp_scratch_bytes(k, nnmax));
+    S.alpha = a.take<double2>(nk);
+    S.beta = a.take<double>(nk);
+    S.gamma = a.take<double2>(nk);
+    S.tnorm2 = a.take<double>(nk);
+    S.x = a.take<double2>(nk);
+    S.xbar = a.take<double2>(nk);
+    S.abar = a.take<double2>(nk);
+    S.bbar = a.take<double>(nk);
+    S.gbar = a.take<double2>(nk);
+    S.nb = a.take<double>(nrhs);
+    S.status = a.take<int>(nrhs);
+    S.coef = a.take<double2>((size_t)kCoefTables * kLinTerms * nrhs);
+    S.kmax = k;
+    S.nrhs = nrhs;
+    P_.parts = a.take<double>((size_t)4 * nrhs * nch * 2 * kLinDots);
+    P_.fparts = a.take<double>((size_t)(g.V + kWG - 1) / kWG + 1);
+    P_.gmu = a.take<double>(1);
+    P_.vjp = a.take<char>(isign_vjp_scratch_bytes(k, nnmax));
     for (int lv = 0; lv < 2; ++lv) {
-      vo[lv].x = a.take<double2>(k);
-      vo[lv].gd = a.take<double2>(k);
-      vo[lv].gsub_re = a.take<double>(k);
-      vo[lv].gsup = a.take<double2>(k);
+      P_.vo[lv].x = a.take<double2>(k);
+      P_.vo[lv].gd = a.take<double2>(k);
+      P_.vo[lv].gsub_re = a.take<double>(k);
+      P_.vo[lv].gsup = a.take<double2>(k);
     }
   };
-  double2 *V, *W, *fld[16], *Fg;
-  GradScalars S;
-  double *parts, *bparts, *fparts, *gmu_dev;
-  void* vjp;
-  IsignVjpOut vo[2];
   Arena sizing{nullptr};
-  carve(sizing, V, W, fld, S, Fg, parts, bparts, fparts, gmu_dev, vjp, vo);
+  carve(sizing);
   ovs_status st = ensure_ws(l, sizing.off + 256);
   if (st != OVS_OK) return st;
   StreamScope scope(l);
-  Arena a{(char*)l->ws};
-  carve(a, V, W, fld, S, Fg, parts, bparts, fparts, gmu_dev, vjp, vo);
+  Arena arena{(char*)l->ws};
+  carve(arena);
+  double2** fld = P_.fld;
   double2 *B = fld[0], *CHI = fld[1], *T = fld[2], *Sv = fld[3];
   double2* VB[2] = {fld[4], fld[5]};
   double2* WB[2] = {fld[6], fld[7]};
   double2* VTB[2] = {fld[8], fld[9]};
   double2* WTB[2] = {fld[10], fld[11]};
-  double2 *TB = fld[12], *T1 = fld[13], *T2 = fld[14], *GB = fld[15];
+  double2 *TB = fld[12], *T1 = fld[13], *T2 = fld[14], *GB = fld[15], *TL = fld[16],
+          *YA = fld[17];
   double* P[4];
-  for (int j = 0; j < 4; ++j) P[j] = parts + (size_t)j * nrhs * nch * 2 * kLinDots;
+  for (int j = 0; j < 4; ++j) P[j] = P_.parts + (size_t)j * nrhs * nch * 2 * kLinDots;
 
   // every field starts at zero (pads stay zero: the stencil writes sites < V only)
-  OVS_HIP(hipMemsetAsync(V, 0, (size_t)((char*)(fld[15] + NF) - (char*)V), l->stream));
-  OVS_HIP(hipMemsetAsync(Fg, 0, sizeof(double2) * 5 * 9 * g.Vs, l->stream));
+  OVS_HIP(hipMemsetAsync(P_.V, 0, (size_t)((char*)(fld[kFields - 1] + NF) - (char*)P_.V),
+                         l->stream));
+  OVS_HIP(hipMemsetAsync(P_.Fg, 0, sizeof(double2) * 5 * 9 * g.Vs, l->stream));
   {
     std::vector<double2> ones((size_t)kLinTerms * nrhs, make_double2(1.0, 0.0));
     OVS_HIP(hipMemcpyAsync(coef_table(S, kTabOne), ones.data(), sizeof(double2) * ones.size(),
@@ -134,8 +155,6 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
   auto applyAd = [&](const double2* in, double2* out) {
     return launch_wilson(false, l->links, in, out, nrhs, g, hAd, false, true, tn, l->stream);
   };
-  auto Vi = [&](int i) { return V + (size_t)i * NF; };
-  auto Wi = [&](int i) { return W + (size_t)i * NF; };
   auto lin = [&](std::initializer_list<const double2*> xs, int tab, double2* out, bool acc,
                  std::initializer_list<const double2*> ys, int ndot, double* part) {
     LinArgs la;
@@ -154,29 +173,54 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
     la.partials = part;
     launch_lin(la, F, nrhs, l->stream);
   };
+  auto copy = [&](double2* dst, const double2* src) {
+    return hipMemcpyAsync(dst, src, sizeof(double2) * NF, hipMemcpyDeviceToDevice, l->stream);
+  };
+  // forward access: the whole basis, or a ring of three in the segment buffer
+  auto Vf = [&](int i) { return store ? P_.V + (size_t)i * NF : P_.V + (size_t)(i % 3) * NF; };
+  auto Wf = [&](int i) { return store ? P_.W + (size_t)i * NF : P_.W + (size_t)(i % 3) * NF; };
+  // reverse access: the whole basis, or the current segment (indices base .. base + cseg + 1)
+  int base = -1;
+  auto Vr = [&](int i) { return store ? P_.V + (size_t)i * NF : P_.V + (size_t)(i - base) * NF; };
+  auto Wr = [&](int i) { return store ? P_.W + (size_t)i * NF : P_.W + (size_t)(i - base) * NF; };
+  // checkpoint j holds (v_{jc-1}, v_{jc}) and (w_{jc-1}, w_{jc}); v_{-1} = w_{-1} = 0
+  auto save_ckpt = [&](int m) -> hipError_t {
+    if (store || m % cseg) return hipSuccess;
+    const int j = m / cseg;
+    hipError_t e = copy(P_.ckV + (size_t)(2 * j + 1) * NF, Vf(m));
+    if (e == hipSuccess) e = copy(P_.ckW + (size_t)(2 * j + 1) * NF, Wf(m));
+    if (m > 0 && e == hipSuccess) e = copy(P_.ckV + (size_t)(2 * j) * NF, Vf(m - 1));
+    if (m > 0 && e == hipSuccess) e = copy(P_.ckW + (size_t)(2 * j) * NF, Wf(m - 1));
+    return e;
+  };
 
   // ---- forward: v_1 = w_1 = b/|b|, then the recurrences ----
   lin({B}, kTabOne, nullptr, false, {nullptr}, 1, P[0]);
   launch_gf_norm(S, P[0], nch, l->stream);
-  lin({B}, kTabNorm, Vi(0), false, {}, 0, nullptr);
-  lin({B}, kTabNorm, Wi(0), false, {}, 0, nullptr);
+  lin({B}, kTabNorm, Vf(0), false, {CHI}, 1, P[3]);
+  launch_gf_xbar(S, 0, P[3], nch, l->stream);
+  lin({B}, kTabNorm, Wf(0), false, {}, 0, nullptr);
+  OVS_HIP(save_ckpt(0));
   for (int i = 0; i < k; ++i) {
-    OVS_HIP(applyA(Vi(i), T));
-    lin({T}, kTabOne, nullptr, false, {Wi(i), nullptr}, 2, P[0]);
+    OVS_HIP(applyA(Vf(i), T));
+    lin({T}, kTabOne, nullptr, false, {Wf(i), nullptr}, 2, P[0]);
     launch_gf_alpha(S, i, P[0], nch, l->stream);
-    if (i == k - 1) break;  // T keeps t_k = A v_k
-    OVS_HIP(applyAd(Wi(i), Sv));
+    if (i == k - 1) break;
+    OVS_HIP(applyAd(Wf(i), Sv));
     if (i > 0) {
-      lin({T, Vi(i), Vi(i - 1)}, kTabV, Vi(i + 1), false, {nullptr}, 1, P[1]);
-      lin({Sv, Wi(i), Wi(i - 1)}, kTabW, Wi(i + 1), false, {Vi(i + 1), nullptr}, 2, P[2]);
+      lin({T, Vf(i), Vf(i - 1)}, kTabV, Vf(i + 1), false, {nullptr}, 1, P[1]);
+      lin({Sv, Wf(i), Wf(i - 1)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2, P[2]);
     } else {
-      lin({T, Vi(i)}, kTabV, Vi(i + 1), false, {nullptr}, 1, P[1]);
-      lin({Sv, Wi(i)}, kTabW, Wi(i + 1), false, {Vi(i + 1), nullptr}, 2, P[2]);
+      lin({T, Vf(i)}, kTabV, Vf(i + 1), false, {nullptr}, 1, P[1]);
+      lin({Sv, Wf(i)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2, P[2]);
     }
     launch_gf_beta(S, i, P[1], P[2], nch, l->stream);
-    lin({Vi(i + 1)}, kTabSV, Vi(i + 1), false, {}, 0, nullptr);
-    lin({Wi(i + 1)}, kTabSW, Wi(i + 1), false, {}, 0, nullptr);
+    lin({Vf(i + 1)}, kTabSV, Vf(i + 1), false, {CHI}, 1, P[3]);
+    launch_gf_xbar(S, i + 1, P[3], nch, l->stream);
+    lin({Wf(i + 1)}, kTabSW, Wf(i + 1), false, {}, 0, nullptr);
+    OVS_HIP(save_ckpt(i + 1));
   }
+  OVS_HIP(copy(TL, T));  // t_k = A v_k, needed by the first reverse step
   OVS_HIP(hipGetLastError());
   std::vector<int> status(nrhs);
   OVS_HIP(hipMemcpyAsync(status.data(), S.status, sizeof(int) * nrhs, hipMemcpyDeviceToHost,
@@ -185,8 +229,7 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
   for (int r = 0; r < nrhs; ++r)
     if (status[r] != 0) return OVS_WARN_BREAKDOWN;  // the gradient needs k full iterations
 
-  // ---- xbar_i = |b| v_i^dagger chi; inner sign and its VJP ----
-  launch_basis_dots(V, CHI, F, k, nrhs, bparts, S, l->stream);
+  // ---- inner sign and its VJP ----
   ovs_status result = OVS_OK;
   for (int r = 0; r < nrhs; ++r) {
     const size_t rk = (size_t)r * k;
@@ -196,16 +239,16 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
     for (;; h *= 0.5, lv ^= 1) {
       int n0, nn;
       vjp_range(h, n0, nn);
-      launch_isign_vjp(S.alpha + rk, S.beta + rk, S.gamma + rk, S.xbar + rk, k, h, n0, nn, vjp,
-                       vo[lv], l->stream);
+      launch_isign_vjp(S.alpha + rk, S.beta + rk, S.gamma + rk, S.xbar + rk, k, h, n0, nn,
+                       P_.vjp, P_.vo[lv], l->stream);
       OVS_HIP(hipGetLastError());
       cur.assign((size_t)3 * k, make_double2(0.0, 0.0));
-      OVS_HIP(hipMemcpyAsync(cur.data(), vo[lv].x, sizeof(double2) * k, hipMemcpyDeviceToHost,
-                             l->stream));
-      OVS_HIP(hipMemcpyAsync(cur.data() + k, vo[lv].gd, sizeof(double2) * k,
+      OVS_HIP(hipMemcpyAsync(cur.data(), P_.vo[lv].x, sizeof(double2) * k,
+                             hipMemcpyDeviceToHost, l->stream));
+      OVS_HIP(hipMemcpyAsync(cur.data() + k, P_.vo[lv].gd, sizeof(double2) * k,
                              hipMemcpyDeviceToHost, l->stream));
       if (k > 1)
-        OVS_HIP(hipMemcpyAsync(cur.data() + 2 * k, vo[lv].gsup, sizeof(double2) * (k - 1),
+        OVS_HIP(hipMemcpyAsync(cur.data() + 2 * k, P_.vo[lv].gsup, sizeof(double2) * (k - 1),
                                hipMemcpyDeviceToHost, l->stream));
       OVS_HIP(hipStreamSynchronize(l->stream));
       used = lv;
@@ -218,65 +261,92 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
     }
     if (quad_err) quad_err[r] = change;
     if (change > 1e-6) result = OVS_WARN_SIGN_AMBIGUOUS;
-    OVS_HIP(hipMemcpyAsync(S.x + rk, vo[used].x, sizeof(double2) * k, hipMemcpyDeviceToDevice,
+    const IsignVjpOut& o = P_.vo[used];
+    OVS_HIP(hipMemcpyAsync(S.x + rk, o.x, sizeof(double2) * k, hipMemcpyDeviceToDevice,
                            l->stream));
-    OVS_HIP(hipMemcpyAsync(S.abar + rk, vo[used].gd, sizeof(double2) * k,
-                           hipMemcpyDeviceToDevice, l->stream));
+    OVS_HIP(hipMemcpyAsync(S.abar + rk, o.gd, sizeof(double2) * k, hipMemcpyDeviceToDevice,
+                           l->stream));
     if (k > 1) {
-      OVS_HIP(hipMemcpyAsync(S.bbar + rk, vo[used].gsub_re, sizeof(double) * (k - 1),
+      OVS_HIP(hipMemcpyAsync(S.bbar + rk, o.gsub_re, sizeof(double) * (k - 1),
                              hipMemcpyDeviceToDevice, l->stream));
-      OVS_HIP(hipMemcpyAsync(S.gbar + rk, vo[used].gsup, sizeof(double2) * (k - 1),
+      OVS_HIP(hipMemcpyAsync(S.gbar + rk, o.gsup, sizeof(double2) * (k - 1),
                              hipMemcpyDeviceToDevice, l->stream));
     }
   }
 
-  // ---- reverse sweep ----
-  {
-    const int i = k - 1, c = i & 1;
-    launch_gr_first(S, l->stream);
-    lin({Wi(i)}, kTabSV, TB, false, {}, 0, nullptr);                      // tbar
-    lin({CHI}, kTabSW, VB[c], false, {}, 0, nullptr);                     // vbar (direct part)
-    lin({T}, kTabWB, WB[c], false, {Wi(i)}, 1, P[3]);                     // wbar, complete
-    OVS_HIP(applyAd(TB, T1));
-    lin({T1}, kTabOne, VB[c], true, {Vi(i)}, 1, P[2]);                    // vbar += A^dag tbar
-    launch_gforce(Fg, TB, Vi(i), nullptr, nullptr, F, nrhs, g, hA, hAd, l->stream);
-  }
-  for (int i = k - 2; i >= 0; --i) {
-    const int c = i & 1, p = (i + 1) & 1;
-    launch_gr_s1(S, i, P[2], P[3], nch, l->stream);
-    if (i > 0) {
-      lin({VB[p], Vi(i + 1), Wi(i + 1)}, kTabV, VTB[c], false, {Vi(i), Vi(i - 1)}, 2, P[0]);
-      lin({WB[p], Vi(i + 1)}, kTabW, WTB[c], false, {Wi(i), Wi(i - 1)}, 2, P[1]);
-    } else {
-      lin({VB[p], Vi(i + 1), Wi(i + 1)}, kTabV, VTB[c], false, {Vi(i)}, 1, P[0]);
-      lin({WB[p], Vi(i + 1)}, kTabW, WTB[c], false, {Wi(i)}, 1, P[1]);
+  // ---- reverse sweep, segment by segment from the last ----
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int lo = j * cseg, hi = std::min((j + 1) * cseg, k) - 1;
+    if (!store) {
+      // replay v_{lo+1} .. v_{top} from the checkpoint, as in the forward pass
+      base = lo - 1;
+      const int top = std::min((j + 1) * cseg, k - 1);
+      OVS_HIP(copy(Vr(lo - 1), P_.ckV + (size_t)(2 * j) * NF));
+      OVS_HIP(copy(Vr(lo), P_.ckV + (size_t)(2 * j + 1) * NF));
+      OVS_HIP(copy(Wr(lo - 1), P_.ckW + (size_t)(2 * j) * NF));
+      OVS_HIP(copy(Wr(lo), P_.ckW + (size_t)(2 * j + 1) * NF));
+      for (int i = lo; i < top; ++i) {
+        launch_gp_coef(S, i, l->stream);
+        OVS_HIP(applyA(Vr(i), T));
+        OVS_HIP(applyAd(Wr(i), Sv));
+        if (i > 0) {
+          lin({T, Vr(i), Vr(i - 1)}, kTabV, Vr(i + 1), false, {}, 0, nullptr);
+          lin({Sv, Wr(i), Wr(i - 1)}, kTabW, Wr(i + 1), false, {}, 0, nullptr);
+        } else {
+          lin({T, Vr(i)}, kTabV, Vr(i + 1), false, {}, 0, nullptr);
+          lin({Sv, Wr(i), }, kTabW, Wr(i + 1), false, {}, 0, nullptr);
+        }
+        lin({Vr(i + 1)}, kTabSV, Vr(i + 1), false, {}, 0, nullptr);
+        lin({Wr(i + 1)}, kTabSW, Wr(i + 1), false, {}, 0, nullptr);
+      }
     }
-    launch_gr_s2(S, i, P[0], P[1], nch, l->stream);
-    lin({VTB[c], Wi(i)}, kTabSV, TB, false, {}, 0, nullptr);
-    lin({CHI, VTB[p], VTB[c]}, kTabSW, VB[c], false, {}, 0, nullptr);
-    if (i > 0)
-      lin({WTB[p], WTB[c], Vi(i + 1), Vi(i), Vi(i - 1)}, kTabWB, WB[c], false, {}, 0, nullptr);
-    else
-      lin({WTB[p], WTB[c], Vi(i + 1), Vi(i)}, kTabWB, WB[c], false, {}, 0, nullptr);
-    OVS_HIP(applyAd(TB, T1));
-    OVS_HIP(applyA(WTB[c], T2));
-    lin({T1}, kTabOne, VB[c], true, {Vi(i)}, 1, P[2]);
-    lin({T2}, kTabOne, WB[c], true, {Wi(i)}, 1, P[3]);
-    launch_gforce(Fg, TB, Vi(i), WTB[c], Wi(i), F, nrhs, g, hA, hAd, l->stream);
+    for (int i = hi; i >= lo; --i) {
+      if (i == k - 1) {
+        const int c = i & 1;
+        launch_gr_first(S, l->stream);
+        lin({Wr(i)}, kTabSV, TB, false, {}, 0, nullptr);      // tbar
+        lin({CHI}, kTabSW, VB[c], false, {}, 0, nullptr);     // vbar (direct part)
+        lin({TL}, kTabWB, WB[c], false, {Wr(i)}, 1, P[3]);    // wbar, complete
+        if (y) lin({Vr(i)}, kTabY, YA, true, {}, 0, nullptr);
+        OVS_HIP(applyAd(TB, T1));
+        lin({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]);    // vbar += A^dag tbar
+        launch_gforce(P_.Fg, TB, Vr(i), nullptr, nullptr, F, nrhs, g, hA, hAd, l->stream);
+        continue;
+      }
+      const int c = i & 1, p = (i + 1) & 1;
+      launch_gr_s1(S, i, P[2], P[3], nch, l->stream);
+      if (i > 0) {
+        lin({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i), Vr(i - 1)}, 2, P[0]);
+        lin({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i), Wr(i - 1)}, 2, P[1]);
+      } else {
+        lin({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i)}, 1, P[0]);
+        lin({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i)}, 1, P[1]);
+      }
+      launch_gr_s2(S, i, P[0], P[1], nch, l->stream);
+      lin({VTB[c], Wr(i)}, kTabSV, TB, false, {}, 0, nullptr);
+      lin({CHI, VTB[p], VTB[c]}, kTabSW, VB[c], false, {}, 0, nullptr);
+      if (i > 0)
+        lin({WTB[p], WTB[c], Vr(i + 1), Vr(i), Vr(i - 1)}, kTabWB, WB[c], false, {}, 0, nullptr);
+      else
+        lin({WTB[p], WTB[c], Vr(i + 1), Vr(i)}, kTabWB, WB[c], false, {}, 0, nullptr);
+      if (y) lin({Vr(i)}, kTabY, YA, true, {}, 0, nullptr);
+      OVS_HIP(applyAd(TB, T1));
+      OVS_HIP(applyA(WTB[c], T2));
+      lin({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]);
+      lin({T2}, kTabOne, WB[c], true, {Wr(i)}, 1, P[3]);
+      launch_gforce(P_.Fg, TB, Vr(i), WTB[c], Wr(i), F, nrhs, g, hA, hAd, l->stream);
+    }
   }
-  // grad_b = ubar/|b| + nbar v_1,  ubar = vbar_1 + wbar_1
-  lin({VB[0], WB[0]}, kTabOne, T1, false, {Vi(0)}, 1, P[0]);
+  // grad_b = ubar/|b| + nbar v_1,  ubar = vbar_1 + wbar_1  (segment 0 holds v_1)
+  lin({VB[0], WB[0]}, kTabOne, T1, false, {Vr(0)}, 1, P[0]);
   launch_gr_final(S, P[0], nch, l->stream);
-  lin({T1, Vi(0)}, kTabFin, GB, false, {}, 0, nullptr);
+  lin({T1, Vr(0)}, kTabFin, GB, false, {}, 0, nullptr);
   launch_unpack_f64(GB, (double2*)grad_b, nrhs, g, l->stream);
-  launch_gforce_out(Fg, (const double2*)l->links, g, l->bc, (double2*)grad_U, fparts, gmu_dev,
-                    l->stream);
-  if (y) {
-    launch_gcombine(V, F, k, nrhs, S, T2, l->stream);
-    launch_unpack_f64(T2, (double2*)y, nrhs, g, l->stream);
-  }
+  launch_gforce_out(P_.Fg, (const double2*)l->links, g, l->bc, (double2*)grad_U, P_.fparts,
+                    P_.gmu, l->stream);
+  if (y) launch_unpack_f64(YA, (double2*)y, nrhs, g, l->stream);
   OVS_HIP(hipGetLastError());
-  OVS_HIP(hipMemcpyAsync(grad_mu, gmu_dev, sizeof(double), hipMemcpyDeviceToHost, l->stream));
+  OVS_HIP(hipMemcpyAsync(grad_mu, P_.gmu, sizeof(double), hipMemcpyDeviceToHost, l->stream));
   OVS_HIP(hipStreamSynchronize(l->stream));
   return result;
 }

@@ -47,7 +47,7 @@ struct GradScalars {
   int kmax;
   int nrhs;
 };
-constexpr int kCoefTables = 8;
+constexpr int kCoefTables = 9;
 // Coefficient tables (indices into GradScalars::coef).
 enum {
   kTabNorm = 0,  // forward: [1/|b|]
@@ -57,7 +57,8 @@ enum {
   kTabSW = 4,    // forward: [1/conj(gamma_i)];  reverse: vbar_i
   kTabWB = 5,    // reverse: wbar_i
   kTabOne = 6,   // [1, 1, 1, 1, 1]
-  kTabFin = 7    // reverse: grad_b = ubar/|b| + nbar v_1
+  kTabFin = 7,   // reverse: grad_b = ubar/|b| + nbar v_1
+  kTabY = 8      // reverse: y += |b| x_i v_i
 };
 inline double2* coef_table(const GradScalars& s, int t) {
   return s.coef + (long)t * kLinTerms * s.nrhs;
@@ -76,12 +77,12 @@ void launch_gr_s2(const GradScalars& s, int i, const double* part_v, const doubl
                   int nchunk, hipStream_t st);
 void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
 
-// xbar_i = nb * v_i^dagger chi for i < kmax (basis [kmax][nrhs][12][Vs]).
-void launch_basis_dots(const double2* basis, const double2* chi, long stride, int kmax, int nrhs,
-                       double* partials, const GradScalars& s, hipStream_t st);
-// y_r = nb_r * sum_i x_i v_i
-void launch_gcombine(const double2* basis, long stride, int kmax, int nrhs, const GradScalars& s,
-                     double2* y, hipStream_t st);
+// xbar_i = nb * conj(dot 0) for the dot chi^dagger v_i of the partials.
+void launch_gf_xbar(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st);
+// Replay of step i from the stored coefficients: the tables of the forward
+// update (kTabV, kTabW) and normalisation (kTabSV, kTabSW), with the same
+// arithmetic as k_gf_alpha / k_gf_beta, so replayed vectors are bitwise equal.
+void launch_gp_coef(const GradScalars& s, int i, hipStream_t st);
 
 // Inner sign and its vector-Jacobian product for one source by the tau = e^u
 // trapezoid rule at step h: x = (1/pi) int sum_+- (G +- i tau)^{-1} e_1 dtau and

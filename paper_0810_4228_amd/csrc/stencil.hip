@@ -511,7 +511,13 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
 // the registers of k_dual, twice the waves in flight.  Tiles are the same 256
 // sites, so the partial-sum layout is unchanged; the even lane also reads
 // W~ at its own site for W~^dagger T.
-template <typename R, int B>
+//
+// STAGE: the tile's own V~ and W~ spinors are first copied to LDS (one
+// coalesced load per component), and every neighbour inside the tile is read
+// from there.  A tile is 256 consecutive sites, so on lattices with
+// Lx Ly = 256 it is one xy-plane and all x and y hops are served from LDS;
+// only the z and t neighbours go to L2/HBM.
+template <typename R, int B, bool STAGE>
 __global__ void __launch_bounds__(512)
 k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
             const typename Vec2<R>::T* __restrict__ basis,
@@ -522,6 +528,7 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
             const int* __restrict__ n_active, int nt, TileMap tm) {
   using T2 = typename Vec2<R>::T;
   __shared__ double lds[(512 / 64) * 3 * B];
+  __shared__ T2 plane[STAGE ? 2 * B * 12 * 256 : 1];  // [op][source][component][tile site]
   int site0, rb, tile;
   if (!map_tile(blockIdx.x, tm, site0, rb, tile)) return;  // uniform over the workgroup
   const int na = *n_active;
@@ -536,7 +543,8 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
   int nsrc = min(B, na - j0);
   __asm__ volatile("" : "+s"(nsrc));
   const int op = threadIdx.x & 1;
-  const int s = site0 + (threadIdx.x >> 1);
+  const int ts = threadIdx.x >> 1;
+  const int s = site0 + ts;
   const bool live = s < g.V;
   const int V = g.Vs;
   const T2* in = op ? in_w : in_v;
@@ -550,6 +558,31 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
   int slot[B];
 #pragma unroll
   for (int r = 0; r < B; ++r) slot[r] = (r < nsrc) ? rhs_map[j0 + r] : 0;
+
+  if constexpr (STAGE) {
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      if (r < nsrc && live) {
+        const T2* f = in + (long)slot[r] * 12 * V;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) plane[((op * B + r) * 12 + c) * 256 + ts] = f[(long)c * V + s];
+      }
+    }
+    __syncthreads();
+  }
+  // spinor of source r at site n: from the staged tile when n is inside it
+  auto load_nb = [&](int r, int n, Cx<R>(&p)[12]) {
+    const unsigned d = (unsigned)(n - site0);
+    if (STAGE && d < 256u) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const T2 v = plane[((op * B + r) * 12 + c) * 256 + d];
+        p[c] = {v.x, v.y};
+      }
+    } else {
+      load_spinor(in + (long)slot[r] * 12 * V, V, n, false, p);
+    }
+  };
 
   double part[3 * B];
 #pragma unroll
@@ -567,14 +600,14 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
   load_link(links, V, NU, nb.b[NU], u);                                                  \
   _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
     if (r < nsrc) {                                                                      \
-      load_spinor(in + (long)slot[r] * 12 * V, V, nb.b[NU], false, psi);                 \
+      load_nb(r, nb.b[NU], psi);                                                         \
       hop<R, NU, +1, false>(acc[r], u, psi, cf[NU]);                                     \
     }                                                                                    \
   }                                                                                      \
   load_link(links, V, NU, s, u);                                                         \
   _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
     if (r < nsrc) {                                                                      \
-      load_spinor(in + (long)slot[r] * 12 * V, V, nb.f[NU], false, psi);                 \
+      load_nb(r, nb.f[NU], psi);                                                         \
       hop<R, NU, -1, true>(acc[r], u, psi, cb[NU]);                                      \
     }                                                                                    \
   }
@@ -588,8 +621,18 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
       if (r < nsrc) {
         const long base = (long)slot[r] * 12 * V;
         Cx<R> p[12], pw[12];
-        load_spinor(in + base, V, s, false, p);
-        if (!op) load_spinor(in_w + base, V, s, false, pw);
+        load_nb(r, s, p);
+        if (!op) {
+          if constexpr (STAGE) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+              const T2 v = plane[((B + r) * 12 + c) * 256 + ts];
+              pw[c] = {v.x, v.y};
+            }
+          } else {
+            load_spinor(in_w + base, V, s, false, pw);
+          }
+        }
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
           Cx<R> o = p[c] - acc[r][c];
@@ -631,19 +674,36 @@ static hipError_t launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, 
                      hipStream_t s) {
   using T2 = typename Vec2<R>::T;
   const TileMap tm = make_tile_map(g, 256, (a.nrhs_slots + B - 1) / B, a.order);
+  // the staged planes take 2 B 12 256 complex values of LDS: one or two sources
+  constexpr bool kStage = 2 * B * 12 * 256 * sizeof(T2) <= 100 * 1024;
   static bool lds_set = false;
   if (!lds_set) {
     apply_lds_limit((const void*)k_dual<R, B>);
-    apply_lds_limit((const void*)k_dual_pair<R, B>);
+    apply_lds_limit((const void*)k_dual_pair<R, B, false>);
+    if constexpr (kStage) apply_lds_limit((const void*)k_dual_pair<R, B, true>);
     lds_set = true;
   }
-  const void* fn = a.pair ? (const void*)k_dual_pair<R, B> : (const void*)k_dual<R, B>;
+  if (a.pair == 2) {
+    if constexpr (kStage) {
+      if (!lds_fits((const void*)k_dual_pair<R, B, true>, a.lds_kb)) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_dual_pair<R, B, true>), dim3(8 * tm.per_xcd), dim3(512),
+                         a.lds_kb * 1024, s, (const T2*)a.links, (const T2*)a.basis,
+                         (const T2*)a.wbuf, a.basis_stride, (int)a.ring, a.it, (T2*)a.out_t,
+                         (T2*)a.out_s, a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd),
+                         a.rhs_map, a.n_active, a.nt, tm);
+      return hipSuccess;
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  const void* fn = a.pair == 1 ? (const void*)k_dual_pair<R, B, false> : (const void*)k_dual<R, B>;
   if (!lds_fits(fn, a.lds_kb)) return hipErrorInvalidValue;
-  if (a.pair)
-    hipLaunchKernelGGL((k_dual_pair<R, B>), dim3(8 * tm.per_xcd), dim3(512), a.lds_kb * 1024, s,
-                       (const T2*)a.links, (const T2*)a.basis, (const T2*)a.wbuf, a.basis_stride,
-                       (int)a.ring, a.it, (T2*)a.out_t, (T2*)a.out_s, a.partials, g,
-                       HopR<R>::make(hA), HopR<R>::make(hAd), a.rhs_map, a.n_active, a.nt, tm);
+  if (a.pair == 1)
+    hipLaunchKernelGGL((k_dual_pair<R, B, false>), dim3(8 * tm.per_xcd), dim3(512),
+                       a.lds_kb * 1024, s, (const T2*)a.links, (const T2*)a.basis,
+                       (const T2*)a.wbuf, a.basis_stride, (int)a.ring, a.it, (T2*)a.out_t,
+                       (T2*)a.out_s, a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd),
+                       a.rhs_map, a.n_active, a.nt, tm);
   else
     hipLaunchKernelGGL((k_dual<R, B>), dim3(8 * tm.per_xcd), dim3(256), a.lds_kb * 1024, s,
                        (const T2*)a.links, (const T2*)a.basis, (const T2*)a.wbuf, a.basis_stride,

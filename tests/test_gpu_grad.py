@@ -28,9 +28,9 @@ def f64_lattice(dims, U, mu):
     return lat
 
 
-def gpu_vjp(lat, b, chi, k, want_y=True):
+def gpu_vjp(lat, b, chi, k, want_y=True, store_basis=False):
     y, gb, gmu, gU, qerr, st = lat.sign_apply_vjp(to_dev(np.atleast_2d(b)), to_dev(np.atleast_2d(chi)),
-                                                  k, want_y=want_y)
+                                                  k, want_y=want_y, store_basis=store_basis)
     yy = y.cpu().numpy() if y is not None else None
     return yy, gb.cpu().numpy(), gmu, gU.cpu().numpy(), qerr, st
 
@@ -63,6 +63,21 @@ def test_vjp_matches_oracle_sweep(small, k):
     assert eb <= 1e-9
     assert emu <= 1e-9
     assert eU <= 1e-9
+
+
+@pytest.mark.parametrize("k", [1, 7, 30, 64])
+def test_vjp_recompute_equals_stored_basis(small, k):
+    """Checkpointed recomputation replays the forward vectors bit for bit, so
+    the gradient equals the stored-basis one exactly (k = 1, a non-square k, a
+    square k and several segments)."""
+    dims, U, mu, _, _ = small
+    B = synth.gaussian_sources(dims, 2, seed=56)
+    C = synth.gaussian_sources(dims, 2, seed=57)
+    lat = f64_lattice(dims, U, mu)
+    a = gpu_vjp(lat, B, C, k, store_basis=False)
+    s = gpu_vjp(lat, B, C, k, store_basis=True)
+    assert np.array_equal(a[0], s[0]) and np.array_equal(a[1], s[1])
+    assert a[2] == s[2] and np.array_equal(a[3], s[3])
 
 
 def test_vjp_batched_equals_single(small):
