@@ -10,9 +10,11 @@ sgn(G_k) e_1 and the combination.  The workload (synthetic, seeded):
 sources, FP32 storage with FP64 coefficients, target relative error 1e-5.
 
 Prints one JSON line.  value = solves/s of the timed steps.  The roofline
-object is for the Wilson stencil kernel (HIP events on the library stream);
-the dual Lanczos stencil is reported beside it.  cpu_baseline times the CPU
-oracle's two-sided Lanczos on a bounded sample of the same workload.
+object is for the Wilson stencil kernel (HIP events on the library stream).
+vs_fp64_single_source solves the same sources one at a time on an FP64
+lattice (autotuned for one source), without and with graphs, and gives the
+batched FP32-storage rate over each.  cpu_baseline times the CPU oracle's
+two-sided Lanczos on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -114,6 +116,30 @@ def free_field_check(ovs, torch, dev):
     return max(errs), [i["k_used"] for i in info]
 
 
+def fp64_single_source(ovs, torch, dev, U, bt, y32, graph):
+    """The same sources solved one at a time on an FP64 lattice (same links,
+    same tolerance), sequentially: solves/s and the largest relative
+    difference from the batched FP32-storage result."""
+    lat = ovs.Lattice(DIMS, precision="f64")
+    lat.set_links(U)
+    lat.set_params(MW, MU)
+    lat.autotune(1)
+    lat.sign_apply(bt[0:1], KMAX, tol=[TOL], graph=graph)  # warm-up (workspace, graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ys = []
+    for r in range(bt.shape[0]):
+        y, _, _ = lat.sign_apply(bt[r:r + 1], KMAX, tol=[TOL], graph=graph)
+        ys.append(y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    y64 = torch.cat(ys).cpu().numpy()
+    yb = y32.cpu().numpy()
+    diff = max(float(np.linalg.norm(yb[r] - y64[r]) / np.linalg.norm(y64[r])) for r in range(len(ys)))
+    lat.close()
+    return bt.shape[0] / dt, diff
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +147,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP64 single-source comparison")
     ap.add_argument("--stencil-only", action="store_true",
                     help="time the stencil kernel only (for counter collection)")
     ap.add_argument("--tuning", default=None,
@@ -155,7 +183,8 @@ def main():
     U = synth.random_links(DIMS, EPS, seed=synth.LINK_SEED)
     b = synth.gaussian_sources(DIMS, NRHS, seed=synth.SOURCE_SEED)
     lat = ovs.Lattice(DIMS, precision="f32")
-    lat.set_links(torch.from_numpy(U).to(dev))
+    Ut = torch.from_numpy(U).to(dev)
+    lat.set_links(Ut)
     lat.set_params(MW, MU)
     bt = torch.from_numpy(b).to(dev)
     del U
@@ -246,6 +275,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": st_gbs / HBM_PEAK_GBS, "traffic": stencil_traffic()},
     }
+    if not args.no_compare:
+        log("bench: FP64 single-source comparison")
+        cmp = {}
+        for graph in (False, True):
+            rate, diff = fp64_single_source(ovs, torch, dev, Ut, bt, y, graph)
+            key = "fp64_single_graph" if graph else "fp64_single"
+            cmp[key] = {"solves_per_s": rate, "ratio": value / rate, "max_rel_diff_vs_batched": diff}
+            log(f"bench: {key}: {rate:.2f} solves/s, batched/this = {value / rate:.2f}")
+        out["vs_fp64_single_source"] = cmp
     if not args.no_check:
         log("bench: free-field accuracy check")
         err, kf = free_field_check(ovs, torch, dev)

@@ -64,7 +64,8 @@ typedef enum { OVS_2SL = 0, OVS_ARNOLDI = 1 } ovs_method;
 enum {
   OVS_FLAG_TWO_PASS = 1,  /* 2sL: do not store V_k; replay the recurrence (end of Section 5) */
   OVS_FLAG_GRAPH    = 4,  /* replay the Lanczos iterations as captured HIP graphs             */
-  OVS_FLAG_OVERLAP  = 8   /* return D_ov b = b + gamma5 sgn(A) b instead of sgn(A) b         */
+  OVS_FLAG_OVERLAP  = 8,  /* return D_ov b = b + gamma5 sgn(A) b instead of sgn(A) b         */
+  OVS_FLAG_NO_SPLIT = 16  /* run a batch of 8 or more sources as one batch, not two halves    */
 };
 enum {
   OVS_VJP_STORE_BASIS = 1 /* ovs_sign_apply_vjp: keep both bases instead of recomputing them */
@@ -179,6 +180,9 @@ ovs_status ovs_deflation_destroy(ovs_deflation d);
  *            the sources with tol < 1e-6 (below what FP32 storage attains) run
  *            as an FP64 group on the FP64 copy of the links; the rest in FP32.
  *   info   : host [nrhs] result records, or NULL.
+ * Batches of 8 or more sources run as two halves at the same time, on the
+ * handle's stream and on a second internal stream (each half with the whole
+ * batch's tuned kernels); OVS_FLAG_NO_SPLIT runs them as one batch.
  * The inner function sgn(G_k) e_1 (or sgn(H_k) e_1) is evaluated on the GPU
  * in FP64.  Returns the most severe per-source warning, or an error. */
 ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, const void* b,

@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "ovs_common.h"
@@ -274,9 +276,22 @@ static void destroy_shadow(ovs_lattice_s* l) {
   l->shadow64 = nullptr;
 }
 
+static void destroy_worker(ovs_lattice_s* l) {
+  ovs_lattice_s* w = l->worker;
+  if (!w) return;
+  (void)hipStreamSynchronize(w->stream);
+  if (w->ws) (void)hipFree(w->ws);
+  (void)hipEventDestroy(w->ev_in);
+  (void)hipEventDestroy(w->ev_out);
+  (void)hipStreamDestroy(w->stream);
+  delete w;  // links belong to the parent
+  l->worker = nullptr;
+}
+
 ovs_status ovs_lattice_destroy(ovs_lattice l) {
   if (!l || l->parent) return OVS_ERR_ARG;
   (void)hipStreamSynchronize(l->stream);
+  destroy_worker(l);
   destroy_shadow(l);
   if (l->split_buf) (void)hipFree(l->split_buf);
   if (l->links) (void)hipFree(l->links);
@@ -729,14 +744,17 @@ ovs_status ovs_deflation_destroy(ovs_deflation d) {
 
 // ---- sign function ------------------------------------------------------------------
 
+// tune_key: the batch size whose tuned kernel configuration is used (the
+// whole batch when this call runs one part of it).
 static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
                                   const void* b, void* y, int32_t nrhs, int32_t k_max,
                                   const double* tol, ovs_method method, int32_t flags,
-                                  ovs_rhs_info* info) {
+                                  ovs_rhs_info* info, int tune_key) {
   if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || k_max < 1) return OVS_ERR_ARG;
   if (!ready(l)) return OVS_ERR_STATE;
   if (method != OVS_2SL && method != OVS_ARNOLDI) return OVS_ERR_ARG;
-  if (flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_OVERLAP)) return OVS_ERR_ARG;
+  if (flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_OVERLAP | OVS_FLAG_NO_SPLIT))
+    return OVS_ERR_ARG;
   if (k_max > 12L * l->g.V) return OVS_ERR_ARG;
   const long N = 12L * l->g.Vs;  // padded field length of one source
   int m = 0;
@@ -941,7 +959,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
                           B.rhs_map, B.ints + 1, nr, B.probes, s);
       OVS_HIP(hipStreamSynchronize(s));  // pidx_h lifetime
     }
-    const Tuning dt = get_dual_tuning(l, nr);
+    const Tuning dt = get_dual_tuning(l, tune_key);
     const int dual_b = std::min(dt.rhs_block, f32 ? 4 : 2);
     DualArgs da{l->links, B.basis, B.wbuf, bstride, two_pass, B.ints, B.T, B.S, B.part1,
                 B.rhs_map, B.ints + 1, nr, dt.lds_kb, dt.order, dt.nt, dt.g - 1};
@@ -1066,7 +1084,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       else
         OVS_HIP(hipMemsetAsync(B.Y, 0, sizeof(double2) * nr * N, s));
       const int kmx = *std::max_element(kused.begin(), kused.end());
-      Tuning tn = get_tuning(l, nr);
+      Tuning tn = get_tuning(l, tune_key);
       for (int it = 0; it < kmx; ++it) {
         if (it + 1 < kmx)
           OVS_HIP(launch_wilson(f32, l->links, B.basis + (size_t)(it % 3) * bstride * es, B.T, nr,
@@ -1088,7 +1106,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     OVS_HIP(hipMemcpyAsync(l->last_x.data(), B.x, sizeof(double2) * nr * K, hipMemcpyDeviceToHost, s));
   } else {
     // ---- Arnoldi with classical Gram-Schmidt applied twice (Section 2) ----
-    Tuning tn = get_tuning(l, nr);
+    Tuning tn = get_tuning(l, tune_key);
     for (int j = 0; j < K; ++j) {
       OVS_HIP(launch_wilson(f32, l->links, B.basis + (size_t)j * bstride * es, B.T, nr, l->g, hA,
                             false, true, tn, s));
@@ -1152,6 +1170,78 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   return worst;
 }
 
+// Batches of kSplitMin or more sources run as two contiguous halves at the
+// same time: the first on the handle's stream, the second on a worker handle
+// (its own stream; the same links, parameters and tuning) from a second host
+// thread.  The latency-bound dual stencil and the per-iteration scalar steps
+// of one half overlap the bandwidth-bound update of the other (+10% solves/s
+// measured at 16^3 x 32 with 12 sources).  Per source the arithmetic is that
+// of the whole batch (both halves use the whole batch's tuned kernels).
+constexpr int kSplitMin = 8;
+
+static ovs_status worker_ready(ovs_lattice_s* l) {
+  if (!l->worker) {
+    ovs_lattice_s* w = new (std::nothrow) ovs_lattice_s();
+    if (!w) return OVS_ERR_ALLOC;
+    w->g = l->g;
+    for (int i = 0; i < 4; ++i) w->bc[i] = l->bc[i];
+    w->prec = l->prec;
+    w->device = l->device;
+    w->lds_max_kb = l->lds_max_kb;
+    w->parent = l;
+    if (hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      delete w;
+      return OVS_ERR_HIP;
+    }
+    l->worker = w;
+  }
+  ovs_lattice_s* w = l->worker;
+  w->user_stream = l->user_stream;
+  w->links = l->links;
+  w->links64 = l->links64;
+  w->m_w = l->m_w;
+  w->mu = l->mu;
+  w->links_set = l->links_set;
+  w->params_set = l->params_set;
+  w->tuning = l->tuning;
+  w->dual_tuning = l->dual_tuning;
+  return OVS_OK;
+}
+
+static ovs_status run_batch(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
+                            void* y, int32_t nrhs, int32_t k_max, const double* tol,
+                            ovs_method method, int32_t flags, ovs_rhs_info* info) {
+  if (nrhs < kSplitMin || (flags & OVS_FLAG_NO_SPLIT))
+    return sign_apply_impl(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info, nrhs);
+  if (!ready(l)) return OVS_ERR_STATE;
+  ovs_status st = worker_ready(l);
+  if (st != OVS_OK) return st;
+  const int n1 = nrhs / 2, n2 = nrhs - n1;
+  const size_t fb = 12ul * l->g.V * sizeof(double2);
+  ovs_status st2 = OVS_OK;
+  std::string err2;
+  std::thread second([&] {
+    if (hipSetDevice(l->device) != hipSuccess) {
+      st2 = OVS_ERR_HIP;
+      return;
+    }
+    st2 = sign_apply_impl(l->worker, defl, n_defl, (const char*)b + n1 * fb, (char*)y + n1 * fb,
+                          n2, k_max, tol ? tol + n1 : nullptr, method, flags,
+                          info ? info + n1 : nullptr, nrhs);
+    if (st2 < 0) err2 = g_last_error;
+  });
+  const ovs_status st1 =
+      sign_apply_impl(l, defl, n_defl, b, y, n1, k_max, tol, method, flags, info, nrhs);
+  second.join();
+  if (st2 < 0 && st1 >= 0) snprintf(g_last_error, sizeof(g_last_error), "%s", err2.c_str());
+  if (st1 < 0) return st1;
+  if (st2 < 0) return st2;
+  return std::max(st1, st2);
+}
+
 // FP32 storage limits the attainable relative error to a few 1e-8 (measured
 // with the oracle at 4^4).  Sources asking for less than kF32Floor run in
 // FP64 on the shadow handle: the same driver on the FP64 copy of the links,
@@ -1193,20 +1283,20 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
                           ovs_method method, int32_t flags, ovs_rhs_info* info) {
   if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || l->parent) return OVS_ERR_ARG;
   if (!tol || l->prec != OVS_F32_STORE)
-    return sign_apply_impl(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
+    return run_batch(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
   std::vector<int> lo, hi;
   for (int r = 0; r < nrhs; ++r) {
     if (!(tol[r] > 0.0)) return OVS_ERR_ARG;
     (tol[r] < kF32Floor ? lo : hi).push_back(r);
   }
   if (lo.empty())
-    return sign_apply_impl(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
+    return run_batch(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
   if (!ready(l)) return OVS_ERR_STATE;
   ovs_status st = shadow_ready(l);
   if (st != OVS_OK) return st;
   if (hi.empty())
     return sign_apply_impl(l->shadow64, defl, n_defl, b, y, nrhs, k_max, tol, method, flags,
-                           info);
+                           info, nrhs);
   // gather both groups: [b_lo | y_lo | b_hi | y_hi], canonical complex128 fields
   const size_t fb = 12ul * l->g.V * sizeof(double2);
   const size_t need = 2 * (size_t)nrhs * fb;
@@ -1239,10 +1329,10 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
   for (int j = 0; j < nhi; ++j) thi[j] = tol[hi[j]];
   std::vector<ovs_rhs_info> ilo(nlo), ihi(nhi);
   const ovs_status s_lo = sign_apply_impl(l->shadow64, defl, n_defl, b_lo, y_lo, nlo, k_max,
-                                          tlo.data(), method, flags, ilo.data());
+                                          tlo.data(), method, flags, ilo.data(), nlo);
   if (s_lo < 0) return s_lo;
-  const ovs_status s_hi = sign_apply_impl(l, defl, n_defl, b_hi, y_hi, nhi, k_max, thi.data(),
-                                          method, flags, ihi.data());
+  const ovs_status s_hi = run_batch(l, defl, n_defl, b_hi, y_hi, nhi, k_max, thi.data(),
+                                    method, flags, ihi.data());
   if (s_hi < 0) return s_hi;
   for (int j = 0; j < nlo; ++j)
     OVS_HIP(hipMemcpyAsync((char*)y + lo[j] * fb, y_lo + j * fb, fb, hipMemcpyDeviceToDevice,

@@ -92,6 +92,8 @@ struct ovs_lattice_s {
   ovs_lattice_s* parent = nullptr;   // set on a shadow: the handle it serves
   void* split_buf = nullptr;         // gathered sources / results of the split
   size_t split_bytes = 0;
+  // second handle (own stream) for the concurrent half of large batches
+  ovs_lattice_s* worker = nullptr;
 };
 
 struct ovs_field_s {

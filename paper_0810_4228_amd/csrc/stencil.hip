@@ -8,6 +8,9 @@
 // neighbour spinor is first projected to two spin components, multiplied by
 // the link and then expanded again (chiral basis of the library header).
 // Loads and stores are coalesced: the field layout is [src][12][V].
+#include <atomic>
+#include <mutex>
+
 #include "ovs_common.h"
 #include "ovs_device.h"
 #include "ovs_spin.h"
@@ -275,7 +278,7 @@ k_wilson_g(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>
 
 // Dynamic LDS requests above the default per-workgroup limit need a
 // per-kernel opt-in; the limit is set once per process from the device query.
-static int g_lds_limit_kb = 64;
+static std::atomic<int> g_lds_limit_kb{64};
 void set_lds_limit(int kb) { g_lds_limit_kb = kb; }
 // A launch whose static plus dynamic LDS exceeds the per-workgroup limit is an
 // invalid dispatch (the queue aborts): launchers check before launching.
@@ -319,8 +322,8 @@ static hipError_t launch_w(const void* links, const void* in, void* out, int nrh
                      int nt, hipStream_t s) {
   using T2 = typename Vec2<R>::T;
   const TileMap tm = make_tile_map(g, wg, (nrhs + B - 1) / B, order);
-  static bool lds_set = false;
-  if (!lds_set) { apply_lds_limit((const void*)k_wilson<R, B>); lds_set = true; }
+  static std::once_flag lds_set;  // launches may come from several host threads
+  std::call_once(lds_set, [] { apply_lds_limit((const void*)k_wilson<R, B>); });
   if (!lds_fits((const void*)k_wilson<R, B>, lds_kb)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_wilson<R, B>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s, (const T2*)links,
                      (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs, (int)g5in, (int)g5out,
@@ -334,8 +337,8 @@ static hipError_t launch_wg(const void* links, const void* in, void* out, int nr
                       hipStream_t s) {
   using T2 = typename Vec2<R>::T;
   const TileMap tm = make_tile_map(g, wg / G, (nrhs + G - 1) / G, order);
-  static bool lds_set = false;
-  if (!lds_set) { apply_lds_limit((const void*)k_wilson_g<R, G>); lds_set = true; }
+  static std::once_flag lds_set;
+  std::call_once(lds_set, [] { apply_lds_limit((const void*)k_wilson_g<R, G>); });
   if (!lds_fits((const void*)k_wilson_g<R, G>, lds_kb)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_wilson_g<R, G>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s,
                      (const T2*)links, (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs,
@@ -676,13 +679,12 @@ static hipError_t launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, 
   const TileMap tm = make_tile_map(g, 256, (a.nrhs_slots + B - 1) / B, a.order);
   // the staged planes take 2 B 12 256 complex values of LDS: one or two sources
   constexpr bool kStage = 2 * B * 12 * 256 * sizeof(T2) <= 100 * 1024;
-  static bool lds_set = false;
-  if (!lds_set) {
+  static std::once_flag lds_set;
+  std::call_once(lds_set, [] {
     apply_lds_limit((const void*)k_dual<R, B>);
     apply_lds_limit((const void*)k_dual_pair<R, B, false>);
     if constexpr (kStage) apply_lds_limit((const void*)k_dual_pair<R, B, true>);
-    lds_set = true;
-  }
+  });
   if (a.pair == 2) {
     if constexpr (kStage) {
       if (!lds_fits((const void*)k_dual_pair<R, B, true>, a.lds_kb)) return hipErrorInvalidValue;

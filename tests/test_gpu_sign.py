@@ -110,6 +110,24 @@ def test_matches_cpu_lanczos_step_by_step():
         assert rel(y.cpu().numpy()[0], yr) < 1e-10
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_split_batch_equals_one_batch(prec):
+    """A batch of 10 sources runs as two concurrent halves on two streams;
+    each source's result and Krylov size equal the single-batch run bit for
+    bit (both use the whole batch's kernels), with uneven tolerances."""
+    dims = (4, 4, 4, 8)
+    U = synth.random_links(dims, 0.5, seed=93)
+    b = synth.gaussian_sources(dims, 10, seed=94)
+    tol = [1e-4, 1e-6, 1e-5, 1e-6, 1e-4, 1e-5, 1e-6, 1e-4, 1e-5, 1e-6] if prec == "f64" else [1e-4, 1e-5] * 5
+    lat = lattice(dims, prec, U, 0.3)
+    y1, i1, s1 = lat.sign_apply(to_dev(b), 800, tol=tol, graph=True, split=False)
+    y2, i2, s2 = lat.sign_apply(to_dev(b), 800, tol=tol, graph=True, split=True)
+    say("split", prec, [i["k_used"] for i in i2])
+    assert [i["k_used"] for i in i1] == [i["k_used"] for i in i2]
+    assert np.array_equal(y1.cpu().numpy(), y2.cpu().numpy())
+    assert s1 == s2
+
+
 def test_mixed_tolerance_fp64_group(cfg1):
     """FP32-storage lattice, tolerances 1e-5 and 1e-9 alternating, m = 20: the
     1e-9 sources run as an FP64 group and reach the exact sign (stored 4^4
