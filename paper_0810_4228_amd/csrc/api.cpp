@@ -133,7 +133,7 @@ constexpr double kQuadAccept = 3e-7;  // coarse/fine difference accepted at step
 constexpr int kProbe = 512;           // sampled entries per source for the convergence estimate
 constexpr int kCheckEvery = 25;       // iterations between convergence checks
 
-// Distinct sampled field positions c*Vs + s (s < V), sorted; a fixed
+// Distinct sampled field positions fidx(c, s) (s < V), sorted; a fixed
 // sequence, the same for all calls.
 std::vector<int> probe_positions(const Geometry& g, int P) {
   const long N = 12L * g.V;
@@ -146,7 +146,7 @@ std::vector<int> probe_positions(const Geometry& g, int P) {
     const long p = (long)((st >> 17) % (unsigned long long)N);
     if (!used[p]) {
       used[p] = 1;
-      idx.push_back((int)((p / g.V) * g.Vs + (p % g.V)));
+      idx.push_back((int)fidx((int)(p / g.V), p % g.V, g.Vs));
     }
   }
   std::sort(idx.begin(), idx.end());
@@ -255,7 +255,7 @@ ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_pr
     set_lds_limit(l->lds_max_kb);
     (void)hipGetLastError();
   }
-  const size_t lb = 4ul * 9 * l->g.Vs * elem_bytes(l);
+  const size_t lb = 4ul * kLinkSlots * l->g.Vs * elem_bytes(l);
   if (hipMalloc(&l->links, lb) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipStreamDestroy(l->stream);
@@ -309,7 +309,8 @@ ovs_status ovs_set_links(ovs_lattice l, const void* U) {
   StreamScope sc(l);
   launch_pack_links((const double2*)U, l->links, l->prec == OVS_F32_STORE, l->g, l->bc, l->stream);
   if (l->prec == OVS_F32_STORE) {
-    if (!l->links64 && hipMalloc(&l->links64, 4ul * 9 * l->g.Vs * sizeof(double2)) != hipSuccess) {
+    if (!l->links64 &&
+        hipMalloc(&l->links64, 4ul * kLinkSlots * l->g.Vs * sizeof(double2)) != hipSuccess) {
       (void)hipGetLastError();
       l->links64 = nullptr;
       return OVS_ERR_ALLOC;

@@ -13,8 +13,8 @@ static int egrid(long n) {
   return (int)b;
 }
 
-// Counter-based fill: entry (f, c, s) of a block gets (u1, u2) uniform in
-// [-1, 1) from splitmix64 of (seed, f, c, s); pad entries are zero.
+// Counter-based fill: the entry at flat offset e of a block gets (u1, u2)
+// uniform in [-1, 1) from splitmix64 of (seed, e); pad entries are zero.
 __device__ __forceinline__ unsigned long long splitmix(unsigned long long x) {
   x += 0x9E3779B97F4A7C15ull;
   x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -26,7 +26,7 @@ __global__ void k_fill_random(double2* __restrict__ X, long nfields, int V, int 
                               unsigned long long seed) {
   const long n = nfields * 12 * Vs;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const int s = (int)(e % Vs);
+    const int s = (int)(((e % (12L * Vs)) >> 1) % Vs);  // site of the pair layout
     if (s >= V) {
       X[e] = make_double2(0.0, 0.0);
       continue;

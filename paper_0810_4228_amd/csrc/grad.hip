@@ -480,7 +480,7 @@ __device__ __forceinline__ void load_sp(const double2* f, long Vs, int s, bool g
                                         Cx<double> (&p)[12]) {
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    p[c] = c64(f[(long)c * Vs + s]);
+    p[c] = c64(f[fidx(c, s, Vs)]);
     if (g5 && c >= 6) p[c] = -p[c];
   }
 }
@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(kWG) k_gforce_out(const double2* F, const doub
         Cx<double> v = c64(F[((long)nu * 9 + e) * g.Vs + s]);
         if (nu == 3) {
           const Cx<double> vm = c64(F[((long)4 * 9 + e) * g.Vs + s]);
-          const Cx<double> u = c64(links[((long)3 * 9 + e) * g.Vs + s]);
+          const Cx<double> u = c64(links[lidx(3, e, s, g.Vs)]);
           part[0] += cmulc(v, u).re - cmulc(vm, u).re;
           v = v + vm;
         }

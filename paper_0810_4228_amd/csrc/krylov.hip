@@ -391,8 +391,10 @@ __global__ void __launch_bounds__(256) k_replay(const T2* __restrict__ T, T2* __
 
 // y <- b + gamma5 y  (D_ov b, eq. (1.1)); fields [nrhs][12][V] FP64
 __global__ void k_overlap(const double2* __restrict__ b, double2* __restrict__ y, long N, int V) {
+  // V: the padded plane stride Vs; component c of offset e (layout of fidx)
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
-    const int c = (int)((e / V) % 12);
+    const long loc = e % (12L * V);
+    const int c = (int)(2 * ((loc >> 1) / V) + (loc & 1));
     Cx<double> v = c64(y[e]);
     if (c >= 6) v = -v;
     y[e] = d2(c64(b[e]) + v);

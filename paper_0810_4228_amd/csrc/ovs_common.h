@@ -1,13 +1,17 @@
 // Internal declarations shared by the ovsign HIP sources.
 //
 // Device layouts (private to the library):
-//   field  : [nrhs][12][Vs] complex, component c = 3*spin + colour; complex is
-//            double2 (OVS_F64) or float2 (OVS_F32_STORE).  Vs = V rounded up
-//            to a wave plus one wave, so component planes are not a power of
-//            two apart (L2 set aliasing); pad entries s >= V are kept zero.
-//   links  : [4][9][Vs] complex, entry 3*a + b of U_{x,nu}; the boundary sign
-//            of the link leaving the last slice in direction nu is folded in
-//   FP64 work fields (deflation, results): [nrhs][12][Vs] double2
+//   field  : [nrhs][6][Vs][2] complex: component c = 3*spin + colour of site s
+//            at ((c/2)*Vs + s)*2 + c%2 (fidx), so the two components of a pair
+//            are adjacent and one 16-byte load brings both in FP32.  Complex is
+//            double2 (OVS_F64) or float2 (OVS_F32_STORE).  Vs = V rounded up to
+//            a wave plus one wave, so pair planes are not a power of two apart
+//            (L2 set aliasing); pad entries s >= V are kept zero.
+//   links  : [4][5][Vs][2] complex: entry e = 3*a + b of U_{x,nu} at
+//            ((nu*5 + e/2)*Vs + s)*2 + e%2 (lidx); the second slot of pair 4
+//            is zero.  The boundary sign of the link leaving the last slice in
+//            direction nu is folded in.
+//   FP64 work fields (deflation, results): the field layout in double2
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,6 +25,16 @@
 namespace ovs {
 
 constexpr int kWG = 256;          // workgroup size of the streaming kernels
+constexpr int kLinkSlots = 10;    // complex slots per site and direction (9 entries + 1 pad)
+
+// Offset of component c of site s in one source field (complex elements).
+__host__ __device__ inline long fidx(int c, long s, long Vs) {
+  return ((long)(c >> 1) * Vs + s) * 2 + (c & 1);
+}
+// Offset of entry e of U_nu at site s in the packed links (complex elements).
+__host__ __device__ inline long lidx(int nu, int e, long s, long Vs) {
+  return ((long)(nu * 5 + (e >> 1)) * Vs + s) * 2 + (e & 1);
+}
 constexpr int kMaxNrhs = 4096;
 constexpr int kMaxDefl = 1024;
 

@@ -98,6 +98,36 @@ __device__ __forceinline__ Cx<double> round_to(const float2*, Cx<double> a) {
   return {(double)(float)a.re, (double)(float)a.im};
 }
 
+// Two adjacent complex values (a component pair of the field layout) in one
+// access: a 16-byte load or store in FP32, two in FP64.
+__device__ __forceinline__ void ld_pair(const float2* p, Cx<float>& a, Cx<float>& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = {v.x, v.y};
+  b = {v.z, v.w};
+}
+__device__ __forceinline__ void ld_pair(const double2* p, Cx<double>& a, Cx<double>& b) {
+  a = ld(p);
+  b = ld(p + 1);
+}
+__device__ __forceinline__ void st_pair(float2* p, Cx<float> a, Cx<float> b) {
+  *reinterpret_cast<float4*>(p) = make_float4(a.re, a.im, b.re, b.im);
+}
+__device__ __forceinline__ void st_pair(double2* p, Cx<double> a, Cx<double> b) {
+  st(p, a);
+  st(p + 1, b);
+}
+__device__ __forceinline__ void st_pair_nt(float2* p, Cx<float> a, Cx<float> b) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  v4 v = {a.re, a.im, b.re, b.im};
+  __builtin_nontemporal_store(v, reinterpret_cast<v4*>(p));
+}
+__device__ __forceinline__ void st_pair_nt(double2* p, Cx<double> a, Cx<double> b) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  v2 va = {a.re, a.im}, vb = {b.re, b.im};
+  __builtin_nontemporal_store(va, reinterpret_cast<v2*>(p));
+  __builtin_nontemporal_store(vb, reinterpret_cast<v2*>(p + 1));
+}
+
 __device__ __forceinline__ Cx<double> c64(double2 v) { return {v.x, v.y}; }
 __device__ __forceinline__ double2 d2(Cx<double> a) { return make_double2(a.re, a.im); }
 __device__ __forceinline__ Cx<double> cdiv(Cx<double> a, Cx<double> b) {

@@ -24,11 +24,13 @@ __global__ void k_pack(const double2* __restrict__ canon, T2* __restrict__ field
                        int Vs) {
   const long n = (long)nrhs * 12 * Vs;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    // e indexes the padded output [r][c][Vs] so the store is coalesced; pad entries are zero
-    const int s = (int)(e % Vs);
-    const long rc = e / Vs;
-    const int c = (int)(rc % 12);
-    const long r = rc / 12;
+    // e indexes the padded output (layout of fidx) so the store is coalesced;
+    // pad entries are zero
+    const long r = e / (12L * Vs);
+    const long loc = e - r * 12L * Vs;
+    const long t = loc >> 1;
+    const int s = (int)(t % Vs);
+    const int c = (int)(2 * (t / Vs) + (loc & 1));
     st64(field + e, s < V ? c64(canon[(r * V + s) * 12 + c]) : Cx<double>{0.0, 0.0});
   }
 }
@@ -43,7 +45,7 @@ __global__ void k_unpack(const T2* __restrict__ field, double2* __restrict__ can
     const long rs = e / 12;
     const int s = (int)(rs % V);
     const long r = rs / V;
-    canon[e] = d2(ld64(field + (r * 12 + c) * Vs + s));
+    canon[e] = d2(ld64(field + r * 12 * Vs + fidx(c, s, Vs)));
   }
 }
 
@@ -71,16 +73,18 @@ void launch_unpack_f32(const float2* field, double2* canon, int nrhs, const Geom
   hipLaunchKernelGGL(k_unpack<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, field, canon, nrhs, g.V, g.Vs);
 }
 
+// nplanes component planes (an even number) = nplanes/2 planes of pairs; the
+// pad entries of a pair plane are the contiguous range [2V, 2Vs).
 template <typename T2>
 __global__ void k_zero_pad(T2* __restrict__ base, long nplanes, int V, int Vs) {
-  const int w = Vs - V;
-  const long n = nplanes * w;
+  const long w = 2L * (Vs - V);
+  const long n = (nplanes / 2) * w;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
-    st64(base + (e / w) * Vs + V + (e % w), Cx<double>{0.0, 0.0});
+    st64(base + (e / w) * 2L * Vs + 2L * V + (e % w), Cx<double>{0.0, 0.0});
 }
 
 void launch_zero_pad(void* base, bool f32, long nplanes, const Geometry& g, hipStream_t s) {
-  const long n = nplanes * (g.Vs - g.V);
+  const long n = (nplanes / 2) * 2L * (g.Vs - g.V);
   if (n <= 0) return;
   if (f32)
     hipLaunchKernelGGL(k_zero_pad<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, (float2*)base, nplanes, g.V, g.Vs);
@@ -88,16 +92,18 @@ void launch_zero_pad(void* base, bool f32, long nplanes, const Geometry& g, hipS
     hipLaunchKernelGGL(k_zero_pad<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, (double2*)base, nplanes, g.V, g.Vs);
 }
 
-// Links: canonical [V][4][3][3] -> [4][9][V], with the boundary sign folded in.
+// Links: canonical [V][4][3][3] -> the packed layout of lidx, with the
+// boundary sign folded in; pad sites and the unused slot are zero.
 template <typename T2>
 __global__ void k_pack_links(const double2* __restrict__ canon, T2* __restrict__ links, Geometry g,
                              int bc0, int bc1, int bc2, int bc3) {
-  const long n = 4L * 9 * g.Vs;
+  const long n = 4L * kLinkSlots * g.Vs;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    const int s = (int)(e % g.Vs);
-    const int ne = (int)(e / g.Vs);
-    const int nu = ne / 9, ent = ne % 9;
-    if (s >= g.V) {
+    const long t = e >> 1;
+    const int s = (int)(t % g.Vs);
+    const int np = (int)(t / g.Vs);
+    const int nu = np / 5, ent = 2 * (np % 5) + (int)(e & 1);
+    if (s >= g.V || ent >= 9) {
       st64(links + e, Cx<double>{0.0, 0.0});
       continue;
     }
@@ -116,7 +122,7 @@ __global__ void k_pack_links(const double2* __restrict__ canon, T2* __restrict__
 
 void launch_pack_links(const double2* canon, void* links, bool f32, const Geometry& g,
                        const int bc[4], hipStream_t s) {
-  long n = 4L * 9 * g.Vs;
+  long n = 4L * kLinkSlots * g.Vs;
   if (f32)
     hipLaunchKernelGGL(k_pack_links<float2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon,
                        (float2*)links, g, bc[0], bc[1], bc[2], bc[3]);
@@ -129,9 +135,10 @@ template <typename T2, typename R>
 __device__ __forceinline__ void load_spinor(const T2* __restrict__ f, int V, int site, bool g5,
                                             Cx<R> (&p)[12]) {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    p[c] = ld(f + (long)c * V + site);
-    if (g5 && c >= 6) p[c] = -p[c];
+  for (int q = 0; q < 6; ++q) ld_pair(f + fidx(2 * q, site, V), p[2 * q], p[2 * q + 1]);
+  if (g5) {
+#pragma unroll
+    for (int c = 6; c < 12; ++c) p[c] = -p[c];
   }
 }
 
@@ -139,20 +146,21 @@ template <typename T2, typename R>
 __device__ __forceinline__ void load_link(const T2* __restrict__ links, int V, int nu, int site,
                                           Cx<R> (&u)[9]) {
 #pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = ld(links + (long)(nu * 9 + e) * V + site);
+  for (int q = 0; q < 4; ++q) ld_pair(links + lidx(nu, 2 * q, site, V), u[2 * q], u[2 * q + 1]);
+  u[8] = ld(links + lidx(nu, 8, site, V));
 }
 
-// Store that marks the line as streaming (not kept for reuse in L2).
-__device__ __forceinline__ void st_nt(float2* p, Cx<float> a) {
-  typedef float v2 __attribute__((ext_vector_type(2)));
-  v2 v = {a.re, a.im};
-  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+// out[c] for c = 0..11 of one site, as six pair stores (streaming if nt).
+template <typename T2, typename R>
+__device__ __forceinline__ void store_spinor(T2* __restrict__ f, int V, int site, int nt,
+                                             const Cx<R> (&o)[12]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (nt) st_pair_nt(f + fidx(2 * q, site, V), o[2 * q], o[2 * q + 1]);
+    else st_pair(f + fidx(2 * q, site, V), o[2 * q], o[2 * q + 1]);
+  }
 }
-__device__ __forceinline__ void st_nt(double2* p, Cx<double> a) {
-  typedef double v2 __attribute__((ext_vector_type(2)));
-  v2 v = {a.re, a.im};
-  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
-}
+
 
 template <typename R> struct HopR;
 template <> struct HopR<double> {
@@ -231,11 +239,10 @@ k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::
       load_spinor(inb + (long)r * 12 * Vs, Vs, s, g5in, psi);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        Cx<R> o = psi[c] - acc[r][c];
-        if (g5out && c >= 6) o = -o;
-        if (nt) st_nt(outb + (long)r * 12 * Vs + (long)c * Vs + s, o);
-        else st(outb + (long)r * 12 * Vs + (long)c * Vs + s, o);
+        psi[c] = psi[c] - acc[r][c];
+        if (g5out && c >= 6) psi[c] = -psi[c];
       }
+      store_spinor(outb + (long)r * 12 * Vs, Vs, s, nt, psi);
     }
   }
 }
@@ -269,11 +276,10 @@ k_wilson_g(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>
   load_spinor(inr, Vs, s, g5in, psi);
 #pragma unroll
   for (int c = 0; c < 12; ++c) {
-    Cx<R> o = psi[c] - acc[0][c];
-    if (g5out && c >= 6) o = -o;
-    if (nt) st_nt(outr + (long)c * Vs + s, o);
-    else st(outr + (long)c * Vs + s, o);
+    psi[c] = psi[c] - acc[0][c];
+    if (g5out && c >= 6) psi[c] = -psi[c];
   }
+  store_spinor(outr, Vs, s, nt, psi);
 }
 
 // Dynamic LDS requests above the default per-workgroup limit need a
@@ -468,19 +474,18 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
         Cx<R> pv[12], pw[12];
         load_spinor(in_v + base, V, s, false, pv);
         load_spinor(in_w + base, V, s, false, pw);
+        Cx<R> t[12], sv[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-          Cx<R> t = pv[c] - accv[r][c];
-          Cx<R> sv = pw[c] - accw[r][c];
-          if (c >= 6) { t = -t; sv = -sv; }
-          if (nt) {
-            st_nt(out_t + base + (long)c * V + s, t);
-            st_nt(out_s + base + (long)c * V + s, sv);
-          } else {
-            st(out_t + base + (long)c * V + s, t);
-            st(out_s + base + (long)c * V + s, sv);
-          }
-          const Cx<double> t64 = {(double)t.re, (double)t.im};
+          t[c] = pv[c] - accv[r][c];
+          sv[c] = pw[c] - accw[r][c];
+          if (c >= 6) { t[c] = -t[c]; sv[c] = -sv[c]; }
+        }
+        store_spinor(out_t + base, V, s, nt, t);
+        store_spinor(out_s + base, V, s, nt, sv);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const Cx<double> t64 = {(double)t[c].re, (double)t[c].im};
           const Cx<double> w64 = {(double)pw[c].re, (double)pw[c].im};
           const Cx<double> p = cmulc(w64, t64);
           part[3 * r + 0] += p.re;
@@ -568,7 +573,7 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
       if (r < nsrc && live) {
         const T2* f = in + (long)slot[r] * 12 * V;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) plane[((op * B + r) * 12 + c) * 256 + ts] = f[(long)c * V + s];
+        for (int c = 0; c < 12; ++c) plane[((op * B + r) * 12 + c) * 256 + ts] = f[fidx(c, s, V)];
       }
     }
     __syncthreads();
@@ -638,10 +643,13 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
         }
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-          Cx<R> o = p[c] - acc[r][c];
-          if (c >= 6) o = -o;
-          if (nt) st_nt(out + base + (long)c * V + s, o);
-          else st(out + base + (long)c * V + s, o);
+          p[c] = p[c] - acc[r][c];
+          if (c >= 6) p[c] = -p[c];
+        }
+        store_spinor(out + base, V, s, nt, p);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const Cx<R> o = p[c];
           if (!op) {
             const Cx<double> t64 = {(double)o.re, (double)o.im};
             const Cx<double> w64 = {(double)pw[c].re, (double)pw[c].im};

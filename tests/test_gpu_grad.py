@@ -274,4 +274,10 @@ def test_vjp_gauge_identity(k):
     tc = float(np.real(np.vdot(y[0], Xc)))
     say(f"gauge identity k {k}: {tU:.10f} + {tb:.10f} + {tc:.10f} = {tU + tb + tc:.2e}")
     assert st == 0
-    assert abs(tU + tb + tc) <= 1e-9 * (abs(tU) + abs(tb) + abs(tc))
+    # k = 40: rounding only.  k = 400: the forward recurrences have lost
+    # biorthogonality and carry rounding noise of ~7e-8 relative in L (measured
+    # and stored with the 8^4 k = 400 fixture); the residual follows that noise.
+    f = np.load(os.path.join(GOLDEN, "gradient_8888_k400.npz"))
+    noise = float(f["noise"]) / abs(float(f["loss"]))
+    rtol = 1e-9 if k <= 40 else max(1e-9, 2.0 * noise)
+    assert abs(tU + tb + tc) <= rtol * (abs(tU) + abs(tb) + abs(tc))
