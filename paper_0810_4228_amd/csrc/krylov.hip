@@ -215,23 +215,41 @@ __global__ void __launch_bounds__(256) k_update(const T2* __restrict__ T, const 
   const T2* Ts = T + slot * slot_stride;
   const T2* Ss = S + slot * slot_stride;
   double v[4] = {0, 0, 0, 0};
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
-    Cx<double> vt = cmul(c1, ld64(Ts + e));
-    vt = cfma(c2, ld64(Vi + e), vt);
-    Cx<double> wt = cmul(d1, ld64(Ss + e));
-    wt = cfma(d2_, ld64(Wi + e), wt);
-    if (prev) {
-      vt = cfma(c3, ld64(Vm + e), vt);
-      wt = cfma(d3, ld64(Wm + e), wt);
+  // two adjacent complex elements per thread (one 16-byte access per vector in
+  // FP32); N is even (12 Vs)
+  for (long e = 2 * (blockIdx.x * (long)blockDim.x + threadIdx.x); e < N;
+       e += 2 * (long)gridDim.x * blockDim.x) {
+    Cx<double> vt[2], wt[2];
+    {
+      Cx<double> x0, x1, y0, y1;
+      ld_pair64(Ts + e, x0, x1);
+      ld_pair64(Vi + e, y0, y1);
+      vt[0] = cfma(c2, y0, cmul(c1, x0));
+      vt[1] = cfma(c2, y1, cmul(c1, x1));
+      ld_pair64(Ss + e, x0, x1);
+      ld_pair64(Wi + e, y0, y1);
+      wt[0] = cfma(d2_, y0, cmul(d1, x0));
+      wt[1] = cfma(d2_, y1, cmul(d1, x1));
+      if (prev) {
+        ld_pair64(Vm + e, x0, x1);
+        ld_pair64(Wm + e, y0, y1);
+        vt[0] = cfma(c3, x0, vt[0]);
+        vt[1] = cfma(c3, x1, vt[1]);
+        wt[0] = cfma(d3, y0, wt[0]);
+        wt[1] = cfma(d3, y1, wt[1]);
+      }
     }
-    st64_nt(Vn + e, vt);
-    st64_nt(Wn + e, wt);
-    const Cx<double> vr = round_to(Vn, vt), wr = round_to(Wn, wt);
-    const Cx<double> dl = cmulc(wr, vr);
-    v[0] += dl.re;
-    v[1] += dl.im;
-    v[2] += cnorm2(vr);
-    v[3] += cnorm2(wr);
+    st_pair64_nt(Vn + e, vt[0], vt[1]);
+    st_pair64_nt(Wn + e, wt[0], wt[1]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const Cx<double> vr = round_to(Vn, vt[q]), wr = round_to(Wn, wt[q]);
+      const Cx<double> dl = cmulc(wr, vr);
+      v[0] += dl.re;
+      v[1] += dl.im;
+      v[2] += cnorm2(vr);
+      v[3] += cnorm2(wr);
+    }
   }
   block_sum<4>(v, lds);
   if (threadIdx.x == 0)

@@ -128,6 +128,24 @@ __device__ __forceinline__ void st_pair_nt(double2* p, Cx<double> a, Cx<double> 
   __builtin_nontemporal_store(vb, reinterpret_cast<v2*>(p + 1));
 }
 
+// A pair of stored values as FP64, and a pair stored in storage precision
+// (streaming), for the elementwise kernels.
+__device__ __forceinline__ void ld_pair64(const float2* p, Cx<double>& a, Cx<double>& b) {
+  Cx<float> x, y;
+  ld_pair(p, x, y);
+  a = {(double)x.re, (double)x.im};
+  b = {(double)y.re, (double)y.im};
+}
+__device__ __forceinline__ void ld_pair64(const double2* p, Cx<double>& a, Cx<double>& b) {
+  ld_pair(p, a, b);
+}
+__device__ __forceinline__ void st_pair64_nt(float2* p, Cx<double> a, Cx<double> b) {
+  st_pair_nt(p, Cx<float>{(float)a.re, (float)a.im}, Cx<float>{(float)b.re, (float)b.im});
+}
+__device__ __forceinline__ void st_pair64_nt(double2* p, Cx<double> a, Cx<double> b) {
+  st_pair_nt(p, a, b);
+}
+
 __device__ __forceinline__ Cx<double> c64(double2 v) { return {v.x, v.y}; }
 __device__ __forceinline__ double2 d2(Cx<double> a) { return make_double2(a.re, a.im); }
 __device__ __forceinline__ Cx<double> cdiv(Cx<double> a, Cx<double> b) {
