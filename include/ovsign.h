@@ -138,7 +138,10 @@ ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int
  *  Lanczos dual-stencil shape = 100*rhs block + 10*variant + streaming stores
  *  (variant 1: one thread computes A v and A^dag w; 2: a lane pair splits the two
  *  operators; 3: as 2 with the tile's spinors staged in LDS, rhs block <= 2 in
- *  FP32, 1 in FP64), its workgroup size, its LDS cap KiB, its block order}. */
+ *  FP32, 1 in FP64; 4: one operator per workgroup, the two workgroups of a tile
+ *  adjacent on one XCD; 5: as 4 with the tile's spinors staged in LDS), its
+ *  workgroup size (512 for variants 2 and 3, else 256), its LDS cap KiB, its
+ *  block order}. */
 ovs_status ovs_get_tuning_ex(ovs_lattice lat, int32_t nrhs, int32_t out[8]);
 /* Install a configuration in the encoding of ovs_get_tuning_ex (e.g. one saved
  * from an earlier ovs_autotune).  OVS_ERR_ARG for values the kernels do not

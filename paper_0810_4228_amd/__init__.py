@@ -250,7 +250,8 @@ class Lattice:
         st.update(rhs_block=shape // 100, lanes_per_site=(shape // 10) % 10, streaming_store=shape % 10)
         du = dict(zip(keys, out[4:8]))
         shape = du["rhs_block"]
-        variants = {1: "one thread per site", 2: "lane pair", 3: "lane pair, LDS-staged tile"}
+        variants = {1: "one thread per site", 2: "lane pair", 3: "lane pair, LDS-staged tile",
+                    4: "operator per workgroup", 5: "operator per workgroup, LDS-staged tile"}
         du.update(rhs_block=shape // 100, variant=variants.get((shape // 10) % 10, "?"),
                   streaming_store=shape % 10)
         return {"stencil": st, "dual": du}

@@ -453,7 +453,7 @@ ovs_status ovs_get_tuning_ex(ovs_lattice l, int32_t nrhs, int32_t out[8]) {
   if (!l || nrhs < 1 || !out) return OVS_ERR_ARG;
   const Tuning t = get_tuning(l, nrhs), d = get_dual_tuning(l, nrhs);
   out[0] = t.rhs_block * 100 + t.g * 10 + t.nt; out[1] = t.wg; out[2] = t.lds_kb; out[3] = t.order;
-  out[4] = d.rhs_block * 100 + d.g * 10 + d.nt; out[5] = d.g == 1 ? 256 : 512; out[6] = d.lds_kb;
+  out[4] = d.rhs_block * 100 + d.g * 10 + d.nt; out[5] = (d.g == 2 || d.g == 3) ? 512 : 256; out[6] = d.lds_kb;
   out[7] = d.order;
   return OVS_OK;
 }
@@ -478,7 +478,7 @@ ovs_status ovs_set_tuning_ex(ovs_lattice l, int32_t nrhs, const int32_t cfg[8]) 
                           : (t.rhs_block >= 1 && t.rhs_block <= 3);
   const bool g_ok = t.g == 1 || ((t.g == 2 || t.g == 4 || t.g == 8) && t.rhs_block == 1);
   const bool wg_ok = t.wg == 64 || t.wg == 128 || t.wg == 256;
-  const bool d_ok = d.rhs_block >= 1 && d.rhs_block <= (f32 ? 4 : 2) && d.g >= 1 && d.g <= 3 &&
+  const bool d_ok = d.rhs_block >= 1 && d.rhs_block <= (f32 ? 4 : 2) && d.g >= 1 && d.g <= 5 &&
                     (d.g != 3 || d.rhs_block <= (f32 ? 2 : 1));
   if (!blk_ok || !g_ok || !wg_ok || !d_ok || t.nt < 0 || t.nt > 1 || d.nt < 0 || d.nt > 1 ||
       t.lds_kb < 0 || t.lds_kb >= l->lds_max_kb || d.lds_kb < 0 || d.lds_kb >= l->lds_max_kb ||
@@ -568,7 +568,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
         const Hop hA = make_hop(l->m_w, l->mu), hAd = make_hop(l->m_w, -l->mu);
         Tuning dbest;
         double bms = 1e300;
-        for (int pair = 0; pair < 3; ++pair)
+        for (int pair = 0; pair < 5; ++pair)
         for (int bb = 1; bb <= (f32 ? 4 : 2); ++bb) {
           if (bb > nrhs && bb != 1) continue;
           for (int kb : lds_candidates(l))

@@ -168,7 +168,9 @@ struct DualArgs {
   int order;
   int nt;              // streaming stores of T and S
   int pair = 0;        // 1: lane pairs split the two operators (k_dual_pair);
-                       // 2: the same with the tile's spinors staged in LDS
+                       // 2: the same with the tile's spinors staged in LDS;
+                       // 3: one operator per workgroup (k_dual_op); 4: the
+                       // same with the tile's spinors staged in LDS
 };
 hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
                        const Hop& hAd, int rhs_block, hipStream_t s);
