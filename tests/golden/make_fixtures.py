@@ -2,7 +2,7 @@
 
 Calls only the CPU oracle (oracle/) and the seeded input generators (synth/);
 nothing here touches the HIP library.  Re-run with
-    python tests/golden/make_fixtures.py [lattice_4444] [gradient_8888]
+    python tests/golden/make_fixtures.py [lattice_4444] [gradient_8888] [sign_16x16x16x32]
 (both when no name is given) after any change to the oracle's arithmetic.
 
 lattice_4444.npz -- the 4^4 workload: links P_SU3(1 + 0.4 G) (seed 0),
@@ -24,6 +24,13 @@ gradient_8888_k150.npz, gradient_8888_k400.npz -- the gradient workload: 8^4,
     (biorthogonality is lost), so its differences are central ones at
     h = 1e-3; at k = 150 it is ~1e-12 and the differences are Richardson
     extrapolations (4 D(h/2) - D(h))/3 of central ones at h = 1e-5.
+
+sign_16x16x16x32.npz -- the benchmark workload: 16^3 x 32, links
+    P_SU3(1 + 0.6 G) (seed 0), m_w = -1.5, mu = 0.4, the first two of the 12
+    Gaussian sources (seed 1).  The oracle's two-sided Lanczos (CSR, FP64,
+    two-pass, no deflation) at k = 650 and k = 700 for each source: 4096
+    sampled entries of y (fixed positions, default_rng(7)) and the full
+    norms; their difference bounds the reference's own error.
 """
 import os
 import sys
@@ -109,8 +116,49 @@ def gradient_8888():
     gradient_8888_at(400, 1e-3, False)
 
 
+def _sign16_source(r):
+    """One source of the 16^3 x 32 fixture: the oracle's two-sided Lanczos to
+    k = 700 (coefficients only), the inner sign of the leading 650 x 650 and
+    the full 700 x 700 tridiagonal matrix, and one replay sweep for each
+    (the steps of krylov.tsl_apply with two_pass, both k from one first pass:
+    the first 650 coefficients of the k = 700 run are those of a k = 650 run)."""
+    dims = (16, 16, 16, 32)
+    m_w, mu, eps = -1.5, 0.4, 0.6
+    U = synth.random_links(dims, eps, seed=synth.LINK_SEED)
+    b = synth.gaussian_sources(dims, 12, seed=synth.SOURCE_SEED)[r]
+    A = dirac.csr_A(dims, U, m_w, mu)
+    Ad = dirac.csr_A(dims, U, m_w, -mu)
+    del U
+    lr = krylov.two_sided_lanczos(lambda z: A @ z, lambda z: Ad @ z, b, b, 700, store=False)
+    assert lr.k == 700 and lr.status != "serious", (lr.k, lr.status)
+    ys = {}
+    for k in (650, 700):
+        x = np.zeros(700, dtype=np.complex128)
+        x[:k] = sign.sign_e1(krylov.tridiag(lr.alpha[:k], lr.beta[:k - 1], lr.gamma[:k - 1]))
+        ys[k] = lr.n_b * krylov.replay_combine(lambda z: A @ z, b / lr.n_b, lr, x)
+        print("source", r, "k", k, "norm", np.linalg.norm(ys[k]), flush=True)
+    return ys
+
+
+def sign_16x16x16x32():
+    from concurrent.futures import ProcessPoolExecutor
+    dims = (16, 16, 16, 32)
+    N = synth.volume(dims) * 12
+    idx = np.sort(np.random.default_rng(7).choice(N, 4096, replace=False))
+    out = {"dims": np.array(dims), "m_w": -1.5, "mu": 0.4, "eps": 0.6, "idx": idx,
+           "ks": np.array([650, 700])}
+    with ProcessPoolExecutor(2) as ex:
+        res = list(ex.map(_sign16_source, (0, 1)))
+    for r, ys in enumerate(res):
+        for k in (650, 700):
+            out[f"y{r}_k{k}"] = ys[k][idx]
+            out[f"norm{r}_k{k}"] = np.linalg.norm(ys[k])
+        out[f"ydiff{r}"] = np.linalg.norm(ys[700][idx] - ys[650][idx]) / np.linalg.norm(ys[700][idx])
+    np.savez_compressed(os.path.join(HERE, "sign_16x16x16x32.npz"), **out)
+
+
 if __name__ == "__main__":
-    names = sys.argv[1:] or ["lattice_4444", "gradient_8888"]
+    names = sys.argv[1:] or ["lattice_4444", "gradient_8888", "sign_16x16x16x32"]
     for name in names:
         if name == "gradient_8888_k150":
             gradient_8888_at(150, 1e-5, True)
