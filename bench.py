@@ -10,7 +10,10 @@ sgn(G_k) e_1 and the combination.  The workload (synthetic, seeded):
 sources, FP32 storage with FP64 coefficients, target relative error 1e-5.
 
 Prints one JSON line.  value = solves/s of the timed steps.  The roofline
-object is for the Wilson stencil kernel (HIP events on the library stream).
+object is for the dominant kernel of a solve, the dual stencil of the Lanczos
+step (A v~ and A^dag w~ with their partial sums), timed on the workload's 12
+sources with HIP events on the library stream; `stencil` gives the same for the
+plain Wilson stencil A x.
 vs_fp64_single_source solves the same sources one at a time on an FP64
 lattice (autotuned for one source), without and with graphs, and gives the
 batched FP32-storage rate over each.  cpu_baseline times the CPU oracle's
@@ -38,25 +41,40 @@ TOL = 1e-5
 KMAX = 1000
 
 
-# HBM bytes per launch of the tuned FP32 stencil on this workload, from the
+# HBM bytes per launch of the tuned FP32 kernels on this workload, from the
 # FETCH_SIZE / WRITE_SIZE counters scaled by a device copy of known size
-# (profiles/k_wilson_16x16x16x32_f32x12_hbm_counters.txt).  Reported only while
-# the kernel source is the one that was measured.
-STENCIL_TRAFFIC = {"source_sha256_prefix": "7d1481024a9d6166",
-                   "bytes_per_launch": 1.9998 * 182832.50 * 1024 + 1.0000 * 147456.00 * 1024}
+# (profiles/*_hbm_counters.txt).  Reported only while the kernel source is the
+# one that was measured.
+TRAFFIC = {
+    "stencil": {"source_sha256_prefix": "5a8ef8415c0cb354",
+                "bytes_per_launch": 1.9998 * 229499.41 * 1024 + 1.0000 * 147460.80 * 1024},
+    "dual": {"source_sha256_prefix": "5a8ef8415c0cb354",
+             "bytes_per_launch": 1.9998 * 204454.51 * 1024 + 1.0000 * 295197.64 * 1024},
+}
 
 
-def stencil_traffic():
+def measured_traffic(kind):
     import hashlib
+    t = TRAFFIC[kind]
+    if not t["source_sha256_prefix"]:
+        return None
     src = os.path.join(ROOT, "paper_0810_4228_amd", "csrc", "stencil.hip")
     try:
         with open(src, "rb") as fh:
             digest = hashlib.sha256(fh.read()).hexdigest()
     except OSError:
         return None
-    if digest.startswith(STENCIL_TRAFFIC["source_sha256_prefix"]):
-        return STENCIL_TRAFFIC["bytes_per_launch"]
-    return None
+    return t["bytes_per_launch"] if digest.startswith(t["source_sha256_prefix"]) else None
+
+
+def dual_kernel_name(du):
+    """Kernel symbol of the tuned dual-stencil variant (as rocprofv3 lists it)."""
+    b = du["rhs_block"]
+    return {"one thread per site": f"k_dual<float, {b}>",
+            "lane pair": f"k_dual_pair<float, {b}, false>",
+            "lane pair, LDS-staged tile": f"k_dual_pair<float, {b}, true>",
+            "operator per workgroup": f"k_dual_op<float, {b}, false>",
+            "operator per workgroup, LDS-staged tile": f"k_dual_op<float, {b}, true>"}.get(du["variant"], "?")
 
 
 def log(*a):
@@ -215,11 +233,19 @@ def main():
     st_bytes = stencil_bytes(V, NRHS, es)
     st_gbs = st_bytes / (ms_st * 1e-3) / 1e9
     log(f"bench: stencil {ms_st * 1e3:.1f} us/apply, {st_gbs:.0f} GB/s (block {rb}, wg {wg})")
+    # ---- dual stencil of the Lanczos step: the solve's dominant kernel ----
+    fi.dual_timed(20)
+    ms_du = fi.dual_timed(200)
+    du_bytes = dual_bytes(V, NRHS, es)
+    du_gbs = du_bytes / (ms_du * 1e-3) / 1e9
+    du_name = dual_kernel_name(tuning["dual"])
+    log(f"bench: dual stencil {du_name} {ms_du * 1e3:.1f} us/apply, {du_gbs:.0f} GB/s")
     fi.close()
     fo.close()
 
     if args.stencil_only:
-        print(json.dumps({"stencil_us": ms_st * 1e3, "stencil_gbps": st_gbs, "tuning": tuning}))
+        print(json.dumps({"stencil_us": ms_st * 1e3, "stencil_gbps": st_gbs,
+                          "dual_us": ms_du * 1e3, "dual_gbps": du_gbs, "tuning": tuning}))
         return
 
     # ---- sign solves ----
@@ -271,9 +297,13 @@ def main():
         "phase_ms": phase,
         "stencil": {"kernel": "k_wilson<float>", "us_per_apply": ms_st * 1e3, "gbps": st_gbs,
                     "frac_peak": st_gbs / HBM_PEAK_GBS, "rhs_block": rb, "wg": wg,
-                    "bytes_per_apply": st_bytes},
-        "roofline": {"bound": "hbm", "achieved": st_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": st_gbs / HBM_PEAK_GBS, "traffic": stencil_traffic()},
+                    "staged_tile": tuning["stencil"]["staged_tile"],
+                    "bytes_per_apply": st_bytes, "traffic": measured_traffic("stencil")},
+        "dual_stencil": {"kernel": du_name, "us_per_apply": ms_du * 1e3, "gbps": du_gbs,
+                         "frac_peak": du_gbs / HBM_PEAK_GBS, "bytes_per_apply": du_bytes},
+        "roofline": {"bound": "hbm", "kernel": du_name, "achieved": du_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": du_gbs / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("dual")},
     }
     if not args.no_compare:
         log("bench: FP64 single-source comparison")

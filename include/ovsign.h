@@ -127,15 +127,26 @@ ovs_status ovs_field_apply(ovs_lattice lat, ovs_op op, ovs_field in, ovs_field o
  * kernel time in milliseconds measured with HIP events on the lattice stream. */
 ovs_status ovs_field_apply_timed(ovs_lattice lat, ovs_op op, ovs_field in, ovs_field out,
                                  int32_t iters, double* ms_per_apply);
+/* Launch the tuned dual stencil of the two-sided Lanczos step (Section 4:
+ * A v~ and A^dag w~ with the partial sums of w~^dagger A v~ and |A v~|^2) for
+ * all nrhs sources of v, with v~ = w~ = v, `iters` times back to back into
+ * library workspace, and return the average kernel time in milliseconds
+ * measured with HIP events on the lattice stream.  v is only read.  For
+ * measurement; OVS_ERR_ARG for a field of another lattice or iters < 1. */
+ovs_status ovs_dual_apply_timed(ovs_lattice lat, ovs_field v, int32_t iters, double* ms_per_apply);
 /* Choose the RHS block and launch shape of the stencil for this nrhs by timing
  * the candidates (the choice is kept in the lattice handle). */
 ovs_status ovs_autotune(ovs_lattice lat, int32_t nrhs);
 /* Current tuned stencil configuration: rhs block and workgroup size. */
 ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int32_t* wg_size);
 /* Full tuned configuration for nrhs sources, host int32 [8]:
- * {stencil shape = 100*rhs block + 10*lanes per site + streaming stores,
+ * {stencil shape = 1000*staged tile + 100*rhs block + 10*lanes per site +
+ *  streaming stores (staged tile: the workgroup's own input spinors copied to
+ *  LDS, lanes per site 1 and rhs block <= 4 in FP32, <= 2 in FP64),
  *  stencil workgroup size, stencil LDS cap KiB, stencil block order,
  *  Lanczos dual-stencil shape = 100*rhs block + 10*variant + streaming stores
+ *  (bit 0: the dual stencil's outputs, bit 1: the new Lanczos vectors of the
+ *  update)
  *  (variant 1: one thread computes A v and A^dag w; 2: a lane pair splits the two
  *  operators; 3: as 2 with the tile's spinors staged in LDS, rhs block <= 2 in
  *  FP32, 1 in FP64; 4: one operator per workgroup, the two workgroups of a tile

@@ -41,7 +41,7 @@ OVS_VJP_STORE_BASIS = 1
 EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
     "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
-    "ovs_field_apply", "ovs_field_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
+    "ovs_field_apply", "ovs_field_apply_timed", "ovs_dual_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
     "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
 ]
@@ -106,6 +106,7 @@ def load():
         "ovs_field_export": [P, P],
         "ovs_field_apply": [P, I, P, P],
         "ovs_field_apply_timed": [P, I, P, P, I, DP],
+        "ovs_dual_apply_timed": [P, P, I, DP],
         "ovs_autotune": [P, I],
         "ovs_get_tuning": [P, I, IP, IP],
         "ovs_get_tuning_ex": [P, I, IP],
@@ -247,13 +248,14 @@ class Lattice:
         keys = ("rhs_block", "wg", "lds_kb", "order")
         st = dict(zip(keys, out[0:4]))
         shape = st["rhs_block"]
-        st.update(rhs_block=shape // 100, lanes_per_site=(shape // 10) % 10, streaming_store=shape % 10)
+        st.update(rhs_block=(shape // 100) % 10, lanes_per_site=(shape // 10) % 10,
+                  streaming_store=shape % 10, staged_tile=shape // 1000)
         du = dict(zip(keys, out[4:8]))
         shape = du["rhs_block"]
         variants = {1: "one thread per site", 2: "lane pair", 3: "lane pair, LDS-staged tile",
                     4: "operator per workgroup", 5: "operator per workgroup, LDS-staged tile"}
         du.update(rhs_block=shape // 100, variant=variants.get((shape // 10) % 10, "?"),
-                  streaming_store=shape % 10)
+                  streaming_store=shape % 2, update_streaming_store=(shape % 10) // 2)
         return {"stencil": st, "dual": du}
 
     def deflation_set(self, lam, R, L):
@@ -418,6 +420,14 @@ class Field:
         ms = ctypes.c_double()
         _check(self.lat._lib.ovs_field_apply_timed(self.lat._h, OPS[op], self._h, out._h, int(iters),
                                                    ctypes.byref(ms)), "ovs_field_apply_timed")
+        return ms.value
+
+    def dual_timed(self, iters):
+        """Average time (ms) of the tuned two-sided Lanczos dual stencil on this
+        field's sources (v~ = w~ = the field), HIP events on the lattice stream."""
+        ms = ctypes.c_double()
+        _check(self.lat._lib.ovs_dual_apply_timed(self.lat._h, self._h, int(iters), ctypes.byref(ms)),
+               "ovs_dual_apply_timed")
         return ms.value
 
 

@@ -73,9 +73,14 @@ __global__ void __launch_bounds__(256) k_defl_dots(const double2* __restrict__ R
   }
   block_sum<4 * kDeflRhs>(v, lds);
   if (threadIdx.x == 0) {
-    for (int q = 0; q < nr; ++q)
-      for (int t = 0; t < 4; ++t)
-        partials[(((long)j * nrhs + r0 + q) * nchunk + blockIdx.x) * 4 + t] = v[4 * q + t];
+    // compile-time bounds keep v[] in registers (a runtime bound indexes it
+    // dynamically, which puts it in scratch memory)
+#pragma unroll
+    for (int q = 0; q < kDeflRhs; ++q)
+      if (q < nr)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          partials[(((long)j * nrhs + r0 + q) * nchunk + blockIdx.x) * 4 + t] = v[4 * q + t];
   }
 }
 
@@ -174,6 +179,11 @@ __global__ void __launch_bounds__(256) k_alpha(const double* __restrict__ partia
 // v~ = sv_i T - alpha sv_i V~_i - gamma_{i-1} sv_{i-1} V~_{i-1}
 // w~ = sw_i S - conj(alpha) sw_i W~_i - conj(beta_{i-1}) sw_{i-1} W~_{i-1}
 // partials [slot][nwg][4] = (delta.re, delta.im, |v~|^2, |w~|^2)
+//
+// With apart != nullptr alpha is formed here instead of by k_alpha: every
+// workgroup reduces the dual stencil's partials of its source in k_alpha's
+// order (same workgroup size, so the same alpha to the last bit), and the
+// first workgroup of the source stores alpha and |t|^2.
 template <typename T2>
 __global__ void __launch_bounds__(256) k_update(const T2* __restrict__ T, const T2* __restrict__ S,
                                                 T2* __restrict__ basis, long basis_stride,
@@ -181,16 +191,38 @@ __global__ void __launch_bounds__(256) k_update(const T2* __restrict__ T, const 
                                                 CoefArrays co, const int* __restrict__ it,
                                                 const int* __restrict__ rhs_map,
                                                 const int* __restrict__ n_active,
-                                                double* __restrict__ partials, int two_pass_ring) {
+                                                double* __restrict__ partials, int two_pass_ring,
+                                                const double* __restrict__ apart, int anparts,
+                                                int nt) {
   __shared__ double lds[4 * 4];
+  __shared__ double abc[2];
   const int jj = blockIdx.y;
   if (jj >= *n_active) return;
   const int slot = rhs_map[jj];
   const int i = *it;
   const long ks = co.kmax;
-  const Cx<double> a = c64(co.alpha[slot * ks + i]);
   const double svi = co.sv[slot * (ks + 1) + i];
   const Cx<double> swi = c64(co.sw[slot * (ks + 1) + i]);
+  Cx<double> a;
+  if (apart) {
+    double av[3] = {0, 0, 0};
+    for (int p = threadIdx.x; p < anparts; p += blockDim.x)
+      for (int t = 0; t < 3; ++t) av[t] += apart[((long)slot * anparts + p) * 3 + t];
+    block_sum<3>(av, lds);
+    if (threadIdx.x == 0) {
+      const Cx<double> aa = scale(svi, cmulc(swi, Cx<double>{av[0], av[1]}));
+      abc[0] = aa.re;
+      abc[1] = aa.im;
+      if (blockIdx.x == 0) {
+        co.alpha[slot * ks + i] = d2(aa);
+        co.tnorm2[slot * ks + i] = svi * svi * av[2];
+      }
+    }
+    __syncthreads();
+    a = {abc[0], abc[1]};
+  } else {
+    a = c64(co.alpha[slot * ks + i]);
+  }
   const bool prev = i > 0;
   const double svm = prev ? co.sv[slot * (ks + 1) + i - 1] : 0.0;
   const Cx<double> swm = prev ? c64(co.sw[slot * (ks + 1) + i - 1]) : Cx<double>{0, 0};
@@ -239,8 +271,13 @@ __global__ void __launch_bounds__(256) k_update(const T2* __restrict__ T, const 
         wt[1] = cfma(d3, y1, wt[1]);
       }
     }
-    st_pair64_nt(Vn + e, vt[0], vt[1]);
-    st_pair64_nt(Wn + e, wt[0], wt[1]);
+    if (nt) {
+      st_pair64_nt(Vn + e, vt[0], vt[1]);
+      st_pair64_nt(Wn + e, wt[0], wt[1]);
+    } else {
+      st_pair64(Vn + e, vt[0], vt[1]);
+      st_pair64(Wn + e, wt[0], wt[1]);
+    }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const Cx<double> vr = round_to(Vn, vt[q]), wr = round_to(Wn, wt[q]);
@@ -296,6 +333,73 @@ __global__ void __launch_bounds__(256) k_beta(const double* __restrict__ partial
       co.gamma[slot * ks + i] = make_double2(0.0, 0.0);
       co.sv[slot * (ks + 1) + i + 1] = 0.0;
       co.sw[slot * (ks + 1) + i + 1] = make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// k_beta, the probe gather of the new V~_{i+1} (when probes != nullptr) and
+// the iteration advance in one launch of one workgroup per source slot.  The
+// last workgroup to finish (a ticket counter, reset by that workgroup, so it
+// is zero between launches) increments *it, after every workgroup has read it.
+template <typename T2>
+__global__ void __launch_bounds__(256) k_beta_tail(const double* __restrict__ partials, int nparts,
+                                                   CoefArrays co, int* __restrict__ it,
+                                                   const int* __restrict__ rhs_map,
+                                                   const int* __restrict__ n_active,
+                                                   int* __restrict__ ticket,
+                                                   const T2* __restrict__ basis, long basis_stride,
+                                                   long N, int ring, const int* __restrict__ idx,
+                                                   int P, double2* __restrict__ probes) {
+  __shared__ double lds[4 * 4];
+  const int jj = blockIdx.x;
+  const int i = *it;
+  if (jj < *n_active) {
+    const int slot = rhs_map[jj];
+    double v[4] = {0, 0, 0, 0};
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x)
+      for (int t = 0; t < 4; ++t) v[t] += partials[((long)slot * nparts + p) * 4 + t];
+    block_sum<4>(v, lds);
+    if (threadIdx.x == 0) {
+      const long ks = co.kmax;
+      const double bn = sqrt(v[2]), wn = sqrt(v[3]);
+      const Cx<double> delta = {v[0], v[1]};
+      const double tn = sqrt(co.tnorm2[slot * ks + i]);
+      int st_ = co.status[slot];
+      if (st_ == 0) {
+        if (!(bn > 1e-14 * tn)) st_ = 1;
+        else if (!(cabs1(delta) > 1e-13 * bn * wn)) st_ = 2;
+        if (st_ != 0) {
+          co.status[slot] = st_;
+          co.kstop[slot] = i + 1;
+        }
+      }
+      if (st_ == 0) {
+        const Cx<double> g = scale(1.0 / bn, delta);
+        co.beta[slot * ks + i] = bn;
+        co.gamma[slot * ks + i] = d2(g);
+        co.sv[slot * (ks + 1) + i + 1] = 1.0 / bn;
+        co.sw[slot * (ks + 1) + i + 1] = d2(cdiv(Cx<double>{1.0, 0.0}, Cx<double>{g.re, -g.im}));
+      } else {
+        co.beta[slot * ks + i] = 0.0;
+        co.gamma[slot * ks + i] = make_double2(0.0, 0.0);
+        co.sv[slot * (ks + 1) + i + 1] = 0.0;
+        co.sw[slot * (ks + 1) + i + 1] = make_double2(0.0, 0.0);
+      }
+    }
+    const int j = i + 1;
+    if (probes && j < co.kmax) {
+      const long sl = ring ? (j % 3) : j;
+      const T2* vb = basis + sl * basis_stride + (long)slot * N;
+      for (int p = threadIdx.x; p < P; p += blockDim.x)
+        probes[((long)slot * co.kmax + j) * P + p] = d2(ld64(vb + idx[p]));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(ticket, 1) == (int)gridDim.x - 1) {
+      *ticket = 0;
+      *it = i + 1;
     }
   }
 }
@@ -801,7 +905,9 @@ void launch_start(const double2* bR, const double2* bL, int nrhs, long N, double
                        bR, bL, sums, N, (double2*)V0, (double2*)W0);
 }
 
-int update_nwg(long N) { return chunks_for(N, 1024); }
+// 256 workgroups per source: each reduces the dual stencil's partials for alpha
+// first, so fewer and longer-running workgroups keep that head cheap.
+int update_nwg(long N) { return chunks_for(N, 256); }
 
 void launch_alpha(const double* partials, int nparts, const CoefArrays& co, const int* it,
                   const int* rhs_map, const int* n_active, int nslots, hipStream_t s) {
@@ -811,16 +917,31 @@ void launch_alpha(const double* partials, int nparts, const CoefArrays& co, cons
 
 void launch_update(bool f32, const void* T, const void* S, void* basis, long basis_stride,
                    void* wbuf, long N, const CoefArrays& co, const int* it, const int* rhs_map,
-                   const int* n_active, int nslots, double* partials, bool ring, hipStream_t s) {
+                   const int* n_active, int nslots, double* partials, bool ring,
+                   const double* apart, int anparts, int nt, hipStream_t s) {
   dim3 grid(update_nwg(N), nslots);
   if (f32)
     hipLaunchKernelGGL(k_update<float2>, grid, dim3(256), 0, s, (const float2*)T, (const float2*)S,
                        (float2*)basis, basis_stride, (float2*)wbuf, N, N, co, it, rhs_map, n_active,
-                       partials, (int)ring);
+                       partials, (int)ring, apart, anparts, nt);
   else
     hipLaunchKernelGGL(k_update<double2>, grid, dim3(256), 0, s, (const double2*)T,
                        (const double2*)S, (double2*)basis, basis_stride, (double2*)wbuf, N, N, co,
-                       it, rhs_map, n_active, partials, (int)ring);
+                       it, rhs_map, n_active, partials, (int)ring, apart, anparts, nt);
+}
+
+void launch_beta_tail(bool f32, const double* partials, int nparts, const CoefArrays& co, int* it,
+                      const int* rhs_map, const int* n_active, int nslots, int* ticket,
+                      const void* basis, long basis_stride, long N, bool ring, const int* idx,
+                      int P, double2* probes, hipStream_t s) {
+  if (f32)
+    hipLaunchKernelGGL(k_beta_tail<float2>, dim3(nslots), dim3(256), 0, s, partials, nparts, co, it,
+                       rhs_map, n_active, ticket, (const float2*)basis, basis_stride, N, (int)ring,
+                       idx, P, probes);
+  else
+    hipLaunchKernelGGL(k_beta_tail<double2>, dim3(nslots), dim3(256), 0, s, partials, nparts, co, it,
+                       rhs_map, n_active, ticket, (const double2*)basis, basis_stride, N, (int)ring,
+                       idx, P, probes);
 }
 
 void launch_beta(const double* partials, int nparts, const CoefArrays& co, const int* it,

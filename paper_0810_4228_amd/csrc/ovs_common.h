@@ -57,6 +57,7 @@ struct Tuning {
   int order = 0;         // 0: source blocks of a tile adjacent, 1: source block slowest
   int g = 1;             // lanes sharing one site (each lane one source); 1 = source blocking
   int nt = 0;            // streaming (non-temporal) stores of the output
+  int stage = 0;         // 1: the tile's input spinors staged in LDS (g = 1 only)
   bool tuned = false;
 };
 

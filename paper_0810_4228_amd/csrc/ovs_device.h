@@ -139,6 +139,12 @@ __device__ __forceinline__ void ld_pair64(const float2* p, Cx<double>& a, Cx<dou
 __device__ __forceinline__ void ld_pair64(const double2* p, Cx<double>& a, Cx<double>& b) {
   ld_pair(p, a, b);
 }
+__device__ __forceinline__ void st_pair64(float2* p, Cx<double> a, Cx<double> b) {
+  st_pair(p, Cx<float>{(float)a.re, (float)a.im}, Cx<float>{(float)b.re, (float)b.im});
+}
+__device__ __forceinline__ void st_pair64(double2* p, Cx<double> a, Cx<double> b) {
+  st_pair(p, a, b);
+}
 __device__ __forceinline__ void st_pair64_nt(float2* p, Cx<double> a, Cx<double> b) {
   st_pair_nt(p, Cx<float>{(float)a.re, (float)a.im}, Cx<float>{(float)b.re, (float)b.im});
 }

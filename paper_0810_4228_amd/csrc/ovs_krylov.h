@@ -20,9 +20,19 @@ void launch_start(const double2* bR, const double2* bL, int nrhs, long N, double
 int update_nwg(long N);
 void launch_alpha(const double* partials, int nparts, const CoefArrays& co, const int* it,
                   const int* rhs_map, const int* n_active, int nslots, hipStream_t s);
+// apart != nullptr: alpha is formed from the dual stencil's anparts partials
+// inside the update (k_alpha is then not launched).  nt: streaming stores of
+// the new vectors.
 void launch_update(bool f32, const void* T, const void* S, void* basis, long basis_stride,
                    void* wbuf, long N, const CoefArrays& co, const int* it, const int* rhs_map,
-                   const int* n_active, int nslots, double* partials, bool ring, hipStream_t s);
+                   const int* n_active, int nslots, double* partials, bool ring,
+                   const double* apart, int anparts, int nt, hipStream_t s);
+// beta, the probe gather (probes != nullptr) and the iteration advance in one
+// launch; *ticket must be zero before the first launch and stays zero after each.
+void launch_beta_tail(bool f32, const double* partials, int nparts, const CoefArrays& co, int* it,
+                      const int* rhs_map, const int* n_active, int nslots, int* ticket,
+                      const void* basis, long basis_stride, long N, bool ring, const int* idx,
+                      int P, double2* probes, hipStream_t s);
 void launch_beta(const double* partials, int nparts, const CoefArrays& co, const int* it,
                  const int* rhs_map, const int* n_active, int nslots, hipStream_t s);
 void launch_advance(int* it, hipStream_t s);

@@ -207,36 +207,109 @@ __device__ __forceinline__ void dir_hops(Cx<R> (&acc)[B][12], const T2* __restri
   }
 }
 
-template <typename R, int B>
+// Staged form of the hops of one direction: neighbours inside the workgroup's
+// tile come from the LDS copy `plane` ([source][component][tile site]).
+template <typename R, typename T2, int NU, int B>
+__device__ __forceinline__ void dir_hops_staged(Cx<R> (&acc)[B][12], const T2* __restrict__ links,
+                                                const T2* __restrict__ in, const T2* plane,
+                                                int site0, int wg, int V, int s, const Nbr& nb,
+                                                int nsrc, bool g5in, R cf, R cb) {
+  Cx<R> u[9];
+  Cx<R> psi[12];
+  auto nb_spinor = [&](int r, int n) {
+    const unsigned d = (unsigned)(n - site0);
+    if (d < (unsigned)wg) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const T2 v = plane[(r * 12 + c) * 256 + d];
+        psi[c] = (g5in && c >= 6) ? Cx<R>{-v.x, -v.y} : Cx<R>{v.x, v.y};
+      }
+    } else {
+      load_spinor(in + (long)r * 12 * V, V, n, g5in, psi);
+    }
+  };
+  load_link(links, V, NU, nb.b[NU], u);
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    if (r < nsrc) {
+      nb_spinor(r, nb.b[NU]);
+      hop<R, NU, +1, false>(acc[r], u, psi, cf);
+    }
+  }
+  load_link(links, V, NU, s, u);
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    if (r < nsrc) {
+      nb_spinor(r, nb.f[NU]);
+      hop<R, NU, -1, true>(acc[r], u, psi, cb);
+    }
+  }
+}
+
+// STAGE: the tile's own input spinors (wg consecutive sites) are first copied
+// to LDS with one coalesced load per component, and neighbours inside the
+// tile are read from there; on lattices with Lx Ly = wg = 256 a tile is an
+// xy-plane and only the z and t hops go to L2/HBM.
+template <typename R, int B, bool STAGE>
 __global__ void __launch_bounds__(256)
 k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T* __restrict__ in,
          typename Vec2<R>::T* __restrict__ out, Geometry g, HopR<R> hop_c, int nrhs, int g5in,
          int g5out, int nt, TileMap tm) {
   using T2 = typename Vec2<R>::T;
+  __shared__ T2 plane[STAGE ? B * 12 * 256 : 1];
   int site0, rb, tile;
-  if (!map_tile(blockIdx.x, tm, site0, rb, tile)) return;
+  if (!map_tile(blockIdx.x, tm, site0, rb, tile)) return;  // uniform over the workgroup
   const int s = site0 + threadIdx.x;
-  if (s >= g.V) return;
   const int r0 = rb * B;
   const int nsrc = min(B, nrhs - r0);
   const int Vs = g.Vs;
   const T2* inb = in + (long)r0 * 12 * Vs;
   T2* outb = out + (long)r0 * 12 * Vs;
+  if constexpr (STAGE) {
+    if (s < g.V) {
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        if (r < nsrc) {
+#pragma unroll
+          for (int c = 0; c < 12; ++c)
+            plane[(r * 12 + c) * 256 + threadIdx.x] = inb[(long)r * 12 * Vs + fidx(c, s, Vs)];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (s >= g.V) return;
   const Nbr nb = neighbours(s, g);
   Cx<R> acc[B][12];
 #pragma unroll
   for (int r = 0; r < B; ++r)
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
-  dir_hops<R, T2, 0, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[0], hop_c.bwd[0]);
-  dir_hops<R, T2, 1, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[1], hop_c.bwd[1]);
-  dir_hops<R, T2, 2, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
-  dir_hops<R, T2, 3, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+  if constexpr (STAGE) {
+    const int wg = blockDim.x;
+    dir_hops_staged<R, T2, 0, B>(acc, links, inb, plane, site0, wg, Vs, s, nb, nsrc, g5in, hop_c.fwd[0], hop_c.bwd[0]);
+    dir_hops_staged<R, T2, 1, B>(acc, links, inb, plane, site0, wg, Vs, s, nb, nsrc, g5in, hop_c.fwd[1], hop_c.bwd[1]);
+    dir_hops_staged<R, T2, 2, B>(acc, links, inb, plane, site0, wg, Vs, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
+    dir_hops_staged<R, T2, 3, B>(acc, links, inb, plane, site0, wg, Vs, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+  } else {
+    dir_hops<R, T2, 0, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[0], hop_c.bwd[0]);
+    dir_hops<R, T2, 1, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[1], hop_c.bwd[1]);
+    dir_hops<R, T2, 2, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
+    dir_hops<R, T2, 3, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+  }
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     if (r < nsrc) {
       Cx<R> psi[12];
-      load_spinor(inb + (long)r * 12 * Vs, Vs, s, g5in, psi);
+      if constexpr (STAGE) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          const T2 v = plane[(r * 12 + c) * 256 + threadIdx.x];
+          psi[c] = (g5in && c >= 6) ? Cx<R>{-v.x, -v.y} : Cx<R>{v.x, v.y};
+        }
+      } else {
+        load_spinor(inb + (long)r * 12 * Vs, Vs, s, g5in, psi);
+      }
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         psi[c] = psi[c] - acc[r][c];
@@ -268,10 +341,14 @@ k_wilson_g(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>
   Cx<R> acc[1][12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[0][c] = {R(0), R(0)};
-  dir_hops<R, T2, 0, 1>(acc, links, inr, Vs, s, nb, 1, g5in, hop_c.fwd[0], hop_c.bwd[0]);
-  dir_hops<R, T2, 1, 1>(acc, links, inr, Vs, s, nb, 1, g5in, hop_c.fwd[1], hop_c.bwd[1]);
-  dir_hops<R, T2, 2, 1>(acc, links, inr, Vs, s, nb, 1, g5in, hop_c.fwd[2], hop_c.bwd[2]);
-  dir_hops<R, T2, 3, 1>(acc, links, inr, Vs, s, nb, 1, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+  // a source count the optimiser cannot see: with a literal 1 the per-source
+  // guards fold away and every load of the site is hoisted (spills)
+  int one = 1;
+  __asm__ volatile("" : "+s"(one));
+  dir_hops<R, T2, 0, 1>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[0], hop_c.bwd[0]);
+  dir_hops<R, T2, 1, 1>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[1], hop_c.bwd[1]);
+  dir_hops<R, T2, 2, 1>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[2], hop_c.bwd[2]);
+  dir_hops<R, T2, 3, 1>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[3], hop_c.bwd[3]);
   Cx<R> psi[12];
   load_spinor(inr, Vs, s, g5in, psi);
 #pragma unroll
@@ -325,15 +402,28 @@ TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order) {
 template <typename R, int B>
 static hipError_t launch_w(const void* links, const void* in, void* out, int nrhs, const Geometry& g,
                      const Hop& hop_c, bool g5in, bool g5out, int wg, int lds_kb, int order,
-                     int nt, hipStream_t s) {
+                     int nt, bool stage, hipStream_t s) {
   using T2 = typename Vec2<R>::T;
+  // the staged tile takes B 12 256 values of LDS
+  constexpr bool kStage = B * 12 * 256 * sizeof(T2) <= 100 * 1024;
   const TileMap tm = make_tile_map(g, wg, (nrhs + B - 1) / B, order);
   static std::once_flag lds_set;  // launches may come from several host threads
-  std::call_once(lds_set, [] { apply_lds_limit((const void*)k_wilson<R, B>); });
-  if (!lds_fits((const void*)k_wilson<R, B>, lds_kb)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_wilson<R, B>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s, (const T2*)links,
-                     (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs, (int)g5in, (int)g5out,
-                     nt, tm);
+  std::call_once(lds_set, [] {
+    apply_lds_limit((const void*)k_wilson<R, B, false>);
+    if constexpr (kStage) apply_lds_limit((const void*)k_wilson<R, B, true>);
+  });
+  if constexpr (!kStage) {
+    if (stage) return hipErrorInvalidValue;
+  }
+  const void* fn = stage ? (const void*)k_wilson<R, B, kStage> : (const void*)k_wilson<R, B, false>;
+  if (!lds_fits(fn, lds_kb)) return hipErrorInvalidValue;
+#define OVS_W(ST)                                                                             \
+  hipLaunchKernelGGL((k_wilson<R, B, ST>), dim3(8 * tm.per_xcd), dim3(wg), lds_kb * 1024, s,  \
+                     (const T2*)links, (const T2*)in, (T2*)out, g, HopR<R>::make(hop_c), nrhs, \
+                     (int)g5in, (int)g5out, nt, tm)
+  if (stage) OVS_W(kStage);
+  else OVS_W(false);
+#undef OVS_W
   return hipSuccess;
 }
 
@@ -380,18 +470,18 @@ hipError_t launch_wilson(bool f32, const void* links, const void* in, void* out,
   }
   if (f32) {
     switch (tn.rhs_block) {
-      case 1: e = launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 2: e = launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 3: e = launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 4: e = launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 6: e = launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 1: e = launch_w<float, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, tn.stage != 0, s); break;
+      case 2: e = launch_w<float, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, tn.stage != 0, s); break;
+      case 3: e = launch_w<float, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, tn.stage != 0, s); break;
+      case 4: e = launch_w<float, 4>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, tn.stage != 0, s); break;
+      case 6: e = launch_w<float, 6>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, tn.stage != 0, s); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     switch (tn.rhs_block) {
-      case 1: e = launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 2: e = launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
-      case 3: e = launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, s); break;
+      case 1: e = launch_w<double, 1>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, tn.stage != 0, s); break;
+      case 2: e = launch_w<double, 2>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, tn.stage != 0, s); break;
+      case 3: e = launch_w<double, 3>(links, in, out, nrhs, g, hop_c, g5in, g5out, wg, tn.lds_kb, tn.order, tn.nt, tn.stage != 0, s); break;
       default: return hipErrorInvalidValue;
     }
   }

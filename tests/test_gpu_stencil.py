@@ -64,6 +64,38 @@ def test_multi_rhs_blocks(prec, nrhs):
     assert rel_rows(y, ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_every_stencil_configuration(prec):
+    """Every stencil configuration the autotuner can pick (source block, lanes
+    per site, LDS-staged tile, workgroup size, block order, streaming stores)
+    against the oracle, for all four operators (the staged tile must apply
+    gamma5 on input as the direct loads do): a ragged lattice (V = 576, not a
+    multiple of any tile) and 7 sources (ragged source blocks)."""
+    dims = (4, 4, 6, 6)
+    mu = 0.3
+    U = synth.random_links(dims, 0.6, seed=11)
+    b = synth.gaussian_sources(dims, 7, seed=12)
+    lat = lattice(dims, prec, U, mu)
+    base = lat.get_tuning_raw(7)
+    refs = {op: (oracle_op(dims, U, mu, op) @ b.T).T for op in ("A", "A_dag", "Dw", "Dw_dag")}
+    shapes = [(blk, 1, st) for blk in ((1, 2, 3, 4, 6) if prec == "f32" else (1, 2, 3))
+              for st in (0, 1) if st == 0 or blk <= (4 if prec == "f32" else 2)]
+    shapes += [(1, g, 0) for g in (2, 4, 8)]
+    n = 0
+    for blk, g, st in shapes:
+        for wg in (64, 128, 256):
+            for order, nt in ((0, 0), (1, 1)):
+                cfg = list(base)
+                cfg[0:4] = [1000 * st + 100 * blk + 10 * g + nt, wg, 0, order]
+                lat.set_tuning_raw(7, cfg)
+                for op, ref in refs.items():
+                    y = lat.apply(op, to_dev(b)).cpu().numpy()
+                    e = rel_rows(y, ref)
+                    assert e <= TOL[prec], (blk, g, st, wg, order, nt, op, e)
+                n += 1
+    say("stencil configurations", prec, n)
+
+
 def test_field_roundtrip_bitwise():
     import torch
     dims = (4, 4, 4, 4)
