@@ -171,6 +171,31 @@ def test_gamma5_hermiticity_dot():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
+def test_dual_timed_entry_point():
+    """ovs_dual_apply_timed: a positive time for a resident field that it leaves
+    unchanged, and OVS_ERR_ARG for iters < 1 and for a field of another lattice."""
+    import ctypes
+    import paper_0810_4228_amd as ovs
+    dims = (4, 4, 4, 8)
+    U = synth.random_links(dims, 0.6, seed=21)
+    b = synth.gaussian_sources(dims, 3, seed=22)
+    lat = lattice(dims, "f32", U, 0.2)
+    other = lattice(dims, "f32", U, 0.2)
+    f = lat.field_create(3)
+    f.import_(to_dev(b))
+    before = f.export().cpu().numpy()
+    assert f.dual_timed(5) > 0
+    assert np.array_equal(f.export().cpu().numpy(), before)
+    with pytest.raises(ovs.OvsError) as e:
+        f.dual_timed(0)
+    assert e.value.status == ovs.OVS_ERR_ARG
+    g = other.field_create(3)
+    ms = ctypes.c_double()
+    assert lat._lib.ovs_dual_apply_timed(lat._h, g._h, 1, ctypes.byref(ms)) == ovs.OVS_ERR_ARG
+    f.close()
+    g.close()
+
+
 def test_argument_errors():
     import paper_0810_4228_amd as ovs
     import torch
