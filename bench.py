@@ -46,10 +46,10 @@ KMAX = 1000
 # (profiles/*_hbm_counters.txt).  Reported only while the kernel source is the
 # one that was measured.
 TRAFFIC = {
-    "stencil": {"source_sha256_prefix": "5a8ef8415c0cb354",
-                "bytes_per_launch": 1.9998 * 229499.41 * 1024 + 1.0000 * 147460.80 * 1024},
-    "dual": {"source_sha256_prefix": "5a8ef8415c0cb354",
-             "bytes_per_launch": 1.9998 * 204454.51 * 1024 + 1.0000 * 295197.64 * 1024},
+    "stencil": {"source_sha256_prefix": "8855166c6d848856",
+                "bytes_per_launch": 1.9998 * 229391.64 * 1024 + 1.0000 * 147457.98 * 1024},
+    "dual": {"source_sha256_prefix": "8855166c6d848856",
+             "bytes_per_launch": 1.9998 * 204335.69 * 1024 + 1.0000 * 295196.24 * 1024},
 }
 
 
@@ -132,6 +132,35 @@ def free_field_check(ovs, torch, dev):
     errs = [float(np.linalg.norm(yc[r] - ref[r]) / np.linalg.norm(ref[r])) for r in range(2)]
     lat.close()
     return max(errs), [i["k_used"] for i in info]
+
+
+def launch_modes(ovs, torch, dev, lat, bt):
+    """Solves/s of captured graphs (the default) against persistent launches:
+    the benchmark workload, and 12 sources on an 8^4 lattice (launch-bound)."""
+    import synth
+    out = {}
+
+    def rate(lt, b, tol, **kw):
+        lt.sign_apply(b, KMAX, tol=[tol] * NRHS, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            lt.sign_apply(b, KMAX, tol=[tol] * NRHS, **kw)
+        torch.cuda.synchronize()
+        return 3 * NRHS / (time.perf_counter() - t0)
+
+    out["16x16x16x32_f32"] = {"graph": rate(lat, bt, TOL, graph=True),
+                              "persistent": rate(lat, bt, TOL, persistent=True)}
+    dims = (8, 8, 8, 8)
+    small = ovs.Lattice(dims, precision="f32")
+    small.set_links(torch.from_numpy(synth.random_links(dims, EPS, seed=synth.LINK_SEED)).to(dev))
+    small.set_params(MW, MU)
+    small.autotune(NRHS)
+    bs = torch.from_numpy(synth.gaussian_sources(dims, NRHS, seed=synth.SOURCE_SEED)).to(dev)
+    out["8x8x8x8_f32"] = {"graph": rate(small, bs, TOL, graph=True),
+                          "persistent": rate(small, bs, TOL, persistent=True)}
+    small.close()
+    return out
 
 
 def fp64_single_source(ovs, torch, dev, U, bt, y32, graph):
@@ -314,6 +343,10 @@ def main():
             cmp[key] = {"solves_per_s": rate, "ratio": value / rate, "max_rel_diff_vs_batched": diff}
             log(f"bench: {key}: {rate:.2f} solves/s, batched/this = {value / rate:.2f}")
         out["vs_fp64_single_source"] = cmp
+    if not args.no_compare:
+        log("bench: launch modes")
+        out["launch_modes"] = launch_modes(ovs, torch, dev, lat, bt)
+        log("bench: launch modes", out["launch_modes"])
     if not args.no_check:
         log("bench: free-field accuracy check")
         err, kf = free_field_check(ovs, torch, dev)

@@ -65,7 +65,8 @@ enum {
   OVS_FLAG_TWO_PASS = 1,  /* 2sL: do not store V_k; replay the recurrence (end of Section 5) */
   OVS_FLAG_GRAPH    = 4,  /* replay the Lanczos iterations as captured HIP graphs             */
   OVS_FLAG_OVERLAP  = 8,  /* return D_ov b = b + gamma5 sgn(A) b instead of sgn(A) b         */
-  OVS_FLAG_NO_SPLIT = 16  /* run a batch of 8 or more sources as one batch, not two halves    */
+  OVS_FLAG_NO_SPLIT = 16, /* run a batch of 8 or more sources as one batch, not two halves    */
+  OVS_FLAG_PERSISTENT = 32 /* 2sL: run the iterations in persistent cooperative launches      */
 };
 enum {
   OVS_VJP_STORE_BASIS = 1 /* ovs_sign_apply_vjp: keep both bases instead of recomputing them */
@@ -197,6 +198,14 @@ ovs_status ovs_deflation_destroy(ovs_deflation d);
  * Batches of 8 or more sources run as two halves at the same time, on the
  * handle's stream and on a second internal stream (each half with the whole
  * batch's tuned kernels); OVS_FLAG_NO_SPLIT runs them as one batch.
+ * OVS_FLAG_PERSISTENT (2sL; ignored by Arnoldi): the iterations between
+ * convergence checks run in cooperative launches of at most 25 iterations,
+ * each iteration's phases (dual stencil, alpha, update, beta) separated by
+ * grid barriers, with the one-operator-per-workgroup dual stencil at the
+ * tuned source block (at most 2 in FP32, 1 in FP64) and LDS staging; the
+ * batch is never split.  Results equal those of the per-step kernels with
+ * the same dual-stencil configuration bit for bit.  OVS_ERR_HIP when the
+ * device has no cooperative launch.
  * The inner function sgn(G_k) e_1 (or sgn(H_k) e_1) is evaluated on the GPU
  * in FP64.  Returns the most severe per-source warning, or an error. */
 ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, const void* b,

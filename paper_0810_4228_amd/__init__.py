@@ -36,6 +36,7 @@ OVS_FLAG_TWO_PASS = 1
 OVS_FLAG_GRAPH = 4
 OVS_FLAG_OVERLAP = 8
 OVS_FLAG_NO_SPLIT = 16
+OVS_FLAG_PERSISTENT = 32
 OVS_VJP_STORE_BASIS = 1
 
 EXPORTED = [
@@ -281,14 +282,17 @@ class Lattice:
         return Deflation(self, h, int(m)), st
 
     def sign_apply(self, b, k_max, defl=None, n_defl=None, tol=None, method="2sl",
-                   two_pass=False, graph=False, overlap=False, out=None, split=True):
+                   two_pass=False, graph=False, overlap=False, out=None, split=True,
+                   persistent=False):
         """y = sgn(A) b (or D_ov b with overlap=True).  Returns (y, infos, status).
-        split=False keeps a batch of 8 or more sources in one batch."""
+        split=False keeps a batch of 8 or more sources in one batch;
+        persistent=True runs the Lanczos iterations in persistent launches."""
         torch = _torch()
         b, nrhs = self._fields(b)
         y = torch.empty_like(b) if out is None else _dev_c128(out, "out")
         flags = (OVS_FLAG_TWO_PASS if two_pass else 0) | (OVS_FLAG_GRAPH if graph else 0) | \
-                (OVS_FLAG_OVERLAP if overlap else 0) | (0 if split else OVS_FLAG_NO_SPLIT)
+                (OVS_FLAG_OVERLAP if overlap else 0) | (0 if split else OVS_FLAG_NO_SPLIT) | \
+                (OVS_FLAG_PERSISTENT if persistent else 0)
         infos = (RhsInfo * nrhs)()
         tol_arr = None
         tol_p = None

@@ -823,7 +823,8 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || k_max < 1) return OVS_ERR_ARG;
   if (!ready(l)) return OVS_ERR_STATE;
   if (method != OVS_2SL && method != OVS_ARNOLDI) return OVS_ERR_ARG;
-  if (flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_OVERLAP | OVS_FLAG_NO_SPLIT))
+  if (flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_OVERLAP | OVS_FLAG_NO_SPLIT |
+                OVS_FLAG_PERSISTENT))
     return OVS_ERR_ARG;
   if (k_max > 12L * l->g.V) return OVS_ERR_ARG;
   const long N = 12L * l->g.Vs;  // padded field length of one source
@@ -835,7 +836,8 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   }
   const bool arn = method == OVS_ARNOLDI;
   const bool two_pass = (flags & OVS_FLAG_TWO_PASS) != 0;
-  const bool use_graph = (flags & OVS_FLAG_GRAPH) != 0;
+  const bool use_persist = (flags & OVS_FLAG_PERSISTENT) != 0;
+  const bool use_graph = (flags & OVS_FLAG_GRAPH) != 0 && !use_persist;
   if (arn && (two_pass || k_max > kHessMaxK)) return OVS_ERR_ARG;
   if (tol)
     for (int r = 0; r < nrhs; ++r)
@@ -859,6 +861,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     int *kstop, *status, *rhs_map, *ints, *kused, *pidx;
     unsigned char* swp;
     double2 *probes, *yp;
+    unsigned* bar;
   } B{};
   const bool probing = tol != nullptr && !arn;
   const int P = (int)std::min<long>(kProbe, 12L * l->g.V);
@@ -892,6 +895,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     B.status = a.take<int>(nr);
     B.rhs_map = a.take<int>(nr);
     B.ints = a.take<int>(4);
+    if (use_persist) B.bar = a.take<unsigned>(kPersistBarWords);
     B.kused = a.take<int>(nr);
     B.x = a.take<double2>((size_t)nr * K);
     B.qerr = a.take<double>(nr);
@@ -1017,10 +1021,12 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       OVS_HIP(hipStreamSynchronize(s));  // host vector lifetime
       return OVS_OK;
     };
-    // iteration counter and the tail kernel's ticket start at zero
+    // iteration counter and the tail kernel's ticket start at zero, and so do
+    // the persistent launches' barrier words
     const int zeros[3] = {0, 0, 0};
     OVS_HIP(hipMemcpyAsync(B.ints, zeros, sizeof(int), hipMemcpyHostToDevice, s));
     OVS_HIP(hipMemcpyAsync(B.ints + 2, zeros + 2, sizeof(int), hipMemcpyHostToDevice, s));
+    if (use_persist) OVS_HIP(hipMemsetAsync(B.bar, 0, sizeof(unsigned) * kPersistBarWords, s));
     ovs_status st = push_map();
     if (st != OVS_OK) return st;
     std::vector<int> pidx_h;
@@ -1072,6 +1078,15 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       int nfull = std::min(iend, K - 1) - i;
       if (nfull < 0) nfull = 0;
       int done_it = 0;
+      while (use_persist && done_it < nfull) {
+        const int n = std::min(chunk, nfull - done_it);
+        PersistArgs pa{l->links, B.basis, B.wbuf, bstride, two_pass, B.ints, B.T, B.S, B.part1,
+                       B.part2, B.rhs_map, B.ints + 1, nr, std::min(dual_b, f32 ? 2 : 1),
+                       dt.g == 5, dt.order, dt.nt & 1, (dt.nt >> 1) & 1, co, B.pidx, P,
+                       probing ? B.probes : nullptr, n, B.bar};
+        OVS_HIP(launch_persistent(f32, pa, l->g, hA, hAd, s));
+        done_it += n;
+      }
       if (use_graph && nfull >= chunk) {
         if (!gexec) {
           OVS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1132,6 +1147,17 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
         }
         st = push_map();
         if (st != OVS_OK) return st;
+      }
+    }
+    if (use_persist) {
+      unsigned berr = 0;
+      OVS_HIP(hipMemcpyAsync(&berr, B.bar + kPersistBarErr, sizeof(unsigned),
+                             hipMemcpyDeviceToHost, s));
+      OVS_HIP(hipStreamSynchronize(s));
+      if (berr) {
+        ovs::record_error("persistent Lanczos: a grid barrier wait ran out of polls", __LINE__,
+                          hipErrorLaunchFailure);
+        return OVS_ERR_HIP;
       }
     }
     OVS_HIP(hipEventRecord(ev[2], s));
@@ -1289,7 +1315,7 @@ static ovs_status worker_ready(ovs_lattice_s* l) {
 static ovs_status run_batch(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
                             void* y, int32_t nrhs, int32_t k_max, const double* tol,
                             ovs_method method, int32_t flags, ovs_rhs_info* info) {
-  if (nrhs < kSplitMin || (flags & OVS_FLAG_NO_SPLIT))
+  if (nrhs < kSplitMin || (flags & (OVS_FLAG_NO_SPLIT | OVS_FLAG_PERSISTENT)))
     return sign_apply_impl(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info, nrhs);
   if (!ready(l)) return OVS_ERR_STATE;
   ovs_status st = worker_ready(l);

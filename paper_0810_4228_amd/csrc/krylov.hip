@@ -9,6 +9,7 @@
 #include "ovs_common.h"
 #include "ovs_device.h"
 #include "ovs_krylov.h"
+#include "ovs_lanczos.h"
 
 namespace ovs {
 
@@ -153,37 +154,15 @@ __global__ void k_start_vectors(const double2* __restrict__ bR, const double2* _
 // in device memory (*it) so a captured chunk of iterations can be replayed.
 // ===========================================================================
 
-// alpha_i = conj(sw_i) sv_i (W~^dag A V~),  |t|^2 = sv_i^2 |A V~|^2
+// ---- per-step kernels (bodies in ovs_lanczos.h) ----------------------------
+
 __global__ void __launch_bounds__(256) k_alpha(const double* __restrict__ partials, int nparts,
                                                CoefArrays co, const int* __restrict__ it,
                                                const int* __restrict__ rhs_map,
                                                const int* __restrict__ n_active) {
-  __shared__ double lds[4 * 3];
-  const int jj = blockIdx.x;
-  if (jj >= *n_active) return;
-  const int slot = rhs_map[jj];
-  const int i = *it;
-  double v[3] = {0, 0, 0};
-  for (int p = threadIdx.x; p < nparts; p += blockDim.x)
-    for (int t = 0; t < 3; ++t) v[t] += partials[((long)slot * nparts + p) * 3 + t];
-  block_sum<3>(v, lds);
-  if (threadIdx.x == 0) {
-    const double sv = co.sv[(long)slot * (co.kmax + 1) + i];
-    const Cx<double> sw = c64(co.sw[(long)slot * (co.kmax + 1) + i]);
-    const Cx<double> a = scale(sv, cmulc(sw, Cx<double>{v[0], v[1]}));
-    co.alpha[(long)slot * co.kmax + i] = d2(a);
-    co.tnorm2[(long)slot * co.kmax + i] = sv * sv * v[2];
-  }
+  alpha_body(blockIdx.x, *it, partials, nparts, co, rhs_map, *n_active);
 }
 
-// v~ = sv_i T - alpha sv_i V~_i - gamma_{i-1} sv_{i-1} V~_{i-1}
-// w~ = sw_i S - conj(alpha) sw_i W~_i - conj(beta_{i-1}) sw_{i-1} W~_{i-1}
-// partials [slot][nwg][4] = (delta.re, delta.im, |v~|^2, |w~|^2)
-//
-// With apart != nullptr alpha is formed here instead of by k_alpha: every
-// workgroup reduces the dual stencil's partials of its source in k_alpha's
-// order (same workgroup size, so the same alpha to the last bit), and the
-// first workgroup of the source stores alpha and |t|^2.
 template <typename T2>
 __global__ void __launch_bounds__(256) k_update(const T2* __restrict__ T, const T2* __restrict__ S,
                                                 T2* __restrict__ basis, long basis_stride,
@@ -194,153 +173,14 @@ __global__ void __launch_bounds__(256) k_update(const T2* __restrict__ T, const 
                                                 double* __restrict__ partials, int two_pass_ring,
                                                 const double* __restrict__ apart, int anparts,
                                                 int nt) {
-  __shared__ double lds[4 * 4];
-  __shared__ double abc[2];
-  const int jj = blockIdx.y;
-  if (jj >= *n_active) return;
-  const int slot = rhs_map[jj];
-  const int i = *it;
-  const long ks = co.kmax;
-  const double svi = co.sv[slot * (ks + 1) + i];
-  const Cx<double> swi = c64(co.sw[slot * (ks + 1) + i]);
-  Cx<double> a;
-  if (apart) {
-    double av[3] = {0, 0, 0};
-    for (int p = threadIdx.x; p < anparts; p += blockDim.x)
-      for (int t = 0; t < 3; ++t) av[t] += apart[((long)slot * anparts + p) * 3 + t];
-    block_sum<3>(av, lds);
-    if (threadIdx.x == 0) {
-      const Cx<double> aa = scale(svi, cmulc(swi, Cx<double>{av[0], av[1]}));
-      abc[0] = aa.re;
-      abc[1] = aa.im;
-      if (blockIdx.x == 0) {
-        co.alpha[slot * ks + i] = d2(aa);
-        co.tnorm2[slot * ks + i] = svi * svi * av[2];
-      }
-    }
-    __syncthreads();
-    a = {abc[0], abc[1]};
-  } else {
-    a = c64(co.alpha[slot * ks + i]);
-  }
-  const bool prev = i > 0;
-  const double svm = prev ? co.sv[slot * (ks + 1) + i - 1] : 0.0;
-  const Cx<double> swm = prev ? c64(co.sw[slot * (ks + 1) + i - 1]) : Cx<double>{0, 0};
-  const Cx<double> gm = prev ? c64(co.gamma[slot * ks + i - 1]) : Cx<double>{0, 0};
-  const double bm = prev ? co.beta[slot * ks + i - 1] : 0.0;
-  const Cx<double> c1 = {svi, 0.0};
-  const Cx<double> c2 = scale(-svi, a);
-  const Cx<double> c3 = scale(-svm, gm);
-  const Cx<double> d1 = swi;
-  const Cx<double> d2_ = -cmulc(a, swi);           // -conj(alpha) sw_i
-  const Cx<double> d3 = scale(-bm, swm);           // -conj(beta) sw_{i-1}, beta real
-  // basis slots: ring of 3 in two-pass mode, else the full basis
-  const long vi = two_pass_ring ? (i % 3) : i;
-  const long vm = two_pass_ring ? ((i + 2) % 3) : (i - 1);
-  const long vn = two_pass_ring ? ((i + 1) % 3) : (i + 1);
-  const T2* Vi = basis + vi * basis_stride + slot * slot_stride;
-  const T2* Vm = basis + (prev ? vm : vi) * basis_stride + slot * slot_stride;
-  T2* Vn = basis + vn * basis_stride + slot * slot_stride;
-  const T2* Wi = wbuf + (long)(i % 3) * basis_stride + slot * slot_stride;
-  const T2* Wm = wbuf + (long)((i + 2) % 3) * basis_stride + slot * slot_stride;
-  T2* Wn = wbuf + (long)((i + 1) % 3) * basis_stride + slot * slot_stride;
-  const T2* Ts = T + slot * slot_stride;
-  const T2* Ss = S + slot * slot_stride;
-  double v[4] = {0, 0, 0, 0};
-  // two adjacent complex elements per thread (one 16-byte access per vector in
-  // FP32); N is even (12 Vs)
-  for (long e = 2 * (blockIdx.x * (long)blockDim.x + threadIdx.x); e < N;
-       e += 2 * (long)gridDim.x * blockDim.x) {
-    Cx<double> vt[2], wt[2];
-    {
-      Cx<double> x0, x1, y0, y1;
-      ld_pair64(Ts + e, x0, x1);
-      ld_pair64(Vi + e, y0, y1);
-      vt[0] = cfma(c2, y0, cmul(c1, x0));
-      vt[1] = cfma(c2, y1, cmul(c1, x1));
-      ld_pair64(Ss + e, x0, x1);
-      ld_pair64(Wi + e, y0, y1);
-      wt[0] = cfma(d2_, y0, cmul(d1, x0));
-      wt[1] = cfma(d2_, y1, cmul(d1, x1));
-      if (prev) {
-        ld_pair64(Vm + e, x0, x1);
-        ld_pair64(Wm + e, y0, y1);
-        vt[0] = cfma(c3, x0, vt[0]);
-        vt[1] = cfma(c3, x1, vt[1]);
-        wt[0] = cfma(d3, y0, wt[0]);
-        wt[1] = cfma(d3, y1, wt[1]);
-      }
-    }
-    if (nt) {
-      st_pair64_nt(Vn + e, vt[0], vt[1]);
-      st_pair64_nt(Wn + e, wt[0], wt[1]);
-    } else {
-      st_pair64(Vn + e, vt[0], vt[1]);
-      st_pair64(Wn + e, wt[0], wt[1]);
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const Cx<double> vr = round_to(Vn, vt[q]), wr = round_to(Wn, wt[q]);
-      const Cx<double> dl = cmulc(wr, vr);
-      v[0] += dl.re;
-      v[1] += dl.im;
-      v[2] += cnorm2(vr);
-      v[3] += cnorm2(wr);
-    }
-  }
-  block_sum<4>(v, lds);
-  if (threadIdx.x == 0)
-    for (int t = 0; t < 4; ++t) partials[((long)slot * gridDim.x + blockIdx.x) * 4 + t] = v[t];
+  update_body<T2>(blockIdx.x, blockIdx.y, gridDim.x, *it, T, S, basis, basis_stride, wbuf,
+                  slot_stride, N, co, rhs_map, *n_active, partials, two_pass_ring, apart, anparts,
+                  nt);
 }
 
-// beta_i = |v~|, gamma_i = delta / beta_i; breakdown tests of the reading in
-// the design notes (lucky: |v~| <= 1e-14 |A v_i|; serious: |delta| <= 1e-13 |v~||w~|).
-__global__ void __launch_bounds__(256) k_beta(const double* __restrict__ partials, int nparts,
-                                              CoefArrays co, const int* __restrict__ it,
-                                              const int* __restrict__ rhs_map,
-                                              const int* __restrict__ n_active) {
-  __shared__ double lds[4 * 4];
-  const int jj = blockIdx.x;
-  if (jj >= *n_active) return;
-  const int slot = rhs_map[jj];
-  const int i = *it;
-  double v[4] = {0, 0, 0, 0};
-  for (int p = threadIdx.x; p < nparts; p += blockDim.x)
-    for (int t = 0; t < 4; ++t) v[t] += partials[((long)slot * nparts + p) * 4 + t];
-  block_sum<4>(v, lds);
-  if (threadIdx.x == 0) {
-    const long ks = co.kmax;
-    const double bn = sqrt(v[2]), wn = sqrt(v[3]);
-    const Cx<double> delta = {v[0], v[1]};
-    const double tn = sqrt(co.tnorm2[slot * ks + i]);
-    int st_ = co.status[slot];
-    if (st_ == 0) {
-      if (!(bn > 1e-14 * tn)) st_ = 1;
-      else if (!(cabs1(delta) > 1e-13 * bn * wn)) st_ = 2;
-      if (st_ != 0) {
-        co.status[slot] = st_;
-        co.kstop[slot] = i + 1;
-      }
-    }
-    if (st_ == 0) {
-      const Cx<double> g = scale(1.0 / bn, delta);
-      co.beta[slot * ks + i] = bn;
-      co.gamma[slot * ks + i] = d2(g);
-      co.sv[slot * (ks + 1) + i + 1] = 1.0 / bn;
-      co.sw[slot * (ks + 1) + i + 1] = d2(cdiv(Cx<double>{1.0, 0.0}, Cx<double>{g.re, -g.im}));
-    } else {
-      co.beta[slot * ks + i] = 0.0;
-      co.gamma[slot * ks + i] = make_double2(0.0, 0.0);
-      co.sv[slot * (ks + 1) + i + 1] = 0.0;
-      co.sw[slot * (ks + 1) + i + 1] = make_double2(0.0, 0.0);
-    }
-  }
-}
-
-// k_beta, the probe gather of the new V~_{i+1} (when probes != nullptr) and
-// the iteration advance in one launch of one workgroup per source slot.  The
-// last workgroup to finish (a ticket counter, reset by that workgroup, so it
-// is zero between launches) increments *it, after every workgroup has read it.
+// beta_body for one source slot per workgroup, then the iteration advance:
+// the last workgroup to finish (a ticket counter, reset by that workgroup, so
+// it is zero between launches) increments *it, after every workgroup has read it.
 template <typename T2>
 __global__ void __launch_bounds__(256) k_beta_tail(const double* __restrict__ partials, int nparts,
                                                    CoefArrays co, int* __restrict__ it,
@@ -350,50 +190,9 @@ __global__ void __launch_bounds__(256) k_beta_tail(const double* __restrict__ pa
                                                    const T2* __restrict__ basis, long basis_stride,
                                                    long N, int ring, const int* __restrict__ idx,
                                                    int P, double2* __restrict__ probes) {
-  __shared__ double lds[4 * 4];
-  const int jj = blockIdx.x;
   const int i = *it;
-  if (jj < *n_active) {
-    const int slot = rhs_map[jj];
-    double v[4] = {0, 0, 0, 0};
-    for (int p = threadIdx.x; p < nparts; p += blockDim.x)
-      for (int t = 0; t < 4; ++t) v[t] += partials[((long)slot * nparts + p) * 4 + t];
-    block_sum<4>(v, lds);
-    if (threadIdx.x == 0) {
-      const long ks = co.kmax;
-      const double bn = sqrt(v[2]), wn = sqrt(v[3]);
-      const Cx<double> delta = {v[0], v[1]};
-      const double tn = sqrt(co.tnorm2[slot * ks + i]);
-      int st_ = co.status[slot];
-      if (st_ == 0) {
-        if (!(bn > 1e-14 * tn)) st_ = 1;
-        else if (!(cabs1(delta) > 1e-13 * bn * wn)) st_ = 2;
-        if (st_ != 0) {
-          co.status[slot] = st_;
-          co.kstop[slot] = i + 1;
-        }
-      }
-      if (st_ == 0) {
-        const Cx<double> g = scale(1.0 / bn, delta);
-        co.beta[slot * ks + i] = bn;
-        co.gamma[slot * ks + i] = d2(g);
-        co.sv[slot * (ks + 1) + i + 1] = 1.0 / bn;
-        co.sw[slot * (ks + 1) + i + 1] = d2(cdiv(Cx<double>{1.0, 0.0}, Cx<double>{g.re, -g.im}));
-      } else {
-        co.beta[slot * ks + i] = 0.0;
-        co.gamma[slot * ks + i] = make_double2(0.0, 0.0);
-        co.sv[slot * (ks + 1) + i + 1] = 0.0;
-        co.sw[slot * (ks + 1) + i + 1] = make_double2(0.0, 0.0);
-      }
-    }
-    const int j = i + 1;
-    if (probes && j < co.kmax) {
-      const long sl = ring ? (j % 3) : j;
-      const T2* vb = basis + sl * basis_stride + (long)slot * N;
-      for (int p = threadIdx.x; p < P; p += blockDim.x)
-        probes[((long)slot * co.kmax + j) * P + p] = d2(ld64(vb + idx[p]));
-    }
-  }
+  beta_body<T2>(blockIdx.x, i, partials, nparts, co, rhs_map, *n_active, basis, basis_stride, N,
+                ring, idx, P, probes);
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -942,12 +741,6 @@ void launch_beta_tail(bool f32, const double* partials, int nparts, const CoefAr
     hipLaunchKernelGGL(k_beta_tail<double2>, dim3(nslots), dim3(256), 0, s, partials, nparts, co, it,
                        rhs_map, n_active, ticket, (const double2*)basis, basis_stride, N, (int)ring,
                        idx, P, probes);
-}
-
-void launch_beta(const double* partials, int nparts, const CoefArrays& co, const int* it,
-                 const int* rhs_map, const int* n_active, int nslots, hipStream_t s) {
-  hipLaunchKernelGGL(k_beta, dim3(nslots), dim3(256), 0, s, partials, nparts, co, it, rhs_map,
-                     n_active);
 }
 
 void launch_probe_gather(bool f32, const void* basis, long basis_stride, long N, bool ring,

@@ -177,6 +177,40 @@ hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop
                        const Hop& hAd, int rhs_block, hipStream_t s);
 int dual_num_wg(const Geometry& g);
 
+// Persistent two-sided Lanczos: nit full iterations (dual stencil of the
+// operator-per-workgroup form, alpha, update, beta with probe gather) in one
+// cooperative launch; *it advances by nit.
+struct PersistArgs {
+  const void* links;
+  void* basis;
+  void* wbuf;
+  long basis_stride;
+  bool ring;
+  int* it;
+  void* T;
+  void* S;
+  double* part1;       // dual partials [slot][dual_num_wg][3]
+  double* part2;       // update partials [slot][update_nwg][4]
+  const int* rhs_map;
+  const int* n_active;
+  int nslots;
+  int rhs_block;       // sources per thread of the dual stencil (1, 2; FP64: 1)
+  bool stage;          // tile staged in LDS
+  int order;
+  int nt_dual;         // streaming stores of T and S
+  int nt_update;       // streaming stores of the new vectors
+  CoefArrays co;
+  const int* idx;      // probe positions (probes != nullptr)
+  int P;
+  double2* probes;
+  int nit;
+  unsigned* bar;       // kPersistBarWords barrier words, zero before the first launch
+};
+constexpr int kPersistBarWords = 352;
+constexpr int kPersistBarErr = 320;  // nonzero: a barrier wait ran out of polls
+hipError_t launch_persistent(bool f32, const PersistArgs& a, const Geometry& g, const Hop& hA,
+                             const Hop& hAd, hipStream_t s);
+
 }  // namespace ovs
 
 // ---- error helpers --------------------------------------------------------

@@ -188,6 +188,9 @@ struct TileMap {
   int rb_slow;     // source block is the slowest index
 };
 
+// Tile map of a launch with nrb source blocks and wg-site tiles (stencil.hip).
+TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order);
+
 __device__ __forceinline__ bool map_tile(int bid, const TileMap& m, int& site0, int& rb, int& tile) {
   const int q = (bid & 7) * m.per_xcd + (bid >> 3);
   if (q >= m.ntiles * m.nrb) return false;

@@ -33,8 +33,6 @@ void launch_beta_tail(bool f32, const double* partials, int nparts, const CoefAr
                       const int* rhs_map, const int* n_active, int nslots, int* ticket,
                       const void* basis, long basis_stride, long N, bool ring, const int* idx,
                       int P, double2* probes, hipStream_t s);
-void launch_beta(const double* partials, int nparts, const CoefArrays& co, const int* it,
-                 const int* rhs_map, const int* n_active, int nslots, hipStream_t s);
 void launch_advance(int* it, hipStream_t s);
 void launch_probe_gather(bool f32, const void* basis, long basis_stride, long N, bool ring,
                          const int* it, bool first, const int* idx, int P, int kmax,

@@ -111,4 +111,55 @@ __device__ __forceinline__ Nbr neighbours(int s, const Geometry& g) {
   return n;
 }
 
+// ---- field and link access (component-pair layout) ----------------------
+
+template <typename T2, typename R>
+__device__ __forceinline__ void load_spinor(const T2* __restrict__ f, int V, int site, bool g5,
+                                            Cx<R> (&p)[12]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) ld_pair(f + fidx(2 * q, site, V), p[2 * q], p[2 * q + 1]);
+  if (g5) {
+#pragma unroll
+    for (int c = 6; c < 12; ++c) p[c] = -p[c];
+  }
+}
+
+template <typename T2, typename R>
+__device__ __forceinline__ void load_link(const T2* __restrict__ links, int V, int nu, int site,
+                                          Cx<R> (&u)[9]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ld_pair(links + lidx(nu, 2 * q, site, V), u[2 * q], u[2 * q + 1]);
+  u[8] = ld(links + lidx(nu, 8, site, V));
+}
+
+// out[c] for c = 0..11 of one site, as six pair stores (streaming if nt).
+template <typename T2, typename R>
+__device__ __forceinline__ void store_spinor(T2* __restrict__ f, int V, int site, int nt,
+                                             const Cx<R> (&o)[12]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (nt) st_pair_nt(f + fidx(2 * q, site, V), o[2 * q], o[2 * q + 1]);
+    else st_pair(f + fidx(2 * q, site, V), o[2 * q], o[2 * q + 1]);
+  }
+}
+
+
+template <typename R> struct HopR;
+template <> struct HopR<double> {
+  double fwd[4], bwd[4];
+  static HopR make(const Hop& h) {
+    HopR r;
+    for (int i = 0; i < 4; ++i) { r.fwd[i] = h.fwd[i]; r.bwd[i] = h.bwd[i]; }
+    return r;
+  }
+};
+template <> struct HopR<float> {
+  float fwd[4], bwd[4];
+  static HopR make(const Hop& h) {
+    HopR r;
+    for (int i = 0; i < 4; ++i) { r.fwd[i] = h.f32_fwd[i]; r.bwd[i] = h.f32_bwd[i]; }
+    return r;
+  }
+};
+
 }  // namespace ovs

@@ -13,6 +13,7 @@
 
 #include "ovs_common.h"
 #include "ovs_device.h"
+#include "ovs_dual.h"
 #include "ovs_spin.h"
 
 namespace ovs {
@@ -130,55 +131,6 @@ void launch_pack_links(const double2* canon, void* links, bool f32, const Geomet
     hipLaunchKernelGGL(k_pack_links<double2>, dim3(grid_for(n)), dim3(kWG), 0, s, canon,
                        (double2*)links, g, bc[0], bc[1], bc[2], bc[3]);
 }
-
-template <typename T2, typename R>
-__device__ __forceinline__ void load_spinor(const T2* __restrict__ f, int V, int site, bool g5,
-                                            Cx<R> (&p)[12]) {
-#pragma unroll
-  for (int q = 0; q < 6; ++q) ld_pair(f + fidx(2 * q, site, V), p[2 * q], p[2 * q + 1]);
-  if (g5) {
-#pragma unroll
-    for (int c = 6; c < 12; ++c) p[c] = -p[c];
-  }
-}
-
-template <typename T2, typename R>
-__device__ __forceinline__ void load_link(const T2* __restrict__ links, int V, int nu, int site,
-                                          Cx<R> (&u)[9]) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) ld_pair(links + lidx(nu, 2 * q, site, V), u[2 * q], u[2 * q + 1]);
-  u[8] = ld(links + lidx(nu, 8, site, V));
-}
-
-// out[c] for c = 0..11 of one site, as six pair stores (streaming if nt).
-template <typename T2, typename R>
-__device__ __forceinline__ void store_spinor(T2* __restrict__ f, int V, int site, int nt,
-                                             const Cx<R> (&o)[12]) {
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    if (nt) st_pair_nt(f + fidx(2 * q, site, V), o[2 * q], o[2 * q + 1]);
-    else st_pair(f + fidx(2 * q, site, V), o[2 * q], o[2 * q + 1]);
-  }
-}
-
-
-template <typename R> struct HopR;
-template <> struct HopR<double> {
-  double fwd[4], bwd[4];
-  static HopR make(const Hop& h) {
-    HopR r;
-    for (int i = 0; i < 4; ++i) { r.fwd[i] = h.fwd[i]; r.bwd[i] = h.bwd[i]; }
-    return r;
-  }
-};
-template <> struct HopR<float> {
-  float fwd[4], bwd[4];
-  static HopR make(const Hop& h) {
-    HopR r;
-    for (int i = 0; i < 4; ++i) { r.fwd[i] = h.f32_fwd[i]; r.bwd[i] = h.f32_bwd[i]; }
-    return r;
-  }
-};
 
 // Accumulate all eight hops of one direction pair for B sources.
 template <typename R, typename T2, int NU, int B>
@@ -768,14 +720,8 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
   }
 }
 
-// Operator-per-workgroup variant: the launch holds two workgroups per tile
-// and source block, adjacent in dispatch order on the same XCD, one computing
-// T = A V~ and the other S = A^dag W~.  Each runs the single-operator stencil
-// (one thread per site, one set of accumulators per source), and the two
-// fetches of every link meet in that XCD's L2.  The A workgroup also reads
-// W~ at its own site for the partial sums; the A^dag workgroup writes none.
-// STAGE: as in k_dual_pair, the tile's spinors of the workgroup's own field
-// are copied to LDS first and in-tile neighbours read from there.
+// Operator-per-workgroup variant (body in ovs_dual.h, shared with the
+// persistent Lanczos kernel).
 template <typename R, int B, bool STAGE>
 __global__ void __launch_bounds__(256)
 k_dual_op(const typename Vec2<R>::T* __restrict__ links,
@@ -785,131 +731,8 @@ k_dual_op(const typename Vec2<R>::T* __restrict__ links,
           typename Vec2<R>::T* __restrict__ out_s, double* __restrict__ partials, Geometry g,
           HopR<R> hA, HopR<R> hAd, const int* __restrict__ rhs_map,
           const int* __restrict__ n_active, int nt, TileMap tm) {
-  using T2 = typename Vec2<R>::T;
-  __shared__ double lds[(256 / 64) * 3 * B];
-  __shared__ T2 plane[STAGE ? B * 12 * 256 : 1];  // [source][component][tile site]
-  // workgroups go round robin over the 8 XCDs: consecutive workgroups of one
-  // XCD alternate the operator over the same tile
-  const int op = (blockIdx.x >> 3) & 1;
-  const int vb = (int)(((blockIdx.x >> 4) << 3) | (blockIdx.x & 7));
-  int site0, rb, tile;
-  if (!map_tile(vb, tm, site0, rb, tile)) return;  // uniform over the workgroup
-  const int na = *n_active;
-  const int iter = *it;
-  const T2* in_v = basis + (long)(ring ? iter % 3 : iter) * basis_stride;
-  const T2* in_w = wbuf + (long)(iter % 3) * basis_stride;
-  const int j0 = rb * B;
-  if (j0 >= na) return;  // uniform over the workgroup
-  // opaque to the optimiser, as in k_dual_pair
-  int nsrc = min(B, na - j0);
-  __asm__ volatile("" : "+s"(nsrc));
-  const int s = site0 + threadIdx.x;
-  const bool live = s < g.V;
-  const int V = g.Vs;
-  const T2* in = op ? in_w : in_v;
-  T2* out = op ? out_s : out_t;
-  const HopR<R>& hc = op ? hAd : hA;
-  int slot[B];
-#pragma unroll
-  for (int r = 0; r < B; ++r) slot[r] = (r < nsrc) ? rhs_map[j0 + r] : 0;
-
-  if constexpr (STAGE) {
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      if (r < nsrc && live) {
-        const T2* f = in + (long)slot[r] * 12 * V;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) plane[(r * 12 + c) * 256 + threadIdx.x] = f[fidx(c, s, V)];
-      }
-    }
-    __syncthreads();
-  }
-  auto load_nb = [&](int r, int n, Cx<R>(&p)[12]) {
-    const unsigned d = (unsigned)(n - site0);
-    if (STAGE && d < 256u) {
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        const T2 v = plane[(r * 12 + c) * 256 + d];
-        p[c] = {v.x, v.y};
-      }
-    } else {
-      load_spinor(in + (long)slot[r] * 12 * V, V, n, false, p);
-    }
-  };
-
-  double part[3 * B];
-#pragma unroll
-  for (int q = 0; q < 3 * B; ++q) part[q] = 0.0;
-
-  if (live) {
-    const Nbr nb = neighbours(s, g);
-    Cx<R> acc[B][12];
-#pragma unroll
-    for (int r = 0; r < B; ++r)
-#pragma unroll
-      for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
-    Cx<R> u[9], psi[12];
-#define OVS_OP_DIR(NU)                                                                   \
-  load_link(links, V, NU, nb.b[NU], u);                                                  \
-  _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
-    if (r < nsrc) {                                                                      \
-      load_nb(r, nb.b[NU], psi);                                                         \
-      hop<R, NU, +1, false>(acc[r], u, psi, hc.fwd[NU]);                                 \
-    }                                                                                    \
-  }                                                                                      \
-  load_link(links, V, NU, s, u);                                                         \
-  _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
-    if (r < nsrc) {                                                                      \
-      load_nb(r, nb.f[NU], psi);                                                         \
-      hop<R, NU, -1, true>(acc[r], u, psi, hc.bwd[NU]);                                  \
-    }                                                                                    \
-  }
-    OVS_OP_DIR(0)
-    OVS_OP_DIR(1)
-    OVS_OP_DIR(2)
-    OVS_OP_DIR(3)
-#undef OVS_OP_DIR
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      if (r < nsrc) {
-        const long base = (long)slot[r] * 12 * V;
-        Cx<R> p[12];
-        load_nb(r, s, p);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          p[c] = p[c] - acc[r][c];
-          if (c >= 6) p[c] = -p[c];
-        }
-        store_spinor(out + base, V, s, nt, p);
-        if (!op) {
-          Cx<R> pw[12];
-          load_spinor(in_w + base, V, s, false, pw);
-#pragma unroll
-          for (int c = 0; c < 12; ++c) {
-            const Cx<double> t64 = {(double)p[c].re, (double)p[c].im};
-            const Cx<double> w64 = {(double)pw[c].re, (double)pw[c].im};
-            const Cx<double> q = cmulc(w64, t64);
-            part[3 * r + 0] += q.re;
-            part[3 * r + 1] += q.im;
-            part[3 * r + 2] += cnorm2(t64);
-          }
-        }
-      }
-    }
-  }
-  if (op) return;  // uniform over the workgroup: only the A workgroup sums
-  block_sum<3 * B>(part, lds);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      if (r < nsrc) {
-        double* p = partials + ((long)slot[r] * tm.ntiles + tile) * 3;
-        p[0] = part[3 * r + 0];
-        p[1] = part[3 * r + 1];
-        p[2] = part[3 * r + 2];
-      }
-    }
-  }
+  dual_op_body<R, B, STAGE>(blockIdx.x, *it, links, basis, wbuf, basis_stride, ring, out_t, out_s,
+                            partials, g, hA, hAd, rhs_map, *n_active, nt, tm);
 }
 
 int dual_num_wg(const Geometry& g) { return (g.V + 255) / 256; }

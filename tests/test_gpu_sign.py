@@ -277,6 +277,57 @@ def test_graph_equals_direct_bitwise():
         assert torch.equal(y2, y3)
 
 
+@pytest.mark.parametrize("prec,blk,variant", [("f64", 1, 4), ("f64", 1, 5), ("f32", 1, 5),
+                                               ("f32", 2, 4), ("f32", 2, 5)])
+def test_persistent_equals_per_step_bitwise(prec, blk, variant):
+    """The persistent launches (grid barriers between the phases of each
+    iteration) give the per-step kernels' result bit for bit, with the same
+    dual-stencil configuration: a ragged lattice (V = 576), 5 sources with
+    different tolerances (uneven stopping, the active map shrinking between
+    launches), one-pass and two-pass; and against the oracle's 2sL."""
+    import torch
+    dims = (4, 4, 6, 6)
+    mu = 0.3
+    U = synth.random_links(dims, 0.6, seed=91)
+    b = synth.gaussian_sources(dims, 5, seed=92)
+    lat = lattice(dims, prec, U, mu)
+    cfg = list(lat.get_tuning_raw(5))
+    cfg[4:8] = [100 * blk + 10 * variant + 3, 256, 0, 1]
+    lat.set_tuning_raw(5, cfg)
+    tol = [1e-4, 1e-6, 1e-5, 1e-6, 1e-4]
+    for two_pass in (False, True):
+        y1, i1, _ = lat.sign_apply(to_dev(b), 400, tol=tol, two_pass=two_pass)
+        y2, i2, _ = lat.sign_apply(to_dev(b), 400, tol=tol, two_pass=two_pass, persistent=True)
+        y3, i3, _ = lat.sign_apply(to_dev(b), 400, tol=tol, two_pass=two_pass, persistent=True)
+        say("persistent", prec, blk, variant, two_pass, [i["k_used"] for i in i2])
+        assert [i["k_used"] for i in i1] == [i["k_used"] for i in i2]
+        assert torch.equal(y1, y2) and torch.equal(y2, y3)
+    A = dirac.csr_A(dims, U, MW, mu)
+    k = 60
+    ref = np.stack([krylov.tsl_apply(lambda v: A @ v, lambda v: A.conj().T @ v, bb, k) for bb in b])
+    y, _, _ = lat.sign_apply(to_dev(b), k, persistent=True)
+    assert rel_rows(y.cpu().numpy(), ref) <= (3e-5 if prec == "f32" else 1e-10)
+
+
+def test_persistent_12_sources_equals_graph():
+    """12 FP32 sources on 8^4 (the staged operator-per-workgroup stencil with
+    two sources per thread): persistent launches against captured graphs of the
+    per-step kernels (one batch, so the same kernels run in the same order)."""
+    import torch
+    dims = (8, 8, 8, 8)
+    U = synth.random_links(dims, 0.6, seed=93)
+    b = to_dev(synth.gaussian_sources(dims, 12, seed=94))
+    lat = lattice(dims, "f32", U, 0.4)
+    cfg = list(lat.get_tuning_raw(12))
+    cfg[4:8] = [253, 256, 0, 0]
+    lat.set_tuning_raw(12, cfg)
+    y1, i1, _ = lat.sign_apply(b, 1000, tol=[1e-5] * 12, graph=True, split=False)
+    y2, i2, _ = lat.sign_apply(b, 1000, tol=[1e-5] * 12, persistent=True)
+    say("persistent 8^4 x 12", [i["k_used"] for i in i2])
+    assert [i["k_used"] for i in i1] == [i["k_used"] for i in i2]
+    assert torch.equal(y1, y2)
+
+
 def test_batched_equals_single():
     dims = (4, 4, 4, 4)
     U = synth.random_links(dims, 0.6, seed=55)
