@@ -13,7 +13,7 @@ with alpha_i = w_i^dagger A v_i and w_{i+1}^dagger v_{i+1} = 1, and
 Section 2 (Arnoldi, eq. (2.1)-(2.5)): orthonormal V_k, Hessenberg H_k = V^dagger A V,
     f(A) b ~= R_m f(Lambda_m) L_m^dagger b + |b_R| V_k f(H_k) e_1   (eq. Arnapp).
 
-Readings where the paper leaves a choice (listed with the design notes):
+Readings where the paper leaves a choice:
   * beta_i = ||v~||_2 (unit-norm v) and gamma_i = delta/beta_i with
     delta = w~^dagger v~; only beta_i gamma_i = delta is fixed by the text.
   * Deflated starts: v_1 = b_R/|b_R|, w_1 = b_L |b_R| / (b_L^dagger b_R)^*,

@@ -1114,7 +1114,9 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       }
       i = iend;
       if (tol && i < K) {
-        // convergence check at k = i (paper silent; reading in the design notes)
+        // convergence check at k = i (the paper gives no stopping rule): the
+        // relative change of y on the sampled entries since the previous check
+        // against tol / 10
         std::vector<int> ks(nr, 0);
         OVS_HIP(hipMemcpyAsync(hkstop.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
         OVS_HIP(hipStreamSynchronize(s));
