@@ -46,10 +46,10 @@ KMAX = 1000
 # (profiles/*_hbm_counters.txt).  Reported only while the kernel source is the
 # one that was measured.
 TRAFFIC = {
-    "stencil": {"source_sha256_prefix": "8855166c6d848856",
-                "bytes_per_launch": 1.9998 * 229391.64 * 1024 + 1.0000 * 147457.98 * 1024},
-    "dual": {"source_sha256_prefix": "8855166c6d848856",
-             "bytes_per_launch": 1.9998 * 204335.69 * 1024 + 1.0000 * 295196.24 * 1024},
+    "stencil": {"source_sha256_prefix": "45fd2bbcf65acb86",
+                "bytes_per_launch": 1.9998 * 203846.35 * 1024 + 1.0000 * 147461.43 * 1024},
+    "dual": {"source_sha256_prefix": "45fd2bbcf65acb86",
+             "bytes_per_launch": 1.9998 * 206562.10 * 1024 + 1.0000 * 295185.34 * 1024},
 }
 
 

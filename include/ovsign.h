@@ -89,7 +89,8 @@ typedef struct {
 /* ---- lattice ------------------------------------------------------------ */
 
 /* Create a lattice handle.  dims = {Lx, Ly, Lz, Lt}, each >= 2 and Lx*Ly*Lz*Lt
- * < 2^26; bc = {+-1, +-1, +-1, +-1}; prec selects the storage type of links
+ * <= 2^24 (the kernels address one source field with 32-bit byte offsets);
+ * bc = {+-1, +-1, +-1, +-1}; prec selects the storage type of links
  * and Krylov vectors (coefficients, dots and deflation are always FP64);
  * hip_stream is a hipStream_t (NULL = default stream).  Section 1 defines the
  * lattice operator this handle applies.  Errors: OVS_ERR_ARG for bad

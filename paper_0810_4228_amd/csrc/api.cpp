@@ -232,7 +232,7 @@ ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_pr
     if (bc[i] != 1 && bc[i] != -1) return OVS_ERR_ARG;
     v *= dims[i];
   }
-  if (v >= (1L << 26)) return OVS_ERR_ARG;
+  if (v > (1L << 24)) return OVS_ERR_ARG;  // 32-bit byte offsets within a source field
   if (prec != OVS_F64 && prec != OVS_F32_STORE) return OVS_ERR_ARG;
   ovs_lattice_s* l = new (std::nothrow) ovs_lattice_s();
   if (!l) return OVS_ERR_ALLOC;

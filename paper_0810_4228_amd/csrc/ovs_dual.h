@@ -60,8 +60,15 @@ __device__ __forceinline__ void dual_op_body(
     for (int r = 0; r < B; ++r) {
       if (r < nsrc && live) {
         const T2* f = in + (long)slot[r] * 12 * V;
+        constexpr unsigned e2 = 2 * sizeof(T2);
+        const __amdgpu_buffer_rsrc_t rs = uniform_rsrc(f, 6u * e2 * (unsigned)V);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) plane[(r * 12 + c) * 256 + threadIdx.x] = f[fidx(c, s, V)];
+        for (int q = 0; q < 6; ++q) {  // component pairs: one 16-byte load each in FP32
+          Cx<R> x0, x1;
+          ld_pair_rs(rs, (unsigned)s * e2, (unsigned)q * e2 * (unsigned)V, x0, x1);
+          plane[(r * 12 + 2 * q) * 256 + threadIdx.x] = T2{x0.re, x0.im};
+          plane[(r * 12 + 2 * q + 1) * 256 + threadIdx.x] = T2{x1.re, x1.im};
+        }
       }
     }
     __syncthreads();
@@ -75,7 +82,7 @@ __device__ __forceinline__ void dual_op_body(
         p[c] = {v.x, v.y};
       }
     } else {
-      load_spinor(in + (long)slot[r] * 12 * V, V, n, false, p);
+      load_spinor_u(in + (long)slot[r] * 12 * V, V, n, false, p);
     }
   };
 
@@ -92,14 +99,14 @@ __device__ __forceinline__ void dual_op_body(
       for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
     Cx<R> u[9], psi[12];
 #define OVS_OP_DIR(NU)                                                                   \
-  load_link(links, V, NU, nb.b[NU], u);                                                  \
+  load_link_u(links, V, NU, nb.b[NU], u);                                                  \
   _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
     if (r < nsrc) {                                                                      \
       load_nb(r, nb.b[NU], psi);                                                         \
       hop<R, NU, +1, false>(acc[r], u, psi, hc.fwd[NU]);                                 \
     }                                                                                    \
   }                                                                                      \
-  load_link(links, V, NU, s, u);                                                         \
+  load_link_u(links, V, NU, s, u);                                                         \
   _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
     if (r < nsrc) {                                                                      \
       load_nb(r, nb.f[NU], psi);                                                         \
@@ -125,7 +132,7 @@ __device__ __forceinline__ void dual_op_body(
         store_spinor(out + base, V, s, nt, p);
         if (!op) {
           Cx<R> pw[12];
-          load_spinor(in_w + base, V, s, false, pw);
+          load_spinor_u(in_w + base, V, s, false, pw);
 #pragma unroll
           for (int c = 0; c < 12; ++c) {
             const Cx<double> t64 = {(double)p[c].re, (double)p[c].im};

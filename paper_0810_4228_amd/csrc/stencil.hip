@@ -132,28 +132,33 @@ void launch_pack_links(const double2* canon, void* links, bool f32, const Geomet
                        (double2*)links, g, bc[0], bc[1], bc[2], bc[3]);
 }
 
-// Accumulate all eight hops of one direction pair for B sources.
-template <typename R, typename T2, int NU, int B>
+// Accumulate all eight hops of one direction pair for B sources.  UNI: `in`
+// is workgroup-uniform (buffer loads); otherwise per-lane global loads.
+template <typename R, typename T2, int NU, int B, bool UNI>
 __device__ __forceinline__ void dir_hops(Cx<R> (&acc)[B][12], const T2* __restrict__ links,
                                          const T2* __restrict__ in, int V, int s, const Nbr& nb,
                                          int nsrc, bool g5in, R cf, R cb) {
   Cx<R> u[9];
   Cx<R> psi[12];
   // forward hop: field from s - nu through U_nu(s - nu)
-  load_link(links, V, NU, nb.b[NU], u);
+  if constexpr (UNI) load_link_u(links, V, NU, nb.b[NU], u);
+  else load_link(links, V, NU, nb.b[NU], u);
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     if (r < nsrc) {
-      load_spinor(in + (long)r * 12 * V, V, nb.b[NU], g5in, psi);
+      if constexpr (UNI) load_spinor_u(in + (long)r * 12 * V, V, nb.b[NU], g5in, psi);
+      else load_spinor(in + (long)r * 12 * V, V, nb.b[NU], g5in, psi);
       hop<R, NU, +1, false>(acc[r], u, psi, cf);
     }
   }
   // backward hop: field from s + nu through U_nu(s)^dagger
-  load_link(links, V, NU, s, u);
+  if constexpr (UNI) load_link_u(links, V, NU, s, u);
+  else load_link(links, V, NU, s, u);
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     if (r < nsrc) {
-      load_spinor(in + (long)r * 12 * V, V, nb.f[NU], g5in, psi);
+      if constexpr (UNI) load_spinor_u(in + (long)r * 12 * V, V, nb.f[NU], g5in, psi);
+      else load_spinor(in + (long)r * 12 * V, V, nb.f[NU], g5in, psi);
       hop<R, NU, -1, true>(acc[r], u, psi, cb);
     }
   }
@@ -177,10 +182,10 @@ __device__ __forceinline__ void dir_hops_staged(Cx<R> (&acc)[B][12], const T2* _
         psi[c] = (g5in && c >= 6) ? Cx<R>{-v.x, -v.y} : Cx<R>{v.x, v.y};
       }
     } else {
-      load_spinor(in + (long)r * 12 * V, V, n, g5in, psi);
+      load_spinor_u(in + (long)r * 12 * V, V, n, g5in, psi);
     }
   };
-  load_link(links, V, NU, nb.b[NU], u);
+  load_link_u(links, V, NU, nb.b[NU], u);
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     if (r < nsrc) {
@@ -188,7 +193,7 @@ __device__ __forceinline__ void dir_hops_staged(Cx<R> (&acc)[B][12], const T2* _
       hop<R, NU, +1, false>(acc[r], u, psi, cf);
     }
   }
-  load_link(links, V, NU, s, u);
+  load_link_u(links, V, NU, s, u);
 #pragma unroll
   for (int r = 0; r < B; ++r) {
     if (r < nsrc) {
@@ -223,8 +228,12 @@ k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::
       for (int r = 0; r < B; ++r) {
         if (r < nsrc) {
 #pragma unroll
-          for (int c = 0; c < 12; ++c)
-            plane[(r * 12 + c) * 256 + threadIdx.x] = inb[(long)r * 12 * Vs + fidx(c, s, Vs)];
+          for (int q = 0; q < 6; ++q) {  // component pairs: one 16-byte load each in FP32
+            Cx<R> x0, x1;
+            ld_pair(pair_at(inb + (long)r * 12 * Vs + (long)q * 2 * Vs, s), x0, x1);
+            plane[(r * 12 + 2 * q) * 256 + threadIdx.x] = T2{x0.re, x0.im};
+            plane[(r * 12 + 2 * q + 1) * 256 + threadIdx.x] = T2{x1.re, x1.im};
+          }
         }
       }
     }
@@ -244,10 +253,10 @@ k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::
     dir_hops_staged<R, T2, 2, B>(acc, links, inb, plane, site0, wg, Vs, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
     dir_hops_staged<R, T2, 3, B>(acc, links, inb, plane, site0, wg, Vs, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
   } else {
-    dir_hops<R, T2, 0, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[0], hop_c.bwd[0]);
-    dir_hops<R, T2, 1, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[1], hop_c.bwd[1]);
-    dir_hops<R, T2, 2, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
-    dir_hops<R, T2, 3, B>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+    dir_hops<R, T2, 0, B, true>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[0], hop_c.bwd[0]);
+    dir_hops<R, T2, 1, B, true>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[1], hop_c.bwd[1]);
+    dir_hops<R, T2, 2, B, true>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[2], hop_c.bwd[2]);
+    dir_hops<R, T2, 3, B, true>(acc, links, inb, Vs, s, nb, nsrc, g5in, hop_c.fwd[3], hop_c.bwd[3]);
   }
 #pragma unroll
   for (int r = 0; r < B; ++r) {
@@ -260,7 +269,7 @@ k_wilson(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::
           psi[c] = (g5in && c >= 6) ? Cx<R>{-v.x, -v.y} : Cx<R>{v.x, v.y};
         }
       } else {
-        load_spinor(inb + (long)r * 12 * Vs, Vs, s, g5in, psi);
+        load_spinor_u(inb + (long)r * 12 * Vs, Vs, s, g5in, psi);
       }
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
@@ -297,10 +306,10 @@ k_wilson_g(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>
   // guards fold away and every load of the site is hoisted (spills)
   int one = 1;
   __asm__ volatile("" : "+s"(one));
-  dir_hops<R, T2, 0, 1>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[0], hop_c.bwd[0]);
-  dir_hops<R, T2, 1, 1>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[1], hop_c.bwd[1]);
-  dir_hops<R, T2, 2, 1>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[2], hop_c.bwd[2]);
-  dir_hops<R, T2, 3, 1>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[3], hop_c.bwd[3]);
+  dir_hops<R, T2, 0, 1, false>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[0], hop_c.bwd[0]);
+  dir_hops<R, T2, 1, 1, false>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[1], hop_c.bwd[1]);
+  dir_hops<R, T2, 2, 1, false>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[2], hop_c.bwd[2]);
+  dir_hops<R, T2, 3, 1, false>(acc, links, inr, Vs, s, nb, one, g5in, hop_c.fwd[3], hop_c.bwd[3]);
   Cx<R> psi[12];
   load_spinor(inr, Vs, s, g5in, psi);
 #pragma unroll
@@ -486,21 +495,21 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
       for (int c = 0; c < 12; ++c) accv[r][c] = accw[r][c] = {R(0), R(0)};
     Cx<R> u[9], psi[12];
 #define OVS_DUAL_DIR(NU)                                                                 \
-  load_link(links, V, NU, nb.b[NU], u);                                                  \
+  load_link_u(links, V, NU, nb.b[NU], u);                                                  \
   _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
     if (r < nsrc) {                                                                      \
-      load_spinor(in_v + (long)slot[r] * 12 * V, V, nb.b[NU], false, psi);               \
+      load_spinor_u(in_v + (long)slot[r] * 12 * V, V, nb.b[NU], false, psi);               \
       hop<R, NU, +1, false>(accv[r], u, psi, hA.fwd[NU]);                                \
-      load_spinor(in_w + (long)slot[r] * 12 * V, V, nb.b[NU], false, psi);               \
+      load_spinor_u(in_w + (long)slot[r] * 12 * V, V, nb.b[NU], false, psi);               \
       hop<R, NU, +1, false>(accw[r], u, psi, hAd.fwd[NU]);                               \
     }                                                                                    \
   }                                                                                      \
-  load_link(links, V, NU, s, u);                                                         \
+  load_link_u(links, V, NU, s, u);                                                         \
   _Pragma("unroll") for (int r = 0; r < B; ++r) {                                        \
     if (r < nsrc) {                                                                      \
-      load_spinor(in_v + (long)slot[r] * 12 * V, V, nb.f[NU], false, psi);               \
+      load_spinor_u(in_v + (long)slot[r] * 12 * V, V, nb.f[NU], false, psi);               \
       hop<R, NU, -1, true>(accv[r], u, psi, hA.bwd[NU]);                                 \
-      load_spinor(in_w + (long)slot[r] * 12 * V, V, nb.f[NU], false, psi);               \
+      load_spinor_u(in_w + (long)slot[r] * 12 * V, V, nb.f[NU], false, psi);               \
       hop<R, NU, -1, true>(accw[r], u, psi, hAd.bwd[NU]);                                \
     }                                                                                    \
   }
@@ -514,8 +523,8 @@ k_dual(const typename Vec2<R>::T* __restrict__ links, const typename Vec2<R>::T*
       if (r < nsrc) {
         const long base = (long)slot[r] * 12 * V;
         Cx<R> pv[12], pw[12];
-        load_spinor(in_v + base, V, s, false, pv);
-        load_spinor(in_w + base, V, s, false, pw);
+        load_spinor_u(in_v + base, V, s, false, pv);
+        load_spinor_u(in_w + base, V, s, false, pw);
         Cx<R> t[12], sv[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
@@ -615,7 +624,12 @@ k_dual_pair(const typename Vec2<R>::T* __restrict__ links,
       if (r < nsrc && live) {
         const T2* f = in + (long)slot[r] * 12 * V;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) plane[((op * B + r) * 12 + c) * 256 + ts] = f[fidx(c, s, V)];
+        for (int q = 0; q < 6; ++q) {  // component pairs: one 16-byte load each in FP32
+          Cx<R> x0, x1;
+          ld_pair(pair_at(f + (long)q * 2 * V, s), x0, x1);
+          plane[((op * B + r) * 12 + 2 * q) * 256 + ts] = T2{x0.re, x0.im};
+          plane[((op * B + r) * 12 + 2 * q + 1) * 256 + ts] = T2{x1.re, x1.im};
+        }
       }
     }
     __syncthreads();
