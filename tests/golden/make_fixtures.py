@@ -3,7 +3,8 @@
 Calls only the CPU oracle (oracle/) and the seeded input generators (synth/);
 nothing here touches the HIP library.  Re-run with
     python tests/golden/make_fixtures.py [lattice_4444] [gradient_8888] [sign_16x16x16x32]
-(both when no name is given) after any change to the oracle's arithmetic.
+                                         [sign_16x16x16x16]
+(all when no name is given) after any change to the oracle's arithmetic.
 
 lattice_4444.npz -- the 4^4 workload: links P_SU3(1 + 0.4 G) (seed 0),
     m_w = -1.5, mu = 0.3, one Gaussian source (seed 1).  Holds the exact
@@ -30,7 +31,15 @@ sign_16x16x16x32.npz -- the benchmark workload: 16^3 x 32, links
     Gaussian sources (seed 1).  The oracle's two-sided Lanczos (CSR, FP64,
     two-pass, no deflation) at k = 650 and k = 700 for each source: 4096
     sampled entries of y (fixed positions, default_rng(7)) and the full
-    norms; their difference bounds the reference's own error.
+    norms; their difference bounds the reference's own error.  The k = 650
+    values come from the k = 700 run's first 650 coefficients (the same
+    numbers a k = 650 run produces).
+
+sign_16x16x16x16.npz -- the 16^4 configuration: links P_SU3(1 + 0.6 G)
+    (seed 0), m_w = -1.5, mu = 0.2, point sources 0 and 1 (spin-colour 0 and
+    1 at the origin).  As above at k = 550 and k = 600; the sampled entries are
+    4096 random ones plus every entry of the 5^4 sites around the origin, where
+    the result is concentrated.
 """
 import os
 import sys
@@ -157,8 +166,60 @@ def sign_16x16x16x32():
     np.savez_compressed(os.path.join(HERE, "sign_16x16x16x32.npz"), **out)
 
 
+def _sign16_4_source(r):
+    """Point source r (spin-colour r at the origin) of the 16^4 configuration:
+    the oracle's two-sided Lanczos to k = 600 (coefficients only) and replays
+    for k = 550 and 600, as in _sign16_source."""
+    dims = (16, 16, 16, 16)
+    m_w, mu, eps = -1.5, 0.2, 0.6
+    U = synth.random_links(dims, eps, seed=synth.LINK_SEED)
+    b = synth.point_sources(dims)[r]
+    A = dirac.csr_A(dims, U, m_w, mu)
+    Ad = dirac.csr_A(dims, U, m_w, -mu)
+    del U
+    lr = krylov.two_sided_lanczos(lambda z: A @ z, lambda z: Ad @ z, b, b, 600, store=False)
+    assert lr.k == 600 and lr.status != "serious", (lr.k, lr.status)
+    ys = {}
+    for k in (550, 600):
+        x = np.zeros(600, dtype=np.complex128)
+        x[:k] = sign.sign_e1(krylov.tridiag(lr.alpha[:k], lr.beta[:k - 1], lr.gamma[:k - 1]))
+        ys[k] = lr.n_b * krylov.replay_combine(lambda z: A @ z, b / lr.n_b, lr, x)
+        print("16^4 source", r, "k", k, "norm", np.linalg.norm(ys[k]), flush=True)
+    return ys
+
+
+def _near_origin(dims, half):
+    """Vector indices (12 s + spin-colour) of the sites whose every coordinate
+    lies within +-half of the origin (periodic): where a point source's
+    sgn(A) e_j is concentrated."""
+    lx, ly, lz, lt = dims
+    rng = range(-half, half + 1)
+    sites = sorted({(x % lx) + lx * ((y % ly) + ly * ((z % lz) + lz * (t % lt)))
+                    for x in rng for y in rng for z in rng for t in rng})
+    return np.array([12 * s + c for s in sites for c in range(12)])
+
+
+def sign_16x16x16x16():
+    from concurrent.futures import ProcessPoolExecutor
+    dims = (16, 16, 16, 16)
+    N = synth.volume(dims) * 12
+    rnd = np.random.default_rng(7).choice(N, 4096, replace=False)
+    idx = np.unique(np.concatenate([rnd, _near_origin(dims, 2)]))
+    out = {"dims": np.array(dims), "m_w": -1.5, "mu": 0.2, "eps": 0.6, "idx": idx,
+           "ks": np.array([550, 600]), "sources": np.array([0, 1])}
+    with ProcessPoolExecutor(2) as ex:
+        res = list(ex.map(_sign16_4_source, (0, 1)))
+    for r, ys in enumerate(res):
+        for k in (550, 600):
+            out[f"y{r}_k{k}"] = ys[k][idx]
+            out[f"norm{r}_k{k}"] = np.linalg.norm(ys[k])
+        out[f"ydiff{r}"] = np.linalg.norm(ys[600][idx] - ys[550][idx]) / np.linalg.norm(ys[600][idx])
+    np.savez_compressed(os.path.join(HERE, "sign_16x16x16x16.npz"), **out)
+
+
 if __name__ == "__main__":
-    names = sys.argv[1:] or ["lattice_4444", "gradient_8888", "sign_16x16x16x32"]
+    names = sys.argv[1:] or ["lattice_4444", "gradient_8888", "sign_16x16x16x32",
+                             "sign_16x16x16x16"]
     for name in names:
         if name == "gradient_8888_k150":
             gradient_8888_at(150, 1e-5, True)
