@@ -80,10 +80,14 @@ typedef struct ovs_field_s* ovs_field;
 typedef struct {
   int32_t k_used;        /* Krylov size actually used                                  */
   int32_t status;        /* OVS_OK or a warning code for this source                   */
-  double est_rel_err;    /* convergence estimate n_b |x_j - x_{j-c}| / |b| (0 if unused) */
+  double est_rel_err;    /* convergence estimate: relative change of y on 512 sampled
+                            entries over the last 25 iterations (0 without tol)        */
   double quad_err;       /* estimated error of the inner sign quadrature               */
   double n_b;            /* |b_R|, norm of the deflated source                         */
   double t_defl_ms, t_krylov_ms, t_inner_ms, t_combine_ms; /* phase times (whole batch) */
+  int32_t fp64;          /* 1: y was computed with FP64 vector storage                 */
+  int32_t escalated;     /* 1: FP32 storage stalled (below) and the source was solved
+                            again with FP64 storage                                    */
 } ovs_rhs_info;
 
 /* ---- lattice ------------------------------------------------------------ */
@@ -195,6 +199,10 @@ ovs_status ovs_deflation_destroy(ovs_deflation d);
  *            tol/10, checked every 25 iterations.  On an OVS_F32_STORE lattice
  *            the sources with tol < 1e-6 (below what FP32 storage attains) run
  *            as an FP64 group on the FP64 copy of the links; the rest in FP32.
+ *            A source whose FP32-storage estimate has not halved over 6 checks
+ *            (150 iterations) while above its target is stopped there and solved
+ *            again with FP64 storage (info.escalated); FP32 rounding of the
+ *            stored vectors can stall the recurrence for an individual source.
  *   info   : host [nrhs] result records, or NULL.
  * Batches of 8 or more sources run as two halves at the same time, on the
  * handle's stream and on a second internal stream (each half with the whole

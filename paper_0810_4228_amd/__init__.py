@@ -71,6 +71,8 @@ class RhsInfo(ctypes.Structure):
         ("t_krylov_ms", ctypes.c_double),
         ("t_inner_ms", ctypes.c_double),
         ("t_combine_ms", ctypes.c_double),
+        ("fp64", ctypes.c_int32),
+        ("escalated", ctypes.c_int32),
     ]
 
     def as_dict(self):

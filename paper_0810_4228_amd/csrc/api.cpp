@@ -133,6 +133,7 @@ constexpr double kHStart = 0.25, kHMin = 0.0625;
 constexpr double kQuadAccept = 3e-7;  // coarse/fine difference accepted at step h
 constexpr int kProbe = 512;           // sampled entries per source for the convergence estimate
 constexpr int kCheckEvery = 25;       // iterations between convergence checks
+constexpr int kStallChecks = 6;       // checks without the estimate halving: FP32 stall
 
 // Distinct sampled field positions fidx(c, s) (s < V), sorted; a fixed
 // sequence, the same for all calls.
@@ -1003,6 +1004,10 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   CoefArrays co{B.alpha, B.beta, B.gamma, B.sv, B.sw, B.tnorm2, B.kstop, B.status, K};
 
   std::vector<double> est(nr, 0.0), qerr(nr, 0.0);
+  // stall tracking (FP32 storage): best estimate so far, checks since it halved
+  std::vector<double> best_est(nr, HUGE_VAL);
+  std::vector<int> since_best(nr, 0);
+  std::vector<char> stalled(nr, 0);
   InnerScratch isc{B.mult, B.swp, B.part, B.ys};
   std::vector<double> errh;
 
@@ -1145,6 +1150,19 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
           if (hkstop[r] <= i || (had_prev && est[r] <= 0.1 * tol[r])) {
             done[r] = 1;
             kused[r] = ks[r];
+          } else if (f32 && had_prev) {
+            // FP32 rounding of the stored vectors can stall one source's
+            // recurrence: an estimate that has not halved in kStallChecks
+            // checks stops the source here, to be solved again with FP64
+            // storage by ovs_sign_apply
+            if (est[r] < 0.5 * best_est[r]) {
+              best_est[r] = est[r];
+              since_best[r] = 0;
+            } else if (++since_best[r] >= kStallChecks) {
+              done[r] = 1;
+              kused[r] = ks[r];
+              stalled[r] = 1;
+            }
           }
         }
         st = push_map();
@@ -1256,9 +1274,11 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     int rs = OVS_OK;
     if (hstatus[r] == 2) rs = OVS_WARN_BREAKDOWN;
     else if (!(qerr[r] <= 1e-3)) rs = OVS_WARN_SIGN_AMBIGUOUS;
-    else if (tol && !done[r] && hstatus[r] == 0) rs = OVS_WARN_NOT_CONVERGED;
+    else if (tol && (!done[r] || stalled[r]) && hstatus[r] == 0) rs = OVS_WARN_NOT_CONVERGED;
     if (rs > worst) worst = rs;
     if (info) {
+      info[r].fp64 = f32 ? 0 : 1;
+      info[r].escalated = stalled[r] ? 1 : 0;  // marks "to escalate" until ovs_sign_apply does
       info[r].k_used = kused[r];
       info[r].status = rs;
       info[r].est_rel_err = est[r];
@@ -1381,74 +1401,100 @@ static ovs_status shadow_ready(ovs_lattice_s* l) {
   return OVS_OK;
 }
 
+// Solves the sources idx (ascending) of (b, y) with FP32 storage through
+// run_batch, or with FP64 storage on the FP64 shadow handle; through the
+// gather buffer unless idx is the whole batch.  Records go to inf[idx[j]].
+static ovs_status solve_subset(ovs_lattice l, bool fp64, ovs_deflation defl, int32_t n_defl,
+                               const void* b, void* y, int32_t nrhs, const std::vector<int>& idx,
+                               int32_t k_max, const double* tol, ovs_method method,
+                               int32_t flags, ovs_rhs_info* inf) {
+  const int n = (int)idx.size();
+  std::vector<double> t(n);
+  for (int j = 0; j < n; ++j) t[j] = tol[idx[j]];
+  std::vector<ovs_rhs_info> rec(n);
+  ovs_status st;
+  if (n == nrhs) {
+    st = fp64 ? sign_apply_impl(l->shadow64, defl, n_defl, b, y, n, k_max, t.data(), method,
+                                flags, rec.data(), n)
+              : run_batch(l, defl, n_defl, b, y, n, k_max, t.data(), method, flags, rec.data());
+  } else {
+    const size_t fb = 12ul * l->g.V * sizeof(double2);
+    const size_t need = 2 * (size_t)n * fb;
+    if (l->split_bytes < need) {
+      OVS_HIP(hipStreamSynchronize(l->stream));
+      if (l->split_buf) (void)hipFree(l->split_buf);
+      l->split_buf = nullptr;
+      l->split_bytes = 0;
+      if (hipMalloc(&l->split_buf, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return OVS_ERR_ALLOC;
+      }
+      l->split_bytes = need;
+    }
+    char* bb = (char*)l->split_buf;
+    char* yy = bb + n * fb;
+    for (int j = 0; j < n; ++j)
+      OVS_HIP(hipMemcpyAsync(bb + j * fb, (const char*)b + idx[j] * fb, fb,
+                             hipMemcpyDeviceToDevice, l->stream));
+    st = fp64 ? sign_apply_impl(l->shadow64, defl, n_defl, bb, yy, n, k_max, t.data(), method,
+                                flags, rec.data(), n)
+              : run_batch(l, defl, n_defl, bb, yy, n, k_max, t.data(), method, flags, rec.data());
+    if (st < 0) return st;
+    for (int j = 0; j < n; ++j)
+      OVS_HIP(hipMemcpyAsync((char*)y + idx[j] * fb, yy + j * fb, fb, hipMemcpyDeviceToDevice,
+                             l->stream));
+    OVS_HIP(hipStreamSynchronize(l->stream));
+  }
+  if (st < 0) return st;
+  for (int j = 0; j < n; ++j) inf[idx[j]] = rec[j];
+  return st;
+}
+
 ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
                           void* y, int32_t nrhs, int32_t k_max, const double* tol,
                           ovs_method method, int32_t flags, ovs_rhs_info* info) {
   if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || l->parent) return OVS_ERR_ARG;
   if (!tol || l->prec != OVS_F32_STORE)
     return run_batch(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
+  // FP32-storage lattice with targets: the FP64 group (targets below the FP32
+  // floor), the FP32 group, then the FP32 sources that stalled, again with
+  // FP64 storage
   std::vector<int> lo, hi;
   for (int r = 0; r < nrhs; ++r) {
     if (!(tol[r] > 0.0)) return OVS_ERR_ARG;
     (tol[r] < kF32Floor ? lo : hi).push_back(r);
   }
-  if (lo.empty())
-    return run_batch(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
   if (!ready(l)) return OVS_ERR_STATE;
-  ovs_status st = shadow_ready(l);
-  if (st != OVS_OK) return st;
-  if (hi.empty())
-    return sign_apply_impl(l->shadow64, defl, n_defl, b, y, nrhs, k_max, tol, method, flags,
-                           info, nrhs);
-  // gather both groups: [b_lo | y_lo | b_hi | y_hi], canonical complex128 fields
-  const size_t fb = 12ul * l->g.V * sizeof(double2);
-  const size_t need = 2 * (size_t)nrhs * fb;
-  if (l->split_bytes < need) {
-    OVS_HIP(hipStreamSynchronize(l->stream));
-    if (l->split_buf) (void)hipFree(l->split_buf);
-    l->split_buf = nullptr;
-    l->split_bytes = 0;
-    if (hipMalloc(&l->split_buf, need) != hipSuccess) {
-      (void)hipGetLastError();
-      return OVS_ERR_ALLOC;
-    }
-    l->split_bytes = need;
-  }
+  std::vector<ovs_rhs_info> inf(nrhs);
   StreamScope sc(l);
-  char* base = (char*)l->split_buf;
-  const int nlo = (int)lo.size(), nhi = (int)hi.size();
-  char* b_lo = base;
-  char* y_lo = b_lo + nlo * fb;
-  char* b_hi = y_lo + nlo * fb;
-  char* y_hi = b_hi + nhi * fb;
-  for (int j = 0; j < nlo; ++j)
-    OVS_HIP(hipMemcpyAsync(b_lo + j * fb, (const char*)b + lo[j] * fb, fb,
-                           hipMemcpyDeviceToDevice, l->stream));
-  for (int j = 0; j < nhi; ++j)
-    OVS_HIP(hipMemcpyAsync(b_hi + j * fb, (const char*)b + hi[j] * fb, fb,
-                           hipMemcpyDeviceToDevice, l->stream));
-  std::vector<double> tlo(nlo), thi(nhi);
-  for (int j = 0; j < nlo; ++j) tlo[j] = tol[lo[j]];
-  for (int j = 0; j < nhi; ++j) thi[j] = tol[hi[j]];
-  std::vector<ovs_rhs_info> ilo(nlo), ihi(nhi);
-  const ovs_status s_lo = sign_apply_impl(l->shadow64, defl, n_defl, b_lo, y_lo, nlo, k_max,
-                                          tlo.data(), method, flags, ilo.data(), nlo);
-  if (s_lo < 0) return s_lo;
-  const ovs_status s_hi = run_batch(l, defl, n_defl, b_hi, y_hi, nhi, k_max, thi.data(),
-                                    method, flags, ihi.data());
-  if (s_hi < 0) return s_hi;
-  for (int j = 0; j < nlo; ++j)
-    OVS_HIP(hipMemcpyAsync((char*)y + lo[j] * fb, y_lo + j * fb, fb, hipMemcpyDeviceToDevice,
-                           l->stream));
-  for (int j = 0; j < nhi; ++j)
-    OVS_HIP(hipMemcpyAsync((char*)y + hi[j] * fb, y_hi + j * fb, fb, hipMemcpyDeviceToDevice,
-                           l->stream));
-  OVS_HIP(hipStreamSynchronize(l->stream));
-  if (info) {
-    for (int j = 0; j < nlo; ++j) info[lo[j]] = ilo[j];
-    for (int j = 0; j < nhi; ++j) info[hi[j]] = ihi[j];
+  ovs_status st = OVS_OK;
+  if (!lo.empty()) {
+    st = shadow_ready(l);
+    if (st == OVS_OK)
+      st = solve_subset(l, true, defl, n_defl, b, y, nrhs, lo, k_max, tol, method, flags,
+                        inf.data());
+    if (st < 0) return st;
   }
-  return std::max(s_lo, s_hi);
+  if (!hi.empty()) {
+    st = solve_subset(l, false, defl, n_defl, b, y, nrhs, hi, k_max, tol, method, flags,
+                      inf.data());
+    if (st < 0) return st;
+    std::vector<int> esc;
+    for (int r : hi)
+      if (inf[r].escalated) esc.push_back(r);
+    if (!esc.empty()) {
+      st = shadow_ready(l);
+      if (st == OVS_OK)
+        st = solve_subset(l, true, defl, n_defl, b, y, nrhs, esc, k_max, tol, method, flags,
+                          inf.data());
+      if (st < 0) return st;
+      for (int r : esc) inf[r].escalated = 1;
+    }
+  }
+  ovs_status worst = OVS_OK;
+  for (int r = 0; r < nrhs; ++r) worst = std::max(worst, (ovs_status)inf[r].status);
+  if (info) std::copy(inf.begin(), inf.end(), info);
+  return worst;
 }
 
 ovs_status ovs_last_coefficients(ovs_lattice l, double* alpha, double* beta, double* gamma,

@@ -110,6 +110,32 @@ def test_matches_cpu_lanczos_step_by_step():
         assert rel(y.cpu().numpy()[0], yr) < 1e-10
 
 
+@pytest.mark.parametrize("mu", [0.0, 0.1, 0.3, 0.5])
+def test_config_8888_lanczos_and_arnoldi_vs_cpu(mu):
+    """8^4, eps 0.6, one Gaussian source, mu in {0, 0.1, 0.3, 0.5}: the GPU's
+    two-sided Lanczos and Arnoldi (FP64, k = 200, no deflation) against the
+    oracle's own 2sL and Arnoldi at the same k.  At mu = 0 A is Hermitian and
+    both reduce to Hermitian Lanczos."""
+    dims = (8, 8, 8, 8)
+    U = synth.random_links(dims, 0.6, seed=synth.LINK_SEED)
+    b = synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)
+    A = dirac.csr_A(dims, U, MW, mu)
+    Ad = dirac.csr_A(dims, U, MW, -mu)
+    lat = lattice(dims, "f64", U, mu)
+    k = 200
+    y2, _, _ = lat.sign_apply(to_dev(b), k)
+    ya, _, _ = lat.sign_apply(to_dev(b), k, method="arnoldi")
+    r2 = krylov.tsl_apply(lambda v: A @ v, lambda v: Ad @ v, b[0], k)
+    ra = krylov.arnoldi_apply(lambda v: A @ v, b[0], k)
+    e2 = rel(y2.cpu().numpy()[0], r2)
+    ea = rel(ya.cpu().numpy()[0], ra)
+    say(f"8^4 mu {mu} k {k}: 2sL vs oracle {e2:.1e}, Arnoldi vs oracle {ea:.1e}, "
+        f"2sL vs Arnoldi {rel(r2, ra):.1e}")
+    lat.close()
+    assert e2 <= 1e-8
+    assert ea <= 1e-10
+
+
 def test_benchmark_workload_against_oracle():
     """The benchmark workload at full size (16^3 x 32, eps 0.6, mu 0.4, 12
     Gaussian sources, FP32 storage, tol 1e-5, two concurrent halves) against
@@ -149,6 +175,78 @@ def test_benchmark_workload_against_oracle():
     # the GPU result is within ~1e-10 of the exact value and the reference within
     # ~unc of it (its own 650 -> 700 change bounds its error)
     assert max(e64) <= 2 * (1e-10 + unc)
+
+
+def test_point_sources_16x16x16x16_persistent():
+    """16^4, mu = 0.2, eps 0.6: the 12 spin-colour point sources at the origin in
+    one FP32-storage batch, autotuned, run in persistent launches for exactly
+    k = 600 iterations, against the oracle's FP64 two-sided Lanczos at k = 600
+    for sources 0 and 1 (tests/golden/sign_16x16x16x16.npz: 4096 random
+    entries plus all entries of the 5^4 sites around the origin, which hold
+    nearly all of each result; the oracle's change from k = 550 to 600 is
+    ~1.5e-10).  Bar: 1e-5 for FP32 storage."""
+    import paper_0810_4228_amd as ovs
+    import torch
+    f = np.load(os.path.join(GOLDEN, "sign_16x16x16x16.npz"))
+    dims = tuple(int(d) for d in f["dims"])
+    mu, idx = float(f["mu"]), f["idx"]
+    U = to_dev(synth.random_links(dims, float(f["eps"]), seed=synth.LINK_SEED))
+    b = to_dev(synth.point_sources(dims))
+    lat = ovs.Lattice(dims, precision="f32")
+    lat.set_links(U)
+    lat.set_params(MW, mu)
+    lat.autotune(12)
+    y, info, st = lat.sign_apply(b, 600, persistent=True)
+    yh = [y[r].cpu().numpy() for r in range(2)]
+    e = [rel(yh[r][idx], f[f"y{r}_k600"]) for r in range(2)]
+    cover = [float(np.linalg.norm(f[f"y{r}_k600"]) / f[f"norm{r}_k600"]) for r in range(2)]
+    say(f"16^4 x 12 point sources, persistent, k = 600: {e} (sampled share of |y|: {cover}); "
+        f"status {st}, k {[i['k_used'] for i in info[:2]]}")
+    lat.close()
+    assert st == 0 and all(i["k_used"] == 600 for i in info)
+    assert min(cover) > 0.9
+    assert max(e) <= 1e-5
+
+
+def test_benchmark_lattice_48_sources_mixed_tolerance():
+    """16^3 x 32, 48 Gaussian sources with target tolerances 1e-5 (even) and
+    1e-8 (odd) in one call on an FP32-storage lattice, two-pass (a stored
+    basis for 48 sources would not fit): the 1e-8 sources run as the FP64
+    group, and an FP32 source whose recurrence stalls (source 20 of this draw
+    does: estimate 8e-5 at k = 1200 with FP32 storage, converged at k = 425
+    with FP64) is solved again with FP64 storage.  Sources 0 and 1 are those of the oracle fixture (the first rows of
+    the seeded draw do not depend on the source count): source 0 within its
+    1e-5, source 1 within 1e-8 of the oracle's k = 700 result, whose own
+    error is below its 650 -> 700 change."""
+    import paper_0810_4228_amd as ovs
+    import torch
+    f = np.load(os.path.join(GOLDEN, "sign_16x16x16x32.npz"))
+    dims = tuple(int(d) for d in f["dims"])
+    mu, idx = float(f["mu"]), f["idx"]
+    U = to_dev(synth.random_links(dims, float(f["eps"]), seed=synth.LINK_SEED))
+    b = to_dev(synth.gaussian_sources(dims, 48, seed=synth.SOURCE_SEED))
+    lat = ovs.Lattice(dims, precision="f32")
+    lat.set_links(U)
+    lat.set_params(MW, mu)
+    tol = [1e-5 if j % 2 == 0 else 1e-8 for j in range(48)]
+    y, info, st = lat.sign_apply(b, 1200, tol=tol, two_pass=True, graph=True)
+    e = [rel(y[r].cpu().numpy()[idx], f[f"y{r}_k700"]) for r in range(2)]
+    unc = max(float(f["ydiff0"]), float(f["ydiff1"]))
+    ks = [i["k_used"] for i in info]
+    esc = [j for j, i in enumerate(info) if i["escalated"]]
+    say(f"16^3x32 x 48 mixed tol: source 0 (1e-5) {e[0]:.2e}, source 1 (1e-8) {e[1]:.2e}; "
+        f"k even {sorted(set(ks[0::2]))} odd {sorted(set(ks[1::2]))}; status {st}; "
+        f"escalated to FP64 storage {esc}")
+    lat.close()
+    del y, b
+    torch.cuda.empty_cache()
+    # every source reaches its target: the 1e-8 ones with FP64 storage, the
+    # 1e-5 ones with FP32 storage unless their recurrence stalled there
+    assert st == 0 and all(i["status"] == 0 for i in info)
+    assert all(info[j]["fp64"] == (1 if (j % 2 or j in esc) else 0) for j in range(48))
+    assert all(j % 2 == 0 for j in esc)
+    assert e[0] <= 1e-5
+    assert e[1] <= 1e-8 + unc
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
