@@ -172,6 +172,25 @@ def free_field_check(ovs, torch, dev):
     return max(errs), [i["k_used"] for i in info]
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, iters=20):
+    """Device-to-device copy rate (read + write bytes / time, HIP events): the
+    practical HBM ceiling the kernels are also compared with."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def launch_modes(ovs, torch, dev, lat, bt):
     """Solves/s of captured graphs (the default) against persistent launches:
     the benchmark workload, and 12 sources on an 8^4 lattice (launch-bound)."""
@@ -321,6 +340,9 @@ def main():
                           "dual_us": ms_du * 1e3, "dual_gbps": du_gbs, "tuning": tuning}))
         return
 
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"bench: device copy {copy_gbs:.0f} GB/s")
+
     # ---- sign solves ----
     tol = [TOL] * NRHS
     for w in range(args.warmup):
@@ -376,7 +398,8 @@ def main():
                          "frac_peak": du_gbs / HBM_PEAK_GBS, "bytes_per_apply": du_bytes},
         "roofline": {"bound": "hbm", "kernel": du_name, "achieved": du_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": du_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("dual")},
+                     "traffic": measured_traffic("dual"),
+                     "copy_gbps": copy_gbs, "frac_of_copy": du_gbs / copy_gbs},
     }
     if not args.no_compare:
         log("bench: FP64 single-source comparison")

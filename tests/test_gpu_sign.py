@@ -132,8 +132,9 @@ def test_config_8888_lanczos_and_arnoldi_vs_cpu(mu):
     say(f"8^4 mu {mu} k {k}: 2sL vs oracle {e2:.1e}, Arnoldi vs oracle {ea:.1e}, "
         f"2sL vs Arnoldi {rel(r2, ra):.1e}")
     lat.close()
-    assert e2 <= 1e-8
-    assert ea <= 1e-10
+    # measured: 2sL 6.5e-15 (mu = 0) to 4.6e-13 (mu = 0.5), Arnoldi 5.8e-15 to 1.1e-13
+    assert e2 <= 1e-11
+    assert ea <= 1e-11
 
 
 def test_benchmark_workload_against_oracle():
