@@ -508,32 +508,48 @@ __global__ void __launch_bounds__(64) k_isign_tri(const double2* __restrict__ al
     swp[mbase + (long)j * 64] = sw ? 1 : 0;
   }
   const Cx<double> inv_r00 = cdiv(Cx<double>{1.0, 0.0}, cd);
-  // z = P E e_1 streamed out top-down; row j-1 is final after column j
+  // z = P E e_1 streamed out top-down; row j-1 is final after column j.  The
+  // weighted rows of the 64 lanes are buffered in LDS for kRows rows at a time
+  // and summed over the lanes in a fixed order, one (row, part) per lane.
+  constexpr int kRows = 16;
+  __shared__ double rows[kRows][4][65];  // [row][fine re, fine im, coarse re, coarse im][lane]
   Cx<double> cur = inv_r00;
-  for (int j = 1; j <= k; ++j) {
-    Cx<double> fin;
-    if (j < k) {
-      const Cx<double> m = c64(mult[mbase + (long)j * 64]);
-      const Cx<double> nw = -cmul(m, cur);
-      if (swp[mbase + (long)j * 64]) {
-        fin = nw;
-      } else {
-        fin = cur;
-        cur = nw;
+  for (int j0 = 1; j0 <= k; j0 += kRows) {
+    const int nrow = min(kRows, k - j0 + 1);
+#pragma unroll 4
+    for (int t = 0; t < kRows; ++t) {
+      if (t < nrow) {
+        const int j = j0 + t;
+        Cx<double> fin;
+        if (j < k) {
+          const Cx<double> m = c64(mult[mbase + (long)j * 64]);
+          const Cx<double> nw = -cmul(m, cur);
+          if (swp[mbase + (long)j * 64]) {
+            fin = nw;
+          } else {
+            fin = cur;
+            cur = nw;
+          }
+        } else {
+          fin = cur;
+        }
+        rows[t][0][lane] = wfine * fin.re;
+        rows[t][1][lane] = wfine * fin.im;
+        rows[t][2][lane] = wcoarse * fin.re;
+        rows[t][3][lane] = wcoarse * fin.im;
       }
-    } else {
-      fin = cur;
     }
-    // row j-1 contributions of this lane, reduced over the wave
-    double f0 = wfine * fin.re, f1 = wfine * fin.im, g0 = wcoarse * fin.re, g1 = wcoarse * fin.im;
-    f0 = wave_sum(f0);
-    f1 = wave_sum(f1);
-    g0 = wave_sum(g0);
-    g1 = wave_sum(g1);
-    if (lane == 0) {
-      part_r[j - 1] = make_double2(f0, f1);
-      part_r[kmax + j - 1] = make_double2(g0, g1);
+    __syncthreads();
+    {
+      const int t = lane & (kRows - 1), c = lane / kRows;  // 16 rows x 4 parts = 64 lanes
+      if (t < nrow) {
+        double acc = 0.0;
+        for (int l = 0; l < 64; ++l) acc += rows[t][c][l];
+        double* out = reinterpret_cast<double*>(part_r + (c < 2 ? 0 : kmax) + (j0 - 1 + t));
+        out[c & 1] = acc;
+      }
     }
+    __syncthreads();
   }
 }
 
