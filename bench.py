@@ -191,6 +191,37 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, iters=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def gradient_timing(ovs, torch, dev, dims=(8, 8, 8, 8), k=400):
+    """ovs_sign_apply_vjp (eps 0.6, mu 0.3, one Gaussian source and cotangent,
+    FP64, k iterations) with the Lanczos vectors recomputed from checkpoints and
+    with the bases stored, against the k-step forward alone (no tolerance, no
+    graphs: the same kernels the sweep uses).  The default is the gradient
+    configuration, 8^4 at k = 400."""
+    import synth
+    lat = ovs.Lattice(dims, precision="f64")
+    lat.set_links(torch.from_numpy(synth.random_links(dims, 0.6, seed=synth.LINK_SEED)).to(dev))
+    lat.set_params(MW, 0.3)
+    b = torch.from_numpy(synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)).to(dev)
+    chi = torch.from_numpy(synth.gaussian_sources(dims, 1, seed=synth.COTANGENT_SEED)).to(dev)
+
+    def t(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    fwd = t(lambda: lat.sign_apply(b, k))
+    rec = t(lambda: lat.sign_apply_vjp(b, chi, k))
+    sto = t(lambda: lat.sign_apply_vjp(b, chi, k, store_basis=True))
+    lat.close()
+    return {"workload": "x".join(map(str, dims)) + f", eps 0.6, mu 0.3, 1 source, FP64, k = {k}",
+            "forward_ms": fwd, "vjp_recompute_ms": rec, "vjp_stored_basis_ms": sto,
+            "ratio_recompute": rec / fwd, "ratio_stored": sto / fwd}
+
+
 def launch_modes(ovs, torch, dev, lat, bt):
     """Solves/s of captured graphs (the default) against persistent launches:
     the benchmark workload, and 12 sources on an 8^4 lattice (launch-bound)."""
@@ -414,6 +445,11 @@ def main():
         log("bench: launch modes")
         out["launch_modes"] = launch_modes(ovs, torch, dev, lat, bt)
         log("bench: launch modes", out["launch_modes"])
+    if not args.no_compare:
+        log("bench: gradient timing")
+        out["gradient"] = [gradient_timing(ovs, torch, dev),
+                           gradient_timing(ovs, torch, dev, dims=(16, 16, 16, 16), k=200)]
+        log("bench: gradient", out["gradient"])
     if not args.no_check:
         log("bench: free-field accuracy check")
         err, kf = free_field_check(ovs, torch, dev)

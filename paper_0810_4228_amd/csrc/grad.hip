@@ -67,15 +67,37 @@ void launch_lin(const LinArgs& a, long stride, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_lin, dim3(lin_nchunk(stride), nrhs), dim3(kWG), 0, s, a, stride, nrhs);
 }
 
-// Fixed-order sum of the partials of dot q for source r.
-__device__ Cx<double> dot_sum(const double* part, int r, int q, int nchunk) {
-  Cx<double> acc = {0.0, 0.0};
-  const double* p = part + (long)r * nchunk * 2 * kLinDots;
-  for (int c = 0; c < nchunk; ++c) {
-    acc.re += p[c * 2 * kLinDots + 2 * q];
-    acc.im += p[c * 2 * kLinDots + 2 * q + 1];
+// Workgroup of the per-source scalar kernels: one per source, the dot sums
+// over the chunks reduced by all its threads.
+constexpr int kScalarWG = 256;
+
+// Fixed-order sums over the chunks of ND dots of source r (dot q[d] of the
+// partials parts[d]): strided over the chunks by the workgroup, then a
+// fixed-order workgroup sum; every thread receives the results.
+template <int ND>
+__device__ void wg_dot_sums(const double* const (&parts)[ND], const int (&q)[ND], int r,
+                            int nchunk, Cx<double> (&out)[ND]) {
+  __shared__ double lds[(kScalarWG / 64) * 2 * ND];
+  __shared__ double res[2 * ND];
+  double v[2 * ND];
+#pragma unroll
+  for (int j = 0; j < 2 * ND; ++j) v[j] = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += blockDim.x) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const double* pp = parts[d] + ((long)r * nchunk + c) * 2 * kLinDots + 2 * q[d];
+      v[2 * d] += pp[0];
+      v[2 * d + 1] += pp[1];
+    }
   }
-  return acc;
+  block_sum<2 * ND>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < 2 * ND; ++j) res[j] = v[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < ND; ++d) out[d] = {res[2 * d], res[2 * d + 1]};
 }
 
 __device__ __forceinline__ Cx<double> cconj(Cx<double> a) { return {a.re, -a.im}; }
@@ -85,23 +107,27 @@ __device__ __forceinline__ void set_coef(const GradScalars& s, int t, int j, int
 
 // ---- forward scalar steps ------------------------------------------------------
 
-__global__ void k_gf_norm(GradScalars s, const double* part, int nchunk) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
-  const double nb = sqrt(dot_sum(part, r, 0, nchunk).re);
+__global__ void __launch_bounds__(kScalarWG) k_gf_norm(GradScalars s, const double* part, int nchunk) {
+  const int r = blockIdx.x;
+  Cx<double> d[1];
+  wg_dot_sums<1>({part}, {0}, r, nchunk, d);
+  if (threadIdx.x != 0) return;
+  const double nb = sqrt(d[0].re);
   s.nb[r] = nb;
   s.status[r] = 0;
   set_coef(s, kTabNorm, 0, r, {nb > 0.0 ? 1.0 / nb : 0.0, 0.0});
 }
 
 // alpha_i = w_i^dagger t_i (dot 0), |t_i|^2 (dot 1); coefficient rows of the update.
-__global__ void k_gf_alpha(GradScalars s, int i, const double* part, int nchunk) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
+__global__ void __launch_bounds__(kScalarWG) k_gf_alpha(GradScalars s, int i, const double* part, int nchunk) {
+  const int r = blockIdx.x;
+  Cx<double> d[2];
+  wg_dot_sums<2>({part, part}, {0, 1}, r, nchunk, d);
+  if (threadIdx.x != 0) return;
   const long rk = (long)r * s.kmax;
-  const Cx<double> al = dot_sum(part, r, 0, nchunk);
+  const Cx<double> al = d[0];
   s.alpha[rk + i] = d2(al);
-  s.tnorm2[rk + i] = dot_sum(part, r, 1, nchunk).re;
+  s.tnorm2[rk + i] = d[1].re;
   const Cx<double> gprev = (i > 0) ? c64(s.gamma[rk + i - 1]) : Cx<double>{0.0, 0.0};
   const double bprev = (i > 0) ? s.beta[rk + i - 1] : 0.0;
   set_coef(s, kTabV, 0, r, {1.0, 0.0});
@@ -115,14 +141,16 @@ __global__ void k_gf_alpha(GradScalars s, int i, const double* part, int nchunk)
 // beta_i = |v~|, delta_i = w~^dagger v~, gamma_i = delta_i / beta_i, with the
 // breakdown tests of the forward recurrences (lucky: |v~| <= 1e-14 |t|;
 // serious: |delta| <= 1e-13 |v~| |w~|).
-__global__ void k_gf_beta(GradScalars s, int i, const double* part_v, const double* part_w,
-                          int nchunk) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
+__global__ void __launch_bounds__(kScalarWG) k_gf_beta(GradScalars s, int i, const double* part_v,
+                                                      const double* part_w, int nchunk) {
+  const int r = blockIdx.x;
+  Cx<double> d[3];
+  wg_dot_sums<3>({part_v, part_w, part_w}, {0, 0, 1}, r, nchunk, d);
+  if (threadIdx.x != 0) return;
   const long rk = (long)r * s.kmax;
-  const double vn = sqrt(dot_sum(part_v, r, 0, nchunk).re);
-  const Cx<double> delta = cconj(dot_sum(part_w, r, 0, nchunk));  // dot 0 = v~^dagger w~
-  const double wn = sqrt(dot_sum(part_w, r, 1, nchunk).re);
+  const double vn = sqrt(d[0].re);
+  const Cx<double> delta = cconj(d[1]);  // dot 0 of part_w = v~^dagger w~
+  const double wn = sqrt(d[2].re);
   if (s.status[r] == 0) {
     if (vn <= 1e-14 * sqrt(s.tnorm2[rk + i])) s.status[r] = 1;
     else if (cabs1(delta) <= 1e-13 * vn * wn) s.status[r] = 2;
@@ -136,14 +164,14 @@ __global__ void k_gf_beta(GradScalars s, int i, const double* part_v, const doub
 }
 
 void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gf_norm, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, part, nchunk);
+  hipLaunchKernelGGL(k_gf_norm, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, nchunk);
 }
 void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gf_alpha, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part, nchunk);
+  hipLaunchKernelGGL(k_gf_alpha, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part, nchunk);
 }
 void launch_gf_beta(const GradScalars& s, int i, const double* part_v, const double* part_w,
                     int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gf_beta, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part_v, part_w,
+  hipLaunchKernelGGL(k_gf_beta, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part_v, part_w,
                      nchunk);
 }
 
@@ -157,7 +185,7 @@ void launch_gf_beta(const GradScalars& s, int i, const double* part_v, const dou
 // Last step (i = k-1): only t = A v_{k-1} and alpha_{k-1} = w_{k-1}^dagger t exist.
 __global__ void k_gr_first(GradScalars s) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
+  if (r >= s.nrhs) return;  // scalar only: one thread per source
   const int i = s.kmax - 1;
   const long rk = (long)r * s.kmax;
   const Cx<double> ab = c64(s.abar[rk + i]);
@@ -175,13 +203,15 @@ __global__ void k_gr_first(GradScalars s) {
 //   dbar    = gbar_i / beta_i
 //   vbar~_i = vbar_{i+1}/beta_i + bbar_i v_{i+1} + dbar conj(gamma_i) w_{i+1}
 //   wbar~_i = wbar_{i+1}/gamma_i + conj(dbar) beta_i v_{i+1}
-__global__ void k_gr_s1(GradScalars s, int i, const double* part_v, const double* part_w,
-                        int nchunk) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
+__global__ void __launch_bounds__(kScalarWG) k_gr_s1(GradScalars s, int i, const double* part_v,
+                                                    const double* part_w, int nchunk) {
+  const int r = blockIdx.x;
+  Cx<double> d[2];
+  wg_dot_sums<2>({part_v, part_w}, {0, 0}, r, nchunk, d);
+  if (threadIdx.x != 0) return;
   const long rk = (long)r * s.kmax;
-  const Cx<double> d2v = cconj(dot_sum(part_v, r, 0, nchunk));  // vbar^dagger v
-  const Cx<double> d1w = cconj(dot_sum(part_w, r, 0, nchunk));  // wbar^dagger w
+  const Cx<double> d2v = cconj(d[0]);  // vbar^dagger v
+  const Cx<double> d1w = cconj(d[1]);  // wbar^dagger w
   const double be = s.beta[rk + i];
   const Cx<double> ga = c64(s.gamma[rk + i]);
   Cx<double> gb = c64(s.gbar[rk + i]);
@@ -209,18 +239,21 @@ __global__ void k_gr_s1(GradScalars s, int i, const double* part_v, const double
 //   vbar_i = nb conj(x_i) chi - conj(gamma_i) vbar~_{i+1} - conj(alpha_i) vbar~_i
 //   wbar_i = -beta_i wbar~_{i+1} - alpha_i wbar~_i + conj(abar_i) t_i,
 //            t_i = beta_i v_{i+1} + alpha_i v_i + gamma_{i-1} v_{i-1}
-__global__ void k_gr_s2(GradScalars s, int i, const double* part_v, const double* part_w,
-                        int nchunk) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
+__global__ void __launch_bounds__(kScalarWG) k_gr_s2(GradScalars s, int i, const double* part_v,
+                                                    const double* part_w, int nchunk) {
+  const int r = blockIdx.x;
+  // dots 1 exist for i > 0 only; at i = 0 their sums are formed and not used
+  Cx<double> d[4];
+  wg_dot_sums<4>({part_v, part_w, part_v, part_w}, {0, 0, 1, 1}, r, nchunk, d);
+  if (threadIdx.x != 0) return;
   const long rk = (long)r * s.kmax;
-  const Cx<double> d5 = dot_sum(part_v, r, 0, nchunk);
-  const Cx<double> d4 = cconj(dot_sum(part_w, r, 0, nchunk));
+  const Cx<double> d5 = d[0];
+  const Cx<double> d4 = cconj(d[1]);
   Cx<double> ab = c64(s.abar[rk + i]) - d4 - d5;
   s.abar[rk + i] = d2(ab);
   if (i > 0) {
-    const Cx<double> d6 = dot_sum(part_v, r, 1, nchunk);
-    const Cx<double> d3 = dot_sum(part_w, r, 1, nchunk);
+    const Cx<double> d6 = d[2];
+    const Cx<double> d3 = d[3];
     s.bbar[rk + i - 1] -= d3.re;
     s.gbar[rk + i - 1] = d2(c64(s.gbar[rk + i - 1]) - d6);
   }
@@ -244,18 +277,22 @@ __global__ void k_gr_s2(GradScalars s, int i, const double* part_v, const double
 
 // v_1 = w_1 = b/|b|: grad_b = ubar/|b| + nbar v_1 with ubar = vbar_1 + wbar_1 and
 // nbar = Re(chi^dagger y)/|b| - Re(ubar^dagger v_1)/|b|, chi^dagger y = sum_i x_i conj(xbar_i).
-__global__ void k_gr_final(GradScalars s, const double* part, int nchunk) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
+__global__ void __launch_bounds__(kScalarWG) k_gr_final(GradScalars s, const double* part, int nchunk) {
+  __shared__ double lds[kScalarWG / 64];
+  const int r = blockIdx.x;
   const long rk = (long)r * s.kmax;
-  const double nb = s.nb[r];
-  double cy = 0.0;
-  for (int i = 0; i < s.kmax; ++i) {
+  Cx<double> d[1];
+  wg_dot_sums<1>({part}, {0}, r, nchunk, d);
+  double cy[1] = {0.0};
+  for (int i = threadIdx.x; i < s.kmax; i += blockDim.x) {
     const Cx<double> p = cmulc(c64(s.xbar[rk + i]), c64(s.x[rk + i]));
-    cy += p.re;
+    cy[0] += p.re;
   }
-  const double uv = dot_sum(part, r, 0, nchunk).re;  // Re(v_1^dagger ubar)
-  const double nbar = (cy - uv) / nb;
+  block_sum<1>(cy, lds);
+  if (threadIdx.x != 0) return;
+  const double nb = s.nb[r];
+  const double uv = d[0].re;  // Re(v_1^dagger ubar)
+  const double nbar = (cy[0] - uv) / nb;
   set_coef(s, kTabFin, 0, r, {1.0 / nb, 0.0});
   set_coef(s, kTabFin, 1, r, {nbar, 0.0});
 }
@@ -265,29 +302,30 @@ void launch_gr_first(const GradScalars& s, hipStream_t st) {
 }
 void launch_gr_s1(const GradScalars& s, int i, const double* part_v, const double* part_w,
                   int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gr_s1, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part_v, part_w,
+  hipLaunchKernelGGL(k_gr_s1, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part_v, part_w,
                      nchunk);
 }
 void launch_gr_s2(const GradScalars& s, int i, const double* part_v, const double* part_w,
                   int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gr_s2, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part_v, part_w,
+  hipLaunchKernelGGL(k_gr_s2, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part_v, part_w,
                      nchunk);
 }
 void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gr_final, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, part, nchunk);
+  hipLaunchKernelGGL(k_gr_final, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, nchunk);
 }
 
 // ---- source projections and replay coefficients -----------------------------
 
-__global__ void k_gf_xbar(GradScalars s, int i, const double* part, int nchunk) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
-  const Cx<double> d = dot_sum(part, r, 0, nchunk);  // chi^dagger v_i
-  s.xbar[(long)r * s.kmax + i] = d2(scale(s.nb[r], cconj(d)));
+__global__ void __launch_bounds__(kScalarWG) k_gf_xbar(GradScalars s, int i, const double* part, int nchunk) {
+  const int r = blockIdx.x;
+  Cx<double> d[1];
+  wg_dot_sums<1>({part}, {0}, r, nchunk, d);  // chi^dagger v_i
+  if (threadIdx.x != 0) return;
+  s.xbar[(long)r * s.kmax + i] = d2(scale(s.nb[r], cconj(d[0])));
 }
 
 void launch_gf_xbar(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gf_xbar, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i, part, nchunk);
+  hipLaunchKernelGGL(k_gf_xbar, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part, nchunk);
 }
 
 __global__ void k_gp_coef(GradScalars s, int i) {

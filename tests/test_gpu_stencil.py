@@ -203,6 +203,9 @@ def test_argument_errors():
         ovs.Lattice((1, 4, 4, 4))
     with pytest.raises(ovs.OvsError):
         ovs.Lattice((4, 4, 4, 4), bc=(1, 1, 1, 0))
+    with pytest.raises(ovs.OvsError) as e:
+        ovs.Lattice((64, 64, 64, 128))  # 2^25 sites: above the 2^24 limit
+    assert e.value.status == ovs.OVS_ERR_ARG
     lat = ovs.Lattice((2, 2, 2, 2))
     x = torch.zeros((1, 12 * 16), dtype=torch.complex128, device="cuda")
     with pytest.raises(ovs.OvsError) as e:
