@@ -47,9 +47,9 @@ KMAX = 1000
 # one that was measured.
 TRAFFIC = {
     "stencil": {"source_sha256_prefix": "45fd2bbcf65acb86",
-                "bytes_per_launch": 1.9998 * 203846.35 * 1024 + 1.0000 * 147461.43 * 1024},
+                "bytes_per_launch": 1.9998 * 203870.85 * 1024 + 1.0000 * 147461.12 * 1024},
     "dual": {"source_sha256_prefix": "45fd2bbcf65acb86",
-             "bytes_per_launch": 1.9998 * 206562.10 * 1024 + 1.0000 * 295185.34 * 1024},
+             "bytes_per_launch": 1.9998 * 604230.46 * 1024 + 1.0000 * 295215.06 * 1024},
 }
 
 

@@ -135,7 +135,8 @@ ovs_status ovs_field_apply_timed(ovs_lattice lat, ovs_op op, ovs_field in, ovs_f
                                  int32_t iters, double* ms_per_apply);
 /* Launch the tuned dual stencil of the two-sided Lanczos step (Section 4:
  * A v~ and A^dag w~ with the partial sums of w~^dagger A v~ and |A v~|^2) for
- * all nrhs sources of v, with v~ = w~ = v, `iters` times back to back into
+ * all nrhs sources of v, with v~ = v and w~ = a copy of v in library
+ * workspace (distinct memory, as in a solve), `iters` times back to back into
  * library workspace, and return the average kernel time in milliseconds
  * measured with HIP events on the lattice stream.  v is only read.  For
  * measurement; OVS_ERR_ARG for a field of another lattice or iters < 1. */
@@ -158,7 +159,10 @@ ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int
  *  FP32, 1 in FP64; 4: one operator per workgroup, the two workgroups of a tile
  *  adjacent on one XCD; 5: as 4 with the tile's spinors staged in LDS), its
  *  workgroup size (512 for variants 2 and 3, else 256), its LDS cap KiB, its
- *  block order}. */
+ *  block order}.  Block order: 0 = the source blocks of a tile adjacent; 1 =
+ *  source block slowest; 2, 3, 4 = each XCD sweeps its chunk of time slices
+ *  once per window of 1, 2, 3 source blocks (lattices whose Lx Ly is a
+ *  multiple of the tile and Lt of 8; otherwise as 0). */
 ovs_status ovs_get_tuning_ex(ovs_lattice lat, int32_t nrhs, int32_t out[8]);
 /* Install a configuration in the encoding of ovs_get_tuning_ex (e.g. one saved
  * from an earlier ovs_autotune).  OVS_ERR_ARG for values the kernels do not

@@ -453,13 +453,14 @@ ovs_status ovs_dual_apply_timed(ovs_lattice l, ovs_field v, int32_t iters, doubl
   const size_t fb = (size_t)nrhs * N * elem_bytes(l);
   const int nwg = dual_num_wg(l->g);
   Arena a{nullptr};
-  a.take<char>(fb); a.take<char>(fb);
+  a.take<char>(fb); a.take<char>(fb); a.take<char>(fb);
   a.take<double>((size_t)nrhs * nwg * 3); a.take<int>(nrhs); a.take<int>(2);
   ovs_status st = ensure_ws(l, a.off + 4096);
   if (st != OVS_OK) return st;
   Arena b{(char*)l->ws};
   void* T = b.take<char>(fb);
   void* S = b.take<char>(fb);
+  void* Wt = b.take<char>(fb);  // w~: a copy of v in its own memory, as in the solve
   double* part = b.take<double>((size_t)nrhs * nwg * 3);
   int* map = b.take<int>(nrhs);
   int* ints = b.take<int>(2);
@@ -468,10 +469,12 @@ ovs_status ovs_dual_apply_timed(ovs_lattice l, ovs_field v, int32_t iters, doubl
   const int hints[2] = {0, nrhs};  // iteration 0, all sources active
   OVS_HIP(hipMemcpyAsync(map, hmap.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, l->stream));
   OVS_HIP(hipMemcpyAsync(ints, hints, sizeof(hints), hipMemcpyHostToDevice, l->stream));
+  OVS_HIP(hipMemcpyAsync(Wt, v->data, fb, hipMemcpyDeviceToDevice, l->stream));
   OVS_HIP(hipStreamSynchronize(l->stream));
   const Tuning dt = get_dual_tuning(l, nrhs);
-  // V~ = W~ = the field (iteration 0 reads slot 0 of both)
-  const DualArgs da{l->links, v->data, v->data, (long)nrhs * N, false, ints, T, S, part, map,
+  // V~ = the field, W~ = its copy: distinct memory, so the A and A^dag
+  // workgroups of a tile do not share spinor fetches (iteration 0 reads slot 0)
+  const DualArgs da{l->links, v->data, Wt, (long)nrhs * N, false, ints, T, S, part, map,
                     ints + 1, nrhs, dt.lds_kb, dt.order, dt.nt & 1, dt.g - 1};
   const Hop hA = make_hop(l->m_w, l->mu), hAd = make_hop(l->m_w, -l->mu);
   hipEvent_t e0, e1;
@@ -543,7 +546,7 @@ ovs_status ovs_set_tuning_ex(ovs_lattice l, int32_t nrhs, const int32_t cfg[8]) 
                     (d.g != 3 || d.rhs_block <= (f32 ? 2 : 1));
   if (!blk_ok || !g_ok || !stage_ok || !wg_ok || !d_ok || t.nt < 0 || t.nt > 1 || d.nt < 0 || d.nt > 3 ||
       t.lds_kb < 0 || t.lds_kb >= l->lds_max_kb || d.lds_kb < 0 || d.lds_kb >= l->lds_max_kb ||
-      t.order < 0 || t.order > 1 || d.order < 0 || d.order > 1)
+      t.order < 0 || t.order > 4 || d.order < 0 || d.order > 4)
     return OVS_ERR_ARG;
   t.tuned = d.tuned = true;
   set_tuning(l, nrhs, t);
@@ -585,7 +588,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
     for (auto sh : shapes) {
       for (int w : wgs)
         for (int kb : lds_candidates(l))
-          for (int order = 0; order < 2; ++order)
+          for (int order = 0; order < 5; ++order)
             for (int nt = 0; nt < 2; ++nt) {
             Tuning t;
             t.rhs_block = sh[0];
@@ -638,7 +641,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
         for (int bb = 1; bb <= (f32 ? 4 : 2); ++bb) {
           if (bb > nrhs && bb != 1) continue;
           for (int kb : lds_candidates(l))
-            for (int order = 0; order < 2; ++order)
+            for (int order = 0; order < 5; ++order)
               for (int nt = 0; nt < 2; ++nt) {
               DualArgs da{l->links, basis, wbuf, (long)nrhs * N, false, ints, T, S, part, map,
                           ints + 1, nrhs, kb, order, nt, pair};

@@ -186,16 +186,36 @@ struct TileMap {
   int plane;       // Lx*Ly
   int lz;
   int rb_slow;     // source block is the slowest index
+  int group;       // > 0: each XCD sweeps its time chunk once per window of
+                   // `group` source blocks (adjacent within the window)
+  int tiles_xcd;   // tiles of one XCD's time chunk (group > 0)
 };
 
 // Tile map of a launch with nrb source blocks and wg-site tiles (stencil.hip).
+// order 0: source blocks of a tile adjacent; 1: source block slowest; 2, 3, 4:
+// per XCD time chunk, windows of order - 1 source blocks (planar lattices with
+// Lt a multiple of 8; otherwise as order 0).
 TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order);
 
 __device__ __forceinline__ bool map_tile(int bid, const TileMap& m, int& site0, int& rb, int& tile) {
-  const int q = (bid & 7) * m.per_xcd + (bid >> 3);
-  if (q >= m.ntiles * m.nrb) return false;
-  rb = m.rb_slow ? q / m.ntiles : q % m.nrb;
-  const int tq = m.rb_slow ? q % m.ntiles : q / m.nrb;
+  int tq;
+  if (m.group > 0) {
+    // XCD x owns time chunk x; it sweeps the chunk's tiles (plane tile, t, z)
+    // once per window of `group` source blocks, so the sites, links and z / t
+    // neighbours a window touches stay within that XCD's L2
+    const int local = bid >> 3;
+    const int span = m.tiles_xcd * m.group;
+    const int grp = local / span, rem = local - grp * span;
+    const int tl = rem / m.group;
+    rb = grp * m.group + (rem - tl * m.group);
+    if (rb >= m.nrb) return false;
+    tq = (bid & 7) * m.tiles_xcd + tl;
+  } else {
+    const int q = (bid & 7) * m.per_xcd + (bid >> 3);
+    if (q >= m.ntiles * m.nrb) return false;
+    rb = m.rb_slow ? q / m.ntiles : q % m.nrb;
+    tq = m.rb_slow ? q % m.ntiles : q / m.nrb;
+  }
   tile = tq;
   if (m.planar) {
     const int p = tq % m.ppt;

@@ -346,7 +346,6 @@ static void apply_lds_limit(const void* fn) {
 
 TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order) {
   TileMap m;
-  m.rb_slow = order;
   m.wg = wg;
   m.nrb = nrb;
   m.plane = g.lx * g.ly;
@@ -355,6 +354,18 @@ TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order) {
   m.ntiles = (g.V + wg - 1) / wg;
   m.ppt = m.planar ? m.plane / wg : 1;
   m.tchunk = (m.planar && g.lt % 8 == 0) ? g.lt / 8 : g.lt;
+  m.group = 0;
+  m.tiles_xcd = 0;
+  if (order >= 2 && m.planar && g.lt % 8 == 0) {
+    // windows of order - 1 source blocks over each XCD's time chunk
+    m.rb_slow = 0;
+    m.group = order - 1 < nrb ? order - 1 : nrb;
+    m.tiles_xcd = m.ntiles / 8;
+    const int ngroups = (nrb + m.group - 1) / m.group;
+    m.per_xcd = ngroups * m.tiles_xcd * m.group;
+    return m;
+  }
+  m.rb_slow = order == 1 ? 1 : 0;
   const long nb = (long)m.ntiles * nrb;
   m.per_xcd = (int)((nb + 7) / 8);
   return m;

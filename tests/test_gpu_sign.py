@@ -334,6 +334,36 @@ def test_dual_variants_match_cpu(prec, tol, agree):
                 assert rel_rows(yh, first) <= agree
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 3e-5)])
+def test_dual_grouped_block_orders(prec, tol):
+    """The operator-per-workgroup dual stencil with block orders 2-4 (windows of
+    1-3 source blocks per XCD time chunk) on 16 x 16 x 2 x 8 (planar for
+    256-site tiles, Lt = 8), 5 sources: against the oracle's 2sL at k = 40, and
+    persistent launches equal to the per-step kernels bit for bit."""
+    import torch
+    dims = (16, 16, 2, 8)
+    U = synth.random_links(dims, 0.5, seed=95)
+    mu = 0.3
+    b = synth.gaussian_sources(dims, 5, seed=96)
+    A = dirac.csr_A(dims, U, MW, mu)
+    k = 40
+    ref = np.stack([krylov.tsl_apply(lambda v: A @ v, lambda v: A.conj().T @ v, bb, k) for bb in b])
+    lat = lattice(dims, prec, U, mu)
+    base = lat.get_tuning_raw(5)
+    for blk in ((1, 2) if prec == "f32" else (1,)):
+        for variant in (4, 5):
+            for order in (2, 3, 4):
+                cfg = list(base)
+                cfg[4:8] = [100 * blk + 10 * variant + 1, 256, 0, order]
+                lat.set_tuning_raw(5, cfg)
+                y, _, _ = lat.sign_apply(to_dev(b), k)
+                yp, _, _ = lat.sign_apply(to_dev(b), k, persistent=True)
+                e = rel_rows(y.cpu().numpy(), ref)
+                assert e <= tol, (blk, variant, order, e)
+                assert torch.equal(y, yp)
+    lat.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_free_field_8444(prec, tol):
     """Unit links: exact answer from the closed form at any size."""
