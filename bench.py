@@ -39,24 +39,27 @@ EPS, MU, MW = 0.6, 0.4, -1.5
 NRHS = 12
 TOL = 1e-5
 KMAX = 1000
+SAVED_TUNING = os.path.join(ROOT, "paper_0810_4228_amd", "tuning_mi355x.json")
 
 
 # HBM bytes per launch of the tuned FP32 kernels on this workload, from the
 # FETCH_SIZE / WRITE_SIZE counters scaled by a device copy of known size
-# (profiles/*_hbm_counters.txt).  Reported only while the kernel source is the
-# one that was measured.
+# (profiles/*_hbm_counters.txt).  Reported only while the kernel source and
+# the autotuner's choice are the ones that were measured.
 TRAFFIC = {
-    "stencil": {"source_sha256_prefix": "45fd2bbcf65acb86",
-                "bytes_per_launch": 1.9998 * 203870.85 * 1024 + 1.0000 * 147461.12 * 1024},
-    "dual": {"source_sha256_prefix": "45fd2bbcf65acb86",
-             "bytes_per_launch": 1.9998 * 604230.46 * 1024 + 1.0000 * 295215.06 * 1024},
+    "stencil": {"source_sha256_prefix": "7577d3ce44290bd2",
+                "tuning": {"rhs_block": 1, "wg": 128, "lds_kb": 0, "order": 7, "lanes_per_site": 1, "streaming_store": 1, "staged_tile": 1},
+                "bytes_per_launch": 1.9998 * 203967.79 * 1024 + 1.0000 * 147459.06 * 1024},
+    "dual": {"source_sha256_prefix": "7577d3ce44290bd2",
+             "tuning": {"rhs_block": 1, "wg": 256, "lds_kb": 53, "order": 4, "variant": "one thread per site", "streaming_store": 1, "update_streaming_store": 1},
+             "bytes_per_launch": 1.9998 * 440757.08 * 1024 + 1.0000 * 295165.87 * 1024},
 }
 
 
-def measured_traffic(kind):
+def measured_traffic(kind, tuning):
     import hashlib
     t = TRAFFIC[kind]
-    if not t["source_sha256_prefix"]:
+    if not t["source_sha256_prefix"] or t.get("tuning") != tuning.get(kind):
         return None
     src = os.path.join(ROOT, "paper_0810_4228_amd", "csrc", "stencil.hip")
     try:
@@ -286,9 +289,13 @@ def main():
                     help="skip the FP64 single-source comparison")
     ap.add_argument("--stencil-only", action="store_true",
                     help="time the stencil kernel only (for counter collection)")
-    ap.add_argument("--tuning", default=None,
+    ap.add_argument("--tuning", default=SAVED_TUNING,
                     help="JSON file with a saved kernel configuration: loaded if present, "
-                         "written after autotuning otherwise")
+                         "written after autotuning otherwise (default: the configuration "
+                         "the autotuner chose on an MI355X, the one the committed counter "
+                         "profiles were taken with)")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune even if the tuning file holds a configuration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times: the known-size reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -331,16 +338,18 @@ def main():
     del U
     key = f"{DIMS}-{NRHS}-f32"
     saved = None
-    if args.tuning and os.path.exists(args.tuning):
+    if args.tuning and os.path.exists(args.tuning) and not args.retune:
         with open(args.tuning) as fh:
             saved = json.load(fh).get(key)
     if saved:
         log("bench: tuning from", args.tuning)
         lat.set_tuning_raw(NRHS, saved)
+        tuning_src = "saved: " + os.path.relpath(args.tuning, ROOT)
     else:
         log("bench: autotune")
         lat.autotune(NRHS)
-        if args.tuning:
+        tuning_src = "autotuned in this run"
+        if args.tuning and args.tuning != SAVED_TUNING:
             with open(args.tuning, "w") as fh:
                 json.dump({key: lat.get_tuning_raw(NRHS)}, fh)
     rb, wg = lat.get_tuning(NRHS)
@@ -418,18 +427,19 @@ def main():
             "graph": True,
         },
         "tuning": tuning,
+        "tuning_source": tuning_src,
         "k_used": k_used,
         "est_rel_err_max": est,
         "phase_ms": phase,
         "stencil": {"kernel": "k_wilson<float>", "us_per_apply": ms_st * 1e3, "gbps": st_gbs,
                     "frac_peak": st_gbs / HBM_PEAK_GBS, "rhs_block": rb, "wg": wg,
                     "staged_tile": tuning["stencil"]["staged_tile"],
-                    "bytes_per_apply": st_bytes, "traffic": measured_traffic("stencil")},
+                    "bytes_per_apply": st_bytes, "traffic": measured_traffic("stencil", tuning)},
         "dual_stencil": {"kernel": du_name, "us_per_apply": ms_du * 1e3, "gbps": du_gbs,
                          "frac_peak": du_gbs / HBM_PEAK_GBS, "bytes_per_apply": du_bytes},
         "roofline": {"bound": "hbm", "kernel": du_name, "achieved": du_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": du_gbs / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("dual"),
+                     "traffic": measured_traffic("dual", tuning),
                      "copy_gbps": copy_gbs, "frac_of_copy": du_gbs / copy_gbs},
     }
     if not args.no_compare:

@@ -160,9 +160,9 @@ ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int
  *  adjacent on one XCD; 5: as 4 with the tile's spinors staged in LDS), its
  *  workgroup size (512 for variants 2 and 3, else 256), its LDS cap KiB, its
  *  block order}.  Block order: 0 = the source blocks of a tile adjacent; 1 =
- *  source block slowest; 2, 3, 4 = each XCD sweeps its chunk of time slices
- *  once per window of 1, 2, 3 source blocks (lattices whose Lx Ly is a
- *  multiple of the tile and Lt of 8; otherwise as 0). */
+ *  source block slowest; 2 to 7 = each XCD sweeps its chunk of time slices
+ *  once per window of 1, 2, 3, 4, 6 or all source blocks (lattices whose Lx Ly
+ *  is a multiple of the tile and Lt of 8; otherwise as 0). */
 ovs_status ovs_get_tuning_ex(ovs_lattice lat, int32_t nrhs, int32_t out[8]);
 /* Install a configuration in the encoding of ovs_get_tuning_ex (e.g. one saved
  * from an earlier ovs_autotune).  OVS_ERR_ARG for values the kernels do not

@@ -32,6 +32,10 @@ void record_error(const char* what, int line, hipError_t e) {
 
 namespace ovs {
 
+// Batches of this many sources or more are solved as two concurrent halves
+// (run_batch); the autotuner times the dual stencil the same way.
+constexpr int kSplitMin = 8;
+
 // kappa * eta^{+-}_nu (Section 1): e^{+-mu} on the time hops only.
 Hop make_hop(double m_w, double mu) {
   Hop h;
@@ -546,7 +550,7 @@ ovs_status ovs_set_tuning_ex(ovs_lattice l, int32_t nrhs, const int32_t cfg[8]) 
                     (d.g != 3 || d.rhs_block <= (f32 ? 2 : 1));
   if (!blk_ok || !g_ok || !stage_ok || !wg_ok || !d_ok || t.nt < 0 || t.nt > 1 || d.nt < 0 || d.nt > 3 ||
       t.lds_kb < 0 || t.lds_kb >= l->lds_max_kb || d.lds_kb < 0 || d.lds_kb >= l->lds_max_kb ||
-      t.order < 0 || t.order > 4 || d.order < 0 || d.order > 4)
+      t.order < 0 || t.order > 7 || d.order < 0 || d.order > 7)
     return OVS_ERR_ARG;
   t.tuned = d.tuned = true;
   set_tuning(l, nrhs, t);
@@ -588,7 +592,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
     for (auto sh : shapes) {
       for (int w : wgs)
         for (int kb : lds_candidates(l))
-          for (int order = 0; order < 5; ++order)
+          for (int order = 0; order < 8; ++order)
             for (int nt = 0; nt < 2; ++nt) {
             Tuning t;
             t.rhs_block = sh[0];
@@ -616,7 +620,7 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
       const int nwg = dual_num_wg(l->g);
       Arena a{nullptr};
       a.take<char>(fb); a.take<char>(3 * fb); a.take<char>(fb); a.take<char>(fb);
-      a.take<double>((size_t)nrhs * nwg * 3); a.take<int>(nrhs); a.take<int>(2);
+      a.take<double>((size_t)nrhs * nwg * 3); a.take<int>(nrhs); a.take<int>(4);
       st = ensure_ws(l, a.off + 4096);
       if (st == OVS_OK) {
         Arena b{(char*)l->ws};
@@ -626,10 +630,20 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
         void* S = b.take<char>(fb);
         double* part = b.take<double>((size_t)nrhs * nwg * 3);
         int* map = b.take<int>(nrhs);
-        int* ints = b.take<int>(2);
+        int* ints = b.take<int>(4);
         std::vector<int> hmap(nrhs);
         for (int i = 0; i < nrhs; ++i) hmap[i] = i;
-        int hints[2] = {0, nrhs};
+        // batches the solve splits run as two concurrent halves (run_batch):
+        // the candidates are timed that way, each half on its own stream
+        const bool halves = nrhs >= kSplitMin;
+        const int n1 = halves ? nrhs / 2 : nrhs, n2 = nrhs - n1;
+        int hints[4] = {0, nrhs, n1, n2};
+        hipStream_t s2 = nullptr;
+        hipEvent_t fork = nullptr, join = nullptr;
+        if (halves && (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
+                       hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess))
+          st = OVS_ERR_HIP;
         (void)hipMemcpyAsync(map, hmap.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, l->stream);
         (void)hipMemcpyAsync(ints, hints, sizeof(hints), hipMemcpyHostToDevice, l->stream);
         (void)hipMemsetAsync(basis, 0, fb, l->stream);
@@ -641,19 +655,31 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
         for (int bb = 1; bb <= (f32 ? 4 : 2); ++bb) {
           if (bb > nrhs && bb != 1) continue;
           for (int kb : lds_candidates(l))
-            for (int order = 0; order < 5; ++order)
+            for (int order = 0; order < 8; ++order)
               for (int nt = 0; nt < 2; ++nt) {
+              const size_t eb = elem_bytes(l);
               DualArgs da{l->links, basis, wbuf, (long)nrhs * N, false, ints, T, S, part, map,
-                          ints + 1, nrhs, kb, order, nt, pair};
+                          halves ? ints + 2 : ints + 1, n1, kb, order, nt, pair};
+              DualArgs db{l->links, (char*)basis + n1 * N * eb, (char*)wbuf + n1 * N * eb,
+                          (long)nrhs * N, false, ints, (char*)T + n1 * N * eb,
+                          (char*)S + n1 * N * eb, part + (size_t)n1 * nwg * 3, map, ints + 3,
+                          n2, kb, order, nt, pair};
+              auto launch = [&]() {
+                if (launch_dual(f32, da, l->g, hA, hAd, bb, l->stream) != hipSuccess) return false;
+                if (!halves) return true;
+                return hipEventRecord(fork, l->stream) == hipSuccess &&
+                       hipStreamWaitEvent(s2, fork, 0) == hipSuccess &&
+                       launch_dual(f32, db, l->g, hA, hAd, bb, s2) == hipSuccess &&
+                       hipEventRecord(join, s2) == hipSuccess &&
+                       hipStreamWaitEvent(l->stream, join, 0) == hipSuccess;
+              };
               hipEvent_t e0, e1;
               (void)hipEventCreate(&e0);
               (void)hipEventCreate(&e1);
-              bool ok = true;
-              for (int w = 0; w < 2 && ok; ++w)
-                ok = launch_dual(f32, da, l->g, hA, hAd, bb, l->stream) == hipSuccess;
+              bool ok = st == OVS_OK;
+              for (int w = 0; w < 2 && ok; ++w) ok = launch();
               (void)hipEventRecord(e0, l->stream);
-              for (int w = 0; w < 6 && ok; ++w)
-                ok = launch_dual(f32, da, l->g, hA, hAd, bb, l->stream) == hipSuccess;
+              for (int w = 0; w < 6 && ok; ++w) ok = launch();
               (void)hipEventRecord(e1, l->stream);
               (void)hipEventSynchronize(e1);
               float f = 0;
@@ -679,7 +705,11 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
         // streaming stores measured ~1% faster over whole solves at 16^3 x 32
         dbest.nt |= 2;
         dbest.tuned = true;
-        set_dual_tuning(l, nrhs, dbest);
+        if (st == OVS_OK) set_dual_tuning(l, nrhs, dbest);
+        if (s2) (void)hipStreamSynchronize(s2);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (s2) (void)hipStreamDestroy(s2);
       }
     }
     (void)hipStreamSynchronize(l->stream);
@@ -1303,7 +1333,6 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
 // of one half overlap the bandwidth-bound update of the other (+10% solves/s
 // measured at 16^3 x 32 with 12 sources).  Per source the arithmetic is that
 // of the whole batch (both halves use the whole batch's tuned kernels).
-constexpr int kSplitMin = 8;
 
 static ovs_status worker_ready(ovs_lattice_s* l) {
   if (!l->worker) {

@@ -192,9 +192,9 @@ struct TileMap {
 };
 
 // Tile map of a launch with nrb source blocks and wg-site tiles (stencil.hip).
-// order 0: source blocks of a tile adjacent; 1: source block slowest; 2, 3, 4:
-// per XCD time chunk, windows of order - 1 source blocks (planar lattices with
-// Lt a multiple of 8; otherwise as order 0).
+// order 0: source blocks of a tile adjacent; 1: source block slowest; 2 to 7:
+// per XCD time chunk, windows of 1, 2, 3, 4, 6 or all source blocks (planar
+// lattices with Lt a multiple of 8; otherwise as order 0).
 TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order);
 
 __device__ __forceinline__ bool map_tile(int bid, const TileMap& m, int& site0, int& rb, int& tile) {

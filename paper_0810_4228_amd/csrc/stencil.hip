@@ -357,9 +357,10 @@ TileMap make_tile_map(const Geometry& g, int wg, int nrb, int order) {
   m.group = 0;
   m.tiles_xcd = 0;
   if (order >= 2 && m.planar && g.lt % 8 == 0) {
-    // windows of order - 1 source blocks over each XCD's time chunk
+    // windows of 1, 2, 3, 4, 6 or all source blocks over each XCD's time chunk
+    static const int kWindow[6] = {1, 2, 3, 4, 6, 1 << 30};
     m.rb_slow = 0;
-    m.group = order - 1 < nrb ? order - 1 : nrb;
+    m.group = kWindow[order - 2] < nrb ? kWindow[order - 2] : nrb;
     m.tiles_xcd = m.ntiles / 8;
     const int ngroups = (nrb + m.group - 1) / m.group;
     m.per_xcd = ngroups * m.tiles_xcd * m.group;

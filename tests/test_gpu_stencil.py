@@ -98,8 +98,9 @@ def test_every_stencil_configuration(prec):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_grouped_block_orders(prec):
-    """Block orders 2-4 (each XCD sweeps its time chunk once per window of 1-3
-    source blocks) need Lx Ly a multiple of the tile and Lt a multiple of 8:
+    """Block orders 2-7 (each XCD sweeps its time chunk once per window of 1, 2,
+    3, 4, 6 or all source blocks) need Lx Ly a multiple of the tile and Lt a
+    multiple of 8:
     16 x 16 x 2 x 8 with 256-site tiles and 8 x 8 x 4 x 8 with 64-site tiles,
     7 sources (ragged windows), against the oracle."""
     for dims, wg in (((16, 16, 2, 8), 256), ((8, 8, 4, 8), 64)):
@@ -113,7 +114,7 @@ def test_grouped_block_orders(prec):
             for st in (0, 1):
                 if st and blk > (4 if prec == "f32" else 2):
                     continue
-                for order in (2, 3, 4):
+                for order in range(2, 8):
                     cfg = list(base)
                     cfg[0:4] = [1000 * st + 100 * blk + 10 + 1, wg, 0, order]
                     lat.set_tuning_raw(7, cfg)
