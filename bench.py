@@ -77,7 +77,8 @@ def dual_kernel_name(du):
             "lane pair": f"k_dual_pair<float, {b}, false>",
             "lane pair, LDS-staged tile": f"k_dual_pair<float, {b}, true>",
             "operator per workgroup": f"k_dual_op<float, {b}, false>",
-            "operator per workgroup, LDS-staged tile": f"k_dual_op<float, {b}, true>"}.get(du["variant"], "?")
+            "operator per workgroup, LDS-staged tile": f"k_dual_op<float, {b}, true>",
+            "operator per workgroup, marching along t": "k_dual_march<float>"}.get(du["variant"], "?")
 
 
 def log(*a):

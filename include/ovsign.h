@@ -157,9 +157,12 @@ ovs_status ovs_get_tuning(ovs_lattice lat, int32_t nrhs, int32_t* rhs_block, int
  *  (variant 1: one thread computes A v and A^dag w; 2: a lane pair splits the two
  *  operators; 3: as 2 with the tile's spinors staged in LDS, rhs block <= 2 in
  *  FP32, 1 in FP64; 4: one operator per workgroup, the two workgroups of a tile
- *  adjacent on one XCD; 5: as 4 with the tile's spinors staged in LDS), its
- *  workgroup size (512 for variants 2 and 3, else 256), its LDS cap KiB, its
- *  block order}.  Block order: 0 = the source blocks of a tile adjacent; 1 =
+ *  adjacent on one XCD; 5: as 4 with the tile's spinors staged in LDS; 6: one
+ *  operator and one source per workgroup, marching along t through the XCD's
+ *  time chunk with the time neighbours in registers and the plane in LDS, FP32
+ *  storage, rhs block 1, Lx Ly = 256 and Lt a multiple of 8, block order 0 (sources of a
+ *  column adjacent) or 1 (columns of a source adjacent)), its workgroup size
+ *  (512 for variants 2 and 3, else 256), its LDS cap KiB, its block order}.  Block order: 0 = the source blocks of a tile adjacent; 1 =
  *  source block slowest; 2 to 7 = each XCD sweeps its chunk of time slices
  *  once per window of 1, 2, 3, 4, 6 or all source blocks (lattices whose Lx Ly
  *  is a multiple of the tile and Lt of 8; otherwise as 0). */

@@ -256,7 +256,8 @@ class Lattice:
         du = dict(zip(keys, out[4:8]))
         shape = du["rhs_block"]
         variants = {1: "one thread per site", 2: "lane pair", 3: "lane pair, LDS-staged tile",
-                    4: "operator per workgroup", 5: "operator per workgroup, LDS-staged tile"}
+                    4: "operator per workgroup", 5: "operator per workgroup, LDS-staged tile",
+                    6: "operator per workgroup, marching along t"}
         du.update(rhs_block=shape // 100, variant=variants.get((shape // 10) % 10, "?"),
                   streaming_store=shape % 2, update_streaming_store=(shape % 10) // 2)
         return {"stencil": st, "dual": du}
@@ -430,7 +431,9 @@ class Field:
 
     def dual_timed(self, iters):
         """Average time (ms) of the tuned two-sided Lanczos dual stencil on this
-        field's sources (v~ = w~ = the field), HIP events on the lattice stream."""
+        field's sources (v~ = the field, w~ = a copy of it in the workspace, so
+        the two are read from distinct memory as in a solve), HIP events on the
+        lattice stream."""
         ms = ctypes.c_double()
         _check(self.lat._lib.ovs_dual_apply_timed(self.lat._h, self._h, int(iters), ctypes.byref(ms)),
                "ovs_dual_apply_timed")

@@ -546,8 +546,12 @@ ovs_status ovs_set_tuning_ex(ovs_lattice l, int32_t nrhs, const int32_t cfg[8]) 
   // the staged tile (B 12 256 values) fits for B <= 4 in FP32 and B <= 2 in FP64
   const bool stage_ok = t.stage == 0 || (t.stage == 1 && t.g == 1 && t.rhs_block <= (f32 ? 4 : 2));
   const bool wg_ok = t.wg == 64 || t.wg == 128 || t.wg == 256;
-  const bool d_ok = d.rhs_block >= 1 && d.rhs_block <= (f32 ? 4 : 2) && d.g >= 1 && d.g <= 5 &&
-                    (d.g != 3 || d.rhs_block <= (f32 ? 2 : 1));
+  // variant 6 marches along t: FP32 storage, one source per thread, xy planes
+  // of 256 sites, Lt % 8 == 0
+  const bool march_ok = f32 && l->g.lx * l->g.ly == 256 && l->g.lt % 8 == 0;
+  const bool d_ok = d.rhs_block >= 1 && d.rhs_block <= (f32 ? 4 : 2) && d.g >= 1 && d.g <= 6 &&
+                    (d.g != 3 || d.rhs_block <= (f32 ? 2 : 1)) &&
+                    (d.g != 6 || (d.rhs_block == 1 && march_ok));
   if (!blk_ok || !g_ok || !stage_ok || !wg_ok || !d_ok || t.nt < 0 || t.nt > 1 || d.nt < 0 || d.nt > 3 ||
       t.lds_kb < 0 || t.lds_kb >= l->lds_max_kb || d.lds_kb < 0 || d.lds_kb >= l->lds_max_kb ||
       t.order < 0 || t.order > 7 || d.order < 0 || d.order > 7)
@@ -651,11 +655,12 @@ ovs_status ovs_autotune(ovs_lattice l, int32_t nrhs) {
         const Hop hA = make_hop(l->m_w, l->mu), hAd = make_hop(l->m_w, -l->mu);
         Tuning dbest;
         double bms = 1e300;
-        for (int pair = 0; pair < 5; ++pair)
+        for (int pair = 0; pair < 6; ++pair)
         for (int bb = 1; bb <= (f32 ? 4 : 2); ++bb) {
           if (bb > nrhs && bb != 1) continue;
+          if (pair == 5 && (bb != 1 || !f32)) continue;  // the t march: FP32, one source per thread
           for (int kb : lds_candidates(l))
-            for (int order = 0; order < 8; ++order)
+            for (int order = 0; order < (pair == 5 ? 2 : 8); ++order)
               for (int nt = 0; nt < 2; ++nt) {
               const size_t eb = elem_bytes(l);
               DualArgs da{l->links, basis, wbuf, (long)nrhs * N, false, ints, T, S, part, map,

@@ -171,7 +171,9 @@ struct DualArgs {
   int pair = 0;        // 1: lane pairs split the two operators (k_dual_pair);
                        // 2: the same with the tile's spinors staged in LDS;
                        // 3: one operator per workgroup (k_dual_op); 4: the
-                       // same with the tile's spinors staged in LDS
+                       // same with the tile's spinors staged in LDS; 5: one
+                       // operator and source per workgroup marching along t
+                       // (k_dual_march; order 0 or 1)
 };
 hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
                        const Hop& hAd, int rhs_block, hipStream_t s);

@@ -10,6 +10,7 @@
 // Loads and stores are coalesced: the field layout is [src][12][V].
 #include <atomic>
 #include <mutex>
+#include <type_traits>
 
 #include "ovs_common.h"
 #include "ovs_device.h"
@@ -761,6 +762,152 @@ k_dual_op(const typename Vec2<R>::T* __restrict__ links,
                             partials, g, hA, hAd, rhs_map, *n_active, nt, tm);
 }
 
+// Dual stencil marching along t (variant 6): one operator and one source per
+// workgroup, over one (xy tile, z) column of the XCD's chunk of time slices.
+// Each thread keeps its own site's spinors at t-1, t and t+1 and the time link
+// at t-1 in registers while the workgroup steps through the chunk, so the time
+// hops fetch nothing twice; at every step the tile's spinors at t go from the
+// registers to LDS, where the in-tile x and y neighbours are read.  The z
+// neighbours (and x, y ones outside the tile) are loaded as in the other
+// variants (the workgroups of neighbouring z, and of the other sources at the
+// same column, run at the same time and share them in L2).  The
+// arithmetic, its order and the per-tile partial sums are those of the
+// operator-per-workgroup body with one source per thread, so the results agree
+// bit for bit.  Needs xy planes of 256 sites (the tile) and Lt a multiple of
+// 8 (the launch checks).  order 0: the sources of a column
+// adjacent in dispatch order; 1: the columns of a source adjacent.
+template <typename R>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_dual_march(const typename Vec2<R>::T* __restrict__ links,
+             const typename Vec2<R>::T* __restrict__ basis,
+             const typename Vec2<R>::T* __restrict__ wbuf, long basis_stride, int ring,
+             const int* __restrict__ it, typename Vec2<R>::T* __restrict__ out_t,
+             typename Vec2<R>::T* __restrict__ out_s, double* __restrict__ partials, Geometry g,
+             HopR<R> hA, HopR<R> hAd, const int* __restrict__ rhs_map,
+             const int* __restrict__ n_active, int nslots, int nt, TileMap tm, int order) {
+  using T2 = typename Vec2<R>::T;
+  __shared__ double lds[(256 / 64) * 3];
+  __shared__ T2 plane[12 * 256];  // the tile's spinors at the current t: [component][site]
+  const int tc = blockIdx.x & 7;  // the XCD's time chunk
+  int local = blockIdx.x >> 3;
+  const int op = local & 1;       // the A and A^dag workgroups of a column are adjacent
+  local >>= 1;
+  const int ncol = tm.ppt * tm.lz;
+  int col, j;
+  if (order == 1) {
+    j = local / ncol;
+    col = local - j * ncol;
+  } else {
+    col = local / nslots;
+    j = local - col * nslots;
+  }
+  if (col >= ncol || j >= *n_active) return;  // uniform over the workgroup
+  const int iter = *it;
+  const T2* in_v = basis + (long)(ring ? iter % 3 : iter) * basis_stride;
+  const T2* in_w = wbuf + (long)(iter % 3) * basis_stride;
+  const int slot = rhs_map[j];
+  const int V = g.Vs;
+  const long base = (long)slot * 12 * V;
+  const T2* f = (op ? in_w : in_v) + base;
+  T2* out = (op ? out_s : out_t) + base;
+  const HopR<R>& hc = op ? hAd : hA;
+  const int p = col % tm.ppt, z = col / tm.ppt;
+  const int st = tm.plane * tm.lz;                         // sites per time slice
+  const int s0 = p * 256 + (int)threadIdx.x + tm.plane * z;  // the thread's site at t = 0
+  const int t0 = tc * tm.tchunk;
+  const int tprev = t0 == 0 ? g.lt - 1 : t0 - 1;
+  // opaque to the optimiser, as nsrc in the other variants: loads stay behind
+  // their direction's guard instead of being hoisted all at once
+  int gate = 1;
+  __asm__ volatile("" : "+s"(gate));
+  Cx<R> pm[12], pc[12], um[9];
+  load_spinor_u(f, V, s0 + tprev * st, false, pm);
+  load_spinor_u(f, V, s0 + t0 * st, false, pc);
+  load_link_u(links, V, 3, s0 + tprev * st, um);
+#pragma unroll 1
+  for (int i = 0; i < tm.tchunk; ++i) {
+    const int s = s0 + (t0 + i) * st;
+    const int site0 = s - (int)threadIdx.x;  // the tile's first site at this t
+    const Nbr nb = neighbours(s, g);
+    // the tile's spinors at t go to LDS from the registers: in-tile x and y
+    // neighbours are read there
+    __syncthreads();  // the previous step's readers are done
+#pragma unroll
+    for (int c = 0; c < 12; ++c) plane[c * 256 + threadIdx.x] = T2{pc[c].re, pc[c].im};
+    __syncthreads();
+    // the xy plane is the tile (256 sites): x and y neighbours are in LDS
+    auto load_lds = [&](int n, Cx<R>(&q)[12]) {
+      const int d = n - site0;
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const T2 v = plane[c * 256 + d];
+        q[c] = {v.x, v.y};
+      }
+    };
+    Cx<R> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+    Cx<R> u[9], psi[12];
+#define OVS_MARCH_DIR(NU, LOAD)                                    \
+  if (gate) {                                                      \
+    load_link_u(links, V, NU, nb.b[NU], u);                        \
+    LOAD(nb.b[NU], psi);                                           \
+    hop<R, NU, +1, false>(acc, u, psi, hc.fwd[NU]);                \
+  }                                                                \
+  if (gate) {                                                      \
+    load_link_u(links, V, NU, s, u);                               \
+    LOAD(nb.f[NU], psi);                                           \
+    hop<R, NU, -1, true>(acc, u, psi, hc.bwd[NU]);                 \
+  }
+#define OVS_GLOBAL(n, q) load_spinor_u(f, V, n, false, q)
+    OVS_MARCH_DIR(0, load_lds)
+    OVS_MARCH_DIR(1, load_lds)
+    OVS_MARCH_DIR(2, OVS_GLOBAL)
+#undef OVS_GLOBAL
+#undef OVS_MARCH_DIR
+    hop<R, 3, +1, false>(acc, um, pm, hc.fwd[3]);
+    if (gate) {
+      load_link_u(links, V, 3, s, um);
+      load_spinor_u(f, V, nb.f[3], false, psi);
+      hop<R, 3, -1, true>(acc, um, psi, hc.bwd[3]);
+    }
+    Cx<R> o[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      o[c] = pc[c] - acc[c];
+      if (c >= 6) o[c] = -o[c];
+    }
+    store_spinor(out, V, s, nt, o);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      pm[c] = pc[c];
+      pc[c] = psi[c];
+    }
+    if (!op) {  // uniform over the workgroup
+      double part[3] = {0.0, 0.0, 0.0};
+      Cx<R> pw[12];
+      load_spinor_u(in_w + base, V, s, false, pw);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        const Cx<double> t64 = {(double)o[c].re, (double)o[c].im};
+        const Cx<double> w64 = {(double)pw[c].re, (double)pw[c].im};
+        const Cx<double> q = cmulc(w64, t64);
+        part[0] += q.re;
+        part[1] += q.im;
+        part[2] += cnorm2(t64);
+      }
+      block_sum<3>(part, lds);
+      if (threadIdx.x == 0) {
+        const int tile = p + tm.ppt * (i + tm.tchunk * (z + tm.lz * tc));
+        double* d = partials + ((long)slot * tm.ntiles + tile) * 3;
+        d[0] = part[0];
+        d[1] = part[1];
+        d[2] = part[2];
+      }
+    }
+  }
+}
+
 int dual_num_wg(const Geometry& g) { return (g.V + 255) / 256; }
 
 template <typename R, int B>
@@ -780,6 +927,25 @@ static hipError_t launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, 
     apply_lds_limit((const void*)k_dual_op<R, B, false>);
     if constexpr (kStageOp) apply_lds_limit((const void*)k_dual_op<R, B, true>);
   });
+  if (a.pair == 5) {
+    // marching along t: FP32 storage (the FP64 ring does not fit the register
+    // budget), one source per thread, xy planes of 256 sites, Lt % 8 == 0
+    if constexpr (std::is_same_v<R, float> && B == 1) {
+      if (g.lx * g.ly != 256 || g.lt % 8 != 0) return hipErrorInvalidValue;
+      static std::once_flag march_lds;
+      std::call_once(march_lds, [] { apply_lds_limit((const void*)k_dual_march<R>); });
+      if (!lds_fits((const void*)k_dual_march<R>, a.lds_kb)) return hipErrorInvalidValue;
+      const int per_xcd = 2 * tm.ppt * tm.lz * a.nrhs_slots;
+      hipLaunchKernelGGL((k_dual_march<R>), dim3(8 * per_xcd), dim3(256), a.lds_kb * 1024, s,
+                         (const T2*)a.links, (const T2*)a.basis, (const T2*)a.wbuf,
+                         a.basis_stride, (int)a.ring, a.it, (T2*)a.out_t, (T2*)a.out_s,
+                         a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd), a.rhs_map,
+                         a.n_active, a.nrhs_slots, a.nt, tm, a.order == 1 ? 1 : 0);
+      return hipSuccess;
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (a.pair == 3 || a.pair == 4) {
     const bool stage = a.pair == 4;
     if constexpr (!kStageOp) {

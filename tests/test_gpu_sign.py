@@ -340,7 +340,8 @@ def test_dual_grouped_block_orders(prec, tol):
     with block orders 2-7 (windows of 1, 2, 3, 4, 6 or all source blocks per
     XCD time chunk) on 16 x 16 x 2 x 8 (planar for 256-site tiles, Lt = 8), 5
     sources: against the oracle's 2sL at k = 40, and persistent launches equal
-    to the per-step kernels bit for bit."""
+    to the per-step kernels bit for bit.  The variant marching along t (FP32)
+    equals the operator-per-workgroup variant bit for bit."""
     import torch
     dims = (16, 16, 2, 8)
     U = synth.random_links(dims, 0.5, seed=95)
@@ -362,6 +363,27 @@ def test_dual_grouped_block_orders(prec, tol):
                 e = rel_rows(y.cpu().numpy(), ref)
                 assert e <= tol, (blk, variant, order, e)
                 assert torch.equal(y, yp)
+    if prec == "f32":
+        # variant 6 (marching along t) does the arithmetic of variant 4 with one
+        # source per thread in the same order: equal bit for bit, both block orders
+        cfg = list(base)
+        cfg[4:8] = [100 + 40 + 1, 256, 0, 0]
+        lat.set_tuning_raw(5, cfg)
+        y4, _, _ = lat.sign_apply(to_dev(b), k)
+        for order in (0, 1):
+            for nt in (0, 1):
+                cfg[4:8] = [100 + 60 + nt, 256, 0, order]
+                lat.set_tuning_raw(5, cfg)
+                y6, _, _ = lat.sign_apply(to_dev(b), k)
+                assert rel_rows(y6.cpu().numpy(), ref) <= tol
+                assert torch.equal(y6, y4), (order, nt)
+        yp, _, _ = lat.sign_apply(to_dev(b), k, persistent=True)
+        assert torch.equal(yp, y4)
+    else:
+        cfg = list(base)
+        cfg[4:8] = [160, 256, 0, 0]
+        with pytest.raises(Exception):
+            lat.set_tuning_raw(5, cfg)  # variant 6 needs FP32 storage
     lat.close()
 
 
