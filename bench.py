@@ -195,6 +195,31 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, iters=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def overlap_eigs_timing(ovs, torch, dev, dims=(8, 8, 8, 8), nev=4, ncv=40):
+    """ovs_overlap_eigs: the nev eigenvalues of smallest magnitude of D_ov(mu)
+    (eps 0.6, mu 0.3, FP64, sign solves to 1e-10, Ritz residuals to 1e-8),
+    wall time of one call after a warm-up call."""
+    import synth
+    lat = ovs.Lattice(dims, precision="f64")
+    lat.set_links(torch.from_numpy(synth.random_links(dims, 0.6, seed=synth.LINK_SEED)).to(dev))
+    lat.set_params(MW, 0.3)
+    kw = dict(ncv=ncv, k_inner=1000, tol_inner=1e-10, tol=1e-8, max_restarts=200)
+    try:
+        lat.overlap_eigs(nev, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, _, info, st = lat.overlap_eigs(nev, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+    except Exception as e:  # reported, not fatal to the bench line
+        lat.close()
+        return {"error": str(e)}
+    lat.close()
+    return {"workload": "x".join(map(str, dims)) + f", eps 0.6, mu 0.3, FP64, nev {nev}, ncv {ncv}",
+            "ms": ms, "status": st, "lambda": [[z.real, z.imag] for z in lam], **info,
+            "ms_per_sign_solve": ms / max(info["sign_solves"], 1)}
+
+
 def gradient_timing(ovs, torch, dev, dims=(8, 8, 8, 8), k=400):
     """ovs_sign_apply_vjp (eps 0.6, mu 0.3, one Gaussian source and cotangent,
     FP64, k iterations) with the Lanczos vectors recomputed from checkpoints and
@@ -460,6 +485,8 @@ def main():
         log("bench: gradient timing")
         out["gradient"] = [gradient_timing(ovs, torch, dev),
                            gradient_timing(ovs, torch, dev, dims=(16, 16, 16, 16), k=200)]
+        log("bench: overlap eigenvalues")
+        out["overlap_eigs"] = overlap_eigs_timing(ovs, torch, dev)
         log("bench: gradient", out["gradient"])
     if not args.no_check:
         log("bench: free-field accuracy check")

@@ -279,6 +279,37 @@ ovs_status ovs_inner_sign_tridiag(ovs_lattice lat, int32_t batch, int32_t k, con
 ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, const double* H,
                                      double* x, double* err);
 
+/* ---- eigenvalues of the overlap operator (Sections 1 and 5) ------------- */
+
+/* The nev eigenvalues of smallest magnitude of D_ov(mu) = 1 + gamma5 sgn(A)
+ * (Section 1), with sgn(A) applied by the two-sided Lanczos driver (Section
+ * 4; the closing outlook of Section 5 applies these methods to the overlap
+ * operator's eigenvalues).  Arnoldi with thick restarts in Krylov-Schur form:
+ * a basis of ncv vectors, one sign solve (ovs_sign_apply, OVS_FLAG_OVERLAP,
+ * one source, deflated by the first n_defl triples of defl if not NULL) per
+ * step, classical Gram-Schmidt twice; at a restart the Ritz vectors of the
+ * nev + (ncv - nev)/2 smallest |theta| are kept.
+ *   nev, ncv    : 1 <= nev, nev + 2 <= ncv <= 256, ncv < N.
+ *   k_inner, tol_inner : k_max and target relative error of each sign solve.
+ *   tol         : stop when every wanted Ritz pair (unit x) has the residual
+ *                 estimate |D_ov x - theta x| <= tol; the inner solves' error
+ *                 limits what tol can reach.
+ *   max_restarts: restarts at most (0: one Arnoldi pass of ncv steps).
+ *   lambda      : host complex128 [nev], ordered by increasing magnitude.
+ *   vecs        : device complex128 [nev][V][4][3] unit Ritz vectors, or NULL.
+ *   info        : host double [4] or NULL: largest residual estimate of the
+ *                 wanted pairs, restarts, sign solves, sign solves that
+ *                 returned a warning.
+ * The library allocates (ncv + 1) + ncv FP64 fields of device memory for the
+ * call and frees them on return.  OVS_WARN_NOT_CONVERGED if tol was not met
+ * within max_restarts or an inner solve returned a warning (outputs still
+ * written); OVS_WARN_BREAKDOWN if the basis could not be extended (an
+ * invariant subspace or dependent Ritz vectors).  Errors: OVS_ERR_ARG,
+ * OVS_ERR_STATE (links or parameters not set), OVS_ERR_ALLOC, OVS_ERR_HIP. */
+ovs_status ovs_overlap_eigs(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, int32_t nev,
+                           int32_t ncv, int32_t k_inner, double tol_inner, double tol,
+                           int32_t max_restarts, double* lambda, void* vecs, double* info);
+
 /* Eigen-decomposition of a small general complex matrix on the host (the
  * Rayleigh-Ritz step of ovs_deflation_compute): A host complex128 n x n,
  * column major; lambda host complex128 [n]; V host complex128 n x n, unit-norm

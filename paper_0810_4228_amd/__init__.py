@@ -43,7 +43,7 @@ EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
     "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
     "ovs_field_apply", "ovs_field_apply_timed", "ovs_dual_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
-    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_last_coefficients",
+    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_overlap_eigs", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
 ]
 
@@ -120,6 +120,7 @@ def load():
         "ovs_deflation_get": [P, DP, P, P, DP],
         "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
         "ovs_sign_apply_vjp": [P, P, P, I, I, I, P, P, DP, P, DP],
+        "ovs_overlap_eigs": [P, P, I, I, I, I, D, D, I, DP, P, DP],
         "ovs_last_coefficients": [P, DP, DP, DP, DP],
         "ovs_inner_sign_tridiag": [P, I, I, DP, DP, DP, DP, DP],
         "ovs_inner_sign_hessenberg": [P, I, I, DP, DP, DP],
@@ -309,6 +310,32 @@ class Lattice:
                                       METHODS[method], flags, infos)
         _check(st, "ovs_sign_apply")
         return y, [i.as_dict() for i in infos], st
+
+    def overlap_eigs(self, nev, ncv=None, k_inner=400, tol_inner=1e-10, tol=1e-8,
+                     max_restarts=100, defl=None, n_defl=None, vectors=False):
+        """The nev eigenvalues of smallest magnitude of D_ov(mu) = 1 + gamma5 sgn(A),
+        each D_ov application a sign solve (two-sided Lanczos, k_inner, tol_inner).
+        Returns (lambda complex128 [nev] numpy, Ritz vectors [nev, V, 4, 3] or None,
+        info dict, status)."""
+        torch = _torch()
+        ncv = max(2 * nev + 8, 20) if ncv is None else int(ncv)
+        lam = np.zeros(2 * nev, dtype=np.float64)
+        info = np.zeros(4, dtype=np.float64)
+        vecs = None
+        if vectors:
+            vecs = torch.empty((nev,) + tuple(reversed(self.dims)) + (4, 3), dtype=torch.complex128,
+                               device="cuda")
+        dh = defl._h if defl is not None else None
+        nd = (defl.m if n_defl is None else int(n_defl)) if defl is not None else 0
+        st = self._lib.ovs_overlap_eigs(self._h, dh, nd, int(nev), ncv, int(k_inner),
+                                        float(tol_inner), float(tol), int(max_restarts),
+                                        _dptr(lam),
+                                        ctypes.c_void_p(vecs.data_ptr()) if vecs is not None else None,
+                                        _dptr(info))
+        _check(st, "ovs_overlap_eigs")
+        lam_c = lam[0::2] + 1j * lam[1::2]
+        return lam_c, vecs, {"max_residual": info[0], "restarts": int(info[1]),
+                             "sign_solves": int(info[2]), "inner_warnings": int(info[3])}, st
 
     def sign_apply_vjp(self, b, chi, k, want_y=True, store_basis=False):
         """Gradient of L = sum_r Re <chi_r, y_r> for the k-step two-sided Lanczos

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libovsign.so")
 SOURCES = ["stencil.hip", "krylov.hip", "persistent.hip", "eig.hip", "grad.hip", "dense.cpp",
+           "overlap_eig.cpp",
            "eigsolve.cpp", "gradient.cpp", "api.cpp"]
 
 HIPCC_FLAGS = [

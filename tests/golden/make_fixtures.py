@@ -3,7 +3,7 @@
 Calls only the CPU oracle (oracle/) and the seeded input generators (synth/);
 nothing here touches the HIP library.  Re-run with
     python tests/golden/make_fixtures.py [lattice_4444] [gradient_8888] [sign_16x16x16x32]
-                                         [sign_16x16x16x16]
+                                         [sign_16x16x16x16] [overlap_4444]
 (all when no name is given) after any change to the oracle's arithmetic.
 
 lattice_4444.npz -- the 4^4 workload: links P_SU3(1 + 0.4 G) (seed 0),
@@ -35,6 +35,11 @@ sign_16x16x16x32.npz -- the benchmark workload: 16^3 x 32, links
     values come from the k = 700 run's first 650 coefficients (the same
     numbers a k = 650 run produces).
 
+overlap_4444.npz -- the spectrum of the overlap operator D_ov(mu) = 1 +
+    gamma5 sgn(A) (Section 1) on the 4^4 lattice of lattice_4444.npz (links
+    P_SU3(1 + 0.4 G), seed 0; m_w = -1.5) at mu = 0 and mu = 0.3: all 3072
+    eigenvalues of the dense operator (oracle.overlap), ordered by magnitude.
+
 sign_16x16x16x16.npz -- the 16^4 configuration: links P_SU3(1 + 0.6 G)
     (seed 0), m_w = -1.5, mu = 0.2, point sources 0 and 1 (spin-colour 0 and
     1 at the origin).  As above at k = 550 and k = 600; the sampled entries are
@@ -50,7 +55,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import synth  # noqa: E402
-from oracle import dirac, grad, krylov, sign  # noqa: E402
+from oracle import dirac, grad, krylov, overlap, sign  # noqa: E402
 
 
 def lattice_4444():
@@ -217,9 +222,19 @@ def sign_16x16x16x16():
     np.savez_compressed(os.path.join(HERE, "sign_16x16x16x16.npz"), **out)
 
 
+def overlap_4444():
+    dims = (4, 4, 4, 4)
+    m_w, eps = -1.5, 0.4
+    U = synth.random_links(dims, eps, seed=synth.LINK_SEED)
+    out = {"dims": np.array(dims), "m_w": m_w, "eps": eps}
+    for key, mu in (("lam_mu0", 0.0), ("lam_mu03", 0.3)):
+        out[key] = overlap.overlap_eigenvalues(dims, U, m_w, mu)
+    np.savez_compressed(os.path.join(HERE, "overlap_4444.npz"), **out)
+
+
 if __name__ == "__main__":
     names = sys.argv[1:] or ["lattice_4444", "gradient_8888", "sign_16x16x16x32",
-                             "sign_16x16x16x16"]
+                             "sign_16x16x16x16", "overlap_4444"]
     for name in names:
         if name == "gradient_8888_k150":
             gradient_8888_at(150, 1e-5, True)

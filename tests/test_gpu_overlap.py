@@ -1,0 +1,74 @@
+"""Eigenvalues of the overlap operator D_ov(mu) = 1 + gamma5 sgn(A) (Section 1;
+the closing outlook of Section 5) from ovs_overlap_eigs against the oracle's
+dense spectrum (tests/golden/overlap_4444.npz), the Ginsparg-Wilson circle at
+mu = 0, and the residual of the returned Ritz vectors."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+from gpu_util import say, to_dev
+
+pytestmark = pytest.mark.gpu
+MW = -1.5
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def lattice(dims, prec, U, mu):
+    import paper_0810_4228_amd as ovs
+    lat = ovs.Lattice(dims, precision=prec)
+    lat.set_links(to_dev(U))
+    lat.set_params(MW, mu)
+    return lat
+
+
+@pytest.mark.parametrize("prec,mu,tol_inner,tol,tol_lam", [
+    ("f64", 0.0, 1e-12, 1e-9, 1e-8),
+    ("f64", 0.3, 1e-12, 1e-9, 1e-7),
+    ("f32", 0.3, 1e-7, 1e-5, 1e-4),
+])
+def test_overlap_eigs_4444(prec, mu, tol_inner, tol, tol_lam):
+    import torch
+    d = np.load(os.path.join(GOLDEN, "overlap_4444.npz"))
+    ref = d["lam_mu0" if mu == 0.0 else "lam_mu03"]
+    dims = tuple(int(x) for x in d["dims"])
+    U = synth.random_links(dims, float(d["eps"]), seed=synth.LINK_SEED)
+    lat = lattice(dims, prec, U, mu)
+    nev = 4
+    lam, vecs, info, st = lat.overlap_eigs(nev, ncv=40, k_inner=1500, tol_inner=tol_inner,
+                                           tol=tol, max_restarts=300, vectors=True)
+    say("overlap eigs", prec, mu, lam, info)
+    assert st == 0, info
+    assert info["max_residual"] <= tol
+    # each is an eigenvalue of the dense operator, and they are the nev of
+    # smallest magnitude (the oracle's spectrum has no tie at the cut)
+    for z in lam:
+        assert np.min(np.abs(ref - z)) <= tol_lam, z
+    assert abs(abs(ref[nev]) - abs(ref[nev - 1])) > 10 * tol_lam
+    assert np.abs(np.sort(np.abs(lam)) - np.abs(ref[:nev])).max() <= tol_lam
+    if mu == 0.0:
+        assert np.abs(np.abs(lam - 1.0) - 1.0).max() <= tol_lam
+    # D_ov x = lambda x for the returned unit Ritz vectors
+    x = vecs.reshape(nev, -1)
+    assert torch.allclose(torch.linalg.vector_norm(x, dim=1).cpu(),
+                          torch.ones(nev, dtype=torch.float64), atol=1e-10)
+    y, _, _ = lat.sign_apply(x, 1500, tol=tol_inner, overlap=True)
+    lt = torch.from_numpy(lam).to(x.device)
+    r = torch.linalg.vector_norm(y - lt[:, None] * x, dim=1).cpu().numpy()
+    say("overlap residuals", r)
+    assert r.max() <= 10 * tol + 10 * tol_inner
+    lat.close()
+
+
+def test_overlap_eigs_argument_errors():
+    import paper_0810_4228_amd as ovs
+    dims = (4, 4, 4, 4)
+    lat = lattice(dims, "f64", synth.unit_links(dims), 0.0)
+    for kw in ({"nev": 0}, {"nev": 4, "ncv": 5}, {"nev": 4, "ncv": 300},
+               {"nev": 4, "tol": 0.0}, {"nev": 4, "tol_inner": -1.0}, {"nev": 4, "k_inner": 0}):
+        nev = kw.pop("nev")
+        with pytest.raises(ovs.OvsError):
+            lat.overlap_eigs(nev, **kw)
+    lat.close()
