@@ -291,6 +291,8 @@ ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, 
  * nev + (ncv - nev)/2 smallest |theta| are kept.
  *   nev, ncv    : 1 <= nev, nev + 2 <= ncv <= 256, ncv < N.
  *   k_inner, tol_inner : k_max and target relative error of each sign solve.
+ *   inner_flags : further flags of each sign solve: OVS_FLAG_GRAPH,
+ *                 OVS_FLAG_TWO_PASS, OVS_FLAG_PERSISTENT (others: OVS_ERR_ARG).
  *   tol         : stop when every wanted Ritz pair (unit x) has the residual
  *                 estimate |D_ov x - theta x| <= tol; the inner solves' error
  *                 limits what tol can reach.
@@ -307,8 +309,9 @@ ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, 
  * invariant subspace or dependent Ritz vectors).  Errors: OVS_ERR_ARG,
  * OVS_ERR_STATE (links or parameters not set), OVS_ERR_ALLOC, OVS_ERR_HIP. */
 ovs_status ovs_overlap_eigs(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, int32_t nev,
-                           int32_t ncv, int32_t k_inner, double tol_inner, double tol,
-                           int32_t max_restarts, double* lambda, void* vecs, double* info);
+                           int32_t ncv, int32_t k_inner, double tol_inner, int32_t inner_flags,
+                           double tol, int32_t max_restarts, double* lambda, void* vecs,
+                           double* info);
 
 /* Eigen-decomposition of a small general complex matrix on the host (the
  * Rayleigh-Ritz step of ovs_deflation_compute): A host complex128 n x n,

@@ -95,10 +95,12 @@ bool mgs2(int m, int k, std::vector<cd>& Y) {
 
 extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
                                        int32_t nev, int32_t ncv, int32_t k_inner,
-                                       double tol_inner, double tol, int32_t max_restarts,
-                                       double* lambda, void* vecs, double* info) {
+                                       double tol_inner, int32_t inner_flags, double tol,
+                                       int32_t max_restarts, double* lambda, void* vecs,
+                                       double* info) {
   if (!l || !lambda || nev < 1 || ncv < nev + 2 || ncv > 256 || k_inner < 1 ||
-      !(tol_inner > 0) || !(tol > 0) || max_restarts < 0)
+      !(tol_inner > 0) || !(tol > 0) || max_restarts < 0 ||
+      (inner_flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_PERSISTENT)))
     return OVS_ERR_ARG;
   if (!ready(l)) return OVS_ERR_STATE;
   const long N = 12L * l->g.V;
@@ -149,7 +151,7 @@ extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_
       const double ti = tol_inner;
       ovs_rhs_info ri;
       st = ovs_sign_apply(l, defl, n_defl, col(j), col(j + 1), 1, k_inner, &ti, OVS_2SL,
-                          OVS_FLAG_OVERLAP, &ri);
+                          OVS_FLAG_OVERLAP | inner_flags, &ri);
       ++matvecs;
       if (st < 0) return st;
       if (st > 0) ++inner_warn;

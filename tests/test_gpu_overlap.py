@@ -24,12 +24,12 @@ def lattice(dims, prec, U, mu):
     return lat
 
 
-@pytest.mark.parametrize("prec,mu,tol_inner,tol,tol_lam", [
-    ("f64", 0.0, 1e-12, 1e-9, 1e-8),
-    ("f64", 0.3, 1e-12, 1e-9, 1e-7),
-    ("f32", 0.3, 1e-7, 1e-5, 1e-4),
+@pytest.mark.parametrize("prec,mu,tol_inner,tol,tol_lam,graph", [
+    ("f64", 0.0, 1e-12, 1e-9, 1e-8, False),
+    ("f64", 0.3, 1e-12, 1e-9, 1e-7, True),
+    ("f32", 0.3, 1e-7, 1e-5, 1e-4, False),
 ])
-def test_overlap_eigs_4444(prec, mu, tol_inner, tol, tol_lam):
+def test_overlap_eigs_4444(prec, mu, tol_inner, tol, tol_lam, graph):
     import torch
     d = np.load(os.path.join(GOLDEN, "overlap_4444.npz"))
     ref = d["lam_mu0" if mu == 0.0 else "lam_mu03"]
@@ -38,7 +38,7 @@ def test_overlap_eigs_4444(prec, mu, tol_inner, tol, tol_lam):
     lat = lattice(dims, prec, U, mu)
     nev = 4
     lam, vecs, info, st = lat.overlap_eigs(nev, ncv=40, k_inner=1500, tol_inner=tol_inner,
-                                           tol=tol, max_restarts=300, vectors=True)
+                                           tol=tol, max_restarts=300, vectors=True, graph=graph)
     say("overlap eigs", prec, mu, lam, info)
     assert st == 0, info
     assert info["max_residual"] <= tol
