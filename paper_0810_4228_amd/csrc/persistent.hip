@@ -147,8 +147,13 @@ static hipError_t launch_p(const PersistArgs& a, const Geometry& g, const Hop& h
   // largest phase has virtual workgroups
   int most = nv_dual > nwg_u * a.nslots ? nv_dual : nwg_u * a.nslots;
   most = (most + 7) / 8 * 8;
-  // one workgroup per CU: fewest arrivals per barrier
-  int grid = ncu;
+  // One workgroup per CU (fewest arrivals per barrier), or two when the dual
+  // phase has 16 or more virtual workgroups per CU: the memory-bound phases
+  // then hide more latency than the extra arrivals cost (measured: 16^3 x 32,
+  // 12 sources 34 -> 43 solves/s; 8^4 loses with two, 235 -> 213; three and
+  // four per CU lose on both).
+  const int per = (nv_dual >= 16 * ncu && per_cu >= 2) ? 2 : 1;
+  int grid = ncu * per;
   grid -= grid % 8;
   if (grid > most) grid = most;
   if (grid < 8) return hipErrorNotSupported;

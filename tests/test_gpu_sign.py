@@ -461,12 +461,14 @@ def test_persistent_equals_per_step_bitwise(prec, blk, variant):
     assert rel_rows(y.cpu().numpy(), ref) <= (3e-5 if prec == "f32" else 1e-10)
 
 
-def test_persistent_12_sources_equals_graph():
-    """12 FP32 sources on 8^4 (the staged operator-per-workgroup stencil with
-    two sources per thread): persistent launches against captured graphs of the
-    per-step kernels (one batch, so the same kernels run in the same order)."""
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 16, 16)])
+def test_persistent_12_sources_equals_graph(dims):
+    """12 FP32 sources (the staged operator-per-workgroup stencil with two
+    sources per thread): persistent launches against captured graphs of the
+    per-step kernels (one batch, so the same kernels run in the same order).
+    8^4 runs one workgroup per CU, 16^4 (16 or more virtual dual-stencil
+    workgroups per CU) two."""
     import torch
-    dims = (8, 8, 8, 8)
     U = synth.random_links(dims, 0.6, seed=93)
     b = to_dev(synth.gaussian_sources(dims, 12, seed=94))
     lat = lattice(dims, "f32", U, 0.4)
@@ -475,7 +477,7 @@ def test_persistent_12_sources_equals_graph():
     lat.set_tuning_raw(12, cfg)
     y1, i1, _ = lat.sign_apply(b, 1000, tol=[1e-5] * 12, graph=True, split=False)
     y2, i2, _ = lat.sign_apply(b, 1000, tol=[1e-5] * 12, persistent=True)
-    say("persistent 8^4 x 12", [i["k_used"] for i in i2])
+    say("persistent x 12", dims, [i["k_used"] for i in i2])
     assert [i["k_used"] for i in i1] == [i["k_used"] for i in i2]
     assert torch.equal(y1, y2)
 
