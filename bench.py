@@ -195,7 +195,7 @@ def copy_bandwidth(torch, dev, nbytes=1 << 30, iters=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def overlap_eigs_timing(ovs, torch, dev, dims=(8, 8, 8, 8), nev=4, ncv=40):
+def overlap_eigs_timing(ovs, torch, dev, dims=(8, 8, 8, 8), nev=4, ncv=80, block=4):
     """ovs_overlap_eigs: the nev eigenvalues of smallest magnitude of D_ov(mu)
     (eps 0.6, mu 0.3, FP64, sign solves to 1e-10, Ritz residuals to 1e-8),
     wall time of one call (its first sign solve allocates the workspace)."""
@@ -203,7 +203,7 @@ def overlap_eigs_timing(ovs, torch, dev, dims=(8, 8, 8, 8), nev=4, ncv=40):
     lat = ovs.Lattice(dims, precision="f64")
     lat.set_links(torch.from_numpy(synth.random_links(dims, 0.6, seed=synth.LINK_SEED)).to(dev))
     lat.set_params(MW, 0.3)
-    kw = dict(ncv=ncv, k_inner=1000, tol_inner=1e-10, tol=1e-8, max_restarts=200)
+    kw = dict(ncv=ncv, block=block, k_inner=1000, tol_inner=1e-10, tol=1e-8, max_restarts=200)
     try:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -214,7 +214,7 @@ def overlap_eigs_timing(ovs, torch, dev, dims=(8, 8, 8, 8), nev=4, ncv=40):
         lat.close()
         return {"error": str(e)}
     lat.close()
-    return {"workload": "x".join(map(str, dims)) + f", eps 0.6, mu 0.3, FP64, nev {nev}, ncv {ncv}",
+    return {"workload": "x".join(map(str, dims)) + f", eps 0.6, mu 0.3, FP64, nev {nev}, ncv {ncv}, block {block}",
             "ms": ms, "status": st, "lambda": [[z.real, z.imag] for z in lam], **info,
             "ms_per_sign_solve": ms / max(info["sign_solves"], 1)}
 

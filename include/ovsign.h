@@ -284,12 +284,22 @@ ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, 
 /* The nev eigenvalues of smallest magnitude of D_ov(mu) = 1 + gamma5 sgn(A)
  * (Section 1), with sgn(A) applied by the two-sided Lanczos driver (Section
  * 4; the closing outlook of Section 5 applies these methods to the overlap
- * operator's eigenvalues).  Arnoldi with thick restarts in Krylov-Schur form:
- * a basis of ncv vectors, one sign solve (ovs_sign_apply, OVS_FLAG_OVERLAP,
- * one source, deflated by the first n_defl triples of defl if not NULL) per
- * step, classical Gram-Schmidt twice; at a restart the Ritz vectors of the
- * nev + (ncv - nev)/2 smallest |theta| are kept.
- *   nev, ncv    : 1 <= nev, nev + 2 <= ncv <= 256, ncv < N.
+ * operator's eigenvalues).  Block Arnoldi with thick restarts in Krylov-Schur
+ * form: a basis of ncv vectors grown by one block of `block` vectors per step,
+ * each step one batched sign solve of `block` sources (ovs_sign_apply,
+ * OVS_FLAG_OVERLAP, deflated by the first n_defl triples of defl if not NULL),
+ * classical Gram-Schmidt twice against the basis and Cholesky QR twice within
+ * the block.  Harmonic Ritz pairs for the target 0 (ordinary Ritz pairs in a
+ * cycle where the projected matrix is singular) are ordered by |theta|; each
+ * is reported with the Rayleigh quotient of its vector.  At a restart the
+ * vectors of about nev + (ncv - nev)/2 smallest |theta| are kept (rounded so
+ * that whole blocks are added), with the block their residuals lie in.
+ *   nev, ncv    : 1 <= nev, nev + 2 block <= ncv <= 256, ncv + block < N.
+ *   block       : 1..16, ncv a multiple of it (1: plain Arnoldi).  The
+ *                 wanted eigenvalues lie inside the spectrum; a cycle of
+ *                 ncv/block steps builds a polynomial of that degree, and
+ *                 fewer than ~20 steps can converge to other eigenvalues than
+ *                 the smallest ones (measured at 8^4: block 4 with ncv 40 did).
  *   k_inner, tol_inner : k_max and target relative error of each sign solve.
  *   inner_flags : further flags of each sign solve: OVS_FLAG_GRAPH,
  *                 OVS_FLAG_TWO_PASS, OVS_FLAG_PERSISTENT (others: OVS_ERR_ARG).
@@ -300,18 +310,18 @@ ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, 
  *   lambda      : host complex128 [nev], ordered by increasing magnitude.
  *   vecs        : device complex128 [nev][V][4][3] unit Ritz vectors, or NULL.
  *   info        : host double [4] or NULL: largest residual estimate of the
- *                 wanted pairs, restarts, sign solves, sign solves that
- *                 returned a warning.
- * The library allocates (ncv + 1) + ncv FP64 fields of device memory for the
- * call and frees them on return.  OVS_WARN_NOT_CONVERGED if tol was not met
+ *                 wanted pairs, restarts, sources solved, sources whose sign
+ *                 solve returned a warning.
+ * The library allocates (ncv + block) + ncv FP64 fields of device memory for
+ * the call and frees them on return.  OVS_WARN_NOT_CONVERGED if tol was not met
  * within max_restarts or an inner solve returned a warning (outputs still
  * written); OVS_WARN_BREAKDOWN if the basis could not be extended (an
  * invariant subspace or dependent Ritz vectors).  Errors: OVS_ERR_ARG,
  * OVS_ERR_STATE (links or parameters not set), OVS_ERR_ALLOC, OVS_ERR_HIP. */
 ovs_status ovs_overlap_eigs(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, int32_t nev,
-                           int32_t ncv, int32_t k_inner, double tol_inner, int32_t inner_flags,
-                           double tol, int32_t max_restarts, double* lambda, void* vecs,
-                           double* info);
+                           int32_t ncv, int32_t block, int32_t k_inner, double tol_inner,
+                           int32_t inner_flags, double tol, int32_t max_restarts,
+                           double* lambda, void* vecs, double* info);
 
 /* Eigen-decomposition of a small general complex matrix on the host (the
  * Rayleigh-Ritz step of ovs_deflation_compute): A host complex128 n x n,

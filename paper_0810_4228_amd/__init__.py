@@ -120,7 +120,7 @@ def load():
         "ovs_deflation_get": [P, DP, P, P, DP],
         "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
         "ovs_sign_apply_vjp": [P, P, P, I, I, I, P, P, DP, P, DP],
-        "ovs_overlap_eigs": [P, P, I, I, I, I, D, I, D, I, DP, P, DP],
+        "ovs_overlap_eigs": [P, P, I, I, I, I, I, D, I, D, I, DP, P, DP],
         "ovs_last_coefficients": [P, DP, DP, DP, DP],
         "ovs_inner_sign_tridiag": [P, I, I, DP, DP, DP, DP, DP],
         "ovs_inner_sign_hessenberg": [P, I, I, DP, DP, DP],
@@ -311,15 +311,19 @@ class Lattice:
         _check(st, "ovs_sign_apply")
         return y, [i.as_dict() for i in infos], st
 
-    def overlap_eigs(self, nev, ncv=None, k_inner=400, tol_inner=1e-10, tol=1e-8,
+    def overlap_eigs(self, nev, ncv=None, block=1, k_inner=400, tol_inner=1e-10, tol=1e-8,
                      max_restarts=100, defl=None, n_defl=None, vectors=False, graph=False):
-        """The nev eigenvalues of smallest magnitude of D_ov(mu) = 1 + gamma5 sgn(A),
-        each D_ov application a sign solve (two-sided Lanczos, k_inner, tol_inner;
-        graph=True runs its iterations as graph replays).
-        Returns (lambda complex128 [nev] numpy, Ritz vectors [nev, V, 4, 3] or None,
-        info dict, status)."""
+        """The nev eigenvalues of smallest magnitude of D_ov(mu) = 1 + gamma5 sgn(A)
+        by block Arnoldi (block vectors per step, one batched sign solve each:
+        two-sided Lanczos, k_inner, tol_inner; graph=True runs its iterations as
+        graph replays).  Returns (lambda complex128 [nev] numpy, Ritz vectors
+        [nev, V, 4, 3] or None, info dict, status)."""
         torch = _torch()
-        ncv = max(2 * nev + 8, 20) if ncv is None else int(ncv)
+        block = int(block)
+        if ncv is None:  # about 20 blocks per restart cycle, whole blocks
+            ncv = max(2 * nev + 8, 20 * block, nev + 2 * block)
+            ncv = min(-(-ncv // block) * block, 256 // block * block)
+        ncv = int(ncv)
         lam = np.zeros(2 * nev, dtype=np.float64)
         info = np.zeros(4, dtype=np.float64)
         vecs = None
@@ -328,7 +332,7 @@ class Lattice:
                                device="cuda")
         dh = defl._h if defl is not None else None
         nd = (defl.m if n_defl is None else int(n_defl)) if defl is not None else 0
-        st = self._lib.ovs_overlap_eigs(self._h, dh, nd, int(nev), ncv, int(k_inner),
+        st = self._lib.ovs_overlap_eigs(self._h, dh, nd, int(nev), ncv, block, int(k_inner),
                                         float(tol_inner), OVS_FLAG_GRAPH if graph else 0,
                                         float(tol), int(max_restarts),
                                         _dptr(lam),

@@ -2,18 +2,20 @@
 // with the sign function applied by the two-sided Lanczos driver: the use the
 // closing outlook of Section 5 names for these methods.
 //
-// Outer method: Arnoldi with thick restarts in Krylov-Schur form.  The
-// factorisation D V_m = V_m H_m + h v_{m+1} e_m^T is built with one sign
-// solve per step (ovs_sign_apply with OVS_FLAG_OVERLAP, one source, writing
-// straight into the next basis column) and classical Gram-Schmidt applied
-// twice (rocBLAS zgemv on the lattice stream).  At a restart the Ritz pairs of
-// H_m are ordered by |theta|; the Ritz vectors of the `keep` smallest span an
-// H_m-invariant subspace, so with Q an orthonormal basis of it (host, modified
-// Gram-Schmidt twice) D (V_m Q) = (V_m Q)(Q^H H_m Q) + h v_{m+1} (e_m^T Q), and
-// the factorisation continues from keep + 1 vectors.  A Ritz pair's residual
-// is |h| |e_m^T y| (unit y); the iteration stops when the nev wanted ones are
-// all below tol.  The inner solves' own error (tol_inner) bounds what tol can
-// reach.
+// Outer method: block Arnoldi with thick restarts in Krylov-Schur form, block
+// size b (b = 1: plain Arnoldi).  The factorisation D V_m = V_m H_m + V' R E^T
+// (V' the next block, E the last b columns) grows by one block per step: one
+// batched sign solve of b sources (ovs_sign_apply with OVS_FLAG_OVERLAP,
+// writing straight into the next block of the basis), classical Gram-Schmidt
+// against the basis applied twice, then Cholesky QR applied twice to the new
+// block (rocBLAS zgemm on the lattice stream, the b x b factors on the host).
+// At a restart the Ritz pairs of H_m are ordered by |theta|; the Ritz vectors
+// of the `keep` smallest span an H_m-invariant subspace, so with Q an
+// orthonormal basis of it (host, modified Gram-Schmidt twice)
+// D (V_m Q) = (V_m Q)(Q^H H_m Q) + V' (R E^T Q), and the factorisation
+// continues from keep + b vectors.  A Ritz pair's residual is |R E^T y| (unit
+// y); the iteration stops when the nev wanted ones are all below tol.  The
+// inner solves' own error (tol_inner) bounds what tol can reach.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -94,17 +96,18 @@ bool mgs2(int m, int k, std::vector<cd>& Y) {
 }  // namespace
 
 extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
-                                       int32_t nev, int32_t ncv, int32_t k_inner,
+                                       int32_t nev, int32_t ncv, int32_t block, int32_t k_inner,
                                        double tol_inner, int32_t inner_flags, double tol,
                                        int32_t max_restarts, double* lambda, void* vecs,
                                        double* info) {
-  if (!l || !lambda || nev < 1 || ncv < nev + 2 || ncv > 256 || k_inner < 1 ||
-      !(tol_inner > 0) || !(tol > 0) || max_restarts < 0 ||
+  const int bs = block;
+  if (!l || !lambda || nev < 1 || bs < 1 || bs > 16 || ncv % bs != 0 || ncv < nev + 2 * bs ||
+      ncv > 256 || k_inner < 1 || !(tol_inner > 0) || !(tol > 0) || max_restarts < 0 ||
       (inner_flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_PERSISTENT)))
     return OVS_ERR_ARG;
   if (!ready(l)) return OVS_ERR_STATE;
   const long N = 12L * l->g.V;
-  if (ncv >= N || k_inner > N) return OVS_ERR_ARG;
+  if (ncv + bs >= N || k_inner > N) return OVS_ERR_ARG;
   const int m = ncv;
   StreamScope sc(l);
   hipStream_t s = l->stream;
@@ -114,131 +117,218 @@ extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_
       rocblas_set_pointer_mode(bl.h, rocblas_pointer_mode_host) != rocblas_status_success)
     return OVS_ERR_HIP;
   Buffers mem;
-  auto* V = mem.alloc<rocblas_double_complex>((size_t)(m + 1) * N);
-  auto* W = mem.alloc<rocblas_double_complex>((size_t)m * N);  // V_m Q at a restart
-  auto* hd = mem.alloc<rocblas_double_complex>(m + 1);
-  auto* Qd = mem.alloc<rocblas_double_complex>((size_t)m * m);
-  if (!V || !W || !hd || !Qd) return OVS_ERR_ALLOC;
+  auto* V = mem.alloc<rocblas_double_complex>((size_t)(m + bs) * N);
+  auto* Wt = mem.alloc<rocblas_double_complex>((size_t)m * N);  // zgemm outputs
+  auto* Hd = mem.alloc<rocblas_double_complex>((size_t)(m + bs) * bs);
+  auto* Rd = mem.alloc<rocblas_double_complex>((size_t)bs * bs);
+  auto* Qd = mem.alloc<rocblas_double_complex>((size_t)(m + bs) * (m + bs));
+  if (!V || !Wt || !Hd || !Rd || !Qd) return OVS_ERR_ALLOC;
   const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0}, mone{-1.0, 0.0};
+  const auto opN = rocblas_operation_none, opC = rocblas_operation_conjugate_transpose;
+  const rocblas_int n32 = (rocblas_int)N;
   auto col = [&](int j) { return V + (size_t)j * N; };
   auto blas_ok = [](rocblas_status st) { return st == rocblas_status_success; };
 
-  {  // start vector
-    std::vector<cd> v0(N);
-    for (long i = 0; i < N; ++i) {
-      const uint64_t a = mix(2 * (uint64_t)i), b = mix(2 * (uint64_t)i + 1);
-      v0[i] = cd((double)(a >> 11) * 0x1.0p-52 - 1.0, (double)(b >> 11) * 0x1.0p-52 - 1.0);
+  // Orthonormalises the block at columns c .. c + bs - 1 against columns
+  // 0 .. c - 1 (classical Gram-Schmidt, twice) and within itself (Cholesky QR,
+  // twice).  Returns the coefficients: hc (c x bs) and the upper triangular
+  // r (bs x bs) with block_in = V[:, 0:c] hc + block_out r.
+  std::vector<cd> hc, hp, g(bs * bs), r(bs * bs), rp(bs * bs);
+  auto orth_block = [&](int c) -> ovs_status {
+    rocblas_double_complex* W = col(c);
+    hc.assign((size_t)c * bs, cd(0));
+    hp.resize((size_t)c * bs);
+    for (int pass = 0; pass < 2 && c > 0; ++pass) {
+      if (!blas_ok(rocblas_zgemm(bl.h, opC, opN, c, bs, n32, &one, V, n32, W, n32, &zero, Hd, c)) ||
+          !blas_ok(rocblas_zgemm(bl.h, opN, opN, n32, bs, c, &mone, V, n32, Hd, c, &one, W, n32)))
+        return OVS_ERR_HIP;
+      OVS_HIP(hipMemcpyAsync(hp.data(), Hd, hp.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
+      OVS_HIP(hipStreamSynchronize(s));
+      for (size_t i = 0; i < hc.size(); ++i) hc[i] += hp[i];
     }
-    OVS_HIP(hipMemcpyAsync(col(0), v0.data(), N * sizeof(cd), hipMemcpyHostToDevice, s));
-    double nrm = 0;
-    if (!blas_ok(rocblas_dznrm2(bl.h, (rocblas_int)N, col(0), 1, &nrm))) return OVS_ERR_HIP;
-    const double inv = 1.0 / nrm;
-    if (!blas_ok(rocblas_zdscal(bl.h, (rocblas_int)N, &inv, col(0), 1))) return OVS_ERR_HIP;
-    OVS_HIP(hipStreamSynchronize(s));  // v0 leaves host memory
+    std::fill(r.begin(), r.end(), cd(0));
+    for (int i = 0; i < bs; ++i) r[(size_t)i * bs + i] = 1.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (!blas_ok(rocblas_zgemm(bl.h, opC, opN, bs, bs, n32, &one, W, n32, W, n32, &zero, Rd, bs)))
+        return OVS_ERR_HIP;
+      OVS_HIP(hipMemcpyAsync(g.data(), Rd, g.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
+      OVS_HIP(hipStreamSynchronize(s));
+      if (dense::cholesky(bs, g.data()) != 0) return OVS_WARN_BREAKDOWN;
+      // r <- g r (both upper triangular)
+      for (int j = 0; j < bs; ++j)
+        for (int i = 0; i <= j; ++i) {
+          cd a = 0;
+          for (int q = i; q <= j; ++q) a += g[(size_t)q * bs + i] * r[(size_t)j * bs + q];
+          rp[(size_t)j * bs + i] = a;
+        }
+      for (int j = 0; j < bs; ++j)
+        for (int i = 0; i < bs; ++i) r[(size_t)j * bs + i] = i <= j ? rp[(size_t)j * bs + i] : 0.0;
+      if (dense::inverse(bs, g.data()) != 0) return OVS_WARN_BREAKDOWN;
+      OVS_HIP(hipMemcpyAsync(Rd, g.data(), g.size() * sizeof(cd), hipMemcpyHostToDevice, s));
+      if (!blas_ok(rocblas_zgemm(bl.h, opN, opN, n32, bs, bs, &one, W, n32, Rd, bs, &zero, Wt, n32)))
+        return OVS_ERR_HIP;
+      OVS_HIP(hipMemcpyAsync(W, Wt, (size_t)bs * N * sizeof(cd), hipMemcpyDeviceToDevice, s));
+      OVS_HIP(hipStreamSynchronize(s));  // g is reused
+    }
+    return OVS_OK;
+  };
+
+  {  // start block
+    std::vector<cd> v0(N);
+    for (int c = 0; c < bs; ++c) {
+      for (long i = 0; i < N; ++i) {
+        const uint64_t e = 2 * ((uint64_t)c * (uint64_t)N + (uint64_t)i);
+        const uint64_t a = mix(e), b = mix(e + 1);
+        v0[i] = cd((double)(a >> 11) * 0x1.0p-52 - 1.0, (double)(b >> 11) * 0x1.0p-52 - 1.0);
+      }
+      OVS_HIP(hipMemcpyAsync(col(c), v0.data(), N * sizeof(cd), hipMemcpyHostToDevice, s));
+      OVS_HIP(hipStreamSynchronize(s));  // v0 is refilled
+    }
+    const ovs_status so = orth_block(0);
+    if (so != OVS_OK) return so;
   }
 
-  std::vector<cd> H((size_t)(m + 1) * m, cd(0));  // column-major, leading dimension m + 1
-  auto Hat = [&](int r, int c) -> cd& { return H[(size_t)c * (m + 1) + r]; };
-  std::vector<cd> hh(m + 1), h2(m + 1), theta(m), Y((size_t)m * m), Hm((size_t)m * m);
+  const int ld = m + bs;
+  std::vector<cd> H((size_t)ld * m, cd(0));  // column-major, leading dimension m + bs
+  auto Hat = [&](int i, int j) -> cd& { return H[(size_t)j * ld + i]; };
+  std::vector<cd> theta(m), Y((size_t)m * m), Hm((size_t)m * m);
   std::vector<int> order(m);
-  std::vector<double> res(m);
+  std::vector<double> res(m), tols(bs, tol_inner);
+  std::vector<cd> rq(nev);
+  std::vector<ovs_rhs_info> ri(bs);
   int k = 0, restarts = 0, matvecs = 0, inner_warn = 0;
   bool converged = false;
-  ovs_status st = OVS_OK;
   for (;;) {
-    // extend the factorisation from k to m columns
-    for (int j = k; j < m; ++j) {
-      const double ti = tol_inner;
-      ovs_rhs_info ri;
-      st = ovs_sign_apply(l, defl, n_defl, col(j), col(j + 1), 1, k_inner, &ti, OVS_2SL,
-                          OVS_FLAG_OVERLAP | inner_flags, &ri);
-      ++matvecs;
+    // extend the factorisation from k to m columns, one block at a time
+    for (int p = k; p < m; p += bs) {
+      const ovs_status st = ovs_sign_apply(l, defl, n_defl, col(p), col(p + bs), bs, k_inner,
+                                           tols.data(), OVS_2SL, OVS_FLAG_OVERLAP | inner_flags,
+                                           ri.data());
+      matvecs += bs;
       if (st < 0) return st;
-      if (st > 0) ++inner_warn;
-      // classical Gram-Schmidt against v_0 .. v_j, twice
-      for (int pass = 0; pass < 2; ++pass) {
-        if (!blas_ok(rocblas_zgemv(bl.h, rocblas_operation_conjugate_transpose, (rocblas_int)N,
-                                   j + 1, &one, V, (rocblas_int)N, col(j + 1), 1, &zero, hd, 1)) ||
-            !blas_ok(rocblas_zgemv(bl.h, rocblas_operation_none, (rocblas_int)N, j + 1, &mone, V,
-                                   (rocblas_int)N, hd, 1, &one, col(j + 1), 1)))
-          return OVS_ERR_HIP;
-        OVS_HIP(hipMemcpyAsync(pass ? h2.data() : hh.data(), hd, (j + 1) * sizeof(cd),
-                               hipMemcpyDeviceToHost, s));
+      for (int i = 0; i < bs; ++i) inner_warn += ri[i].status != OVS_OK;
+      const ovs_status so = orth_block(p + bs);
+      if (so != OVS_OK) return so;
+      for (int j = 0; j < bs; ++j) {
+        for (int i = 0; i < p + bs; ++i) Hat(i, p + j) = hc[(size_t)j * (p + bs) + i];
+        for (int i = 0; i < bs; ++i) Hat(p + bs + i, p + j) = r[(size_t)j * bs + i];
       }
-      double beta = 0;
-      if (!blas_ok(rocblas_dznrm2(bl.h, (rocblas_int)N, col(j + 1), 1, &beta))) return OVS_ERR_HIP;
-      OVS_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i <= j; ++i) Hat(i, j) = hh[i] + h2[i];
-      Hat(j + 1, j) = beta;
-      if (!(beta > 0) || !std::isfinite(beta)) return OVS_WARN_BREAKDOWN;
-      const double inv = 1.0 / beta;
-      if (!blas_ok(rocblas_zdscal(bl.h, (rocblas_int)N, &inv, col(j + 1), 1))) return OVS_ERR_HIP;
     }
-    // Ritz pairs of H_m, ordered by |theta|
+    // Harmonic Ritz pairs for the target 0 (the wanted eigenvalues lie inside
+    // the spectrum, where Ritz values are unreliable): with H_m and the last
+    // block row R, M = H_m + H_m^{-H} E R^H R E^T; (theta, y) eigenpairs of M,
+    // ordered by |theta|.  Each y (unit) is reported with its Rayleigh
+    // quotient rho = y^H H_m y and the residual |H_bar y - rho [y; 0]| of
+    // D (V_m y) - rho V_m y.  If H_m is singular (a zero mode already in the
+    // basis) the cycle takes ordinary Ritz pairs (eigenpairs of H_m).
     for (int c = 0; c < m; ++c)
-      for (int r = 0; r < m; ++r) Hm[(size_t)c * m + r] = Hat(r, c);
-    if (dense::eig(m, Hm.data(), theta.data(), Y.data()) != 0) return OVS_WARN_BREAKDOWN;
+      for (int i = 0; i < m; ++i) Hm[(size_t)c * m + i] = Hat(i, c);
+    std::vector<cd> Hinv((size_t)m * m), M(Hm), RR((size_t)bs * bs);
+    for (int c = 0; c < m; ++c)
+      for (int i = 0; i < m; ++i) Hinv[(size_t)c * m + i] = std::conj(Hm[(size_t)i * m + c]);
+    const bool harmonic = dense::inverse(m, Hinv.data()) == 0;  // H_m^{-H}
+    if (harmonic) {
+      for (int j = 0; j < bs; ++j)  // R^H R
+        for (int i = 0; i < bs; ++i) {
+          cd a = 0;
+          for (int q = 0; q < bs; ++q) a += std::conj(Hat(m + q, m - bs + i)) * Hat(m + q, m - bs + j);
+          RR[(size_t)j * bs + i] = a;
+        }
+      for (int j = 0; j < bs; ++j)
+        for (int i = 0; i < m; ++i) {
+          cd a = 0;
+          for (int q = 0; q < bs; ++q) a += Hinv[(size_t)(m - bs + q) * m + i] * RR[(size_t)j * bs + q];
+          M[(size_t)(m - bs + j) * m + i] += a;
+        }
+    }
+    if (dense::eig(m, M.data(), theta.data(), Y.data()) != 0) return OVS_WARN_BREAKDOWN;
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return std::abs(theta[a]) < std::abs(theta[b]); });
-    const double hlast = std::abs(Hat(m, m - 1));
     double worst = 0;
-    for (int i = 0; i < m; ++i) res[i] = hlast * std::abs(Y[(size_t)order[i] * m + (m - 1)]);
-    for (int i = 0; i < nev; ++i) worst = std::max(worst, res[i]);
+    for (int q = 0; q < nev; ++q) {
+      const cd* y = &Y[(size_t)order[q] * m];
+      std::vector<cd> hy(m, cd(0));
+      for (int c = 0; c < m; ++c)
+        for (int i = 0; i < m; ++i) hy[i] += Hm[(size_t)c * m + i] * y[c];
+      cd rho = 0;
+      for (int i = 0; i < m; ++i) rho += std::conj(y[i]) * hy[i];
+      double n2 = 0;
+      for (int i = 0; i < m; ++i) n2 += std::norm(hy[i] - rho * y[i]);
+      for (int i = 0; i < bs; ++i) {
+        cd a = 0;
+        for (int j = 0; j < bs; ++j) a += Hat(m + i, m - bs + j) * y[m - bs + j];
+        n2 += std::norm(a);
+      }
+      rq[q] = rho;
+      res[q] = std::sqrt(n2);
+      worst = std::max(worst, res[q]);
+    }
     if (info) info[0] = worst;
     if (worst <= tol) {
       converged = true;
       break;
     }
     if (restarts == max_restarts) break;
-    // thick restart: keep the Ritz vectors of the `keep` smallest |theta|
-    int keep = std::min(nev + (m - nev) / 2, m - 1);
-    std::vector<cd> Q((size_t)m * keep);
+    // thick restart: keep the vectors of the `keep` smallest |theta| (rounded so
+    // that whole blocks are added; ncv >= nev + 2 bs keeps keep >= nev) and the
+    // block G = [-H_m^{-H} E R^H; I] that the residuals of harmonic pairs lie in
+    // (G = [0; I] for ordinary Ritz pairs).  With Qt an orthonormal basis of
+    // [[Q; 0], G] ((m + bs) x (keep + bs)), D (V_m Q) = (V_bar Qt)(Qt^H H_bar Q).
+    const int add = std::max(1, ((m - nev) - (m - nev) / 2) / bs) * bs;
+    const int keep = m - add;
+    const int kt = keep + bs;
+    std::vector<cd> Qt((size_t)ld * kt, cd(0));
     for (int i = 0; i < keep; ++i)
-      std::copy_n(&Y[(size_t)order[i] * m], m, &Q[(size_t)i * m]);
-    if (!mgs2(m, keep, Q)) return OVS_WARN_BREAKDOWN;
-    OVS_HIP(hipMemcpyAsync(Qd, Q.data(), Q.size() * sizeof(cd), hipMemcpyHostToDevice, s));
-    if (!blas_ok(rocblas_zgemm(bl.h, rocblas_operation_none, rocblas_operation_none,
-                               (rocblas_int)N, keep, m, &one, V, (rocblas_int)N, Qd, m, &zero, W,
-                               (rocblas_int)N)))
-      return OVS_ERR_HIP;
-    OVS_HIP(hipMemcpyAsync(col(0), W, (size_t)keep * N * sizeof(cd), hipMemcpyDeviceToDevice, s));
-    OVS_HIP(hipMemcpyAsync(col(keep), col(m), N * sizeof(cd), hipMemcpyDeviceToDevice, s));
-    // T = Q^H H_m Q and the new residual row h e_m^T Q
-    std::vector<cd> HQ((size_t)m * keep, cd(0)), T((size_t)keep * keep, cd(0));
-    for (int c = 0; c < keep; ++c)
-      for (int r = 0; r < m; ++r) {
-        cd a = 0;
-        for (int q = 0; q < m; ++q) a += Hm[(size_t)q * m + r] * Q[(size_t)c * m + q];
-        HQ[(size_t)c * m + r] = a;
-      }
-    for (int c = 0; c < keep; ++c)
-      for (int r = 0; r < keep; ++r) {
-        cd a = 0;
-        for (int q = 0; q < m; ++q) a += std::conj(Q[(size_t)r * m + q]) * HQ[(size_t)c * m + q];
-        T[(size_t)c * keep + r] = a;
-      }
-    const cd hm = Hat(m, m - 1);
-    std::fill(H.begin(), H.end(), cd(0));
-    for (int c = 0; c < keep; ++c) {
-      for (int r = 0; r < keep; ++r) Hat(r, c) = T[(size_t)c * keep + r];
-      Hat(keep, c) = hm * Q[(size_t)c * m + (m - 1)];
+      std::copy_n(&Y[(size_t)order[i] * m], m, &Qt[(size_t)i * ld]);
+    for (int j = 0; j < bs; ++j) {
+      cd* gj = &Qt[(size_t)(keep + j) * ld];
+      if (harmonic)
+        for (int i = 0; i < m; ++i) {
+          cd a = 0;
+          for (int q = 0; q < bs; ++q)
+            a -= Hinv[(size_t)(m - bs + q) * m + i] * std::conj(Hat(m + j, m - bs + q));
+          gj[i] = a;
+        }
+      gj[m + j] = 1.0;
     }
+    if (!mgs2(ld, kt, Qt)) return OVS_WARN_BREAKDOWN;
+    OVS_HIP(hipMemcpyAsync(Qd, Qt.data(), Qt.size() * sizeof(cd), hipMemcpyHostToDevice, s));
+    if (!blas_ok(rocblas_zgemm(bl.h, opN, opN, n32, kt, ld, &one, V, n32, Qd, ld, &zero, Wt, n32)))
+      return OVS_ERR_HIP;
+    OVS_HIP(hipMemcpyAsync(col(0), Wt, (size_t)kt * N * sizeof(cd), hipMemcpyDeviceToDevice, s));
+    // new projected matrix Qt^H H_bar Q, (keep + bs) x keep
+    std::vector<cd> HQ((size_t)ld * keep, cd(0));
+    for (int c = 0; c < keep; ++c)
+      for (int i = 0; i < ld; ++i) {
+        cd a = 0;
+        for (int q = 0; q < m; ++q) a += Hat(i, q) * Qt[(size_t)c * ld + q];
+        HQ[(size_t)c * ld + i] = a;
+      }
+    std::vector<cd> Hn((size_t)kt * keep, cd(0));
+    for (int c = 0; c < keep; ++c)
+      for (int i = 0; i < kt; ++i) {
+        cd a = 0;
+        for (int q = 0; q < ld; ++q) a += std::conj(Qt[(size_t)i * ld + q]) * HQ[(size_t)c * ld + q];
+        Hn[(size_t)c * kt + i] = a;
+      }
+    std::fill(H.begin(), H.end(), cd(0));
+    for (int c = 0; c < keep; ++c)
+      for (int i = 0; i < kt; ++i) Hat(i, c) = Hn[(size_t)c * kt + i];
     k = keep;
     ++restarts;
     OVS_HIP(hipStreamSynchronize(s));  // Q and the host matrices are reused
   }
   for (int i = 0; i < nev; ++i) {
-    lambda[2 * i] = theta[order[i]].real();
-    lambda[2 * i + 1] = theta[order[i]].imag();
+    lambda[2 * i] = rq[i].real();
+    lambda[2 * i + 1] = rq[i].imag();
   }
   if (vecs) {  // x_i = V_m y_i: unit norm (V_m orthonormal, y_i unit)
     std::vector<cd> Ys((size_t)m * nev);
     for (int i = 0; i < nev; ++i) std::copy_n(&Y[(size_t)order[i] * m], m, &Ys[(size_t)i * m]);
     OVS_HIP(hipMemcpyAsync(Qd, Ys.data(), Ys.size() * sizeof(cd), hipMemcpyHostToDevice, s));
-    if (!blas_ok(rocblas_zgemm(bl.h, rocblas_operation_none, rocblas_operation_none,
-                               (rocblas_int)N, nev, m, &one, V, (rocblas_int)N, Qd, m, &zero,
-                               (rocblas_double_complex*)vecs, (rocblas_int)N)))
+    if (!blas_ok(rocblas_zgemm(bl.h, opN, opN, n32, nev, m, &one, V, n32, Qd, m, &zero,
+                               (rocblas_double_complex*)vecs, n32)))
       return OVS_ERR_HIP;
     OVS_HIP(hipStreamSynchronize(s));
   }

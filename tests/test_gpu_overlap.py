@@ -24,12 +24,14 @@ def lattice(dims, prec, U, mu):
     return lat
 
 
-@pytest.mark.parametrize("prec,mu,tol_inner,tol,tol_lam,graph", [
-    ("f64", 0.0, 1e-12, 1e-9, 1e-8, False),
-    ("f64", 0.3, 1e-12, 1e-9, 1e-7, True),
-    ("f32", 0.3, 1e-7, 1e-5, 1e-4, False),
+@pytest.mark.parametrize("prec,mu,tol_inner,tol,tol_lam,graph,block", [
+    ("f64", 0.0, 1e-12, 1e-9, 1e-8, False, 1),
+    ("f64", 0.3, 1e-12, 1e-9, 1e-7, True, 1),
+    ("f32", 0.3, 1e-7, 1e-5, 1e-4, False, 1),
+    ("f64", 0.0, 1e-12, 1e-9, 1e-8, False, 4),
+    ("f64", 0.3, 1e-12, 1e-9, 1e-7, False, 8),
 ])
-def test_overlap_eigs_4444(prec, mu, tol_inner, tol, tol_lam, graph):
+def test_overlap_eigs_4444(prec, mu, tol_inner, tol, tol_lam, graph, block):
     import torch
     d = np.load(os.path.join(GOLDEN, "overlap_4444.npz"))
     ref = d["lam_mu0" if mu == 0.0 else "lam_mu03"]
@@ -38,8 +40,9 @@ def test_overlap_eigs_4444(prec, mu, tol_inner, tol, tol_lam, graph):
     lat = lattice(dims, prec, U, mu)
     nev = 4
     lam, vecs, info, st = lat.overlap_eigs(nev, ncv=40, k_inner=1500, tol_inner=tol_inner,
-                                           tol=tol, max_restarts=300, vectors=True, graph=graph)
-    say("overlap eigs", prec, mu, lam, info)
+                                           tol=tol, max_restarts=300, vectors=True, graph=graph,
+                                           block=block)
+    say("overlap eigs", prec, mu, block, lam, info)
     assert st == 0, info
     assert info["max_residual"] <= tol
     # each is an eigenvalue of the dense operator, and they are the nev of
@@ -67,7 +70,9 @@ def test_overlap_eigs_argument_errors():
     dims = (4, 4, 4, 4)
     lat = lattice(dims, "f64", synth.unit_links(dims), 0.0)
     for kw in ({"nev": 0}, {"nev": 4, "ncv": 5}, {"nev": 4, "ncv": 300},
-               {"nev": 4, "tol": 0.0}, {"nev": 4, "tol_inner": -1.0}, {"nev": 4, "k_inner": 0}):
+               {"nev": 4, "tol": 0.0}, {"nev": 4, "tol_inner": -1.0}, {"nev": 4, "k_inner": 0},
+               {"nev": 4, "ncv": 30, "block": 4}, {"nev": 4, "ncv": 8, "block": 4},
+               {"nev": 4, "ncv": 34, "block": 17}, {"nev": 4, "block": 0, "ncv": 20}):
         nev = kw.pop("nev")
         with pytest.raises(ovs.OvsError):
             lat.overlap_eigs(nev, **kw)
