@@ -26,8 +26,7 @@ int lin_nchunk(long stride) {
   return (int)c;
 }
 
-__global__ void __launch_bounds__(kWG) k_lin(LinArgs a, long stride, int nrhs) {
-  __shared__ double lds[(kWG / 64) * 2 * kLinDots];
+__device__ __forceinline__ void lin_body(const LinArgs& a, long stride, int nrhs, double* lds) {
   const int r = blockIdx.y;
   const long off = (long)r * stride;
   Cx<double> c[kLinTerms];
@@ -63,8 +62,30 @@ __global__ void __launch_bounds__(kWG) k_lin(LinArgs a, long stride, int nrhs) {
   }
 }
 
+__global__ void __launch_bounds__(kWG) k_lin(LinArgs a, long stride, int nrhs) {
+  __shared__ double lds[(kWG / 64) * 2 * kLinDots];
+  lin_body(a, stride, nrhs, lds);
+}
+
+// Several independent linear combinations in one launch: each is computed as
+// k_lin computes it (same grid, same per-element arithmetic, its own partial
+// sums), so the results equal those of separate launches bit for bit.  None
+// may read another's output.
+__global__ void __launch_bounds__(kWG) k_lin_multi(LinMulti m, long stride, int nrhs) {
+  __shared__ double lds[(kWG / 64) * 2 * kLinDots];
+  for (int j = 0; j < m.n; ++j) {
+    __syncthreads();  // lds of the previous combination
+    lin_body(m.a[j], stride, nrhs, lds);
+  }
+}
+
 void launch_lin(const LinArgs& a, long stride, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_lin, dim3(lin_nchunk(stride), nrhs), dim3(kWG), 0, s, a, stride, nrhs);
+}
+
+void launch_lin_multi(const LinMulti& m, long stride, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_lin_multi, dim3(lin_nchunk(stride), nrhs), dim3(kWG), 0, s, m, stride,
+                     nrhs);
 }
 
 // Workgroup of the per-source scalar kernels: one per source, the dot sums

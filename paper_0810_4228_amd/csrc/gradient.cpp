@@ -155,8 +155,8 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
   auto applyAd = [&](const double2* in, double2* out) {
     return launch_wilson(false, l->links, in, out, nrhs, g, hAd, false, true, tn, l->stream);
   };
-  auto lin = [&](std::initializer_list<const double2*> xs, int tab, double2* out, bool acc,
-                 std::initializer_list<const double2*> ys, int ndot, double* part) {
+  auto mk = [&](std::initializer_list<const double2*> xs, int tab, double2* out, bool acc,
+                std::initializer_list<const double2*> ys, int ndot, double* part) {
     LinArgs la;
     int j = 0;
     for (const double2* p : xs) la.x[j++] = p;
@@ -171,7 +171,17 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
     }
     la.ndot = ndot;
     la.partials = part;
-    launch_lin(la, F, nrhs, l->stream);
+    return la;
+  };
+  auto lin = [&](std::initializer_list<const double2*> xs, int tab, double2* out, bool acc,
+                 std::initializer_list<const double2*> ys, int ndot, double* part) {
+    launch_lin(mk(xs, tab, out, acc, ys, ndot, part), F, nrhs, l->stream);
+  };
+  // independent combinations (none reads another's output) in one launch
+  auto multi = [&](std::initializer_list<LinArgs> las) {
+    LinMulti m;
+    for (const LinArgs& a : las) m.a[m.n++] = a;
+    launch_lin_multi(m, F, nrhs, l->stream);
   };
   auto copy = [&](double2* dst, const double2* src) {
     return hipMemcpyAsync(dst, src, sizeof(double2) * NF, hipMemcpyDeviceToDevice, l->stream);
@@ -215,9 +225,9 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
       lin({Sv, Wf(i)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2, P[2]);
     }
     launch_gf_beta(S, i, P[1], P[2], nch, l->stream);
-    lin({Vf(i + 1)}, kTabSV, Vf(i + 1), false, {CHI}, 1, P[3]);
+    multi({mk({Vf(i + 1)}, kTabSV, Vf(i + 1), false, {CHI}, 1, P[3]),
+           mk({Wf(i + 1)}, kTabSW, Wf(i + 1), false, {}, 0, nullptr)});
     launch_gf_xbar(S, i + 1, P[3], nch, l->stream);
-    lin({Wf(i + 1)}, kTabSW, Wf(i + 1), false, {}, 0, nullptr);
     OVS_HIP(save_ckpt(i + 1));
   }
   OVS_HIP(copy(TL, T));  // t_k = A v_k, needed by the first reverse step
@@ -289,25 +299,26 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
         launch_gp_coef(S, i, l->stream);
         OVS_HIP(applyA(Vr(i), T));
         OVS_HIP(applyAd(Wr(i), Sv));
-        if (i > 0) {
-          lin({T, Vr(i), Vr(i - 1)}, kTabV, Vr(i + 1), false, {}, 0, nullptr);
-          lin({Sv, Wr(i), Wr(i - 1)}, kTabW, Wr(i + 1), false, {}, 0, nullptr);
-        } else {
-          lin({T, Vr(i)}, kTabV, Vr(i + 1), false, {}, 0, nullptr);
-          lin({Sv, Wr(i), }, kTabW, Wr(i + 1), false, {}, 0, nullptr);
-        }
-        lin({Vr(i + 1)}, kTabSV, Vr(i + 1), false, {}, 0, nullptr);
-        lin({Wr(i + 1)}, kTabSW, Wr(i + 1), false, {}, 0, nullptr);
+        if (i > 0)
+          multi({mk({T, Vr(i), Vr(i - 1)}, kTabV, Vr(i + 1), false, {}, 0, nullptr),
+                 mk({Sv, Wr(i), Wr(i - 1)}, kTabW, Wr(i + 1), false, {}, 0, nullptr)});
+        else
+          multi({mk({T, Vr(i)}, kTabV, Vr(i + 1), false, {}, 0, nullptr),
+                 mk({Sv, Wr(i)}, kTabW, Wr(i + 1), false, {}, 0, nullptr)});
+        multi({mk({Vr(i + 1)}, kTabSV, Vr(i + 1), false, {}, 0, nullptr),
+               mk({Wr(i + 1)}, kTabSW, Wr(i + 1), false, {}, 0, nullptr)});
       }
     }
     for (int i = hi; i >= lo; --i) {
       if (i == k - 1) {
         const int c = i & 1;
         launch_gr_first(S, l->stream);
-        lin({Wr(i)}, kTabSV, TB, false, {}, 0, nullptr);      // tbar
-        lin({CHI}, kTabSW, VB[c], false, {}, 0, nullptr);     // vbar (direct part)
-        lin({TL}, kTabWB, WB[c], false, {Wr(i)}, 1, P[3]);    // wbar, complete
-        if (y) lin({Vr(i)}, kTabY, YA, true, {}, 0, nullptr);
+        LinMulti m0;
+        m0.a[m0.n++] = mk({Wr(i)}, kTabSV, TB, false, {}, 0, nullptr);    // tbar
+        m0.a[m0.n++] = mk({CHI}, kTabSW, VB[c], false, {}, 0, nullptr);   // vbar (direct part)
+        m0.a[m0.n++] = mk({TL}, kTabWB, WB[c], false, {Wr(i)}, 1, P[3]);  // wbar, complete
+        if (y) m0.a[m0.n++] = mk({Vr(i)}, kTabY, YA, true, {}, 0, nullptr);
+        launch_lin_multi(m0, F, nrhs, l->stream);
         OVS_HIP(applyAd(TB, T1));
         lin({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]);    // vbar += A^dag tbar
         launch_gforce(P_.Fg, TB, Vr(i), nullptr, nullptr, F, nrhs, g, hA, hAd, l->stream);
@@ -315,25 +326,27 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
       }
       const int c = i & 1, p = (i + 1) & 1;
       launch_gr_s1(S, i, P[2], P[3], nch, l->stream);
-      if (i > 0) {
-        lin({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i), Vr(i - 1)}, 2, P[0]);
-        lin({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i), Wr(i - 1)}, 2, P[1]);
-      } else {
-        lin({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i)}, 1, P[0]);
-        lin({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i)}, 1, P[1]);
-      }
-      launch_gr_s2(S, i, P[0], P[1], nch, l->stream);
-      lin({VTB[c], Wr(i)}, kTabSV, TB, false, {}, 0, nullptr);
-      lin({CHI, VTB[p], VTB[c]}, kTabSW, VB[c], false, {}, 0, nullptr);
       if (i > 0)
-        lin({WTB[p], WTB[c], Vr(i + 1), Vr(i), Vr(i - 1)}, kTabWB, WB[c], false, {}, 0, nullptr);
+        multi({mk({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i), Vr(i - 1)}, 2, P[0]),
+               mk({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i), Wr(i - 1)}, 2, P[1])});
       else
-        lin({WTB[p], WTB[c], Vr(i + 1), Vr(i)}, kTabWB, WB[c], false, {}, 0, nullptr);
-      if (y) lin({Vr(i)}, kTabY, YA, true, {}, 0, nullptr);
+        multi({mk({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i)}, 1, P[0]),
+               mk({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i)}, 1, P[1])});
+      launch_gr_s2(S, i, P[0], P[1], nch, l->stream);
+      LinMulti m2;
+      m2.a[m2.n++] = mk({VTB[c], Wr(i)}, kTabSV, TB, false, {}, 0, nullptr);
+      m2.a[m2.n++] = mk({CHI, VTB[p], VTB[c]}, kTabSW, VB[c], false, {}, 0, nullptr);
+      if (i > 0)
+        m2.a[m2.n++] = mk({WTB[p], WTB[c], Vr(i + 1), Vr(i), Vr(i - 1)}, kTabWB, WB[c], false, {},
+                          0, nullptr);
+      else
+        m2.a[m2.n++] = mk({WTB[p], WTB[c], Vr(i + 1), Vr(i)}, kTabWB, WB[c], false, {}, 0, nullptr);
+      if (y) m2.a[m2.n++] = mk({Vr(i)}, kTabY, YA, true, {}, 0, nullptr);
+      launch_lin_multi(m2, F, nrhs, l->stream);
       OVS_HIP(applyAd(TB, T1));
       OVS_HIP(applyA(WTB[c], T2));
-      lin({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]);
-      lin({T2}, kTabOne, WB[c], true, {Wr(i)}, 1, P[3]);
+      multi({mk({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]),
+             mk({T2}, kTabOne, WB[c], true, {Wr(i)}, 1, P[3])});
       launch_gforce(P_.Fg, TB, Vr(i), WTB[c], Wr(i), F, nrhs, g, hA, hAd, l->stream);
     }
   }

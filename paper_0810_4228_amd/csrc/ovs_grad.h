@@ -29,6 +29,14 @@ struct LinArgs {
 };
 int lin_nchunk(long stride);
 void launch_lin(const LinArgs& a, long stride, int nrhs, hipStream_t s);
+// Up to kLinMulti independent combinations (none reads another's output) in
+// one launch, each computed exactly as launch_lin computes it.
+constexpr int kLinMulti = 4;
+struct LinMulti {
+  LinArgs a[kLinMulti];
+  int n = 0;
+};
+void launch_lin_multi(const LinMulti& m, long stride, int nrhs, hipStream_t s);
 
 // Per-source scalar steps (one thread per source); see grad.hip.
 struct GradScalars {
