@@ -69,7 +69,11 @@ Tuning get_tuning(const ovs_lattice_s* l, int nrhs) {
   Tuning t;
   const bool f32 = l->prec == OVS_F32_STORE;
   t.rhs_block = f32 ? (nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1)) : 1;
+  // smaller workgroups while the grid is small: more CUs take part (8^4 with
+  // one source: 64 workgroups of 64 rather than 16 of 256)
+  const long blocks = (nrhs + t.rhs_block - 1) / t.rhs_block;
   t.wg = 256;
+  while (t.wg > 64 && (long)l->g.V / t.wg * blocks < 1024) t.wg /= 2;
   return t;
 }
 

@@ -612,13 +612,17 @@ __device__ __forceinline__ void force_dir(double2* F, const double2* pbar, const
 __global__ void __launch_bounds__(kWG) k_gforce(double2* F, const double2* pbar, const double2* p,
                                                 const double2* qbar, const double2* q, long stride,
                                                 int nrhs, Geometry g, HopPair hp) {
+  // one thread per site and direction (blockIdx.y): each direction writes
+  // only its own slots of F, so the directions are independent
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= g.V) return;
   const Nbr nb = neighbours(s, g);
-  force_dir<0>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[0], hp);
-  force_dir<1>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[1], hp);
-  force_dir<2>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[2], hp);
-  force_dir<3>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[3], hp);
+  switch (blockIdx.y) {
+    case 0: force_dir<0>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[0], hp); break;
+    case 1: force_dir<1>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[1], hp); break;
+    case 2: force_dir<2>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[2], hp); break;
+    default: force_dir<3>(F, pbar, p, qbar, q, stride, nrhs, g, s, nb.f[3], hp); break;
+  }
 }
 
 void launch_gforce(double2* F, const double2* pbar, const double2* p, const double2* qbar,
@@ -631,8 +635,8 @@ void launch_gforce(double2* F, const double2* pbar, const double2* p, const doub
     hp.fAd[nu] = hAd.fwd[nu];
     hp.bAd[nu] = hAd.bwd[nu];
   }
-  hipLaunchKernelGGL(k_gforce, dim3((g.V + kWG - 1) / kWG), dim3(kWG), 0, st, F, pbar, p, qbar, q,
-                     stride, nrhs, g, hp);
+  hipLaunchKernelGGL(k_gforce, dim3((g.V + kWG - 1) / kWG, 4), dim3(kWG), 0, st, F, pbar, p, qbar,
+                     q, stride, nrhs, g, hp);
 }
 
 __global__ void __launch_bounds__(kWG) k_gforce_out(const double2* F, const double2* links,
