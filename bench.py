@@ -321,6 +321,9 @@ def main():
                          "profiles were taken with)")
     ap.add_argument("--retune", action="store_true",
                     help="autotune even if the tuning file holds a configuration")
+    ap.add_argument("--gradient-only", nargs=2, metavar=("LXxLYxLZxLT", "K"), default=None,
+                    help="only time the gradient (ovs_sign_apply_vjp) against the forward on "
+                         "that lattice at k iterations (for profiling), e.g. 8x8x8x8 400")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times: the known-size reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -329,6 +332,13 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
 
+    if args.gradient_only:
+        import torch
+        import paper_0810_4228_amd as ovs
+        dims = tuple(int(x) for x in args.gradient_only[0].split("x"))
+        print(json.dumps(gradient_timing(ovs, torch, torch.device("cuda:0"), dims=dims,
+                                         k=int(args.gradient_only[1]))))
+        return
     cpu_t = None
     if not args.no_cpu and not args.stencil_only and not args.copy_calibration:
         log(f"bench: cpu baseline ({CPU_PROCS} oracle processes, before GPU use)")
