@@ -19,9 +19,11 @@ namespace ovs {
 
 // ---- linear combinations with fused dots -------------------------------------
 
+// Workgroups per source of the linear combinations: up to 1024 (four per CU),
+// so that one source's pass keeps enough waves in flight to stream from HBM.
 int lin_nchunk(long stride) {
   long c = (stride + kWG - 1) / kWG;
-  if (c > 256) c = 256;
+  if (c > 1024) c = 1024;
   if (c < 1) c = 1;
   return (int)c;
 }
