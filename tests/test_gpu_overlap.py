@@ -77,3 +77,28 @@ def test_overlap_eigs_argument_errors():
         with pytest.raises(ovs.OvsError):
             lat.overlap_eigs(nev, **kw)
     lat.close()
+
+
+def test_overlap_eigs_8888_block_agrees_with_single():
+    """8^4 (eps 0.6, mu 0.3, FP64), where no dense spectrum is available: plain
+    Arnoldi (block 1, ncv 40) and block Arnoldi (block 4, ncv 80: about 20 block
+    steps per cycle) find the same four eigenvalues of smallest magnitude, each
+    with D_ov x = lambda x to the requested residual."""
+    import torch
+    dims = (8, 8, 8, 8)
+    U = synth.random_links(dims, 0.6, seed=synth.LINK_SEED)
+    lat = lattice(dims, "f64", U, 0.3)
+    kw = dict(k_inner=1000, tol_inner=1e-10, tol=1e-8, max_restarts=200)
+    l1, _, i1, s1 = lat.overlap_eigs(4, ncv=40, block=1, **kw)
+    l4, x4, i4, s4 = lat.overlap_eigs(4, ncv=80, block=4, vectors=True, **kw)
+    say("overlap 8^4 block 1", l1, i1)
+    say("overlap 8^4 block 4", l4, i4)
+    assert s1 == 0 and s4 == 0
+    for z in l4:
+        assert np.min(np.abs(l1 - z)) <= 1e-7, z
+    assert np.abs(np.sort(np.abs(l1)) - np.sort(np.abs(l4))).max() <= 1e-7
+    x = x4.reshape(4, -1)
+    y, _, _ = lat.sign_apply(x, 1000, tol=1e-10, overlap=True)
+    r = torch.linalg.vector_norm(y - torch.from_numpy(l4).to(x.device)[:, None] * x, dim=1)
+    assert r.max().item() <= 1e-7
+    lat.close()
