@@ -279,6 +279,18 @@ ovs_status ovs_inner_sign_tridiag(ovs_lattice lat, int32_t batch, int32_t k, con
 ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, const double* H,
                                      double* x, double* err);
 
+/* su(3) force of a real function L of the links, from its link gradient (for
+ * molecular-dynamics updates of the gauge field; the paper computes no forces):
+ * for U -> exp(eps X) U with X traceless anti-Hermitian, dL/deps = sum over
+ * links of Re tr(F^dagger X) with F = -TA(U G^dagger), TA(M) = (M - M^dagger)/2
+ * - tr(M - M^dagger)/6 * 1, where G = dL/dRe U + i dL/dIm U is the gradient
+ * ovs_sign_apply_vjp returns.
+ *   U      : device complex128 [V][4][3][3], the links as given to ovs_set_links.
+ *   grad_U : device complex128 [V][4][3][3].
+ *   force  : device complex128 [V][4][3][3] (traceless anti-Hermitian), written.
+ * Runs on the handle's stream.  OVS_ERR_ARG for NULL pointers. */
+ovs_status ovs_link_force(ovs_lattice lat, const void* U, const void* grad_U, void* force);
+
 /* ---- eigenvalues of the overlap operator (Sections 1 and 5) ------------- */
 
 /* The nev eigenvalues of smallest magnitude of D_ov(mu) = 1 + gamma5 sgn(A)

@@ -275,3 +275,21 @@ def tsl_vjp(dims, U, m_w, mu, b, chi, k, bc=dirac.DEFAULT_BC):
 def loss(y, chi) -> float:
     """L = Re <chi, y>."""
     return float(np.real(np.vdot(chi, y)))
+
+
+# ------------------------------------------------ Lie-algebra force
+
+def lie_force(U: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """The su(3) force of a real L(U) from its link gradient G (the convention
+    above: G = dL/dRe U + i dL/dIm U, per link [.., 3, 3]).
+
+    For U -> exp(eps X) U with X traceless anti-Hermitian, dL/deps =
+    Re tr(G^dagger X U) = Re tr(X U G^dagger) = <F, X> with <A, B> = Re tr(A^dagger B)
+    and F = -TA(U G^dagger), TA(M) = (M - M^dagger)/2 - tr(M - M^dagger)/6 * 1
+    (the projection onto su(3), orthogonal for that inner product).  Not in the
+    paper: the link force a molecular-dynamics update of the gauge field needs.
+    Pinned by central differences of the dense exact L along exp(eps X) U."""
+    M = U @ np.conj(np.swapaxes(G, -1, -2))
+    A = 0.5 * (M - np.conj(np.swapaxes(M, -1, -2)))
+    tr = np.trace(A, axis1=-2, axis2=-1)[..., None, None]
+    return -(A - tr / 3.0 * np.eye(3))

@@ -43,7 +43,7 @@ EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
     "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
     "ovs_field_apply", "ovs_field_apply_timed", "ovs_dual_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
-    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_overlap_eigs", "ovs_last_coefficients",
+    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_link_force", "ovs_overlap_eigs", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
 ]
 
@@ -121,6 +121,7 @@ def load():
         "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
         "ovs_sign_apply_vjp": [P, P, P, I, I, I, P, P, DP, P, DP],
         "ovs_overlap_eigs": [P, P, I, I, I, I, I, D, I, D, I, DP, P, DP],
+        "ovs_link_force": [P, P, P, P],
         "ovs_last_coefficients": [P, DP, DP, DP, DP],
         "ovs_inner_sign_tridiag": [P, I, I, DP, DP, DP, DP, DP],
         "ovs_inner_sign_hessenberg": [P, I, I, DP, DP, DP],
@@ -310,6 +311,21 @@ class Lattice:
                                       METHODS[method], flags, infos)
         _check(st, "ovs_sign_apply")
         return y, [i.as_dict() for i in infos], st
+
+    def link_force(self, U, grad_U):
+        """su(3) force F = -TA(U grad_U^dagger) per link, [V, 4, 3, 3] complex128 on the
+        GPU, for a real function of the links with gradient grad_U (as returned by
+        sign_apply_vjp)."""
+        torch = _torch()
+        U = _dev_c128(U, "U").contiguous()
+        G = _dev_c128(grad_U, "grad_U").contiguous()
+        if U.numel() != 36 * self.V or G.numel() != 36 * self.V:
+            raise ValueError("U and grad_U must hold V*4*3*3 complex entries")
+        F = torch.empty((self.V, 4, 3, 3), dtype=torch.complex128, device=U.device)
+        _check(self._lib.ovs_link_force(self._h, ctypes.c_void_p(U.data_ptr()),
+                                        ctypes.c_void_p(G.data_ptr()),
+                                        ctypes.c_void_p(F.data_ptr())), "ovs_link_force")
+        return F
 
     def overlap_eigs(self, nev, ncv=None, block=1, k_inner=400, tol_inner=1e-10, tol=1e-8,
                      max_restarts=100, defl=None, n_defl=None, vectors=False, graph=False):

@@ -687,3 +687,50 @@ void launch_gforce_out(const double2* F, const double2* links, const Geometry& g
 }
 
 }  // namespace ovs
+
+namespace ovs {
+
+// ---- su(3) link force ------------------------------------------------------
+// F = -TA(U G^dagger) per link, TA(M) = (M - M^dagger)/2 - tr(M - M^dagger)/6:
+// the force of a real L(U) for U -> exp(eps X) U, X in su(3), from its link
+// gradient G = dL/dRe U + i dL/dIm U.  Canonical layout [V][4][3][3].
+__global__ void __launch_bounds__(kWG) k_link_force(const double2* __restrict__ U,
+                                                    const double2* __restrict__ G,
+                                                    double2* __restrict__ F, long nlinks) {
+  const long n = (long)blockIdx.x * kWG + threadIdx.x;
+  if (n >= nlinks) return;
+  Cx<double> u[9], g[9], m[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    u[e] = c64(U[n * 9 + e]);
+    g[e] = c64(G[n * 9 + e]);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      Cx<double> s = {0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s = cfmac(g[b * 3 + c], u[a * 3 + c], s);  // U_ac conj(G_bc)
+      m[a * 3 + b] = s;
+    }
+  // trace of the anti-Hermitian part: i Im tr M
+  const double imtr = (m[0].im + m[4].im + m[8].im) / 3.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const Cx<double> x = m[a * 3 + b], y = m[b * 3 + a];
+      Cx<double> t = {0.5 * (x.re - y.re), 0.5 * (x.im + y.im)};  // (M - M^dagger)/2
+      if (a == b) t.im -= imtr;
+      F[n * 9 + a * 3 + b] = d2(-t);
+    }
+}
+
+void launch_link_force(const double2* U, const double2* G, double2* F, long nlinks,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_link_force, dim3((unsigned)((nlinks + kWG - 1) / kWG)), dim3(kWG), 0, s,
+                     U, G, F, nlinks);
+}
+
+}  // namespace ovs

@@ -363,3 +363,12 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
   OVS_HIP(hipStreamSynchronize(l->stream));
   return result;
 }
+
+extern "C" ovs_status ovs_link_force(ovs_lattice l, const void* U, const void* grad_U, void* force) {
+  if (!l || !U || !grad_U || !force || l->parent) return OVS_ERR_ARG;
+  StreamScope sc(l);
+  launch_link_force((const double2*)U, (const double2*)grad_U, (double2*)force, 4L * l->g.V,
+                    l->stream);
+  OVS_HIP(hipGetLastError());
+  return OVS_OK;
+}

@@ -37,6 +37,9 @@ struct LinMulti {
   int n = 0;
 };
 void launch_lin_multi(const LinMulti& m, long stride, int nrhs, hipStream_t s);
+// su(3) force F = -TA(U G^dagger) of nlinks links (canonical [..][3][3] layout).
+void launch_link_force(const double2* U, const double2* G, double2* F, long nlinks,
+                       hipStream_t s);
 
 // Per-source scalar steps (one thread per source); see grad.hip.
 struct GradScalars {

@@ -281,3 +281,21 @@ def test_vjp_gauge_identity(k):
     noise = float(f["noise"]) / abs(float(f["loss"]))
     rtol = 1e-9 if k <= 40 else max(1e-9, 2.0 * noise)
     assert abs(tU + tb + tc) <= rtol * (abs(tU) + abs(tb) + abs(tc))
+
+
+def test_link_force_matches_oracle():
+    """ovs_link_force (F = -TA(U G^dagger) per link) against the oracle's
+    lie_force, itself pinned by differences of the exact L along exp(eps X) U;
+    the result is traceless anti-Hermitian."""
+    from oracle import grad as ograd
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 0.6, seed=61)
+    rng = np.random.default_rng(62)
+    G = rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape)
+    lat = f64_lattice(dims, U, 0.3)
+    F = lat.link_force(to_dev(U), to_dev(G)).cpu().numpy()
+    ref = ograd.lie_force(U, G)
+    assert np.abs(F - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(F + np.conj(np.swapaxes(F, -1, -2))).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(np.trace(F, axis1=-2, axis2=-1)).max() <= 1e-13 * np.abs(ref).max()
+    lat.close()
