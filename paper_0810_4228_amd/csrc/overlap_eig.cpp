@@ -95,19 +95,16 @@ bool mgs2(int m, int k, std::vector<cd>& Y) {
 
 }  // namespace
 
-extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
-                                       int32_t nev, int32_t ncv, int32_t block, int32_t k_inner,
-                                       double tol_inner, int32_t inner_flags, double tol,
-                                       int32_t max_restarts, double* lambda, void* vecs,
-                                       double* info) {
+namespace ovs {
+
+// The block Krylov-Schur driver for any operator given as op(in, out, n, warn):
+// n canonical complex128 fields in, n out (device), *warn += sources whose
+// application returned a warning.  Arguments are checked by the callers.
+ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int ncv, int block,
+                             double tol, int max_restarts, double* lambda, void* vecs,
+                             double* info) {
   const int bs = block;
-  if (!l || !lambda || nev < 1 || bs < 1 || bs > 16 || ncv % bs != 0 || ncv < nev + 2 * bs ||
-      ncv > 256 || k_inner < 1 || !(tol_inner > 0) || !(tol > 0) || max_restarts < 0 ||
-      (inner_flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_PERSISTENT)))
-    return OVS_ERR_ARG;
-  if (!ready(l)) return OVS_ERR_STATE;
   const long N = 12L * l->g.V;
-  if (ncv + bs >= N || k_inner > N) return OVS_ERR_ARG;
   const int m = ncv;
   StreamScope sc(l);
   hipStream_t s = l->stream;
@@ -193,20 +190,16 @@ extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_
   auto Hat = [&](int i, int j) -> cd& { return H[(size_t)j * ld + i]; };
   std::vector<cd> theta(m), Y((size_t)m * m), Hm((size_t)m * m);
   std::vector<int> order(m);
-  std::vector<double> res(m), tols(bs, tol_inner);
+  std::vector<double> res(m);
   std::vector<cd> rq(nev);
-  std::vector<ovs_rhs_info> ri(bs);
   int k = 0, restarts = 0, matvecs = 0, inner_warn = 0;
   bool converged = false;
   for (;;) {
     // extend the factorisation from k to m columns, one block at a time
     for (int p = k; p < m; p += bs) {
-      const ovs_status st = ovs_sign_apply(l, defl, n_defl, col(p), col(p + bs), bs, k_inner,
-                                           tols.data(), OVS_2SL, OVS_FLAG_OVERLAP | inner_flags,
-                                           ri.data());
+      const ovs_status st = op(col(p), col(p + bs), bs, &inner_warn);
       matvecs += bs;
       if (st < 0) return st;
-      for (int i = 0; i < bs; ++i) inner_warn += ri[i].status != OVS_OK;
       const ovs_status so = orth_block(p + bs);
       if (so != OVS_OK) return so;
       for (int j = 0; j < bs; ++j) {
@@ -339,3 +332,32 @@ extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_
   }
   return converged && inner_warn == 0 ? OVS_OK : OVS_WARN_NOT_CONVERGED;
 }
+
+}  // namespace ovs
+
+extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
+                                       int32_t nev, int32_t ncv, int32_t block, int32_t k_inner,
+                                       double tol_inner, int32_t inner_flags, double tol,
+                                       int32_t max_restarts, double* lambda, void* vecs,
+                                       double* info) {
+  const int bs = block;
+  if (!l || !lambda || nev < 1 || bs < 1 || bs > 16 || ncv % bs != 0 || ncv < nev + 2 * bs ||
+      ncv > 256 || k_inner < 1 || !(tol_inner > 0) || !(tol > 0) || max_restarts < 0 ||
+      (inner_flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_PERSISTENT)))
+    return OVS_ERR_ARG;
+  if (!ready(l)) return OVS_ERR_STATE;
+  const long N = 12L * l->g.V;
+  if (ncv + bs >= N || k_inner > N) return OVS_ERR_ARG;
+  std::vector<double> tols(bs, tol_inner);
+  std::vector<ovs_rhs_info> ri(bs);
+  // one application of D_ov to a block: a batched sign solve
+  const BlockOp op = [&](const void* in, void* out, int n, int* warn) -> ovs_status {
+    const ovs_status st = ovs_sign_apply(l, defl, n_defl, in, out, n, k_inner, tols.data(),
+                                         OVS_2SL, OVS_FLAG_OVERLAP | inner_flags, ri.data());
+    if (st >= 0)
+      for (int i = 0; i < n; ++i) *warn += ri[i].status != OVS_OK;
+    return st;
+  };
+  return block_krylov_eigs(l, op, nev, ncv, bs, tol, max_restarts, lambda, vecs, info);
+}
+

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <functional>
 
 #include "ovs_common.h"
 
@@ -51,5 +52,17 @@ void pack_field(const ovs_lattice_s* l, const void* canon, void* field, int nrhs
 void unpack_field(const ovs_lattice_s* l, const void* field, void* canon, int nrhs);
 // links and parameters set
 bool ready(const ovs_lattice_s* l);
+
+// An operator on blocks of canonical complex128 fields (device): op(in, out,
+// n, warn) applies it to n fields; *warn counts fields whose application
+// returned a warning.
+using BlockOp = std::function<ovs_status(const void*, void*, int, int*)>;
+// Block Arnoldi with thick restarts in Krylov-Schur form and harmonic Ritz
+// extraction for the target 0 (overlap_eig.cpp): the nev eigenvalues of
+// smallest magnitude (host complex128 [nev]) and, if vecs, their unit vectors
+// (device [nev][12V]); info [4] as for ovs_overlap_eigs.
+ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int ncv, int block,
+                             double tol, int max_restarts, double* lambda, void* vecs,
+                             double* info);
 
 }  // namespace ovs

@@ -66,3 +66,4 @@ def test_eigentriples_8444_residuals():
     # smallest magnitude: no Ritz value of A on the Krylov space of a random vector
     # (checked by a short CPU Arnoldi) falls well inside |lambda_m|
     assert np.all(np.diff(np.abs(lam)) >= -1e-12)
+
