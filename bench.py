@@ -329,7 +329,7 @@ def main():
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
 
     if args.gradient_only:
