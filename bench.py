@@ -463,6 +463,7 @@ def main():
         },
         "tuning": tuning,
         "tuning_source": tuning_src,
+        "workspace_bytes": lat.workspace_size(NRHS, KMAX),
         "k_used": k_used,
         "est_rel_err_max": est,
         "phase_ms": phase,

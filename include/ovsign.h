@@ -196,6 +196,17 @@ ovs_status ovs_deflation_destroy(ovs_deflation d);
 
 /* ---- sign function ------------------------------------------------------ */
 
+/* Device memory (bytes) an ovs_sign_apply call with these arguments holds in
+ * the handle's cached workspace: both halves for a batch that is split, with
+ * convergence checks; the FP64 group of an OVS_F32_STORE lattice (tolerances
+ * below 1e-6, or escalated sources) uses the FP64 workspace of its own group
+ * in addition.  The one-pass combination stores k_max basis vectors per source:
+ * at 16^3 x 32 with 12 sources and k_max = 1000, about 150 GB in FP32 storage;
+ * OVS_FLAG_TWO_PASS keeps three.  No device work, and links need not be set;
+ * OVS_ERR_ARG as for ovs_sign_apply. */
+ovs_status ovs_workspace_size(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, int32_t nrhs,
+                              int32_t k_max, ovs_method method, int32_t flags, size_t* bytes);
+
 /* y = sgn(A) b (or D_ov b with OVS_FLAG_OVERLAP) for nrhs sources, A = gamma5
  * Dw(mu): LR-deflated two-sided Lanczos (eq. 2sLapp) or Arnoldi (eq. Arnapp).
  *   defl   : NULL for no deflation, else the first n_defl triples are used.

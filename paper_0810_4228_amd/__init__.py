@@ -43,7 +43,7 @@ EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
     "ovs_field_create", "ovs_field_destroy", "ovs_field_import", "ovs_field_export",
     "ovs_field_apply", "ovs_field_apply_timed", "ovs_dual_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
-    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_link_force", "ovs_overlap_eigs", "ovs_last_coefficients",
+    "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_workspace_size", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_link_force", "ovs_overlap_eigs", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
 ]
 
@@ -122,6 +122,7 @@ def load():
         "ovs_sign_apply_vjp": [P, P, P, I, I, I, P, P, DP, P, DP],
         "ovs_overlap_eigs": [P, P, I, I, I, I, I, D, I, D, I, DP, P, DP],
         "ovs_link_force": [P, P, P, P],
+        "ovs_workspace_size": [P, P, I, I, I, I, I, ctypes.POINTER(ctypes.c_size_t)],
         "ovs_last_coefficients": [P, DP, DP, DP, DP],
         "ovs_inner_sign_tridiag": [P, I, I, DP, DP, DP, DP, DP],
         "ovs_inner_sign_hessenberg": [P, I, I, DP, DP, DP],
@@ -285,6 +286,19 @@ class Lattice:
         st = _check(self._lib.ovs_deflation_compute(self._h, int(m), float(tol), int(max_iter),
                                                     ctypes.byref(h)), "ovs_deflation_compute")
         return Deflation(self, h, int(m)), st
+
+    def workspace_size(self, nrhs, k_max, defl=None, n_defl=None, method="2sl", two_pass=False,
+                       split=True, persistent=False):
+        """Bytes of device workspace a sign_apply with these arguments holds."""
+        flags = (OVS_FLAG_TWO_PASS if two_pass else 0) | (0 if split else OVS_FLAG_NO_SPLIT) | \
+                (OVS_FLAG_PERSISTENT if persistent else 0)
+        dh = defl._h if defl is not None else None
+        nd = (defl.m if n_defl is None else int(n_defl)) if defl is not None else 0
+        out = ctypes.c_size_t()
+        _check(self._lib.ovs_workspace_size(self._h, dh, nd, int(nrhs), int(k_max),
+                                            METHODS[method], flags, ctypes.byref(out)),
+               "ovs_workspace_size")
+        return int(out.value)
 
     def sign_apply(self, b, k_max, defl=None, n_defl=None, tol=None, method="2sl",
                    two_pass=False, graph=False, overlap=False, out=None, split=True,

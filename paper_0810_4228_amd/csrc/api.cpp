@@ -859,12 +859,15 @@ ovs_status ovs_deflation_destroy(ovs_deflation d) {
 
 // tune_key: the batch size whose tuned kernel configuration is used (the
 // whole batch when this call runs one part of it).
+// ws_bytes: if not NULL, only the workspace this call needs is computed and
+// stored there (b, y, tol and info are not used).
 static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
                                   const void* b, void* y, int32_t nrhs, int32_t k_max,
                                   const double* tol, ovs_method method, int32_t flags,
-                                  ovs_rhs_info* info, int tune_key) {
-  if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || k_max < 1) return OVS_ERR_ARG;
-  if (!ready(l)) return OVS_ERR_STATE;
+                                  ovs_rhs_info* info, int tune_key, size_t* ws_bytes = nullptr) {
+  if (!l || (!ws_bytes && (!b || !y || b == y)) || nrhs < 1 || nrhs > kMaxNrhs || k_max < 1)
+    return OVS_ERR_ARG;
+  if (!ws_bytes && !ready(l)) return OVS_ERR_STATE;  // sizing needs no links
   if (method != OVS_2SL && method != OVS_ARNOLDI) return OVS_ERR_ARG;
   if (flags & ~(OVS_FLAG_TWO_PASS | OVS_FLAG_GRAPH | OVS_FLAG_OVERLAP | OVS_FLAG_NO_SPLIT |
                 OVS_FLAG_PERSISTENT))
@@ -966,6 +969,10 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   {
     Arena sizing{nullptr};
     layout(sizing);
+    if (ws_bytes) {
+      *ws_bytes = sizing.off + 4096;
+      return OVS_OK;
+    }
     ovs_status st = ensure_ws(l, sizing.off + 4096);
     if (st != OVS_OK) return st;
     Arena real{(char*)l->ws};
@@ -1489,6 +1496,24 @@ static ovs_status solve_subset(ovs_lattice l, bool fp64, ovs_deflation defl, int
   if (st < 0) return st;
   for (int j = 0; j < n; ++j) inf[idx[j]] = rec[j];
   return st;
+}
+
+ovs_status ovs_workspace_size(ovs_lattice l, ovs_deflation defl, int32_t n_defl, int32_t nrhs,
+                              int32_t k_max, ovs_method method, int32_t flags, size_t* bytes) {
+  if (!l || !bytes || l->parent) return OVS_ERR_ARG;
+  *bytes = 0;
+  const bool split = nrhs >= kSplitMin && !(flags & (OVS_FLAG_NO_SPLIT | OVS_FLAG_PERSISTENT));
+  const int n1 = split ? nrhs / 2 : nrhs, n2 = nrhs - n1;
+  size_t w1 = 0, w2 = 0;
+  const std::vector<double> tols(nrhs > 0 ? nrhs : 1, 1.0);  // with convergence checks
+  ovs_status st = sign_apply_impl(l, defl, n_defl, nullptr, nullptr, n1, k_max, tols.data(),
+                                  method, flags, nullptr, nrhs, &w1);
+  if (st == OVS_OK && split)
+    st = sign_apply_impl(l, defl, n_defl, nullptr, nullptr, n2, k_max, tols.data(), method,
+                         flags, nullptr, nrhs, &w2);
+  if (st != OVS_OK) return st;
+  *bytes = w1 + w2;
+  return OVS_OK;
 }
 
 ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,

@@ -567,3 +567,24 @@ def test_sign_errors(cfg1):
     with pytest.raises(ovs.OvsError):
         lat.sign_apply(bt, 2000, method="arnoldi", two_pass=True)
     del torch
+
+
+def test_workspace_size():
+    """ovs_workspace_size: the one-pass basis dominates (k_max vectors per
+    source), two-pass keeps three, a split batch adds the second half's
+    workspace, and a solve with that k_max runs (a warning allowed)."""
+    dims = (4, 4, 4, 4)
+    U = synth.random_links(dims, 0.6, seed=71)
+    lat = lattice(dims, "f32", U, 0.3)
+    N = 12 * 256
+    one = lat.workspace_size(12, 400)
+    two = lat.workspace_size(12, 400, two_pass=True)
+    assert one >= 12 * 400 * N * 8 and two < one
+    assert lat.workspace_size(12, 800) - one >= 12 * 400 * N * 8
+    # one batch of 12 against two halves of 6: the same basis, other buffers twice
+    whole = lat.workspace_size(12, 400, split=False)
+    assert abs(one - whole) < 0.05 * whole
+    b = to_dev(synth.gaussian_sources(dims, 12, seed=72))
+    y, info, st = lat.sign_apply(b, 400, tol=[1e-5] * 12)
+    assert st >= 0  # runs (k_max = 400 need not reach 1e-5 on these rough links)
+    lat.close()
