@@ -51,7 +51,9 @@ typedef int32_t ovs_status;
 #define OVS_OK                   0
 #define OVS_WARN_NOT_CONVERGED   1  /* tolerance not reached within k_max        */
 #define OVS_WARN_BREAKDOWN       2  /* serious Lanczos breakdown (delta ~ 0)      */
-#define OVS_WARN_SIGN_AMBIGUOUS  3  /* inner quadrature error above its target    */
+#define OVS_WARN_SIGN_AMBIGUOUS  3  /* inner quadrature error above its target:   */
+                                     /* a Ritz value near the imaginary axis, where */
+                                     /* sgn(z) = sgn(Re z) jumps (Section 1)        */
 #define OVS_ERR_ARG             -1  /* invalid argument                           */
 #define OVS_ERR_HIP             -2  /* HIP runtime error                          */
 #define OVS_ERR_ALLOC           -3  /* device allocation failed                   */
@@ -82,7 +84,10 @@ typedef struct {
   int32_t status;        /* OVS_OK or a warning code for this source                   */
   double est_rel_err;    /* convergence estimate: relative change of y on 512 sampled
                             entries over the last 25 iterations (0 without tol)        */
-  double quad_err;       /* estimated error of the inner sign quadrature               */
+  double quad_err;       /* estimated relative error of x = sgn(G_k) e_1: the coarse/fine
+                            difference of the quadrature at the step that met its target
+                            (3e-7, or tol/10 if smaller) or at the finest step, 1/64;
+                            above the target the status is OVS_WARN_SIGN_AMBIGUOUS     */
   double n_b;            /* |b_R|, norm of the deflated source                         */
   double t_defl_ms, t_krylov_ms, t_inner_ms, t_combine_ms; /* phase times (whole batch) */
   int32_t fp64;          /* 1: y was computed with FP64 vector storage                 */
@@ -214,7 +219,7 @@ ovs_status ovs_workspace_size(ovs_lattice lat, ovs_deflation defl, int32_t n_def
  *   k_max  : maximal Krylov size (1 <= k_max <= N).
  *   tol    : host [nrhs] target relative errors, or NULL to run exactly k_max
  *            steps.  With tol, a source stops when its estimate falls below
- *            tol/10, checked every 25 iterations.  On an OVS_F32_STORE lattice
+ *            tol/10, checked every 25 iterations (2sL and Arnoldi alike).  On an OVS_F32_STORE lattice
  *            the sources with tol < 1e-6 (below what FP32 storage attains) run
  *            as an FP64 group on the FP64 copy of the links; the rest in FP32.
  *            A source whose FP32-storage estimate has not halved over 6 checks
@@ -234,7 +239,11 @@ ovs_status ovs_workspace_size(ovs_lattice lat, ovs_deflation defl, int32_t n_def
  * the same dual-stencil configuration bit for bit.  OVS_ERR_HIP when the
  * device has no cooperative launch.
  * The inner function sgn(G_k) e_1 (or sgn(H_k) e_1) is evaluated on the GPU
- * in FP64.  Returns the most severe per-source warning, or an error. */
+ * in FP64 by a quadrature whose step is halved per source (from 1/4 down to
+ * 1/64) until its error estimate meets 3e-7 and tol/10; a source that misses
+ * it at the finest step has a Ritz value within a few degrees of the
+ * imaginary axis and returns OVS_WARN_SIGN_AMBIGUOUS (y still written).
+ * Returns the most severe per-source warning, or an error. */
 ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, const void* b,
                           void* y, int32_t nrhs, int32_t k_max, const double* tol,
                           ovs_method method, int32_t flags, ovs_rhs_info* info);
@@ -279,14 +288,20 @@ ovs_status ovs_last_coefficients(ovs_lattice lat, double* alpha, double* beta, d
                                  double* x);
 
 /* x = sgn(T) e_1 for a batch of tridiagonal T (Section 4: G_k), on the GPU,
- * by the library's inner-sign quadrature.  Host inputs: diag, super (gamma)
- * complex128 [batch][k]; sub (beta) complex128 [batch][k] (entry k-1 unused).
- * Output x host complex128 [batch][k]; err host double [batch] (may be NULL). */
+ * by the library's inner-sign quadrature (the same refinement as
+ * ovs_sign_apply without tol: target 3e-7).  Host inputs: diag, super (gamma)
+ * complex128 [batch][k]; sub (beta) complex128 [batch][k] (entry k-1 unused,
+ * imaginary parts zero, else OVS_ERR_ARG).  Output x host complex128
+ * [batch][k]; err host double [batch] (may be NULL): the estimate of each
+ * x's relative error.  Returns OVS_WARN_SIGN_AMBIGUOUS (outputs written) if
+ * an estimate is above the target: T has an eigenvalue near the imaginary
+ * axis, where sgn(Re z) is ill-defined (Section 1). */
 ovs_status ovs_inner_sign_tridiag(ovs_lattice lat, int32_t batch, int32_t k, const double* diag,
                                   const double* sub, const double* super, double* x, double* err);
 
 /* x = sgn(H) e_1 for a batch of upper Hessenberg H (Section 2: H_k), column
- * major complex128 [batch][k][k] host; x host complex128 [batch][k]. */
+ * major complex128 [batch][k][k] host; x host complex128 [batch][k]; err and
+ * the returned status as for ovs_inner_sign_tridiag. */
 ovs_status ovs_inner_sign_hessenberg(ovs_lattice lat, int32_t batch, int32_t k, const double* H,
                                      double* x, double* err);
 

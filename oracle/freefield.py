@@ -82,13 +82,3 @@ def free_sign_apply(dims, m_w, mu, b):
     """sgn(A) b for U = 1 from the closed form.  b: complex [nrhs][12V]."""
     b = np.atleast_2d(b)
     return _apply_momentum_space(tuple(dims), b, free_sign_momentum(tuple(dims), m_w, mu))
-
-
-def free_min_abs_re(dims, m_w, mu):
-    """Smallest |Re lambda| of A over all momenta (eigenvalues +-2 kappa root)."""
-    kap = 1.0 / (8.0 + 2.0 * m_w)
-    q = _momenta(dims, mu)
-    mq = m_w + sum(1.0 - np.cos(qn) for qn in q)
-    s2 = sum(np.sin(qn) ** 2 for qn in q)
-    root = np.sqrt(mq * mq + s2 + 0j)
-    return float(np.min(np.abs((2 * kap * root).real)))

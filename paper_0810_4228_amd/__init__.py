@@ -409,22 +409,27 @@ class Lattice:
                "ovs_last_coefficients")
         return a, bb, g, x
 
-    def inner_sign_tridiag(self, diag, sub, sup):
-        """sgn(T) e_1 for a batch of tridiagonal T ([batch, k] complex arrays, host)."""
+    def inner_sign_tridiag(self, diag, sub, sup, return_status=False):
+        """sgn(T) e_1 for a batch of tridiagonal T ([batch, k] complex arrays, host).
+        Returns (x, err), or (x, err, status) with return_status: status is
+        OVS_WARN_SIGN_AMBIGUOUS when the quadrature missed its target (an
+        eigenvalue of T near the imaginary axis)."""
         diag = np.ascontiguousarray(np.atleast_2d(diag), dtype=np.complex128)
         sub = np.ascontiguousarray(np.atleast_2d(sub), dtype=np.complex128)
         sup = np.ascontiguousarray(np.atleast_2d(sup), dtype=np.complex128)
         batch, k = diag.shape
         x = np.zeros((batch, k), dtype=np.complex128)
         err = np.zeros(batch)
-        _check(self._lib.ovs_inner_sign_tridiag(self._h, batch, k, _dptr(diag.view(np.float64)),
-                                                _dptr(sub.view(np.float64)), _dptr(sup.view(np.float64)),
-                                                _dptr(x.view(np.float64)), _dptr(err)),
-               "ovs_inner_sign_tridiag")
-        return x, err
+        st = _check(self._lib.ovs_inner_sign_tridiag(self._h, batch, k, _dptr(diag.view(np.float64)),
+                                                     _dptr(sub.view(np.float64)),
+                                                     _dptr(sup.view(np.float64)),
+                                                     _dptr(x.view(np.float64)), _dptr(err)),
+                    "ovs_inner_sign_tridiag")
+        return (x, err, st) if return_status else (x, err)
 
-    def inner_sign_hessenberg(self, H):
-        """sgn(H) e_1 for a batch of upper Hessenberg H ([batch, k, k] complex, host)."""
+    def inner_sign_hessenberg(self, H, return_status=False):
+        """sgn(H) e_1 for a batch of upper Hessenberg H ([batch, k, k] complex, host).
+        Returns (x, err), or (x, err, status) as inner_sign_tridiag."""
         H = np.asarray(H, dtype=np.complex128)
         if H.ndim == 2:
             H = H[None]
@@ -432,10 +437,10 @@ class Lattice:
         Hc = np.ascontiguousarray(np.swapaxes(H, 1, 2))  # column-major per matrix
         x = np.zeros((batch, k), dtype=np.complex128)
         err = np.zeros(batch)
-        _check(self._lib.ovs_inner_sign_hessenberg(self._h, batch, k, _dptr(Hc.view(np.float64)),
-                                                   _dptr(x.view(np.float64)), _dptr(err)),
-               "ovs_inner_sign_hessenberg")
-        return x, err
+        st = _check(self._lib.ovs_inner_sign_hessenberg(self._h, batch, k, _dptr(Hc.view(np.float64)),
+                                                        _dptr(x.view(np.float64)), _dptr(err)),
+                    "ovs_inner_sign_hessenberg")
+        return (x, err, st) if return_status else (x, err)
 
 
 def small_eig(A):

@@ -137,8 +137,15 @@ bool ready(const ovs_lattice_s* l) { return l && l->links_set && l->params_set; 
 
 // ---- inner sign with step refinement ----------------------------------------
 constexpr double kULo = -40.0, kUHi = 45.0;  // u range of the tau = e^u quadrature
-constexpr double kHStart = 0.25, kHMin = 0.0625;
-constexpr double kQuadAccept = 3e-7;  // coarse/fine difference accepted at step h
+constexpr double kHStart = 0.25, kHMin = 1.0 / 64;
+// Target of the coarse/fine difference of x = sgn(G) e_1 (the error of the
+// rule with step 2h, an upper bound of the error of step h while the rule
+// converges exponentially): kQuadAccept, and a tenth of the source's
+// tolerance when that is smaller.  The error of step s behaves like
+// exp(-2 pi d / s) for a Ritz value at angle d from the imaginary axis, so a
+// target missed at h = 1/64 means a Ritz value within a few degrees of it:
+// the sign is ambiguous there (sgn(z) = sgn(Re z) jumps across the axis).
+constexpr double kQuadAccept = 3e-7;
 constexpr int kProbe = 512;           // sampled entries per source for the convergence estimate
 constexpr int kCheckEvery = 25;       // iterations between convergence checks
 constexpr int kStallChecks = 6;       // checks without the estimate halving: FP32 stall
@@ -175,38 +182,74 @@ int max_nodes() {
   return nn;
 }
 
+// Scratch of the inner sign (sizes in ovs_krylov.h): mult, swp, part for
+// the tridiagonal form; ys, acc for the Hessenberg form; xtmp [nrhs][kmax]
+// and kv [nrhs] for the refinement levels.
 struct InnerScratch {
   double2* mult = nullptr;
   unsigned char* swp = nullptr;
   double2* part = nullptr;
   double2* ys = nullptr;
+  double2* acc = nullptr;
+  double2* xtmp = nullptr;
+  int* kv = nullptr;
 };
 
-// Runs the quadrature at h = 0.25 and halves h while the coarse/fine
-// difference of any source exceeds kQuadAccept (down to h = 1/16).
+// Quadrature target of each source (see kQuadAccept); tol may be NULL.
+std::vector<double> quad_targets(const double* tol, int nrhs) {
+  std::vector<double> t(nrhs, kQuadAccept);
+  if (tol)
+    for (int r = 0; r < nrhs; ++r) t[r] = std::min(kQuadAccept, 0.1 * tol[r]);
+  return t;
+}
+
+// x[r] = sgn(T_r) e_1 for the sources with kvec[r] > 0 (rows of the others
+// are zero).  Runs the quadrature at h = 0.25 and halves h for the sources
+// whose coarse/fine difference is above their target, down to h = kHMin;
+// each source keeps the x of the first step that met its target (or of the
+// finest), so its result does not depend on the other sources of the batch.
+// err_host[r]: that step's difference.
 ovs_status inner_sign(ovs_lattice_s* l, bool tri, const double2* alpha, const double* beta,
-                      const double2* gamma, const double2* H, int kmax, const int* kvec_dev,
-                      int nrhs, InnerScratch& sc, double2* x, double* err_dev,
+                      const double2* gamma, const double2* H, int kmax,
+                      const std::vector<int>& kvec, int nrhs, InnerScratch& sc, double2* x,
+                      double* err_dev, const std::vector<double>& target,
                       std::vector<double>& err_host) {
-  double h = kHStart;
+  hipStream_t s = l->stream;
+  std::vector<int> klev(kvec.begin(), kvec.begin() + nrhs);
+  std::vector<double> eh(nrhs, 0.0);
   err_host.assign(nrhs, 0.0);
-  for (;;) {
+  double h = kHStart;
+  for (bool first = true;; first = false) {
     int n0, nn;
     quad_range(h, n0, nn);
+    OVS_HIP(hipMemcpyAsync(sc.kv, klev.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    double2* xl = first ? x : sc.xtmp;  // the first level writes every row
     if (tri)
-      launch_isign_tri(alpha, beta, gamma, kmax, kvec_dev, nrhs, h, n0, nn, sc.mult, sc.swp,
-                       sc.part, x, err_dev, l->stream);
+      launch_isign_tri(alpha, beta, gamma, kmax, sc.kv, nrhs, h, n0, nn, sc.mult, sc.swp, sc.part,
+                       xl, err_dev, s);
     else
-      launch_isign_hess(H, kmax, kvec_dev, nrhs, h, n0, nn, sc.ys, x, err_dev, l->stream);
+      launch_isign_hess(H, kmax, sc.kv, nrhs, h, n0, nn, sc.ys, sc.acc, xl, err_dev, s);
     OVS_HIP(hipGetLastError());
-    OVS_HIP(hipMemcpyAsync(err_host.data(), err_dev, sizeof(double) * nrhs, hipMemcpyDeviceToHost,
-                           l->stream));
-    OVS_HIP(hipStreamSynchronize(l->stream));
-    double emax = 0.0;
-    for (double e : err_host) emax = std::max(emax, std::isfinite(e) ? e : 1e300);
-    if (emax <= kQuadAccept || h <= kHMin) break;
+    OVS_HIP(hipMemcpyAsync(eh.data(), err_dev, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipStreamSynchronize(s));
+    const bool last = h <= kHMin;
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) {
+      if (klev[r] <= 0) continue;
+      if ((eh[r] <= target[r]) || last) {  // NaN stays unaccepted until the last step
+        if (!first)
+          OVS_HIP(hipMemcpyAsync(x + (size_t)r * kmax, sc.xtmp + (size_t)r * kmax,
+                                 sizeof(double2) * kmax, hipMemcpyDeviceToDevice, s));
+        err_host[r] = eh[r];
+        klev[r] = 0;
+      } else {
+        any = true;
+      }
+    }
+    if (!any) break;
     h *= 0.5;
   }
+  OVS_HIP(hipStreamSynchronize(s));  // klev lifetime
   return OVS_OK;
 }
 
@@ -304,6 +347,7 @@ ovs_status ovs_lattice_destroy(ovs_lattice l) {
   destroy_worker(l);
   destroy_shadow(l);
   if (l->split_buf) (void)hipFree(l->split_buf);
+  if (l->ev_fork) (void)hipEventDestroy(l->ev_fork);
   if (l->links) (void)hipFree(l->links);
   if (l->links64) (void)hipFree(l->links64);
   if (l->ws) (void)hipFree(l->ws);
@@ -894,7 +938,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   const int nslots = two_pass ? 3 : K;
   const int nwg_d = dual_num_wg(l->g), nwg_u = update_nwg(N);
   const int nwave_max = isign_tri_nwave(max_nodes());
-  const int nq_max = 2 * max_nodes();
+  const int nq_chunk = std::min(kIsignHessChunk, 2 * max_nodes());
   const int nch_start = 512, nch_arn = arn_nchunk(N);
 
   // ---- workspace layout (sizing pass, then the real one) ----
@@ -902,14 +946,14 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     double2 *Bq, *bR, *bL, *yex, *Y;
     char *basis, *wbuf, *T, *S;
     double *part1, *part2, *dpart, *CD, *spart, *sums, *sumsb, *nb;
-    double2 *alpha, *gamma, *sw, *coef, *x, *mult, *part, *H, *hcur, *ys;
+    double2 *alpha, *gamma, *sw, *coef, *x, *mult, *part, *H, *hcur, *ys, *acc, *xtmp;
     double *beta, *sv, *tnorm2, *qerr, *red, *apart, *red_n, *red_tn, *scl;
-    int *kstop, *status, *rhs_map, *ints, *kused, *pidx;
+    int *kstop, *status, *rhs_map, *ints, *kused, *pidx, *kv;
     unsigned char* swp;
     double2 *probes, *yp;
     unsigned* bar;
   } B{};
-  const bool probing = tol != nullptr && !arn;
+  const bool probing = tol != nullptr;
   const int P = (int)std::min<long>(kProbe, 12L * l->g.V);
   auto layout = [&](Arena& a) {
     B.Bq = a.take<double2>((size_t)nr * N);
@@ -946,14 +990,17 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     B.x = a.take<double2>((size_t)nr * K);
     B.qerr = a.take<double>(nr);
     B.coef = a.take<double2>((size_t)nr * K);
+    B.xtmp = a.take<double2>((size_t)nr * K);
+    B.kv = a.take<int>(nr);
     if (probing) {
       B.pidx = a.take<int>(P);
       B.probes = a.take<double2>((size_t)nr * K * P);
       B.yp = a.take<double2>((size_t)nr * P);
     }
     if (!arn) {
-      B.mult = a.take<double2>((size_t)nr * nwave_max * K * 64);
-      B.swp = a.take<unsigned char>((size_t)nr * nwave_max * K * 64);
+      const int wchunk = std::min(kIsignWaveChunk, nwave_max);
+      B.mult = a.take<double2>((size_t)nr * wchunk * K * 64);
+      B.swp = a.take<unsigned char>((size_t)nr * wchunk * K * 64);
       B.part = a.take<double2>((size_t)nr * nwave_max * 2 * K);
     } else {
       B.H = a.take<double2>((size_t)nr * K * K);
@@ -963,7 +1010,8 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       B.red_n = a.take<double>(nr);
       B.red_tn = a.take<double>(nr);
       B.scl = a.take<double>(nr);
-      B.ys = a.take<double2>((size_t)nr * nq_max * K);
+      B.ys = a.take<double2>((size_t)nr * nq_chunk * K);
+      B.acc = a.take<double2>((size_t)nr * 2 * K);
     }
   };
   {
@@ -1057,7 +1105,8 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   std::vector<double> best_est(nr, HUGE_VAL);
   std::vector<int> since_best(nr, 0);
   std::vector<char> stalled(nr, 0);
-  InnerScratch isc{B.mult, B.swp, B.part, B.ys};
+  InnerScratch isc{B.mult, B.swp, B.part, B.ys, B.acc, B.xtmp, B.kv};
+  const std::vector<double> qtarget = quad_targets(tol, nr);
   std::vector<double> errh;
 
   if (!arn) {
@@ -1176,8 +1225,8 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
         OVS_HIP(hipStreamSynchronize(s));
         for (int r : amap) ks[r] = std::min(i, hkstop[r]);
         OVS_HIP(hipMemcpyAsync(B.kused, ks.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
-        st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, B.kused, nr, isc, B.x,
-                        B.qerr, errh);
+        st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, ks, nr, isc, B.x,
+                        B.qerr, qtarget, errh);
         if (st != OVS_OK) return st;
         // relative change of y on the sampled entries since the previous check
         launch_make_coef(B.x, B.sv, B.nb, K, nr, B.coef, s);
@@ -1238,8 +1287,8 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       else if (kused[r] > 0) kused[r] = std::min(kused[r], hkstop[r]);
     }
     OVS_HIP(hipMemcpyAsync(B.kused, kused.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
-    st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, B.kused, nr, isc, B.x, B.qerr,
-                    errh);
+    st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, kused, nr, isc, B.x, B.qerr,
+                    qtarget, errh);
     if (st != OVS_OK) return st;
     qerr = errh;
     OVS_HIP(hipEventRecord(ev[3], s));
@@ -1277,6 +1326,24 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   } else {
     // ---- Arnoldi with classical Gram-Schmidt applied twice (Section 2) ----
     Tuning tn = get_tuning(l, tune_key);
+    // convergence checks as for 2sL: every kCheckEvery steps, x_j = sgn(H_j) e_1
+    // and y on the sampled entries; a converged source keeps its k (its later
+    // columns are computed but not used)
+    std::vector<int> pidx_h;
+    std::vector<std::vector<double>> yprev(nr);
+    std::vector<int> ks(nr, 0);
+    if (probing) {
+      std::vector<int> ident(nr);
+      for (int r = 0; r < nr; ++r) ident[r] = r;
+      const int hints[2] = {0, nr};
+      pidx_h = probe_positions(l->g, P);
+      OVS_HIP(hipMemcpyAsync(B.rhs_map, ident.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+      OVS_HIP(hipMemcpyAsync(B.ints, hints, sizeof(hints), hipMemcpyHostToDevice, s));
+      OVS_HIP(hipMemcpyAsync(B.pidx, pidx_h.data(), sizeof(int) * P, hipMemcpyHostToDevice, s));
+      launch_probe_gather(f32, B.basis, bstride, N, false, B.ints, true, B.pidx, P, K, B.rhs_map,
+                          B.ints + 1, nr, B.probes, s);
+      OVS_HIP(hipStreamSynchronize(s));  // host vector lifetimes
+    }
     for (int j = 0; j < K; ++j) {
       OVS_HIP(launch_wilson(f32, l->links, B.basis + (size_t)j * bstride * es, B.T, nr, l->g, hA,
                             false, true, tn, s));
@@ -1289,18 +1356,66 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       if (j < K - 1) {
         launch_arn_sub(B.red_n, B.red_tn, B.H, K, j, B.scl, B.kstop, B.status, nr, s);
         launch_scale_copy(f32, B.T, B.basis + (size_t)(j + 1) * bstride * es, N, B.scl, nr, s);
+        if (probing) {
+          // sampled entries of v_{j+2} (B.ints[0] = j, so the gather takes j + 1)
+          launch_probe_gather(f32, B.basis, bstride, N, false, B.ints, false, B.pidx, P, K,
+                              B.rhs_map, B.ints + 1, nr, B.probes, s);
+          launch_advance(B.ints, s);
+        }
       }
       OVS_HIP(hipGetLastError());
+      const int kj = j + 1;
+      if (probing && kj % kCheckEvery == 0 && kj < K) {
+        OVS_HIP(hipMemcpyAsync(hkstop.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+        OVS_HIP(hipStreamSynchronize(s));
+        int nact = 0;
+        for (int r = 0; r < nr; ++r) {
+          ks[r] = done[r] ? 0 : std::min(kj, hkstop[r]);
+          nact += done[r] ? 0 : 1;
+        }
+        if (nact == 0) break;
+        OVS_HIP(hipMemcpyAsync(B.kused, ks.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+        ovs_status st = inner_sign(l, false, nullptr, nullptr, nullptr, B.H, K, ks, nr, isc,
+                                   B.x, B.qerr, qtarget, errh);
+        if (st != OVS_OK) return st;
+        launch_make_coef(B.x, nullptr, B.nb, K, nr, B.coef, s);
+        launch_probe_y(B.probes, B.coef, B.kused, K, B.yex, N, B.pidx, P, B.yp, nr, s);
+        std::vector<double> yph((size_t)nr * P * 2);
+        OVS_HIP(hipMemcpyAsync(yph.data(), B.yp, sizeof(double2) * nr * P, hipMemcpyDeviceToHost, s));
+        OVS_HIP(hipStreamSynchronize(s));
+        bool all_done = true;
+        for (int r = 0; r < nr; ++r) {
+          if (done[r]) continue;
+          const double* yr = &yph[(size_t)r * P * 2];
+          double dn = 0.0, yn = 0.0;
+          for (int q = 0; q < 2 * P; ++q) {
+            yn += yr[q] * yr[q];
+            if (!yprev[r].empty()) dn += (yr[q] - yprev[r][q]) * (yr[q] - yprev[r][q]);
+          }
+          const bool had_prev = !yprev[r].empty();
+          est[r] = (had_prev && yn > 0) ? std::sqrt(dn / yn) : 1.0;
+          yprev[r].assign(yr, yr + 2 * P);
+          if (hkstop[r] <= kj || (had_prev && est[r] <= 0.1 * tol[r])) {
+            done[r] = 1;
+            kused[r] = ks[r];
+          } else {
+            all_done = false;
+          }
+        }
+        if (all_done) break;
+      }
     }
     OVS_HIP(hipEventRecord(ev[2], s));
     OVS_HIP(hipMemcpyAsync(hkstop.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
     OVS_HIP(hipMemcpyAsync(hstatus.data(), B.status, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
     OVS_HIP(hipStreamSynchronize(s));
-    for (int r = 0; r < nr; ++r)
+    for (int r = 0; r < nr; ++r) {
       if (!done[r]) kused[r] = std::min(K, hkstop[r]);
+      else if (kused[r] > 0) kused[r] = std::min(kused[r], hkstop[r]);
+    }
     OVS_HIP(hipMemcpyAsync(B.kused, kused.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
-    ovs_status st = inner_sign(l, false, nullptr, nullptr, nullptr, B.H, K, B.kused, nr, isc, B.x,
-                               B.qerr, errh);
+    ovs_status st = inner_sign(l, false, nullptr, nullptr, nullptr, B.H, K, kused, nr, isc, B.x,
+                               B.qerr, qtarget, errh);
     if (st != OVS_OK) return st;
     qerr = errh;
     OVS_HIP(hipEventRecord(ev[3], s));
@@ -1322,7 +1437,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   for (int r = 0; r < nr; ++r) {
     int rs = OVS_OK;
     if (hstatus[r] == 2) rs = OVS_WARN_BREAKDOWN;
-    else if (!(qerr[r] <= 1e-3)) rs = OVS_WARN_SIGN_AMBIGUOUS;
+    else if (kused[r] > 0 && !(qerr[r] <= qtarget[r])) rs = OVS_WARN_SIGN_AMBIGUOUS;
     else if (tol && (!done[r] || stalled[r]) && hstatus[r] == 0) rs = OVS_WARN_NOT_CONVERGED;
     if (rs > worst) worst = rs;
     if (info) {
@@ -1369,6 +1484,11 @@ static ovs_status worker_ready(ovs_lattice_s* l) {
     }
     l->worker = w;
   }
+  if (!l->ev_fork && hipEventCreateWithFlags(&l->ev_fork, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    l->ev_fork = nullptr;
+    return OVS_ERR_HIP;
+  }
   ovs_lattice_s* w = l->worker;
   w->user_stream = l->user_stream;
   w->links = l->links;
@@ -1392,6 +1512,11 @@ static ovs_status run_batch(ovs_lattice l, ovs_deflation defl, int32_t n_defl, c
   if (st != OVS_OK) return st;
   const int n1 = nrhs / 2, n2 = nrhs - n1;
   const size_t fb = 12ul * l->g.V * sizeof(double2);
+  // the second half reads b on the worker stream: order it after the caller's
+  // stream (the worker's StreamScope) and after everything already enqueued
+  // on this handle's stream (the gather of solve_subset writes b there)
+  OVS_HIP(hipEventRecord(l->ev_fork, l->stream));
+  OVS_HIP(hipStreamWaitEvent(l->worker->stream, l->ev_fork, 0));
   ovs_status st2 = OVS_OK;
   std::string err2;
   std::thread second([&] {
@@ -1583,7 +1708,8 @@ static ovs_status inner_sign_entry(ovs_lattice l, bool tri, int batch, int k, co
   StreamScope scope(l);
   hipStream_t s = l->stream;
   const int nwave = isign_tri_nwave(max_nodes());
-  const int nq = 2 * max_nodes();
+  const int wchunk = std::min(kIsignWaveChunk, nwave);
+  const int nq = std::min(kIsignHessChunk, 2 * max_nodes());
   Arena sizing{nullptr};
   auto lay = [&](Arena& a, double2*& al, double*& be, double2*& ga, double2*& H, int*& kv,
                  InnerScratch& sc, double2*& xd, double*& ed) {
@@ -1591,16 +1717,19 @@ static ovs_status inner_sign_entry(ovs_lattice l, bool tri, int batch, int k, co
       al = a.take<double2>((size_t)batch * k);
       be = a.take<double>((size_t)batch * k);
       ga = a.take<double2>((size_t)batch * k);
-      sc.mult = a.take<double2>((size_t)batch * nwave * k * 64);
-      sc.swp = a.take<unsigned char>((size_t)batch * nwave * k * 64);
+      sc.mult = a.take<double2>((size_t)batch * wchunk * k * 64);
+      sc.swp = a.take<unsigned char>((size_t)batch * wchunk * k * 64);
       sc.part = a.take<double2>((size_t)batch * nwave * 2 * k);
     } else {
       H = a.take<double2>((size_t)batch * k * k);
       sc.ys = a.take<double2>((size_t)batch * nq * k);
+      sc.acc = a.take<double2>((size_t)batch * 2 * k);
     }
     kv = a.take<int>(batch);
     xd = a.take<double2>((size_t)batch * k);
     ed = a.take<double>(batch);
+    sc.xtmp = a.take<double2>((size_t)batch * k);
+    sc.kv = a.take<int>(batch);
   };
   double2 *al = nullptr, *ga = nullptr, *H = nullptr, *xd = nullptr;
   double *be = nullptr, *ed = nullptr;
@@ -1627,11 +1756,14 @@ static ovs_status inner_sign_entry(ovs_lattice l, bool tri, int batch, int k, co
     OVS_HIP(hipMemcpyAsync(H, Hh, sizeof(double2) * batch * k * k, hipMemcpyHostToDevice, s));
   }
   std::vector<double> eh;
-  st = inner_sign(l, tri, al, be, ga, H, k, kv, batch, sc, xd, ed, eh);
+  const std::vector<double> target = quad_targets(nullptr, batch);
+  st = inner_sign(l, tri, al, be, ga, H, k, kh, batch, sc, xd, ed, target, eh);
   if (st != OVS_OK) return st;
   OVS_HIP(hipMemcpyAsync(x, xd, sizeof(double2) * batch * k, hipMemcpyDeviceToHost, s));
   OVS_HIP(hipStreamSynchronize(s));
   if (err) std::memcpy(err, eh.data(), sizeof(double) * batch);
+  for (int r = 0; r < batch; ++r)
+    if (!(eh[r] <= target[r])) return OVS_WARN_SIGN_AMBIGUOUS;
   return OVS_OK;
 }
 

@@ -6,6 +6,8 @@
 // All inner products and norms accumulate in FP64 and are reduced in a fixed
 // order (per-workgroup partials, then one pass over the partials), so results
 // are bitwise repeatable from run to run.
+#include <algorithm>
+
 #include "ovs_common.h"
 #include "ovs_device.h"
 #include "ovs_krylov.h"
@@ -457,16 +459,20 @@ struct QuadNodes {
 
 // One thread per (source r, shifted solve q): q = 2*node + (0: +tau, 1: -tau).
 // Tridiagonal T_r = tridiag(beta, alpha, gamma) of size k_r.  Wave results are
-// reduced over lanes: part[r][wave][2][kmax] complex (fine rule, coarse rule).
+// reduced over lanes: part[r][wave][2][kmax] complex (fine rule, coarse rule),
+// wave = wave0 + blockIdx.x of nwave in all.  A launch covers one chunk of
+// waves; the multipliers of a chunk live in mult/swp [r][blockIdx.x][kmax][64],
+// which the next chunk (ordered on the stream) reuses.
 __global__ void __launch_bounds__(64) k_isign_tri(const double2* __restrict__ alpha,
                                                   const double* __restrict__ beta,
                                                   const double2* __restrict__ gamma, int kmax,
                                                   const int* __restrict__ kvec, QuadNodes qn,
+                                                  int wave0, int nwave,
                                                   double2* __restrict__ mult,
                                                   unsigned char* __restrict__ swp,
                                                   double2* __restrict__ part) {
   const int r = blockIdx.y;
-  const int wave = blockIdx.x;
+  const int wave = wave0 + blockIdx.x;
   const int lane = threadIdx.x;
   const int q = wave * 64 + lane;
   const int nq = 2 * qn.nnode;
@@ -480,8 +486,8 @@ __global__ void __launch_bounds__(64) k_isign_tri(const double2* __restrict__ al
   const double2* al = alpha + (long)r * kmax;
   const double* be = beta + (long)r * kmax;
   const double2* ga = gamma + (long)r * kmax;
-  const long mbase = ((long)(r * gridDim.x + wave) * kmax) * 64 + lane;
-  double2* part_r = part + ((long)r * gridDim.x + wave) * 2 * kmax;
+  const long mbase = ((long)(r * gridDim.x + blockIdx.x) * kmax) * 64 + lane;
+  double2* part_r = part + ((long)r * nwave + wave) * 2 * kmax;
   if (k <= 0) return;
   // elimination from the bottom: current column j holds (cu: row j-1, cd: row j)
   Cx<double> cu = (k >= 2) ? c64(ga[k - 2]) : Cx<double>{0, 0};
@@ -579,27 +585,28 @@ __global__ void __launch_bounds__(256) k_isign_final(const double2* __restrict__
   if (threadIdx.x == 0) err[r] = v[1] > 0 ? sqrt(v[0] / v[1]) : 0.0;
 }
 
-// Hessenberg variant: one workgroup per (source r, shifted solve q).  The
-// current column lives in LDS; H is column-major [r][kmax][kmax].
-// Output ys[r][q][kmax] = (H + i sigma)^{-1} e_1 (unweighted).
+// Hessenberg variant: one workgroup per (source r, shifted solve q), q = q0 +
+// blockIdx.x for a chunk of gridDim.x solves.  The current column lives in
+// LDS; H is column-major [r][kmax][kmax].
+// Output ys[r][blockIdx.x][kmax] = (H + i sigma)^{-1} e_1 (unweighted).
 constexpr int kHessMax = 1536;
 
 __global__ void __launch_bounds__(256) k_isign_hess(const double2* __restrict__ H, int kmax,
                                                     const int* __restrict__ kvec, QuadNodes qn,
-                                                    double2* __restrict__ ys) {
+                                                    int q0, double2* __restrict__ ys) {
   __shared__ double2 c[kHessMax];
   __shared__ double2 mlt[kHessMax];
   __shared__ unsigned char swv[kHessMax];
   __shared__ double2 bc_m;
   __shared__ int bc_sw;
-  const int q = blockIdx.x;
+  const int q = q0 + blockIdx.x;
   const int r = blockIdx.y;
   const int k = kvec[r];
   const int node = qn.n0 + q / 2;
   const double tau = exp(node * qn.h);
   const double sig = (q & 1) ? -tau : tau;
   const double2* Hr = H + (long)r * kmax * kmax;
-  double2* y = ys + ((long)r * gridDim.x + q) * kmax;
+  double2* y = ys + ((long)r * gridDim.x + blockIdx.x) * kmax;
   if (k <= 0) return;
   // current column k-1 (rows 0..k-1)
   for (int i = threadIdx.x; i < k; i += blockDim.x) {
@@ -646,10 +653,38 @@ __global__ void __launch_bounds__(256) k_isign_hess(const double2* __restrict__ 
   }
 }
 
-// x[r][j] = sum_q w_q ys[r][q][j]; fine and coarse rules; err as above
-__global__ void __launch_bounds__(256) k_isign_hess_final(const double2* __restrict__ ys, int nq,
-                                                          int kmax, const int* __restrict__ kvec,
-                                                          QuadNodes qn, double2* __restrict__ x,
+// acc[r][0][j] += sum over the chunk's solves of w_q ys (fine rule),
+// acc[r][1][j] the same over the coarse rule's nodes; solves in order, so the
+// sums are the same for every run.  first: the chunk starts the sums.
+__global__ void __launch_bounds__(256) k_isign_hess_accum(const double2* __restrict__ ys, int q0,
+                                                          int nq_chunk, int kmax,
+                                                          const int* __restrict__ kvec,
+                                                          QuadNodes qn, int first,
+                                                          double2* __restrict__ acc) {
+  const int r = blockIdx.y;
+  const int k = kvec[r];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kmax) return;
+  double2* a = acc + (long)r * 2 * kmax;
+  Cx<double> f = first ? Cx<double>{0, 0} : c64(a[j]);
+  Cx<double> c = first ? Cx<double>{0, 0} : c64(a[kmax + j]);
+  if (j < k) {
+    for (int qq = 0; qq < nq_chunk; ++qq) {
+      const int node = qn.n0 + (q0 + qq) / 2;
+      const double tau = exp(node * qn.h);
+      const Cx<double> yv = c64(ys[((long)r * nq_chunk + qq) * kmax + j]);
+      f = f + scale(qn.h / M_PI * tau, yv);
+      if ((node & 1) == 0) c = c + scale(2.0 * qn.h / M_PI * tau, yv);
+    }
+  }
+  a[j] = d2(f);
+  a[kmax + j] = d2(c);
+}
+
+// x[r] = fine sums; err[r] = |x_fine - x_coarse| / |x_fine|
+__global__ void __launch_bounds__(256) k_isign_hess_final(const double2* __restrict__ acc, int kmax,
+                                                          const int* __restrict__ kvec,
+                                                          double2* __restrict__ x,
                                                           double* __restrict__ err) {
   __shared__ double lds[4 * 2];
   const int r = blockIdx.x;
@@ -658,13 +693,8 @@ __global__ void __launch_bounds__(256) k_isign_hess_final(const double2* __restr
   for (int j = threadIdx.x; j < kmax; j += blockDim.x) {
     Cx<double> f = {0, 0}, c = {0, 0};
     if (j < k) {
-      for (int q = 0; q < nq; ++q) {
-        const int node = qn.n0 + q / 2;
-        const double tau = exp(node * qn.h);
-        const Cx<double> yv = c64(ys[((long)r * nq + q) * kmax + j]);
-        f = f + scale(qn.h / M_PI * tau, yv);
-        if ((node & 1) == 0) c = c + scale(2.0 * qn.h / M_PI * tau, yv);
-      }
+      f = c64(acc[(long)r * 2 * kmax + j]);
+      c = c64(acc[(long)r * 2 * kmax + kmax + j]);
     }
     x[(long)r * kmax + j] = d2(f);
     v[0] += cnorm2(f - c);
@@ -889,17 +919,24 @@ void launch_isign_tri(const double2* alpha, const double* beta, const double2* g
                       unsigned char* swp, double2* part, double2* x, double* err, hipStream_t s) {
   QuadNodes qn{h, n0, nnode};
   const int nw = isign_tri_nwave(nnode);
-  hipLaunchKernelGGL(k_isign_tri, dim3(nw, nrhs), dim3(64), 0, s, alpha, beta, gamma, kmax, kvec,
-                     qn, mult, swp, part);
+  for (int w0 = 0; w0 < nw; w0 += kIsignWaveChunk)
+    hipLaunchKernelGGL(k_isign_tri, dim3(std::min(kIsignWaveChunk, nw - w0), nrhs), dim3(64), 0,
+                       s, alpha, beta, gamma, kmax, kvec, qn, w0, nw, mult, swp, part);
   hipLaunchKernelGGL(k_isign_final, dim3(nrhs), dim3(256), 0, s, part, nw, kmax, kvec, x, err);
 }
 
 void launch_isign_hess(const double2* H, int kmax, const int* kvec, int nrhs, double h, int n0,
-                       int nnode, double2* ys, double2* x, double* err, hipStream_t s) {
+                       int nnode, double2* ys, double2* acc, double2* x, double* err,
+                       hipStream_t s) {
   QuadNodes qn{h, n0, nnode};
   const int nq = 2 * nnode;
-  hipLaunchKernelGGL(k_isign_hess, dim3(nq, nrhs), dim3(256), 0, s, H, kmax, kvec, qn, ys);
-  hipLaunchKernelGGL(k_isign_hess_final, dim3(nrhs), dim3(256), 0, s, ys, nq, kmax, kvec, qn, x, err);
+  for (int q0 = 0; q0 < nq; q0 += kIsignHessChunk) {
+    const int nc = std::min(kIsignHessChunk, nq - q0);
+    hipLaunchKernelGGL(k_isign_hess, dim3(nc, nrhs), dim3(256), 0, s, H, kmax, kvec, qn, q0, ys);
+    hipLaunchKernelGGL(k_isign_hess_accum, dim3(cdiv_i(kmax, 256), nrhs), dim3(256), 0, s, ys, q0,
+                       nc, kmax, kvec, qn, (int)(q0 == 0), acc);
+  }
+  hipLaunchKernelGGL(k_isign_hess_final, dim3(nrhs), dim3(256), 0, s, acc, kmax, kvec, x, err);
 }
 
 }  // namespace ovs

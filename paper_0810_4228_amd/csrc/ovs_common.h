@@ -109,6 +109,10 @@ struct ovs_lattice_s {
   size_t split_bytes = 0;
   // second handle (own stream) for the concurrent half of large batches
   ovs_lattice_s* worker = nullptr;
+  // recorded on this handle's stream before the worker half starts: the
+  // worker's stream waits on it, so work already enqueued here (e.g. a gather
+  // of the sources into split_buf) is complete before the worker reads it
+  hipEvent_t ev_fork = nullptr;
 };
 
 struct ovs_field_s {

@@ -67,11 +67,19 @@ void launch_arn_sub(const double* red_n, const double* red_tn, double2* H, int k
 void launch_scale_copy(bool f32, const void* T, void* out, long N, const double* scl, int nrhs,
                        hipStream_t s);
 
+// Inner sign by the tau = e^u trapezoid rule.  The tridiagonal form runs its
+// shifted solves in launches of at most kIsignWaveChunk waves of 64 solves
+// per source (mult, swp: [nrhs][kIsignWaveChunk][kmax][64]; part: [nrhs][all
+// waves][2][kmax]); the Hessenberg form kIsignHessChunk solves per source
+// (ys: [nrhs][kIsignHessChunk][kmax]; acc: [nrhs][2][kmax]).
+constexpr int kIsignWaveChunk = 48;
+constexpr int kIsignHessChunk = 1024;
 int isign_tri_nwave(int nnode);
 void launch_isign_tri(const double2* alpha, const double* beta, const double2* gamma, int kmax,
                       const int* kvec, int nrhs, double h, int n0, int nnode, double2* mult,
                       unsigned char* swp, double2* part, double2* x, double* err, hipStream_t s);
 void launch_isign_hess(const double2* H, int kmax, const int* kvec, int nrhs, double h, int n0,
-                       int nnode, double2* ys, double2* x, double* err, hipStream_t s);
+                       int nnode, double2* ys, double2* acc, double2* x, double* err,
+                       hipStream_t s);
 
 }  // namespace ovs

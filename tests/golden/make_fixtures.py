@@ -3,7 +3,7 @@
 Calls only the CPU oracle (oracle/) and the seeded input generators (synth/);
 nothing here touches the HIP library.  Re-run with
     python tests/golden/make_fixtures.py [lattice_4444] [gradient_8888] [sign_16x16x16x32]
-                                         [sign_16x16x16x16] [overlap_4444]
+                                         [sign_16x16x16x16] [overlap_4444] [config2_8888]
 (all when no name is given) after any change to the oracle's arithmetic.
 
 lattice_4444.npz -- the 4^4 workload: links P_SU3(1 + 0.4 G) (seed 0),
@@ -35,6 +35,20 @@ sign_16x16x16x32.npz -- the benchmark workload: 16^3 x 32, links
     values come from the k = 700 run's first 650 coefficients (the same
     numbers a k = 650 run produces).
 
+config2_8888.npz -- the 8^4 configuration of the Lanczos/Arnoldi comparison:
+    links P_SU3(1 + 0.6 G) (seed 0), m_w = -1.5, one Gaussian source (seed 1),
+    mu in {0, 0.1, 0.3, 0.5}.  Per mu: the 34 eigenvalues of smallest
+    magnitude with their eigentriples' residuals and biorthogonality
+    (eigtrip.sparse_eigentriples, the shift-invert route of Section 5); the
+    LR-deflated (m = 30, Section 3) two-sided Lanczos (Section 4) and Arnoldi
+    (Section 2) results at k = 200, 400 and 800 (4096 sampled entries,
+    default_rng(7)) and their relative errors against the reference, the
+    deflated two-sided Lanczos at k = 1600 (two-pass), whose own uncertainty
+    is its difference from the Arnoldi result at k = 800.  At mu = 0.3 also
+    the undeflated Lanczos coefficients to k = 800 and sgn(G_k) e_1 at k = 400
+    and 800 by the spectral definition (with the eigenvector condition number
+    and the smallest |Re| of the Ritz values).
+
 overlap_4444.npz -- the spectrum of the overlap operator D_ov(mu) = 1 +
     gamma5 sgn(A) (Section 1) on the 4^4 lattice of lattice_4444.npz (links
     P_SU3(1 + 0.4 G), seed 0; m_w = -1.5) at mu = 0 and mu = 0.3: all 3072
@@ -55,7 +69,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import synth  # noqa: E402
-from oracle import dirac, grad, krylov, overlap, sign  # noqa: E402
+from oracle import dirac, eigtrip, grad, krylov, overlap, sign  # noqa: E402
 
 
 def lattice_4444():
@@ -222,6 +236,63 @@ def sign_16x16x16x16():
     np.savez_compressed(os.path.join(HERE, "sign_16x16x16x16.npz"), **out)
 
 
+def _config2_mu(mu):
+    dims = (8, 8, 8, 8)
+    m_w, eps, m = -1.5, 0.6, 30
+    U = synth.random_links(dims, eps, seed=synth.LINK_SEED)
+    b = synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)[0]
+    A = dirac.csr_A(dims, U, m_w, mu)
+    Ad = dirac.csr_A(dims, U, m_w, -mu)
+    del U
+    N = A.shape[0]
+    idx = np.sort(np.random.default_rng(7).choice(N, 4096, replace=False))
+    lam, R, L = eigtrip.sparse_eigentriples(A, m + 4)
+    res_r = np.linalg.norm(A @ R - R * lam[None, :], axis=0) / np.abs(lam)
+    res_l = np.linalg.norm(Ad @ L - L * np.conj(lam)[None, :], axis=0) / np.abs(lam)
+    res_l = res_l / np.linalg.norm(L, axis=0)
+    biorth = np.abs(L[:, :m].conj().T @ R[:, :m] - np.eye(m)).max()
+    print("mu", mu, "eigentriples", lam[:3], "res", res_r.max(), res_l.max(), biorth, flush=True)
+    defl = (lam[:m], R[:, :m], L[:, :m])
+    mv = lambda z: A @ z  # noqa: E731
+    rmv = lambda z: Ad @ z  # noqa: E731
+    yref = krylov.tsl_apply(mv, rmv, b, 1600, defl=defl, two_pass=True)
+    out = {f"lam_mu{mu}": lam, f"res_r_mu{mu}": res_r, f"res_l_mu{mu}": res_l,
+           f"biorth_mu{mu}": biorth, f"yref_mu{mu}": yref[idx], f"normref_mu{mu}": np.linalg.norm(yref)}
+    for k in (200, 400, 800):
+        y2 = krylov.tsl_apply(mv, rmv, b, k, defl=defl, two_pass=True)
+        ya = krylov.arnoldi_apply(mv, b, k, defl=defl)
+        out[f"y2sl_k{k}_mu{mu}"] = y2[idx]
+        out[f"yarn_k{k}_mu{mu}"] = ya[idx]
+        out[f"e2sl_k{k}_mu{mu}"] = np.linalg.norm(y2 - yref) / np.linalg.norm(yref)
+        out[f"earn_k{k}_mu{mu}"] = np.linalg.norm(ya - yref) / np.linalg.norm(yref)
+        print("mu", mu, "k", k, out[f"e2sl_k{k}_mu{mu}"], out[f"earn_k{k}_mu{mu}"], flush=True)
+        if k == 800:
+            out[f"refunc_mu{mu}"] = np.linalg.norm(ya - yref) / np.linalg.norm(yref)
+    if mu == 0.3:
+        lr = krylov.two_sided_lanczos(mv, rmv, b, b, 800, store=False)
+        assert lr.k == 800 and lr.status == "ok", (lr.k, lr.status)
+        out["g_alpha"], out["g_beta"], out["g_gamma"] = lr.alpha, lr.beta, lr.gamma
+        for k in (400, 800):
+            G = krylov.tridiag(lr.alpha[:k], lr.beta[:k - 1], lr.gamma[:k - 1])
+            ev, vecs = np.linalg.eig(G)
+            out[f"g_x{k}"] = sign.sign_e1(G)
+            out[f"g_cond{k}"] = np.linalg.cond(vecs)
+            out[f"g_minre{k}"] = np.abs(ev.real).min()
+            out[f"g_minangle{k}"] = np.min(np.abs(np.arctan2(ev.real, np.abs(ev.imag))))
+    return out
+
+
+def config2_8888():
+    from concurrent.futures import ProcessPoolExecutor
+    out = {"dims": np.array((8, 8, 8, 8)), "m_w": -1.5, "eps": 0.6, "m": 30,
+           "mus": np.array([0.0, 0.1, 0.3, 0.5]), "ks": np.array([200, 400, 800]),
+           "idx": np.sort(np.random.default_rng(7).choice(12 * 8 ** 4, 4096, replace=False))}
+    with ProcessPoolExecutor(4) as ex:
+        for res in ex.map(_config2_mu, (0.0, 0.1, 0.3, 0.5)):
+            out.update(res)
+    np.savez_compressed(os.path.join(HERE, "config2_8888.npz"), **out)
+
+
 def overlap_4444():
     dims = (4, 4, 4, 4)
     m_w, eps = -1.5, 0.4
@@ -234,7 +305,7 @@ def overlap_4444():
 
 if __name__ == "__main__":
     names = sys.argv[1:] or ["lattice_4444", "gradient_8888", "sign_16x16x16x32",
-                             "sign_16x16x16x16", "overlap_4444"]
+                             "sign_16x16x16x16", "overlap_4444", "config2_8888"]
     for name in names:
         if name == "gradient_8888_k150":
             gradient_8888_at(150, 1e-5, True)
