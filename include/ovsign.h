@@ -123,6 +123,21 @@ ovs_status ovs_set_params(ovs_lattice lat, double m_w, double mu);
  * OVS_F32_STORE mode the stencil runs in FP32 (inputs rounded to FP32). */
 ovs_status ovs_apply(ovs_lattice lat, ovs_op op, const void* x, void* y, int32_t nrhs);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ovs_apply
+ * with the same arguments, stream semantics and results (the same kernels),
+ * but its two staging fields (the packed input and output) live in a fixed
+ * per-device scratch array of OVS_APPLY_NOALLOC_MAX_BYTES held by the library
+ * until the process ends, so the call allocates and frees nothing.
+ * 2 * nrhs * 12 * Vs * (16 for OVS_F64, 8 for OVS_F32_STORE) bytes must fit,
+ * Vs = V rounded up to a multiple of 64, plus 64 (each field rounded up to 256
+ * bytes): OVS_ERR_ARG otherwise (e.g. 16^3 x 32 FP64: one source; 16^4 FP32:
+ * up to five).  Every call on one GPU shares that GPU's scratch and leaves its
+ * contents behind: calls that overlap on one GPU (two streams, two host
+ * threads) race and must be serialised by the caller. */
+#define OVS_APPLY_NOALLOC_MAX_BYTES (64ull << 20)
+ovs_status ovs_apply_noalloc(ovs_lattice lat, ovs_op op, const void* x, void* y, int32_t nrhs);
+
 /* ---- resident fields (library layout, for repeated stencil application) -- */
 
 /* A field of nrhs sources in the library's private layout and storage type. */

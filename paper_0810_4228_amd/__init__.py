@@ -45,6 +45,7 @@ EXPORTED = [
     "ovs_field_apply", "ovs_field_apply_timed", "ovs_dual_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
     "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_workspace_size", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_link_force", "ovs_overlap_eigs", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
+    "ovs_apply_noalloc",
 ]
 
 
@@ -103,6 +104,7 @@ def load():
         "ovs_set_links": [P, P],
         "ovs_set_params": [P, D, D],
         "ovs_apply": [P, I, P, P, I],
+        "ovs_apply_noalloc": [P, I, P, P, I],
         "ovs_field_create": [P, I, ctypes.POINTER(P)],
         "ovs_field_destroy": [P],
         "ovs_field_import": [P, P],
@@ -225,6 +227,16 @@ class Lattice:
         y = torch.empty_like(x) if out is None else _dev_c128(out, "out")
         _check(self._lib.ovs_apply(self._h, OPS[op], ctypes.c_void_p(x.data_ptr()),
                                    ctypes.c_void_p(y.data_ptr()), nrhs), "ovs_apply")
+        return y
+
+    def apply_noalloc(self, op, x, out):
+        """y = op x like apply(), through ovs_apply_noalloc: the library's staging
+        fields are its fixed per-device scratch (nothing is allocated); out is
+        required.  Raises OvsError (OVS_ERR_ARG) when the staging does not fit."""
+        x, nrhs = self._fields(x)
+        y = _dev_c128(out, "out")
+        _check(self._lib.ovs_apply_noalloc(self._h, OPS[op], ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(y.data_ptr()), nrhs), "ovs_apply_noalloc")
         return y
 
     def field_create(self, nrhs):

@@ -18,7 +18,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libovsign.so")
-SOURCES = ["stencil.hip", "krylov.hip", "persistent.hip", "eig.hip", "grad.hip", "dense.cpp",
+SOURCES = ["stencil.hip", "krylov.hip", "persistent.hip", "eig.hip", "grad.hip", "noalloc.hip",
+           "dense.cpp",
            "overlap_eig.cpp",
            "eigsolve.cpp", "gradient.cpp", "api.cpp"]
 
