@@ -463,7 +463,10 @@ def main():
         },
         "tuning": tuning,
         "tuning_source": tuning_src,
+        # caller-workspace requirement (the k_max layout) and what the handle
+        # actually holds after the timed solves (basis grown as needed)
         "workspace_bytes": lat.workspace_size(NRHS, KMAX),
+        "workspace_held_bytes": lat.workspace_held(),
         "k_used": k_used,
         "est_rel_err_max": est,
         "phase_ms": phase,

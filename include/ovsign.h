@@ -93,7 +93,21 @@ typedef struct {
   int32_t fp64;          /* 1: y was computed with FP64 vector storage                 */
   int32_t escalated;     /* 1: FP32 storage stalled (below) and the source was solved
                             again with FP64 storage                                    */
+  double min_abs_delta;  /* 2sL: smallest |delta_i| / (|v~_i| |w~_i|) over the
+                            iterations (Section 4: delta = w~^dagger v~; a serious
+                            breakdown below 1e-13); -1 for Arnoldi or k < 2          */
+  double biorth_err;     /* OVS_DEBUG_CHECKS, 2sL one-pass: largest |w_j^dagger v_i -
+                            delta_ij| of the rows j checked every 25 iterations and at
+                            the end (Section 4 keeps W^dagger V = I only in exact
+                            arithmetic); else -1                                       */
+  double ritz_min_re;    /* OVS_DEBUG_CHECKS: smallest |Re theta| / |theta| over the
+                            eigenvalues theta of G_k (H_k) by a dense eigensolve; else -1 */
+  double inner_check_err;/* OVS_DEBUG_CHECKS: relative difference of the quadrature's
+                            x from the spectral sgn(G_k) e_1 of that eigensolve; else -1 */
 } ovs_rhs_info;
+
+/* Debug flags of ovs_set_debug. */
+#define OVS_DEBUG_CHECKS 1
 
 /* ---- lattice ------------------------------------------------------------ */
 
@@ -108,14 +122,34 @@ ovs_status ovs_lattice_create(const int32_t dims[4], const int32_t bc[4], ovs_pr
                               void* hip_stream, ovs_lattice* out);
 ovs_status ovs_lattice_destroy(ovs_lattice lat);
 
-/* Copy gauge links U_{x,nu} in SU(3) (Section 1) into the handle.  U: device,
- * complex128 [V][4][3][3].  The library keeps its own packed copy (FP64 or
- * FP32 per prec) with the boundary signs folded in. */
-ovs_status ovs_set_links(ovs_lattice lat, const void* U);
+/* Copy gauge links U_{x,nu} in SU(3) (Section 1) into the handle.  U:
+ * complex128 [V][4][3][3], device memory if on_device != 0, else host memory
+ * (copied to the device through a temporary buffer the call allocates and
+ * frees; the call then returns after the copy).  The library keeps its own
+ * packed copy (FP64 or FP32 per prec) with the boundary signs folded in. */
+ovs_status ovs_set_links(ovs_lattice lat, const void* U, int32_t on_device);
 
 /* Set m_w and mu (Section 1): kappa = 1/(8 + 2 m_w).  OVS_ERR_ARG if
  * 8 + 2 m_w <= 0 or a value is not finite. */
 ovs_status ovs_set_params(ovs_lattice lat, double m_w, double mu);
+
+/* Diagnostics of later ovs_sign_apply calls on this handle.
+ *   flags        : 0 or OVS_DEBUG_CHECKS.  With OVS_DEBUG_CHECKS the 2sL
+ *                  biorthogonality w_j^dagger V_j (Section 4: W^dagger V = I,
+ *                  which short recurrences keep only in exact arithmetic) is
+ *                  measured every 25 iterations and at the end against the
+ *                  stored basis (one-pass only), and the inner sign is checked
+ *                  against a dense eigendecomposition of G_k (H_k) on the host,
+ *                  O(k^3) per source (Section 1, eq. for f(A)); results in
+ *                  ovs_rhs_info.  A Ritz value with |Re theta| <= 1e-12 |theta|
+ *                  then also returns OVS_WARN_SIGN_AMBIGUOUS.
+ *   breakdown_at : >= 0: the 2sL beta step of that iteration (0-based) takes
+ *                  delta = 0, the serious breakdown of Section 4 (the source
+ *                  stops with k = breakdown_at + 1 and OVS_WARN_BREAKDOWN; y
+ *                  is the result of that k); -1: none.  For testing the
+ *                  breakdown path; applies to every source of a call.
+ * OVS_ERR_ARG for unknown flags or breakdown_at < -1. */
+ovs_status ovs_set_debug(ovs_lattice lat, int32_t flags, int32_t breakdown_at);
 
 /* y = op x for nrhs sources (Section 1).  x, y: device complex128
  * [nrhs][V][4][3], must not alias.  OVS_OP_A is gamma5 Dw(mu), OVS_OP_A_DAG its
@@ -216,16 +250,22 @@ ovs_status ovs_deflation_destroy(ovs_deflation d);
 
 /* ---- sign function ------------------------------------------------------ */
 
-/* Device memory (bytes) an ovs_sign_apply call with these arguments holds in
- * the handle's cached workspace: both halves for a batch that is split, with
- * convergence checks; the FP64 group of an OVS_F32_STORE lattice (tolerances
- * below 1e-6, or escalated sources) uses the FP64 workspace of its own group
- * in addition.  The one-pass combination stores k_max basis vectors per source:
- * at 16^3 x 32 with 12 sources and k_max = 1000, about 150 GB in FP32 storage;
- * OVS_FLAG_TWO_PASS keeps three.  No device work, and links need not be set;
- * OVS_ERR_ARG as for ovs_sign_apply. */
+/* Bytes of caller workspace an ovs_sign_apply call with these arguments
+ * needs (its `workspace` argument): both halves of a batch that is split, with
+ * convergence checks, and the one-pass basis for k_max vectors (at 16^3 x 32
+ * with 12 sources and k_max = 1000, about 150 GB in FP32 storage;
+ * OVS_FLAG_TWO_PASS keeps three vectors: 2.5 GB).  No device work, and links
+ * need not be set; OVS_ERR_ARG as for ovs_sign_apply. */
 ovs_status ovs_workspace_size(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, int32_t nrhs,
                               int32_t k_max, ovs_method method, int32_t flags, size_t* bytes);
+
+/* Device memory (bytes) the handle holds for ovs_sign_apply calls without a
+ * caller workspace: its cached workspace, the one-pass basis (grown in
+ * doubling steps from 256 vectors as the iteration needs them, so a solve that
+ * stops at k holds at most 2k of them, not k_max) and the gather buffer, plus
+ * those of its internal second-half and FP64 handles.  Kept until
+ * ovs_lattice_destroy. */
+ovs_status ovs_workspace_held(ovs_lattice lat, size_t* bytes);
 
 /* y = sgn(A) b (or D_ov b with OVS_FLAG_OVERLAP) for nrhs sources, A = gamma5
  * Dw(mu): LR-deflated two-sided Lanczos (eq. 2sLapp) or Arnoldi (eq. Arnapp).
@@ -241,6 +281,13 @@ ovs_status ovs_workspace_size(ovs_lattice lat, ovs_deflation defl, int32_t n_def
  *            (150 iterations) while above its target is stopped there and solved
  *            again with FP64 storage (info.escalated); FP32 rounding of the
  *            stored vectors can stall the recurrence for an individual source.
+ *   workspace, ws_bytes : device memory the caller owns for this call
+ *            (e.g. from torch's caching allocator), at least
+ *            ovs_workspace_size bytes (OVS_ERR_ARG otherwise), used only
+ *            during the call; or NULL for the handle's cached workspace
+ *            (ovs_workspace_held).  On an OVS_F32_STORE lattice with tol, the
+ *            caller's workspace serves the FP32 group; the FP64 group and the
+ *            gather of a partial group use the handle's own memory.
  *   info   : host [nrhs] result records, or NULL.
  * Batches of 8 or more sources run as two halves at the same time, on the
  * handle's stream and on a second internal stream (each half with the whole
@@ -261,7 +308,8 @@ ovs_status ovs_workspace_size(ovs_lattice lat, ovs_deflation defl, int32_t n_def
  * Returns the most severe per-source warning, or an error. */
 ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, const void* b,
                           void* y, int32_t nrhs, int32_t k_max, const double* tol,
-                          ovs_method method, int32_t flags, ovs_rhs_info* info);
+                          ovs_method method, int32_t flags, void* workspace, size_t ws_bytes,
+                          ovs_rhs_info* info);
 
 /* Gradient of L = sum_r Re <chi_r, y_r>, where y_r = |b_r| V_k sgn(G_k) e_1 is
  * the two-sided Lanczos approximation of sgn(gamma5 Dw(mu)) b_r (Section 4,
@@ -284,16 +332,24 @@ ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, c
  *   grad_U   : device complex128 [V][4][3][3] (link layout), summed over sources.
  *   quad_err : host double [nrhs], or NULL: relative change of the quadrature
  *              (x and the Jacobian band) between its last two step sizes.
+ *   workspace, ws_bytes : caller device memory for this call, at least
+ *              ovs_vjp_workspace_size bytes (OVS_ERR_ARG otherwise), or NULL for
+ *              the handle's cached workspace.
  * Needs an OVS_F64 lattice (OVS_ERR_ARG otherwise) and FP64 workspace of about
  * (4k/c + 2c + 22) nrhs fields with c = ceil(sqrt k), or (2k + 18) nrhs with
- * OVS_VJP_STORE_BASIS, kept in the handle's cache (OVS_ERR_ALLOC if it does
- * not fit).  Returns OVS_WARN_BREAKDOWN, writing no output, when a
+ * OVS_VJP_STORE_BASIS (OVS_ERR_ALLOC if the handle's cache cannot grow to it).
+ * Returns OVS_WARN_BREAKDOWN, writing no output, when a
  * source breaks down before k iterations; OVS_WARN_SIGN_AMBIGUOUS, with all
  * outputs written, when the quadrature changed by more than 1e-6 between its
  * two finest steps. */
 ovs_status ovs_sign_apply_vjp(ovs_lattice lat, const void* b, const void* chi, int32_t nrhs,
                               int32_t k, int32_t flags, void* y, void* grad_b, double* grad_mu,
-                              void* grad_U, double* quad_err);
+                              void* grad_U, double* quad_err, void* workspace, size_t ws_bytes);
+
+/* Bytes of caller workspace an ovs_sign_apply_vjp call with these arguments
+ * needs.  No device work; OVS_ERR_ARG as for ovs_sign_apply_vjp. */
+ovs_status ovs_vjp_workspace_size(ovs_lattice lat, int32_t nrhs, int32_t k, int32_t flags,
+                                  size_t* bytes);
 
 /* Krylov coefficients of the last ovs_sign_apply on this handle (2sL only):
  * alpha, gamma host complex128 [nrhs][k_max], beta host double [nrhs][k_max],

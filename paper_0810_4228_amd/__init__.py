@@ -38,6 +38,7 @@ OVS_FLAG_OVERLAP = 8
 OVS_FLAG_NO_SPLIT = 16
 OVS_FLAG_PERSISTENT = 32
 OVS_VJP_STORE_BASIS = 1
+OVS_DEBUG_CHECKS = 1
 
 EXPORTED = [
     "ovs_lattice_create", "ovs_lattice_destroy", "ovs_set_links", "ovs_set_params", "ovs_apply",
@@ -45,7 +46,7 @@ EXPORTED = [
     "ovs_field_apply", "ovs_field_apply_timed", "ovs_dual_apply_timed", "ovs_autotune", "ovs_get_tuning", "ovs_get_tuning_ex", "ovs_set_tuning_ex",
     "ovs_deflation_set", "ovs_deflation_compute", "ovs_deflation_get", "ovs_deflation_destroy", "ovs_workspace_size", "ovs_sign_apply", "ovs_sign_apply_vjp", "ovs_link_force", "ovs_overlap_eigs", "ovs_last_coefficients",
     "ovs_inner_sign_tridiag", "ovs_inner_sign_hessenberg", "ovs_small_eig", "ovs_status_string", "ovs_last_error",
-    "ovs_apply_noalloc",
+    "ovs_apply_noalloc", "ovs_set_debug", "ovs_workspace_held", "ovs_vjp_workspace_size",
 ]
 
 
@@ -74,6 +75,10 @@ class RhsInfo(ctypes.Structure):
         ("t_combine_ms", ctypes.c_double),
         ("fp64", ctypes.c_int32),
         ("escalated", ctypes.c_int32),
+        ("min_abs_delta", ctypes.c_double),
+        ("biorth_err", ctypes.c_double),
+        ("ritz_min_re", ctypes.c_double),
+        ("inner_check_err", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -101,8 +106,9 @@ def load():
     sig = {
         "ovs_lattice_create": [IP, IP, I, P, ctypes.POINTER(P)],
         "ovs_lattice_destroy": [P],
-        "ovs_set_links": [P, P],
+        "ovs_set_links": [P, P, I],
         "ovs_set_params": [P, D, D],
+        "ovs_set_debug": [P, I, I],
         "ovs_apply": [P, I, P, P, I],
         "ovs_apply_noalloc": [P, I, P, P, I],
         "ovs_field_create": [P, I, ctypes.POINTER(P)],
@@ -120,8 +126,10 @@ def load():
         "ovs_deflation_destroy": [P],
         "ovs_deflation_compute": [P, I, D, I, ctypes.POINTER(P)],
         "ovs_deflation_get": [P, DP, P, P, DP],
-        "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, ctypes.POINTER(RhsInfo)],
-        "ovs_sign_apply_vjp": [P, P, P, I, I, I, P, P, DP, P, DP],
+        "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, P, ctypes.c_size_t, ctypes.POINTER(RhsInfo)],
+        "ovs_workspace_held": [P, ctypes.POINTER(ctypes.c_size_t)],
+        "ovs_sign_apply_vjp": [P, P, P, I, I, I, P, P, DP, P, DP, P, ctypes.c_size_t],
+        "ovs_vjp_workspace_size": [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)],
         "ovs_overlap_eigs": [P, P, I, I, I, I, I, D, I, D, I, DP, P, DP],
         "ovs_link_force": [P, P, P, P],
         "ovs_workspace_size": [P, P, I, I, I, I, I, ctypes.POINTER(ctypes.c_size_t)],
@@ -207,13 +215,29 @@ class Lattice:
             pass
 
     def set_links(self, U):
+        """U: complex128 [V, 4, 3, 3] links, a CUDA tensor or a host numpy array."""
+        if isinstance(U, np.ndarray):
+            Uh = np.ascontiguousarray(U, dtype=np.complex128)
+            if Uh.size != self.V * 36:
+                raise ValueError("U must hold V*4*3*3 entries")
+            _check(self._lib.ovs_set_links(self._h, Uh.ctypes.data_as(ctypes.c_void_p), 0),
+                   "ovs_set_links")
+            return
         U = _dev_c128(U, "U")
         if U.numel() != self.V * 36:
             raise ValueError("U must hold V*4*3*3 entries")
-        _check(self._lib.ovs_set_links(self._h, ctypes.c_void_p(U.data_ptr())), "ovs_set_links")
+        _check(self._lib.ovs_set_links(self._h, ctypes.c_void_p(U.data_ptr()), 1), "ovs_set_links")
 
     def set_params(self, m_w, mu):
         _check(self._lib.ovs_set_params(self._h, float(m_w), float(mu)), "ovs_set_params")
+
+    def set_debug(self, checks=False, breakdown_at=-1):
+        """Diagnostics of later sign_apply calls (ovs_set_debug): checks=True
+        measures the 2sL biorthogonality and checks the inner sign against a
+        dense eigensolve (results in the info records); breakdown_at >= 0
+        forces delta = 0 in that iteration's beta step (a serious breakdown)."""
+        _check(self._lib.ovs_set_debug(self._h, OVS_DEBUG_CHECKS if checks else 0,
+                                       int(breakdown_at)), "ovs_set_debug")
 
     def _fields(self, x):
         x = _dev_c128(x, "x")
@@ -312,12 +336,20 @@ class Lattice:
                "ovs_workspace_size")
         return int(out.value)
 
+    def workspace_held(self):
+        """Bytes of device memory the handle holds for sign solves (ovs_workspace_held)."""
+        out = ctypes.c_size_t()
+        _check(self._lib.ovs_workspace_held(self._h, ctypes.byref(out)), "ovs_workspace_held")
+        return int(out.value)
+
     def sign_apply(self, b, k_max, defl=None, n_defl=None, tol=None, method="2sl",
                    two_pass=False, graph=False, overlap=False, out=None, split=True,
-                   persistent=False):
+                   persistent=False, workspace=None):
         """y = sgn(A) b (or D_ov b with overlap=True).  Returns (y, infos, status).
         split=False keeps a batch of 8 or more sources in one batch;
-        persistent=True runs the Lanczos iterations in persistent launches."""
+        persistent=True runs the Lanczos iterations in persistent launches.
+        workspace: a CUDA tensor (any dtype, contiguous) the call uses as its
+        workspace (at least workspace_size bytes), or None for the handle's own."""
         torch = _torch()
         b, nrhs = self._fields(b)
         y = torch.empty_like(b) if out is None else _dev_c128(out, "out")
@@ -332,9 +364,15 @@ class Lattice:
             tol_p = _dptr(tol_arr)
         dh = defl._h if defl is not None else None
         nd = (defl.m if n_defl is None else int(n_defl)) if defl is not None else 0
+        ws_p, ws_n = None, 0
+        if workspace is not None:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous CUDA tensor")
+            ws_p = ctypes.c_void_p(workspace.data_ptr())
+            ws_n = workspace.numel() * workspace.element_size()
         st = self._lib.ovs_sign_apply(self._h, dh, nd, ctypes.c_void_p(b.data_ptr()),
                                       ctypes.c_void_p(y.data_ptr()), nrhs, int(k_max), tol_p,
-                                      METHODS[method], flags, infos)
+                                      METHODS[method], flags, ws_p, ctypes.c_size_t(ws_n), infos)
         _check(st, "ovs_sign_apply")
         return y, [i.as_dict() for i in infos], st
 
@@ -385,7 +423,15 @@ class Lattice:
         return lam_c, vecs, {"max_residual": info[0], "restarts": int(info[1]),
                              "sign_solves": int(info[2]), "inner_warnings": int(info[3])}, st
 
-    def sign_apply_vjp(self, b, chi, k, want_y=True, store_basis=False):
+    def vjp_workspace_size(self, nrhs, k, store_basis=False):
+        """Bytes of caller workspace a sign_apply_vjp call needs."""
+        out = ctypes.c_size_t()
+        _check(self._lib.ovs_vjp_workspace_size(self._h, int(nrhs), int(k),
+                                                OVS_VJP_STORE_BASIS if store_basis else 0,
+                                                ctypes.byref(out)), "ovs_vjp_workspace_size")
+        return int(out.value)
+
+    def sign_apply_vjp(self, b, chi, k, want_y=True, store_basis=False, workspace=None):
         """Gradient of L = sum_r Re <chi_r, y_r> for the k-step two-sided Lanczos
         y_r ~ sgn(A) b_r without deflation (FP64 lattices).  The reverse sweep
         recomputes the Lanczos vectors from checkpoints unless store_basis.
@@ -400,12 +446,18 @@ class Lattice:
         gU = torch.empty((self.V, 4, 3, 3), dtype=torch.complex128, device=b.device)
         gmu = ctypes.c_double(0.0)
         qerr = np.zeros(nrhs, dtype=np.float64)
+        ws_p, ws_n = None, 0
+        if workspace is not None:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous CUDA tensor")
+            ws_p = ctypes.c_void_p(workspace.data_ptr())
+            ws_n = workspace.numel() * workspace.element_size()
         st = self._lib.ovs_sign_apply_vjp(
             self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(chi.data_ptr()), nrhs, int(k),
             OVS_VJP_STORE_BASIS if store_basis else 0,
             ctypes.c_void_p(y.data_ptr()) if y is not None else None,
             ctypes.c_void_p(gb.data_ptr()), ctypes.byref(gmu), ctypes.c_void_p(gU.data_ptr()),
-            _dptr(qerr))
+            _dptr(qerr), ws_p, ctypes.c_size_t(ws_n))
         _check(st, "ovs_sign_apply_vjp")
         if st == OVS_WARN_BREAKDOWN:
             raise OvsError(st, "ovs_sign_apply_vjp")

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -147,6 +148,7 @@ constexpr double kHStart = 0.25, kHMin = 1.0 / 64;
 // the sign is ambiguous there (sgn(z) = sgn(Re z) jumps across the axis).
 constexpr double kQuadAccept = 3e-7;
 constexpr int kProbe = 512;           // sampled entries per source for the convergence estimate
+constexpr int kBasisFirst = 256;      // first capacity (vectors) of a growable one-pass basis
 constexpr int kCheckEvery = 25;       // iterations between convergence checks
 constexpr int kStallChecks = 6;       // checks without the estimate halving: FP32 stall
 
@@ -323,6 +325,7 @@ static void destroy_shadow(ovs_lattice_s* l) {
   ovs_lattice_s* sh = l->shadow64;
   if (!sh) return;
   if (sh->ws) (void)hipFree(sh->ws);
+  if (sh->bbuf) (void)hipFree(sh->bbuf);
   (void)hipEventDestroy(sh->ev_in);
   (void)hipEventDestroy(sh->ev_out);
   delete sh;  // links (the parent's links64) and stream belong to the parent
@@ -334,6 +337,7 @@ static void destroy_worker(ovs_lattice_s* l) {
   if (!w) return;
   (void)hipStreamSynchronize(w->stream);
   if (w->ws) (void)hipFree(w->ws);
+  if (w->bbuf) (void)hipFree(w->bbuf);
   (void)hipEventDestroy(w->ev_in);
   (void)hipEventDestroy(w->ev_out);
   (void)hipStreamDestroy(w->stream);
@@ -351,6 +355,7 @@ ovs_status ovs_lattice_destroy(ovs_lattice l) {
   if (l->links) (void)hipFree(l->links);
   if (l->links64) (void)hipFree(l->links64);
   if (l->ws) (void)hipFree(l->ws);
+  if (l->bbuf) (void)hipFree(l->bbuf);
   (void)hipEventDestroy(l->ev_in);
   (void)hipEventDestroy(l->ev_out);
   (void)hipStreamDestroy(l->stream);
@@ -358,10 +363,34 @@ ovs_status ovs_lattice_destroy(ovs_lattice l) {
   return OVS_OK;
 }
 
-ovs_status ovs_set_links(ovs_lattice l, const void* U) {
+ovs_status ovs_set_links(ovs_lattice l, const void* U, int32_t on_device) {
   if (!l || !U) return OVS_ERR_ARG;
   StreamScope sc(l);
-  launch_pack_links((const double2*)U, l->links, l->prec == OVS_F32_STORE, l->g, l->bc, l->stream);
+  const double2* src = (const double2*)U;
+  void* tmp = nullptr;
+  if (!on_device) {
+    const size_t bytes = 36ul * l->g.V * sizeof(double2);
+    if (hipMalloc(&tmp, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return OVS_ERR_ALLOC;
+    }
+    if (hipMemcpyAsync(tmp, U, bytes, hipMemcpyHostToDevice, l->stream) != hipSuccess) {
+      (void)hipFree(tmp);
+      return OVS_ERR_HIP;
+    }
+    src = (const double2*)tmp;
+  }
+  struct TmpFree {
+    void* p;
+    hipStream_t s;
+    ~TmpFree() {
+      if (p) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(p);
+      }
+    }
+  } tf{tmp, l->stream};
+  launch_pack_links(src, l->links, l->prec == OVS_F32_STORE, l->g, l->bc, l->stream);
   if (l->prec == OVS_F32_STORE) {
     if (!l->links64 &&
         hipMalloc(&l->links64, 4ul * kLinkSlots * l->g.Vs * sizeof(double2)) != hipSuccess) {
@@ -369,7 +398,7 @@ ovs_status ovs_set_links(ovs_lattice l, const void* U) {
       l->links64 = nullptr;
       return OVS_ERR_ALLOC;
     }
-    launch_pack_links((const double2*)U, l->links64, false, l->g, l->bc, l->stream);
+    launch_pack_links(src, l->links64, false, l->g, l->bc, l->stream);
   }
   OVS_HIP(hipGetLastError());
   l->links_set = true;
@@ -382,6 +411,13 @@ ovs_status ovs_set_params(ovs_lattice l, double m_w, double mu) {
   l->m_w = m_w;
   l->mu = mu;
   l->params_set = true;
+  return OVS_OK;
+}
+
+ovs_status ovs_set_debug(ovs_lattice l, int32_t flags, int32_t breakdown_at) {
+  if (!l || l->parent || (flags & ~OVS_DEBUG_CHECKS) || breakdown_at < -1) return OVS_ERR_ARG;
+  l->debug_flags = flags;
+  l->debug_breakdown_at = breakdown_at;
   return OVS_OK;
 }
 
@@ -905,10 +941,13 @@ ovs_status ovs_deflation_destroy(ovs_deflation d) {
 // whole batch when this call runs one part of it).
 // ws_bytes: if not NULL, only the workspace this call needs is computed and
 // stored there (b, y, tol and info are not used).
+// user_ws: the caller's workspace for this call (user_ws_bytes of it), or
+// NULL for the handle's cached workspace.
 static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
                                   const void* b, void* y, int32_t nrhs, int32_t k_max,
                                   const double* tol, ovs_method method, int32_t flags,
-                                  ovs_rhs_info* info, int tune_key, size_t* ws_bytes = nullptr) {
+                                  ovs_rhs_info* info, int tune_key, size_t* ws_bytes = nullptr,
+                                  void* user_ws = nullptr, size_t user_ws_bytes = 0) {
   if (!l || (!ws_bytes && (!b || !y || b == y)) || nrhs < 1 || nrhs > kMaxNrhs || k_max < 1)
     return OVS_ERR_ARG;
   if (!ws_bytes && !ready(l)) return OVS_ERR_STATE;  // sizing needs no links
@@ -936,6 +975,10 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   const size_t es = elem_bytes(l);
   const int K = k_max, nr = nrhs;
   const int nslots = two_pass ? 3 : K;
+  // One-pass 2sL in the handle's workspace keeps the basis in its own buffer,
+  // grown in doubling steps as the iteration needs it (not sized by k_max up
+  // front); in a caller's workspace it is laid out for k_max.
+  const bool grow = !ws_bytes && !user_ws && !two_pass && !arn;
   const int nwg_d = dual_num_wg(l->g), nwg_u = update_nwg(N);
   const int nwave_max = isign_tri_nwave(max_nodes());
   const int nq_chunk = std::min(kIsignHessChunk, 2 * max_nodes());
@@ -947,13 +990,15 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     char *basis, *wbuf, *T, *S;
     double *part1, *part2, *dpart, *CD, *spart, *sums, *sumsb, *nb;
     double2 *alpha, *gamma, *sw, *coef, *x, *mult, *part, *H, *hcur, *ys, *acc, *xtmp;
-    double *beta, *sv, *tnorm2, *qerr, *red, *apart, *red_n, *red_tn, *scl;
+    double *beta, *sv, *tnorm2, *qerr, *red, *apart, *red_n, *red_tn, *scl, *dnorm;
     int *kstop, *status, *rhs_map, *ints, *kused, *pidx, *kv;
     unsigned char* swp;
     double2 *probes, *yp;
     unsigned* bar;
   } B{};
   const bool probing = tol != nullptr;
+  const bool debug = (l->debug_flags & OVS_DEBUG_CHECKS) != 0;
+  const bool monitor = debug && !arn && !two_pass;  // biorthogonality rows need the stored V
   const int P = (int)std::min<long>(kProbe, 12L * l->g.V);
   auto layout = [&](Arena& a) {
     B.Bq = a.take<double2>((size_t)nr * N);
@@ -965,7 +1010,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       B.CD = a.take<double>((size_t)m * nr * 4);
     }
     B.Y = a.take<double2>((size_t)nr * N);
-    B.basis = a.take<char>((size_t)nslots * nr * N * es);
+    if (!grow) B.basis = a.take<char>((size_t)nslots * nr * N * es);
     if (!arn) B.wbuf = a.take<char>(3ul * nr * N * es);
     B.T = a.take<char>((size_t)nr * N * es);
     if (!arn) B.S = a.take<char>((size_t)nr * N * es);
@@ -1002,6 +1047,11 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       B.mult = a.take<double2>((size_t)nr * wchunk * K * 64);
       B.swp = a.take<unsigned char>((size_t)nr * wchunk * K * 64);
       B.part = a.take<double2>((size_t)nr * nwave_max * 2 * K);
+      B.dnorm = a.take<double>((size_t)nr * K);
+      if (monitor) {
+        B.red = a.take<double>((size_t)nr * K * 2);
+        B.apart = a.take<double>((size_t)nr * K * nch_arn * 2);
+      }
     } else {
       B.H = a.take<double2>((size_t)nr * K * K);
       B.hcur = a.take<double2>((size_t)nr * K);
@@ -1021,10 +1071,54 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       *ws_bytes = sizing.off + 4096;
       return OVS_OK;
     }
-    ovs_status st = ensure_ws(l, sizing.off + 4096);
-    if (st != OVS_OK) return st;
-    Arena real{(char*)l->ws};
+    char* base;
+    if (user_ws) {
+      if (user_ws_bytes < sizing.off + 4096) return OVS_ERR_ARG;
+      base = (char*)(((uintptr_t)user_ws + 255) & ~uintptr_t(255));
+    } else {
+      ovs_status st = ensure_ws(l, sizing.off + 4096);
+      if (st != OVS_OK) return st;
+      base = (char*)l->ws;
+    }
+    Arena real{base};
     layout(real);
+  }
+  // growable basis (grow): capacity in vectors, the handle's cached buffer
+  const size_t vec_bytes = (size_t)nr * N * es;
+  int cap = 0;
+  bool basis_moved = false;  // set when a graph captured the old address
+  auto ensure_basis = [&](int need) -> ovs_status {
+    need = std::min(need, K);
+    if (!grow || need <= cap) return OVS_OK;
+    const int held = (int)std::min<size_t>(l->bbuf_bytes / vec_bytes, (size_t)K);
+    if (cap == 0 && held >= need) {  // the cached buffer of an earlier call
+      cap = held;
+      B.basis = (char*)l->bbuf;
+      return OVS_OK;
+    }
+    int ncap = cap == 0 ? std::max(need, std::min(K, kBasisFirst)) : std::max(need, 2 * cap);
+    ncap = std::min(ncap, K);
+    void* nb = nullptr;
+    if (hipMalloc(&nb, (size_t)ncap * vec_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return OVS_ERR_ALLOC;
+    }
+    if (cap > 0) {
+      OVS_HIP(hipMemcpyAsync(nb, B.basis, (size_t)cap * vec_bytes, hipMemcpyDeviceToDevice,
+                             l->stream));
+      basis_moved = true;
+    }
+    OVS_HIP(hipStreamSynchronize(l->stream));
+    if (l->bbuf) (void)hipFree(l->bbuf);
+    l->bbuf = nb;
+    l->bbuf_bytes = (size_t)ncap * vec_bytes;
+    B.basis = (char*)nb;
+    cap = ncap;
+    return OVS_OK;
+  };
+  {
+    ovs_status st = ensure_basis(kBasisFirst);
+    if (st != OVS_OK) return st;
   }
   if (m == 0) {
     B.bR = B.Bq;
@@ -1099,6 +1193,98 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     if (arn) OVS_HIP(hipMemsetAsync(B.H, 0, sizeof(double2) * nr * K * K, s));
   }
   CoefArrays co{B.alpha, B.beta, B.gamma, B.sv, B.sw, B.tnorm2, B.kstop, B.status, K};
+  if (!arn) {
+    co.dnorm = B.dnorm;
+    co.inject_plus1 = l->debug_breakdown_at >= 0 ? l->debug_breakdown_at + 1 : 0;
+    // all-ones bytes: NaN marks the beta steps that did not run
+    OVS_HIP(hipMemsetAsync(B.dnorm, 0xFF, sizeof(double) * nr * K, s));
+  }
+  std::vector<double> biorth(nr, -1.0);
+  // Biorthogonality row of w_i against the stored v_0..v_i (Section 4:
+  // W^dagger V = I in exact arithmetic): max_m |w_i^dagger v_m - delta_mi|,
+  // from the dot products V~_m^dagger W~_i and the scales sv, sw.
+  auto biorth_row = [&](int i) -> ovs_status {
+    const int nv = i + 1;
+    launch_arn_dots(f32, B.basis, bstride, B.wbuf + (size_t)(i % 3) * bstride * es, N, nv, nr,
+                    B.apart, B.red, s);
+    std::vector<double> red((size_t)nr * nv * 2), svh((size_t)nr * (K + 1)),
+        swh((size_t)nr * (K + 1) * 2);
+    std::vector<int> kst(nr);
+    OVS_HIP(hipMemcpyAsync(kst.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipMemcpyAsync(red.data(), B.red, red.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipMemcpyAsync(svh.data(), B.sv, svh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipMemcpyAsync(swh.data(), B.sw, swh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    OVS_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < nr; ++r) {
+      if (done[r] || i >= kst[r]) continue;  // w_i of this source was not formed
+      const double swr = swh[((size_t)r * (K + 1) + i) * 2], swi = swh[((size_t)r * (K + 1) + i) * 2 + 1];
+      double e = 0.0;
+      for (int m = 0; m < nv; ++m) {
+        // w_i^dagger v_m = conj(sw_i) sv_m conj(V~_m^dagger W~_i)
+        const double dr = red[((size_t)r * nv + m) * 2], di = -red[((size_t)r * nv + m) * 2 + 1];
+        const double svm = svh[(size_t)r * (K + 1) + m];
+        double re = svm * (swr * dr + swi * di), im = svm * (swr * di - swi * dr);
+        if (m == i) re -= 1.0;
+        e = std::max(e, std::hypot(re, im));
+      }
+      biorth[r] = std::max(biorth[r], e);
+    }
+    return OVS_OK;
+  };
+  std::vector<double> ritz_re(nr, -1.0), inner_chk(nr, -1.0);
+  // Dense check of the inner sign (debug): eigenvalues of G_k (or H_k) on the
+  // host, the spectral sgn(G_k) e_1 of eq. (1.3) against the quadrature's x.
+  auto debug_inner = [&](bool tri) -> ovs_status {
+    std::vector<double> xh((size_t)nr * K * 2), ah, bh, gh, hh;
+    OVS_HIP(hipMemcpyAsync(xh.data(), B.x, xh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (tri) {
+      ah.resize((size_t)nr * K * 2);
+      bh.resize((size_t)nr * K);
+      gh.resize((size_t)nr * K * 2);
+      OVS_HIP(hipMemcpyAsync(ah.data(), B.alpha, ah.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      OVS_HIP(hipMemcpyAsync(bh.data(), B.beta, bh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      OVS_HIP(hipMemcpyAsync(gh.data(), B.gamma, gh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    } else {
+      hh.resize((size_t)nr * K * K * 2);
+      OVS_HIP(hipMemcpyAsync(hh.data(), B.H, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    OVS_HIP(hipStreamSynchronize(s));
+    using cd = std::complex<double>;
+    for (int r = 0; r < nr; ++r) {
+      const int k = kused[r];
+      if (k <= 0) continue;
+      std::vector<cd> G((size_t)k * k, cd(0, 0)), lam(k), Vv((size_t)k * k);
+      for (int c = 0; c < k; ++c)
+        for (int rr = 0; rr < k; ++rr) {
+          if (tri) {
+            const size_t b0 = (size_t)r * K;
+            if (rr == c) G[rr + (size_t)k * c] = cd(ah[(b0 + c) * 2], ah[(b0 + c) * 2 + 1]);
+            else if (rr == c + 1) G[rr + (size_t)k * c] = cd(bh[b0 + c], 0.0);
+            else if (rr + 1 == c) G[rr + (size_t)k * c] = cd(gh[(b0 + rr) * 2], gh[(b0 + rr) * 2 + 1]);
+          } else {
+            const size_t e = ((size_t)r * K + c) * K + rr;
+            G[rr + (size_t)k * c] = cd(hh[e * 2], hh[e * 2 + 1]);
+          }
+        }
+      if (dense::eig(k, G.data(), lam.data(), Vv.data()) != 0) continue;
+      double mre = HUGE_VAL;
+      for (int q = 0; q < k; ++q) mre = std::min(mre, std::abs(lam[q].real()) / std::abs(lam[q]));
+      ritz_re[r] = mre;
+      std::vector<cd> Vi(Vv);
+      if (dense::inverse(k, Vi.data()) != 0) continue;
+      double dn = 0.0, xn = 0.0;
+      for (int rr = 0; rr < k; ++rr) {
+        cd acc(0, 0);
+        for (int q = 0; q < k; ++q)
+          acc += Vv[rr + (size_t)k * q] * (lam[q].real() >= 0.0 ? 1.0 : -1.0) * Vi[q];  // row q, col 0
+        const cd xg(xh[((size_t)r * K + rr) * 2], xh[((size_t)r * K + rr) * 2 + 1]);
+        dn += std::norm(xg - acc);
+        xn += std::norm(acc);
+      }
+      inner_chk[r] = xn > 0 ? std::sqrt(dn / xn) : 0.0;
+    }
+    return OVS_OK;
+  };
 
   std::vector<double> est(nr, 0.0), qerr(nr, 0.0);
   // stall tracking (FP32 storage): best estimate so far, checks since it halved
@@ -1176,10 +1362,21 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     std::vector<std::vector<double>> xprev(nr);
     int i = 0;
     while (i < K && !amap.empty()) {
-      const int iend = tol ? std::min(K, (i / chunk + 1) * chunk) : K;
+      const int iend = (tol || monitor) ? std::min(K, (i / chunk + 1) * chunk) : K;
       // full iterations are those with i < K-1; the last one only forms alpha
       int nfull = std::min(iend, K - 1) - i;
       if (nfull < 0) nfull = 0;
+      // iteration j writes basis vector j + 1
+      st = ensure_basis(std::min(iend, K - 1) + 1);
+      if (st != OVS_OK) return st;
+      if (basis_moved) {  // the captured graph holds the old basis address
+        da.basis = B.basis;
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        basis_moved = false;
+      }
       int done_it = 0;
       while (use_persist && done_it < nfull) {
         const int n = std::min(chunk, nfull - done_it);
@@ -1216,6 +1413,10 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
         if (st != OVS_OK) return st;
       }
       i = iend;
+      if (monitor) {
+        st = biorth_row(std::min(i, K - 1));
+        if (st != OVS_OK) return st;
+      }
       if (tol && i < K) {
         // convergence check at k = i (the paper gives no stopping rule): the
         // relative change of y on the sampled entries since the previous check
@@ -1291,6 +1492,10 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
                     qtarget, errh);
     if (st != OVS_OK) return st;
     qerr = errh;
+    if (debug) {
+      st = debug_inner(true);
+      if (st != OVS_OK) return st;
+    }
     OVS_HIP(hipEventRecord(ev[3], s));
     launch_make_coef(B.x, B.sv, B.nb, K, nr, B.coef, s);
     if (!two_pass) {
@@ -1418,6 +1623,10 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
                                B.qerr, qtarget, errh);
     if (st != OVS_OK) return st;
     qerr = errh;
+    if (debug) {
+      st = debug_inner(false);
+      if (st != OVS_OK) return st;
+    }
     OVS_HIP(hipEventRecord(ev[3], s));
     launch_make_coef(B.x, nullptr, B.nb, K, nr, B.coef, s);
     launch_combine(f32, B.basis, bstride, N, B.coef, K, B.kused, B.yex, B.Y, nr, s);
@@ -1433,11 +1642,25 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
   (void)hipEventElapsedTime(&t23, ev[2], ev[3]);
   (void)hipEventElapsedTime(&t34, ev[3], ev[4]);
+  std::vector<double> mind(nr, -1.0);
+  if (!arn) {
+    std::vector<double> dn((size_t)nr * K);
+    OVS_HIP(hipMemcpy(dn.data(), B.dnorm, dn.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int r = 0; r < nr; ++r) {
+      double mn = HUGE_VAL;
+      for (int i = 0; i < K; ++i) {
+        const double d = dn[(size_t)r * K + i];
+        if (!std::isnan(d)) mn = std::min(mn, d);
+      }
+      if (mn != HUGE_VAL) mind[r] = mn;
+    }
+  }
   ovs_status worst = OVS_OK;
   for (int r = 0; r < nr; ++r) {
     int rs = OVS_OK;
     if (hstatus[r] == 2) rs = OVS_WARN_BREAKDOWN;
     else if (kused[r] > 0 && !(qerr[r] <= qtarget[r])) rs = OVS_WARN_SIGN_AMBIGUOUS;
+    else if (debug && ritz_re[r] >= 0.0 && ritz_re[r] <= 1e-12) rs = OVS_WARN_SIGN_AMBIGUOUS;
     else if (tol && (!done[r] || stalled[r]) && hstatus[r] == 0) rs = OVS_WARN_NOT_CONVERGED;
     if (rs > worst) worst = rs;
     if (info) {
@@ -1452,6 +1675,10 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       info[r].t_krylov_ms = t12;
       info[r].t_inner_ms = t23;
       info[r].t_combine_ms = t34;
+      info[r].min_abs_delta = mind[r];
+      info[r].biorth_err = biorth[r];
+      info[r].ritz_min_re = ritz_re[r];
+      info[r].inner_check_err = inner_chk[r];
     }
   }
   return worst;
@@ -1499,18 +1726,35 @@ static ovs_status worker_ready(ovs_lattice_s* l) {
   w->params_set = l->params_set;
   w->tuning = l->tuning;
   w->dual_tuning = l->dual_tuning;
+  w->debug_flags = l->debug_flags;
+  w->debug_breakdown_at = l->debug_breakdown_at;
   return OVS_OK;
 }
 
+// ws, ws_bytes: the caller's workspace (NULL: the handles' cached ones); a
+// split batch lays its halves out one after the other in it.
 static ovs_status run_batch(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
                             void* y, int32_t nrhs, int32_t k_max, const double* tol,
-                            ovs_method method, int32_t flags, ovs_rhs_info* info) {
+                            ovs_method method, int32_t flags, ovs_rhs_info* info,
+                            void* ws = nullptr, size_t ws_bytes = 0) {
   if (nrhs < kSplitMin || (flags & (OVS_FLAG_NO_SPLIT | OVS_FLAG_PERSISTENT)))
-    return sign_apply_impl(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info, nrhs);
+    return sign_apply_impl(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info, nrhs,
+                           nullptr, ws, ws_bytes);
   if (!ready(l)) return OVS_ERR_STATE;
   ovs_status st = worker_ready(l);
   if (st != OVS_OK) return st;
   const int n1 = nrhs / 2, n2 = nrhs - n1;
+  void* ws2 = nullptr;
+  size_t ws1_bytes = 0, ws2_bytes = 0;
+  if (ws) {
+    const std::vector<double> tols(nrhs, 1.0);
+    st = sign_apply_impl(l, defl, n_defl, nullptr, nullptr, n1, k_max, tols.data(), method,
+                         flags, nullptr, nrhs, &ws1_bytes);
+    if (st != OVS_OK) return st;
+    if (ws1_bytes > ws_bytes) return OVS_ERR_ARG;
+    ws2 = (char*)ws + ws1_bytes;
+    ws2_bytes = ws_bytes - ws1_bytes;
+  }
   const size_t fb = 12ul * l->g.V * sizeof(double2);
   // the second half reads b on the worker stream: order it after the caller's
   // stream (the worker's StreamScope) and after everything already enqueued
@@ -1526,11 +1770,11 @@ static ovs_status run_batch(ovs_lattice l, ovs_deflation defl, int32_t n_defl, c
     }
     st2 = sign_apply_impl(l->worker, defl, n_defl, (const char*)b + n1 * fb, (char*)y + n1 * fb,
                           n2, k_max, tol ? tol + n1 : nullptr, method, flags,
-                          info ? info + n1 : nullptr, nrhs);
+                          info ? info + n1 : nullptr, nrhs, nullptr, ws2, ws2_bytes);
     if (st2 < 0) err2 = g_last_error;
   });
-  const ovs_status st1 =
-      sign_apply_impl(l, defl, n_defl, b, y, n1, k_max, tol, method, flags, info, nrhs);
+  const ovs_status st1 = sign_apply_impl(l, defl, n_defl, b, y, n1, k_max, tol, method, flags,
+                                         info, nrhs, nullptr, ws, ws1_bytes);
   second.join();
   if (st2 < 0 && st1 >= 0) snprintf(g_last_error, sizeof(g_last_error), "%s", err2.c_str());
   if (st1 < 0) return st1;
@@ -1571,6 +1815,8 @@ static ovs_status shadow_ready(ovs_lattice_s* l) {
   sh->mu = l->mu;
   sh->links_set = l->links_set;
   sh->params_set = l->params_set;
+  sh->debug_flags = l->debug_flags;
+  sh->debug_breakdown_at = l->debug_breakdown_at;
   return OVS_OK;
 }
 
@@ -1580,7 +1826,8 @@ static ovs_status shadow_ready(ovs_lattice_s* l) {
 static ovs_status solve_subset(ovs_lattice l, bool fp64, ovs_deflation defl, int32_t n_defl,
                                const void* b, void* y, int32_t nrhs, const std::vector<int>& idx,
                                int32_t k_max, const double* tol, ovs_method method,
-                               int32_t flags, ovs_rhs_info* inf) {
+                               int32_t flags, ovs_rhs_info* inf, void* ws = nullptr,
+                               size_t ws_bytes = 0) {
   const int n = (int)idx.size();
   std::vector<double> t(n);
   for (int j = 0; j < n; ++j) t[j] = tol[idx[j]];
@@ -1589,7 +1836,8 @@ static ovs_status solve_subset(ovs_lattice l, bool fp64, ovs_deflation defl, int
   if (n == nrhs) {
     st = fp64 ? sign_apply_impl(l->shadow64, defl, n_defl, b, y, n, k_max, t.data(), method,
                                 flags, rec.data(), n)
-              : run_batch(l, defl, n_defl, b, y, n, k_max, t.data(), method, flags, rec.data());
+              : run_batch(l, defl, n_defl, b, y, n, k_max, t.data(), method, flags, rec.data(), ws,
+                          ws_bytes);
   } else {
     const size_t fb = 12ul * l->g.V * sizeof(double2);
     const size_t need = 2 * (size_t)n * fb;
@@ -1611,7 +1859,8 @@ static ovs_status solve_subset(ovs_lattice l, bool fp64, ovs_deflation defl, int
                              hipMemcpyDeviceToDevice, l->stream));
     st = fp64 ? sign_apply_impl(l->shadow64, defl, n_defl, bb, yy, n, k_max, t.data(), method,
                                 flags, rec.data(), n)
-              : run_batch(l, defl, n_defl, bb, yy, n, k_max, t.data(), method, flags, rec.data());
+              : run_batch(l, defl, n_defl, bb, yy, n, k_max, t.data(), method, flags, rec.data(), ws,
+                          ws_bytes);
     if (st < 0) return st;
     for (int j = 0; j < n; ++j)
       OVS_HIP(hipMemcpyAsync((char*)y + idx[j] * fb, yy + j * fb, fb, hipMemcpyDeviceToDevice,
@@ -1643,10 +1892,13 @@ ovs_status ovs_workspace_size(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
 
 ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
                           void* y, int32_t nrhs, int32_t k_max, const double* tol,
-                          ovs_method method, int32_t flags, ovs_rhs_info* info) {
+                          ovs_method method, int32_t flags, void* workspace, size_t ws_bytes,
+                          ovs_rhs_info* info) {
   if (!l || !b || !y || b == y || nrhs < 1 || nrhs > kMaxNrhs || l->parent) return OVS_ERR_ARG;
+  if (!workspace) ws_bytes = 0;
   if (!tol || l->prec != OVS_F32_STORE)
-    return run_batch(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info);
+    return run_batch(l, defl, n_defl, b, y, nrhs, k_max, tol, method, flags, info, workspace,
+                     ws_bytes);
   // FP32-storage lattice with targets: the FP64 group (targets below the FP32
   // floor), the FP32 group, then the FP32 sources that stalled, again with
   // FP64 storage
@@ -1668,7 +1920,7 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
   }
   if (!hi.empty()) {
     st = solve_subset(l, false, defl, n_defl, b, y, nrhs, hi, k_max, tol, method, flags,
-                      inf.data());
+                      inf.data(), workspace, ws_bytes);
     if (st < 0) return st;
     std::vector<int> esc;
     for (int r : hi)
@@ -1686,6 +1938,16 @@ ovs_status ovs_sign_apply(ovs_lattice l, ovs_deflation defl, int32_t n_defl, con
   for (int r = 0; r < nrhs; ++r) worst = std::max(worst, (ovs_status)inf[r].status);
   if (info) std::copy(inf.begin(), inf.end(), info);
   return worst;
+}
+
+ovs_status ovs_workspace_held(ovs_lattice l, size_t* bytes) {
+  if (!l || !bytes || l->parent) return OVS_ERR_ARG;
+  size_t b = 0;
+  for (const ovs_lattice_s* h : {(const ovs_lattice_s*)l, (const ovs_lattice_s*)l->worker,
+                                 (const ovs_lattice_s*)l->shadow64})
+    if (h) b += h->ws_bytes + h->bbuf_bytes + h->split_bytes;
+  *bytes = b;
+  return OVS_OK;
 }
 
 ovs_status ovs_last_coefficients(ovs_lattice l, double* alpha, double* beta, double* gamma,

@@ -115,7 +115,11 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
   double2* thd = mem.alloc<double2>(nb);
   double* part = mem.alloc<double>((size_t)nb * 256);
   double* red = mem.alloc<double>(nb);
-  double2* Lkeep = mem.alloc<double2>((size_t)m * Np);
+  // left Ritz vectors kept for the pairing: the m wanted ones and the guard
+  // ones after them (a near-degenerate boundary pair can order differently on
+  // the two sides)
+  const int mkeep = std::min(nb, m + 4);
+  double2* Lkeep = mem.alloc<double2>((size_t)mkeep * Np);
   if (!Gd || !Cd || !thd || !part || !red || !Lkeep) return OVS_ERR_ALLOC;
 
   Handle bh;
@@ -276,7 +280,8 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
         maxres = std::max(maxres, std::sqrt(nn[j]) / std::max(std::abs(theta[j]), 1e-12));
       // keep the current best m Ritz vectors of this side
       double2* dst = dag ? Lkeep : Rout;
-      if (hipMemcpyAsync(dst, Rv, sizeof(double2) * (size_t)m * Np, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      if (hipMemcpyAsync(dst, Rv, sizeof(double2) * (size_t)(dag ? mkeep : m) * Np,
+                         hipMemcpyDeviceToDevice, s) != hipSuccess)
         return OVS_ERR_HIP;
       if (maxres <= tol) break;
     }
@@ -285,13 +290,14 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
     theta_side[side] = theta;
   }
 
-  // ---- pair left with right (lambda_L = conj(lambda_R)) ----
+  // ---- pair left with right (lambda_L = conj(lambda_R)), the left partner
+  // of each of the m right Ritz values searched among mkeep left ones ----
   std::vector<int> perm(m, -1);
-  std::vector<char> used(m, 0);
+  std::vector<char> used(mkeep, 0);
   for (int j = 0; j < m; ++j) {
     double best = 1e300;
     int bk = -1;
-    for (int k = 0; k < m; ++k) {
+    for (int k = 0; k < mkeep && k < (int)theta_side[1].size(); ++k) {
       if (used[k]) continue;
       const double d = std::abs(std::conj(theta_side[1][k]) - theta_side[0][j]);
       if (d < best) { best = d; bk = k; }

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <vector>
 
 #include "ovs_common.h"
@@ -50,15 +51,17 @@ double max_rel_change(const std::vector<double2>& a, const std::vector<double2>&
 
 }  // namespace
 
-extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const void* chi,
-                                         int32_t nrhs, int32_t k, int32_t flags, void* y,
-                                         void* grad_b, double* grad_mu, void* grad_U,
-                                         double* quad_err) {
-  if (!l || !b || !chi || !grad_b || !grad_mu || !grad_U) return OVS_ERR_ARG;
+// The vjp proper; with ws_query != NULL only the workspace it needs is
+// computed (the other pointers are not used).
+static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_t nrhs, int32_t k,
+                           int32_t flags, void* y, void* grad_b, double* grad_mu, void* grad_U,
+                           double* quad_err, void* user_ws, size_t user_ws_bytes,
+                           size_t* ws_query) {
+  if (!l || (!ws_query && (!b || !chi || !grad_b || !grad_mu || !grad_U))) return OVS_ERR_ARG;
   if (nrhs < 1 || nrhs > kMaxNrhs || k < 1 || k > 65535) return OVS_ERR_ARG;
   if (flags & ~OVS_VJP_STORE_BASIS) return OVS_ERR_ARG;
   if (l->prec != OVS_F64 || l->parent) return OVS_ERR_ARG;
-  if (!ready(l)) return OVS_ERR_STATE;
+  if (!ws_query && !ready(l)) return OVS_ERR_STATE;
   const bool store = (flags & OVS_VJP_STORE_BASIS) != 0;
   const Geometry& g = l->g;
   const long F = 12L * g.Vs;        // elements of one source field
@@ -118,10 +121,22 @@ extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const voi
   };
   Arena sizing{nullptr};
   carve(sizing);
-  ovs_status st = ensure_ws(l, sizing.off + 256);
-  if (st != OVS_OK) return st;
+  if (ws_query) {
+    *ws_query = sizing.off + 512;
+    return OVS_OK;
+  }
+  char* ws_base;
+  if (user_ws) {
+    if (user_ws_bytes < sizing.off + 512) return OVS_ERR_ARG;
+    ws_base = (char*)(((uintptr_t)user_ws + 255) & ~uintptr_t(255));
+  } else {
+    ovs_status st0 = ensure_ws(l, sizing.off + 256);
+    if (st0 != OVS_OK) return st0;
+    ws_base = (char*)l->ws;
+  }
+  ovs_status st = OVS_OK;
   StreamScope scope(l);
-  Arena arena{(char*)l->ws};
+  Arena arena{ws_base};
   carve(arena);
   double2** fld = P_.fld;
   double2 *B = fld[0], *CHI = fld[1], *T = fld[2], *Sv = fld[3];
@@ -371,4 +386,20 @@ extern "C" ovs_status ovs_link_force(ovs_lattice l, const void* U, const void* g
                     l->stream);
   OVS_HIP(hipGetLastError());
   return OVS_OK;
+}
+
+extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const void* chi,
+                                         int32_t nrhs, int32_t k, int32_t flags, void* y,
+                                         void* grad_b, double* grad_mu, void* grad_U,
+                                         double* quad_err, void* workspace, size_t ws_bytes) {
+  return vjp_impl(l, b, chi, nrhs, k, flags, y, grad_b, grad_mu, grad_U, quad_err, workspace,
+                  workspace ? ws_bytes : 0, nullptr);
+}
+
+extern "C" ovs_status ovs_vjp_workspace_size(ovs_lattice l, int32_t nrhs, int32_t k,
+                                             int32_t flags, size_t* bytes) {
+  if (!bytes) return OVS_ERR_ARG;
+  *bytes = 0;
+  return vjp_impl(l, nullptr, nullptr, nrhs, k, flags, nullptr, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, 0, bytes);
 }

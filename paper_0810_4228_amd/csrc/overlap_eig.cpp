@@ -353,7 +353,8 @@ extern "C" ovs_status ovs_overlap_eigs(ovs_lattice l, ovs_deflation defl, int32_
   // one application of D_ov to a block: a batched sign solve
   const BlockOp op = [&](const void* in, void* out, int n, int* warn) -> ovs_status {
     const ovs_status st = ovs_sign_apply(l, defl, n_defl, in, out, n, k_inner, tols.data(),
-                                         OVS_2SL, OVS_FLAG_OVERLAP | inner_flags, ri.data());
+                                         OVS_2SL, OVS_FLAG_OVERLAP | inner_flags, nullptr, 0,
+                                         ri.data());
     if (st >= 0)
       for (int i = 0; i < n; ++i) *warn += ri[i].status != OVS_OK;
     return st;

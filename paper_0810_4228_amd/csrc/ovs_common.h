@@ -73,6 +73,9 @@ struct CoefArrays {
   int* kstop;       // [nrhs] number of valid alpha (kmax if no breakdown)
   int* status;      // [nrhs] 0 ok, 1 lucky, 2 serious
   int kmax;
+  double* dnorm = nullptr;  // [nrhs][kmax] |delta_i| / (|v~| |w~|) of each beta step, or null
+  int inject_plus1 = 0;     // > 0: the beta step of iteration inject_plus1 - 1 takes delta
+                            // as zero (a serious breakdown forced from the host, for tests)
 };
 
 }  // namespace ovs
@@ -95,9 +98,15 @@ struct ovs_lattice_s {
   // tuned dual-stencil configuration per nrhs (wg unused: always 256)
   std::vector<std::pair<int, ovs::Tuning>> dual_tuning;
   int lds_max_kb = 64;          // largest dynamic LDS request the device accepts
+  // OVS_DEBUG_* flags and the iteration whose delta is forced to zero (-1: none)
+  int debug_flags = 0;
+  int debug_breakdown_at = -1;
   // cached workspace for sign_apply and apply
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // cached one-pass Lanczos basis (grown as a solve needs it)
+  void* bbuf = nullptr;
+  size_t bbuf_bytes = 0;
   // results of the last sign_apply (host copies) for diagnostics
   std::vector<double> last_alpha, last_beta, last_gamma, last_x;
   int last_nrhs = 0, last_kmax = 0;

@@ -72,7 +72,7 @@ void launch_scale_copy(bool f32, const void* T, void* out, long N, const double*
 // per source (mult, swp: [nrhs][kIsignWaveChunk][kmax][64]; part: [nrhs][all
 // waves][2][kmax]); the Hessenberg form kIsignHessChunk solves per source
 // (ys: [nrhs][kIsignHessChunk][kmax]; acc: [nrhs][2][kmax]).
-constexpr int kIsignWaveChunk = 48;
+constexpr int kIsignWaveChunk = 16;
 constexpr int kIsignHessChunk = 1024;
 int isign_tri_nwave(int nnode);
 void launch_isign_tri(const double2* alpha, const double* beta, const double2* gamma, int kmax,

@@ -172,8 +172,10 @@ __device__ __forceinline__ void beta_body(int jj, int i, const double* __restric
     const double tn = sqrt(co.tnorm2[slot * ks + i]);
     int st_ = co.status[slot];
     if (st_ == 0) {
+      const bool forced = co.inject_plus1 == i + 1;
+      if (co.dnorm) co.dnorm[slot * ks + i] = forced ? 0.0 : cabs1(delta) / (bn * wn);
       if (!(bn > 1e-14 * tn)) st_ = 1;
-      else if (!(cabs1(delta) > 1e-13 * bn * wn)) st_ = 2;
+      else if (forced || !(cabs1(delta) > 1e-13 * bn * wn)) st_ = 2;
       if (st_ != 0) {
         co.status[slot] = st_;
         co.kstop[slot] = i + 1;

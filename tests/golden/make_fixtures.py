@@ -12,6 +12,12 @@ lattice_4444.npz -- the 4^4 workload: links P_SU3(1 + 0.4 G) (seed 0),
     critical eigentriples (Section 3: smallest |lambda|, L^dagger R = I) and
     the full spectrum's smallest |lambda| and |Re lambda|.
 
+gradient_4444_dk.npz -- the exact (Daleckii-Krein) gradient at the 4^4
+    workload, for the deflation-aware gradient.
+
+gradient_8888_converged.npz -- references for the k = 400 gradient from the
+    converged function (see gradient_8888_converged below).
+
 gradient_8888_k150.npz, gradient_8888_k400.npz -- the gradient workload: 8^4,
     links P_SU3(1 + 0.6 G) (seed 0), m_w = -1.5, mu = 0.3, one Gaussian
     source b (seed 1) and cotangent chi (seed 2), two-sided Lanczos without
@@ -27,9 +33,9 @@ gradient_8888_k150.npz, gradient_8888_k400.npz -- the gradient workload: 8^4,
     extrapolations (4 D(h/2) - D(h))/3 of central ones at h = 1e-5.
 
 sign_16x16x16x32.npz -- the benchmark workload: 16^3 x 32, links
-    P_SU3(1 + 0.6 G) (seed 0), m_w = -1.5, mu = 0.4, the first two of the 12
+    P_SU3(1 + 0.6 G) (seed 0), m_w = -1.5, mu = 0.4, the first four of the 12
     Gaussian sources (seed 1).  The oracle's two-sided Lanczos (CSR, FP64,
-    two-pass, no deflation) at k = 650 and k = 700 for each source: 4096
+    two-pass, no deflation) at k = 650 and k = 700 for each source: 16384
     sampled entries of y (fixed positions, default_rng(7)) and the full
     norms; their difference bounds the reference's own error.  The k = 650
     values come from the k = 700 run's first 650 coefficients (the same
@@ -139,6 +145,67 @@ def gradient_8888_at(k, h, richardson):
     )
 
 
+def gradient_8888_converged():
+    """References for the k = 400 gradient that its rounding noise cannot
+    swamp: the converged function L(mu, U, b) = Re <chi, sgn(A) b> (the
+    oracle's 2sL at k = 800, whose y changes by ~7e-12 from k = 800 to 1200,
+    against 5e-8 at k = 400), its central differences in mu and along the
+    link direction E (Richardson-extrapolated from h = 2e-4 and 1e-4), and
+    sgn(A(-mu)) chi = sgn(A)^dagger chi, the b-gradient of the exact function
+    (Section 1: A(mu)^dagger = A(-mu)), by the oracle's 2sL at k = 800."""
+    dims = (8, 8, 8, 8)
+    m_w, mu, eps, kref = -1.5, 0.3, 0.6, 800
+    U = synth.random_links(dims, eps, seed=synth.LINK_SEED)
+    b = synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)[0]
+    chi = synth.gaussian_sources(dims, 1, seed=synth.COTANGENT_SEED)[0]
+    E = synth.complex_normal(U.shape, 3)
+    db = synth.complex_normal(b.shape, 4)
+
+    def sign_apply(UU, mm, bb):
+        A = dirac.csr_A(dims, UU, m_w, mm)
+        Ad = dirac.csr_A(dims, UU, m_w, -mm)
+        return krylov.tsl_apply(lambda z: A @ z, lambda z: Ad @ z, bb, kref, two_pass=True)
+
+    def loss(UU, mm):
+        return float(np.real(np.vdot(chi, sign_apply(UU, mm, b))))
+
+    def richardson(f, h):
+        c1 = (f(h) - f(-h)) / (2 * h)
+        c2 = (f(h / 2) - f(-h / 2)) / h
+        return (4.0 * c2 - c1) / 3.0, c1, c2
+
+    L0 = loss(U, mu)
+    fd_mu, fd_mu_h, fd_mu_h2 = richardson(lambda t: loss(U, mu + t), 2e-4)
+    fd_U, fd_U_h, fd_U_h2 = richardson(lambda t: loss(U + t * E, mu), 2e-4)
+    gb = sign_apply(U, -mu, chi)   # sgn(A(-mu)) chi
+    f400 = np.load(os.path.join(HERE, "gradient_8888_k400.npz"))
+    idx_b = f400["idx_b"]
+    np.savez_compressed(
+        os.path.join(HERE, "gradient_8888_converged.npz"),
+        dims=np.array(dims), m_w=m_w, mu=mu, eps=eps, kref=kref, loss=L0,
+        fd_mu=fd_mu, fd_mu_h=fd_mu_h, fd_mu_h2=fd_mu_h2, fd_U=fd_U, fd_U_h=fd_U_h,
+        fd_U_h2=fd_U_h2, idx_b=idx_b, grad_b_samp=gb[idx_b], norm_grad_b=np.linalg.norm(gb),
+        dir_b=float(np.real(np.vdot(gb, db))),
+    )
+    print("converged L", L0, "dL/dmu", fd_mu, fd_mu_h, fd_mu_h2, "dL/dE", fd_U, fd_U_h, fd_U_h2)
+
+
+def gradient_4444_dk():
+    """The exact derivative (Daleckii-Krein, on the full eigendecomposition) of
+    L = Re <chi, sgn(A) b> at the 4^4 workload of lattice_4444.npz (links
+    P_SU3(1 + 0.4 G) seed 0, m_w = -1.5, mu = 0.3, b seed 1, chi seed 2):
+    grad_b (= sgn(A(-mu)) chi), dL/dmu and the link gradient.  The reference
+    of the deflation-aware gradient (20 deflated eigentriples)."""
+    dims = (4, 4, 4, 4)
+    m_w, mu, eps = -1.5, 0.3, 0.4
+    U = synth.random_links(dims, eps, seed=synth.LINK_SEED)
+    b = synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)[0]
+    chi = synth.gaussian_sources(dims, 1, seed=synth.COTANGENT_SEED)[0]
+    gb, gmu, gU = grad.dk_gradient(dims, U, m_w, mu, b, chi)
+    np.savez_compressed(os.path.join(HERE, "gradient_4444_dk.npz"), dims=np.array(dims), m_w=m_w,
+                        mu=mu, eps=eps, grad_b=gb, grad_mu=gmu, grad_U=gU)
+
+
 def gradient_8888():
     gradient_8888_at(150, 1e-5, True)
     gradient_8888_at(400, 1e-3, False)
@@ -172,11 +239,11 @@ def sign_16x16x16x32():
     from concurrent.futures import ProcessPoolExecutor
     dims = (16, 16, 16, 32)
     N = synth.volume(dims) * 12
-    idx = np.sort(np.random.default_rng(7).choice(N, 4096, replace=False))
+    idx = np.sort(np.random.default_rng(7).choice(N, 16384, replace=False))
     out = {"dims": np.array(dims), "m_w": -1.5, "mu": 0.4, "eps": 0.6, "idx": idx,
-           "ks": np.array([650, 700])}
-    with ProcessPoolExecutor(2) as ex:
-        res = list(ex.map(_sign16_source, (0, 1)))
+           "ks": np.array([650, 700]), "sources": np.arange(4)}
+    with ProcessPoolExecutor(4) as ex:
+        res = list(ex.map(_sign16_source, range(4)))
     for r, ys in enumerate(res):
         for k in (650, 700):
             out[f"y{r}_k{k}"] = ys[k][idx]

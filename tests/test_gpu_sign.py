@@ -24,6 +24,12 @@ def lattice(dims, prec, U, mu):
     return lat
 
 
+def oracle_2sl(A, b, ks):
+    """The oracle's two-sided Lanczos result of each source b[r] at its own k."""
+    return np.stack([krylov.tsl_apply(lambda v: A @ v, lambda v: A.conj().T @ v, bb, int(k))
+                     for bb, k in zip(b, ks)])
+
+
 @pytest.fixture(scope="module")
 def cfg1():
     """4^4, eps 0.4, mu 0.3, Gaussian source; exact sign and 20 eigentriples (stored)."""
@@ -53,6 +59,30 @@ def test_inner_sign_tridiag_vs_eig():
         x, err = lat.inner_sign_tridiag(lr.alpha[None], sub[None], sup[None])
         say("tri k", k, rel(x[0], ref), err)
         assert rel(x[0], ref) < 1e-11
+
+
+@pytest.mark.parametrize("k", [400, 800])
+def test_inner_sign_tridiag_large_k(k):
+    """sgn(G_k) e_1 at k = 400 and 800 for the tridiagonal G_k of the oracle's
+    two-sided Lanczos at 8^4 (eps 0.6, mu 0.3, Section 4; coefficients and the
+    spectral x = V sgn(Lambda) V^{-1} e_1 in tests/golden/config2_8888.npz):
+    the GPU quadrature within 1e-10 (the eigenvector condition numbers, 5e4 and
+    7e4, bound the reference's own rounding near 1e-11)."""
+    import paper_0810_4228_amd as ovs
+    f = np.load(os.path.join(GOLDEN, "config2_8888.npz"))
+    lat = ovs.Lattice((2, 2, 2, 2))
+    al, be, ga = f["g_alpha"][:k], f["g_beta"][:k - 1], f["g_gamma"][:k - 1]
+    sub = np.zeros(k, complex)
+    sub[:k - 1] = be
+    sup = np.zeros(k, complex)
+    sup[:k - 1] = ga
+    x, err, st = lat.inner_sign_tridiag(al[None], sub[None], sup[None], return_status=True)
+    e = rel(x[0], f[f"g_x{k}"])
+    say(f"inner sign k={k}: vs eig {e:.2e}, quadrature estimate {err[0]:.1e}, status {st}, "
+        f"cond {float(f[f'g_cond{k}']):.1e}, min angle to the imaginary axis "
+        f"{float(f[f'g_minangle{k}']):.2f}")
+    assert st == 0
+    assert e <= 1e-10
 
 
 def test_inner_sign_hessenberg_vs_eig():
@@ -211,39 +241,46 @@ def test_config_8888_lanczos_and_arnoldi_vs_cpu(mu):
 def test_benchmark_workload_against_oracle():
     """The benchmark workload at full size (16^3 x 32, eps 0.6, mu 0.4, 12
     Gaussian sources, FP32 storage, tol 1e-5, two concurrent halves) against
-    the oracle's FP64 two-sided Lanczos at k = 700 for sources 0 and 1 (4096
-    sampled entries, tests/golden/sign_16x16x16x32.npz; the oracle's own change
-    from k = 650 to 700 bounds the reference's error).  The FP32-storage bar is
-    1e-5; the FP64 path at tol 1e-10 must land within the reference's own
-    uncertainty."""
+    the oracle's FP64 two-sided Lanczos at k = 700 for the fixture's sources
+    (0-3: two in each half of the split batch; sampled entries,
+    tests/golden/sign_16x16x16x32.npz; the oracle's own change from k = 650
+    to 700 bounds the reference's error).  The FP32-storage bar is 1e-5; the
+    FP64 path at tol 1e-10 must land within the reference's own uncertainty.
+    All 12 FP32 results are also checked against the FP64 ones (1e-5)."""
     import paper_0810_4228_amd as ovs
     import torch
     f = np.load(os.path.join(GOLDEN, "sign_16x16x16x32.npz"))
     dims = tuple(int(d) for d in f["dims"])
     mu, idx = float(f["mu"]), f["idx"]
+    nsrc = len(f["sources"]) if "sources" in f.files else 2
     U = to_dev(synth.random_links(dims, float(f["eps"]), seed=synth.LINK_SEED))
     b = synth.gaussian_sources(dims, 12, seed=synth.SOURCE_SEED)
-    ref = [f["y0_k700"], f["y1_k700"]]
-    unc = max(float(f["ydiff0"]), float(f["ydiff1"]))
+    ref = [f[f"y{r}_k700"] for r in range(nsrc)]
+    unc = max(float(f[f"ydiff{r}"]) for r in range(nsrc))
     lat = ovs.Lattice(dims, precision="f32")
     lat.set_links(U)
     lat.set_params(MW, mu)
     y, info, st = lat.sign_apply(to_dev(b), 1000, tol=[1e-5] * 12, graph=True)
-    e32 = [rel(y[r].cpu().numpy()[idx], ref[r]) for r in range(2)]
-    est = [info[r]["est_rel_err"] for r in range(2)]
+    e32 = [rel(y[r].cpu().numpy()[idx], ref[r]) for r in range(nsrc)]
+    est = [info[r]["est_rel_err"] for r in range(nsrc)]
     lat.close()
-    del y
-    torch.cuda.empty_cache()
     lat64 = ovs.Lattice(dims, precision="f64")
     lat64.set_links(U)
     lat64.set_params(MW, mu)
-    y64, info64, st64 = lat64.sign_apply(to_dev(b[:2]), 1000, tol=[1e-10] * 2, graph=True)
-    e64 = [rel(y64[r].cpu().numpy()[idx], ref[r]) for r in range(2)]
+    y64, info64, st64 = lat64.sign_apply(to_dev(b), 1000, tol=[1e-10] * 12, graph=True,
+                                         two_pass=True)
+    e64 = [rel(y64[r].cpu().numpy()[idx], ref[r]) for r in range(nsrc)]
+    e_all = (torch.linalg.vector_norm(y - y64, dim=1) /
+             torch.linalg.vector_norm(y64, dim=1)).cpu().numpy()
     lat64.close()
     say(f"16^3x32 vs oracle k=700 (reference change 650->700: {unc:.1e}): FP32 {e32} "
-        f"(estimates {est}, k {[i['k_used'] for i in info[:2]]}), FP64 {e64} "
-        f"(k {[i['k_used'] for i in info64]})")
+        f"(estimates {est}, k {[i['k_used'] for i in info[:nsrc]]}), FP64 {e64} "
+        f"(k {[i['k_used'] for i in info64]}); all 12 FP32 vs FP64: max {e_all.max():.2e}")
+    del y, y64
+    torch.cuda.empty_cache()
+    assert st == 0 and st64 == 0
     assert max(e32) <= 1e-5
+    assert e_all.max() <= 1e-5
     # the GPU result is within ~1e-10 of the exact value and the reference within
     # ~unc of it (its own 650 -> 700 change bounds its error)
     assert max(e64) <= 2 * (1e-10 + unc)
@@ -308,7 +345,7 @@ def test_benchmark_lattice_48_sources_mixed_tolerance():
     tol = [1e-5 if j % 2 == 0 else 1e-8 for j in range(48)]
     y, info, st = lat.sign_apply(b, 1200, tol=tol, two_pass=True, graph=True)
     e = [rel(y[r].cpu().numpy()[idx], f[f"y{r}_k700"]) for r in range(2)]
-    unc = max(float(f["ydiff0"]), float(f["ydiff1"]))
+    unc = max(float(f["ydiff0"]), float(f["ydiff1"]))  # the fixture's sources 0 and 1
     ks = [i["k_used"] for i in info]
     esc = [j for j, i in enumerate(info) if i["escalated"]]
     lat.close()
@@ -377,29 +414,35 @@ def test_mixed_tolerance_fp64_group(cfg1):
     errs = [rel(y[r], ref[r]) for r in range(4)]
     say("mixed tolerances: errors", errs, "k", [i["k_used"] for i in info])
     assert errs[1] <= 1e-8 and errs[3] <= 1e-8
-    assert errs[0] <= 1e-4 and errs[2] <= 1e-4
+    assert errs[0] <= 1e-5 and errs[2] <= 1e-5
     lat64 = lattice(dims, "f64", U, mu)
     d64 = lat64.deflation_set(f["lam"], to_dev(f["R"].T), to_dev(f["L"].T))
     y64, _, _ = lat64.sign_apply(to_dev(b[[1, 3]]), 1000, defl=d64, tol=[1e-9, 1e-9])
     assert np.array_equal(y[[1, 3]], y64.cpu().numpy())
 
 
-@pytest.mark.parametrize("prec,tol,agree", [("f64", 1e-10, 1e-12), ("f32", 3e-5, 1e-6)])
+@pytest.mark.parametrize("prec,tol,agree", [("f64", 1e-10, 1e-12), ("f32", 1e-5, 1e-6)])
 def test_dual_variants_match_cpu(prec, tol, agree):
     """Every dual-stencil configuration the autotuner can pick (one thread for
     both operators, a lane pair, a lane pair with the tile staged in LDS, one
     operator per workgroup with and without the staged tile; source blocks
     1..4, block order, streaming stores) gives the CPU oracle's two-sided Lanczos result: a ragged lattice
     (V = 576, not a multiple of the 256-site tile) and 5 sources (ragged
-    source blocks).  FP32 storage at this unconverged k sits ~8e-6 from the
-    FP64 oracle; the variants agree with each other to rounding."""
+    source blocks).  FP64 storage at k = 40 (unconverged: the step-by-step
+    parity of the recurrence); FP32 storage stopped at its convergence check
+    for 1e-6 and compared with the oracle at each source's k_used, where the
+    the benchmark spec's FP32 bar of 1e-5 applies (at a fixed k = 40, FP32 rounding
+    amplified by the unconverged polynomial sits at 1.2e-5 from the FP64
+    oracle, at a fixed k = 200, past convergence, at 2e-5).  The variants agree
+    with each other to rounding."""
     dims = (4, 4, 6, 6)
     U = synth.random_links(dims, 0.5, seed=81)
     mu = 0.35
     b = synth.gaussian_sources(dims, 5, seed=82)
     A = dirac.csr_A(dims, U, MW, mu)
-    k = 40
-    ref = np.stack([krylov.tsl_apply(lambda v: A @ v, lambda v: A.conj().T @ v, bb, k) for bb in b])
+    k = 40 if prec == "f64" else 400
+    stol = None if prec == "f64" else [1e-6] * 5
+    refs = {}
     lat = lattice(dims, prec, U, mu)
     base = lat.get_tuning_raw(5)
     blocks = (1, 2, 3, 4) if prec == "f32" else (1, 2)
@@ -415,31 +458,42 @@ def test_dual_variants_match_cpu(prec, tol, agree):
                 cfg[6] = 0
                 cfg[7] = order
                 lat.set_tuning_raw(5, cfg)
-                y, info, st = lat.sign_apply(to_dev(b), k)
+                y, info, st = lat.sign_apply(to_dev(b), k, tol=stol)
                 yh = y.cpu().numpy()
-                e = rel_rows(yh, ref)
+                ks = tuple(i["k_used"] for i in info)
+                if ks not in refs:
+                    refs[ks] = oracle_2sl(A, b, ks)
+                e = rel_rows(yh, refs[ks])
                 first = yh if first is None else first
                 say("dual", prec, "lanes", lanes, "block", blk, "order", order, "nt", nt, f"{e:.2e}")
                 assert e <= tol
                 assert rel_rows(yh, first) <= agree
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 3e-5)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-5)])
 def test_dual_grouped_block_orders(prec, tol):
     """The dual stencil (one thread per site, and one operator per workgroup)
     with block orders 2-7 (windows of 1, 2, 3, 4, 6 or all source blocks per
     XCD time chunk) on 16 x 16 x 2 x 8 (planar for 256-site tiles, Lt = 8), 5
-    sources: against the oracle's 2sL at k = 40, and persistent launches equal
-    to the per-step kernels bit for bit.  The variant marching along t (FP32)
-    equals the operator-per-workgroup variant bit for bit."""
+    sources: against the oracle's 2sL at the same k (40 in FP64; in FP32 the
+    k each source stops at for 1e-6, for the 1e-5 bar), and persistent
+    launches equal to the per-step kernels bit for bit.  The variant marching along t (FP32) equals
+    the operator-per-workgroup variant bit for bit."""
     import torch
     dims = (16, 16, 2, 8)
     U = synth.random_links(dims, 0.5, seed=95)
     mu = 0.3
     b = synth.gaussian_sources(dims, 5, seed=96)
     A = dirac.csr_A(dims, U, MW, mu)
-    k = 40
-    ref = np.stack([krylov.tsl_apply(lambda v: A @ v, lambda v: A.conj().T @ v, bb, k) for bb in b])
+    k = 40 if prec == "f64" else 400
+    stol = None if prec == "f64" else [1e-6] * 5
+    refs = {}
+
+    def err(y, info):
+        ks = tuple(i["k_used"] for i in info)
+        if ks not in refs:
+            refs[ks] = oracle_2sl(A, b, ks)
+        return rel_rows(y.cpu().numpy(), refs[ks])
     lat = lattice(dims, prec, U, mu)
     base = lat.get_tuning_raw(5)
     for blk in ((1, 2) if prec == "f32" else (1,)):
@@ -448,9 +502,9 @@ def test_dual_grouped_block_orders(prec, tol):
                 cfg = list(base)
                 cfg[4:8] = [100 * blk + 10 * variant + 1, 256, 0, order]
                 lat.set_tuning_raw(5, cfg)
-                y, _, _ = lat.sign_apply(to_dev(b), k)
-                yp, _, _ = lat.sign_apply(to_dev(b), k, persistent=True)
-                e = rel_rows(y.cpu().numpy(), ref)
+                y, info, _ = lat.sign_apply(to_dev(b), k, tol=stol)
+                yp, _, _ = lat.sign_apply(to_dev(b), k, tol=stol, persistent=True)
+                e = err(y, info)
                 assert e <= tol, (blk, variant, order, e)
                 assert torch.equal(y, yp)
     if prec == "f32":
@@ -459,15 +513,15 @@ def test_dual_grouped_block_orders(prec, tol):
         cfg = list(base)
         cfg[4:8] = [100 + 40 + 1, 256, 0, 0]
         lat.set_tuning_raw(5, cfg)
-        y4, _, _ = lat.sign_apply(to_dev(b), k)
+        y4, _, _ = lat.sign_apply(to_dev(b), k, tol=stol)
         for order in (0, 1):
             for nt in (0, 1):
                 cfg[4:8] = [100 + 60 + nt, 256, 0, order]
                 lat.set_tuning_raw(5, cfg)
-                y6, _, _ = lat.sign_apply(to_dev(b), k)
-                assert rel_rows(y6.cpu().numpy(), ref) <= tol
+                y6, info6, _ = lat.sign_apply(to_dev(b), k, tol=stol)
+                assert err(y6, info6) <= tol
                 assert torch.equal(y6, y4), (order, nt)
-        yp, _, _ = lat.sign_apply(to_dev(b), k, persistent=True)
+        yp, _, _ = lat.sign_apply(to_dev(b), k, tol=stol, persistent=True)
         assert torch.equal(yp, y4)
     else:
         cfg = list(base)
@@ -545,10 +599,17 @@ def test_persistent_equals_per_step_bitwise(prec, blk, variant):
         assert [i["k_used"] for i in i1] == [i["k_used"] for i in i2]
         assert torch.equal(y1, y2) and torch.equal(y2, y3)
     A = dirac.csr_A(dims, U, MW, mu)
-    k = 60
-    ref = np.stack([krylov.tsl_apply(lambda v: A @ v, lambda v: A.conj().T @ v, bb, k) for bb in b])
-    y, _, _ = lat.sign_apply(to_dev(b), k, persistent=True)
-    assert rel_rows(y.cpu().numpy(), ref) <= (3e-5 if prec == "f32" else 1e-10)
+    # FP64 at k = 60; FP32 stopped at its check for 1e-6 (the 1e-5 bar), each
+    # source against the oracle at its own k
+    if prec == "f32":
+        y, info, _ = lat.sign_apply(to_dev(b), 400, tol=[1e-6] * 5, persistent=True)
+        ks = [i["k_used"] for i in info]
+    else:
+        y, _, _ = lat.sign_apply(to_dev(b), 60, persistent=True)
+        ks = [60] * 5
+    e = rel_rows(y.cpu().numpy(), oracle_2sl(A, b, ks))
+    say("persistent vs oracle", prec, ks, e)
+    assert e <= (1e-5 if prec == "f32" else 1e-10)
 
 
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 16, 16, 16)])
@@ -659,10 +720,111 @@ def test_sign_errors(cfg1):
     del torch
 
 
+def test_forced_serious_breakdown(cfg1):
+    """A serious breakdown (Section 4: delta = w~^dagger v~ = 0, no
+    biorthogonal continuation) forced from the host at iteration 30: every
+    source stops with k = 31 and OVS_WARN_BREAKDOWN, min_abs_delta = 0, and y
+    is the two-sided Lanczos result of that k (equal to a run with k_max =
+    31); without the injection the same call is OK."""
+    import paper_0810_4228_amd as ovs
+    dims, U, b1, f = cfg1
+    b = np.stack([b1[0], 0.5j * b1[0] + synth.gaussian_sources(dims, 1, seed=7)[0]])
+    for prec in ("f64", "f32"):
+        lat = lattice(dims, prec, U, float(f["mu"]))
+        y0, i0, s0 = lat.sign_apply(to_dev(b), 100)
+        lat.set_debug(breakdown_at=30)
+        y1, i1, s1 = lat.sign_apply(to_dev(b), 100)
+        y1g, _, s1g = lat.sign_apply(to_dev(b), 100, graph=True, tol=[1e-12, 1e-12])
+        lat.set_debug(breakdown_at=-1)
+        y31, _, s31 = lat.sign_apply(to_dev(b), 31)
+        e = rel_rows(y1.cpu().numpy(), y31.cpu().numpy())
+        say("forced breakdown", prec, s0, s1, s1g, [i["k_used"] for i in i1],
+            [i["min_abs_delta"] for i in i0], [i["min_abs_delta"] for i in i1], e)
+        assert s0 == 0 and s31 == 0
+        assert s1 == ovs.OVS_WARN_BREAKDOWN and s1g == ovs.OVS_WARN_BREAKDOWN
+        assert all(i["k_used"] == 31 and i["status"] == ovs.OVS_WARN_BREAKDOWN for i in i1)
+        assert all(i["min_abs_delta"] == 0.0 for i in i1)
+        assert all(i["min_abs_delta"] > 1e-13 for i in i0)
+        assert e <= 1e-12
+        lat.close()
+
+
+def test_zero_and_infinite_sources(cfg1):
+    """A zero source gives y = 0 exactly with k_used = 0 and status OK (next to
+    an ordinary source in the same batch); an infinite entry is rejected."""
+    import paper_0810_4228_amd as ovs
+    dims, U, b1, f = cfg1
+    lat = lattice(dims, "f64", U, float(f["mu"]))
+    b = np.stack([np.zeros_like(b1[0]), b1[0]])
+    y, info, st = lat.sign_apply(to_dev(b), 500, tol=[1e-8, 1e-8])
+    yh = y.cpu().numpy()
+    yr, _, _ = lat.sign_apply(to_dev(b1), 500, tol=[1e-8])
+    say("zero source", st, [i["k_used"] for i in info], np.abs(yh[0]).max())
+    assert st == 0 and info[0]["status"] == 0 and info[0]["k_used"] == 0
+    assert np.all(yh[0] == 0)
+    assert np.array_equal(yh[1], yr.cpu().numpy()[0])
+    bad = to_dev(b1).clone()
+    bad[0, 17] = complex(float("inf"), 0.0)
+    with pytest.raises(ovs.OvsError) as ei:
+        lat.sign_apply(bad, 50)
+    assert ei.value.status == ovs.OVS_ERR_ARG
+    lat.close()
+
+
+def test_debug_checks(cfg1):
+    """OVS_DEBUG_CHECKS: the biorthogonality rows |w_j^dagger v_i - delta_ij|
+    (Section 4), measured every 25 iterations against the stored basis, and
+    the inner sign checked against a dense eigendecomposition of G_k (eq. for
+    f(A) in Section 1).  4^4 configuration, k = 300: the quadrature's x agrees
+    with the spectral one to 1e-10; biorthogonality is reported (it degrades
+    with k: short recurrences keep W^dagger V = I only in exact arithmetic);
+    no Ritz value near the imaginary axis here.  Two-pass has no stored basis
+    to check against (-1); the result is unchanged by the checks."""
+    dims, U, b, f = cfg1
+    mu = float(f["mu"])
+    lat = lattice(dims, "f64", U, mu)
+    y0, _, _ = lat.sign_apply(to_dev(b), 300)
+    lat.set_debug(checks=True)
+    y, info, st = lat.sign_apply(to_dev(b), 300)
+    y60, info60, _ = lat.sign_apply(to_dev(b), 60)
+    y2, info2, st2 = lat.sign_apply(to_dev(b), 300, two_pass=True)
+    ya, infoa, sta = lat.sign_apply(to_dev(b), 200, method="arnoldi")
+    lat.set_debug()
+    i0, i2, ia = info[0], info2[0], infoa[0]
+    # the oracle's W^dagger V on the rows the monitor measures at k = 60
+    # (iterations 25, 50 and the last, 59), before biorthogonality is lost
+    A = dirac.csr_A(dims, U, MW, mu)
+    lr = krylov.two_sided_lanczos(lambda v: A @ v, lambda v: A.conj().T @ v, b[0], b[0], 60)
+    M = np.array(lr.W).conj() @ np.array(lr.V).T
+    ora60 = max(np.abs(M[j, :j + 1] - np.eye(60)[j, :j + 1]).max() for j in (25, 50, 59))
+    say("debug checks: biorth k=300", i0["biorth_err"], "k=60", info60[0]["biorth_err"],
+        "(oracle", ora60, ") ritz min re", i0["ritz_min_re"], "inner check", i0["inner_check_err"],
+        "min delta", i0["min_abs_delta"], "| two-pass", i2["biorth_err"], i2["inner_check_err"],
+        "| arnoldi", ia["inner_check_err"], ia["ritz_min_re"])
+    assert st == 0 and st2 == 0 and sta == 0
+    assert np.array_equal(y.cpu().numpy(), y0.cpu().numpy())
+    # before the loss the monitor sees the oracle's rounding level; by k = 300
+    # the short recurrences have lost biorthogonality (entries of order one)
+    assert info60[0]["biorth_err"] <= max(10 * ora60, 1e-12)
+    assert i0["biorth_err"] >= info60[0]["biorth_err"]
+    assert i2["biorth_err"] == -1.0
+    assert 0.0 < i0["ritz_min_re"] <= 1.0
+    assert 0.0 <= i0["inner_check_err"] <= 1e-10
+    assert 0.0 <= i2["inner_check_err"] <= 1e-10
+    assert 0.0 <= ia["inner_check_err"] <= 1e-10 and ia["min_abs_delta"] == -1.0
+    lat.close()
+
+
 def test_workspace_size():
     """ovs_workspace_size: the one-pass basis dominates (k_max vectors per
     source), two-pass keeps three, a split batch adds the second half's
-    workspace, and a solve with that k_max runs (a warning allowed)."""
+    workspace.  A solve runs on a caller workspace of exactly that size (a
+    torch tensor) with the same result as on the handle's own memory, and a
+    smaller one is rejected; without a caller workspace the handle grows its
+    basis as the iteration needs it, so after a solve that stops at k it holds
+    far less than the k_max estimate."""
+    import paper_0810_4228_amd as ovs
+    import torch
     dims = (4, 4, 4, 4)
     U = synth.random_links(dims, 0.6, seed=71)
     lat = lattice(dims, "f32", U, 0.3)
@@ -677,4 +839,30 @@ def test_workspace_size():
     b = to_dev(synth.gaussian_sources(dims, 12, seed=72))
     y, info, st = lat.sign_apply(b, 400, tol=[1e-5] * 12)
     assert st >= 0  # runs (k_max = 400 need not reach 1e-5 on these rough links)
+    held = lat.workspace_held()
+    big = lat.workspace_size(12, 3000)
+    y2, _, _ = lat.sign_apply(b, 3000, tol=[1e-5] * 12)
+    held2 = lat.workspace_held()
+    ws = torch.empty(big, dtype=torch.uint8, device="cuda")
+    y3, info3, st3 = lat.sign_apply(b, 3000, tol=[1e-5] * 12, workspace=ws)
+    say("workspace: k_max 3000 estimate", big, "held after solves", held, held2, "k",
+        [i["k_used"] for i in info3])
+    assert torch.equal(y2, y3)
+    assert lat.workspace_held() == held2  # the caller's memory was used
+    # the basis grew to at most twice the k used, not to k_max = 3000
+    vec = 12 * 320 * 8  # one FP32 source field (V = 256 padded to 320)
+    kmx = max(i["k_used"] for i in info3)
+    assert big - held2 >= 0.9 * (3000 - 2 * kmx) * 12 * vec
+    with pytest.raises(ovs.OvsError):
+        lat.sign_apply(b, 3000, tol=[1e-5] * 12, workspace=ws[: big // 2])
+    # FP64, unsplit and Arnoldi on a caller workspace
+    lat64 = lattice(dims, "f64", U, 0.3)
+    for kw in ({"split": False}, {"method": "arnoldi"}, {"two_pass": True}):
+        n = lat64.workspace_size(3, 300, **{k: v for k, v in kw.items() if k != "method"},
+                                 method=kw.get("method", "2sl"))
+        w = torch.empty(n, dtype=torch.uint8, device="cuda")
+        ya, _, sa = lat64.sign_apply(b[:3], 300, tol=[1e-8] * 3, workspace=w, **kw)
+        yb, _, sb = lat64.sign_apply(b[:3], 300, tol=[1e-8] * 3, **kw)
+        assert sa == sb and torch.equal(ya, yb), kw
+    lat64.close()
     lat.close()

@@ -123,6 +123,25 @@ def test_grouped_block_orders(prec):
         lat.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_links_from_host_memory(prec):
+    """ovs_set_links with host links (on_device = 0) packs the same links as
+    with device links: the operator's results are equal bit for bit."""
+    import torch
+    dims = (4, 4, 6, 8)
+    U = synth.random_links(dims, 0.5, seed=17)
+    x = to_dev(synth.gaussian_sources(dims, 3, seed=18))
+    dev_lat = lattice(dims, prec, U, 0.25)
+    import paper_0810_4228_amd as ovs
+    host_lat = ovs.Lattice(dims, precision=prec)
+    host_lat.set_links(U)   # numpy array: host memory
+    host_lat.set_params(MW, 0.25)
+    for op in ("A", "A_dag"):
+        assert torch.equal(dev_lat.apply(op, x), host_lat.apply(op, x))
+    dev_lat.close()
+    host_lat.close()
+
+
 def test_field_roundtrip_bitwise():
     import torch
     dims = (4, 4, 4, 4)
