@@ -108,6 +108,11 @@ typedef struct {
 
 /* Debug flags of ovs_set_debug. */
 #define OVS_DEBUG_CHECKS 1
+#define OVS_DEBUG_PROGRESS 2   /* ovs_deflation_compute prints its progress (subspace passes,
+                                  inner solves, restarts) to stderr */
+#define OVS_DEBUG_RANGES 4     /* roctx ranges around each call and its phases (deflation,
+                                  Lanczos, inner sign, combination; the gradient's and the
+                                  eigensolver's phases), for rocprofv3 --marker-trace */
 
 /* ---- lattice ------------------------------------------------------------ */
 
@@ -134,7 +139,8 @@ ovs_status ovs_set_links(ovs_lattice lat, const void* U, int32_t on_device);
 ovs_status ovs_set_params(ovs_lattice lat, double m_w, double mu);
 
 /* Diagnostics of later ovs_sign_apply calls on this handle.
- *   flags        : 0 or OVS_DEBUG_CHECKS.  With OVS_DEBUG_CHECKS the 2sL
+ *   flags        : OVS_DEBUG_CHECKS and/or OVS_DEBUG_PROGRESS.  With
+ *                  OVS_DEBUG_CHECKS the 2sL
  *                  biorthogonality w_j^dagger V_j (Section 4: W^dagger V = I,
  *                  which short recurrences keep only in exact arithmetic) is
  *                  measured every 25 iterations and at the end against the
@@ -235,16 +241,22 @@ ovs_status ovs_set_tuning_ex(ovs_lattice lat, int32_t nrhs, const int32_t cfg[8]
 ovs_status ovs_deflation_set(ovs_lattice lat, int32_t m, const double* lambda, const void* R,
                              const void* L, ovs_deflation* out);
 /* Compute the m critical eigentriples on the GPU (Section 5 obtains them with
- * ARPACK; here Chebyshev-filtered subspace iteration on A^2 and on A^dagger^2
- * with Rayleigh-Ritz steps on A, A^dagger; FP64 throughout, also on FP32
- * lattices).  tol: target relative residual |A r - lambda r| / |lambda|;
- * max_iter: filter passes per side.  Returns OVS_WARN_NOT_CONVERGED (handle
- * still created) if tol or |L^dagger R - I| <= 1e-6 was not reached. */
+ * ARPACK; here shift-and-invert Krylov-Schur on A^{-1} and on A^dagger^{-1},
+ * each inverse applied by conjugate gradients on the normal equations started
+ * from a deflation space of small singular vectors, then Rayleigh-Ritz on A,
+ * pairing lambda_L = conj(lambda_R) and L <- L (L^dagger R)^{-dagger}; FP64
+ * throughout, also on FP32 lattices).  tol: target relative residual
+ * |A r - lambda r| / |lambda| (and the same for the left vectors), 1e-10
+ * typical; max_iter: Krylov-Schur restarts per side (30 is ample).  Returns
+ * OVS_WARN_NOT_CONVERGED (handle still created) if tol or |L^dagger R - I| <=
+ * 1e-6 was not reached.  Cost grows with the condition number of A (an inner
+ * CG solve per Krylov vector). */
 ovs_status ovs_deflation_compute(ovs_lattice lat, int32_t m, double tol, int32_t max_iter,
                                  ovs_deflation* out);
 /* Copy out eigenvalues (host complex128 [m]), R and L (device complex128
- * [m][V][4][3]) and info (host double [3]: max relative residual,
- * max |L^dagger R - I|, filter passes).  Any pointer may be NULL. */
+ * [m][V][4][3]) and info (host double [3]: max relative residual of right
+ * and left vectors, max |L^dagger R - I|, Krylov-Schur restarts of both
+ * sides; for supplied triples the checked values).  Any pointer may be NULL. */
 ovs_status ovs_deflation_get(ovs_deflation d, double* lambda, void* R, void* L, double* info);
 ovs_status ovs_deflation_destroy(ovs_deflation d);
 
@@ -313,12 +325,20 @@ ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, c
 
 /* Gradient of L = sum_r Re <chi_r, y_r>, where y_r = |b_r| V_k sgn(G_k) e_1 is
  * the two-sided Lanczos approximation of sgn(gamma5 Dw(mu)) b_r (Section 4,
- * eq. 2sLapp) at exactly k iterations without deflation, with respect to the
- * sources, mu and the links: the exact derivative of that algorithm (reverse
- * sweep of its recurrences; the inner sign and its Jacobian by the tau = e^u
- * trapezoid rule).  Complex gradients follow dL = Re <zbar, dz> with
+ * eq. 2sLapp) at exactly k iterations, with respect to the sources, mu and
+ * the links.  Without deflation: the exact derivative of that algorithm
+ * (reverse sweep of its recurrences; the inner sign and its Jacobian by the
+ * tau = e^u trapezoid rule).  With n_defl LR-deflation eigentriples (Section
+ * 3), y_r = R S L^dagger b_r + the run from the deflated starts, and the
+ * gradient is that of sgn(A) b_r through the eigentriples as well: the
+ * Daleckii-Krein terms that couple the deflated eigenvalues with the rest
+ * are formed from the eigentriples and from a second k-step two-sided
+ * Lanczos run on A^dagger started from (1 - L R^dagger) chi (about twice the
+ * undeflated cost).  The eigentriples must be those of A at the lattice's
+ * current mu and links.  Complex gradients follow dL = Re <zbar, dz> with
  * zbar = dL/dRe z + i dL/dIm z; link matrices are differentiated entry by
  * entry (no projection on su(3)).
+ *   defl, n_defl : as for ovs_sign_apply (n_defl = 0: no deflation).
  *   b, chi   : device complex128 [nrhs][V][4][3] (canonical layout).
  *   k        : Krylov size, 1 <= k <= 65535; every source must complete k
  *              iterations.
@@ -337,19 +357,21 @@ ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, c
  *              the handle's cached workspace.
  * Needs an OVS_F64 lattice (OVS_ERR_ARG otherwise) and FP64 workspace of about
  * (4k/c + 2c + 22) nrhs fields with c = ceil(sqrt k), or (2k + 18) nrhs with
- * OVS_VJP_STORE_BASIS (OVS_ERR_ALLOC if the handle's cache cannot grow to it).
- * Returns OVS_WARN_BREAKDOWN, writing no output, when a
- * source breaks down before k iterations; OVS_WARN_SIGN_AMBIGUOUS, with all
- * outputs written, when the quadrature changed by more than 1e-6 between its
- * two finest steps. */
-ovs_status ovs_sign_apply_vjp(ovs_lattice lat, const void* b, const void* chi, int32_t nrhs,
-                              int32_t k, int32_t flags, void* y, void* grad_b, double* grad_mu,
-                              void* grad_U, double* quad_err, void* workspace, size_t ws_bytes);
+ * OVS_VJP_STORE_BASIS, plus (k + 11) nrhs fields with deflation
+ * (OVS_ERR_ALLOC if the handle's cache cannot grow to it).
+ * Returns OVS_WARN_BREAKDOWN, writing no output, when a source (or the
+ * second run) breaks down before k iterations or a deflated eigenvalue is an
+ * eigenvalue of G_k; OVS_WARN_SIGN_AMBIGUOUS, with all outputs written, when
+ * the quadrature changed by more than 1e-6 between its two finest steps. */
+ovs_status ovs_sign_apply_vjp(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, const void* b,
+                              const void* chi, int32_t nrhs, int32_t k, int32_t flags, void* y,
+                              void* grad_b, double* grad_mu, void* grad_U, double* quad_err,
+                              void* workspace, size_t ws_bytes);
 
 /* Bytes of caller workspace an ovs_sign_apply_vjp call with these arguments
  * needs.  No device work; OVS_ERR_ARG as for ovs_sign_apply_vjp. */
-ovs_status ovs_vjp_workspace_size(ovs_lattice lat, int32_t nrhs, int32_t k, int32_t flags,
-                                  size_t* bytes);
+ovs_status ovs_vjp_workspace_size(ovs_lattice lat, ovs_deflation defl, int32_t n_defl,
+                                  int32_t nrhs, int32_t k, int32_t flags, size_t* bytes);
 
 /* Krylov coefficients of the last ovs_sign_apply on this handle (2sL only):
  * alpha, gamma host complex128 [nrhs][k_max], beta host double [nrhs][k_max],

@@ -128,8 +128,8 @@ def load():
         "ovs_deflation_get": [P, DP, P, P, DP],
         "ovs_sign_apply": [P, P, I, P, P, I, I, DP, I, I, P, ctypes.c_size_t, ctypes.POINTER(RhsInfo)],
         "ovs_workspace_held": [P, ctypes.POINTER(ctypes.c_size_t)],
-        "ovs_sign_apply_vjp": [P, P, P, I, I, I, P, P, DP, P, DP, P, ctypes.c_size_t],
-        "ovs_vjp_workspace_size": [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)],
+        "ovs_sign_apply_vjp": [P, P, I, P, P, I, I, I, P, P, DP, P, DP, P, ctypes.c_size_t],
+        "ovs_vjp_workspace_size": [P, P, I, I, I, I, ctypes.POINTER(ctypes.c_size_t)],
         "ovs_overlap_eigs": [P, P, I, I, I, I, I, D, I, D, I, DP, P, DP],
         "ovs_link_force": [P, P, P, P],
         "ovs_workspace_size": [P, P, I, I, I, I, I, ctypes.POINTER(ctypes.c_size_t)],
@@ -231,13 +231,15 @@ class Lattice:
     def set_params(self, m_w, mu):
         _check(self._lib.ovs_set_params(self._h, float(m_w), float(mu)), "ovs_set_params")
 
-    def set_debug(self, checks=False, breakdown_at=-1):
+    def set_debug(self, checks=False, breakdown_at=-1, progress=False, ranges=False):
         """Diagnostics of later sign_apply calls (ovs_set_debug): checks=True
         measures the 2sL biorthogonality and checks the inner sign against a
         dense eigensolve (results in the info records); breakdown_at >= 0
-        forces delta = 0 in that iteration's beta step (a serious breakdown)."""
-        _check(self._lib.ovs_set_debug(self._h, OVS_DEBUG_CHECKS if checks else 0,
-                                       int(breakdown_at)), "ovs_set_debug")
+        forces delta = 0 in that iteration's beta step (a serious breakdown);
+        progress=True prints the eigentriple solver's progress to stderr;
+        ranges=True marks each call and its phases with roctx ranges."""
+        flags = (OVS_DEBUG_CHECKS if checks else 0) | (2 if progress else 0) | (4 if ranges else 0)
+        _check(self._lib.ovs_set_debug(self._h, flags, int(breakdown_at)), "ovs_set_debug")
 
     def _fields(self, x):
         x = _dev_c128(x, "x")
@@ -423,17 +425,21 @@ class Lattice:
         return lam_c, vecs, {"max_residual": info[0], "restarts": int(info[1]),
                              "sign_solves": int(info[2]), "inner_warnings": int(info[3])}, st
 
-    def vjp_workspace_size(self, nrhs, k, store_basis=False):
+    def vjp_workspace_size(self, nrhs, k, store_basis=False, defl=None, n_defl=None):
         """Bytes of caller workspace a sign_apply_vjp call needs."""
         out = ctypes.c_size_t()
-        _check(self._lib.ovs_vjp_workspace_size(self._h, int(nrhs), int(k),
+        dh = defl._h if defl is not None else None
+        nd = (defl.m if n_defl is None else int(n_defl)) if defl is not None else 0
+        _check(self._lib.ovs_vjp_workspace_size(self._h, dh, nd, int(nrhs), int(k),
                                                 OVS_VJP_STORE_BASIS if store_basis else 0,
                                                 ctypes.byref(out)), "ovs_vjp_workspace_size")
         return int(out.value)
 
-    def sign_apply_vjp(self, b, chi, k, want_y=True, store_basis=False, workspace=None):
+    def sign_apply_vjp(self, b, chi, k, want_y=True, store_basis=False, workspace=None,
+                       defl=None, n_defl=None):
         """Gradient of L = sum_r Re <chi_r, y_r> for the k-step two-sided Lanczos
-        y_r ~ sgn(A) b_r without deflation (FP64 lattices).  The reverse sweep
+        y_r ~ sgn(A) b_r (FP64 lattices), with LR deflation by `defl` (its
+        first n_defl eigentriples, all by default) if given.  The reverse sweep
         recomputes the Lanczos vectors from checkpoints unless store_basis.
         Returns (y or None, grad_b, grad_mu, grad_U [V,4,3,3], quad_err [nrhs], status)."""
         torch = _torch()
@@ -452,8 +458,11 @@ class Lattice:
                 raise ValueError("workspace must be a contiguous CUDA tensor")
             ws_p = ctypes.c_void_p(workspace.data_ptr())
             ws_n = workspace.numel() * workspace.element_size()
+        dh = defl._h if defl is not None else None
+        nd = (defl.m if n_defl is None else int(n_defl)) if defl is not None else 0
         st = self._lib.ovs_sign_apply_vjp(
-            self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(chi.data_ptr()), nrhs, int(k),
+            self._h, dh, nd, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(chi.data_ptr()), nrhs,
+            int(k),
             OVS_VJP_STORE_BASIS if store_basis else 0,
             ctypes.c_void_p(y.data_ptr()) if y is not None else None,
             ctypes.c_void_p(gb.data_ptr()), ctypes.byref(gmu), ctypes.c_void_p(gU.data_ptr()),

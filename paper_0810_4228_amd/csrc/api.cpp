@@ -4,6 +4,7 @@
 // stream; the host only makes the decisions that need a global view
 // (convergence checks, quadrature refinement, breakdown bookkeeping).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <array>
@@ -135,6 +136,22 @@ void unpack_field(const ovs_lattice_s* l, const void* field, void* canon, int nr
 }
 
 bool ready(const ovs_lattice_s* l) { return l && l->links_set && l->params_set; }
+
+Ranges::Ranges(const ovs_lattice_s* l, const char* call)
+    : on_(l && (l->debug_flags & OVS_DEBUG_RANGES)) {
+  if (on_) roctxRangePushA(call);
+}
+Ranges::~Ranges() {
+  if (!on_) return;
+  if (inner_) roctxRangePop();
+  roctxRangePop();
+}
+void Ranges::phase(const char* name) {
+  if (!on_) return;
+  if (inner_) roctxRangePop();
+  roctxRangePushA(name);
+  inner_ = true;
+}
 
 // ---- inner sign with step refinement ----------------------------------------
 constexpr double kULo = -40.0, kUHi = 45.0;  // u range of the tau = e^u quadrature
@@ -415,7 +432,9 @@ ovs_status ovs_set_params(ovs_lattice l, double m_w, double mu) {
 }
 
 ovs_status ovs_set_debug(ovs_lattice l, int32_t flags, int32_t breakdown_at) {
-  if (!l || l->parent || (flags & ~OVS_DEBUG_CHECKS) || breakdown_at < -1) return OVS_ERR_ARG;
+  if (!l || l->parent ||
+      (flags & ~(OVS_DEBUG_CHECKS | OVS_DEBUG_PROGRESS | OVS_DEBUG_RANGES)) || breakdown_at < -1)
+    return OVS_ERR_ARG;
   l->debug_flags = flags;
   l->debug_breakdown_at = breakdown_at;
   return OVS_OK;
@@ -964,6 +983,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     m = n_defl;
   }
   const bool arn = method == OVS_ARNOLDI;
+  Ranges rg(ws_bytes ? nullptr : l, "ovs_sign_apply");
   const bool two_pass = (flags & OVS_FLAG_TWO_PASS) != 0;
   const bool use_persist = (flags & OVS_FLAG_PERSISTENT) != 0;
   const bool use_graph = (flags & OVS_FLAG_GRAPH) != 0 && !use_persist;
@@ -997,7 +1017,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     unsigned* bar;
   } B{};
   const bool probing = tol != nullptr;
-  const bool debug = (l->debug_flags & OVS_DEBUG_CHECKS) != 0;
+  const bool debug = (l->debug_flags & OVS_DEBUG_CHECKS) != 0;  // progress alone checks nothing
   const bool monitor = debug && !arn && !two_pass;  // biorthogonality rows need the stored V
   const int P = (int)std::min<long>(kProbe, 12L * l->g.V);
   auto layout = [&](Arena& a) {
@@ -1141,6 +1161,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   const Hop hA = make_hop(l->m_w, l->mu), hAd = make_hop(l->m_w, -l->mu);
 
   // ---- deflation and start vectors ----
+  rg.phase("deflation");
   OVS_HIP(hipEventRecord(ev[0], s));
   launch_pack_f64((const double2*)b, B.Bq, nr, l->g, s);
   if (m > 0)
@@ -1152,6 +1173,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   OVS_HIP(hipMemcpyAsync(sums.data(), B.sums, sizeof(double) * nr * 3, hipMemcpyDeviceToHost, s));
   if (m > 0)
     OVS_HIP(hipMemcpyAsync(sumsb.data(), B.sumsb, sizeof(double) * nr * 3, hipMemcpyDeviceToHost, s));
+  rg.phase(arn ? "arnoldi" : "lanczos");
   OVS_HIP(hipEventRecord(ev[1], s));
   OVS_HIP(hipStreamSynchronize(s));
   if (m == 0) sumsb = sums;
@@ -1479,6 +1501,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
         return OVS_ERR_HIP;
       }
     }
+    rg.phase("inner_sign");
     OVS_HIP(hipEventRecord(ev[2], s));
     OVS_HIP(hipMemcpyAsync(hkstop.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
     OVS_HIP(hipMemcpyAsync(hstatus.data(), B.status, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
@@ -1496,6 +1519,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       st = debug_inner(true);
       if (st != OVS_OK) return st;
     }
+    rg.phase("combine");
     OVS_HIP(hipEventRecord(ev[3], s));
     launch_make_coef(B.x, B.sv, B.nb, K, nr, B.coef, s);
     if (!two_pass) {
@@ -1610,6 +1634,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
         if (all_done) break;
       }
     }
+    rg.phase("inner_sign");
     OVS_HIP(hipEventRecord(ev[2], s));
     OVS_HIP(hipMemcpyAsync(hkstop.data(), B.kstop, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
     OVS_HIP(hipMemcpyAsync(hstatus.data(), B.status, sizeof(int) * nr, hipMemcpyDeviceToHost, s));
@@ -1627,6 +1652,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       st = debug_inner(false);
       if (st != OVS_OK) return st;
     }
+    rg.phase("combine");
     OVS_HIP(hipEventRecord(ev[3], s));
     launch_make_coef(B.x, nullptr, B.nb, K, nr, B.coef, s);
     launch_combine(f32, B.basis, bstride, N, B.coef, K, B.kused, B.yex, B.Y, nr, s);

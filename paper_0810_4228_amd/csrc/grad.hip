@@ -141,6 +141,22 @@ __global__ void __launch_bounds__(kScalarWG) k_gf_norm(GradScalars s, const doub
   set_coef(s, kTabNorm, 0, r, {nb > 0.0 ? 1.0 / nb : 0.0, 0.0});
 }
 
+__global__ void __launch_bounds__(kScalarWG) k_gf_start(GradScalars s, const double* part, int nchunk) {
+  const int r = blockIdx.x;
+  Cx<double> d[2];
+  wg_dot_sums<2>({part, part}, {0, 1}, r, nchunk, d);
+  if (threadIdx.x != 0) return;
+  const double nb = sqrt(d[0].re);
+  const Cx<double> sig = d[1];
+  s.nb[r] = nb;
+  s.sigma[r] = d2(sig);
+  s.status[r] = 0;
+  set_coef(s, kTabNorm, 0, r, {nb > 0.0 ? 1.0 / nb : 0.0, 0.0});
+  const bool ok = nb > 0.0 && (sig.re != 0.0 || sig.im != 0.0);
+  set_coef(s, kTabStartW, 0, r, ok ? cdiv(Cx<double>{nb, 0.0}, cconj(sig)) : Cx<double>{0.0, 0.0});
+  if (!ok) s.status[r] = 2;  // no biorthogonal start: the gradient is not defined
+}
+
 // alpha_i = w_i^dagger t_i (dot 0), |t_i|^2 (dot 1); coefficient rows of the update.
 __global__ void __launch_bounds__(kScalarWG) k_gf_alpha(GradScalars s, int i, const double* part, int nchunk) {
   const int r = blockIdx.x;
@@ -188,6 +204,9 @@ __global__ void __launch_bounds__(kScalarWG) k_gf_beta(GradScalars s, int i, con
 
 void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
   hipLaunchKernelGGL(k_gf_norm, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, nchunk);
+}
+void launch_gf_start(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gf_start, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, nchunk);
 }
 void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st) {
   hipLaunchKernelGGL(k_gf_alpha, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part, nchunk);
@@ -318,6 +337,38 @@ __global__ void __launch_bounds__(kScalarWG) k_gr_final(GradScalars s, const dou
   const double nbar = (cy[0] - uv) / nb;
   set_coef(s, kTabFin, 0, r, {1.0 / nb, 0.0});
   set_coef(s, kTabFin, 1, r, {nbar, 0.0});
+}
+
+__global__ void __launch_bounds__(kScalarWG) k_gr_final_defl(GradScalars s, const double* part_v,
+                                                             const double* part_w, int nchunk) {
+  __shared__ double lds[kScalarWG / 64];
+  const int r = blockIdx.x;
+  const long rk = (long)r * s.kmax;
+  Cx<double> d[2];
+  wg_dot_sums<2>({part_v, part_w}, {0, 0}, r, nchunk, d);
+  double cy[1] = {0.0};
+  for (int i = threadIdx.x; i < s.kmax; i += blockDim.x) {
+    const Cx<double> p = cmulc(c64(s.xbar[rk + i]), c64(s.x[rk + i]));
+    cy[0] += p.re;
+  }
+  block_sum<1>(cy, lds);
+  if (threadIdx.x != 0) return;
+  const double nb = s.nb[r];
+  const Cx<double> sig = c64(s.sigma[r]);
+  const Cx<double> rho = cconj(d[1]);           // wbar_1^dagger w_1
+  const double nbar = (cy[0] - d[0].re + rho.re) / nb;
+  const Cx<double> tau = -cdiv(rho, cconj(sig));
+  set_coef(s, kTabFin, 0, r, {1.0 / nb, 0.0});
+  set_coef(s, kTabFin, 1, r, tau);
+  set_coef(s, kTabFin, 2, r, {nbar / nb, 0.0});
+  set_coef(s, kTabFinW, 0, r, cdiv(Cx<double>{nb, 0.0}, sig));
+  set_coef(s, kTabFinW, 1, r, cconj(tau));
+}
+
+void launch_gr_final_defl(const GradScalars& s, const double* part_v, const double* part_w,
+                          int nchunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_gr_final_defl, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part_v, part_w,
+                     nchunk);
 }
 
 void launch_gr_first(const GradScalars& s, hipStream_t st) {

@@ -1,7 +1,29 @@
 // ovs_sign_apply_vjp: the gradient of L = sum_r Re <chi_r, y_r> with
-// y_r = |b_r| V_k sgn(G_k) e_1 (two-sided Lanczos of Section 4 at fixed k,
-// no deflation) with respect to the sources b, the chemical potential mu and
-// the links U.
+// y_r = |b_r| V_k sgn(G_k) e_1 (two-sided Lanczos of Section 4 at fixed k)
+// with respect to the sources b, the chemical potential mu and the links U;
+// with m LR-deflation eigentriples (Section 3) y_r = R S L^dagger b_r +
+// |b_R| V_k sgn(G_k) e_1 from the starts b_R = (1 - R L^dagger) b_r,
+// b_L = (1 - L R^dagger) b_r.
+//
+// Deflated gradient.  With A = sum_k lambda_k r_k l_k^dagger, c = L^dagger b,
+// s_j = sgn Re lambda_j and g_j(z) = (sgn z - s_j) / (z - lambda_j) (zero
+// where sgn z = s_j), the Daleckii-Krein form of d sgn(A) splits
+// dL = Re chi^dagger d sgn(A) b into
+//   (i)   the complement block, the Krylov derivative of the deflated run
+//         with the operator taken as Q A Q (Q = 1 - R L^dagger): the forces
+//         Re <tbar, dA v> and Re <sbar, dA^dagger w> of the sweep act through
+//         Q^dagger tbar and Q sbar;
+//   (ii)  sum_j Re <(r_j^dagger chi) l_j, dA g_j(A) b_R>, with g_j(A) b_R =
+//         |b_R| V_k g_j(G_k) e_1 = |b_R| V_k (G_k - lambda_j)^{-1} (x - s_j e_1)
+//         taken from the same basis, so that it joins the force of step i as
+//         the extra vector sum_j conj(|b_R| z_ji) (r_j^dagger chi) l_j;
+//   (iii) sum_j Re <conj(c_j) q_j, dA r_j>, q_j = g_j(A)^dagger chi: the
+//         deflated part sum_{k != j} l_k (s_k - s_j) / (conj lambda_k -
+//         conj lambda_j) (r_k^dagger chi) in closed form, the complement part
+//         by a second two-sided Lanczos run on A^dagger from Q^dagger chi (left
+//         start Q chi) as |.| V' (G' - conj lambda_j)^{-1} (sgn(G') e_1 - s_j e_1).
+// The eigentriples are those of A at the current (mu, U); the sources enter
+// through grad_b = Q^dagger bbar_R + Q bbar_L + L S R^dagger chi.
 //
 // Forward: the recurrences (4.1)-(4.4) in FP64.  By default only checkpoints
 // are kept: the pairs (v_{jc-1}, v_{jc}), (w_{jc-1}, w_{jc}) every c = ceil(sqrt k)
@@ -20,12 +42,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <vector>
 
 #include "ovs_common.h"
 #include "ovs_grad.h"
 #include "ovs_host.h"
+#include "ovs_krylov.h"
 
 using namespace ovs;
 
@@ -49,16 +73,58 @@ double max_rel_change(const std::vector<double2>& a, const std::vector<double2>&
   return den > 0.0 ? num / den : num;
 }
 
+using cd = std::complex<double>;
+
+// z = (T - shift)^{-1} rhs for the tridiagonal T (diagonal d, T(i+1,i) = lo_i,
+// T(i,i+1) = up_i), Gaussian elimination with partial pivoting; false if a
+// pivot vanishes.
+bool tri_solve(int n, const cd* d, const cd* lo, const cd* up, cd shift, std::vector<cd>& z) {
+  std::vector<cd> D(n), DU(std::max(n - 1, 1)), DL(std::max(n - 1, 1)), DU2(std::max(n - 1, 1), 0.0);
+  for (int i = 0; i < n; ++i) D[i] = d[i] - shift;
+  for (int i = 0; i + 1 < n; ++i) {
+    DU[i] = up[i];
+    DL[i] = lo[i];
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    if (std::abs(D[i]) >= std::abs(DL[i])) {
+      if (D[i] == 0.0) return false;
+      const cd f = DL[i] / D[i];
+      D[i + 1] -= f * DU[i];
+      z[i + 1] -= f * z[i];
+    } else {  // rows i and i + 1 interchanged
+      const cd f = D[i] / DL[i];
+      D[i] = DL[i];
+      const cd t = D[i + 1];
+      D[i + 1] = DU[i] - f * t;
+      if (i + 2 < n) {
+        DU2[i] = DU[i + 1];
+        DU[i + 1] = -f * DU[i + 1];
+      }
+      DU[i] = t;
+      std::swap(z[i], z[i + 1]);
+      z[i + 1] -= f * z[i];
+    }
+  }
+  if (D[n - 1] == 0.0) return false;
+  z[n - 1] /= D[n - 1];
+  if (n > 1) z[n - 2] = (z[n - 2] - DU[n - 2] * z[n - 1]) / D[n - 2];
+  for (int i = n - 3; i >= 0; --i) z[i] = (z[i] - DU[i] * z[i + 1] - DU2[i] * z[i + 2]) / D[i];
+  return true;
+}
+
 }  // namespace
 
 // The vjp proper; with ws_query != NULL only the workspace it needs is
 // computed (the other pointers are not used).
-static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_t nrhs, int32_t k,
-                           int32_t flags, void* y, void* grad_b, double* grad_mu, void* grad_U,
-                           double* quad_err, void* user_ws, size_t user_ws_bytes,
-                           size_t* ws_query) {
+static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, const void* b,
+                           const void* chi, int32_t nrhs, int32_t k, int32_t flags, void* y,
+                           void* grad_b, double* grad_mu, void* grad_U, double* quad_err,
+                           void* user_ws, size_t user_ws_bytes, size_t* ws_query) {
   if (!l || (!ws_query && (!b || !chi || !grad_b || !grad_mu || !grad_U))) return OVS_ERR_ARG;
   if (nrhs < 1 || nrhs > kMaxNrhs || k < 1 || k > 65535) return OVS_ERR_ARG;
+  if (n_defl < 0 || (n_defl > 0 && (!defl || defl->lat != l || n_defl > defl->m)))
+    return OVS_ERR_ARG;
+  const int md = n_defl;  // deflated eigentriples (0: none)
   if (flags & ~OVS_VJP_STORE_BASIS) return OVS_ERR_ARG;
   if (l->prec != OVS_F64 || l->parent) return OVS_ERR_ARG;
   if (!ws_query && !ready(l)) return OVS_ERR_STATE;
@@ -79,8 +145,32 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
     double *parts, *fparts, *gmu;
     void* vjp;
     IsignVjpOut vo[2];
+    // deflation: projected sources and chi, projected forces, the second run
+    // on A^dagger (full basis V2, ring W2), its coefficients
+    double2 *BR, *BL, *YEX, *CHIL, *CHIR, *YCHI, *TBp, *WTBp, *V2, *W2, *QJ;
+    double *CDb, *CDchi, *CDt, *dpart;
+    double2 *kappa, *coefQ, *coefL;
+    int* kused;
   } P_{};
-  GradScalars S{};
+  GradScalars S{}, S2{};
+  auto carve_scalars = [&](Arena& a, GradScalars& Sx) {
+    const size_t nk = (size_t)nrhs * k;
+    Sx.alpha = a.take<double2>(nk);
+    Sx.beta = a.take<double>(nk);
+    Sx.gamma = a.take<double2>(nk);
+    Sx.tnorm2 = a.take<double>(nk);
+    Sx.x = a.take<double2>(nk);
+    Sx.xbar = a.take<double2>(nk);
+    Sx.abar = a.take<double2>(nk);
+    Sx.bbar = a.take<double>(nk);
+    Sx.gbar = a.take<double2>(nk);
+    Sx.nb = a.take<double>(nrhs);
+    Sx.sigma = a.take<double2>(nrhs);
+    Sx.status = a.take<int>(nrhs);
+    Sx.coef = a.take<double2>((size_t)kCoefTables * kLinTerms * nrhs);
+    Sx.kmax = k;
+    Sx.nrhs = nrhs;
+  };
   auto carve = [&](Arena& a) {
     if (store) {
       P_.V = a.take<double2>((size_t)k * NF);
@@ -93,21 +183,7 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
     }
     for (int j = 0; j < kFields; ++j) P_.fld[j] = a.take<double2>(NF);
     P_.Fg = a.take<double2>(5L * 9 * g.Vs);
-    const size_t nk = (size_t)nrhs * k;
-    S.alpha = a.take<double2>(nk);
-    S.beta = a.take<double>(nk);
-    S.gamma = a.take<double2>(nk);
-    S.tnorm2 = a.take<double>(nk);
-    S.x = a.take<double2>(nk);
-    S.xbar = a.take<double2>(nk);
-    S.abar = a.take<double2>(nk);
-    S.bbar = a.take<double>(nk);
-    S.gbar = a.take<double2>(nk);
-    S.nb = a.take<double>(nrhs);
-    S.status = a.take<int>(nrhs);
-    S.coef = a.take<double2>((size_t)kCoefTables * kLinTerms * nrhs);
-    S.kmax = k;
-    S.nrhs = nrhs;
+    carve_scalars(a, S);
     P_.parts = a.take<double>((size_t)4 * nrhs * nch * 2 * kLinDots);
     P_.fparts = a.take<double>((size_t)(g.V + kWG - 1) / kWG + 1);
     P_.gmu = a.take<double>(1);
@@ -117,6 +193,21 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
       P_.vo[lv].gd = a.take<double2>(k);
       P_.vo[lv].gsub_re = a.take<double>(k);
       P_.vo[lv].gsup = a.take<double2>(k);
+    }
+    if (md > 0) {
+      for (double2** f : {&P_.BR, &P_.BL, &P_.YEX, &P_.CHIL, &P_.CHIR, &P_.YCHI, &P_.TBp, &P_.WTBp})
+        *f = a.take<double2>(NF);
+      P_.V2 = a.take<double2>((size_t)k * NF);
+      P_.W2 = a.take<double2>((size_t)3 * NF);
+      P_.QJ = a.take<double2>(F);
+      carve_scalars(a, S2);
+      for (double** c : {&P_.CDb, &P_.CDchi, &P_.CDt})
+        *c = a.take<double>((size_t)md * nrhs * 4);
+      P_.dpart = a.take<double>((size_t)md * nrhs * defl_nchunk(F) * 4);
+      P_.kappa = a.take<double2>((size_t)k * nrhs * md);
+      P_.coefQ = a.take<double2>((size_t)md * k * nrhs);
+      P_.coefL = a.take<double2>((size_t)md * md);
+      P_.kused = a.take<int>(2);
     }
   };
   Arena sizing{nullptr};
@@ -136,6 +227,8 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
   }
   ovs_status st = OVS_OK;
   StreamScope scope(l);
+  Ranges rg(l, "ovs_sign_apply_vjp");
+  rg.phase("forward");
   Arena arena{ws_base};
   carve(arena);
   double2** fld = P_.fld;
@@ -152,11 +245,22 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
   // every field starts at zero (pads stay zero: the stencil writes sites < V only)
   OVS_HIP(hipMemsetAsync(P_.V, 0, (size_t)((char*)(fld[kFields - 1] + NF) - (char*)P_.V),
                          l->stream));
+  if (md > 0) {
+    for (double2* f : {P_.BR, P_.BL, P_.YEX, P_.CHIL, P_.CHIR, P_.YCHI, P_.TBp, P_.WTBp})
+      OVS_HIP(hipMemsetAsync(f, 0, sizeof(double2) * NF, l->stream));
+    OVS_HIP(hipMemsetAsync(P_.V2, 0, sizeof(double2) * (size_t)k * NF, l->stream));
+    OVS_HIP(hipMemsetAsync(P_.W2, 0, sizeof(double2) * 3 * NF, l->stream));
+    OVS_HIP(hipMemsetAsync(P_.QJ, 0, sizeof(double2) * F, l->stream));
+    OVS_HIP(hipMemsetAsync(S2.xbar, 0, sizeof(double2) * (size_t)nrhs * k, l->stream));
+  }
   OVS_HIP(hipMemsetAsync(P_.Fg, 0, sizeof(double2) * 5 * 9 * g.Vs, l->stream));
   {
     std::vector<double2> ones((size_t)kLinTerms * nrhs, make_double2(1.0, 0.0));
     OVS_HIP(hipMemcpyAsync(coef_table(S, kTabOne), ones.data(), sizeof(double2) * ones.size(),
                            hipMemcpyHostToDevice, l->stream));
+    if (md > 0)
+      OVS_HIP(hipMemcpyAsync(coef_table(S2, kTabOne), ones.data(), sizeof(double2) * ones.size(),
+                             hipMemcpyHostToDevice, l->stream));
     OVS_HIP(hipStreamSynchronize(l->stream));
   }
   launch_pack_f64((const double2*)b, B, nrhs, g, l->stream);
@@ -170,13 +274,14 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
   auto applyAd = [&](const double2* in, double2* out) {
     return launch_wilson(false, l->links, in, out, nrhs, g, hAd, false, true, tn, l->stream);
   };
-  auto mk = [&](std::initializer_list<const double2*> xs, int tab, double2* out, bool acc,
-                std::initializer_list<const double2*> ys, int ndot, double* part) {
+  auto mks = [&](const GradScalars& Sx, std::initializer_list<const double2*> xs, int tab,
+                 double2* out, bool acc, std::initializer_list<const double2*> ys, int ndot,
+                 double* part) {
     LinArgs la;
     int j = 0;
     for (const double2* p : xs) la.x[j++] = p;
     la.nterm = j;
-    la.coef = coef_table(S, tab);
+    la.coef = coef_table(Sx, tab);
     la.out = out;
     la.accumulate = acc ? 1 : 0;
     j = 0;
@@ -188,9 +293,17 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
     la.partials = part;
     return la;
   };
+  auto mk = [&](std::initializer_list<const double2*> xs, int tab, double2* out, bool acc,
+                std::initializer_list<const double2*> ys, int ndot, double* part) {
+    return mks(S, xs, tab, out, acc, ys, ndot, part);
+  };
   auto lin = [&](std::initializer_list<const double2*> xs, int tab, double2* out, bool acc,
                  std::initializer_list<const double2*> ys, int ndot, double* part) {
     launch_lin(mk(xs, tab, out, acc, ys, ndot, part), F, nrhs, l->stream);
+  };
+  auto lin2 = [&](std::initializer_list<const double2*> xs, int tab, double2* out, bool acc,
+                  std::initializer_list<const double2*> ys, int ndot, double* part) {
+    launch_lin(mks(S2, xs, tab, out, acc, ys, ndot, part), F, nrhs, l->stream);
   };
   // independent combinations (none reads another's output) in one launch
   auto multi = [&](std::initializer_list<LinArgs> las) {
@@ -219,12 +332,28 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
     return e;
   };
 
-  // ---- forward: v_1 = w_1 = b/|b|, then the recurrences ----
-  lin({B}, kTabOne, nullptr, false, {nullptr}, 1, P[0]);
-  launch_gf_norm(S, P[0], nch, l->stream);
-  lin({B}, kTabNorm, Vf(0), false, {CHI}, 1, P[3]);
-  launch_gf_xbar(S, 0, P[3], nch, l->stream);
-  lin({B}, kTabNorm, Wf(0), false, {}, 0, nullptr);
+  // ---- forward: v_1 = w_1 = b/|b| (deflated: v_1 = b_R/|b_R|, w_1 = b_L
+  // |b_R| / conj(b_L^dagger b_R)), then the recurrences ----
+  const ovs_deflation_s* d = defl;
+  if (md > 0) {
+    launch_defl(d->R, d->L, B, d->sgn, md, nrhs, F, P_.dpart, P_.CDb, P_.BR, P_.BL, P_.YEX,
+                l->stream);
+    // roles swapped: Q^dagger chi, Q chi and L S R^dagger chi; CDchi = (R^dag chi, L^dag chi)
+    launch_defl(d->L, d->R, CHI, d->sgn, md, nrhs, F, P_.dpart, P_.CDchi, P_.CHIL, P_.CHIR,
+                P_.YCHI, l->stream);
+    lin({P_.BR}, kTabOne, nullptr, false, {nullptr, P_.BL}, 2, P[0]);
+    launch_gf_start(S, P[0], nch, l->stream);
+    lin({P_.BR}, kTabNorm, Vf(0), false, {CHI}, 1, P[3]);
+    launch_gf_xbar(S, 0, P[3], nch, l->stream);
+    lin({P_.BL}, kTabStartW, Wf(0), false, {}, 0, nullptr);
+    if (y) OVS_HIP(copy(YA, P_.YEX));
+  } else {
+    lin({B}, kTabOne, nullptr, false, {nullptr}, 1, P[0]);
+    launch_gf_norm(S, P[0], nch, l->stream);
+    lin({B}, kTabNorm, Vf(0), false, {CHI}, 1, P[3]);
+    launch_gf_xbar(S, 0, P[3], nch, l->stream);
+    lin({B}, kTabNorm, Wf(0), false, {}, 0, nullptr);
+  }
   OVS_HIP(save_ckpt(0));
   for (int i = 0; i < k; ++i) {
     OVS_HIP(applyA(Vf(i), T));
@@ -255,6 +384,7 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
     if (status[r] != 0) return OVS_WARN_BREAKDOWN;  // the gradient needs k full iterations
 
   // ---- inner sign and its VJP ----
+  rg.phase("inner_sign_vjp");
   ovs_status result = OVS_OK;
   for (int r = 0; r < nrhs; ++r) {
     const size_t rk = (size_t)r * k;
@@ -299,7 +429,190 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
     }
   }
 
+  // ---- deflated gradient: the coefficients of term (ii) and the forces of
+  // term (iii) (see the head of this file) ----
+  if (md > 0) {
+    rg.phase("deflation_terms");
+    const size_t nk = (size_t)nrhs * k;
+    std::vector<cd> lam(md);
+    std::vector<double> sg(md);
+    for (int j = 0; j < md; ++j) {
+      lam[j] = cd(d->lambda[2 * j], d->lambda[2 * j + 1]);
+      sg[j] = d->lambda[2 * j] >= 0.0 ? 1.0 : -1.0;  // as the forward's sgn table
+    }
+    std::vector<double> cdb((size_t)md * nrhs * 4), cdchi((size_t)md * nrhs * 4);
+    OVS_HIP(hipMemcpyAsync(cdb.data(), P_.CDb, sizeof(double) * cdb.size(), hipMemcpyDeviceToHost,
+                           l->stream));
+    OVS_HIP(hipMemcpyAsync(cdchi.data(), P_.CDchi, sizeof(double) * cdchi.size(),
+                           hipMemcpyDeviceToHost, l->stream));
+    auto cb = [&](int j, int r) {  // l_j^dagger b_r
+      return cd(cdb[((size_t)j * nrhs + r) * 4], cdb[((size_t)j * nrhs + r) * 4 + 1]);
+    };
+    auto rchi = [&](int j, int r) {  // r_j^dagger chi_r
+      return cd(cdchi[((size_t)j * nrhs + r) * 4], cdchi[((size_t)j * nrhs + r) * 4 + 1]);
+    };
+    // G_k of each source (host) from the run's coefficients
+    struct Tri {
+      std::vector<cd> d, lo, up, x;
+      std::vector<double> nb;
+    };
+    auto fetch = [&](const GradScalars& Sx, Tri& t) -> hipError_t {
+      std::vector<double2> a(nk), gm(nk), xx(nk);
+      std::vector<double> bt(nk);
+      t.nb.resize(nrhs);
+      hipError_t e = hipMemcpyAsync(a.data(), Sx.alpha, sizeof(double2) * nk, hipMemcpyDeviceToHost, l->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(gm.data(), Sx.gamma, sizeof(double2) * nk, hipMemcpyDeviceToHost, l->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(xx.data(), Sx.x, sizeof(double2) * nk, hipMemcpyDeviceToHost, l->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(bt.data(), Sx.beta, sizeof(double) * nk, hipMemcpyDeviceToHost, l->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(t.nb.data(), Sx.nb, sizeof(double) * nrhs, hipMemcpyDeviceToHost, l->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(l->stream);
+      t.d.resize(nk);
+      t.lo.resize(nk);
+      t.up.resize(nk);
+      t.x.resize(nk);
+      for (size_t q = 0; q < nk; ++q) {
+        t.d[q] = cd(a[q].x, a[q].y);
+        t.up[q] = cd(gm[q].x, gm[q].y);
+        t.lo[q] = cd(bt[q], 0.0);
+        t.x[q] = cd(xx[q].x, xx[q].y);
+      }
+      return e;
+    };
+    // z = (G_r - shift)^{-1} (x_r - s e_1)
+    auto zsolve = [&](const Tri& t, int r, cd shift, double sj, std::vector<cd>& z) -> bool {
+      const size_t rk = (size_t)r * k;
+      z.assign(t.x.begin() + rk, t.x.begin() + rk + k);
+      z[0] -= sj;
+      return tri_solve(k, &t.d[rk], &t.lo[rk], &t.up[rk], shift, z);
+    };
+    Tri t1;
+    OVS_HIP(fetch(S, t1));
+    std::vector<double2> kap((size_t)k * nrhs * md);
+    std::vector<cd> z(k);
+    for (int r = 0; r < nrhs; ++r)
+      for (int j = 0; j < md; ++j) {
+        if (!zsolve(t1, r, lam[j], sg[j], z)) return OVS_WARN_BREAKDOWN;
+        const cd a = rchi(j, r);
+        for (int i = 0; i < k; ++i) {
+          const cd v = std::conj(t1.nb[r] * z[i]) * a;
+          kap[((size_t)i * nrhs + r) * md + j] = make_double2(v.real(), v.imag());
+        }
+      }
+    OVS_HIP(hipMemcpyAsync(P_.kappa, kap.data(), sizeof(double2) * kap.size(),
+                           hipMemcpyHostToDevice, l->stream));
+
+    // second run: A^dagger from Q^dagger chi, left start Q chi, full basis kept
+    auto V2 = [&](int i) { return P_.V2 + (size_t)i * NF; };
+    auto W2 = [&](int i) { return P_.W2 + (size_t)(i % 3) * NF; };
+    lin2({P_.CHIL}, kTabOne, nullptr, false, {nullptr, P_.CHIR}, 2, P[0]);
+    launch_gf_start(S2, P[0], nch, l->stream);
+    lin2({P_.CHIL}, kTabNorm, V2(0), false, {}, 0, nullptr);
+    lin2({P_.CHIR}, kTabStartW, W2(0), false, {}, 0, nullptr);
+    for (int i = 0; i < k; ++i) {
+      OVS_HIP(applyAd(V2(i), T));
+      lin2({T}, kTabOne, nullptr, false, {W2(i), nullptr}, 2, P[0]);
+      launch_gf_alpha(S2, i, P[0], nch, l->stream);
+      if (i == k - 1) break;
+      OVS_HIP(applyA(W2(i), Sv));
+      if (i > 0) {
+        lin2({T, V2(i), V2(i - 1)}, kTabV, V2(i + 1), false, {nullptr}, 1, P[1]);
+        lin2({Sv, W2(i), W2(i - 1)}, kTabW, W2(i + 1), false, {V2(i + 1), nullptr}, 2, P[2]);
+      } else {
+        lin2({T, V2(i)}, kTabV, V2(i + 1), false, {nullptr}, 1, P[1]);
+        lin2({Sv, W2(i)}, kTabW, W2(i + 1), false, {V2(i + 1), nullptr}, 2, P[2]);
+      }
+      launch_gf_beta(S2, i, P[1], P[2], nch, l->stream);
+      multi({mks(S2, {V2(i + 1)}, kTabSV, V2(i + 1), false, {}, 0, nullptr),
+             mks(S2, {W2(i + 1)}, kTabSW, W2(i + 1), false, {}, 0, nullptr)});
+    }
+    OVS_HIP(hipGetLastError());
+    OVS_HIP(hipMemcpyAsync(status.data(), S2.status, sizeof(int) * nrhs, hipMemcpyDeviceToHost,
+                           l->stream));
+    OVS_HIP(hipStreamSynchronize(l->stream));
+    for (int r = 0; r < nrhs; ++r)
+      if (status[r] != 0) return OVS_WARN_BREAKDOWN;
+    // x' = sgn(G') e_1 by the same quadrature (zero adjoint seed)
+    for (int r = 0; r < nrhs; ++r) {
+      const size_t rk = (size_t)r * k;
+      std::vector<double2> prev, cur;
+      double h = kVjpHStart, change = 0.0;
+      int lv = 0, used = 0;
+      for (;; h *= 0.5, lv ^= 1) {
+        int n0, nn;
+        vjp_range(h, n0, nn);
+        launch_isign_vjp(S2.alpha + rk, S2.beta + rk, S2.gamma + rk, S2.xbar + rk, k, h, n0, nn,
+                         P_.vjp, P_.vo[lv], l->stream);
+        OVS_HIP(hipGetLastError());
+        cur.assign(k, make_double2(0.0, 0.0));
+        OVS_HIP(hipMemcpyAsync(cur.data(), P_.vo[lv].x, sizeof(double2) * k,
+                               hipMemcpyDeviceToHost, l->stream));
+        OVS_HIP(hipStreamSynchronize(l->stream));
+        used = lv;
+        if (!prev.empty()) {
+          change = max_rel_change(cur, prev);
+          if (change <= kVjpAccept) break;
+        }
+        if (h <= kVjpHMin) break;
+        prev.swap(cur);
+      }
+      if (change > 1e-6) result = OVS_WARN_SIGN_AMBIGUOUS;
+      OVS_HIP(hipMemcpyAsync(S2.x + rk, P_.vo[used].x, sizeof(double2) * k,
+                             hipMemcpyDeviceToDevice, l->stream));
+    }
+    Tri t2;
+    OVS_HIP(fetch(S2, t2));
+    std::vector<double2> cq((size_t)md * k * nrhs), cl((size_t)md * md, make_double2(0.0, 0.0));
+    for (int j = 0; j < md; ++j) {
+      for (int r = 0; r < nrhs; ++r) {
+        if (!zsolve(t2, r, std::conj(lam[j]), sg[j], z)) return OVS_WARN_BREAKDOWN;
+        const cd w = std::conj(cb(j, r)) * t2.nb[r];
+        for (int i = 0; i < k; ++i) {
+          const cd v = w * z[i];
+          cq[(size_t)j * k * nrhs + (size_t)i * nrhs + r] = make_double2(v.real(), v.imag());
+        }
+      }
+      for (int q = 0; q < md; ++q) {
+        if (q == j || sg[q] == sg[j]) continue;
+        cd v = 0.0;
+        for (int r = 0; r < nrhs; ++r) v += std::conj(cb(j, r)) * rchi(q, r);
+        v *= (sg[q] - sg[j]) / (std::conj(lam[q]) - std::conj(lam[j]));
+        cl[(size_t)j * md + q] = make_double2(v.real(), v.imag());
+      }
+    }
+    const int ku[2] = {k * nrhs, md};
+    OVS_HIP(hipMemcpyAsync(P_.coefQ, cq.data(), sizeof(double2) * cq.size(), hipMemcpyHostToDevice,
+                           l->stream));
+    OVS_HIP(hipMemcpyAsync(P_.coefL, cl.data(), sizeof(double2) * cl.size(), hipMemcpyHostToDevice,
+                           l->stream));
+    OVS_HIP(hipMemcpyAsync(P_.kused, ku, sizeof(ku), hipMemcpyHostToDevice, l->stream));
+    // Q_j = sum_r conj(c_jr) q_jr, force Re <Q_j, dA r_j>
+    for (int j = 0; j < md; ++j) {
+      launch_combine(false, P_.V2, F, F, P_.coefQ + (size_t)j * k * nrhs, k * nrhs, P_.kused,
+                     nullptr, P_.QJ, 1, l->stream);
+      launch_combine(false, d->L, F, F, P_.coefL + (size_t)j * md, md, P_.kused + 1, P_.QJ, P_.QJ,
+                     1, l->stream);
+      launch_gforce(P_.Fg, P_.QJ, d->R + (size_t)j * F, nullptr, nullptr, F, 1, g, hA, hAd,
+                    l->stream);
+    }
+    OVS_HIP(hipGetLastError());
+    OVS_HIP(hipStreamSynchronize(l->stream));  // host coefficient vectors are released
+  }
+  // forces of the sweep: Q^dagger tbar (+ the term (ii) vector of step i) and Q sbar
+  auto ptb = [&](int i, const double2* tb) -> const double2* {
+    if (md == 0) return tb;
+    launch_defl_proj(d->R, d->L, tb, md, nrhs, F, P_.dpart, P_.CDt,
+                     P_.kappa + (size_t)i * nrhs * md, nullptr, P_.TBp, l->stream);
+    return P_.TBp;
+  };
+  auto psb = [&](const double2* sb) -> const double2* {
+    if (md == 0) return sb;
+    launch_defl_proj(d->R, d->L, sb, md, nrhs, F, P_.dpart, P_.CDt, nullptr, P_.WTBp, nullptr,
+                     l->stream);
+    return P_.WTBp;
+  };
+
   // ---- reverse sweep, segment by segment from the last ----
+  rg.phase("reverse_sweep");
   for (int j = nseg - 1; j >= 0; --j) {
     const int lo = j * cseg, hi = std::min((j + 1) * cseg, k) - 1;
     if (!store) {
@@ -336,7 +649,7 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
         launch_lin_multi(m0, F, nrhs, l->stream);
         OVS_HIP(applyAd(TB, T1));
         lin({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]);    // vbar += A^dag tbar
-        launch_gforce(P_.Fg, TB, Vr(i), nullptr, nullptr, F, nrhs, g, hA, hAd, l->stream);
+        launch_gforce(P_.Fg, ptb(i, TB), Vr(i), nullptr, nullptr, F, nrhs, g, hA, hAd, l->stream);
         continue;
       }
       const int c = i & 1, p = (i + 1) & 1;
@@ -362,13 +675,31 @@ static ovs_status vjp_impl(ovs_lattice l, const void* b, const void* chi, int32_
       OVS_HIP(applyA(WTB[c], T2));
       multi({mk({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]),
              mk({T2}, kTabOne, WB[c], true, {Wr(i)}, 1, P[3])});
-      launch_gforce(P_.Fg, TB, Vr(i), WTB[c], Wr(i), F, nrhs, g, hA, hAd, l->stream);
+      {
+        const double2* tbp = ptb(i, TB);
+        launch_gforce(P_.Fg, tbp, Vr(i), psb(WTB[c]), Wr(i), F, nrhs, g, hA, hAd, l->stream);
+      }
     }
   }
-  // grad_b = ubar/|b| + nbar v_1,  ubar = vbar_1 + wbar_1  (segment 0 holds v_1)
-  lin({VB[0], WB[0]}, kTabOne, T1, false, {Vr(0)}, 1, P[0]);
-  launch_gr_final(S, P[0], nch, l->stream);
-  lin({T1, Vr(0)}, kTabFin, GB, false, {}, 0, nullptr);
+  if (md > 0) {
+    // bbar_R, bbar_L from vbar_1, wbar_1, then grad_b = Q^dagger bbar_R + Q bbar_L
+    // + L S R^dagger chi  (segment 0 holds v_1, w_1)
+    lin({VB[0]}, kTabOne, nullptr, false, {Vr(0)}, 1, P[0]);
+    lin({WB[0]}, kTabOne, nullptr, false, {Wr(0)}, 1, P[1]);
+    launch_gr_final_defl(S, P[0], P[1], nch, l->stream);
+    lin({VB[0], P_.BL, P_.BR}, kTabFin, T1, false, {}, 0, nullptr);
+    lin({WB[0], P_.BR}, kTabFinW, T2, false, {}, 0, nullptr);
+    launch_defl_proj(d->R, d->L, T1, md, nrhs, F, P_.dpart, P_.CDt, nullptr, nullptr, GB,
+                     l->stream);
+    launch_defl_proj(d->R, d->L, T2, md, nrhs, F, P_.dpart, P_.CDt, nullptr, T2, nullptr,
+                     l->stream);
+    lin({T2, P_.YCHI}, kTabOne, GB, true, {}, 0, nullptr);
+  } else {
+    // grad_b = ubar/|b| + nbar v_1,  ubar = vbar_1 + wbar_1  (segment 0 holds v_1)
+    lin({VB[0], WB[0]}, kTabOne, T1, false, {Vr(0)}, 1, P[0]);
+    launch_gr_final(S, P[0], nch, l->stream);
+    lin({T1, Vr(0)}, kTabFin, GB, false, {}, 0, nullptr);
+  }
   launch_unpack_f64(GB, (double2*)grad_b, nrhs, g, l->stream);
   launch_gforce_out(P_.Fg, (const double2*)l->links, g, l->bc, (double2*)grad_U, P_.fparts,
                     P_.gmu, l->stream);
@@ -388,18 +719,20 @@ extern "C" ovs_status ovs_link_force(ovs_lattice l, const void* U, const void* g
   return OVS_OK;
 }
 
-extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, const void* b, const void* chi,
-                                         int32_t nrhs, int32_t k, int32_t flags, void* y,
-                                         void* grad_b, double* grad_mu, void* grad_U,
-                                         double* quad_err, void* workspace, size_t ws_bytes) {
-  return vjp_impl(l, b, chi, nrhs, k, flags, y, grad_b, grad_mu, grad_U, quad_err, workspace,
-                  workspace ? ws_bytes : 0, nullptr);
+extern "C" ovs_status ovs_sign_apply_vjp(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
+                                         const void* b, const void* chi, int32_t nrhs, int32_t k,
+                                         int32_t flags, void* y, void* grad_b, double* grad_mu,
+                                         void* grad_U, double* quad_err, void* workspace,
+                                         size_t ws_bytes) {
+  return vjp_impl(l, defl, n_defl, b, chi, nrhs, k, flags, y, grad_b, grad_mu, grad_U, quad_err,
+                  workspace, workspace ? ws_bytes : 0, nullptr);
 }
 
-extern "C" ovs_status ovs_vjp_workspace_size(ovs_lattice l, int32_t nrhs, int32_t k,
-                                             int32_t flags, size_t* bytes) {
+extern "C" ovs_status ovs_vjp_workspace_size(ovs_lattice l, ovs_deflation defl, int32_t n_defl,
+                                             int32_t nrhs, int32_t k, int32_t flags,
+                                             size_t* bytes) {
   if (!bytes) return OVS_ERR_ARG;
   *bytes = 0;
-  return vjp_impl(l, nullptr, nullptr, nrhs, k, flags, nullptr, nullptr, nullptr, nullptr,
-                  nullptr, nullptr, 0, bytes);
+  return vjp_impl(l, defl, n_defl, nullptr, nullptr, nrhs, k, flags, nullptr, nullptr, nullptr,
+                  nullptr, nullptr, nullptr, 0, bytes);
 }

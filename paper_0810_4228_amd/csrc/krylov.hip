@@ -106,12 +106,23 @@ __global__ void __launch_bounds__(256) k_defl_axpy(const double2* __restrict__ R
       const Cx<double> rr = c64(R[(long)j * N + e]), ll = c64(L[(long)j * N + e]);
       pr = cfma(rr, c, pr);
       pl = cfma(ll, d, pl);
-      py = cfma(rr, scale(sgn[j], c), py);
+      if (yex) py = cfma(rr, scale(sgn[j], c), py);
     }
-    bR[(long)r * N + e] = d2(b - pr);
-    bL[(long)r * N + e] = d2(b - pl);
-    yex[(long)r * N + e] = d2(py);
+    if (bR) bR[(long)r * N + e] = d2(b - pr);
+    if (bL) bL[(long)r * N + e] = d2(b - pl);
+    if (yex) yex[(long)r * N + e] = d2(py);
   }
+}
+
+// D[j][r] -= kappa[r][j] (the bL output of k_defl_axpy then gains + L kappa)
+__global__ void k_cd_shift(double* __restrict__ CD, const double2* __restrict__ kappa, int m,
+                           int nrhs) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * nrhs) return;
+  const int j = e / nrhs, r = e % nrhs;
+  const double2 k = kappa[(long)r * m + j];
+  CD[(long)e * 4 + 2] -= k.x;
+  CD[(long)e * 4 + 3] -= k.y;
 }
 
 // per-source partials of |b_R|^2 and b_L^dag b_R: [nrhs][nchunk][3]
@@ -728,6 +739,19 @@ void launch_defl(const double2* R, const double2* L, const double2* B, const dou
                      sgn, m, nrhs, N, bR, bL, yex);
 }
 
+void launch_defl_proj(const double2* R, const double2* L, const double2* X, int m, int nrhs, long N,
+                      double* partials, double* CD, const double2* kappa, double2* outQ,
+                      double2* outQd, hipStream_t s) {
+  const int nch = defl_nchunk(N);
+  hipLaunchKernelGGL(k_defl_dots, dim3(nch, m, cdiv_i(nrhs, kDeflRhs)), dim3(256), 0, s, R, L, X,
+                     nrhs, N, nch, partials);
+  hipLaunchKernelGGL(k_reduce_partials<4>, dim3(m * nrhs), dim3(256), 0, s, partials, nch, CD);
+  if (kappa)
+    hipLaunchKernelGGL(k_cd_shift, dim3(cdiv_i(m * nrhs, 256)), dim3(256), 0, s, CD, kappa, m, nrhs);
+  hipLaunchKernelGGL(k_defl_axpy, dim3(chunks_for(N, 4096), nrhs), dim3(256), 0, s, R, L, X, CD,
+                     (const double*)nullptr, m, nrhs, N, outQ, outQd, (double2*)nullptr);
+}
+
 void launch_defl_cd(const double2* R, const double2* L, const double2* B, int m, int nrhs, long N,
                     double* partials, double* CD, hipStream_t s) {
   const int nch = defl_nchunk(N);
@@ -862,6 +886,12 @@ void launch_arn_dots(bool f32, const void* basis, long basis_stride, const void*
     hipLaunchKernelGGL(k_block_dots<double2>, grid, dim3(256), 0, s, (const double2*)basis,
                        basis_stride, (const double2*)T, N, nvec, nch, partials);
   hipLaunchKernelGGL(k_reduce_partials<2>, dim3(nrhs * nvec), dim3(256), 0, s, partials, nch, red);
+}
+
+void launch_gram(const double2* X, int nx, const double2* Y, int ny, long N, double* partials,
+                 double2* G, hipStream_t s) {
+  for (int j = 0; j < ny; ++j)
+    launch_arn_dots(false, X, N, Y + (long)j * N, N, nx, 1, partials, (double*)(G + (long)j * nx), s);
 }
 
 void launch_arn_accum(const double* red, int nvec, int kmax, int j, bool first, double2* H,

@@ -30,6 +30,7 @@
 #include "dense.h"
 #include "ovs_common.h"
 #include "ovs_host.h"
+#include "ovs_krylov.h"
 
 using namespace ovs;
 
@@ -102,9 +103,10 @@ namespace ovs {
 // application returned a warning.  Arguments are checked by the callers.
 ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int ncv, int block,
                              double tol, int max_restarts, double* lambda, void* vecs,
-                             double* info) {
+                             double* info, const KrylovOptions& opt) {
   const int bs = block;
-  const long N = 12L * l->g.V;
+  const long N = opt.field_len > 0 ? opt.field_len : 12L * l->g.V;
+  const int nconv = opt.nconv > 0 ? std::min(opt.nconv, nev) : nev;
   const int m = ncv;
   StreamScope sc(l);
   hipStream_t s = l->stream;
@@ -119,9 +121,10 @@ ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int n
   auto* Hd = mem.alloc<rocblas_double_complex>((size_t)(m + bs) * bs);
   auto* Rd = mem.alloc<rocblas_double_complex>((size_t)bs * bs);
   auto* Qd = mem.alloc<rocblas_double_complex>((size_t)(m + bs) * (m + bs));
-  if (!V || !Wt || !Hd || !Rd || !Qd) return OVS_ERR_ALLOC;
+  double* gpart = mem.alloc<double>((size_t)2 * (m + bs) * arn_nchunk(N));  // dot partials
+  if (!V || !Wt || !Hd || !Rd || !Qd || !gpart) return OVS_ERR_ALLOC;
   const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0}, mone{-1.0, 0.0};
-  const auto opN = rocblas_operation_none, opC = rocblas_operation_conjugate_transpose;
+  const auto opN = rocblas_operation_none;
   const rocblas_int n32 = (rocblas_int)N;
   auto col = [&](int j) { return V + (size_t)j * N; };
   auto blas_ok = [](rocblas_status st) { return st == rocblas_status_success; };
@@ -136,8 +139,10 @@ ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int n
     hc.assign((size_t)c * bs, cd(0));
     hp.resize((size_t)c * bs);
     for (int pass = 0; pass < 2 && c > 0; ++pass) {
-      if (!blas_ok(rocblas_zgemm(bl.h, opC, opN, c, bs, n32, &one, V, n32, W, n32, &zero, Hd, c)) ||
-          !blas_ok(rocblas_zgemm(bl.h, opN, opN, n32, bs, c, &mone, V, n32, Hd, c, &one, W, n32)))
+      // V^H W by the dot kernel (tall-skinny: K = N), W -= V (V^H W) by zgemm
+      launch_gram((const double2*)V, c, (const double2*)W, bs, N, gpart, (double2*)Hd, s);
+      OVS_HIP(hipGetLastError());
+      if (!blas_ok(rocblas_zgemm(bl.h, opN, opN, n32, bs, c, &mone, V, n32, Hd, c, &one, W, n32)))
         return OVS_ERR_HIP;
       OVS_HIP(hipMemcpyAsync(hp.data(), Hd, hp.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
       OVS_HIP(hipStreamSynchronize(s));
@@ -146,8 +151,8 @@ ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int n
     std::fill(r.begin(), r.end(), cd(0));
     for (int i = 0; i < bs; ++i) r[(size_t)i * bs + i] = 1.0;
     for (int pass = 0; pass < 2; ++pass) {
-      if (!blas_ok(rocblas_zgemm(bl.h, opC, opN, bs, bs, n32, &one, W, n32, W, n32, &zero, Rd, bs)))
-        return OVS_ERR_HIP;
+      launch_gram((const double2*)W, bs, (const double2*)W, bs, N, gpart, (double2*)Rd, s);
+      OVS_HIP(hipGetLastError());
       OVS_HIP(hipMemcpyAsync(g.data(), Rd, g.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
       OVS_HIP(hipStreamSynchronize(s));
       if (dense::cholesky(bs, g.data()) != 0) return OVS_WARN_BREAKDOWN;
@@ -170,7 +175,11 @@ ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int n
     return OVS_OK;
   };
 
-  {  // start block
+  if (opt.start) {
+    opt.start(col(0), bs);
+    const ovs_status so = orth_block(0);
+    if (so != OVS_OK) return so;
+  } else {  // start block
     std::vector<cd> v0(N);
     for (int c = 0; c < bs; ++c) {
       for (long i = 0; i < N; ++i) {
@@ -213,13 +222,14 @@ ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int n
     // ordered by |theta|.  Each y (unit) is reported with its Rayleigh
     // quotient rho = y^H H_m y and the residual |H_bar y - rho [y; 0]| of
     // D (V_m y) - rho V_m y.  If H_m is singular (a zero mode already in the
-    // basis) the cycle takes ordinary Ritz pairs (eigenpairs of H_m).
+    // basis) the cycle takes ordinary Ritz pairs (eigenpairs of H_m), and so
+    // does the largest-magnitude mode, ordered by decreasing |theta|.
     for (int c = 0; c < m; ++c)
       for (int i = 0; i < m; ++i) Hm[(size_t)c * m + i] = Hat(i, c);
     std::vector<cd> Hinv((size_t)m * m), M(Hm), RR((size_t)bs * bs);
     for (int c = 0; c < m; ++c)
       for (int i = 0; i < m; ++i) Hinv[(size_t)c * m + i] = std::conj(Hm[(size_t)i * m + c]);
-    const bool harmonic = dense::inverse(m, Hinv.data()) == 0;  // H_m^{-H}
+    const bool harmonic = !opt.largest && dense::inverse(m, Hinv.data()) == 0;  // H_m^{-H}
     if (harmonic) {
       for (int j = 0; j < bs; ++j)  // R^H R
         for (int i = 0; i < bs; ++i) {
@@ -236,8 +246,12 @@ ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int n
     }
     if (dense::eig(m, M.data(), theta.data(), Y.data()) != 0) return OVS_WARN_BREAKDOWN;
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return std::abs(theta[a]) < std::abs(theta[b]); });
+    if (opt.largest)
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int b) { return std::abs(theta[a]) > std::abs(theta[b]); });
+    else
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int b) { return std::abs(theta[a]) < std::abs(theta[b]); });
     double worst = 0;
     for (int q = 0; q < nev; ++q) {
       const cd* y = &Y[(size_t)order[q] * m];
@@ -255,9 +269,10 @@ ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int n
       }
       rq[q] = rho;
       res[q] = std::sqrt(n2);
-      worst = std::max(worst, res[q]);
+      if (q < nconv) worst = std::max(worst, res[q]);
     }
     if (info) info[0] = worst;
+    if (opt.progress) opt.progress(restarts, worst, matvecs);
     if (worst <= tol) {
       converged = true;
       break;

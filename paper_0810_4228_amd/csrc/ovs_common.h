@@ -137,7 +137,7 @@ struct ovs_deflation_s {
   double2* R;                    // device [m][12][Vs]
   double2* L;                    // device [m][12][Vs]
   double* sgn;                   // device [m] sgn(Re lambda)
-  double info[3] = {0, 0, 0};    // computed: max residual, max |L^dag R - I|, passes
+  double info[3] = {0, 0, 0};    // computed: max residual, max |L^dag R - I|, restarts
 };
 
 // ---- launchers implemented in stencil.hip --------------------------------

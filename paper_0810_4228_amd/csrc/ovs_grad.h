@@ -53,12 +53,13 @@ struct GradScalars {
   double* bbar;      // [nrhs][kmax]
   double2* gbar;     // [nrhs][kmax]
   double* nb;        // [nrhs]
+  double2* sigma;    // [nrhs] b_L^dagger b_R of LR-deflated starts (Section 3)
   int* status;       // [nrhs] 0 ok, 1 lucky breakdown, 2 serious breakdown
   double2* coef;     // [kCoefTables][kLinTerms][nrhs]
   int kmax;
   int nrhs;
 };
-constexpr int kCoefTables = 9;
+constexpr int kCoefTables = 11;
 // Coefficient tables (indices into GradScalars::coef).
 enum {
   kTabNorm = 0,  // forward: [1/|b|]
@@ -69,7 +70,9 @@ enum {
   kTabWB = 5,    // reverse: wbar_i
   kTabOne = 6,   // [1, 1, 1, 1, 1]
   kTabFin = 7,   // reverse: grad_b = ubar/|b| + nbar v_1
-  kTabY = 8      // reverse: y += |b| x_i v_i
+  kTabY = 8,     // reverse: y += |b| x_i v_i
+  kTabStartW = 9,  // deflated forward: w_1 = b_L |b_R| / conj(sigma)
+  kTabFinW = 10    // deflated reverse: bbar_L
 };
 inline double2* coef_table(const GradScalars& s, int t) {
   return s.coef + (long)t * kLinTerms * s.nrhs;
@@ -77,6 +80,10 @@ inline double2* coef_table(const GradScalars& s, int t) {
 
 // forward
 void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
+// LR-deflated starts (Section 3): from the dots |b_R|^2 (dot 0) and
+// sigma = b_L^dagger b_R (dot 1): nb = |b_R|, v_1 = b_R / nb (kTabNorm),
+// w_1 = b_L nb / conj(sigma) (kTabStartW), so that w_1^dagger v_1 = 1.
+void launch_gf_start(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
 void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st);
 void launch_gf_beta(const GradScalars& s, int i, const double* part_v, const double* part_w,
                     int nchunk, hipStream_t st);
@@ -87,6 +94,14 @@ void launch_gr_s1(const GradScalars& s, int i, const double* part_v, const doubl
 void launch_gr_s2(const GradScalars& s, int i, const double* part_v, const double* part_w,
                   int nchunk, hipStream_t st);
 void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
+// Deflated starts: from v_1^dagger vbar_1 (part_v, dot 0) and w_1^dagger wbar_1
+// (part_w, dot 0), the adjoints of b_R and b_L:
+//   bbar_R = vbar_1 / nb + tau b_L + (nbar / nb) b_R     (kTabFin: 1/nb, tau, nbar/nb)
+//   bbar_L = (nb / sigma) wbar_1 + conj(tau) b_R         (kTabFinW: nb/sigma, conj(tau))
+// with rho = wbar_1^dagger w_1, tau = -rho / conj(sigma) and
+// nbar = (Re chi^dagger y_K - Re vbar_1^dagger v_1 + Re rho) / nb.
+void launch_gr_final_defl(const GradScalars& s, const double* part_v, const double* part_w,
+                          int nchunk, hipStream_t st);
 
 // xbar_i = nb * conj(dot 0) for the dot chi^dagger v_i of the partials.
 void launch_gf_xbar(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st);

@@ -53,16 +53,45 @@ void unpack_field(const ovs_lattice_s* l, const void* field, void* canon, int nr
 // links and parameters set
 bool ready(const ovs_lattice_s* l);
 
+// roctx ranges around a call and its phases, when OVS_DEBUG_RANGES is set:
+// the call's range encloses one phase range at a time.
+class Ranges {
+ public:
+  Ranges(const ovs_lattice_s* l, const char* call);
+  ~Ranges();
+  void phase(const char* name);
+  Ranges(const Ranges&) = delete;
+  Ranges& operator=(const Ranges&) = delete;
+
+ private:
+  bool on_ = false, inner_ = false;
+};
+
 // An operator on blocks of canonical complex128 fields (device): op(in, out,
 // n, warn) applies it to n fields; *warn counts fields whose application
 // returned a warning.
 using BlockOp = std::function<ovs_status(const void*, void*, int, int*)>;
+// Options of block_krylov_eigs.  field_len: complex entries per field (0:
+// 12 V, the canonical layout); largest: the nev eigenvalues of largest
+// magnitude by ordinary Ritz extraction (for a shift-and-invert operator)
+// instead of the smallest by harmonic extraction; start: if set, fills the
+// start block (n fields) in place of the fixed splitmix vectors; progress: if
+// set, called after every cycle with (restarts, largest wanted residual,
+// operator applications so far); nconv: the leading wanted pairs that must
+// meet tol (0: all nev; the others are returned as they stand).
+struct KrylovOptions {
+  long field_len = 0;
+  bool largest = false;
+  int nconv = 0;
+  std::function<void(void*, int)> start;
+  std::function<void(int, double, int)> progress;
+};
 // Block Arnoldi with thick restarts in Krylov-Schur form and harmonic Ritz
 // extraction for the target 0 (overlap_eig.cpp): the nev eigenvalues of
 // smallest magnitude (host complex128 [nev]) and, if vecs, their unit vectors
-// (device [nev][12V]); info [4] as for ovs_overlap_eigs.
+// (device [nev][field_len]); info [4] as for ovs_overlap_eigs.
 ovs_status block_krylov_eigs(ovs_lattice_s* l, const BlockOp& op, int nev, int ncv, int block,
                              double tol, int max_restarts, double* lambda, void* vecs,
-                             double* info);
+                             double* info, const KrylovOptions& opt = KrylovOptions());
 
 }  // namespace ovs

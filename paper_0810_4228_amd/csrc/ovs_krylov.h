@@ -11,6 +11,12 @@ int defl_nchunk(long N);
 void launch_defl(const double2* R, const double2* L, const double2* B, const double* sgn, int m,
                  int nrhs, long N, double* partials, double* CD, double2* bR, double2* bL,
                  double2* yex, hipStream_t s);
+// Projections of X (nrhs fields) against the deflation space: outQ = X - R
+// (L^dag X) and outQd = X - L (R^dag X) + L kappa (kappa [nrhs][m] or null);
+// either output may be null.  CD [m][nrhs][4] receives the dots.
+void launch_defl_proj(const double2* R, const double2* L, const double2* X, int m, int nrhs, long N,
+                      double* partials, double* CD, const double2* kappa, double2* outQ,
+                      double2* outQd, hipStream_t s);
 // CD[j][r] = (L_j^dag B_r, R_j^dag B_r) only (used to check L^dag R = I)
 void launch_defl_cd(const double2* R, const double2* L, const double2* B, int m, int nrhs, long N,
                     double* partials, double* CD, hipStream_t s);
@@ -55,6 +61,11 @@ void launch_overlap(const double2* b, double2* y, long N, int V, hipStream_t s);
 int arn_nchunk(long N);
 void launch_arn_dots(bool f32, const void* basis, long basis_stride, const void* T, long N,
                      int nvec, int nrhs, double* partials, double* red, hipStream_t s);
+// G = X^H Y (nx x ny, column-major) for column-major FP64 blocks with
+// leading dimension N: one dot launch per column of Y (tall-skinny products
+// that library GEMMs tile poorly); partials hold nx * arn_nchunk(N) * 2.
+void launch_gram(const double2* X, int nx, const double2* Y, int ny, long N, double* partials,
+                 double2* G, hipStream_t s);
 void launch_arn_accum(const double* red, int nvec, int kmax, int j, bool first, double2* H,
                       double2* hcur, int nrhs, hipStream_t s);
 void launch_arn_axpy(bool f32, const void* basis, long basis_stride, void* T, long N, int nvec,

@@ -317,6 +317,39 @@ def test_point_sources_16x16x16x16_persistent():
     assert max(e) <= 1e-5
 
 
+def test_point_sources_16x16x16x16_deflated():
+    """The 16^4 configuration as specified (Sections 3 and 5): 40 critical
+    eigentriples computed on the GPU (relative residuals of right and left
+    vectors <= 1e-10, |L^dagger R - I| <= 1e-10), then the 12 point sources
+    with LR deflation in FP32 storage to tol 1e-7, against the oracle's
+    undeflated FP64 result at k = 600 (converged to ~1.5e-10, so both equal
+    sgn(A) b well below the bar) on the sampled entries of sources 0 and 1.
+    Bar: 1e-5 for FP32 storage."""
+    import paper_0810_4228_amd as ovs
+    f = np.load(os.path.join(GOLDEN, "sign_16x16x16x16.npz"))
+    dims = tuple(int(d) for d in f["dims"])
+    mu, idx = float(f["mu"]), f["idx"]
+    U = to_dev(synth.random_links(dims, float(f["eps"]), seed=synth.LINK_SEED))
+    b = to_dev(synth.point_sources(dims))
+    lat = ovs.Lattice(dims, precision="f32")
+    lat.set_links(U)
+    lat.set_params(MW, mu)
+    d, st_d = lat.deflation_compute(40, tol=1e-10, max_iter=30)
+    lam, R, L, dinfo = d.get()
+    del R, L
+    y, info, st = lat.sign_apply(b, 600, defl=d, tol=[1e-7] * 12)
+    yh = [y[r].cpu().numpy() for r in range(2)]
+    e = [rel(yh[r][idx], f[f"y{r}_k600"]) for r in range(2)]
+    say(f"16^4 m=40 eigentriples: status {st_d}, residual {dinfo[0]:.1e}, |L^dag R - I| {dinfo[1]:.1e}, "
+        f"|lambda| {abs(lam[0]):.4f}..{abs(lam[-1]):.4f}; deflated point sources: {e}, status {st}, "
+        f"k {[i['k_used'] for i in info]}")
+    d.close()
+    lat.close()
+    assert st_d == 0 and dinfo[0] <= 1e-10 and dinfo[1] <= 1e-10
+    assert st == 0
+    assert max(e) <= 1e-5
+
+
 def test_benchmark_lattice_48_sources_mixed_tolerance():
     """16^3 x 32, 48 Gaussian sources with target tolerances 1e-5 (even) and
     1e-8 (odd) in one call on an FP32-storage lattice, two-pass (a stored
