@@ -804,6 +804,25 @@ def test_zero_and_infinite_sources(cfg1):
     lat.close()
 
 
+def test_debug_ranges_leave_results_unchanged(cfg1):
+    """OVS_DEBUG_RANGES: roctx ranges around the call and its phases (host
+    markers for rocprofv3 --marker-trace); the solve's result is bitwise the
+    one without them, for 2sL, Arnoldi and the gradient."""
+    dims, U, b, f = cfg1
+    lat = lattice(dims, "f64", U, float(f["mu"]))
+    ys = []
+    for ranges in (False, True):
+        lat.set_debug(ranges=ranges)
+        y1, _, s1 = lat.sign_apply(to_dev(b), 120)
+        y2, _, s2 = lat.sign_apply(to_dev(b), 80, method="arnoldi")
+        g = lat.sign_apply_vjp(to_dev(b), to_dev(b), 30, want_y=False)
+        ys.append((y1.cpu().numpy(), y2.cpu().numpy(), g[1].cpu().numpy(), g[2]))
+    lat.set_debug()
+    lat.close()
+    for a, c in zip(ys[0], ys[1]):
+        assert np.array_equal(a, c)
+
+
 def test_debug_checks(cfg1):
     """OVS_DEBUG_CHECKS: the biorthogonality rows |w_j^dagger v_i - delta_ij|
     (Section 4), measured every 25 iterations against the stored basis, and
