@@ -86,7 +86,8 @@ typedef struct {
                             entries over the last 25 iterations (0 without tol)        */
   double quad_err;       /* estimated relative error of x = sgn(G_k) e_1: the coarse/fine
                             difference of the quadrature at the step that met its target
-                            (3e-7, or tol/10 if smaller) or at the finest step, 1/64;
+                            (3e-7, or tol/10 if smaller but at least 1e-12, the FP64
+                            rounding level of the difference) or at the finest step, 1/64;
                             above the target the status is OVS_WARN_SIGN_AMBIGUOUS     */
   double n_b;            /* |b_R|, norm of the deflated source                         */
   double t_defl_ms, t_krylov_ms, t_inner_ms, t_combine_ms; /* phase times (whole batch) */

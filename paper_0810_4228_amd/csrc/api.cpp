@@ -159,11 +159,15 @@ constexpr double kHStart = 0.25, kHMin = 1.0 / 64;
 // Target of the coarse/fine difference of x = sgn(G) e_1 (the error of the
 // rule with step 2h, an upper bound of the error of step h while the rule
 // converges exponentially): kQuadAccept, and a tenth of the source's
-// tolerance when that is smaller.  The error of step s behaves like
-// exp(-2 pi d / s) for a Ritz value at angle d from the imaginary axis, so a
-// target missed at h = 1/64 means a Ritz value within a few degrees of it:
-// the sign is ambiguous there (sgn(z) = sgn(Re z) jumps across the axis).
+// tolerance when that is smaller, but not below kQuadFloor: the FP64
+// rounding of thousands of node solves puts differences of ~1e-13 between
+// two converged levels, which say nothing about the sign.  The error of step
+// s behaves like exp(-2 pi d / s) for a Ritz value at angle d from the
+// imaginary axis, so a target missed at h = 1/64 means a Ritz value within a
+// few degrees of it: the sign is ambiguous there (sgn(z) = sgn(Re z) jumps
+// across the axis).
 constexpr double kQuadAccept = 3e-7;
+constexpr double kQuadFloor = 1e-12;
 constexpr int kProbe = 512;           // sampled entries per source for the convergence estimate
 constexpr int kBasisFirst = 256;      // first capacity (vectors) of a growable one-pass basis
 constexpr int kCheckEvery = 25;       // iterations between convergence checks
@@ -218,7 +222,7 @@ struct InnerScratch {
 std::vector<double> quad_targets(const double* tol, int nrhs) {
   std::vector<double> t(nrhs, kQuadAccept);
   if (tol)
-    for (int r = 0; r < nrhs; ++r) t[r] = std::min(kQuadAccept, 0.1 * tol[r]);
+    for (int r = 0; r < nrhs; ++r) t[r] = std::min(kQuadAccept, std::max(kQuadFloor, 0.1 * tol[r]));
   return t;
 }
 

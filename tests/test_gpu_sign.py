@@ -137,19 +137,21 @@ def test_inner_sign_near_imaginary_axis_warns():
 
 def test_quadrature_status_follows_tolerance(cfg1):
     """The inner sign is refined until its coarse/fine difference is below a
-    tenth of each source's tolerance (and 3e-7); the status is OK only when
-    the returned quad_err meets that target.  At the 4^4 configuration with
-    tol 1e-12 (FP64), every source's quad_err must be <= 1e-13."""
+    tenth of each source's tolerance (and 3e-7), floored at 1e-12 (the FP64
+    rounding level of the difference); the status is OK only when the
+    returned quad_err meets that target.  At the 4^4 configuration: tol 1e-8
+    needs quad_err <= 1e-9, tol 1e-12 needs <= 1e-12."""
     dims, U, b, f = cfg1
     lat = lattice(dims, "f64", U, float(f["mu"]))
     d = lat.deflation_set(f["lam"], to_dev(f["R"].T), to_dev(f["L"].T))
-    y, info, st = lat.sign_apply(to_dev(b), 600, defl=d, tol=[1e-12])
-    e = rel(y.cpu().numpy()[0], f["y"])
-    say("tol 1e-12: err", e, "quad_err", info[0]["quad_err"], "k", info[0]["k_used"], "status", st)
-    assert (st == 0) == (info[0]["quad_err"] <= 1e-13)
-    assert st in (0, 3)
-    if st == 0:
-        assert e <= 1e-10
+    for tol, target in ((1e-8, 1e-9), (1e-12, 1e-12)):
+        y, info, st = lat.sign_apply(to_dev(b), 600, defl=d, tol=[tol])
+        e = rel(y.cpu().numpy()[0], f["y"])
+        say(f"tol {tol}: err", e, "quad_err", info[0]["quad_err"], "k", info[0]["k_used"], "status", st)
+        assert (st == 0) == (info[0]["quad_err"] <= target)
+        assert st in (0, 3)
+        if st == 0:
+            assert e <= max(10 * tol, 1e-10)
 
 
 def test_arnoldi_with_tolerance_stops(cfg1):
