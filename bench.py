@@ -219,18 +219,42 @@ def overlap_eigs_timing(ovs, torch, dev, dims=(8, 8, 8, 8), nev=4, ncv=80, block
             "ms_per_sign_solve": ms / max(info["sign_solves"], 1)}
 
 
-def gradient_timing(ovs, torch, dev, dims=(8, 8, 8, 8), k=400):
+def eig_timing(ovs, torch, dev, dims=(8, 8, 8, 8), eps=0.6, mu=0.3, m=30, tol=1e-10):
+    """ovs_deflation_compute: m critical eigentriples (right and left, FP64)
+    by shift-invert Krylov-Schur; seconds, status and the solver's info."""
+    import synth
+    lat = ovs.Lattice(dims, precision="f64")
+    lat.set_links(torch.from_numpy(synth.random_links(dims, eps, seed=synth.LINK_SEED)).to(dev))
+    lat.set_params(MW, mu)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d, st = lat.deflation_compute(m, tol=tol, max_iter=30)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lam, R, L, info = d.get()
+    d.close()
+    lat.close()
+    return {"workload": "x".join(map(str, dims)) + f", eps {eps}, mu {mu}, m = {m}, tol {tol}",
+            "seconds": dt, "status": int(st), "max_rel_residual": float(info[0]),
+            "biorth_dev": float(info[1]), "restarts": int(info[2]),
+            "abs_lambda_range": [float(abs(lam[0])), float(abs(lam[-1]))]}
+
+
+def gradient_timing(ovs, torch, dev, dims=(8, 8, 8, 8), k=400, m_defl=0):
     """ovs_sign_apply_vjp (eps 0.6, mu 0.3, one Gaussian source and cotangent,
     FP64, k iterations) with the Lanczos vectors recomputed from checkpoints and
     with the bases stored, against the k-step forward alone (no tolerance, no
     graphs: the same kernels the sweep uses).  The default is the gradient
-    configuration, 8^4 at k = 400."""
+    configuration, 8^4 at k = 400.  With m_defl > 0 both run with that many
+    computed eigentriples (LR deflation; the eigentriples are computed
+    outside the timed region)."""
     import synth
     lat = ovs.Lattice(dims, precision="f64")
     lat.set_links(torch.from_numpy(synth.random_links(dims, 0.6, seed=synth.LINK_SEED)).to(dev))
     lat.set_params(MW, 0.3)
     b = torch.from_numpy(synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)).to(dev)
     chi = torch.from_numpy(synth.gaussian_sources(dims, 1, seed=synth.COTANGENT_SEED)).to(dev)
+    d = lat.deflation_compute(m_defl, tol=1e-10, max_iter=30)[0] if m_defl else None
 
     def t(fn, reps=3):
         fn()
@@ -241,11 +265,14 @@ def gradient_timing(ovs, torch, dev, dims=(8, 8, 8, 8), k=400):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps * 1e3
 
-    fwd = t(lambda: lat.sign_apply(b, k))
-    rec = t(lambda: lat.sign_apply_vjp(b, chi, k))
-    sto = t(lambda: lat.sign_apply_vjp(b, chi, k, store_basis=True))
+    fwd = t(lambda: lat.sign_apply(b, k, defl=d))
+    rec = t(lambda: lat.sign_apply_vjp(b, chi, k, defl=d))
+    sto = t(lambda: lat.sign_apply_vjp(b, chi, k, store_basis=True, defl=d))
+    if d is not None:
+        d.close()
     lat.close()
-    return {"workload": "x".join(map(str, dims)) + f", eps 0.6, mu 0.3, 1 source, FP64, k = {k}",
+    return {"workload": "x".join(map(str, dims)) + f", eps 0.6, mu 0.3, 1 source, FP64, k = {k}"
+                        + (f", {m_defl} deflated eigentriples" if m_defl else ""),
             "forward_ms": fwd, "vjp_recompute_ms": rec, "vjp_stored_basis_ms": sto,
             "ratio_recompute": rec / fwd, "ratio_stored": sto / fwd}
 
@@ -377,9 +404,13 @@ def main():
                          "profiles were taken with)")
     ap.add_argument("--retune", action="store_true",
                     help="autotune even if the tuning file holds a configuration")
-    ap.add_argument("--gradient-only", nargs=2, metavar=("LXxLYxLZxLT", "K"), default=None,
-                    help="only time the gradient (ovs_sign_apply_vjp) against the forward on "
-                         "that lattice at k iterations (for profiling), e.g. 8x8x8x8 400")
+    ap.add_argument("--gradient-only", nargs="+", metavar="ARG", default=None,
+                    help="LXxLYxLZxLT K [M]: only time the gradient (ovs_sign_apply_vjp) "
+                         "against the forward on that lattice at k iterations, with M computed "
+                         "eigentriples if given (for profiling), e.g. 8x8x8x8 400 30")
+    ap.add_argument("--eig-only", nargs=4, metavar=("LXxLYxLZxLT", "M", "EPS", "MU"), default=None,
+                    help="only time ovs_deflation_compute (m eigentriples, FP64, tol 1e-10) on "
+                         "that lattice; prints one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times: the known-size reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -388,12 +419,21 @@ def main():
         print(json.dumps({"error": "bench.py runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
 
+    if args.eig_only:
+        import torch
+        import paper_0810_4228_amd as ovs
+        dims = tuple(int(x) for x in args.eig_only[0].split("x"))
+        print(json.dumps(eig_timing(ovs, torch, torch.device("cuda:0"), dims=dims,
+                                    eps=float(args.eig_only[2]), mu=float(args.eig_only[3]),
+                                    m=int(args.eig_only[1]))))
+        return
     if args.gradient_only:
         import torch
         import paper_0810_4228_amd as ovs
         dims = tuple(int(x) for x in args.gradient_only[0].split("x"))
+        mdef = int(args.gradient_only[2]) if len(args.gradient_only) > 2 else 0
         print(json.dumps(gradient_timing(ovs, torch, torch.device("cuda:0"), dims=dims,
-                                         k=int(args.gradient_only[1]))))
+                                         k=int(args.gradient_only[1]), m_defl=mdef)))
         return
     cpu_t = None
     if not args.no_cpu and not args.stencil_only and not args.copy_calibration:
@@ -558,7 +598,11 @@ def main():
     if not args.no_compare:
         log("bench: gradient timing")
         out["gradient"] = [gradient_timing(ovs, torch, dev),
-                           gradient_timing(ovs, torch, dev, dims=(16, 16, 16, 16), k=200)]
+                           gradient_timing(ovs, torch, dev, dims=(16, 16, 16, 16), k=200),
+                           gradient_timing(ovs, torch, dev, m_defl=30)]
+        log("bench: eigentriples")
+        out["eigentriples"] = eig_timing(ovs, torch, dev)
+        log("bench: eigentriples", out["eigentriples"])
         log("bench: overlap eigenvalues")
         out["overlap_eigs"] = overlap_eigs_timing(ovs, torch, dev)
         log("bench: gradient", out["gradient"])

@@ -110,6 +110,7 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
   // CG work blocks (bs fields each) and the per-side results (nev fields each)
   double2 *cR = mem.alloc<double2>((size_t)bs * Np), *cP = mem.alloc<double2>((size_t)bs * Np);
   double2 *cT = mem.alloc<double2>((size_t)bs * Np), *cW = mem.alloc<double2>((size_t)bs * Np);
+  double2 *cX = mem.alloc<double2>((size_t)bs * Np), *cY = mem.alloc<double2>((size_t)bs * Np);
   double2 *vecs = mem.alloc<double2>((size_t)nev * Np), *AS = mem.alloc<double2>((size_t)nev * Np);
   double2 *spare = mem.alloc<double2>((size_t)nev * Np), *Lkeep = mem.alloc<double2>((size_t)nev * Np);
   double2* Gd = mem.alloc<double2>((size_t)nev * nev);
@@ -125,11 +126,11 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
   double* red = mem.alloc<double>(nev);
   double* rrd = mem.alloc<double>(2 * bs);
   double* ttd = mem.alloc<double>(bs);
-  if (!cR || !cP || !cT || !cW || !vecs || !AS || !spare || !Lkeep || !Gd || !Cd || !thd ||
+  if (!cR || !cP || !cT || !cW || !cX || !cY || !vecs || !AS || !spare || !Lkeep || !Gd || !Cd || !thd ||
       !part || !red || !rrd || !ttd)
     return OVS_ERR_ALLOC;
   // the stencil writes only lattice sites: pad entries stay zero from here on
-  for (double2* b : {cR, cP, cT, cW})
+  for (double2* b : {cR, cP, cT, cW, cX, cY})
     if (hipMemsetAsync(b, 0, sizeof(double2) * bs * Np, s) != hipSuccess) return OVS_ERR_HIP;
   for (double2* b : {vecs, AS, spare, Lkeep})
     if (hipMemsetAsync(b, 0, sizeof(double2) * nev * Np, s) != hipSuccess) return OVS_ERR_HIP;
@@ -317,7 +318,7 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
   // outer tolerance on A^{-1}; the inner solves run below it
   const double tol_outer = 0.5 * tol / anorm;
   const double tol_inner = std::max(0.1 * tol, 1e-14);
-  constexpr int kCgMax = 100000, kCgCheck = 25, kCgStall = 2000;
+  constexpr int kCgMax = 100000, kCgCheck = 24, kCgStall = 2000;  // even: graphs of two steps
   long cg_total = 0;
   int cg_fail = 0;
   // x += D diag(1 / eta) D^H r for one field (D = S or U)
@@ -338,21 +339,49 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
   // A^dagger (hf = hAd, space U): CG on M^H M x = M^H y from the deflated
   // start, restarted from the true residual with a second projection once it
   // is 1e-5 of the start (rounding brings back the components along D).
+  // Two CG steps (parity back to rr[0]) on the fixed work fields, captured
+  // once per operator as a HIP graph: at 8^4 a step is a few microseconds of
+  // work per launch, so launch overhead would dominate the solve.
+  struct CgGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~CgGraph() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } cg_graph[2];
+  auto enqueue_two_steps = [&](const Hop& hf, const Hop& hb) -> bool {
+    for (int c = 0; c < 2; ++c) {
+      if (!apply(cP, cT, 1, hf)) return false;  // t = M p
+      launch_norm2(false, cT, Np, 1, part, ttd, s);
+      if (!apply(cT, cW, 1, hb)) return false;  // w = M^H t
+      launch_cg_xr(cX, cR, cP, cW, rrd + c * bs, ttd, 1, Np, part, s);
+      launch_cg_p(cP, cR, rrd + c * bs, rrd + (1 - c) * bs, part, 1, Np, s);
+    }
+    return true;
+  };
+  // x = M^{-1} y for one source, M = A (hf = hA, deflation space S) or
+  // A^dagger (hf = hAd, space U): CG on M^H M x = M^H y from the deflated
+  // start, restarted from the true residual with a second projection once it
+  // is 1e-5 of the start (rounding brings back the components along D).
+  // y is copied to cY and the iterate lives in cX (the graph's fields).
   auto solve = [&](const double2* Y, double2* X, int n, const Hop& hf, const Hop& hb,
-                   const double2* D) -> ovs_status {
+                   const double2* D, CgGraph& cg) -> ovs_status {
     if (n != 1) return OVS_ERR_ARG;
     std::vector<double> yy, res;
-    if (!norms2(Y, 1, yy)) return OVS_ERR_HIP;
-    if (hipMemsetAsync(X, 0, sizeof(double2) * Np, s) != hipSuccess) return OVS_ERR_HIP;
+    if (hipMemcpyAsync(cY, Y, sizeof(double2) * Np, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return OVS_ERR_HIP;
+    if (!norms2(cY, 1, yy)) return OVS_ERR_HIP;
+    if (hipMemsetAsync(cX, 0, sizeof(double2) * Np, s) != hipSuccess) return OVS_ERR_HIP;
     const std::vector<double2> ones(1, make_double2(1.0, 0.0));
     if (hipMemcpyAsync(thd, ones.data(), sizeof(double2), hipMemcpyHostToDevice, s) != hipSuccess)
       return OVS_ERR_HIP;
-    if (!apply(Y, cW, 1, hb)) return OVS_ERR_HIP;  // b = M^H y (kept in cW until the first step)
-    if (!project_add(D, cW, X)) return OVS_ERR_HIP;
+    if (!apply(cY, cW, 1, hb)) return OVS_ERR_HIP;  // b = M^H y (kept in cW until the first step)
+    if (!project_add(D, cW, cX)) return OVS_ERR_HIP;
     // r = b - M^H M x, p = r
     auto restart = [&]() -> bool {
-      if (!apply(X, cT, 1, hf)) return false;
-      launch_resid(cP, Y, cT, thd, 1, Np, s);  // y - M x
+      if (!apply(cX, cT, 1, hf)) return false;
+      launch_resid(cP, cY, cT, thd, 1, Np, s);  // y - M x
       if (!apply(cP, cR, 1, hb)) return false;  // r = M^H (y - M x)
       if (hipMemcpyAsync(cP, cR, sizeof(double2) * Np, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return false;
@@ -360,19 +389,21 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
       return true;
     };
     if (!restart()) return OVS_ERR_HIP;
-    int cur = 0, nproj = 1;
+    if (!cg.x) {
+      if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return OVS_ERR_HIP;
+      const bool ok = enqueue_two_steps(hf, hb);
+      const hipError_t ce = hipStreamEndCapture(s, &cg.g);
+      if (!ok || ce != hipSuccess) return OVS_ERR_HIP;
+      if (hipGraphInstantiate(&cg.x, cg.g, nullptr, nullptr, 0) != hipSuccess) return OVS_ERR_HIP;
+    }
+    int nproj = 1;
     double best = 1e300;
     int best_it = 0;
-    for (int it = 1; it <= kCgMax; ++it) {
-      if (!apply(cP, cT, 1, hf)) return OVS_ERR_HIP;       // t = M p
-      launch_norm2(false, cT, Np, 1, part, ttd, s);
-      if (!apply(cT, cW, 1, hb)) return OVS_ERR_HIP;       // w = M^H t
-      launch_cg_xr(X, cR, cP, cW, rrd + cur * bs, ttd, 1, Np, part, s);
-      launch_cg_p(cP, cR, rrd + cur * bs, rrd + (1 - cur) * bs, part, 1, Np, s);
-      cur = 1 - cur;
+    for (int it = 2; it <= kCgMax; it += 2) {
+      if (hipGraphLaunch(cg.x, s) != hipSuccess) return OVS_ERR_HIP;
       if (it % kCgCheck == 0 || it == kCgMax) {  // true residual y - M x
-        if (!apply(X, cT, 1, hf)) return OVS_ERR_HIP;
-        launch_resid(cW, cT, Y, thd, 1, Np, s);
+        if (!apply(cX, cT, 1, hf)) return OVS_ERR_HIP;
+        launch_resid(cW, cT, cY, thd, 1, Np, s);
         if (!norms2(cW, 1, res)) return OVS_ERR_HIP;
         const double rel = std::sqrt(res[0] / yy[0]);
         const bool done = rel <= tol_inner;
@@ -388,11 +419,12 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
             fprintf(stderr, "ovs eigentriples: solve: %d CG iterations, residual %.2e\n", it, rel);
             fflush(stderr);
           }
+          if (hipMemcpyAsync(X, cX, sizeof(double2) * Np, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return OVS_ERR_HIP;
           return OVS_OK;
         }
         if (nproj == 1 && rel <= 1e-5) {  // second projection from the current residual
-          if (!project_add(D, cR, X) || !restart()) return OVS_ERR_HIP;
-          cur = 0;
+          if (!project_add(D, cR, cX) || !restart()) return OVS_ERR_HIP;
           nproj = 2;
         }
       }
@@ -421,7 +453,7 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
         fflush(stderr);
       };
     const BlockOp op = [&](const void* in, void* out, int n, int*) -> ovs_status {
-      return solve((const double2*)in, (double2*)out, n, hf, hb, side ? Ud : Sd);
+      return solve((const double2*)in, (double2*)out, n, hf, hb, side ? Ud : Sd, cg_graph[side]);
     };
     std::vector<double> lam_inv(2 * nev);
     double kinfo[4] = {0, 0, 0, 0};

@@ -726,7 +726,15 @@ static int chunks_for(long N, int cap = 1024) {
   return (int)b;
 }
 
-int defl_nchunk(long N) { return chunks_for(N, 512); }
+// chunks of the deflation dots: at least 16 entries per thread, so that the
+// per-workgroup reduction of 4 kDeflRhs values does not dominate (one entry
+// per thread made the dots latency-bound: 107 us for m = 30 at 8^4)
+int defl_nchunk(long N) {
+  long c = (N + 256L * 16 - 1) / (256L * 16);
+  if (c > 512) c = 512;
+  if (c < 1) c = 1;
+  return (int)c;
+}
 
 void launch_defl(const double2* R, const double2* L, const double2* B, const double* sgn, int m,
                  int nrhs, long N, double* partials, double* CD, double2* bR, double2* bL,
