@@ -306,13 +306,13 @@ def launch_modes(ovs, torch, dev, lat, bt):
     return out
 
 
-def fp64_single_source(ovs, torch, dev, U, bt, y32, graph):
+def fp64_single_source(ovs, torch, dev, U, bt, y32, graph, mu=MU):
     """The same sources solved one at a time on an FP64 lattice (same links,
     same tolerance), sequentially: solves/s and the largest relative
     difference from the batched FP32-storage result."""
     lat = ovs.Lattice(DIMS, precision="f64")
     lat.set_links(U)
-    lat.set_params(MW, MU)
+    lat.set_params(MW, mu)
     lat.autotune(1)
     lat.sign_apply(bt[0:1], KMAX, tol=[TOL], graph=graph)  # warm-up (workspace, graph)
     torch.cuda.synchronize()
@@ -330,7 +330,7 @@ def fp64_single_source(ovs, torch, dev, U, bt, y32, graph):
     return bt.shape[0] / dt, diff
 
 
-def plain_fp64_single(ovs, torch, dev, U, bt, k_used, y32, nsrc=2):
+def plain_fp64_single(ovs, torch, dev, U, bt, k_used, y32, nsrc=NRHS, mu=MU):
     """The plain single-source FP64 form of the same solve: one source at a
     time, each two-sided Lanczos step (Section 4) as separate launches -- the
     library's FP64 stencil for A v and A^dag w (ovs_apply, canonical layout),
@@ -341,7 +341,7 @@ def plain_fp64_single(ovs, torch, dev, U, bt, k_used, y32, nsrc=2):
     solves/s and the largest relative difference from the batched result."""
     lat = ovs.Lattice(DIMS, precision="f64")
     lat.set_links(U)
-    lat.set_params(MW, MU)
+    lat.set_params(MW, mu)
 
     def solve(b, k):
         nb = torch.linalg.vector_norm(b)
@@ -587,9 +587,32 @@ def main():
             log(f"bench: {key}: {rate:.2f} solves/s, batched/this = {value / rate:.2f}")
         rate, diff = plain_fp64_single(ovs, torch, dev, Ut, bt, k_used, y)
         cmp["plain_fp64_single"] = {"solves_per_s": rate, "ratio": value / rate,
-                                    "max_rel_diff_vs_batched": diff, "sources_timed": 2,
+                                    "max_rel_diff_vs_batched": diff, "sources_timed": NRHS,
                                     "form": "one source, FP64, unfused launches, host scalars, no graph, k = k_used"}
         log(f"bench: plain_fp64_single: {rate:.2f} solves/s, batched/this = {value / rate:.2f}")
+        # the same three forms at the other chemical potential of the comparison
+        lat01 = ovs.Lattice(DIMS, precision="f32")
+        lat01.set_links(Ut)
+        lat01.set_params(MW, 0.1)
+        lat01.set_tuning_raw(NRHS, lat.get_tuning_raw(NRHS))
+        lat01.sign_apply(bt, KMAX, tol=[TOL] * NRHS, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            y01, info01, _ = lat01.sign_apply(bt, KMAX, tol=[TOL] * NRHS, graph=True)
+        torch.cuda.synchronize()
+        v01 = 3 * NRHS / (time.perf_counter() - t0)
+        k01 = [i["k_used"] for i in info01]
+        lat01.close()
+        r64, d64 = fp64_single_source(ovs, torch, dev, Ut, bt, y01, True, mu=0.1)
+        rpl, dpl = plain_fp64_single(ovs, torch, dev, Ut, bt, k01, y01, mu=0.1)
+        cmp["mu_0.1"] = {"batched_solves_per_s": v01, "k_used": k01,
+                         "fp64_single_graph": {"solves_per_s": r64, "ratio": v01 / r64,
+                                               "max_rel_diff_vs_batched": d64},
+                         "plain_fp64_single": {"solves_per_s": rpl, "ratio": v01 / rpl,
+                                               "max_rel_diff_vs_batched": dpl}}
+        log(f"bench: mu 0.1: batched {v01:.2f} solves/s, x{v01 / r64:.2f} fused FP64, "
+            f"x{v01 / rpl:.2f} plain FP64")
         out["vs_fp64_single_source"] = cmp
     if not args.no_compare:
         log("bench: launch modes")
