@@ -416,3 +416,43 @@ def test_vjp_deflated_4444_daleckii_krein():
     assert eb <= 1e-9 and emu <= 1e-9 and eU <= 1e-9
     d.close()
     lat.close()
+
+
+def test_vjp_deflated_batched_and_stored_equal_single():
+    """The deflation-aware gradient of a batch of two sources (4^4 workload, the
+    fixture's 20 eigentriples, k = 200) against the two sources run alone:
+    grad_b per source, dL/dmu and the link gradient as the sums (the batch's
+    per-source coefficients kappa, Q_j and the second run are indexed by
+    source); and the stored-basis sweep against the recomputed one.  y and
+    grad_b agree bit for bit; the force sums differ in their order of
+    summation (the batch combines the sources' q_j before one force per
+    eigentriple), and the deflation terms cancel by ~1e5 in them (their
+    difference from Daleckii-Krein is ~2e-11 too), so they are held to 1e-10."""
+    f = np.load(os.path.join(GOLDEN, "lattice_4444.npz"))
+    dims = tuple(int(x) for x in f["dims"])
+    U = synth.random_links(dims, float(f["eps"]), seed=synth.LINK_SEED)
+    b = synth.gaussian_sources(dims, 2, seed=synth.SOURCE_SEED)
+    chi = synth.gaussian_sources(dims, 2, seed=synth.COTANGENT_SEED)
+    lat = f64_lattice(dims, U, float(f["mu"]))
+    d = lat.deflation_set(f["lam"], to_dev(f["R"].T), to_dev(f["L"].T))
+    k = 200
+    yb, gbb, gmub, gUb, _, st = lat.sign_apply_vjp(to_dev(b), to_dev(chi), k, defl=d)
+    ys, gbs, gmus, gUs, _, st2 = lat.sign_apply_vjp(to_dev(b), to_dev(chi), k, defl=d,
+                                                    store_basis=True)
+    assert st == 0 and st2 == 0
+    singles = [lat.sign_apply_vjp(to_dev(b[r:r + 1]), to_dev(chi[r:r + 1]), k, defl=d)
+               for r in range(2)]
+    gb1 = np.concatenate([s[1].cpu().numpy() for s in singles])
+    gmu1 = sum(s[2] for s in singles)
+    gU1 = sum(s[3].cpu().numpy() for s in singles)
+    y1 = np.concatenate([s[0].cpu().numpy() for s in singles])
+    e = (rel(yb.cpu().numpy(), y1), rel(gbb.cpu().numpy(), gb1), abs(gmub - gmu1) / abs(gmu1),
+         rel(gUb.cpu().numpy(), gU1))
+    say(f"deflated batch of 2 vs singles: y {e[0]:.1e} grad_b {e[1]:.1e} grad_mu {e[2]:.1e} "
+        f"grad_U {e[3]:.1e}")
+    assert e[0] == 0.0 and e[1] == 0.0
+    assert e[2] <= 1e-10 and e[3] <= 1e-10
+    assert np.array_equal(gbs.cpu().numpy(), gbb.cpu().numpy()) and gmus == gmub
+    assert np.array_equal(gUs.cpu().numpy(), gUb.cpu().numpy())
+    d.close()
+    lat.close()
