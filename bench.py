@@ -240,6 +240,48 @@ def eig_timing(ovs, torch, dev, dims=(8, 8, 8, 8), eps=0.6, mu=0.3, m=30, tol=1e
             "abs_lambda_range": [float(abs(lam[0])), float(abs(lam[-1]))]}
 
 
+def compare_methods(ovs, torch, dev, dims=(8, 8, 8, 8), mu=0.3, m=30, ks=(200, 400, 600, 800)):
+    """The paper's comparison (Section 5, its accuracy-vs-k and accuracy-vs-time
+    figures) on the GPU: LR-deflated two-sided Lanczos against LR-deflated
+    Arnoldi, FP64, one Gaussian source, eps 0.6, m computed eigentriples, at
+    each k: the relative error against the 2sL result at k = 1600 and the
+    time of one ovs_sign_apply (no tolerance: exactly k steps; graphs off, as
+    Arnoldi has none).  Also times the eigentriples (setup)."""
+    import synth
+    lat = ovs.Lattice(dims, precision="f64")
+    lat.set_links(torch.from_numpy(synth.random_links(dims, 0.6, seed=synth.LINK_SEED)).to(dev))
+    lat.set_params(MW, mu)
+    b = torch.from_numpy(synth.gaussian_sources(dims, 1, seed=synth.SOURCE_SEED)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d, st = lat.deflation_compute(m, tol=1e-10, max_iter=30)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    lam, R, L, info = d.get()
+    del R, L
+    yref = lat.sign_apply(b, 1600, defl=d)[0].cpu().numpy()[0]
+    rows = []
+    for k in ks:
+        row = {"k": k}
+        for meth in ("2sl", "arnoldi"):
+            lat.sign_apply(b, k, defl=d, method=meth)  # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            y = lat.sign_apply(b, k, defl=d, method=meth)[0]
+            torch.cuda.synchronize()
+            row[meth + "_ms"] = (time.perf_counter() - t1) * 1e3
+            yc = y.cpu().numpy()[0]
+            row[meth + "_rel_err"] = float(np.linalg.norm(yc - yref) / np.linalg.norm(yref))
+        rows.append(row)
+    d.close()
+    lat.close()
+    return {"workload": "x".join(map(str, dims)) + f", eps 0.6, mu {mu}, 1 Gaussian source, FP64, "
+                        f"{m} computed eigentriples; reference: 2sL at k = 1600",
+            "eigentriples": {"seconds": t_eig, "status": int(st), "max_rel_residual": float(info[0]),
+                             "biorth_dev": float(info[1]), "restarts": int(info[2])},
+            "rows": rows}
+
+
 def gradient_timing(ovs, torch, dev, dims=(8, 8, 8, 8), k=400, m_defl=0):
     """ovs_sign_apply_vjp (eps 0.6, mu 0.3, one Gaussian source and cotangent,
     FP64, k iterations) with the Lanczos vectors recomputed from checkpoints and
@@ -411,6 +453,8 @@ def main():
     ap.add_argument("--eig-only", nargs=4, metavar=("LXxLYxLZxLT", "M", "EPS", "MU"), default=None,
                     help="only time ovs_deflation_compute (m eigentriples, FP64, tol 1e-10) on "
                          "that lattice; prints one JSON line")
+    ap.add_argument("--methods-only", action="store_true",
+                    help="only run the 2sL-against-Arnoldi comparison at 8^4; prints one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 5 times: the known-size reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -419,6 +463,11 @@ def main():
         print(json.dumps({"error": "bench.py runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
 
+    if args.methods_only:
+        import torch
+        import paper_0810_4228_amd as ovs
+        print(json.dumps(compare_methods(ovs, torch, torch.device("cuda:0"))))
+        return
     if args.eig_only:
         import torch
         import paper_0810_4228_amd as ovs
@@ -623,9 +672,9 @@ def main():
         out["gradient"] = [gradient_timing(ovs, torch, dev),
                            gradient_timing(ovs, torch, dev, dims=(16, 16, 16, 16), k=200),
                            gradient_timing(ovs, torch, dev, m_defl=30)]
-        log("bench: eigentriples")
-        out["eigentriples"] = eig_timing(ovs, torch, dev)
-        log("bench: eigentriples", out["eigentriples"])
+        log("bench: 2sL against Arnoldi")
+        out["methods"] = compare_methods(ovs, torch, dev)
+        log("bench: methods", out["methods"])
         log("bench: overlap eigenvalues")
         out["overlap_eigs"] = overlap_eigs_timing(ovs, torch, dev)
         log("bench: gradient", out["gradient"])
