@@ -373,9 +373,7 @@ ovs_status compute_eigentriples(ovs_lattice_s* l, int m, double tol, int max_ite
       return OVS_ERR_HIP;
     if (!norms2(cY, 1, yy)) return OVS_ERR_HIP;
     if (hipMemsetAsync(cX, 0, sizeof(double2) * Np, s) != hipSuccess) return OVS_ERR_HIP;
-    const std::vector<double2> ones(1, make_double2(1.0, 0.0));
-    if (hipMemcpyAsync(thd, ones.data(), sizeof(double2), hipMemcpyHostToDevice, s) != hipSuccess)
-      return OVS_ERR_HIP;
+    if (!to_dev(std::vector<cd>(1, cd(1.0)), thd)) return OVS_ERR_HIP;  // theta = 1: resid = a - b
     if (!apply(cY, cW, 1, hb)) return OVS_ERR_HIP;  // b = M^H y (kept in cW until the first step)
     if (!project_add(D, cW, cX)) return OVS_ERR_HIP;
     // r = b - M^H M x, p = r
