@@ -361,8 +361,9 @@ ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, c
  * OVS_VJP_STORE_BASIS, plus (k + 11) nrhs fields with deflation
  * (OVS_ERR_ALLOC if the handle's cache cannot grow to it).
  * Returns OVS_WARN_BREAKDOWN, writing no output, when a source (or the
- * second run) breaks down before k iterations or a deflated eigenvalue is an
- * eigenvalue of G_k; OVS_WARN_SIGN_AMBIGUOUS, with all outputs written, when
+ * second run) breaks down before k iterations, when with deflation a source
+ * lies in span R (|b_R| <= 1e-12 |b|) or chi in span L, or when a deflated
+ * eigenvalue is an eigenvalue of G_k; OVS_WARN_SIGN_AMBIGUOUS, with all outputs written, when
  * the quadrature changed by more than 1e-6 between its two finest steps. */
 ovs_status ovs_sign_apply_vjp(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, const void* b,
                               const void* chi, int32_t nrhs, int32_t k, int32_t flags, void* y,

@@ -141,10 +141,11 @@ __global__ void __launch_bounds__(kScalarWG) k_gf_norm(GradScalars s, const doub
   set_coef(s, kTabNorm, 0, r, {nb > 0.0 ? 1.0 / nb : 0.0, 0.0});
 }
 
-__global__ void __launch_bounds__(kScalarWG) k_gf_start(GradScalars s, const double* part, int nchunk) {
+__global__ void __launch_bounds__(kScalarWG) k_gf_start(GradScalars s, const double* part,
+                                                         const double* part_b, int nchunk) {
   const int r = blockIdx.x;
-  Cx<double> d[2];
-  wg_dot_sums<2>({part, part}, {0, 1}, r, nchunk, d);
+  Cx<double> d[3];
+  wg_dot_sums<3>({part, part, part_b}, {0, 1, 0}, r, nchunk, d);
   if (threadIdx.x != 0) return;
   const double nb = sqrt(d[0].re);
   const Cx<double> sig = d[1];
@@ -152,9 +153,11 @@ __global__ void __launch_bounds__(kScalarWG) k_gf_start(GradScalars s, const dou
   s.sigma[r] = d2(sig);
   s.status[r] = 0;
   set_coef(s, kTabNorm, 0, r, {nb > 0.0 ? 1.0 / nb : 0.0, 0.0});
-  const bool ok = nb > 0.0 && (sig.re != 0.0 || sig.im != 0.0);
+  // |b_R| <= 1e-12 |b|: the source lies in span R (the solve drops the Krylov
+  // part there); like a start with no biorthogonal partner, it has no gradient
+  const bool ok = nb > 1e-12 * sqrt(d[2].re) && (sig.re != 0.0 || sig.im != 0.0);
   set_coef(s, kTabStartW, 0, r, ok ? cdiv(Cx<double>{nb, 0.0}, cconj(sig)) : Cx<double>{0.0, 0.0});
-  if (!ok) s.status[r] = 2;  // no biorthogonal start: the gradient is not defined
+  if (!ok) s.status[r] = 2;
 }
 
 // alpha_i = w_i^dagger t_i (dot 0), |t_i|^2 (dot 1); coefficient rows of the update.
@@ -205,8 +208,9 @@ __global__ void __launch_bounds__(kScalarWG) k_gf_beta(GradScalars s, int i, con
 void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
   hipLaunchKernelGGL(k_gf_norm, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, nchunk);
 }
-void launch_gf_start(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gf_start, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, nchunk);
+void launch_gf_start(const GradScalars& s, const double* part, const double* part_b, int nchunk,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_gf_start, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, part_b, nchunk);
 }
 void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st) {
   hipLaunchKernelGGL(k_gf_alpha, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part, nchunk);

@@ -341,8 +341,9 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     // roles swapped: Q^dagger chi, Q chi and L S R^dagger chi; CDchi = (R^dag chi, L^dag chi)
     launch_defl(d->L, d->R, CHI, d->sgn, md, nrhs, F, P_.dpart, P_.CDchi, P_.CHIL, P_.CHIR,
                 P_.YCHI, l->stream);
+    lin({B}, kTabOne, nullptr, false, {nullptr}, 1, P[1]);
     lin({P_.BR}, kTabOne, nullptr, false, {nullptr, P_.BL}, 2, P[0]);
-    launch_gf_start(S, P[0], nch, l->stream);
+    launch_gf_start(S, P[0], P[1], nch, l->stream);
     lin({P_.BR}, kTabNorm, Vf(0), false, {CHI}, 1, P[3]);
     launch_gf_xbar(S, 0, P[3], nch, l->stream);
     lin({P_.BL}, kTabStartW, Wf(0), false, {}, 0, nullptr);
@@ -504,8 +505,9 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     // second run: A^dagger from Q^dagger chi, left start Q chi, full basis kept
     auto V2 = [&](int i) { return P_.V2 + (size_t)i * NF; };
     auto W2 = [&](int i) { return P_.W2 + (size_t)(i % 3) * NF; };
+    lin2({CHI}, kTabOne, nullptr, false, {nullptr}, 1, P[1]);
     lin2({P_.CHIL}, kTabOne, nullptr, false, {nullptr, P_.CHIR}, 2, P[0]);
-    launch_gf_start(S2, P[0], nch, l->stream);
+    launch_gf_start(S2, P[0], P[1], nch, l->stream);
     lin2({P_.CHIL}, kTabNorm, V2(0), false, {}, 0, nullptr);
     lin2({P_.CHIR}, kTabStartW, W2(0), false, {}, 0, nullptr);
     for (int i = 0; i < k; ++i) {

@@ -81,9 +81,12 @@ inline double2* coef_table(const GradScalars& s, int t) {
 // forward
 void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
 // LR-deflated starts (Section 3): from the dots |b_R|^2 (dot 0) and
-// sigma = b_L^dagger b_R (dot 1): nb = |b_R|, v_1 = b_R / nb (kTabNorm),
-// w_1 = b_L nb / conj(sigma) (kTabStartW), so that w_1^dagger v_1 = 1.
-void launch_gf_start(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
+// sigma = b_L^dagger b_R (dot 1) of part, and |b|^2 (dot 0 of part_b):
+// nb = |b_R|, v_1 = b_R / nb (kTabNorm), w_1 = b_L nb / conj(sigma)
+// (kTabStartW), so that w_1^dagger v_1 = 1; status 2 when sigma = 0 or
+// |b_R| <= 1e-12 |b|.
+void launch_gf_start(const GradScalars& s, const double* part, const double* part_b, int nchunk,
+                     hipStream_t st);
 void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st);
 void launch_gf_beta(const GradScalars& s, int i, const double* part_v, const double* part_w,
                     int nchunk, hipStream_t st);

@@ -169,6 +169,34 @@ def test_vjp_errors(small):
     assert ei.value.status == ovs.OVS_WARN_BREAKDOWN
 
 
+def test_vjp_deflation_errors(small):
+    """Deflation arguments of the gradient: eigentriples of another handle,
+    n_defl beyond the set, and a source inside span(R_m) (b_R = 0: no
+    biorthogonal start, so no gradient: OVS_WARN_BREAKDOWN)."""
+    import paper_0810_4228_amd as ovs
+    from oracle import eigtrip
+    dims, U, mu, b, chi = small
+    A = dirac.dense_A(dims, U, MW, mu)
+    lam, R, L = eigtrip.dense_eigentriples(A, 6)
+    lat = f64_lattice(dims, U, mu)
+    other = f64_lattice(dims, U, mu)
+    d = lat.deflation_set(lam, to_dev(R.T), to_dev(L.T))
+    dother = other.deflation_set(lam, to_dev(R.T), to_dev(L.T))
+    with pytest.raises(ovs.OvsError) as ei:
+        lat.sign_apply_vjp(to_dev(b[None]), to_dev(chi[None]), 10, defl=dother)
+    assert ei.value.status == ovs.OVS_ERR_ARG
+    with pytest.raises(ovs.OvsError) as ei:
+        lat.sign_apply_vjp(to_dev(b[None]), to_dev(chi[None]), 10, defl=d, n_defl=7)
+    assert ei.value.status == ovs.OVS_ERR_ARG
+    with pytest.raises(ovs.OvsError) as ei:
+        lat.sign_apply_vjp(to_dev(R[:, 0][None]), to_dev(chi[None]), 10, defl=d)
+    assert ei.value.status == ovs.OVS_WARN_BREAKDOWN
+    d.close()
+    dother.close()
+    other.close()
+    lat.close()
+
+
 def noisy_tol(f, fd):
     """FD tolerance: 1e-6 relative, plus four times the measured rounding
     noise of the forward divided by the step (the noise is stored with the
