@@ -626,14 +626,20 @@ def _sign_function():
         (b, mu, U); the backward pass is ovs_sign_apply_vjp."""
 
         @staticmethod
-        def forward(ctx, b, mu, U, lat, m_w, k):
+        def forward(ctx, b, mu, U, lat, m_w, k, n_defl, defl_tol):
             lat.set_links(U)
             lat.set_params(m_w, float(mu))
-            y, _, st = lat.sign_apply(b, k)
+            defl = None
+            if n_defl > 0:  # the eigentriples of this (mu, U), kept for the backward pass
+                defl, dst = lat.deflation_compute(n_defl, tol=defl_tol)
+                if dst != OVS_OK:
+                    defl.close()
+                    raise OvsError(dst, "ovs_deflation_compute")
+            y, _, st = lat.sign_apply(b, k, defl=defl)
             if st == OVS_WARN_BREAKDOWN:
                 raise OvsError(st, "ovs_sign_apply")
             ctx.save_for_backward(b, mu, U)
-            ctx.lat, ctx.m_w, ctx.k = lat, m_w, k
+            ctx.lat, ctx.m_w, ctx.k, ctx.defl = lat, m_w, k, defl
             return y
 
         @staticmethod
@@ -642,18 +648,25 @@ def _sign_function():
             lat = ctx.lat
             lat.set_links(U)
             lat.set_params(ctx.m_w, float(mu))
-            _, gb, gmu, gU, _, _ = lat.sign_apply_vjp(b, gy.contiguous(), ctx.k, want_y=False)
+            _, gb, gmu, gU, _, _ = lat.sign_apply_vjp(b, gy.contiguous(), ctx.k, want_y=False,
+                                                       defl=ctx.defl)
+            if ctx.defl is not None:
+                ctx.defl.close()
+                ctx.defl = None
             gmu_t = torch.tensor(gmu, dtype=mu.dtype, device=mu.device)
-            return gb.view_as(b), gmu_t, gU.view_as(U), None, None, None
+            return gb.view_as(b), gmu_t, gU.view_as(U), None, None, None, None, None
 
     _sign_fn = SignFunction
     return _sign_fn
 
 
-def sign_autograd(lat, b, mu, U, m_w, k):
-    """Differentiable y = sgn(A) b by k-step two-sided Lanczos without deflation.
+def sign_autograd(lat, b, mu, U, m_w, k, n_defl=0, defl_tol=1e-10):
+    """Differentiable y = sgn(A) b by k-step two-sided Lanczos.
 
     lat: an FP64 Lattice of the right size; its links and parameters are set
     from U (complex128 [V,4,3,3], CUDA) and mu (real 0-dim tensor) on every
-    call.  b: complex128 CUDA [nrhs, 12V] or [12V]."""
-    return _sign_function().apply(b, mu, U, lat, float(m_w), int(k))
+    call.  b: complex128 CUDA [nrhs, 12V] or [12V].  n_defl > 0: LR deflation
+    by that many eigentriples, computed for this (mu, U) in the forward pass
+    (ovs_deflation_compute to defl_tol) and differentiated through in the
+    backward pass (the deflation-aware gradient)."""
+    return _sign_function().apply(b, mu, U, lat, float(m_w), int(k), int(n_defl), float(defl_tol))
