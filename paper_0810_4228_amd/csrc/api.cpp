@@ -232,44 +232,76 @@ std::vector<double> quad_targets(const double* tol, int nrhs) {
 // each source keeps the x of the first step that met its target (or of the
 // finest), so its result does not depend on the other sources of the batch.
 // err_host[r]: that step's difference.
+//
+// h_level (optional, per source, in and out): on entry the step at which the
+// source's refinement starts (kHStart or a power-of-two fraction of it; a
+// source joins the launches once h has come down to its start), on return
+// the step it was accepted at.  The convergence checks of a solve start at
+// the finest step the previous check needed, so that Ritz values near the
+// imaginary axis do not make every check run the coarser levels (each a
+// launch and a host synchronisation) again.  Without it every source starts
+// at kHStart.
 ovs_status inner_sign(ovs_lattice_s* l, bool tri, const double2* alpha, const double* beta,
                       const double2* gamma, const double2* H, int kmax,
                       const std::vector<int>& kvec, int nrhs, InnerScratch& sc, double2* x,
                       double* err_dev, const std::vector<double>& target,
-                      std::vector<double>& err_host) {
+                      std::vector<double>& err_host, std::vector<double>* h_level = nullptr) {
   hipStream_t s = l->stream;
   std::vector<int> klev(kvec.begin(), kvec.begin() + nrhs);
-  std::vector<double> eh(nrhs, 0.0);
+  std::vector<int> kl(nrhs, 0);
+  std::vector<double> eh(nrhs, 0.0), hs(nrhs, kHStart);
   err_host.assign(nrhs, 0.0);
-  double h = kHStart;
-  for (bool first = true;; first = false) {
-    int n0, nn;
-    quad_range(h, n0, nn);
-    OVS_HIP(hipMemcpyAsync(sc.kv, klev.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-    double2* xl = first ? x : sc.xtmp;  // the first level writes every row
-    if (tri)
-      launch_isign_tri(alpha, beta, gamma, kmax, sc.kv, nrhs, h, n0, nn, sc.mult, sc.swp, sc.part,
-                       xl, err_dev, s);
-    else
-      launch_isign_hess(H, kmax, sc.kv, nrhs, h, n0, nn, sc.ys, sc.acc, xl, err_dev, s);
-    OVS_HIP(hipGetLastError());
-    OVS_HIP(hipMemcpyAsync(eh.data(), err_dev, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
-    OVS_HIP(hipStreamSynchronize(s));
-    const bool last = h <= kHMin;
-    bool any = false;
-    for (int r = 0; r < nrhs; ++r) {
-      if (klev[r] <= 0) continue;
-      if ((eh[r] <= target[r]) || last) {  // NaN stays unaccepted until the last step
-        if (!first)
-          OVS_HIP(hipMemcpyAsync(x + (size_t)r * kmax, sc.xtmp + (size_t)r * kmax,
-                                 sizeof(double2) * kmax, hipMemcpyDeviceToDevice, s));
-        err_host[r] = eh[r];
-        klev[r] = 0;
-      } else {
-        any = true;
-      }
+  if (h_level && (int)h_level->size() >= nrhs)
+    for (int r = 0; r < nrhs; ++r) hs[r] = std::max(kHMin, std::min(kHStart, (*h_level)[r]));
+  // the first step is the coarsest start of an active source (kHStart when
+  // none is active: that launch writes the zero rows)
+  double h = kHMin;
+  bool active = false;
+  for (int r = 0; r < nrhs; ++r)
+    if (klev[r] > 0) {
+      h = std::max(h, hs[r]);
+      active = true;
     }
-    if (!any) break;
+  if (!active) h = kHStart;
+  bool first = true;
+  for (;;) {
+    // the sources that take part at this step: active, and h at or below
+    // their start (steps are powers of two: the comparison is exact)
+    bool any_part = false;
+    for (int r = 0; r < nrhs; ++r) {
+      kl[r] = (klev[r] > 0 && h <= hs[r]) ? klev[r] : 0;
+      any_part = any_part || kl[r] > 0;
+    }
+    if (any_part || first) {
+      int n0, nn;
+      quad_range(h, n0, nn);
+      OVS_HIP(hipMemcpyAsync(sc.kv, kl.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+      double2* xl = first ? x : sc.xtmp;  // the first launch writes every row
+      if (tri)
+        launch_isign_tri(alpha, beta, gamma, kmax, sc.kv, nrhs, h, n0, nn, sc.mult, sc.swp,
+                         sc.part, xl, err_dev, s);
+      else
+        launch_isign_hess(H, kmax, sc.kv, nrhs, h, n0, nn, sc.ys, sc.acc, xl, err_dev, s);
+      OVS_HIP(hipGetLastError());
+      OVS_HIP(hipMemcpyAsync(eh.data(), err_dev, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+      OVS_HIP(hipStreamSynchronize(s));
+      const bool last = h <= kHMin;
+      for (int r = 0; r < nrhs; ++r) {
+        if (kl[r] <= 0) continue;
+        if ((eh[r] <= target[r]) || last) {  // NaN stays unaccepted until the last step
+          if (!first)
+            OVS_HIP(hipMemcpyAsync(x + (size_t)r * kmax, sc.xtmp + (size_t)r * kmax,
+                                   sizeof(double2) * kmax, hipMemcpyDeviceToDevice, s));
+          err_host[r] = eh[r];
+          klev[r] = 0;
+          if (h_level && (int)h_level->size() >= nrhs) (*h_level)[r] = h;
+        }
+      }
+      first = false;
+    }
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) any = any || klev[r] > 0;
+    if (!any || h <= kHMin) break;
     h *= 0.5;
   }
   OVS_HIP(hipStreamSynchronize(s));  // klev lifetime
@@ -1386,6 +1418,9 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       }
     } gg{&graph, &gexec};
     std::vector<std::vector<double>> xprev(nr);
+    // the quadrature step the next convergence check starts at (all sources)
+    double hcheck = kHStart;
+    std::vector<double> hlev;
     int i = 0;
     while (i < K && !amap.empty()) {
       const int iend = (tol || monitor) ? std::min(K, (i / chunk + 1) * chunk) : K;
@@ -1452,9 +1487,20 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
         OVS_HIP(hipStreamSynchronize(s));
         for (int r : amap) ks[r] = std::min(i, hkstop[r]);
         OVS_HIP(hipMemcpyAsync(B.kused, ks.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
+        hlev.assign(nr, hcheck);
         st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, ks, nr, isc, B.x,
-                        B.qerr, qtarget, errh);
+                        B.qerr, qtarget, errh, &hlev);
         if (st != OVS_OK) return st;
+        {
+          // a launch costs about k sequential steps whatever its width, so
+          // the next check starts every source at the finest step one needed
+          // here; when none needed refinement it tries one step coarser (a
+          // Ritz value near the imaginary axis may have moved away)
+          double finest = hcheck;
+          for (int r = 0; r < nr; ++r)
+            if (ks[r] > 0) finest = std::min(finest, hlev[r]);
+          hcheck = finest < hcheck ? finest : std::min(kHStart, 2.0 * hcheck);
+        }
         // relative change of y on the sampled entries since the previous check
         launch_make_coef(B.x, B.sv, B.nb, K, nr, B.coef, s);
         launch_probe_y(B.probes, B.coef, B.kused, K, B.yex, N, B.pidx, P, B.yp, nr, s);

@@ -248,8 +248,23 @@ __global__ void __launch_bounds__(256) k_probe_y(const double2* __restrict__ pro
   const int k = kvec[r];
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
     Cx<double> acc = yex ? c64(yex[(long)r * N + idx[p]]) : Cx<double>{0, 0};
-    for (int i = 0; i < k; ++i)
-      acc = cfma(c64(coef[(long)r * kmax + i]), c64(probes[((long)r * kmax + i) * P + p]), acc);
+    const double2* cr = coef + (long)r * kmax;
+    const double2* pr = probes + (long)r * kmax * P + p;
+    // the same sequential sum as one term per step, with the loads of eight
+    // terms issued before their multiply-adds (one thread's loop is otherwise
+    // a chain of dependent memory latencies)
+    int i = 0;
+    for (; i + 8 <= k; i += 8) {
+      Cx<double> c[8], q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        c[u] = c64(cr[i + u]);
+        q[u] = c64(pr[(long)(i + u) * P]);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cfma(c[u], q[u], acc);
+    }
+    for (; i < k; ++i) acc = cfma(c64(cr[i]), c64(pr[(long)i * P]), acc);
     yp[(long)r * P + p] = d2(acc);
   }
 }
@@ -839,7 +854,7 @@ void launch_probe_gather(bool f32, const void* basis, long basis_stride, long N,
 void launch_probe_y(const double2* probes, const double2* coef, const int* kvec, int kmax,
                     const double2* yex, long N, const int* idx, int P, double2* yp, int nrhs,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_probe_y, dim3(cdiv_i(P, 256), nrhs), dim3(256), 0, s, probes, coef, kvec,
+  hipLaunchKernelGGL(k_probe_y, dim3(cdiv_i(P, 64), nrhs), dim3(64), 0, s, probes, coef, kvec,
                      kmax, yex, N, idx, P, yp);
 }
 

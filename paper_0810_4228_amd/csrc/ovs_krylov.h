@@ -82,8 +82,11 @@ void launch_scale_copy(bool f32, const void* T, void* out, long N, const double*
 // shifted solves in launches of at most kIsignWaveChunk waves of 64 solves
 // per source (mult, swp: [nrhs][kIsignWaveChunk][kmax][64]; part: [nrhs][all
 // waves][2][kmax]); the Hessenberg form kIsignHessChunk solves per source
-// (ys: [nrhs][kIsignHessChunk][kmax]; acc: [nrhs][2][kmax]).
-constexpr int kIsignWaveChunk = 16;
+// (ys: [nrhs][kIsignHessChunk][kmax]; acc: [nrhs][2][kmax]).  A launch takes
+// about k sequential elimination steps whatever its number of waves, so the
+// chunk holds every solve of the rules down to step 1/16 (43 waves): one
+// launch for those, two at 1/32 and four at 1/64.
+constexpr int kIsignWaveChunk = 48;
 constexpr int kIsignHessChunk = 1024;
 int isign_tri_nwave(int nnode);
 void launch_isign_tri(const double2* alpha, const double* beta, const double2* gamma, int kmax,
