@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <thread>
@@ -216,6 +217,7 @@ struct InnerScratch {
   double2* acc = nullptr;
   double2* xtmp = nullptr;
   int* kv = nullptr;
+  QuadNodes* rules = nullptr;  // [nrhs] the rule of each source (tridiagonal form)
 };
 
 // Quadrature target of each source (see kQuadAccept); tol may be NULL.
@@ -234,13 +236,13 @@ std::vector<double> quad_targets(const double* tol, int nrhs) {
 // err_host[r]: that step's difference.
 //
 // h_level (optional, per source, in and out): on entry the step at which the
-// source's refinement starts (kHStart or a power-of-two fraction of it; a
-// source joins the launches once h has come down to its start), on return
-// the step it was accepted at.  The convergence checks of a solve start at
-// the finest step the previous check needed, so that Ritz values near the
-// imaginary axis do not make every check run the coarser levels (each a
-// launch and a host synchronisation) again.  Without it every source starts
-// at kHStart.
+// source's refinement starts (kHStart or a power-of-two fraction of it), on
+// return the step it was accepted at.  Without it every source starts at
+// kHStart.  Every round takes each unaccepted source at its own step: the
+// tridiagonal form in one launch (per-source rules), the Hessenberg form in
+// one launch per distinct step.  A source's steps depend only on its own
+// differences, so its x, and with it the convergence checks that pass their
+// levels from one check to the next, do not depend on the rest of the batch.
 ovs_status inner_sign(ovs_lattice_s* l, bool tri, const double2* alpha, const double* beta,
                       const double2* gamma, const double2* H, int kmax,
                       const std::vector<int>& kvec, int nrhs, InnerScratch& sc, double2* x,
@@ -249,62 +251,79 @@ ovs_status inner_sign(ovs_lattice_s* l, bool tri, const double2* alpha, const do
   hipStream_t s = l->stream;
   std::vector<int> klev(kvec.begin(), kvec.begin() + nrhs);
   std::vector<int> kl(nrhs, 0);
-  std::vector<double> eh(nrhs, 0.0), hs(nrhs, kHStart);
+  std::vector<double> eh(nrhs, 0.0), cur(nrhs, kHStart);
+  std::vector<QuadNodes> rules(nrhs);
   err_host.assign(nrhs, 0.0);
-  if (h_level && (int)h_level->size() >= nrhs)
-    for (int r = 0; r < nrhs; ++r) hs[r] = std::max(kHMin, std::min(kHStart, (*h_level)[r]));
-  // the first step is the coarsest start of an active source (kHStart when
-  // none is active: that launch writes the zero rows)
-  double h = kHMin;
-  bool active = false;
-  for (int r = 0; r < nrhs; ++r)
-    if (klev[r] > 0) {
-      h = std::max(h, hs[r]);
-      active = true;
-    }
-  if (!active) h = kHStart;
-  bool first = true;
-  for (;;) {
-    // the sources that take part at this step: active, and h at or below
-    // their start (steps are powers of two: the comparison is exact)
-    bool any_part = false;
+  const bool lev = h_level && (int)h_level->size() >= nrhs;
+  if (lev)
+    for (int r = 0; r < nrhs; ++r) cur[r] = std::max(kHMin, std::min(kHStart, (*h_level)[r]));
+  bool first = true;  // the first launch writes every row of x
+  // accept or refine the sources that took part in the launch just read back
+  auto settle = [&](const std::vector<int>& part_in) -> ovs_status {
     for (int r = 0; r < nrhs; ++r) {
-      kl[r] = (klev[r] > 0 && h <= hs[r]) ? klev[r] : 0;
-      any_part = any_part || kl[r] > 0;
+      if (part_in[r] <= 0) continue;
+      if ((eh[r] <= target[r]) || cur[r] <= kHMin) {  // NaN stays unaccepted until the last step
+        if (!first)
+          OVS_HIP(hipMemcpyAsync(x + (size_t)r * kmax, sc.xtmp + (size_t)r * kmax,
+                                 sizeof(double2) * kmax, hipMemcpyDeviceToDevice, s));
+        err_host[r] = eh[r];
+        klev[r] = 0;
+        if (lev) (*h_level)[r] = cur[r];
+      } else {
+        cur[r] *= 0.5;
+      }
     }
-    if (any_part || first) {
-      int n0, nn;
-      quad_range(h, n0, nn);
-      OVS_HIP(hipMemcpyAsync(sc.kv, kl.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-      double2* xl = first ? x : sc.xtmp;  // the first launch writes every row
-      if (tri)
-        launch_isign_tri(alpha, beta, gamma, kmax, sc.kv, nrhs, h, n0, nn, sc.mult, sc.swp,
-                         sc.part, xl, err_dev, s);
-      else
-        launch_isign_hess(H, kmax, sc.kv, nrhs, h, n0, nn, sc.ys, sc.acc, xl, err_dev, s);
+    return OVS_OK;
+  };
+  for (;;) {
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) any = any || klev[r] > 0;
+    if (!any && !first) break;
+    if (tri) {
+      int nw = 1;
+      for (int r = 0; r < nrhs; ++r) {
+        int n0, nn;
+        quad_range(klev[r] > 0 ? cur[r] : kHStart, n0, nn);
+        rules[r] = QuadNodes{klev[r] > 0 ? cur[r] : kHStart, n0, nn};
+        if (klev[r] > 0) nw = std::max(nw, isign_tri_nwave(nn));
+      }
+      OVS_HIP(hipMemcpyAsync(sc.kv, klev.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+      OVS_HIP(hipMemcpyAsync(sc.rules, rules.data(), sizeof(QuadNodes) * nrhs,
+                             hipMemcpyHostToDevice, s));
+      launch_isign_tri(alpha, beta, gamma, kmax, sc.kv, nrhs, sc.rules, nw, sc.mult, sc.swp,
+                       sc.part, first ? x : sc.xtmp, err_dev, s);
       OVS_HIP(hipGetLastError());
       OVS_HIP(hipMemcpyAsync(eh.data(), err_dev, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
       OVS_HIP(hipStreamSynchronize(s));
-      const bool last = h <= kHMin;
-      for (int r = 0; r < nrhs; ++r) {
-        if (kl[r] <= 0) continue;
-        if ((eh[r] <= target[r]) || last) {  // NaN stays unaccepted until the last step
-          if (!first)
-            OVS_HIP(hipMemcpyAsync(x + (size_t)r * kmax, sc.xtmp + (size_t)r * kmax,
-                                   sizeof(double2) * kmax, hipMemcpyDeviceToDevice, s));
-          err_host[r] = eh[r];
-          klev[r] = 0;
-          if (h_level && (int)h_level->size() >= nrhs) (*h_level)[r] = h;
-        }
-      }
+      const std::vector<int> took = klev;
+      const ovs_status sst = settle(took);
+      if (sst != OVS_OK) return sst;
       first = false;
+    } else {
+      // one launch per distinct step of the round, coarsest first
+      std::vector<double> steps;
+      for (int r = 0; r < nrhs; ++r)
+        if (klev[r] > 0 && std::find(steps.begin(), steps.end(), cur[r]) == steps.end())
+          steps.push_back(cur[r]);
+      if (steps.empty()) steps.push_back(kHStart);  // no active source: zero rows
+      std::sort(steps.begin(), steps.end(), std::greater<double>());
+      for (double h : steps) {
+        for (int r = 0; r < nrhs; ++r) kl[r] = (klev[r] > 0 && cur[r] == h) ? klev[r] : 0;
+        int n0, nn;
+        quad_range(h, n0, nn);
+        OVS_HIP(hipMemcpyAsync(sc.kv, kl.data(), sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        launch_isign_hess(H, kmax, sc.kv, nrhs, h, n0, nn, sc.ys, sc.acc, first ? x : sc.xtmp,
+                          err_dev, s);
+        OVS_HIP(hipGetLastError());
+        OVS_HIP(hipMemcpyAsync(eh.data(), err_dev, sizeof(double) * nrhs, hipMemcpyDeviceToHost, s));
+        OVS_HIP(hipStreamSynchronize(s));
+        const ovs_status sst = settle(kl);
+        if (sst != OVS_OK) return sst;
+        first = false;
+      }
     }
-    bool any = false;
-    for (int r = 0; r < nrhs; ++r) any = any || klev[r] > 0;
-    if (!any || h <= kHMin) break;
-    h *= 0.5;
   }
-  OVS_HIP(hipStreamSynchronize(s));  // klev lifetime
+  OVS_HIP(hipStreamSynchronize(s));  // host vector lifetimes
   return OVS_OK;
 }
 
@@ -1048,6 +1067,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     double2 *alpha, *gamma, *sw, *coef, *x, *mult, *part, *H, *hcur, *ys, *acc, *xtmp;
     double *beta, *sv, *tnorm2, *qerr, *red, *apart, *red_n, *red_tn, *scl, *dnorm;
     int *kstop, *status, *rhs_map, *ints, *kused, *pidx, *kv;
+    QuadNodes* rules;
     unsigned char* swp;
     double2 *probes, *yp;
     unsigned* bar;
@@ -1093,6 +1113,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     B.coef = a.take<double2>((size_t)nr * K);
     B.xtmp = a.take<double2>((size_t)nr * K);
     B.kv = a.take<int>(nr);
+    B.rules = a.take<QuadNodes>(nr);
     if (probing) {
       B.pidx = a.take<int>(P);
       B.probes = a.take<double2>((size_t)nr * K * P);
@@ -1349,7 +1370,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   std::vector<double> best_est(nr, HUGE_VAL);
   std::vector<int> since_best(nr, 0);
   std::vector<char> stalled(nr, 0);
-  InnerScratch isc{B.mult, B.swp, B.part, B.ys, B.acc, B.xtmp, B.kv};
+  InnerScratch isc{B.mult, B.swp, B.part, B.ys, B.acc, B.xtmp, B.kv, B.rules};
   const std::vector<double> qtarget = quad_targets(tol, nr);
   std::vector<double> errh;
 
@@ -1418,9 +1439,8 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       }
     } gg{&graph, &gexec};
     std::vector<std::vector<double>> xprev(nr);
-    // the quadrature step the next convergence check starts at (all sources)
-    double hcheck = kHStart;
-    std::vector<double> hlev;
+    // per source: the quadrature step its next convergence check starts at
+    std::vector<double> hcheck(nr, kHStart), hlev;
     int i = 0;
     while (i < K && !amap.empty()) {
       const int iend = (tol || monitor) ? std::min(K, (i / chunk + 1) * chunk) : K;
@@ -1487,20 +1507,16 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
         OVS_HIP(hipStreamSynchronize(s));
         for (int r : amap) ks[r] = std::min(i, hkstop[r]);
         OVS_HIP(hipMemcpyAsync(B.kused, ks.data(), sizeof(int) * nr, hipMemcpyHostToDevice, s));
-        hlev.assign(nr, hcheck);
+        hlev = hcheck;
         st = inner_sign(l, true, B.alpha, B.beta, B.gamma, nullptr, K, ks, nr, isc, B.x,
                         B.qerr, qtarget, errh, &hlev);
         if (st != OVS_OK) return st;
-        {
-          // a launch costs about k sequential steps whatever its width, so
-          // the next check starts every source at the finest step one needed
-          // here; when none needed refinement it tries one step coarser (a
-          // Ritz value near the imaginary axis may have moved away)
-          double finest = hcheck;
-          for (int r = 0; r < nr; ++r)
-            if (ks[r] > 0) finest = std::min(finest, hlev[r]);
-          hcheck = finest < hcheck ? finest : std::min(kHStart, 2.0 * hcheck);
-        }
+        // a source that needed refinement starts its next check where it was
+        // accepted; one accepted at its first step tries one step coarser (a
+        // Ritz value near the imaginary axis may have moved away)
+        for (int r = 0; r < nr; ++r)
+          if (ks[r] > 0)
+            hcheck[r] = hlev[r] < hcheck[r] ? hlev[r] : std::min(kHStart, 2.0 * hcheck[r]);
         // relative change of y on the sampled entries since the previous check
         launch_make_coef(B.x, B.sv, B.nb, K, nr, B.coef, s);
         launch_probe_y(B.probes, B.coef, B.kused, K, B.yex, N, B.pidx, P, B.yp, nr, s);
@@ -2068,6 +2084,7 @@ static ovs_status inner_sign_entry(ovs_lattice l, bool tri, int batch, int k, co
     ed = a.take<double>(batch);
     sc.xtmp = a.take<double2>((size_t)batch * k);
     sc.kv = a.take<int>(batch);
+    sc.rules = a.take<QuadNodes>(batch);
   };
   double2 *al = nullptr, *ga = nullptr, *H = nullptr, *xd = nullptr;
   double *be = nullptr, *ed = nullptr;

@@ -477,27 +477,25 @@ __global__ void k_scale_copy(const T2* __restrict__ T, T2* __restrict__ out, lon
 // multiplier and one swap bit per column.
 // ===========================================================================
 
-struct QuadNodes {
-  double h;   // step in u
-  int n0;     // first node index (u = n h)
-  int nnode;  // number of nodes
-};
-
 // One thread per (source r, shifted solve q): q = 2*node + (0: +tau, 1: -tau).
-// Tridiagonal T_r = tridiag(beta, alpha, gamma) of size k_r.  Wave results are
+// Tridiagonal T_r = tridiag(beta, alpha, gamma) of size k_r, with the rule of
+// source r (rules[r]: each source may be at its own step).  Wave results are
 // reduced over lanes: part[r][wave][2][kmax] complex (fine rule, coarse rule),
-// wave = wave0 + blockIdx.x of nwave in all.  A launch covers one chunk of
-// waves; the multipliers of a chunk live in mult/swp [r][blockIdx.x][kmax][64],
-// which the next chunk (ordered on the stream) reuses.
+// wave = wave0 + blockIdx.x of nwave in all; waves beyond a source's nodes
+// write zero rows.  A launch covers one chunk of waves; the multipliers of a
+// chunk live in mult/swp [r][blockIdx.x][kmax][64], which the next chunk
+// (ordered on the stream) reuses.
 __global__ void __launch_bounds__(64) k_isign_tri(const double2* __restrict__ alpha,
                                                   const double* __restrict__ beta,
                                                   const double2* __restrict__ gamma, int kmax,
-                                                  const int* __restrict__ kvec, QuadNodes qn,
+                                                  const int* __restrict__ kvec,
+                                                  const QuadNodes* __restrict__ rules,
                                                   int wave0, int nwave,
                                                   double2* __restrict__ mult,
                                                   unsigned char* __restrict__ swp,
                                                   double2* __restrict__ part) {
   const int r = blockIdx.y;
+  const QuadNodes qn = rules[r];
   const int wave = wave0 + blockIdx.x;
   const int lane = threadIdx.x;
   const int q = wave * 64 + lane;
@@ -515,6 +513,15 @@ __global__ void __launch_bounds__(64) k_isign_tri(const double2* __restrict__ al
   const long mbase = ((long)(r * gridDim.x + blockIdx.x) * kmax) * 64 + lane;
   double2* part_r = part + ((long)r * nwave + wave) * 2 * kmax;
   if (k <= 0) return;
+  if (wave * 64 >= nq) {
+    // beyond this source's nodes (its rule is coarser than another
+    // source's in the launch): zero rows, no solves (uniform over the wave)
+    for (int j = lane; j < k; j += 64) {
+      part_r[j] = make_double2(0.0, 0.0);
+      part_r[kmax + j] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
   // elimination from the bottom: current column j holds (cu: row j-1, cd: row j)
   Cx<double> cu = (k >= 2) ? c64(ga[k - 2]) : Cx<double>{0, 0};
   Cx<double> cd = c64(al[k - 1]) + Cx<double>{0.0, sig};
@@ -968,13 +975,12 @@ void launch_scale_copy(bool f32, const void* T, void* out, long N, const double*
 int isign_tri_nwave(int nnode) { return cdiv_i(2L * nnode, 64); }
 
 void launch_isign_tri(const double2* alpha, const double* beta, const double2* gamma, int kmax,
-                      const int* kvec, int nrhs, double h, int n0, int nnode, double2* mult,
+                      const int* kvec, int nrhs, const QuadNodes* rules, int nwave, double2* mult,
                       unsigned char* swp, double2* part, double2* x, double* err, hipStream_t s) {
-  QuadNodes qn{h, n0, nnode};
-  const int nw = isign_tri_nwave(nnode);
+  const int nw = std::max(nwave, 1);
   for (int w0 = 0; w0 < nw; w0 += kIsignWaveChunk)
     hipLaunchKernelGGL(k_isign_tri, dim3(std::min(kIsignWaveChunk, nw - w0), nrhs), dim3(64), 0,
-                       s, alpha, beta, gamma, kmax, kvec, qn, w0, nw, mult, swp, part);
+                       s, alpha, beta, gamma, kmax, kvec, rules, w0, nw, mult, swp, part);
   hipLaunchKernelGGL(k_isign_final, dim3(nrhs), dim3(256), 0, s, part, nw, kmax, kvec, x, err);
 }
 

@@ -88,9 +88,17 @@ void launch_scale_copy(bool f32, const void* T, void* out, long N, const double*
 // launch for those, two at 1/32 and four at 1/64.
 constexpr int kIsignWaveChunk = 48;
 constexpr int kIsignHessChunk = 1024;
+// A trapezoid rule in u: nodes u = n h for n0 <= n < n0 + nnode.
+struct QuadNodes {
+  double h;   // step in u
+  int n0;     // first node index (u = n h)
+  int nnode;  // number of nodes
+};
 int isign_tri_nwave(int nnode);
+// rules: device array [nrhs], the rule of each source; nwave: the largest
+// isign_tri_nwave over the sources with kvec[r] > 0 (the part stride).
 void launch_isign_tri(const double2* alpha, const double* beta, const double2* gamma, int kmax,
-                      const int* kvec, int nrhs, double h, int n0, int nnode, double2* mult,
+                      const int* kvec, int nrhs, const QuadNodes* rules, int nwave, double2* mult,
                       unsigned char* swp, double2* part, double2* x, double* err, hipStream_t s);
 void launch_isign_hess(const double2* H, int kmax, const int* kvec, int nrhs, double h, int n0,
                        int nnode, double2* ys, double2* acc, double2* x, double* err,
