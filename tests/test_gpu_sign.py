@@ -698,6 +698,30 @@ def test_tolerance_stop_uneven(cfg1):
         assert errs[r] <= 10 * tol[r]
 
 
+def test_tolerance_stop_sources_independent(cfg1):
+    """Sources with different tolerances need different quadrature steps at
+    the convergence checks, and each check takes every source at its own step
+    (one launch for all).  Each source's stopping point and final estimate in
+    the batch equal those of the same source solved alone, and its result
+    agrees to rounding."""
+    dims, U, b1, f = cfg1
+    lat = lattice(dims, "f64", U, float(f["mu"]))
+    d = lat.deflation_set(f["lam"], to_dev(f["R"].T), to_dev(f["L"].T))
+    b = synth.gaussian_sources(dims, 3, seed=71)
+    tol = [1e-3, 1e-7, 1e-10]
+    y, info, st = lat.sign_apply(to_dev(b), 400, defl=d, tol=tol)
+    y = y.cpu().numpy()
+    for r in range(3):
+        y1, i1, s1 = lat.sign_apply(to_dev(b[r:r + 1]), 400, defl=d, tol=[tol[r]])
+        say("source", r, "k", info[r]["k_used"], i1[0]["k_used"], "est", info[r]["est_rel_err"],
+            i1[0]["est_rel_err"], "quad", info[r]["quad_err"], i1[0]["quad_err"])
+        assert s1 == 0
+        assert info[r]["k_used"] == i1[0]["k_used"]
+        assert info[r]["est_rel_err"] == pytest.approx(i1[0]["est_rel_err"], rel=1e-6)
+        assert rel(y1.cpu().numpy()[0], y[r]) <= 1e-13
+    assert st == 0
+
+
 def test_overlap_flag(cfg1):
     """D_ov b = b + gamma5 sgn(A) b (eq. (1.1))."""
     dims, U, b, f = cfg1
