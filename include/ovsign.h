@@ -267,7 +267,7 @@ ovs_status ovs_deflation_destroy(ovs_deflation d);
  * needs (its `workspace` argument): both halves of a batch that is split, with
  * convergence checks, and the one-pass basis for k_max vectors (at 16^3 x 32
  * with 12 sources and k_max = 1000, about 150 GB in FP32 storage;
- * OVS_FLAG_TWO_PASS keeps three vectors: 2.5 GB).  No device work, and links
+ * OVS_FLAG_TWO_PASS keeps three vectors: 2.6 GB).  No device work, and links
  * need not be set; OVS_ERR_ARG as for ovs_sign_apply. */
 ovs_status ovs_workspace_size(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, int32_t nrhs,
                               int32_t k_max, ovs_method method, int32_t flags, size_t* bytes);
