@@ -151,8 +151,15 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     double *CDb, *CDchi, *CDt, *dpart;
     double2 *kappa, *coefQ, *coefL;
     int* kused;
+    // paired stencil (T = A x, S = A^dagger y in one launch): iteration 0,
+    // active count, identity source map; per-tile partials (not used)
+    int* dints;
+    double* dpart2;
   } P_{};
   GradScalars S{}, S2{};
+  // tile of the paired stencil: 64 sites on small lattices, where 256-site
+  // tiles would leave most CUs idle
+  const int dual_tile = (g.V / 256 < 128) ? 64 : 256;
   auto carve_scalars = [&](Arena& a, GradScalars& Sx) {
     const size_t nk = (size_t)nrhs * k;
     Sx.alpha = a.take<double2>(nk);
@@ -187,6 +194,8 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     P_.parts = a.take<double>((size_t)4 * nrhs * nch * 2 * kLinDots);
     P_.fparts = a.take<double>((size_t)(g.V + kWG - 1) / kWG + 1);
     P_.gmu = a.take<double>(1);
+    P_.dints = a.take<int>(2 + (size_t)nrhs);
+    P_.dpart2 = a.take<double>((size_t)nrhs * ((g.V + dual_tile - 1) / dual_tile) * 3);
     P_.vjp = a.take<char>(isign_vjp_scratch_bytes(k, nnmax));
     for (int lv = 0; lv < 2; ++lv) {
       P_.vo[lv].x = a.take<double2>(k);
@@ -258,6 +267,12 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     std::vector<double2> ones((size_t)kLinTerms * nrhs, make_double2(1.0, 0.0));
     OVS_HIP(hipMemcpyAsync(coef_table(S, kTabOne), ones.data(), sizeof(double2) * ones.size(),
                            hipMemcpyHostToDevice, l->stream));
+    std::vector<int> dints(2 + (size_t)nrhs);
+    dints[0] = 0;
+    dints[1] = nrhs;
+    for (int r = 0; r < nrhs; ++r) dints[2 + r] = r;
+    OVS_HIP(hipMemcpyAsync(P_.dints, dints.data(), sizeof(int) * dints.size(),
+                           hipMemcpyHostToDevice, l->stream));
     if (md > 0)
       OVS_HIP(hipMemcpyAsync(coef_table(S2, kTabOne), ones.data(), sizeof(double2) * ones.size(),
                              hipMemcpyHostToDevice, l->stream));
@@ -273,6 +288,16 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
   };
   auto applyAd = [&](const double2* in, double2* out) {
     return launch_wilson(false, l->links, in, out, nrhs, g, hAd, false, true, tn, l->stream);
+  };
+  // ta = A x and tb = A^dagger y in one launch (the dual stencil of the solve,
+  // one thread per site for both operators): half the launches of a pair of
+  // applications, and the links read once.  Every step of the forward pass,
+  // its replay and the reverse sweep uses it, so replayed vectors stay
+  // bitwise equal to the forward ones.
+  auto applyBoth = [&](const double2* x, const double2* y, double2* ta, double2* tb) {
+    DualArgs da{l->links, x, y, 0, false, P_.dints, ta, tb, P_.dpart2, P_.dints + 2,
+                P_.dints + 1, nrhs, 0, 0, 0, 0, dual_tile};
+    return launch_dual(false, da, g, hA, hAd, 1, l->stream);
   };
   auto mks = [&](const GradScalars& Sx, std::initializer_list<const double2*> xs, int tab,
                  double2* out, bool acc, std::initializer_list<const double2*> ys, int ndot,
@@ -357,11 +382,11 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
   }
   OVS_HIP(save_ckpt(0));
   for (int i = 0; i < k; ++i) {
-    OVS_HIP(applyA(Vf(i), T));
+    if (i < k - 1) OVS_HIP(applyBoth(Vf(i), Wf(i), T, Sv));
+    else OVS_HIP(applyA(Vf(i), T));
     lin({T}, kTabOne, nullptr, false, {Wf(i), nullptr}, 2, P[0]);
     launch_gf_alpha(S, i, P[0], nch, l->stream);
     if (i == k - 1) break;
-    OVS_HIP(applyAd(Wf(i), Sv));
     if (i > 0) {
       lin({T, Vf(i), Vf(i - 1)}, kTabV, Vf(i + 1), false, {nullptr}, 1, P[1]);
       lin({Sv, Wf(i), Wf(i - 1)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2, P[2]);
@@ -627,8 +652,7 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
       OVS_HIP(copy(Wr(lo), P_.ckW + (size_t)(2 * j + 1) * NF));
       for (int i = lo; i < top; ++i) {
         launch_gp_coef(S, i, l->stream);
-        OVS_HIP(applyA(Vr(i), T));
-        OVS_HIP(applyAd(Wr(i), Sv));
+        OVS_HIP(applyBoth(Vr(i), Wr(i), T, Sv));
         if (i > 0)
           multi({mk({T, Vr(i), Vr(i - 1)}, kTabV, Vr(i + 1), false, {}, 0, nullptr),
                  mk({Sv, Wr(i), Wr(i - 1)}, kTabW, Wr(i + 1), false, {}, 0, nullptr)});
@@ -673,8 +697,7 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
         m2.a[m2.n++] = mk({WTB[p], WTB[c], Vr(i + 1), Vr(i)}, kTabWB, WB[c], false, {}, 0, nullptr);
       if (y) m2.a[m2.n++] = mk({Vr(i)}, kTabY, YA, true, {}, 0, nullptr);
       launch_lin_multi(m2, F, nrhs, l->stream);
-      OVS_HIP(applyAd(TB, T1));
-      OVS_HIP(applyA(WTB[c], T2));
+      OVS_HIP(applyBoth(WTB[c], TB, T2, T1));
       multi({mk({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]),
              mk({T2}, kTabOne, WB[c], true, {Wr(i)}, 1, P[3])});
       {

@@ -187,6 +187,9 @@ struct DualArgs {
                        // same with the tile's spinors staged in LDS; 5: one
                        // operator and source per workgroup marching along t
                        // (k_dual_march; order 0 or 1)
+  int tile = 256;      // sites per tile of k_dual (pair 0): 256, or 64 for small
+                       // lattices (more workgroups); the other variants need 256;
+                       // partials are [slot][ceil(V / tile)][3]
 };
 hipError_t launch_dual(bool f32, const DualArgs& a, const Geometry& g, const Hop& hA,
                        const Hop& hAd, int rhs_block, hipStream_t s);

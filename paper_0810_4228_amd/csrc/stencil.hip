@@ -914,7 +914,8 @@ template <typename R, int B>
 static hipError_t launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, const Hop& hAd,
                      hipStream_t s) {
   using T2 = typename Vec2<R>::T;
-  const TileMap tm = make_tile_map(g, 256, (a.nrhs_slots + B - 1) / B, a.order);
+  if (a.tile != 256 && (a.tile != 64 || a.pair != 0)) return hipErrorInvalidValue;
+  const TileMap tm = make_tile_map(g, a.tile, (a.nrhs_slots + B - 1) / B, a.order);
   // the staged planes take 2 B 12 256 complex values of LDS: one or two sources
   constexpr bool kStage = 2 * B * 12 * 256 * sizeof(T2) <= 100 * 1024;
   // the operator-per-workgroup variant stages one field: B 12 256 values
@@ -985,7 +986,7 @@ static hipError_t launch_d(const DualArgs& a, const Geometry& g, const Hop& hA, 
                        (T2*)a.out_s, a.partials, g, HopR<R>::make(hA), HopR<R>::make(hAd),
                        a.rhs_map, a.n_active, a.nt, tm);
   else
-    hipLaunchKernelGGL((k_dual<R, B>), dim3(8 * tm.per_xcd), dim3(256), a.lds_kb * 1024, s,
+    hipLaunchKernelGGL((k_dual<R, B>), dim3(8 * tm.per_xcd), dim3(a.tile), a.lds_kb * 1024, s,
                        (const T2*)a.links, (const T2*)a.basis, (const T2*)a.wbuf, a.basis_stride,
                        (int)a.ring, a.it, (T2*)a.out_t, (T2*)a.out_s, a.partials, g,
                        HopR<R>::make(hA), HopR<R>::make(hAd), a.rhs_map, a.n_active, a.nt, tm);
