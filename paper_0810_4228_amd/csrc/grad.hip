@@ -28,13 +28,24 @@ int lin_nchunk(long stride) {
   return (int)c;
 }
 
-__device__ __forceinline__ void lin_body(const LinArgs& a, long stride, int nrhs, double* lds) {
+// TAB: the launch ran a scalar step whose coefficient rows are in `tab`
+// (LDS); a combination with a.tab >= 0 takes them from there instead of the
+// global table a.coef.
+template <bool TAB>
+__device__ __forceinline__ void lin_body(const LinArgs& a, long stride, int nrhs, double* lds,
+                                         const double2 (*tab)[kLinTerms]) {
   const int r = blockIdx.y;
   const long off = (long)r * stride;
   Cx<double> c[kLinTerms];
+  if (TAB && a.tab >= 0) {
 #pragma unroll
-  for (int j = 0; j < kLinTerms; ++j)
-    c[j] = (j < a.nterm) ? c64(a.coef[(long)j * nrhs + r]) : Cx<double>{0.0, 0.0};
+    for (int j = 0; j < kLinTerms; ++j)
+      c[j] = (j < a.nterm) ? c64(tab[a.tab][j]) : Cx<double>{0.0, 0.0};
+  } else {
+#pragma unroll
+    for (int j = 0; j < kLinTerms; ++j)
+      c[j] = (j < a.nterm) ? c64(a.coef[(long)j * nrhs + r]) : Cx<double>{0.0, 0.0};
+  }
   double part[2 * kLinDots];
 #pragma unroll
   for (int q = 0; q < 2 * kLinDots; ++q) part[q] = 0.0;
@@ -66,7 +77,7 @@ __device__ __forceinline__ void lin_body(const LinArgs& a, long stride, int nrhs
 
 __global__ void __launch_bounds__(kWG) k_lin(LinArgs a, long stride, int nrhs) {
   __shared__ double lds[(kWG / 64) * 2 * kLinDots];
-  lin_body(a, stride, nrhs, lds);
+  lin_body<false>(a, stride, nrhs, lds, nullptr);
 }
 
 // Several independent linear combinations in one launch: each is computed as
@@ -77,7 +88,7 @@ __global__ void __launch_bounds__(kWG) k_lin_multi(LinMulti m, long stride, int 
   __shared__ double lds[(kWG / 64) * 2 * kLinDots];
   for (int j = 0; j < m.n; ++j) {
     __syncthreads();  // lds of the previous combination
-    lin_body(m.a[j], stride, nrhs, lds);
+    lin_body<false>(m.a[j], stride, nrhs, lds, nullptr);
   }
 }
 
@@ -128,6 +139,24 @@ __device__ __forceinline__ void set_coef(const GradScalars& s, int t, int j, int
   s.coef[((long)t * kLinTerms + j) * s.nrhs + r] = d2(v);
 }
 
+// Where a scalar step puts the coefficient rows it forms for source r: the
+// LDS table of the linear combination that follows it in the same launch
+// (`lds`, read by all of that launch's threads), and/or the global tables
+// (`coef`) for later launches.  `wr`: the step also writes its scalars
+// (alpha, beta, ...) to global memory; in a combination launch only its
+// first workgroup of each source does.
+struct TabOut {
+  double2 (*lds)[kLinTerms];
+  double2* coef;
+  int nrhs;
+  int r;
+  bool wr;
+  __device__ void put(int t, int j, Cx<double> v) const {
+    if (lds) lds[t][j] = d2(v);
+    if (coef) coef[((long)t * kLinTerms + j) * nrhs + r] = d2(v);
+  }
+};
+
 // ---- forward scalar steps ------------------------------------------------------
 
 __global__ void __launch_bounds__(kScalarWG) k_gf_norm(GradScalars s, const double* part, int nchunk) {
@@ -160,32 +189,40 @@ __global__ void __launch_bounds__(kScalarWG) k_gf_start(GradScalars s, const dou
   if (!ok) s.status[r] = 2;
 }
 
-// alpha_i = w_i^dagger t_i (dot 0), |t_i|^2 (dot 1); coefficient rows of the update.
-__global__ void __launch_bounds__(kScalarWG) k_gf_alpha(GradScalars s, int i, const double* part, int nchunk) {
-  const int r = blockIdx.x;
+// alpha_i = w_i^dagger t_i (dot 0), |t_i|^2 (dot 1); coefficient rows of the
+// update.  All threads of the workgroup take part (the dot sums); thread 0
+// forms the rows.
+__device__ void step_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk,
+                              const TabOut& o) {
+  const int r = o.r;
   Cx<double> d[2];
   wg_dot_sums<2>({part, part}, {0, 1}, r, nchunk, d);
   if (threadIdx.x != 0) return;
   const long rk = (long)r * s.kmax;
   const Cx<double> al = d[0];
-  s.alpha[rk + i] = d2(al);
-  s.tnorm2[rk + i] = d[1].re;
+  if (o.wr) {
+    s.alpha[rk + i] = d2(al);
+    s.tnorm2[rk + i] = d[1].re;
+  }
   const Cx<double> gprev = (i > 0) ? c64(s.gamma[rk + i - 1]) : Cx<double>{0.0, 0.0};
   const double bprev = (i > 0) ? s.beta[rk + i - 1] : 0.0;
-  set_coef(s, kTabV, 0, r, {1.0, 0.0});
-  set_coef(s, kTabV, 1, r, -al);
-  set_coef(s, kTabV, 2, r, -gprev);
-  set_coef(s, kTabW, 0, r, {1.0, 0.0});
-  set_coef(s, kTabW, 1, r, -cconj(al));
-  set_coef(s, kTabW, 2, r, {-bprev, 0.0});
+  o.put(kTabV, 0, {1.0, 0.0});
+  o.put(kTabV, 1, -al);
+  o.put(kTabV, 2, -gprev);
+  o.put(kTabW, 0, {1.0, 0.0});
+  o.put(kTabW, 1, -cconj(al));
+  o.put(kTabW, 2, {-bprev, 0.0});
+}
+__global__ void __launch_bounds__(kScalarWG) k_gf_alpha(GradScalars s, int i, const double* part, int nchunk) {
+  step_gf_alpha(s, i, part, nchunk, TabOut{nullptr, s.coef, s.nrhs, (int)blockIdx.x, true});
 }
 
 // beta_i = |v~|, delta_i = w~^dagger v~, gamma_i = delta_i / beta_i, with the
 // breakdown tests of the forward recurrences (lucky: |v~| <= 1e-14 |t|;
 // serious: |delta| <= 1e-13 |v~| |w~|).
-__global__ void __launch_bounds__(kScalarWG) k_gf_beta(GradScalars s, int i, const double* part_v,
-                                                      const double* part_w, int nchunk) {
-  const int r = blockIdx.x;
+__device__ void step_gf_beta(const GradScalars& s, int i, const double* part_v,
+                             const double* part_w, int nchunk, const TabOut& o) {
+  const int r = o.r;
   Cx<double> d[3];
   wg_dot_sums<3>({part_v, part_w, part_w}, {0, 0, 1}, r, nchunk, d);
   if (threadIdx.x != 0) return;
@@ -193,16 +230,22 @@ __global__ void __launch_bounds__(kScalarWG) k_gf_beta(GradScalars s, int i, con
   const double vn = sqrt(d[0].re);
   const Cx<double> delta = cconj(d[1]);  // dot 0 of part_w = v~^dagger w~
   const double wn = sqrt(d[2].re);
-  if (s.status[r] == 0) {
-    if (vn <= 1e-14 * sqrt(s.tnorm2[rk + i])) s.status[r] = 1;
-    else if (cabs1(delta) <= 1e-13 * vn * wn) s.status[r] = 2;
-  }
   const Cx<double> g = vn > 0.0 ? scale(1.0 / vn, delta) : Cx<double>{0.0, 0.0};
-  s.beta[rk + i] = vn;
-  s.gamma[rk + i] = d2(g);
-  set_coef(s, kTabSV, 0, r, {vn > 0.0 ? 1.0 / vn : 0.0, 0.0});
+  if (o.wr) {
+    if (s.status[r] == 0) {
+      if (vn <= 1e-14 * sqrt(s.tnorm2[rk + i])) s.status[r] = 1;
+      else if (cabs1(delta) <= 1e-13 * vn * wn) s.status[r] = 2;
+    }
+    s.beta[rk + i] = vn;
+    s.gamma[rk + i] = d2(g);
+  }
+  o.put(kTabSV, 0, {vn > 0.0 ? 1.0 / vn : 0.0, 0.0});
   const bool gz = g.re == 0.0 && g.im == 0.0;
-  set_coef(s, kTabSW, 0, r, gz ? Cx<double>{0.0, 0.0} : cdiv({1.0, 0.0}, cconj(g)));
+  o.put(kTabSW, 0, gz ? Cx<double>{0.0, 0.0} : cdiv({1.0, 0.0}, cconj(g)));
+}
+__global__ void __launch_bounds__(kScalarWG) k_gf_beta(GradScalars s, int i, const double* part_v,
+                                                      const double* part_w, int nchunk) {
+  step_gf_beta(s, i, part_v, part_w, nchunk, TabOut{nullptr, s.coef, s.nrhs, (int)blockIdx.x, true});
 }
 
 void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
@@ -249,9 +292,12 @@ __global__ void k_gr_first(GradScalars s) {
 //   dbar    = gbar_i / beta_i
 //   vbar~_i = vbar_{i+1}/beta_i + bbar_i v_{i+1} + dbar conj(gamma_i) w_{i+1}
 //   wbar~_i = wbar_{i+1}/gamma_i + conj(dbar) beta_i v_{i+1}
-__global__ void __launch_bounds__(kScalarWG) k_gr_s1(GradScalars s, int i, const double* part_v,
-                                                    const double* part_w, int nchunk) {
-  const int r = blockIdx.x;
+// gbar_i and bbar_i are read here and used nowhere after this step, so the
+// updated values are not written back (a combination launch that forms them
+// in every workgroup could not write them without racing its own reads).
+__device__ void step_gr_s1(const GradScalars& s, int i, const double* part_v, const double* part_w,
+                           int nchunk, const TabOut& o) {
+  const int r = o.r;
   Cx<double> d[2];
   wg_dot_sums<2>({part_v, part_w}, {0, 0}, r, nchunk, d);
   if (threadIdx.x != 0) return;
@@ -266,13 +312,15 @@ __global__ void __launch_bounds__(kScalarWG) k_gr_s1(GradScalars s, int i, const
   bb -= d2v.re / be;
   const Cx<double> db = scale(1.0 / be, gb);
   bb -= (gb.re * ga.re + gb.im * ga.im) / be;  // Re(conj(gbar) gamma)
-  s.gbar[rk + i] = d2(gb);
-  s.bbar[rk + i] = bb;
-  set_coef(s, kTabV, 0, r, {1.0 / be, 0.0});
-  set_coef(s, kTabV, 1, r, {bb, 0.0});
-  set_coef(s, kTabV, 2, r, cmul(db, cconj(ga)));
-  set_coef(s, kTabW, 0, r, cdiv({1.0, 0.0}, ga));
-  set_coef(s, kTabW, 1, r, scale(be, cconj(db)));
+  o.put(kTabV, 0, {1.0 / be, 0.0});
+  o.put(kTabV, 1, {bb, 0.0});
+  o.put(kTabV, 2, cmul(db, cconj(ga)));
+  o.put(kTabW, 0, cdiv({1.0, 0.0}, ga));
+  o.put(kTabW, 1, scale(be, cconj(db)));
+}
+__global__ void __launch_bounds__(kScalarWG) k_gr_s1(GradScalars s, int i, const double* part_v,
+                                                    const double* part_w, int nchunk) {
+  step_gr_s1(s, i, part_v, part_w, nchunk, TabOut{nullptr, s.coef, s.nrhs, (int)blockIdx.x, true});
 }
 
 // Step i < k-1, second half.  Inputs: v_i^dagger vbar~ (d5), v_{i-1}^dagger vbar~
@@ -285,9 +333,11 @@ __global__ void __launch_bounds__(kScalarWG) k_gr_s1(GradScalars s, int i, const
 //   vbar_i = nb conj(x_i) chi - conj(gamma_i) vbar~_{i+1} - conj(alpha_i) vbar~_i
 //   wbar_i = -beta_i wbar~_{i+1} - alpha_i wbar~_i + conj(abar_i) t_i,
 //            t_i = beta_i v_{i+1} + alpha_i v_i + gamma_{i-1} v_{i-1}
-__global__ void __launch_bounds__(kScalarWG) k_gr_s2(GradScalars s, int i, const double* part_v,
-                                                    const double* part_w, int nchunk) {
-  const int r = blockIdx.x;
+// abar_i is read here and used nowhere after this step (not written back, as
+// gbar_i in step 1); bbar_{i-1}, gbar_{i-1} are written for step i-1.
+__device__ void step_gr_s2(const GradScalars& s, int i, const double* part_v, const double* part_w,
+                           int nchunk, const TabOut& o) {
+  const int r = o.r;
   // dots 1 exist for i > 0 only; at i = 0 their sums are formed and not used
   Cx<double> d[4];
   wg_dot_sums<4>({part_v, part_w, part_v, part_w}, {0, 0, 1, 1}, r, nchunk, d);
@@ -295,9 +345,8 @@ __global__ void __launch_bounds__(kScalarWG) k_gr_s2(GradScalars s, int i, const
   const long rk = (long)r * s.kmax;
   const Cx<double> d5 = d[0];
   const Cx<double> d4 = cconj(d[1]);
-  Cx<double> ab = c64(s.abar[rk + i]) - d4 - d5;
-  s.abar[rk + i] = d2(ab);
-  if (i > 0) {
+  const Cx<double> ab = c64(s.abar[rk + i]) - d4 - d5;
+  if (o.wr && i > 0) {
     const Cx<double> d6 = d[2];
     const Cx<double> d3 = d[3];
     s.bbar[rk + i - 1] -= d3.re;
@@ -307,18 +356,22 @@ __global__ void __launch_bounds__(kScalarWG) k_gr_s2(GradScalars s, int i, const
   const Cx<double> ga = c64(s.gamma[rk + i]);
   const double be = s.beta[rk + i];
   const Cx<double> gprev = (i > 0) ? c64(s.gamma[rk + i - 1]) : Cx<double>{0.0, 0.0};
-  set_coef(s, kTabSV, 0, r, {1.0, 0.0});
-  set_coef(s, kTabSV, 1, r, ab);
-  set_coef(s, kTabSW, 0, r, scale(s.nb[r], cconj(c64(s.x[rk + i]))));
-  set_coef(s, kTabSW, 1, r, -cconj(ga));
-  set_coef(s, kTabSW, 2, r, -cconj(al));
+  o.put(kTabSV, 0, {1.0, 0.0});
+  o.put(kTabSV, 1, ab);
+  o.put(kTabSW, 0, scale(s.nb[r], cconj(c64(s.x[rk + i]))));
+  o.put(kTabSW, 1, -cconj(ga));
+  o.put(kTabSW, 2, -cconj(al));
   const Cx<double> cab = cconj(ab);
-  set_coef(s, kTabWB, 0, r, {-be, 0.0});
-  set_coef(s, kTabWB, 1, r, -al);
-  set_coef(s, kTabWB, 2, r, scale(be, cab));
-  set_coef(s, kTabWB, 3, r, cmul(cab, al));
-  set_coef(s, kTabWB, 4, r, cmul(cab, gprev));
-  set_coef(s, kTabY, 0, r, scale(s.nb[r], c64(s.x[rk + i])));
+  o.put(kTabWB, 0, {-be, 0.0});
+  o.put(kTabWB, 1, -al);
+  o.put(kTabWB, 2, scale(be, cab));
+  o.put(kTabWB, 3, cmul(cab, al));
+  o.put(kTabWB, 4, cmul(cab, gprev));
+  o.put(kTabY, 0, scale(s.nb[r], c64(s.x[rk + i])));
+}
+__global__ void __launch_bounds__(kScalarWG) k_gr_s2(GradScalars s, int i, const double* part_v,
+                                                    const double* part_w, int nchunk) {
+  step_gr_s2(s, i, part_v, part_w, nchunk, TabOut{nullptr, s.coef, s.nrhs, (int)blockIdx.x, true});
 }
 
 // v_1 = w_1 = b/|b|: grad_b = ubar/|b| + nbar v_1 with ubar = vbar_1 + wbar_1 and
@@ -394,40 +447,105 @@ void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipSt
 
 // ---- source projections and replay coefficients -----------------------------
 
-__global__ void __launch_bounds__(kScalarWG) k_gf_xbar(GradScalars s, int i, const double* part, int nchunk) {
-  const int r = blockIdx.x;
+__device__ void step_gf_xbar(const GradScalars& s, int i, const double* part, int nchunk,
+                             const TabOut& o) {
+  const int r = o.r;
   Cx<double> d[1];
   wg_dot_sums<1>({part}, {0}, r, nchunk, d);  // chi^dagger v_i
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || !o.wr) return;
   s.xbar[(long)r * s.kmax + i] = d2(scale(s.nb[r], cconj(d[0])));
+}
+__global__ void __launch_bounds__(kScalarWG) k_gf_xbar(GradScalars s, int i, const double* part, int nchunk) {
+  step_gf_xbar(s, i, part, nchunk, TabOut{nullptr, nullptr, s.nrhs, (int)blockIdx.x, true});
 }
 
 void launch_gf_xbar(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st) {
   hipLaunchKernelGGL(k_gf_xbar, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part, nchunk);
 }
 
-__global__ void k_gp_coef(GradScalars s, int i) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
+// The rows of the forward update and normalisation of step i from the stored
+// coefficients, with the arithmetic of steps alpha and beta (one thread).
+__device__ void gp_coef_rows(const GradScalars& s, int i, const TabOut& o) {
+  const int r = o.r;
   const long rk = (long)r * s.kmax;
   const Cx<double> al = c64(s.alpha[rk + i]);
   const Cx<double> gprev = (i > 0) ? c64(s.gamma[rk + i - 1]) : Cx<double>{0.0, 0.0};
   const double bprev = (i > 0) ? s.beta[rk + i - 1] : 0.0;
-  set_coef(s, kTabV, 0, r, {1.0, 0.0});
-  set_coef(s, kTabV, 1, r, -al);
-  set_coef(s, kTabV, 2, r, -gprev);
-  set_coef(s, kTabW, 0, r, {1.0, 0.0});
-  set_coef(s, kTabW, 1, r, -cconj(al));
-  set_coef(s, kTabW, 2, r, {-bprev, 0.0});
+  o.put(kTabV, 0, {1.0, 0.0});
+  o.put(kTabV, 1, -al);
+  o.put(kTabV, 2, -gprev);
+  o.put(kTabW, 0, {1.0, 0.0});
+  o.put(kTabW, 1, -cconj(al));
+  o.put(kTabW, 2, {-bprev, 0.0});
   const double vn = s.beta[rk + i];
   const Cx<double> g = c64(s.gamma[rk + i]);
-  set_coef(s, kTabSV, 0, r, {vn > 0.0 ? 1.0 / vn : 0.0, 0.0});
+  o.put(kTabSV, 0, {vn > 0.0 ? 1.0 / vn : 0.0, 0.0});
   const bool gz = g.re == 0.0 && g.im == 0.0;
-  set_coef(s, kTabSW, 0, r, gz ? Cx<double>{0.0, 0.0} : cdiv({1.0, 0.0}, cconj(g)));
+  o.put(kTabSW, 0, gz ? Cx<double>{0.0, 0.0} : cdiv({1.0, 0.0}, cconj(g)));
+}
+__global__ void k_gp_coef(GradScalars s, int i) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= s.nrhs) return;
+  gp_coef_rows(s, i, TabOut{nullptr, s.coef, s.nrhs, r, true});
 }
 
 void launch_gp_coef(const GradScalars& s, int i, hipStream_t st) {
   hipLaunchKernelGGL(k_gp_coef, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i);
+}
+
+// ---- linear combinations preceded by their scalar step ------------------------
+// Every workgroup of source r forms the step's coefficient rows itself (the
+// same dot sums in the same order, kWG = kScalarWG threads, so the same
+// values as the separate scalar kernel) and keeps them in LDS; the first
+// workgroup of each source also writes the step's scalars and, with
+// global_tabs, the global tables.  That saves the scalar kernel's launch.
+// Every value a step reads is written by earlier launches and none is
+// written in this one, except the scalars of workgroup 0, which no other
+// workgroup of the launch reads.
+__device__ void run_step(const ScalarStep& st, double2 (*tab)[kLinTerms]) {
+  const bool first = blockIdx.x == 0;
+  const TabOut o{tab, (st.global_tabs && first) ? st.s.coef : nullptr, st.s.nrhs, (int)blockIdx.y,
+                 first};
+  switch (st.kind) {
+    case kStepAlpha: step_gf_alpha(st.s, st.i, st.pa, st.nchunk, o); break;
+    case kStepBeta: step_gf_beta(st.s, st.i, st.pa, st.pb, st.nchunk, o); break;
+    case kStepXbar: step_gf_xbar(st.s, st.i, st.pa, st.nchunk, o); break;
+    case kStepCoef:
+      if (threadIdx.x == 0) gp_coef_rows(st.s, st.i, o);
+      break;
+    case kStepS1: step_gr_s1(st.s, st.i, st.pa, st.pb, st.nchunk, o); break;
+    case kStepS2: step_gr_s2(st.s, st.i, st.pa, st.pb, st.nchunk, o); break;
+    default: break;
+  }
+  __syncthreads();  // the rows in LDS for every thread
+}
+
+__global__ void __launch_bounds__(kWG) k_lin_step(LinArgs a, long stride, int nrhs, ScalarStep st) {
+  __shared__ double lds[(kWG / 64) * 2 * kLinDots];
+  __shared__ double2 tab[kCoefTables][kLinTerms];
+  run_step(st, tab);
+  lin_body<true>(a, stride, nrhs, lds, tab);
+}
+
+__global__ void __launch_bounds__(kWG) k_lin_multi_step(LinMulti m, long stride, int nrhs,
+                                                        ScalarStep st) {
+  __shared__ double lds[(kWG / 64) * 2 * kLinDots];
+  __shared__ double2 tab[kCoefTables][kLinTerms];
+  run_step(st, tab);
+  for (int j = 0; j < m.n; ++j) {
+    __syncthreads();  // lds of the previous combination
+    lin_body<true>(m.a[j], stride, nrhs, lds, tab);
+  }
+}
+
+void launch_lin_step(const LinArgs& a, long stride, int nrhs, const ScalarStep& st, hipStream_t s) {
+  hipLaunchKernelGGL(k_lin_step, dim3(lin_nchunk(stride), nrhs), dim3(kWG), 0, s, a, stride, nrhs,
+                     st);
+}
+void launch_lin_multi_step(const LinMulti& m, long stride, int nrhs, const ScalarStep& st,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_lin_multi_step, dim3(lin_nchunk(stride), nrhs), dim3(kWG), 0, s, m, stride,
+                     nrhs, st);
 }
 
 // ---- inner sign and its vector-Jacobian product -----------------------------------

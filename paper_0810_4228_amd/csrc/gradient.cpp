@@ -336,6 +336,28 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     for (const LinArgs& a : las) m.a[m.n++] = a;
     launch_lin_multi(m, F, nrhs, l->stream);
   };
+  // a combination whose coefficients come from the scalar step run at the
+  // start of the same launch (table `tab` of the step)
+  auto from_step = [](LinArgs a, int tab) {
+    a.tab = tab;
+    return a;
+  };
+  auto step_of = [&](int kind, int i, const double* pa, const double* pb, bool global_tabs) {
+    ScalarStep st;
+    st.kind = kind;
+    st.i = i;
+    st.pa = pa;
+    st.pb = pb;
+    st.nchunk = nch;
+    st.s = S;
+    st.global_tabs = global_tabs ? 1 : 0;
+    return st;
+  };
+  auto multi_step = [&](const ScalarStep& st, std::initializer_list<LinArgs> las) {
+    LinMulti m;
+    for (const LinArgs& a : las) m.a[m.n++] = a;
+    launch_lin_multi_step(m, F, nrhs, st, l->stream);
+  };
   auto copy = [&](double2* dst, const double2* src) {
     return hipMemcpyAsync(dst, src, sizeof(double2) * NF, hipMemcpyDeviceToDevice, l->stream);
   };
@@ -381,23 +403,37 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     lin({B}, kTabNorm, Wf(0), false, {}, 0, nullptr);
   }
   OVS_HIP(save_ckpt(0));
+  // Each step's scalar kernels (alpha, beta, xbar) run at the start of the
+  // combination launch that follows them (launch_lin_step): five launches
+  // per step.
   for (int i = 0; i < k; ++i) {
     if (i < k - 1) OVS_HIP(applyBoth(Vf(i), Wf(i), T, Sv));
     else OVS_HIP(applyA(Vf(i), T));
-    lin({T}, kTabOne, nullptr, false, {Wf(i), nullptr}, 2, P[0]);
-    launch_gf_alpha(S, i, P[0], nch, l->stream);
-    if (i == k - 1) break;
+    // dots w_i^dagger t, |t|^2; xbar_i from the previous step's chi^dagger v_i
+    if (i > 0)
+      launch_lin_step(mk({T}, kTabOne, nullptr, false, {Wf(i), nullptr}, 2, P[0]), F, nrhs,
+                      step_of(kStepXbar, i, P[3], nullptr, false), l->stream);
+    else
+      lin({T}, kTabOne, nullptr, false, {Wf(i), nullptr}, 2, P[0]);
+    if (i == k - 1) {
+      launch_gf_alpha(S, i, P[0], nch, l->stream);
+      break;
+    }
+    // alpha_i (written, with the W rows for the next launch, by workgroup 0)
+    const ScalarStep sa = step_of(kStepAlpha, i, P[0], nullptr, true);
     if (i > 0) {
-      lin({T, Vf(i), Vf(i - 1)}, kTabV, Vf(i + 1), false, {nullptr}, 1, P[1]);
+      launch_lin_step(from_step(mk({T, Vf(i), Vf(i - 1)}, kTabV, Vf(i + 1), false, {nullptr}, 1,
+                                   P[1]), kTabV), F, nrhs, sa, l->stream);
       lin({Sv, Wf(i), Wf(i - 1)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2, P[2]);
     } else {
-      lin({T, Vf(i)}, kTabV, Vf(i + 1), false, {nullptr}, 1, P[1]);
+      launch_lin_step(from_step(mk({T, Vf(i)}, kTabV, Vf(i + 1), false, {nullptr}, 1, P[1]), kTabV),
+                      F, nrhs, sa, l->stream);
       lin({Sv, Wf(i)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2, P[2]);
     }
-    launch_gf_beta(S, i, P[1], P[2], nch, l->stream);
-    multi({mk({Vf(i + 1)}, kTabSV, Vf(i + 1), false, {CHI}, 1, P[3]),
-           mk({Wf(i + 1)}, kTabSW, Wf(i + 1), false, {}, 0, nullptr)});
-    launch_gf_xbar(S, i + 1, P[3], nch, l->stream);
+    // beta_i, gamma_i, then the normalisation
+    multi_step(step_of(kStepBeta, i, P[1], P[2], false),
+               {from_step(mk({Vf(i + 1)}, kTabSV, Vf(i + 1), false, {CHI}, 1, P[3]), kTabSV),
+                from_step(mk({Wf(i + 1)}, kTabSW, Wf(i + 1), false, {}, 0, nullptr), kTabSW)});
     OVS_HIP(save_ckpt(i + 1));
   }
   OVS_HIP(copy(TL, T));  // t_k = A v_k, needed by the first reverse step
@@ -651,16 +687,21 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
       OVS_HIP(copy(Wr(lo - 1), P_.ckW + (size_t)(2 * j) * NF));
       OVS_HIP(copy(Wr(lo), P_.ckW + (size_t)(2 * j + 1) * NF));
       for (int i = lo; i < top; ++i) {
-        launch_gp_coef(S, i, l->stream);
+        // the rows of step i from the stored coefficients, formed in each launch
+        const ScalarStep sc = step_of(kStepCoef, i, nullptr, nullptr, false);
         OVS_HIP(applyBoth(Vr(i), Wr(i), T, Sv));
         if (i > 0)
-          multi({mk({T, Vr(i), Vr(i - 1)}, kTabV, Vr(i + 1), false, {}, 0, nullptr),
-                 mk({Sv, Wr(i), Wr(i - 1)}, kTabW, Wr(i + 1), false, {}, 0, nullptr)});
+          multi_step(sc, {from_step(mk({T, Vr(i), Vr(i - 1)}, kTabV, Vr(i + 1), false, {}, 0,
+                                       nullptr), kTabV),
+                          from_step(mk({Sv, Wr(i), Wr(i - 1)}, kTabW, Wr(i + 1), false, {}, 0,
+                                       nullptr), kTabW)});
         else
-          multi({mk({T, Vr(i)}, kTabV, Vr(i + 1), false, {}, 0, nullptr),
-                 mk({Sv, Wr(i)}, kTabW, Wr(i + 1), false, {}, 0, nullptr)});
-        multi({mk({Vr(i + 1)}, kTabSV, Vr(i + 1), false, {}, 0, nullptr),
-               mk({Wr(i + 1)}, kTabSW, Wr(i + 1), false, {}, 0, nullptr)});
+          multi_step(sc, {from_step(mk({T, Vr(i)}, kTabV, Vr(i + 1), false, {}, 0, nullptr), kTabV),
+                          from_step(mk({Sv, Wr(i)}, kTabW, Wr(i + 1), false, {}, 0, nullptr),
+                                    kTabW)});
+        multi_step(sc, {from_step(mk({Vr(i + 1)}, kTabSV, Vr(i + 1), false, {}, 0, nullptr), kTabSV),
+                        from_step(mk({Wr(i + 1)}, kTabSW, Wr(i + 1), false, {}, 0, nullptr),
+                                  kTabSW)});
       }
     }
     for (int i = hi; i >= lo; --i) {
@@ -679,24 +720,31 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
         continue;
       }
       const int c = i & 1, p = (i + 1) & 1;
-      launch_gr_s1(S, i, P[2], P[3], nch, l->stream);
+      // step 1 of the reverse scalars (from the dots of vbar_{i+1}, wbar_{i+1})
+      const ScalarStep s1 = step_of(kStepS1, i, P[2], P[3], false);
       if (i > 0)
-        multi({mk({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i), Vr(i - 1)}, 2, P[0]),
-               mk({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i), Wr(i - 1)}, 2, P[1])});
+        multi_step(s1, {from_step(mk({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false,
+                                     {Vr(i), Vr(i - 1)}, 2, P[0]), kTabV),
+                        from_step(mk({WB[p], Vr(i + 1)}, kTabW, WTB[c], false,
+                                     {Wr(i), Wr(i - 1)}, 2, P[1]), kTabW)});
       else
-        multi({mk({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i)}, 1, P[0]),
-               mk({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i)}, 1, P[1])});
-      launch_gr_s2(S, i, P[0], P[1], nch, l->stream);
+        multi_step(s1, {from_step(mk({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i)},
+                                     1, P[0]), kTabV),
+                        from_step(mk({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i)}, 1, P[1]),
+                                  kTabW)});
+      // step 2 (abar_i; bbar_{i-1}, gbar_{i-1} written by workgroup 0)
       LinMulti m2;
-      m2.a[m2.n++] = mk({VTB[c], Wr(i)}, kTabSV, TB, false, {}, 0, nullptr);
-      m2.a[m2.n++] = mk({CHI, VTB[p], VTB[c]}, kTabSW, VB[c], false, {}, 0, nullptr);
+      m2.a[m2.n++] = from_step(mk({VTB[c], Wr(i)}, kTabSV, TB, false, {}, 0, nullptr), kTabSV);
+      m2.a[m2.n++] = from_step(mk({CHI, VTB[p], VTB[c]}, kTabSW, VB[c], false, {}, 0, nullptr),
+                               kTabSW);
       if (i > 0)
-        m2.a[m2.n++] = mk({WTB[p], WTB[c], Vr(i + 1), Vr(i), Vr(i - 1)}, kTabWB, WB[c], false, {},
-                          0, nullptr);
+        m2.a[m2.n++] = from_step(mk({WTB[p], WTB[c], Vr(i + 1), Vr(i), Vr(i - 1)}, kTabWB, WB[c],
+                                    false, {}, 0, nullptr), kTabWB);
       else
-        m2.a[m2.n++] = mk({WTB[p], WTB[c], Vr(i + 1), Vr(i)}, kTabWB, WB[c], false, {}, 0, nullptr);
-      if (y) m2.a[m2.n++] = mk({Vr(i)}, kTabY, YA, true, {}, 0, nullptr);
-      launch_lin_multi(m2, F, nrhs, l->stream);
+        m2.a[m2.n++] = from_step(mk({WTB[p], WTB[c], Vr(i + 1), Vr(i)}, kTabWB, WB[c], false, {}, 0,
+                                    nullptr), kTabWB);
+      if (y) m2.a[m2.n++] = from_step(mk({Vr(i)}, kTabY, YA, true, {}, 0, nullptr), kTabY);
+      launch_lin_multi_step(m2, F, nrhs, step_of(kStepS2, i, P[0], P[1], false), l->stream);
       OVS_HIP(applyBoth(WTB[c], TB, T2, T1));
       multi({mk({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]),
              mk({T2}, kTabOne, WB[c], true, {Wr(i)}, 1, P[3])});

@@ -26,6 +26,8 @@ struct LinArgs {
   const double2* y[kLinDots] = {};
   int ndot = 0;
   double* partials = nullptr;      // [nrhs][lin_nchunk][kLinDots][2]
+  int tab = -1;                    // >= 0: coefficients from this table of the
+                                   // launch's scalar step (launch_lin_step), not coef
 };
 int lin_nchunk(long stride);
 void launch_lin(const LinArgs& a, long stride, int nrhs, hipStream_t s);
@@ -105,6 +107,28 @@ void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipSt
 // nbar = (Re chi^dagger y_K - Re vbar_1^dagger v_1 + Re rho) / nb.
 void launch_gr_final_defl(const GradScalars& s, const double* part_v, const double* part_w,
                           int nchunk, hipStream_t st);
+
+// A scalar step run at the start of a combination launch (launch_lin_step,
+// launch_lin_multi_step), with the arithmetic of its separate kernel: alpha
+// (pa: dots of w_i^dagger t, |t|^2), beta (pa, pb: as launch_gf_beta), xbar
+// (pa: chi^dagger v_i), the replay rows of step i (no dots), reverse step 1
+// (pa, pb: as launch_gr_s1) and 2 (as launch_gr_s2).  The rows go to the
+// launch's tables for combinations with LinArgs::tab >= 0; global_tabs: also
+// to the global tables (for later launches).  Reverse steps 1 and 2 do not
+// write back gbar_i, bbar_i and abar_i, which nothing reads after them.
+enum { kStepNone = 0, kStepAlpha, kStepBeta, kStepXbar, kStepCoef, kStepS1, kStepS2 };
+struct ScalarStep {
+  int kind = kStepNone;
+  int i = 0;
+  const double* pa = nullptr;
+  const double* pb = nullptr;
+  int nchunk = 0;
+  GradScalars s{};
+  int global_tabs = 0;
+};
+void launch_lin_step(const LinArgs& a, long stride, int nrhs, const ScalarStep& st, hipStream_t s);
+void launch_lin_multi_step(const LinMulti& m, long stride, int nrhs, const ScalarStep& st,
+                           hipStream_t s);
 
 // xbar_i = nb * conj(dot 0) for the dot chi^dagger v_i of the partials.
 void launch_gf_xbar(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st);
