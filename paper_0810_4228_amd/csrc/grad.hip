@@ -80,10 +80,12 @@ __global__ void __launch_bounds__(kWG) k_lin(LinArgs a, long stride, int nrhs) {
   lin_body<false>(a, stride, nrhs, lds, nullptr);
 }
 
-// Several independent linear combinations in one launch: each is computed as
-// k_lin computes it (same grid, same per-element arithmetic, its own partial
-// sums), so the results equal those of separate launches bit for bit.  None
-// may read another's output.
+// Several linear combinations in one launch: each is computed as k_lin
+// computes it (same grid, same per-element arithmetic, its own partial sums),
+// so the results equal those of separate launches bit for bit.  A thread
+// visits the same elements in every combination, so a combination may read
+// an earlier one's output at the element it is computing (written by the same
+// thread); no other element of another's output.
 __global__ void __launch_bounds__(kWG) k_lin_multi(LinMulti m, long stride, int nrhs) {
   __shared__ double lds[(kWG / 64) * 2 * kLinDots];
   for (int j = 0; j < m.n; ++j) {

@@ -419,17 +419,18 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
       launch_gf_alpha(S, i, P[0], nch, l->stream);
       break;
     }
-    // alpha_i (written, with the W rows for the next launch, by workgroup 0)
-    const ScalarStep sa = step_of(kStepAlpha, i, P[0], nullptr, true);
-    if (i > 0) {
-      launch_lin_step(from_step(mk({T, Vf(i), Vf(i - 1)}, kTabV, Vf(i + 1), false, {nullptr}, 1,
-                                   P[1]), kTabV), F, nrhs, sa, l->stream);
-      lin({Sv, Wf(i), Wf(i - 1)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2, P[2]);
-    } else {
-      launch_lin_step(from_step(mk({T, Vf(i)}, kTabV, Vf(i + 1), false, {nullptr}, 1, P[1]), kTabV),
-                      F, nrhs, sa, l->stream);
-      lin({Sv, Wf(i)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2, P[2]);
-    }
+    // alpha_i (written by workgroup 0), then v~ and w~ in one launch (the dot
+    // v~^dagger w~ reads v~ at the element the same thread has just written)
+    const ScalarStep sa = step_of(kStepAlpha, i, P[0], nullptr, false);
+    if (i > 0)
+      multi_step(sa, {from_step(mk({T, Vf(i), Vf(i - 1)}, kTabV, Vf(i + 1), false, {nullptr}, 1,
+                                   P[1]), kTabV),
+                      from_step(mk({Sv, Wf(i), Wf(i - 1)}, kTabW, Wf(i + 1), false,
+                                   {Vf(i + 1), nullptr}, 2, P[2]), kTabW)});
+    else
+      multi_step(sa, {from_step(mk({T, Vf(i)}, kTabV, Vf(i + 1), false, {nullptr}, 1, P[1]), kTabV),
+                      from_step(mk({Sv, Wf(i)}, kTabW, Wf(i + 1), false, {Vf(i + 1), nullptr}, 2,
+                                   P[2]), kTabW)});
     // beta_i, gamma_i, then the normalisation
     multi_step(step_of(kStepBeta, i, P[1], P[2], false),
                {from_step(mk({Vf(i + 1)}, kTabSV, Vf(i + 1), false, {CHI}, 1, P[3]), kTabSV),
@@ -688,20 +689,25 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
       OVS_HIP(copy(Wr(lo), P_.ckW + (size_t)(2 * j + 1) * NF));
       for (int i = lo; i < top; ++i) {
         // the rows of step i from the stored coefficients, formed in each launch
+        // and v~, w~ and their normalisation in one launch (the scaling reads
+        // each element the same thread has just written)
         const ScalarStep sc = step_of(kStepCoef, i, nullptr, nullptr, false);
         OVS_HIP(applyBoth(Vr(i), Wr(i), T, Sv));
+        const LinArgs nv =
+            from_step(mk({Vr(i + 1)}, kTabSV, Vr(i + 1), false, {}, 0, nullptr), kTabSV);
+        const LinArgs nw =
+            from_step(mk({Wr(i + 1)}, kTabSW, Wr(i + 1), false, {}, 0, nullptr), kTabSW);
         if (i > 0)
           multi_step(sc, {from_step(mk({T, Vr(i), Vr(i - 1)}, kTabV, Vr(i + 1), false, {}, 0,
                                        nullptr), kTabV),
                           from_step(mk({Sv, Wr(i), Wr(i - 1)}, kTabW, Wr(i + 1), false, {}, 0,
-                                       nullptr), kTabW)});
+                                       nullptr), kTabW),
+                          nv, nw});
         else
           multi_step(sc, {from_step(mk({T, Vr(i)}, kTabV, Vr(i + 1), false, {}, 0, nullptr), kTabV),
                           from_step(mk({Sv, Wr(i)}, kTabW, Wr(i + 1), false, {}, 0, nullptr),
-                                    kTabW)});
-        multi_step(sc, {from_step(mk({Vr(i + 1)}, kTabSV, Vr(i + 1), false, {}, 0, nullptr), kTabSV),
-                        from_step(mk({Wr(i + 1)}, kTabSW, Wr(i + 1), false, {}, 0, nullptr),
-                                  kTabSW)});
+                                    kTabW),
+                          nv, nw});
       }
     }
     for (int i = hi; i >= lo; --i) {

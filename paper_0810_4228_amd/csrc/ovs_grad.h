@@ -31,8 +31,11 @@ struct LinArgs {
 };
 int lin_nchunk(long stride);
 void launch_lin(const LinArgs& a, long stride, int nrhs, hipStream_t s);
-// Up to kLinMulti independent combinations (none reads another's output) in
-// one launch, each computed exactly as launch_lin computes it.
+// Up to kLinMulti combinations in one launch, each computed exactly as
+// launch_lin computes it.  Every combination visits the elements in the same
+// thread order, so one may read (as a term or a dot operand) the output of an
+// earlier one in the list, element by element; nothing else of another's
+// output.
 constexpr int kLinMulti = 4;
 struct LinMulti {
   LinArgs a[kLinMulti];
