@@ -342,16 +342,20 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     a.tab = tab;
     return a;
   };
-  auto step_of = [&](int kind, int i, const double* pa, const double* pb, bool global_tabs) {
+  auto step_of_s = [&](const GradScalars& Sx, int kind, int i, const double* pa, const double* pb,
+                       bool global_tabs) {
     ScalarStep st;
     st.kind = kind;
     st.i = i;
     st.pa = pa;
     st.pb = pb;
     st.nchunk = nch;
-    st.s = S;
+    st.s = Sx;
     st.global_tabs = global_tabs ? 1 : 0;
     return st;
+  };
+  auto step_of = [&](int kind, int i, const double* pa, const double* pb, bool global_tabs) {
+    return step_of_s(S, kind, i, pa, pb, global_tabs);
   };
   auto multi_step = [&](const ScalarStep& st, std::initializer_list<LinArgs> las) {
     LinMulti m;
@@ -572,22 +576,32 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     launch_gf_start(S2, P[0], P[1], nch, l->stream);
     lin2({P_.CHIL}, kTabNorm, V2(0), false, {}, 0, nullptr);
     lin2({P_.CHIR}, kTabStartW, W2(0), false, {}, 0, nullptr);
+    // the same launches per step as the main forward pass: the operator pair
+    // in one dual-stencil launch (here t = A^dagger v, s = A w), alpha and
+    // beta at the start of the combinations that use them
     for (int i = 0; i < k; ++i) {
-      OVS_HIP(applyAd(V2(i), T));
+      if (i < k - 1) OVS_HIP(applyBoth(W2(i), V2(i), Sv, T));
+      else OVS_HIP(applyAd(V2(i), T));
       lin2({T}, kTabOne, nullptr, false, {W2(i), nullptr}, 2, P[0]);
-      launch_gf_alpha(S2, i, P[0], nch, l->stream);
-      if (i == k - 1) break;
-      OVS_HIP(applyA(W2(i), Sv));
-      if (i > 0) {
-        lin2({T, V2(i), V2(i - 1)}, kTabV, V2(i + 1), false, {nullptr}, 1, P[1]);
-        lin2({Sv, W2(i), W2(i - 1)}, kTabW, W2(i + 1), false, {V2(i + 1), nullptr}, 2, P[2]);
-      } else {
-        lin2({T, V2(i)}, kTabV, V2(i + 1), false, {nullptr}, 1, P[1]);
-        lin2({Sv, W2(i)}, kTabW, W2(i + 1), false, {V2(i + 1), nullptr}, 2, P[2]);
+      if (i == k - 1) {
+        launch_gf_alpha(S2, i, P[0], nch, l->stream);
+        break;
       }
-      launch_gf_beta(S2, i, P[1], P[2], nch, l->stream);
-      multi({mks(S2, {V2(i + 1)}, kTabSV, V2(i + 1), false, {}, 0, nullptr),
-             mks(S2, {W2(i + 1)}, kTabSW, W2(i + 1), false, {}, 0, nullptr)});
+      const ScalarStep sa = step_of_s(S2, kStepAlpha, i, P[0], nullptr, false);
+      if (i > 0)
+        multi_step(sa, {from_step(mks(S2, {T, V2(i), V2(i - 1)}, kTabV, V2(i + 1), false, {nullptr},
+                                      1, P[1]), kTabV),
+                        from_step(mks(S2, {Sv, W2(i), W2(i - 1)}, kTabW, W2(i + 1), false,
+                                      {V2(i + 1), nullptr}, 2, P[2]), kTabW)});
+      else
+        multi_step(sa, {from_step(mks(S2, {T, V2(i)}, kTabV, V2(i + 1), false, {nullptr}, 1, P[1]),
+                                  kTabV),
+                        from_step(mks(S2, {Sv, W2(i)}, kTabW, W2(i + 1), false,
+                                      {V2(i + 1), nullptr}, 2, P[2]), kTabW)});
+      multi_step(step_of_s(S2, kStepBeta, i, P[1], P[2], false),
+                 {from_step(mks(S2, {V2(i + 1)}, kTabSV, V2(i + 1), false, {}, 0, nullptr), kTabSV),
+                  from_step(mks(S2, {W2(i + 1)}, kTabSW, W2(i + 1), false, {}, 0, nullptr),
+                            kTabSW)});
     }
     OVS_HIP(hipGetLastError());
     OVS_HIP(hipMemcpyAsync(status.data(), S2.status, sizeof(int) * nrhs, hipMemcpyDeviceToHost,
