@@ -802,9 +802,7 @@ __global__ void __launch_bounds__(kWG) k_gforce(double2* F, const double2* pbar,
   }
 }
 
-void launch_gforce(double2* F, const double2* pbar, const double2* p, const double2* qbar,
-                   const double2* q, long stride, int nrhs, const Geometry& g, const Hop& hA,
-                   const Hop& hAd, hipStream_t st) {
+static HopPair hop_pair(const Hop& hA, const Hop& hAd) {
   HopPair hp;
   for (int nu = 0; nu < 4; ++nu) {
     hp.fA[nu] = hA.fwd[nu];
@@ -812,8 +810,82 @@ void launch_gforce(double2* F, const double2* pbar, const double2* p, const doub
     hp.fAd[nu] = hAd.fwd[nu];
     hp.bAd[nu] = hAd.bwd[nu];
   }
+  return hp;
+}
+
+void launch_gforce(double2* F, const double2* pbar, const double2* p, const double2* qbar,
+                   const double2* q, long stride, int nrhs, const Geometry& g, const Hop& hA,
+                   const Hop& hAd, hipStream_t st) {
+  const HopPair hp = hop_pair(hA, hAd);
   hipLaunchKernelGGL(k_gforce, dim3((g.V + kWG - 1) / kWG, 4), dim3(kWG), 0, st, F, pbar, p, qbar,
                      q, stride, nrhs, g, hp);
+}
+
+// The force of n consecutive reverse steps in one pass: the contributions of
+// every step and source are summed in registers (steps in order, then
+// sources, as force_dir sums the sources of one step) and F is read and
+// written once, not once per step.  Step j's fields are at pbar0 + j *
+// step_stride etc.
+template <int NU>
+__device__ __forceinline__ void force_dir_group(double2* F, const double2* pbar0,
+                                                const double2* p0, const double2* qbar0,
+                                                const double2* q0, int nsteps, long step_stride,
+                                                long stride, int nrhs, const Geometry& g, int s,
+                                                int sf, const HopPair& hp) {
+  const long Vs = g.Vs;
+  Cx<double> fp[9], fm[9];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) fp[e] = fm[e] = {0.0, 0.0};
+  for (int j = 0; j < nsteps; ++j) {
+    const long js = (long)j * step_stride;
+    for (int r = 0; r < nrhs; ++r) {
+      const long o = js + (long)r * stride;
+      if constexpr (NU == 3) {
+        force_pair<NU>(fp, fm, pbar0 + o, p0 + o, Vs, s, sf, hp.fA[NU], hp.bA[NU]);
+        force_pair<NU>(fm, fp, qbar0 + o, q0 + o, Vs, s, sf, hp.fAd[NU], hp.bAd[NU]);
+      } else {
+        force_pair<NU>(fp, fp, pbar0 + o, p0 + o, Vs, s, sf, hp.fA[NU], hp.bA[NU]);
+        force_pair<NU>(fp, fp, qbar0 + o, q0 + o, Vs, s, sf, hp.fAd[NU], hp.bAd[NU]);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    double2* dst = F + ((long)NU * 9 + e) * Vs + s;
+    *dst = d2(c64(*dst) + fp[e]);
+  }
+  if constexpr (NU == 3) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      double2* dst = F + ((long)4 * 9 + e) * Vs + s;
+      *dst = d2(c64(*dst) + fm[e]);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kWG) k_gforce_group(double2* F, const double2* pbar0,
+                                                      const double2* p0, const double2* qbar0,
+                                                      const double2* q0, int nsteps,
+                                                      long step_stride, long stride, int nrhs,
+                                                      Geometry g, HopPair hp) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.V) return;
+  const Nbr nb = neighbours(s, g);
+  switch (blockIdx.y) {
+    case 0: force_dir_group<0>(F, pbar0, p0, qbar0, q0, nsteps, step_stride, stride, nrhs, g, s, nb.f[0], hp); break;
+    case 1: force_dir_group<1>(F, pbar0, p0, qbar0, q0, nsteps, step_stride, stride, nrhs, g, s, nb.f[1], hp); break;
+    case 2: force_dir_group<2>(F, pbar0, p0, qbar0, q0, nsteps, step_stride, stride, nrhs, g, s, nb.f[2], hp); break;
+    default: force_dir_group<3>(F, pbar0, p0, qbar0, q0, nsteps, step_stride, stride, nrhs, g, s, nb.f[3], hp); break;
+  }
+}
+
+void launch_gforce_group(double2* F, const double2* pbar0, const double2* p0,
+                         const double2* qbar0, const double2* q0, int nsteps, long step_stride,
+                         long stride, int nrhs, const Geometry& g, const Hop& hA, const Hop& hAd,
+                         hipStream_t st) {
+  const HopPair hp = hop_pair(hA, hAd);
+  hipLaunchKernelGGL(k_gforce_group, dim3((g.V + kWG - 1) / kWG, 4), dim3(kWG), 0, st, F, pbar0,
+                     p0, qbar0, q0, nsteps, step_stride, stride, nrhs, g, hp);
 }
 
 __global__ void __launch_bounds__(kWG) k_gforce_out(const double2* F, const double2* links,

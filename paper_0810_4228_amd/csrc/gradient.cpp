@@ -155,11 +155,17 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     // active count, identity source map; per-tile partials (not used)
     int* dints;
     double* dpart2;
+    // the projected tbar_i and sbar_i of the steps of one force group
+    double2 *GT, *GS;
   } P_{};
   GradScalars S{}, S2{};
   // tile of the paired stencil: 64 sites on small lattices, where 256-site
   // tiles would leave most CUs idle
   const int dual_tile = (g.V / 256 < 128) ? 64 : 256;
+  // force groups: the link force of cg consecutive reverse steps is summed in
+  // one pass (steps i with i / cg equal; the recomputation segments, in both
+  // modes, so the sums are the same)
+  const int cg = std::max(1, (int)std::ceil(std::sqrt((double)k)));
   auto carve_scalars = [&](Arena& a, GradScalars& Sx) {
     const size_t nk = (size_t)nrhs * k;
     Sx.alpha = a.take<double2>(nk);
@@ -194,6 +200,8 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     P_.parts = a.take<double>((size_t)4 * nrhs * nch * 2 * kLinDots);
     P_.fparts = a.take<double>((size_t)(g.V + kWG - 1) / kWG + 1);
     P_.gmu = a.take<double>(1);
+    P_.GT = a.take<double2>((size_t)cg * NF);
+    P_.GS = a.take<double2>((size_t)cg * NF);
     P_.dints = a.take<int>(2 + (size_t)nrhs);
     P_.dpart2 = a.take<double>((size_t)nrhs * ((g.V + dual_tile - 1) / dual_tile) * 3);
     P_.vjp = a.take<char>(isign_vjp_scratch_bytes(k, nnmax));
@@ -263,6 +271,8 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     OVS_HIP(hipMemsetAsync(S2.xbar, 0, sizeof(double2) * (size_t)nrhs * k, l->stream));
   }
   OVS_HIP(hipMemsetAsync(P_.Fg, 0, sizeof(double2) * 5 * 9 * g.Vs, l->stream));
+  OVS_HIP(hipMemsetAsync(P_.GT, 0, sizeof(double2) * (size_t)cg * NF, l->stream));
+  OVS_HIP(hipMemsetAsync(P_.GS, 0, sizeof(double2) * (size_t)cg * NF, l->stream));
   {
     std::vector<double2> ones((size_t)kLinTerms * nrhs, make_double2(1.0, 0.0));
     OVS_HIP(hipMemcpyAsync(coef_table(S, kTabOne), ones.data(), sizeof(double2) * ones.size(),
@@ -676,18 +686,25 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     OVS_HIP(hipStreamSynchronize(l->stream));  // host coefficient vectors are released
   }
   // forces of the sweep: Q^dagger tbar (+ the term (ii) vector of step i) and Q sbar
-  auto ptb = [&](int i, const double2* tb) -> const double2* {
+  auto ptb = [&](int i, const double2* tb, double2* out) -> const double2* {
     if (md == 0) return tb;
     launch_defl_proj(d->R, d->L, tb, md, nrhs, F, P_.dpart, P_.CDt,
-                     P_.kappa + (size_t)i * nrhs * md, nullptr, P_.TBp, l->stream);
-    return P_.TBp;
+                     P_.kappa + (size_t)i * nrhs * md, nullptr, out, l->stream);
+    return out;
   };
-  auto psb = [&](const double2* sb) -> const double2* {
+  auto psb = [&](const double2* sb, double2* out) -> const double2* {
     if (md == 0) return sb;
-    launch_defl_proj(d->R, d->L, sb, md, nrhs, F, P_.dpart, P_.CDt, nullptr, P_.WTBp, nullptr,
+    launch_defl_proj(d->R, d->L, sb, md, nrhs, F, P_.dpart, P_.CDt, nullptr, out, nullptr,
                      l->stream);
-    return P_.WTBp;
+    return out;
   };
+  // force-group slots of step i; without deflation tbar_i and sbar_i are
+  // formed there directly (sbar_{i+1} of the previous step is in the next
+  // slot), with deflation their projections go there
+  auto slotT = [&](int i) { return P_.GT + (size_t)(i % cg) * NF; };
+  auto slotS = [&](int i) { return P_.GS + (size_t)(i % cg) * NF; };
+  auto TBc = [&](int i) { return md == 0 ? slotT(i) : TB; };
+  auto WTBc = [&](int i) { return md == 0 ? slotS(i) : WTB[i & 1]; };
 
   // ---- reverse sweep, segment by segment from the last ----
   rg.phase("reverse_sweep");
@@ -736,41 +753,52 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
         launch_lin_multi(m0, F, nrhs, l->stream);
         OVS_HIP(applyAd(TB, T1));
         lin({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]);    // vbar += A^dag tbar
-        launch_gforce(P_.Fg, ptb(i, TB), Vr(i), nullptr, nullptr, F, nrhs, g, hA, hAd, l->stream);
+        launch_gforce(P_.Fg, ptb(i, TB, P_.TBp), Vr(i), nullptr, nullptr, F, nrhs, g, hA, hAd,
+                      l->stream);
         continue;
       }
       const int c = i & 1, p = (i + 1) & 1;
       // step 1 of the reverse scalars (from the dots of vbar_{i+1}, wbar_{i+1})
       const ScalarStep s1 = step_of(kStepS1, i, P[2], P[3], false);
+      double2* const tbi = TBc(i);
+      double2* const sbi = WTBc(i);
+      const double2* const sbn = WTBc(i + 1);  // sbar_{i+1}
       if (i > 0)
         multi_step(s1, {from_step(mk({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false,
                                      {Vr(i), Vr(i - 1)}, 2, P[0]), kTabV),
-                        from_step(mk({WB[p], Vr(i + 1)}, kTabW, WTB[c], false,
+                        from_step(mk({WB[p], Vr(i + 1)}, kTabW, sbi, false,
                                      {Wr(i), Wr(i - 1)}, 2, P[1]), kTabW)});
       else
         multi_step(s1, {from_step(mk({VB[p], Vr(i + 1), Wr(i + 1)}, kTabV, VTB[c], false, {Vr(i)},
                                      1, P[0]), kTabV),
-                        from_step(mk({WB[p], Vr(i + 1)}, kTabW, WTB[c], false, {Wr(i)}, 1, P[1]),
+                        from_step(mk({WB[p], Vr(i + 1)}, kTabW, sbi, false, {Wr(i)}, 1, P[1]),
                                   kTabW)});
       // step 2 (abar_i; bbar_{i-1}, gbar_{i-1} written by workgroup 0)
       LinMulti m2;
-      m2.a[m2.n++] = from_step(mk({VTB[c], Wr(i)}, kTabSV, TB, false, {}, 0, nullptr), kTabSV);
+      m2.a[m2.n++] = from_step(mk({VTB[c], Wr(i)}, kTabSV, tbi, false, {}, 0, nullptr), kTabSV);
       m2.a[m2.n++] = from_step(mk({CHI, VTB[p], VTB[c]}, kTabSW, VB[c], false, {}, 0, nullptr),
                                kTabSW);
       if (i > 0)
-        m2.a[m2.n++] = from_step(mk({WTB[p], WTB[c], Vr(i + 1), Vr(i), Vr(i - 1)}, kTabWB, WB[c],
-                                    false, {}, 0, nullptr), kTabWB);
+        m2.a[m2.n++] = from_step(mk({sbn, sbi, Vr(i + 1), Vr(i), Vr(i - 1)}, kTabWB, WB[c], false,
+                                    {}, 0, nullptr), kTabWB);
       else
-        m2.a[m2.n++] = from_step(mk({WTB[p], WTB[c], Vr(i + 1), Vr(i)}, kTabWB, WB[c], false, {}, 0,
+        m2.a[m2.n++] = from_step(mk({sbn, sbi, Vr(i + 1), Vr(i)}, kTabWB, WB[c], false, {}, 0,
                                     nullptr), kTabWB);
       if (y) m2.a[m2.n++] = from_step(mk({Vr(i)}, kTabY, YA, true, {}, 0, nullptr), kTabY);
       launch_lin_multi_step(m2, F, nrhs, step_of(kStepS2, i, P[0], P[1], false), l->stream);
-      OVS_HIP(applyBoth(WTB[c], TB, T2, T1));
+      OVS_HIP(applyBoth(sbi, tbi, T2, T1));
       multi({mk({T1}, kTabOne, VB[c], true, {Vr(i)}, 1, P[2]),
              mk({T2}, kTabOne, WB[c], true, {Wr(i)}, 1, P[3])});
-      {
-        const double2* tbp = ptb(i, TB);
-        launch_gforce(P_.Fg, tbp, Vr(i), psb(WTB[c]), Wr(i), F, nrhs, g, hA, hAd, l->stream);
+      // the force of this step waits in its group's slots; a group (the steps
+      // i .. i + cg - 1 below k - 1) is summed when its lowest step is done
+      if (md > 0) {
+        ptb(i, tbi, slotT(i));
+        psb(sbi, slotS(i));
+      }
+      if (i % cg == 0) {
+        const int n = std::min(i + cg - 1, k - 2) - i + 1;
+        launch_gforce_group(P_.Fg, slotT(i), Vr(i), slotS(i), Wr(i), n, NF, F, nrhs, g, hA, hAd,
+                            l->stream);
       }
     }
   }

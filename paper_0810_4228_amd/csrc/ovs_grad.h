@@ -162,6 +162,13 @@ void launch_isign_vjp(const double2* alpha, const double* beta, const double2* g
 void launch_gforce(double2* F, const double2* pbar, const double2* p, const double2* qbar,
                    const double2* q, long stride, int nrhs, const Geometry& g, const Hop& hA,
                    const Hop& hAd, hipStream_t st);
+// The same force for nsteps reverse steps at once (both terms present):
+// step j's pbar, p, qbar, q are at pbar0 + j step_stride etc.; their
+// contributions are summed in registers and F is read and written once.
+void launch_gforce_group(double2* F, const double2* pbar0, const double2* p0,
+                         const double2* qbar0, const double2* q0, int nsteps, long step_stride,
+                         long stride, int nrhs, const Geometry& g, const Hop& hA, const Hop& hAd,
+                         hipStream_t st);
 // grad_U (canonical [V][4][3][3]) = boundary sign * (F_nu + [nu=3] F_4), and
 // grad_mu = Re sum tr(F_3^dagger U_4) - Re sum tr(F_4^dagger U_4) (packed links).
 void launch_gforce_out(const double2* F, const double2* links, const Geometry& g, const int bc[4],
