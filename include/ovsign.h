@@ -357,8 +357,8 @@ ovs_status ovs_sign_apply(ovs_lattice lat, ovs_deflation defl, int32_t n_defl, c
  *              ovs_vjp_workspace_size bytes (OVS_ERR_ARG otherwise), or NULL for
  *              the handle's cached workspace.
  * Needs an OVS_F64 lattice (OVS_ERR_ARG otherwise) and FP64 workspace of about
- * (4k/c + 2c + 22) nrhs fields with c = ceil(sqrt k), or (2k + 18) nrhs with
- * OVS_VJP_STORE_BASIS, plus (k + 11) nrhs fields with deflation
+ * (4k/c + 4c + 22) nrhs fields with c = ceil(sqrt k), or (2k + 2c + 18) nrhs
+ * with OVS_VJP_STORE_BASIS, plus (k + 11) nrhs fields with deflation
  * (OVS_ERR_ALLOC if the handle's cache cannot grow to it).
  * Returns OVS_WARN_BREAKDOWN, writing no output, when a source (or the
  * second run) breaks down before k iterations, when with deflation a source
