@@ -3,11 +3,14 @@
 // deflation, y_k = |b| V_k sgn(G_k) e_1 (eq. 2sLapp with m = 0).
 //
 // The driver (gradient.cpp) runs the Lanczos recurrences forward storing the
-// FP64 bases V, W, then walks them backwards.  Every vector step of the
-// reverse sweep is a short linear combination of stored fields with fused
-// dot products (k_lin); the scalar steps run one thread per source; the
-// stencil adjoints are ordinary A and A^dagger applications; the link and mu
-// derivatives are accumulated by k_gforce.  Reductions are fixed-order.
+// FP64 bases V, W (or checkpoints), then walks them backwards.  Every vector
+// step is a short linear combination of stored fields with fused dot
+// products (k_lin, k_lin_multi); the per-source scalar steps mostly run at
+// the start of the combination launch that uses their coefficient rows
+// (k_lin_step, k_lin_multi_step); the pairs of A and A^dagger applications
+// are the dual stencil; the link and mu derivatives are accumulated by
+// k_gforce (one step) and k_gforce_group (a group of steps).  Reductions
+// are fixed-order.
 #include <cmath>
 
 #include "ovs_common.h"
@@ -245,10 +248,6 @@ __device__ void step_gf_beta(const GradScalars& s, int i, const double* part_v,
   const bool gz = g.re == 0.0 && g.im == 0.0;
   o.put(kTabSW, 0, gz ? Cx<double>{0.0, 0.0} : cdiv({1.0, 0.0}, cconj(g)));
 }
-__global__ void __launch_bounds__(kScalarWG) k_gf_beta(GradScalars s, int i, const double* part_v,
-                                                      const double* part_w, int nchunk) {
-  step_gf_beta(s, i, part_v, part_w, nchunk, TabOut{nullptr, s.coef, s.nrhs, (int)blockIdx.x, true});
-}
 
 void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
   hipLaunchKernelGGL(k_gf_norm, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, nchunk);
@@ -259,11 +258,6 @@ void launch_gf_start(const GradScalars& s, const double* part, const double* par
 }
 void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st) {
   hipLaunchKernelGGL(k_gf_alpha, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part, nchunk);
-}
-void launch_gf_beta(const GradScalars& s, int i, const double* part_v, const double* part_w,
-                    int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gf_beta, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part_v, part_w,
-                     nchunk);
 }
 
 // ---- reverse scalar steps ------------------------------------------------------
@@ -320,10 +314,6 @@ __device__ void step_gr_s1(const GradScalars& s, int i, const double* part_v, co
   o.put(kTabW, 0, cdiv({1.0, 0.0}, ga));
   o.put(kTabW, 1, scale(be, cconj(db)));
 }
-__global__ void __launch_bounds__(kScalarWG) k_gr_s1(GradScalars s, int i, const double* part_v,
-                                                    const double* part_w, int nchunk) {
-  step_gr_s1(s, i, part_v, part_w, nchunk, TabOut{nullptr, s.coef, s.nrhs, (int)blockIdx.x, true});
-}
 
 // Step i < k-1, second half.  Inputs: v_i^dagger vbar~ (d5), v_{i-1}^dagger vbar~
 // (d6), w_i^dagger wbar~ (conj d4), w_{i-1}^dagger wbar~ (d3).  Through
@@ -370,10 +360,6 @@ __device__ void step_gr_s2(const GradScalars& s, int i, const double* part_v, co
   o.put(kTabWB, 3, cmul(cab, al));
   o.put(kTabWB, 4, cmul(cab, gprev));
   o.put(kTabY, 0, scale(s.nb[r], c64(s.x[rk + i])));
-}
-__global__ void __launch_bounds__(kScalarWG) k_gr_s2(GradScalars s, int i, const double* part_v,
-                                                    const double* part_w, int nchunk) {
-  step_gr_s2(s, i, part_v, part_w, nchunk, TabOut{nullptr, s.coef, s.nrhs, (int)blockIdx.x, true});
 }
 
 // v_1 = w_1 = b/|b|: grad_b = ubar/|b| + nbar v_1 with ubar = vbar_1 + wbar_1 and
@@ -433,16 +419,6 @@ void launch_gr_final_defl(const GradScalars& s, const double* part_v, const doub
 void launch_gr_first(const GradScalars& s, hipStream_t st) {
   hipLaunchKernelGGL(k_gr_first, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s);
 }
-void launch_gr_s1(const GradScalars& s, int i, const double* part_v, const double* part_w,
-                  int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gr_s1, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part_v, part_w,
-                     nchunk);
-}
-void launch_gr_s2(const GradScalars& s, int i, const double* part_v, const double* part_w,
-                  int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_gr_s2, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, i, part_v, part_w,
-                     nchunk);
-}
 void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipStream_t st) {
   hipLaunchKernelGGL(k_gr_final, dim3(s.nrhs), dim3(kScalarWG), 0, st, s, part, nchunk);
 }
@@ -485,15 +461,7 @@ __device__ void gp_coef_rows(const GradScalars& s, int i, const TabOut& o) {
   const bool gz = g.re == 0.0 && g.im == 0.0;
   o.put(kTabSW, 0, gz ? Cx<double>{0.0, 0.0} : cdiv({1.0, 0.0}, cconj(g)));
 }
-__global__ void k_gp_coef(GradScalars s, int i) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= s.nrhs) return;
-  gp_coef_rows(s, i, TabOut{nullptr, s.coef, s.nrhs, r, true});
-}
 
-void launch_gp_coef(const GradScalars& s, int i, hipStream_t st) {
-  hipLaunchKernelGGL(k_gp_coef, dim3((s.nrhs + 63) / 64), dim3(64), 0, st, s, i);
-}
 
 // ---- linear combinations preceded by their scalar step ------------------------
 // Every workgroup of source r forms the step's coefficient rows itself (the

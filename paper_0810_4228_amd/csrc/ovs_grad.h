@@ -93,14 +93,8 @@ void launch_gf_norm(const GradScalars& s, const double* part, int nchunk, hipStr
 void launch_gf_start(const GradScalars& s, const double* part, const double* part_b, int nchunk,
                      hipStream_t st);
 void launch_gf_alpha(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st);
-void launch_gf_beta(const GradScalars& s, int i, const double* part_v, const double* part_w,
-                    int nchunk, hipStream_t st);
 // reverse
 void launch_gr_first(const GradScalars& s, hipStream_t st);
-void launch_gr_s1(const GradScalars& s, int i, const double* part_v, const double* part_w,
-                  int nchunk, hipStream_t st);
-void launch_gr_s2(const GradScalars& s, int i, const double* part_v, const double* part_w,
-                  int nchunk, hipStream_t st);
 void launch_gr_final(const GradScalars& s, const double* part, int nchunk, hipStream_t st);
 // Deflated starts: from v_1^dagger vbar_1 (part_v, dot 0) and w_1^dagger wbar_1
 // (part_w, dot 0), the adjoints of b_R and b_L:
@@ -112,10 +106,14 @@ void launch_gr_final_defl(const GradScalars& s, const double* part_v, const doub
                           int nchunk, hipStream_t st);
 
 // A scalar step run at the start of a combination launch (launch_lin_step,
-// launch_lin_multi_step), with the arithmetic of its separate kernel: alpha
-// (pa: dots of w_i^dagger t, |t|^2), beta (pa, pb: as launch_gf_beta), xbar
-// (pa: chi^dagger v_i), the replay rows of step i (no dots), reverse step 1
-// (pa, pb: as launch_gr_s1) and 2 (as launch_gr_s2).  The rows go to the
+// launch_lin_multi_step), one workgroup per chunk and source, each forming
+// the step's rows with the same sums: alpha (pa: partials of w_i^dagger t
+// and |t|^2), beta (pa: |v~|^2; pb: v~^dagger w~ and |w~|^2), xbar (pa:
+// chi^dagger v_i), the replay rows of step i from the stored coefficients
+// (no dots, the arithmetic of alpha and beta, so replayed vectors are
+// bitwise equal), reverse step 1 (pa: vbar_{i+1}^dagger v_{i+1}; pb:
+// wbar_{i+1}^dagger w_{i+1}) and reverse step 2 (pa: v_i^dagger vbar~,
+// v_{i-1}^dagger vbar~; pb: the same with w and wbar~).  The rows go to the
 // launch's tables for combinations with LinArgs::tab >= 0; global_tabs: also
 // to the global tables (for later launches).  Reverse steps 1 and 2 do not
 // write back gbar_i, bbar_i and abar_i, which nothing reads after them.
@@ -135,11 +133,6 @@ void launch_lin_multi_step(const LinMulti& m, long stride, int nrhs, const Scala
 
 // xbar_i = nb * conj(dot 0) for the dot chi^dagger v_i of the partials.
 void launch_gf_xbar(const GradScalars& s, int i, const double* part, int nchunk, hipStream_t st);
-// Replay of step i from the stored coefficients: the tables of the forward
-// update (kTabV, kTabW) and normalisation (kTabSV, kTabSW), with the same
-// arithmetic as k_gf_alpha / k_gf_beta, so replayed vectors are bitwise equal.
-void launch_gp_coef(const GradScalars& s, int i, hipStream_t st);
-
 // Inner sign and its vector-Jacobian product for one source by the tau = e^u
 // trapezoid rule at step h: x = (1/pi) int sum_+- (G +- i tau)^{-1} e_1 dtau and
 // Gbar (band of G) = -(1/pi) int sum_+- p conj(q)^T dtau with
