@@ -628,24 +628,36 @@ __global__ void k_isign_vjp(const double2* alpha, const double* beta, const doub
 #undef AT
 }
 
-// Sums over nodes (fixed order) with the trapezoid weights h tau / pi.
+// Sums over nodes (fixed order) with the trapezoid weights h tau / pi.  With
+// coarse.x set, also the rule of step 2h (the nodes of even index, weights
+// 2 h tau / pi) into coarse (x, gd, gsup), for the first comparison of two
+// levels without a launch at step 2h.
 __global__ void k_isign_vjp_reduce(int k, double h, int n0, int nnode, VjpScratch sc,
-                                   IsignVjpOut out) {
+                                   IsignVjpOut out, IsignVjpOut coarse) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
   const int nthr = 2 * nnode;
+  const bool two = coarse.x != nullptr;
   Cx<double> x = {0.0, 0.0}, gd = {0.0, 0.0}, gs = {0.0, 0.0}, gu = {0.0, 0.0};
+  Cx<double> xc = {0.0, 0.0}, gdc = {0.0, 0.0}, guc = {0.0, 0.0};
   for (int t = 0; t < nthr; ++t) {
-    const double w = h * exp((double)(n0 + (t >> 1)) * h) / M_PI;
+    const int node = n0 + (t >> 1);
+    const double w = h * exp((double)node * h) / M_PI;
     const Cx<double> qi = c64(sc.q[(long)i * nthr + t]);
     const Cx<double> pi_ = c64(sc.p[(long)i * nthr + t]);
     x = x + scale(w, qi);
     gd = gd - scale(w, cmulc(qi, pi_));
+    const bool even = two && (node & 1) == 0;
+    if (even) {
+      xc = xc + scale(2.0 * w, qi);
+      gdc = gdc - scale(2.0 * w, cmulc(qi, pi_));
+    }
     if (i + 1 < k) {
       const Cx<double> qn = c64(sc.q[(long)(i + 1) * nthr + t]);
       const Cx<double> pn = c64(sc.p[(long)(i + 1) * nthr + t]);
       gs = gs - scale(w, cmulc(qi, pn));   // Gbar_{i+1,i} = -p_{i+1} conj(q_i)
       gu = gu - scale(w, cmulc(qn, pi_));  // Gbar_{i,i+1} = -p_i conj(q_{i+1})
+      if (even) guc = guc - scale(2.0 * w, cmulc(qn, pi_));
     }
   }
   out.x[i] = d2(x);
@@ -654,17 +666,23 @@ __global__ void k_isign_vjp_reduce(int k, double h, int n0, int nnode, VjpScratc
     out.gsub_re[i] = gs.re;
     out.gsup[i] = d2(gu);
   }
+  if (two) {
+    coarse.x[i] = d2(xc);
+    coarse.gd[i] = d2(gdc);
+    if (i + 1 < k) coarse.gsup[i] = d2(guc);
+  }
 }
 
 void launch_isign_vjp(const double2* alpha, const double* beta, const double2* gamma,
                       const double2* xbar, int k, double h, int n0, int nnode, void* scratch,
-                      const IsignVjpOut& out, hipStream_t st) {
+                      const IsignVjpOut& out, hipStream_t st, const IsignVjpOut* coarse) {
   const int nthr = 2 * nnode;
   const VjpScratch sc = carve(scratch, k, nthr);
   hipLaunchKernelGGL(k_isign_vjp, dim3((nthr + 63) / 64), dim3(64), 0, st, alpha, beta, gamma,
                      xbar, k, h, n0, nnode, sc);
+  const IsignVjpOut none{};
   hipLaunchKernelGGL(k_isign_vjp_reduce, dim3((k + 63) / 64), dim3(64), 0, st, k, h, n0, nnode, sc,
-                     out);
+                     out, coarse ? *coarse : none);
 }
 
 // ---- link force -----------------------------------------------------------------

@@ -466,22 +466,31 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
   for (int r = 0; r < nrhs; ++r) {
     const size_t rk = (size_t)r * k;
     std::vector<double2> prev, cur;
-    double h = kVjpHStart, change = 0.0;
+    // the first launch takes step kVjpHStart / 2 and forms the rule of step
+    // kVjpHStart from the same solves (its even nodes): one launch for the
+    // first comparison of two levels
+    double h = 0.5 * kVjpHStart, change = 0.0;
     int lv = 0, used = 0;
-    for (;; h *= 0.5, lv ^= 1) {
+    auto fetch_level = [&](const IsignVjpOut& o, std::vector<double2>& v) -> hipError_t {
+      v.assign((size_t)3 * k, make_double2(0.0, 0.0));
+      hipError_t e = hipMemcpyAsync(v.data(), o.x, sizeof(double2) * k, hipMemcpyDeviceToHost,
+                                    l->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(v.data() + k, o.gd, sizeof(double2) * k, hipMemcpyDeviceToHost,
+                           l->stream);
+      if (e == hipSuccess && k > 1)
+        e = hipMemcpyAsync(v.data() + 2 * k, o.gsup, sizeof(double2) * (k - 1),
+                           hipMemcpyDeviceToHost, l->stream);
+      return e;
+    };
+    for (bool first = true;; h *= 0.5, lv ^= 1, first = false) {
       int n0, nn;
       vjp_range(h, n0, nn);
       launch_isign_vjp(S.alpha + rk, S.beta + rk, S.gamma + rk, S.xbar + rk, k, h, n0, nn,
-                       P_.vjp, P_.vo[lv], l->stream);
+                       P_.vjp, P_.vo[lv], l->stream, first ? &P_.vo[1 - lv] : nullptr);
       OVS_HIP(hipGetLastError());
-      cur.assign((size_t)3 * k, make_double2(0.0, 0.0));
-      OVS_HIP(hipMemcpyAsync(cur.data(), P_.vo[lv].x, sizeof(double2) * k,
-                             hipMemcpyDeviceToHost, l->stream));
-      OVS_HIP(hipMemcpyAsync(cur.data() + k, P_.vo[lv].gd, sizeof(double2) * k,
-                             hipMemcpyDeviceToHost, l->stream));
-      if (k > 1)
-        OVS_HIP(hipMemcpyAsync(cur.data() + 2 * k, P_.vo[lv].gsup, sizeof(double2) * (k - 1),
-                               hipMemcpyDeviceToHost, l->stream));
+      OVS_HIP(fetch_level(P_.vo[lv], cur));
+      if (first) OVS_HIP(fetch_level(P_.vo[1 - lv], prev));
       OVS_HIP(hipStreamSynchronize(l->stream));
       used = lv;
       if (!prev.empty()) {
@@ -623,17 +632,22 @@ static ovs_status vjp_impl(ovs_lattice l, ovs_deflation defl, int32_t n_defl, co
     for (int r = 0; r < nrhs; ++r) {
       const size_t rk = (size_t)r * k;
       std::vector<double2> prev, cur;
-      double h = kVjpHStart, change = 0.0;
+      double h = 0.5 * kVjpHStart, change = 0.0;  // first launch: two levels, as above
       int lv = 0, used = 0;
-      for (;; h *= 0.5, lv ^= 1) {
+      for (bool first = true;; h *= 0.5, lv ^= 1, first = false) {
         int n0, nn;
         vjp_range(h, n0, nn);
         launch_isign_vjp(S2.alpha + rk, S2.beta + rk, S2.gamma + rk, S2.xbar + rk, k, h, n0, nn,
-                         P_.vjp, P_.vo[lv], l->stream);
+                         P_.vjp, P_.vo[lv], l->stream, first ? &P_.vo[1 - lv] : nullptr);
         OVS_HIP(hipGetLastError());
         cur.assign(k, make_double2(0.0, 0.0));
         OVS_HIP(hipMemcpyAsync(cur.data(), P_.vo[lv].x, sizeof(double2) * k,
                                hipMemcpyDeviceToHost, l->stream));
+        if (first) {
+          prev.assign(k, make_double2(0.0, 0.0));
+          OVS_HIP(hipMemcpyAsync(prev.data(), P_.vo[1 - lv].x, sizeof(double2) * k,
+                                 hipMemcpyDeviceToHost, l->stream));
+        }
         OVS_HIP(hipStreamSynchronize(l->stream));
         used = lv;
         if (!prev.empty()) {

@@ -144,9 +144,13 @@ struct IsignVjpOut {
   double2* gsup;     // [k-1] Gbar_{i,i+1}
 };
 size_t isign_vjp_scratch_bytes(int k, int nnode);
+// coarse (optional): also the rule of step 2h from the same solves (the
+// nodes of even index), its x, gd and gsup, for comparing two levels with one
+// launch.
 void launch_isign_vjp(const double2* alpha, const double* beta, const double2* gamma,
                       const double2* xbar, int k, double h, int n0, int nnode, void* scratch,
-                      const IsignVjpOut& out, hipStream_t st);
+                      const IsignVjpOut& out, hipStream_t st,
+                      const IsignVjpOut* coarse = nullptr);
 
 // Link force: F ([5][9][Vs] FP64, packed-link gradient; slot 3 the e^{+mu}
 // part and slot 4 the e^{-mu} part of direction 4) += gradient of
