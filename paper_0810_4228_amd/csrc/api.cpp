@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -106,8 +107,15 @@ std::vector<int> lds_candidates(const ovs_lattice_s* l) {
   return c;
 }
 
+// The two halves of a split batch run on two host threads.  While one
+// captures its chunk of iterations as a graph, the other must not free or
+// allocate device memory (hipFree synchronises the device), so captures and
+// the growth of cached buffers hold this lock.
+static std::mutex g_capture_mu;
+
 ovs_status ensure_ws(ovs_lattice_s* l, size_t bytes) {
   if (l->ws && l->ws_bytes >= bytes) return OVS_OK;
+  std::lock_guard<std::mutex> lock(g_capture_mu);
   if (l->ws) {
     OVS_HIP(hipStreamSynchronize(l->stream));
     (void)hipFree(l->ws);
@@ -1175,6 +1183,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
     }
     int ncap = cap == 0 ? std::max(need, std::min(K, kBasisFirst)) : std::max(need, 2 * cap);
     ncap = std::min(ncap, K);
+    std::lock_guard<std::mutex> lock(g_capture_mu);
     void* nb = nullptr;
     if (hipMalloc(&nb, (size_t)ncap * vec_bytes) != hipSuccess) {
       (void)hipGetLastError();
@@ -1470,6 +1479,7 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
       }
       if (use_graph && nfull >= chunk) {
         if (!gexec) {
+          std::lock_guard<std::mutex> lock(g_capture_mu);  // see ensure_ws
           OVS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
           for (int c = 0; c < chunk; ++c) {
             st = enqueue_iter(true);
@@ -1737,7 +1747,12 @@ static ovs_status sign_apply_impl(ovs_lattice l, ovs_deflation defl, int32_t n_d
   std::vector<double> mind(nr, -1.0);
   if (!arn) {
     std::vector<double> dn((size_t)nr * K);
-    OVS_HIP(hipMemcpy(dn.data(), B.dnorm, dn.size() * sizeof(double), hipMemcpyDeviceToHost));
+    // on the handle's (non-blocking) stream: a synchronous copy on the legacy
+    // stream would have to wait for every blocking stream, and is refused
+    // while the other half of a split batch captures its graph
+    OVS_HIP(hipMemcpyAsync(dn.data(), B.dnorm, dn.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s));
+    OVS_HIP(hipStreamSynchronize(s));
     for (int r = 0; r < nr; ++r) {
       double mn = HUGE_VAL;
       for (int i = 0; i < K; ++i) {
