@@ -466,7 +466,7 @@ def test_dual_variants_match_cpu(prec, tol, agree):
     source blocks).  FP64 storage at k = 40 (unconverged: the step-by-step
     parity of the recurrence); FP32 storage stopped at its convergence check
     for 1e-6 and compared with the oracle at each source's k_used, where the
-    the benchmark spec's FP32 bar of 1e-5 applies (at a fixed k = 40, FP32 rounding
+    FP32-storage bar of 1e-5 relative applies (at a fixed k = 40, FP32 rounding
     amplified by the unconverged polynomial sits at 1.2e-5 from the FP64
     oracle, at a fixed k = 200, past convergence, at 2e-5).  The variants agree
     with each other to rounding."""
