@@ -59,3 +59,16 @@ def test_small_eig_host():
     T = np.triu(rng.standard_normal((20, 20)), 1) + np.diag(np.repeat([0.5, -0.5], 10) + 1e-3 * np.arange(20))
     lam, V = ovs.small_eig(T.astype(complex))
     assert np.abs(np.sort(lam.real) - np.sort(np.diag(T))).max() < 1e-9
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and a
+    message saying so, before touching a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
