@@ -282,10 +282,22 @@ __global__ void __launch_bounds__(256) k_combine(const T2* __restrict__ basis, l
                                                  double2* __restrict__ y) {
   const int r = blockIdx.y;
   const int kr = kused[r];
+  const double2* cr = coef + (long)r * kmax;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x) {
     Cx<double> acc = yex ? c64(yex[(long)r * N + e]) : Cx<double>{0, 0};
-    for (int i = 0; i < kr; ++i)
-      acc = cfma(c64(coef[(long)r * kmax + i]), ld64(basis + i * basis_stride + (long)r * N + e), acc);
+    const T2* br = basis + (long)r * N + e;
+    // the same sequential sum as one term per step, with the loads of eight
+    // basis vectors issued before their multiply-adds: one load in flight per
+    // wave would leave the sweep over the k_used stored vectors latency-bound
+    int i = 0;
+    for (; i + 8 <= kr; i += 8) {
+      Cx<double> q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = ld64(br + (long)(i + u) * basis_stride);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cfma(c64(cr[i + u]), q[u], acc);
+    }
+    for (; i < kr; ++i) acc = cfma(c64(cr[i]), ld64(br + (long)i * basis_stride), acc);
     y[(long)r * N + e] = d2(acc);
   }
 }
