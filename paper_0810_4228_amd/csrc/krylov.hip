@@ -567,15 +567,25 @@ __global__ void __launch_bounds__(64) k_isign_tri(const double2* __restrict__ al
   Cx<double> cur = inv_r00;
   for (int j0 = 1; j0 <= k; j0 += kRows) {
     const int nrow = min(kRows, k - j0 + 1);
-#pragma unroll 4
+    // the block's multipliers and swaps, loaded together rather than one row
+    // per dependent step (rows from k on clamped to row k-1, never used)
+    double2 mb[kRows];
+    unsigned char sb[kRows];
+#pragma unroll
+    for (int t = 0; t < kRows; ++t) {
+      const long jc = min(j0 + t, k - 1);
+      mb[t] = mult[mbase + jc * 64];
+      sb[t] = swp[mbase + jc * 64];
+    }
+#pragma unroll
     for (int t = 0; t < kRows; ++t) {
       if (t < nrow) {
         const int j = j0 + t;
         Cx<double> fin;
         if (j < k) {
-          const Cx<double> m = c64(mult[mbase + (long)j * 64]);
+          const Cx<double> m = c64(mb[t]);
           const Cx<double> nw = -cmul(m, cur);
-          if (swp[mbase + (long)j * 64]) {
+          if (sb[t]) {
             fin = nw;
           } else {
             fin = cur;
